@@ -1,0 +1,183 @@
+"""CompaSO oracle: plain FP64 CPU reference.  TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the package smoke check and the benchmark's CPU-baseline
+leg may import this package.  The product path (the HIP library and its Python
+binding) never imports it and shares no code with it.
+
+The arithmetic lives in ``compaso_oracle.c`` (FP64, OpenMP over particles and
+L0 groups, brute-force and cell-list neighbour modes); this module only marshals
+arguments.  Each C function cites the passage of the paper (Hadzhiyska et al.,
+CompaSO) that it follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "compaso_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+# Paper defaults (Table 1 and Sec. 2.2; Einstein-de Sitter thresholds 60/200).
+DEFAULTS = {
+    "box": 1.0,
+    "mean_density": 0.0,      # <= 0: N / box^3
+    "b_kernel": 0.4,          # DensityKernelRad, units of l_mean
+    "l_fof": 0.25,            # FoFLinkingLength, units of l_mean
+    "delta_l0_min": 60.0,     # L0DensityThreshold
+    "delta_l1": 200.0,        # SODensityL1
+    "alpha_elig": 0.8,        # SO_alpha_eligible
+    "c_roche": 2.0,           # SO_RocheCoeff
+    "n_new_min": 35.0,        # SO_NPForMinDensity
+    "particle_mass": 1.0,
+    "n_l1_min": 35,           # MinL1HaloNP
+    "self_count": 0,          # include W(0) = 1 for the particle itself
+}
+_ORDER = ["box", "mean_density", "b_kernel", "l_fof", "delta_l0_min", "delta_l1",
+          "alpha_elig", "c_roche", "n_new_min", "particle_mass", "n_l1_min", "self_count"]
+DERIVED = ["nbar", "b", "l", "b2", "l2", "norm", "K", "K2", "floor", "A6", "C3"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (FP64, no contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+                               "-std=gnu11", "-Wall", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        lib.orc_derive.argtypes = [P, I64, P]
+        lib.orc_density.argtypes = [I64, P, P, ctypes.c_int, P]
+        lib.orc_density_sample.argtypes = [I64, P, P, I64, P, P]
+        lib.orc_fof.argtypes = [I64, P, P, P, ctypes.c_int, P, P]
+        lib.orc_compaso.argtypes = [I64, P, P, P, P, ctypes.c_int, P, P, I64,
+                                    P, P, P, P, P, P, P, I64, P, P, P, P]
+        lib.orc_num_threads.restype = ctypes.c_int
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
+        _lib = lib
+    return _lib
+
+
+def params_vector(**kw) -> np.ndarray:
+    p = dict(DEFAULTS)
+    for k, v in kw.items():
+        if k not in p:
+            raise KeyError(k)
+        p[k] = v
+    return np.array([float(p[k]) for k in _ORDER], dtype=np.float64)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _pos(pos):
+    pos = np.ascontiguousarray(pos, dtype=np.float32)
+    assert pos.ndim == 2 and pos.shape[1] == 3
+    return pos
+
+
+def derive(n: int, **kw) -> dict:
+    """Derived constants (Sec. 2.2, App. B.2): see orc_derive."""
+    p = params_vector(**kw)
+    out = np.zeros(len(DERIVED), np.float64)
+    if _load().orc_derive(_ptr(p), int(n), _ptr(out)) != 0:
+        raise ValueError("invalid parameters")
+    return dict(zip(DERIVED, out.tolist()))
+
+
+def set_threads(k: int) -> None:
+    _load().orc_set_threads(int(k))
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())
+
+
+def density(pos, mode: str = "cells", **kw) -> np.ndarray:
+    """Kernel density Delta (FP64) per particle (Sec. 2.2.1, App. B.2)."""
+    pos = _pos(pos)
+    p = params_vector(**kw)
+    out = np.zeros(len(pos), np.float64)
+    rc = _load().orc_density(len(pos), _ptr(pos), _ptr(p), 0 if mode == "brute" else 1, _ptr(out))
+    if rc:
+        raise RuntimeError(f"orc_density failed ({rc})")
+    return out
+
+
+def density_sample(pos, which, **kw) -> np.ndarray:
+    """Kernel density of the particles listed in ``which`` only."""
+    pos = _pos(pos)
+    which = np.ascontiguousarray(which, dtype=np.int64)
+    p = params_vector(**kw)
+    out = np.zeros(len(which), np.float64)
+    rc = _load().orc_density_sample(len(pos), _ptr(pos), _ptr(p), len(which), _ptr(which), _ptr(out))
+    if rc:
+        raise RuntimeError(f"orc_density_sample failed ({rc})")
+    return out
+
+
+def fof(pos, dens, mode: str = "cells", **kw):
+    """L0 labels (1 + min index; 0 = not dense enough) and the group count."""
+    pos = _pos(pos)
+    dens = np.ascontiguousarray(dens, dtype=np.float64)
+    p = params_vector(**kw)
+    l0 = np.zeros(len(pos), np.int32)
+    ng = np.zeros(1, np.int64)
+    rc = _load().orc_fof(len(pos), _ptr(pos), _ptr(p), _ptr(dens), 0 if mode == "brute" else 1,
+                         _ptr(l0), _ptr(ng))
+    if rc:
+        raise RuntimeError(f"orc_fof failed ({rc})")
+    return l0, int(ng[0])
+
+
+def compaso(pos, dens, l0, mode: str = "cells", cap: int | None = None, **kw) -> dict:
+    """CompaSO L1 (literal sequential loop of Sec. 2.2.2) plus the output cut."""
+    pos = _pos(pos)
+    n = len(pos)
+    dens = np.ascontiguousarray(dens, dtype=np.float64)
+    l0 = np.ascontiguousarray(l0, dtype=np.int32)
+    p = params_vector(**kw)
+    cap = n if cap is None else int(cap)
+    halo_id = np.zeros(n, np.int32)
+    owner_all = np.zeros(n, np.int32)
+    t = {k: np.zeros(max(cap, 1), np.int32) for k in ("id", "nucleus", "l0", "n", "ienc")}
+    f = {k: np.zeros(max(n, 1), np.int32) for k in ("nucleus", "ienc", "count", "l0")}
+    nh = np.zeros(1, np.int64)
+    nf = np.zeros(1, np.int64)
+    rc = _load().orc_compaso(n, _ptr(pos), _ptr(p), _ptr(dens), _ptr(l0),
+                             0 if mode == "brute" else 1, _ptr(halo_id), _ptr(owner_all), cap,
+                             _ptr(t["id"]), _ptr(t["nucleus"]), _ptr(t["l0"]), _ptr(t["n"]),
+                             _ptr(t["ienc"]), _ptr(nh), _ptr(nf), n, _ptr(f["nucleus"]),
+                             _ptr(f["ienc"]), _ptr(f["count"]), _ptr(f["l0"]))
+    if rc:
+        raise RuntimeError(f"orc_compaso failed ({rc})")
+    k = int(min(nh[0], cap))
+    table = {key: v[:k].copy() for key, v in t.items()}
+    found = {key: v[:int(nf[0])].copy() for key, v in f.items()}
+    return {"halo_id": halo_id, "owner_all": owner_all, "table": table, "found": found,
+            "n_halos": int(nh[0]), "n_found": int(nf[0])}
+
+
+def find(pos, mode: str = "cells", density_override=None, **kw) -> dict:
+    """The whole pass: density (or the given field), L0 FoF, CompaSO L1, cut."""
+    dens = density(pos, mode=mode, **kw) if density_override is None \
+        else np.asarray(density_override, dtype=np.float64)
+    l0, ng = fof(pos, dens, mode=mode, **kw)
+    res = compaso(pos, dens, l0, mode=mode, **kw)
+    res.update({"density": dens, "l0": l0, "n_groups": ng})
+    return res

@@ -1,0 +1,603 @@
+/*
+ * CompaSO group-finding oracle.  TEST INFRASTRUCTURE: only the test suite, the
+ * package smoke check and the benchmark's CPU-baseline leg load this library.
+ * The product path (the HIP library) never links, includes or calls it, and the
+ * two share no code.
+ *
+ * A plain, slow FP64 CPU implementation of the on-the-fly group finder of
+ * Hadzhiyska et al., "CompaSO: A new halo finder for competitive assignment to
+ * spherical overdensities":
+ *   - kernel density per particle            (Sec. 2.2.1, kernel W = 1 - r^2/b^2;
+ *                                             normalisation from App. B.2)
+ *   - L0 friends-of-friends over dense particles (Sec. 2.2.1; FoF as in Sec. 1)
+ *   - CompaSO L1 inside every L0 group, run literally as the sequential loop of
+ *     Sec. 2.2.2 steps 1-4 (nucleus, R_L1 from all L0 particles, eligibility,
+ *     competitive reassignment, density floor), with the flat-rotation-curve
+ *     enclosed density of Sec. 2.3.2 and squared distances as in Sec. 2.3.3.
+ *   - output cut at the minimum L1 halo size (end of Sec. 2.2.2, Table 1).
+ *
+ * Neighbour search has two modes that must agree exactly: brute force over all
+ * pairs (mode 0) and a cell list (mode 1) whose cells are at least the search
+ * radius, so that every pair within the radius is in the 27-cell stencil.
+ *
+ * Canonical geometric predicate (used by every label decision):
+ *   dx = (double)x_j - (double)x_i; if dx > L/2: dx -= L; else if dx < -L/2: dx += L
+ *   d2 = (dx*dx + dy*dy) + dz*dz           (IEEE FP64, no fused multiply-add)
+ * Enclosed-count predicates use E3(e) = (e*e)*e on squared distances and
+ * II(k) = (double)k*(double)k, so that no root is ever taken:
+ *   R^3 = i/K with K = (4 pi/3) Delta_L1 nbar  =>  r < R  <=>  K^2 e^3 < i^2.
+ *
+ * Parameter vector (doubles), shared layout with the Python wrapper only:
+ *   [0] box  [1] mean_density (<=0: N/L^3)  [2] b_kernel (units of l_mean)
+ *   [3] l_fof (units of l_mean)  [4] delta_l0_min  [5] delta_l1  [6] alpha_elig
+ *   [7] c_roche  [8] n_new_min  [9] particle_mass  [10] n_l1_min  [11] self_count
+ * Derived vector (orc_derive):
+ *   [0] nbar [1] b [2] l [3] b2 [4] l2 [5] norm [6] K [7] K2 [8] floor [9] A6 [10] C3
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_PI 3.14159265358979323846
+
+enum { P_BOX, P_NBAR, P_B, P_L, P_DL0, P_DL1, P_ALPHA, P_CROCHE, P_NNEW, P_MASS,
+       P_NL1MIN, P_SELF, P_COUNT };
+enum { D_NBAR, D_B, D_L, D_B2, D_L2, D_NORM, D_K, D_K2, D_FLOOR, D_A6, D_C3, D_COUNT };
+
+/* ---------------------------------------------------------------- constants */
+
+/* Derived constants.
+ * - l_mean = nbar^(-1/3); b and l are given in units of l_mean (Sec. 2.2.1,
+ *   Table 1: DensityKernelRad 0.4, FoFLinkingLength 0.25).
+ * - norm: Delta = norm * sum W, with the unit-integral kernel so that a uniform
+ *   field has Delta = 1; int W d^3r = (2/5)(4 pi/3) b^3 (App. B.2).
+ * - K: the enclosed density inside radius r around a nucleus with k particles
+ *   inside is k / ((4 pi/3) r^3 nbar) in units of the mean, so it equals
+ *   Delta_L1 when r^3 = k / K (Sec. 2.2.2 step 1).
+ * - floor: kernel-smoothed central density of a singular isothermal sphere whose
+ *   200x-mean radius holds N_new,min particles (Sec. 2.2.2 step 4); the SIS
+ *   A/r^2 with A = (Delta_L1/3) R^2 smoothed by the unit-integral W gives 5A/b^2
+ *   at its centre (App. B.2, r < b branch at r -> 0).
+ * - A6 = alpha^6 (r < alpha R  <=>  K^2 e^3 < alpha^6 i^2), C3 = c_Roche^3
+ *   (competition cubed: R_new^2/e_new >= c R_own^2/e_own, Sec. 2.2.2 step 3 with
+ *   the flat-rotation-curve model of Sec. 2.3.2). */
+int orc_derive(const double *p, int64_t n, double *d)
+{
+    double box = p[P_BOX];
+    if (!(box > 0.0)) return 1;
+    double nbar = p[P_NBAR] > 0.0 ? p[P_NBAR] : (double)n / ((box * box) * box);
+    if (!(nbar > 0.0)) return 1;
+    double lmean = cbrt(1.0 / nbar);
+    double b = p[P_B] * lmean;
+    double l = p[P_L] * lmean;
+    double K = ((4.0 * ORC_PI) / 3.0) * p[P_DL1] * nbar;
+    double rnew = cbrt(p[P_NNEW] / K);
+    double a3 = (p[P_ALPHA] * p[P_ALPHA]) * p[P_ALPHA];
+    d[D_NBAR] = nbar;
+    d[D_B] = b;
+    d[D_L] = l;
+    d[D_B2] = b * b;
+    d[D_L2] = l * l;
+    d[D_NORM] = 15.0 / (((8.0 * ORC_PI) * ((b * b) * b)) * nbar);
+    d[D_K] = K;
+    d[D_K2] = K * K;
+    d[D_FLOOR] = ((5.0 * p[P_DL1]) / 3.0) * (rnew * rnew) / (b * b);
+    d[D_A6] = a3 * a3;
+    d[D_C3] = (p[P_CROCHE] * p[P_CROCHE]) * p[P_CROCHE];
+    return 0;
+}
+
+/* ---------------------------------------------------------------- geometry */
+
+/* Minimum-image squared distance in FP64 (canonical predicate, see header). */
+static double d2_periodic(const float *pos, int64_t i, int64_t j, double L)
+{
+    double half = 0.5 * L;
+    double dx = (double)pos[3 * j + 0] - (double)pos[3 * i + 0];
+    double dy = (double)pos[3 * j + 1] - (double)pos[3 * i + 1];
+    double dz = (double)pos[3 * j + 2] - (double)pos[3 * i + 2];
+    if (dx > half) dx -= L; else if (dx < -half) dx += L;
+    if (dy > half) dy -= L; else if (dy < -half) dy += L;
+    if (dz > half) dz -= L; else if (dz < -half) dz += L;
+    double xx = dx * dx;
+    double yy = dy * dy;
+    double zz = dz * dz;
+    double s = xx + yy;
+    return s + zz;
+}
+
+static double e3(double e) { double ee = e * e; return ee * e; }
+static double ii(int64_t k) { double x = (double)k; return x * x; }
+
+/* -------------------------------------------------------------- cell list */
+
+typedef struct {
+    int nc;              /* cells per side (>= 3) */
+    double cell;         /* cell side = L / nc >= search radius */
+    int64_t *start;      /* [nc^3 + 1] */
+    int64_t *items;      /* particle indices grouped by cell, ascending inside a cell */
+} grid_t;
+
+static int cell_coord(double x, double cell, int nc)
+{
+    int c = (int)floor(x / cell);
+    if (c < 0) c = 0;
+    if (c >= nc) c = nc - 1;
+    return c;
+}
+
+/* Returns 0 on success, 1 if the box is too small for a 27-cell stencil
+ * (callers then fall back to brute force), 2 on allocation failure. */
+static int grid_build(grid_t *g, int64_t n, const float *pos, double L, double rmin)
+{
+    double ncd = floor(L / rmin);
+    if (!(ncd >= 3.0)) return 1;
+    if (ncd > 512.0) ncd = 512.0;           /* coarser cells stay >= rmin */
+    int nc = (int)ncd;
+    int64_t ncell = (int64_t)nc * nc * nc;
+    g->nc = nc;
+    g->cell = L / nc;
+    g->start = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
+    g->items = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    int64_t *key = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    if (!g->start || !g->items || !key) { free(g->start); free(g->items); free(key); return 2; }
+    for (int64_t i = 0; i < n; i++) {
+        int cx = cell_coord(pos[3 * i + 0], g->cell, nc);
+        int cy = cell_coord(pos[3 * i + 1], g->cell, nc);
+        int cz = cell_coord(pos[3 * i + 2], g->cell, nc);
+        key[i] = ((int64_t)cz * nc + cy) * nc + cx;
+        g->start[key[i] + 1]++;
+    }
+    for (int64_t c = 0; c < ncell; c++) g->start[c + 1] += g->start[c];
+    int64_t *fill = (int64_t *)malloc((size_t)ncell * sizeof(int64_t));
+    if (!fill) { free(g->start); free(g->items); free(key); return 2; }
+    memcpy(fill, g->start, (size_t)ncell * sizeof(int64_t));
+    for (int64_t i = 0; i < n; i++) g->items[fill[key[i]]++] = i;
+    free(fill);
+    free(key);
+    return 0;
+}
+
+static void grid_free(grid_t *g) { free(g->start); free(g->items); }
+
+/* The 27 neighbour cells (with periodic wrap) of particle i's cell. */
+static void grid_stencil(const grid_t *g, const float *pos, int64_t i, int64_t out[27])
+{
+    int nc = g->nc;
+    int cx = cell_coord(pos[3 * i + 0], g->cell, nc);
+    int cy = cell_coord(pos[3 * i + 1], g->cell, nc);
+    int cz = cell_coord(pos[3 * i + 2], g->cell, nc);
+    int t = 0;
+    for (int oz = -1; oz <= 1; oz++)
+        for (int oy = -1; oy <= 1; oy++)
+            for (int ox = -1; ox <= 1; ox++) {
+                int x = (cx + ox + nc) % nc, y = (cy + oy + nc) % nc, z = (cz + oz + nc) % nc;
+                out[t++] = ((int64_t)z * nc + y) * nc + x;
+            }
+}
+
+/* ---------------------------------------------------------------- density */
+
+/* Kernel density of one particle: Delta_i = norm * sum_{j != i, r < b} (1 - r^2/b^2)
+ * (Sec. 2.2.1; unit-integral normalisation of App. B.2).  The self pair is left
+ * out unless self_count is set, in which case W(0) = 1 is added. */
+static double density_one(int64_t i, int64_t n, const float *pos, double L,
+                          const double *d, int self_count, const grid_t *g)
+{
+    double b2 = d[D_B2];
+    double s = self_count ? 1.0 : 0.0;
+    if (g) {
+        int64_t st[27];
+        grid_stencil(g, pos, i, st);
+        for (int t = 0; t < 27; t++)
+            for (int64_t k = g->start[st[t]]; k < g->start[st[t] + 1]; k++) {
+                int64_t j = g->items[k];
+                if (j == i) continue;
+                double r2 = d2_periodic(pos, i, j, L);
+                if (r2 < b2) s += 1.0 - r2 / b2;
+            }
+    } else {
+        for (int64_t j = 0; j < n; j++) {
+            if (j == i) continue;
+            double r2 = d2_periodic(pos, i, j, L);
+            if (r2 < b2) s += 1.0 - r2 / b2;
+        }
+    }
+    return d[D_NORM] * s;
+}
+
+/* mode 0: brute force; mode 1: cell list.  out[n] receives Delta (FP64). */
+int orc_density(int64_t n, const float *pos, const double *p, int mode, double *out)
+{
+    double d[D_COUNT];
+    if (orc_derive(p, n, d)) return 1;
+    double L = p[P_BOX];
+    int self_count = p[P_SELF] != 0.0;
+    grid_t g;
+    int use_grid = 0;
+    if (mode == 1) {
+        int rc = grid_build(&g, n, pos, L, d[D_B]);
+        if (rc == 2) return 2;
+        use_grid = rc == 0;
+    }
+    #pragma omp parallel for schedule(dynamic, 1024)
+    for (int64_t i = 0; i < n; i++)
+        out[i] = density_one(i, n, pos, L, d, self_count, use_grid ? &g : NULL);
+    if (use_grid) grid_free(&g);
+    return 0;
+}
+
+/* Density of selected particles only (cell list over the whole box). */
+int orc_density_sample(int64_t n, const float *pos, const double *p, int64_t m,
+                       const int64_t *which, double *out)
+{
+    double d[D_COUNT];
+    if (orc_derive(p, n, d)) return 1;
+    double L = p[P_BOX];
+    int self_count = p[P_SELF] != 0.0;
+    grid_t g;
+    int rc = grid_build(&g, n, pos, L, d[D_B]);
+    if (rc == 2) return 2;
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t t = 0; t < m; t++)
+        out[t] = density_one(which[t], n, pos, L, d, self_count, rc == 0 ? &g : NULL);
+    if (rc == 0) grid_free(&g);
+    return 0;
+}
+
+/* ---------------------------------------------------------------- L0 FoF */
+
+static int64_t uf_find(int64_t *parent, int64_t x)
+{
+    while (parent[x] != x) {
+        parent[x] = parent[parent[x]];
+        x = parent[x];
+    }
+    return x;
+}
+
+/* Union keeping the smaller index as the root, so a component's root is its
+ * minimum original index. */
+static void uf_union(int64_t *parent, int64_t a, int64_t b)
+{
+    int64_t ra = uf_find(parent, a), rb = uf_find(parent, b);
+    if (ra == rb) return;
+    if (ra < rb) parent[rb] = ra; else parent[ra] = rb;
+}
+
+/* L0 groups: friends-of-friends with linking length l over the particles whose
+ * density exceeds delta_l0_min (Sec. 2.2.1); two members are friends when their
+ * separation is less than l (FoF definition, Sec. 1).  l0[i] = 1 + minimum
+ * original index of i's group for members, 0 for non-members.  n_groups counts
+ * groups including single-member ones. */
+int orc_fof(int64_t n, const float *pos, const double *p, const double *dens,
+            int mode, int32_t *l0, int64_t *n_groups)
+{
+    double d[D_COUNT];
+    if (orc_derive(p, n, d)) return 1;
+    double L = p[P_BOX], l2 = d[D_L2], dmin = p[P_DL0];
+    int64_t *parent = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    if (!parent) return 2;
+    for (int64_t i = 0; i < n; i++) parent[i] = i;
+    grid_t g;
+    int use_grid = 0;
+    if (mode == 1) {
+        int rc = grid_build(&g, n, pos, L, d[D_L]);
+        if (rc == 2) { free(parent); return 2; }
+        use_grid = rc == 0;
+    }
+    for (int64_t i = 0; i < n; i++) {
+        if (!(dens[i] > dmin)) continue;
+        if (use_grid) {
+            int64_t st[27];
+            grid_stencil(&g, pos, i, st);
+            for (int t = 0; t < 27; t++)
+                for (int64_t k = g.start[st[t]]; k < g.start[st[t] + 1]; k++) {
+                    int64_t j = g.items[k];
+                    if (j <= i || !(dens[j] > dmin)) continue;
+                    if (d2_periodic(pos, i, j, L) < l2) uf_union(parent, i, j);
+                }
+        } else {
+            for (int64_t j = i + 1; j < n; j++) {
+                if (!(dens[j] > dmin)) continue;
+                if (d2_periodic(pos, i, j, L) < l2) uf_union(parent, i, j);
+            }
+        }
+    }
+    int64_t groups = 0;
+    for (int64_t i = 0; i < n; i++) {
+        if (!(dens[i] > dmin)) { l0[i] = 0; continue; }
+        int64_t r = uf_find(parent, i);
+        if (r == i) groups++;
+        l0[i] = (int32_t)(r + 1);
+    }
+    if (use_grid) grid_free(&g);
+    free(parent);
+    *n_groups = groups;
+    return 0;
+}
+
+/* ---------------------------------------------------------------- CompaSO */
+
+typedef struct { int64_t nucleus; int64_t ienc; int64_t count; } halo_t;
+
+typedef struct {
+    const float *pos;
+    const double *dens;
+    const int32_t *l0;
+    double L;
+    const double *d;
+    const grid_t *g;       /* cell list with cells >= b, or NULL (brute force) */
+    int64_t n;
+} ctx_t;
+
+/* "Denser" in the total order used for nuclei: higher density first, ties
+ * broken by lower original index. */
+static int denser(const double *dens, int64_t a, int64_t b)
+{
+    if (dens[a] != dens[b]) return dens[a] > dens[b];
+    return a < b;
+}
+
+/* Step 2 peak condition: q is denser than every other particle of its L0 group
+ * (eligible or not) within the kernel radius b. */
+static int is_local_peak(const ctx_t *c, int64_t q)
+{
+    double b2 = c->d[D_B2];
+    int32_t lab = c->l0[q];
+    if (c->g) {
+        int64_t st[27];
+        grid_stencil(c->g, c->pos, q, st);
+        for (int t = 0; t < 27; t++)
+            for (int64_t k = c->g->start[st[t]]; k < c->g->start[st[t] + 1]; k++) {
+                int64_t j = c->g->items[k];
+                if (j == q || c->l0[j] != lab) continue;
+                if (d2_periodic(c->pos, q, j, c->L) < b2 && denser(c->dens, j, q)) return 0;
+            }
+    } else {
+        for (int64_t j = 0; j < c->n; j++) {
+            if (j == q || c->l0[j] != lab) continue;
+            if (d2_periodic(c->pos, q, j, c->L) < b2 && denser(c->dens, j, q)) return 0;
+        }
+    }
+    return 1;
+}
+
+static int cmp_double(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+typedef struct { double dens; int64_t idx; int64_t t; } rank_t;
+
+/* Descending density, ties by ascending original index (the "denser" order). */
+static int cmp_rank(const void *a, const void *b)
+{
+    const rank_t *x = (const rank_t *)a, *y = (const rank_t *)b;
+    if (x->dens != y->dens) return x->dens > y->dens ? -1 : 1;
+    return (x->idx > y->idx) - (x->idx < y->idx);
+}
+
+/* One L0 group, literally as the sequential loop of Sec. 2.2.2:
+ *   repeat: take the densest particle that is still eligible, at or above the
+ *   nucleation floor (step 4) and a local peak within b (step 2; the densest
+ *   particle of the group always is one, step 1); find R from ALL particles of
+ *   the group (sorted squared distances: the enclosed count at sorted position k
+ *   is k, and R_L1 is the innermost radius where the enclosed density falls
+ *   below Delta_L1); assign the particles inside R if unassigned or if their
+ *   model enclosed density Delta_L1 R^2/r^2 w.r.t. the new nucleus is at least
+ *   c_Roche times that w.r.t. their current halo (step 3, Sec. 2.3.2); mark
+ *   the particles inside alpha R ineligible (step 1).
+ * mem[0..m) are the members' original indices.  Returns the halos in creation
+ * order; owner[t] is the local halo index of mem[t] (-1: none). */
+static int64_t compaso_group(const ctx_t *c, const int64_t *mem, int64_t m,
+                             halo_t **halos_out, int64_t *owner)
+{
+    const double *d = c->d;
+    double K2 = d[D_K2], A6 = d[D_A6], C3 = d[D_C3], floor_nuc = d[D_FLOOR];
+    rank_t *order = (rank_t *)malloc((size_t)m * sizeof(rank_t));
+    unsigned char *elig = (unsigned char *)malloc((size_t)m);
+    signed char *peak = (signed char *)malloc((size_t)m);   /* -1 unknown, 0, 1 */
+    double *e = (double *)malloc((size_t)m * sizeof(double));
+    double *es = (double *)malloc((size_t)m * sizeof(double));
+    double *eown = (double *)malloc((size_t)m * sizeof(double));
+    int64_t *iown = (int64_t *)malloc((size_t)m * sizeof(int64_t));
+    int64_t cap = 4, nh = 0;
+    halo_t *halos = (halo_t *)malloc((size_t)cap * sizeof(halo_t));
+    for (int64_t t = 0; t < m; t++) {
+        order[t].dens = c->dens[mem[t]];
+        order[t].idx = mem[t];
+        order[t].t = t;
+        elig[t] = 1;
+        peak[t] = -1;
+        owner[t] = -1;
+    }
+    /* the search order of steps 1-2: descending density */
+    qsort(order, (size_t)m, sizeof(rank_t), cmp_rank);
+    for (;;) {
+        int64_t cand = -1;
+        for (int64_t r = 0; r < m; r++) {
+            int64_t t = order[r].t;
+            int64_t q = order[r].idx;
+            if (!(order[r].dens >= floor_nuc)) break;  /* step 4: stop below the floor */
+            if (!elig[t]) continue;
+            if (peak[t] < 0) peak[t] = (signed char)is_local_peak(c, q);
+            if (peak[t]) { cand = q; break; }
+        }
+        if (cand < 0) break;
+        /* R from all particles of the group, by sorting squared distances. */
+        for (int64_t t = 0; t < m; t++) {
+            e[t] = d2_periodic(c->pos, cand, mem[t], c->L);
+            es[t] = e[t];
+        }
+        qsort(es, (size_t)m, sizeof(double), cmp_double);
+        int64_t ienc = m;   /* no crossing inside the group: R bounded by the L0 edge */
+        for (int64_t k = 1; k < m; k++)
+            if (K2 * e3(es[k]) > ii(k)) { ienc = k; break; }
+        if (nh == cap) { cap *= 2; halos = (halo_t *)realloc(halos, (size_t)cap * sizeof(halo_t)); }
+        int64_t h = nh++;
+        halos[h].nucleus = cand;
+        halos[h].ienc = ienc;
+        halos[h].count = 0;
+        double iih = ii(ienc);
+        for (int64_t t = 0; t < m; t++) {
+            double ee = e[t];
+            if (K2 * e3(ee) < iih) {                       /* inside R */
+                if (owner[t] < 0) {
+                    owner[t] = h; eown[t] = ee; iown[t] = ienc;
+                } else {
+                    double lhs = iih * e3(eown[t]);
+                    double rhs = (C3 * ii(iown[t])) * e3(ee);
+                    if (lhs >= rhs) { owner[t] = h; eown[t] = ee; iown[t] = ienc; }
+                }
+            }
+            if (K2 * e3(ee) < A6 * iih) elig[t] = 0;      /* inside alpha R */
+        }
+    }
+    for (int64_t t = 0; t < m; t++)
+        if (owner[t] >= 0) halos[owner[t]].count++;
+    free(order); free(elig); free(peak);
+    free(e); free(es); free(eown); free(iown);
+    *halos_out = halos;
+    return nh;
+}
+
+/* CompaSO L1 over all L0 groups, then the output cut (N >= n_l1_min).
+ * Outputs (host arrays):
+ *   halo_id[n]   1 + nucleus original index of the particle's halo if kept, else 0
+ *   owner_all[n] (optional) 1 + nucleus index of the owning halo before the cut
+ *   table (optional, capacity cap, ascending id): t_id, t_nucleus, t_l0, t_n, t_ienc
+ *   *n_halos     number of kept halos (may exceed cap; then the table is partial)
+ *   *n_found     number of halos before the cut
+ *   found list (optional, capacity fcap): every halo before the cut, grouped by
+ *                L0 group (ascending label) and in creation order inside a group:
+ *                f_nucleus, f_ienc, f_count, f_l0
+ * dens may be any density field (e.g. the GPU's values) and l0 any L0 labelling
+ * with the 1 + min-index convention. */
+int orc_compaso(int64_t n, const float *pos, const double *p, const double *dens,
+                const int32_t *l0, int mode, int32_t *halo_id, int32_t *owner_all,
+                int64_t cap, int32_t *t_id, int32_t *t_nucleus, int32_t *t_l0,
+                int32_t *t_n, int32_t *t_ienc, int64_t *n_halos, int64_t *n_found,
+                int64_t fcap, int32_t *f_nucleus, int32_t *f_ienc, int32_t *f_count,
+                int32_t *f_l0)
+{
+    double d[D_COUNT];
+    if (orc_derive(p, n, d)) return 1;
+    int64_t nmin = (int64_t)p[P_NL1MIN];
+    /* group members by label (counting sort on label-1; members ascending) */
+    int64_t *cnt = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    int64_t *mem = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    if (!cnt || !mem) { free(cnt); free(mem); return 2; }
+    for (int64_t i = 0; i < n; i++) if (l0[i] > 0) cnt[l0[i]]++;   /* l0 in 1..n */
+    int64_t ngroups = 0;
+    for (int64_t k = 1; k <= n; k++) if (cnt[k]) ngroups++;
+    int64_t *gstart = (int64_t *)malloc((size_t)(ngroups + 1) * sizeof(int64_t));
+    int64_t *glab = (int64_t *)malloc((size_t)(ngroups > 0 ? ngroups : 1) * sizeof(int64_t));
+    int64_t *off = (int64_t *)calloc((size_t)n + 2, sizeof(int64_t));
+    if (!gstart || !glab || !off) { free(cnt); free(mem); free(gstart); free(glab); free(off); return 2; }
+    int64_t gi = 0, acc = 0;
+    for (int64_t k = 1; k <= n; k++)
+        if (cnt[k]) { glab[gi] = k; gstart[gi] = acc; off[k] = acc; acc += cnt[k]; gi++; }
+    gstart[ngroups] = acc;
+    for (int64_t i = 0; i < n; i++) if (l0[i] > 0) mem[off[l0[i]]++] = i;
+    free(off);
+    free(cnt);
+
+    grid_t g;
+    int use_grid = 0;
+    if (mode == 1) {
+        int rc = grid_build(&g, n, pos, p[P_BOX], d[D_B]);
+        if (rc == 2) { free(mem); free(gstart); free(glab); return 2; }
+        use_grid = rc == 0;
+    }
+    ctx_t c = { pos, dens, l0, p[P_BOX], d, use_grid ? &g : NULL, n };
+
+    halo_t **gh = (halo_t **)calloc((size_t)(ngroups > 0 ? ngroups : 1), sizeof(halo_t *));
+    int64_t *gnh = (int64_t *)calloc((size_t)(ngroups > 0 ? ngroups : 1), sizeof(int64_t));
+    int64_t *own = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    for (int64_t i = 0; i < n; i++) { halo_id[i] = 0; if (owner_all) owner_all[i] = 0; }
+
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < ngroups; k++) {
+        int64_t s = gstart[k], m = gstart[k + 1] - s;
+        gnh[k] = compaso_group(&c, mem + s, m, &gh[k], own + s);
+    }
+
+    /* output cut and ids; table ascending by id via a flag sweep over indices */
+    int64_t found = 0, kept = 0;
+    unsigned char *keep_flag = (unsigned char *)calloc((size_t)(n > 0 ? n : 1), 1);
+    int32_t *hN = (int32_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int32_t));
+    int32_t *hI = (int32_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int32_t));
+    int32_t *hL = (int32_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int32_t));
+    for (int64_t k = 0; k < ngroups; k++) {
+        int64_t s = gstart[k], m = gstart[k + 1] - s;
+        for (int64_t h = 0; h < gnh[k]; h++) {
+            halo_t *H = &gh[k][h];
+            if (found + h < fcap) {
+                if (f_nucleus) f_nucleus[found + h] = (int32_t)H->nucleus;
+                if (f_ienc) f_ienc[found + h] = (int32_t)H->ienc;
+                if (f_count) f_count[found + h] = (int32_t)H->count;
+                if (f_l0) f_l0[found + h] = (int32_t)glab[k];
+            }
+            if (H->count >= nmin) {
+                keep_flag[H->nucleus] = 1;
+                hN[H->nucleus] = (int32_t)H->count;
+                hI[H->nucleus] = (int32_t)H->ienc;
+                hL[H->nucleus] = (int32_t)glab[k];
+                kept++;
+            }
+        }
+        for (int64_t t = 0; t < m; t++) {
+            int64_t q = mem[s + t];
+            int64_t o = own[s + t];
+            if (o < 0) continue;
+            int64_t nuc = gh[k][o].nucleus;
+            if (owner_all) owner_all[q] = (int32_t)(nuc + 1);
+            if (gh[k][o].count >= nmin) halo_id[q] = (int32_t)(nuc + 1);
+        }
+        found += gnh[k];
+        free(gh[k]);
+    }
+    int64_t w = 0;
+    for (int64_t i = 0; i < n; i++) {
+        if (!keep_flag[i]) continue;
+        if (w < cap) {
+            if (t_id) t_id[w] = (int32_t)(i + 1);
+            if (t_nucleus) t_nucleus[w] = (int32_t)i;
+            if (t_l0) t_l0[w] = hL[i];
+            if (t_n) t_n[w] = hN[i];
+            if (t_ienc) t_ienc[w] = hI[i];
+        }
+        w++;
+    }
+    *n_halos = kept;
+    if (n_found) *n_found = found;
+    free(keep_flag); free(hN); free(hI); free(hL);
+    free(gh); free(gnh); free(own);
+    if (use_grid) grid_free(&g);
+    free(mem); free(gstart); free(glab);
+    return 0;
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_threads(int k)
+{
+#ifdef _OPENMP
+    if (k > 0) omp_set_num_threads(k);
+#else
+    (void)k;
+#endif
+}
