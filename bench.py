@@ -1,0 +1,143 @@
+"""Benchmark of the CompaSO group-finding pass on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload plain256]
+                [--no-cpu-baseline] [--cpu-seconds S]
+
+A step is one hf_find call (binning, kernel density, L0 FoF, CompaSO L1 and the
+output cut) over the whole box, with positions already resident in HBM.  Prints
+one JSON line with whole-job throughput in particles/s, the roofline of the
+dominant kernel (its average duration measured with HIP events on the stream it
+runs on, over the timed steps) and the FP64 CPU oracle timed on a bounded
+sample of the same generator.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "halo-finding particles/sec at 1 MI355X (batched+served vs plain); p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+FLOPS_PER_PAIR = 11          # 3 sub + 3 fma (6 flops) + max + add
+
+WORKLOADS = {
+    "plain256": "256^3 = 16,777,216 FP32 particles, periodic box 256, half uniform background, "
+                "half NFW haloes (c=8, R200) of 35..20000 particles (dn/dN ~ N^-1.9), 20% of "
+                "haloes in pairs at 0.5-1.5 R200; b=0.4, l=0.25, Delta_L0=60, Delta_L1=200, N>=35",
+    "plain64": "64^3 = 262,144 FP32 particles, periodic box 64, same generator without pairs",
+}
+
+
+def _stage_models(n, stats, pairs):
+    """Algorithmic work per launch of each stage (roofline)."""
+    ncell = stats["n_cells"]
+    return {
+        # density: useful pairs x 11 flops, FP32 vector ALU
+        "density": ("alu", pairs * FLOPS_PER_PAIR / 1e12, FP32_PEAK_TFLOPS, "TFLOP/s"),
+        # binning: read xyz 12 + key/ticket 16 + sorted float4 x2 32 + reads of keys 8 = 68 B/particle,
+        # plus count/offset arrays 12 B per cell
+        "bin": ("hbm", (68.0 * n + 12.0 * ncell) / 1e9, HBM_PEAK_GBS, "GB/s"),
+        # FoF: read float4 x2 + density for every particle (36 B), parent r/w 8 B
+        "fof": ("hbm", 44.0 * n / 1e9, HBM_PEAK_GBS, "GB/s"),
+    }
+
+
+def cpu_baseline(target_s: float):
+    import numpy as np  # noqa: F401
+    import oracle
+    from paper_2110_11408_amd import synth
+    oracle.build(force=False)
+    threads = oracle.num_threads()
+    done = 0
+    t0 = time.perf_counter()
+    k = 0
+    while True:
+        pos, L, _ = synth.named_box("plain64", k)
+        t = time.perf_counter()
+        oracle.find(pos, box=L)
+        done += len(pos)
+        k += 1
+        if time.perf_counter() - t0 > target_s or k >= 64:
+            break
+    wall = time.perf_counter() - t0
+    return {"value": done / wall, "unit": "particles/s", "cores": threads, "kind": "oracle",
+            "sample": f"full FP64 oracle pass (density, L0 FoF, literal CompaSO, cut) on {k} "
+                      f"64^3 boxes of the same generator ({done} particles, {wall:.1f} s); "
+                      "the 256^3 box itself takes minutes on the host"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="plain256", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (this build is "
+              "single-GPU: the sharded design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2110_11408_amd import _lib, synth
+    from paper_2110_11408_amd.api import Context
+
+    pos, L, _ = synth.named_box(args.workload)
+    n = len(pos)
+    dev = torch.device("cuda:0")
+    pos_d = torch.from_numpy(pos).to(dev)
+    p = _lib.default_params(box=L)
+    ctx = Context(0)
+    pairs = ctx.count_pairs(pos_d, p)
+    cap = max(1024, n // 64)
+    for _ in range(args.warmup):
+        ctx.find(pos_d, p, halos_cap=cap)
+    torch.cuda.synchronize()
+    keys = ("ms_bin", "ms_density", "ms_fof", "ms_segment", "ms_candidates", "ms_accept",
+            "ms_assign", "ms_output", "ms_total")
+    acc = {k: 0.0 for k in keys}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = ctx.find(pos_d, p, halos_cap=cap)
+        st = ctx.stats()
+        for k in keys:
+            acc[k] += st[k]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall * 1e3 / args.steps
+    stages = {k[3:]: acc[k] / args.steps for k in keys}
+    models = _stage_models(n, st, pairs)
+    dom = max((k for k in models), key=lambda k: stages[k])
+    bound, work, peak, unit = models[dom]
+    achieved = work / (stages[dom] / 1e3)
+    roof = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak, "traffic": None}
+    res = {
+        "metric": METRIC, "value": n / (ms_step / 1e3), "unit": "particles/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
+                   "n_particles": n, "box": L, "path": "plain (hf_find, one box per call)"},
+        "roofline": roof,
+        "stages_ms": stages,
+        "counts": {"pairs_within_b": pairs, "n_cells": st["n_cells"], "n_members": st["n_members"],
+                   "n_groups": st["n_groups"], "n_candidates": st["n_candidates"],
+                   "n_found": st["n_found"], "n_halos": out["n_halos"]},
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,159 @@
+/*
+ * hf.h -- C ABI of libhf, the MI355X (gfx950) CompaSO group-finding library.
+ *
+ * The library implements the on-the-fly group-finding pass of Hadzhiyska et al.,
+ * "CompaSO: A new halo finder for competitive assignment to spherical
+ * overdensities" (Sec. 2.2 and 2.3 of the paper):
+ *
+ *   1. kernel density of every particle, W(r) = 1 - r^2/b^2          (Sec. 2.2.1)
+ *   2. L0 friends-of-friends over the particles denser than Delta_L0,min (Sec. 2.2.1)
+ *   3. CompaSO L1 inside every L0 group: nuclei in descending density, the
+ *      enclosed-density radius R_L1, eligibility inside alpha R_L1 and the
+ *      competitive reassignment with c_Roche                          (Sec. 2.2.2)
+ *   4. the output cut at the minimum L1 halo size                      (Sec. 2.2.2, Table 1)
+ *
+ * Conventions shared by every entry point
+ *   - Array arguments named pos, density, l0_id, halo_id and halos are DEVICE
+ *     pointers owned by the caller (for instance torch tensors on the GPU).  The
+ *     library never frees or retains them beyond the call.
+ *   - pos is float32 [n][3] (x, y, z interleaved, C-contiguous) with coordinates
+ *     in [0, box).  Coordinates outside that range are rejected.
+ *   - Lengths b_kernel and l_fof are given in units of the mean interparticle
+ *     spacing l_mean = nbar^(-1/3) (as in Table 1); nbar is mean_density, or
+ *     n / box^3 when mean_density <= 0.
+ *   - Densities are in units of the mean density (a uniform field has Delta = 1).
+ *   - Labels are int32: 0 means "none"; otherwise 1 + an original particle index
+ *     (L0: the smallest index of the group; halo: the index of its nucleus).
+ *   - Pointers named n_groups / n_halos are HOST pointers; filling them makes the
+ *     call wait for the stream.  All other work is enqueued on `stream` (a
+ *     hipStream_t; NULL = the default stream).
+ *   - Argument errors are reported before anything is enqueued.  Device errors
+ *     return HF_ERR_DEVICE and hf_last_error() gives the HIP error text.
+ *   - An hf_ctx owns the scratch memory (cell lists, union-find, queues); it grows
+ *     on demand with hipMalloc and is released by hf_destroy.  A context is not
+ *     thread-safe: use one context per host thread / stream.
+ */
+#ifndef HF_H
+#define HF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HF_OK = 0,
+    HF_ERR_INVALID = 1,     /* bad argument (n < 0, box <= 0, NaN parameter, box too small) */
+    HF_ERR_NOMEM = 2,       /* device allocation failed */
+    HF_ERR_CAPACITY = 3,    /* halos_cap too small: *n_halos holds the required count */
+    HF_ERR_DEVICE = 4,      /* a HIP call failed */
+    HF_ERR_UNSUPPORTED = 5  /* no usable gfx950 device */
+} hf_status;
+
+/* Parameters; Table 1 names in brackets.  hf_default_params() gives the paper's
+ * Einstein-de Sitter values. */
+typedef struct {
+    double box;            /* periodic box side L [BoxSize]                           */
+    double mean_density;   /* nbar; <= 0 means n / box^3                              */
+    double b_kernel;       /* kernel radius b, units of l_mean: 0.4 [DensityKernelRad]*/
+    double l_fof;          /* L0 linking length, units of l_mean: 0.25 [FoFLinkingLength] */
+    double delta_l0_min;   /* L0 density threshold: 60 [L0DensityThreshold]           */
+    double delta_l1;       /* L1 SO threshold: 200 [SODensityL1]                      */
+    double alpha_elig;     /* eligibility radius / R_L1: 0.8 [SO_alpha_eligible]      */
+    double c_roche;        /* reassignment factor: 2 [SO_RocheCoeff]                  */
+    double n_new_min;      /* nucleation floor from a SIS of this many particles: 35
+                              [SO_NPForMinDensity]                                    */
+    double particle_mass;  /* mass per particle for hf_halo.mass: 1                   */
+    int32_t n_l1_min;      /* smallest L1 halo kept in the output: 35 [MinL1HaloNP]   */
+    int32_t self_count;    /* 1 adds W(0) = 1 (the particle itself) to its density; 0 */
+} hf_params;
+
+/* One output halo.  Rows of the halo table are sorted by ascending id. */
+typedef struct {
+    int32_t id;          /* 1 + nucleus (the value written to halo_id)               */
+    int32_t nucleus;     /* original index of the nucleus particle (SO_central_particle) */
+    int32_t l0_id;       /* label of the L0 group holding the halo                    */
+    int32_t n;           /* number of member particles N (>= n_l1_min)                */
+    int32_t n_enclosed;  /* particles of the L0 group inside R_L1 (enclosed count i)  */
+    float x, y, z;       /* halo centre = nucleus position                            */
+    float r;             /* R_L1 = (i / ((4 pi/3) Delta_L1 nbar))^(1/3)               */
+    float mass;          /* n * particle_mass                                         */
+} hf_halo;
+
+/* Per-call statistics of the last call on a context (device event timings of
+ * each stage on the call's stream, and work counters). */
+typedef struct {
+    float ms_bin, ms_density, ms_fof, ms_segment, ms_candidates, ms_accept, ms_assign,
+          ms_output, ms_total;
+    int64_t n_cells;          /* cells of the binning grid                      */
+    int64_t n_members;        /* particles above delta_l0_min                   */
+    int64_t n_groups;         /* L0 groups (including single particles)         */
+    int64_t n_candidates;     /* nucleus candidates (local peaks above the floor) */
+    int64_t n_found;          /* halos before the output cut                    */
+    int64_t n_halos;          /* halos after the cut                            */
+} hf_stats;
+
+typedef struct hf_ctx hf_ctx;
+
+/* Fill p with the paper's defaults (Table 1, Einstein-de Sitter thresholds). */
+void hf_default_params(hf_params *p);
+
+/* Derived constants for n particles under p, computed on the host exactly as the
+ * kernels use them (out[11]): nbar, b, l, b^2, l^2, density normalisation
+ * 15/(8 pi b^3 nbar) (App. B.2), K = (4 pi/3) Delta_L1 nbar (so that R^3 = i/K,
+ * Sec. 2.2.2 step 1), K^2, the nucleation floor (smoothed centre of a SIS with
+ * n_new_min particles inside its 200x-mean radius, Sec. 2.2.2 step 4 and
+ * App. B.2), alpha^6 and c_Roche^3. */
+hf_status hf_derived(const hf_params *p, int64_t n, double *out);
+
+/* Create a context on HIP device `device`.  Fails with HF_ERR_UNSUPPORTED when the
+ * device is not gfx950. */
+hf_status hf_create(hf_ctx **ctx, int device);
+void hf_destroy(hf_ctx *ctx);
+const char *hf_last_error(const hf_ctx *ctx);
+hf_status hf_get_stats(const hf_ctx *ctx, hf_stats *out);
+
+/* Step 1 (Sec. 2.2.1): density[i] = norm * sum_{j != i, r_ij < b} (1 - r_ij^2/b^2)
+ * over periodic minimum images; norm makes a uniform field average 1 (App. B.2).
+ * density: float32 [n], original particle order. */
+hf_status hf_density(hf_ctx *ctx, const float *pos, int64_t n, const hf_params *p,
+                     float *density, void *stream);
+
+/* Step 2 (Sec. 2.2.1): L0 groups = friends-of-friends with linking length l over
+ * the particles with density > delta_l0_min (two members are friends when their
+ * separation is less than l).  density: float32 [n] (any field, e.g. from
+ * hf_density).  l0_id: int32 [n], 1 + smallest original index of the group,
+ * 0 for particles below the threshold.  *n_groups (host, may be NULL): number of
+ * groups including single-particle ones. */
+hf_status hf_l0_fof(hf_ctx *ctx, const float *pos, const float *density, int64_t n,
+                    const hf_params *p, int32_t *l0_id, int64_t *n_groups, void *stream);
+
+/* Step 3 + 4 (Sec. 2.2.2): CompaSO L1 inside every L0 group given by l0_id (any
+ * labelling with values in [0, n], 0 = outside every group, equal values = one
+ * group), then the cut N >= n_l1_min.  halo_id: int32 [n], 1 + nucleus index of
+ * the particle's halo, 0 if none.  halos: device array of halos_cap rows,
+ * ascending id.  *n_halos (host): number of halos kept.  If it exceeds halos_cap
+ * the call returns HF_ERR_CAPACITY; halo_id is still written, halos is not. */
+hf_status hf_compaso(hf_ctx *ctx, const float *pos, const float *density,
+                     const int32_t *l0_id, int64_t n, const hf_params *p, int32_t *halo_id,
+                     hf_halo *halos, int64_t halos_cap, int64_t *n_halos, void *stream);
+
+/* Measurement helper: number of ordered pairs (i, j), j != i, closer than b (the
+ * useful pair count of step 1, P_b = sum_i #{j != i : r_ij < b}) into *pairs
+ * (host).  Used to express the density kernel's work in pair-interactions. */
+hf_status hf_count_pairs(hf_ctx *ctx, const float *pos, int64_t n, const hf_params *p,
+                         int64_t *pairs, void *stream);
+
+/* The whole pass: density, L0 FoF and CompaSO L1 with the output cut, sharing one
+ * cell binning.  Outputs as in the three calls above; density and l0_id may be
+ * NULL when not wanted. */
+hf_status hf_find(hf_ctx *ctx, const float *pos, int64_t n, const hf_params *p,
+                  float *density, int32_t *l0_id, int32_t *halo_id, hf_halo *halos,
+                  int64_t halos_cap, int64_t *n_halos, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HF_H */

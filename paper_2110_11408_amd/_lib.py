@@ -1,0 +1,106 @@
+"""ctypes binding of libhf (argument marshalling only).
+
+Every step of the pass runs in the HIP library; this module converts torch
+tensors to device pointers and the current HIP stream, and raises on errors.
+There is no fallback: without the built library, or without a gfx950 GPU, the
+calls fail.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhf.so")
+
+HF_OK, HF_ERR_INVALID, HF_ERR_NOMEM, HF_ERR_CAPACITY, HF_ERR_DEVICE, HF_ERR_UNSUPPORTED = range(6)
+STATUS = {0: "HF_OK", 1: "HF_ERR_INVALID", 2: "HF_ERR_NOMEM", 3: "HF_ERR_CAPACITY",
+          4: "HF_ERR_DEVICE", 5: "HF_ERR_UNSUPPORTED"}
+
+EXPORTS = ["hf_default_params", "hf_derived", "hf_create", "hf_destroy", "hf_last_error",
+           "hf_get_stats", "hf_density", "hf_l0_fof", "hf_compaso", "hf_find", "hf_count_pairs"]
+
+
+class HfParams(ctypes.Structure):
+    _fields_ = [("box", ctypes.c_double), ("mean_density", ctypes.c_double),
+                ("b_kernel", ctypes.c_double), ("l_fof", ctypes.c_double),
+                ("delta_l0_min", ctypes.c_double), ("delta_l1", ctypes.c_double),
+                ("alpha_elig", ctypes.c_double), ("c_roche", ctypes.c_double),
+                ("n_new_min", ctypes.c_double), ("particle_mass", ctypes.c_double),
+                ("n_l1_min", ctypes.c_int32), ("self_count", ctypes.c_int32)]
+
+
+class HfHalo(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int32), ("nucleus", ctypes.c_int32), ("l0_id", ctypes.c_int32),
+                ("n", ctypes.c_int32), ("n_enclosed", ctypes.c_int32), ("x", ctypes.c_float),
+                ("y", ctypes.c_float), ("z", ctypes.c_float), ("r", ctypes.c_float),
+                ("mass", ctypes.c_float)]
+
+
+class HfStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_float) for k in
+                ("ms_bin", "ms_density", "ms_fof", "ms_segment", "ms_candidates", "ms_accept",
+                 "ms_assign", "ms_output", "ms_total")] + \
+               [(k, ctypes.c_int64) for k in
+                ("n_cells", "n_members", "n_groups", "n_candidates", "n_found", "n_halos")]
+
+
+HALO_FIELDS = [f[0] for f in HfHalo._fields_]
+HALO_WORDS = ctypes.sizeof(HfHalo) // 4   # 10 x 32-bit words per row
+
+_lib = None
+
+
+class HfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def load(path: str = LIB_PATH):
+    """Load libhf.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it with paper_2110_11408_amd/build.py")
+        lib = ctypes.CDLL(path)
+        P, I64, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+        PP = ctypes.POINTER(HfParams)
+        lib.hf_default_params.argtypes = [PP]
+        lib.hf_default_params.restype = None
+        lib.hf_derived.argtypes = [PP, I64, P]
+        lib.hf_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), I32]
+        lib.hf_destroy.argtypes = [P]
+        lib.hf_destroy.restype = None
+        lib.hf_last_error.argtypes = [P]
+        lib.hf_last_error.restype = ctypes.c_char_p
+        lib.hf_get_stats.argtypes = [P, ctypes.POINTER(HfStats)]
+        lib.hf_density.argtypes = [P, P, I64, PP, P, P]
+        lib.hf_l0_fof.argtypes = [P, P, P, I64, PP, P, P, P]
+        lib.hf_compaso.argtypes = [P, P, P, P, I64, PP, P, P, I64, P, P]
+        lib.hf_find.argtypes = [P, P, I64, PP, P, P, P, P, I64, P, P]
+        lib.hf_count_pairs.argtypes = [P, P, I64, PP, P, P]
+        for name in ("hf_derived", "hf_create", "hf_get_stats", "hf_density", "hf_l0_fof",
+                     "hf_compaso", "hf_find", "hf_count_pairs"):
+            getattr(lib, name).restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def default_params(**kw) -> HfParams:
+    p = HfParams()
+    load().hf_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def derived(p: HfParams, n: int) -> dict:
+    out = (ctypes.c_double * 11)()
+    st = load().hf_derived(ctypes.byref(p), int(n), out)
+    if st:
+        raise HfError(st, "invalid parameters")
+    names = ["nbar", "b", "l", "b2", "l2", "norm", "K", "K2", "floor", "A6", "C3"]
+    return dict(zip(names, list(out)))

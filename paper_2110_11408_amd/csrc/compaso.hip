@@ -1,0 +1,495 @@
+// CompaSO L1 inside every L0 group (Sec. 2.2.2) and the output cut.
+//
+// The paper's per-group loop is sequential (find a nucleus, assign, mark
+// ineligible, repeat).  It decomposes exactly into data-parallel stages because
+//   - the peak condition and the nucleation floor depend only on the densities
+//     (steps 2 and 4), so the candidate set is fixed before the loop;
+//   - R_L1 of a nucleus uses ALL particles of the L0 group and is independent of
+//     earlier assignments (steps 1-2);
+//   - eligibility depends only on earlier nuclei and their R (step 1);
+//   - a particle's reassignment depends only on its current halo (step 3).
+// Hence: candidates are found in parallel; one workgroup per group walks its
+// candidates in descending density, rejects those inside alpha R of an
+// accepted nucleus and computes R for the accepted ones; finally every
+// particle folds over its group's accepted halos in creation order.
+//
+// R without sorting (Sec. 2.3.3: the enclosed mass at sorted position k is k,
+// R_L1 is where the enclosed density first drops below Delta_L1).  With
+// T(e) = K^2 e^3 for a squared distance e (R^3 = i/K), the sorted definition
+// "first k >= 1 whose k-th smallest T exceeds k^2" is equivalent to
+// "first k >= 1 with C(k) <= k", where C(k) counts particles with T <= k^2.
+// C is the prefix sum of a histogram over integer buckets
+// ceil(sqrt(T)) (computed exactly with integer-square comparisons), so each
+// accepted nucleus costs one pass over the group plus a prefix scan.
+#include "hf_internal.h"
+
+namespace hf {
+
+namespace {
+
+inline dim3 grid(int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); }
+
+__device__ __forceinline__ int32_t ldi(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ldu(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void stu(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ------------------------------------------------------------ segmentation
+
+__global__ __launch_bounds__(kBlock) void k_seg_count(int64_t n, const int32_t *__restrict__ gkey,
+                                                      uint32_t *__restrict__ gcnt) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int k = gkey[i];
+    if (k >= 0) atomicAdd(&gcnt[k], 1u);
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_flags(int64_t n, const uint32_t *__restrict__ gcnt,
+                                                      uint32_t *__restrict__ gflag) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    gflag[k] = gcnt[k] > 0 ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_groups(int64_t n, const uint32_t *__restrict__ gcnt,
+                                                       const uint32_t *__restrict__ goff,
+                                                       const uint32_t *__restrict__ gidx,
+                                                       int32_t *__restrict__ g_start,
+                                                       int32_t *__restrict__ g_size,
+                                                       int32_t *__restrict__ g_label) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    uint32_t c = gcnt[k];
+    if (!c) return;
+    uint32_t g = gidx[k];
+    g_start[g] = (int32_t)goff[k];
+    g_size[g] = (int32_t)c;
+    g_label[g] = (int32_t)k + 1;
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_scatter(int64_t n, const int32_t *__restrict__ gkey,
+                                                        const uint32_t *__restrict__ goff,
+                                                        const uint32_t *__restrict__ gidx,
+                                                        uint32_t *__restrict__ gfill,
+                                                        int32_t *__restrict__ mem,
+                                                        int32_t *__restrict__ gid_of) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int k = gkey[i];
+    if (k < 0) {
+        gid_of[i] = -1;
+        return;
+    }
+    uint32_t slot = goff[k] + atomicAdd(&gfill[k], 1u);
+    mem[slot] = (int32_t)i;
+    gid_of[i] = (int32_t)gidx[k];
+}
+
+// --------------------------------------------------------------- candidates
+// Step 2 peak condition + step 4 floor: density >= floor and no denser particle
+// of the same L0 group (eligible or not) within b.
+__global__ __launch_bounds__(kBlock) void k_candidates(int64_t n, Geo g, const float4 *__restrict__ sloc,
+                                                       const float4 *__restrict__ spos,
+                                                       const uint32_t *__restrict__ off,
+                                                       const float *__restrict__ dens_s,
+                                                       const int32_t *__restrict__ gkey,
+                                                       const int32_t *__restrict__ gid_of,
+                                                       uint32_t *__restrict__ gccnt,
+                                                       int32_t *__restrict__ cflag) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    cflag[i] = 0;
+    const int key = gkey[i];
+    if (key < 0) return;
+    const float di = dens_s[i];
+    if (!((double)di >= g.floor_nuc)) return;
+    const float4 li = sloc[i];
+    const float4 pi = spos[i];
+    const uint32_t oi = orig_of(pi);
+    const uint32_t c = __float_as_uint(li.w);
+    const int nc = g.nc;
+    const int cx = (int)(c % (uint32_t)nc), cy = (int)((c / (uint32_t)nc) % (uint32_t)nc),
+              cz = (int)(c / ((uint32_t)nc * (uint32_t)nc));
+    for (int oz = -1; oz <= 1; oz++) {
+        const int z = wrapc(cz + oz, nc);
+        const float zs = li.z - (float)oz * g.cellb;
+        for (int oy = -1; oy <= 1; oy++) {
+            const int y = wrapc(cy + oy, nc);
+            const float ys = li.y - (float)oy * g.cellb;
+            const uint32_t row = ((uint32_t)z * (uint32_t)nc + (uint32_t)y) * (uint32_t)nc;
+            for (int ox = -1; ox <= 1; ox++) {
+                const int x = wrapc(cx + ox, nc);
+                const float xs = li.x - (float)ox * g.cellb;
+                const uint32_t nb = row + (uint32_t)x;
+                const uint32_t a = off[nb], b = off[nb + 1];
+                for (uint32_t j = a; j < b; j++) {
+                    const float dj = dens_s[j];
+                    if (dj < di) continue;
+                    if (gkey[j] != key || (int64_t)j == i) continue;
+                    const float4 pj = spos[j];
+                    if (!denser(dj, orig_of(pj), di, oi)) continue;
+                    const float4 lj = sloc[j];
+                    const float dx = lj.x - xs, dy = lj.y - ys, dz = lj.z - zs;
+                    const float d2f = dx * dx + dy * dy + dz * dz;
+                    if (d2f >= g.b2b_hi) continue;
+                    if (d2f >= g.b2b_lo && !(d2_exact(pi, pj, g.L, g.half) < g.b2)) continue;
+                    return;  // a denser particle of the group lies within b
+                }
+            }
+        }
+    }
+    cflag[i] = 1;
+    atomicAdd(&gccnt[gid_of[i]], 1u);
+}
+
+__global__ __launch_bounds__(kBlock) void k_cand_scatter(int64_t n, const int32_t *__restrict__ cflag,
+                                                         const int32_t *__restrict__ gid_of,
+                                                         const uint32_t *__restrict__ gcoff,
+                                                         uint32_t *__restrict__ gcfill,
+                                                         int32_t *__restrict__ cand) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !cflag[i]) return;
+    int gi = gid_of[i];
+    cand[gcoff[gi] + atomicAdd(&gcfill[gi], 1u)] = (int32_t)i;
+}
+
+// Candidate slot -> group, via a marker per group start and a max-scan would be
+// heavier than a binary search over the group candidate offsets.
+__device__ __forceinline__ int group_of_slot(const uint32_t *gcoff, int G, uint32_t s) {
+    int lo = 0, hi = G - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (gcoff[mid] <= s) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Order candidates of a group by "denser" (density desc, original index asc):
+// the rank of a candidate is the number of denser candidates in its group.
+__global__ __launch_bounds__(kBlock) void k_cand_rank(int64_t NC, int G, const uint32_t *__restrict__ gcoff,
+                                                      const int32_t *__restrict__ cand,
+                                                      const float *__restrict__ dens_s,
+                                                      const float4 *__restrict__ spos,
+                                                      int32_t *__restrict__ cand_sorted) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= NC) return;
+    int gi = group_of_slot(gcoff, G, (uint32_t)s);
+    uint32_t a = gcoff[gi], b = gcoff[gi + 1];
+    int me = cand[s];
+    float dm = dens_s[me];
+    uint32_t om = orig_of(spos[me]);
+    uint32_t rank = 0;
+    for (uint32_t t = a; t < b; t++) {
+        int o = cand[t];
+        rank += denser(dens_s[o], orig_of(spos[o]), dm, om) ? 1u : 0u;
+    }
+    cand_sorted[a + rank] = me;
+}
+
+__global__ __launch_bounds__(kBlock) void k_glist_flags(int G, const uint32_t *__restrict__ gccnt,
+                                                        uint32_t *__restrict__ flag) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    flag[g] = gccnt[g] > 0 ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_glist(int G, const uint32_t *__restrict__ flag,
+                                                  const uint32_t *__restrict__ idx,
+                                                  int32_t *__restrict__ glist) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    if (flag[g]) glist[idx[g]] = g;
+}
+
+// ------------------------------------------------------ acceptance and R
+// Smallest integer k >= 0 with T <= k^2 (both sides as the FP64 expressions
+// T and ii(k)); m when T > ii(m - 1) (beyond every k the search inspects).
+__device__ __forceinline__ int64_t bucket_of(double T, int64_t m) {
+    if (!(T > 0.0)) return 0;
+    if (m <= 1 || T > ii(m - 1)) return m;
+    int64_t k = (int64_t)ceil(sqrt(T));
+    if (k > m - 1) k = m - 1;
+    if (k < 0) k = 0;
+    while (k > 0 && T <= ii(k - 1)) k--;
+    while (T > ii(k)) k++;
+    return k;
+}
+
+// One workgroup per L0 group that has candidates.
+__global__ __launch_bounds__(kBlock) void k_accept(Geo g, const int32_t *__restrict__ glist,
+                                                   const int32_t *__restrict__ g_start,
+                                                   const int32_t *__restrict__ g_size,
+                                                   const uint32_t *__restrict__ gcoff,
+                                                   const int32_t *__restrict__ cand_sorted,
+                                                   const int32_t *__restrict__ mem,
+                                                   const float4 *__restrict__ spos,
+                                                   uint32_t *__restrict__ hist_all,
+                                                   int32_t *__restrict__ h_nuc,
+                                                   int32_t *__restrict__ h_ienc,
+                                                   int32_t *__restrict__ h_gid,
+                                                   int32_t *__restrict__ g_nh) {
+#pragma clang fp contract(off)
+    __shared__ int s_nh;
+    __shared__ int s_flag;
+    __shared__ uint32_t s_red[kBlock / 64];
+    __shared__ int s_min[kBlock / 64];
+    const int gi = glist[blockIdx.x];
+    const int64_t start = g_start[gi];
+    const int64_t m = g_size[gi];
+    const uint32_t cs = gcoff[gi], ce = gcoff[gi + 1];
+    uint32_t *hist = hist_all + start + gi;  // m + 1 buckets, disjoint per group
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    if (tid == 0) s_nh = 0;
+    __syncthreads();
+    for (uint32_t r = cs; r < ce; r++) {
+        const int c = cand_sorted[r];
+        const float4 pc = spos[c];
+        const int nh = s_nh;
+        // eligibility: not inside alpha R of any accepted nucleus
+        int inel = 0;
+        for (int h = tid; h < nh; h += kBlock) {
+            const double e = d2_exact(pc, spos[ldi(h_nuc + cs + h)], g.L, g.half);
+            if (g.K2 * e3(e) < g.A6 * ii(ldi(h_ienc + cs + h))) inel = 1;
+        }
+        if (__syncthreads_or(inel)) continue;
+        // R: histogram of buckets over all particles of the group
+        for (int64_t k = tid; k <= m; k += kBlock) stu(hist + k, 0u);
+        __threadfence();
+        __syncthreads();
+        for (int64_t t = tid; t < m; t += kBlock) {
+            const double e = d2_exact(pc, spos[mem[start + t]], g.L, g.half);
+            const int64_t bk = bucket_of(g.K2 * e3(e), m);
+            atomicAdd(hist + bk, 1u);
+        }
+        __threadfence();
+        __syncthreads();
+        // first k in [1, m-1] with C(k) <= k, C(k) = sum of buckets 0..k
+        int64_t found = m;
+        uint32_t run = 0;
+        for (int64_t base = 0; base < m; base += kBlock) {
+            const int64_t k = base + tid;
+            uint32_t v = k < m ? ldu(hist + k) : 0u;
+            // inclusive block scan
+            uint32_t inc = v;
+            for (int d = 1; d < 64; d <<= 1) {
+                uint32_t tv = __shfl_up(inc, d, 64);
+                if (lane >= d) inc += tv;
+            }
+            if (lane == 63) s_red[wid] = inc;
+            __syncthreads();
+            uint32_t pre = 0, tot = 0;
+            for (int w = 0; w < kBlock / 64; w++) {
+                if (w < wid) pre += s_red[w];
+                tot += s_red[w];
+            }
+            const uint32_t Ck = run + pre + inc;
+            const bool hit = k >= 1 && k < m && (int64_t)Ck <= k;
+            // block minimum of the hit positions
+            int cand_k = hit ? (int)(k - base) : kBlock;
+            for (int d = 32; d >= 1; d >>= 1) cand_k = min(cand_k, __shfl_xor(cand_k, d, 64));
+            if (lane == 0) s_min[wid] = cand_k;
+            __syncthreads();
+            int best = kBlock;
+            for (int w = 0; w < kBlock / 64; w++) best = min(best, s_min[w]);
+            __syncthreads();
+            run += tot;
+            if (best < kBlock) {
+                found = base + best;
+                break;
+            }
+        }
+        if (tid == 0) {
+            h_nuc[cs + nh] = c;
+            h_ienc[cs + nh] = (int32_t)found;
+            h_gid[cs + nh] = gi;
+            s_nh = nh + 1;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) g_nh[gi] = s_nh;
+}
+
+// --------------------------------------------------------------- assignment
+// Step 3 as a per-particle fold over the group's halos in creation order, with
+// the flat-rotation-curve enclosed density Delta_L1 R^2 / r^2 (Sec. 2.3.2)
+// compared in cubed form: i_new^2 e_own^3 >= c^3 i_own^2 e_new^3.
+__global__ __launch_bounds__(kBlock) void k_assign(int64_t n, Geo g, const int32_t *__restrict__ gid_of,
+                                                   const uint32_t *__restrict__ gcoff,
+                                                   const int32_t *__restrict__ g_nh,
+                                                   const int32_t *__restrict__ h_nuc,
+                                                   const int32_t *__restrict__ h_ienc,
+                                                   const float4 *__restrict__ spos,
+                                                   int32_t *__restrict__ owner,
+                                                   uint32_t *__restrict__ h_count) {
+#pragma clang fp contract(off)
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int gi = gid_of[i];
+    int own = -1;
+    if (gi >= 0) {
+        const uint32_t cs = gcoff[gi];
+        const int nh = g_nh[gi];
+        const float4 pi = spos[i];
+        double eown = 0.0, iown = 0.0;
+        for (int h = 0; h < nh; h++) {
+            const double e = d2_exact(pi, spos[h_nuc[cs + h]], g.L, g.half);
+            const double ih = ii(h_ienc[cs + h]);
+            if (!(g.K2 * e3(e) < ih)) continue;
+            bool take;
+            if (own < 0) {
+                take = true;
+            } else {
+                const double lhs = ih * e3(eown);
+                const double rhs = (g.C3 * iown) * e3(e);
+                take = lhs >= rhs;
+            }
+            if (take) {
+                own = (int)cs + h;
+                eown = e;
+                iown = ih;
+            }
+        }
+        if (own >= 0) atomicAdd(&h_count[own], 1u);
+    }
+    owner[i] = own;
+}
+
+// ------------------------------------------------------------------- output
+
+__global__ __launch_bounds__(kBlock) void k_out_flags(int64_t NC, Geo g, const int32_t *__restrict__ h_nuc,
+                                                      const uint32_t *__restrict__ h_count,
+                                                      const float4 *__restrict__ spos,
+                                                      uint32_t *__restrict__ tflag,
+                                                      int32_t *__restrict__ counters) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= NC) return;
+    int nuc = h_nuc[s];
+    if (nuc < 0) return;
+    atomicAdd(&counters[2], 1);
+    if (h_count[s] >= (uint32_t)g.n_l1_min) tflag[orig_of(spos[nuc])] = 1u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_out_table(int64_t NC, Geo g, const int32_t *__restrict__ h_nuc,
+                                                      const int32_t *__restrict__ h_ienc,
+                                                      const int32_t *__restrict__ h_gid,
+                                                      const uint32_t *__restrict__ h_count,
+                                                      const int32_t *__restrict__ g_label,
+                                                      const float4 *__restrict__ spos,
+                                                      const uint32_t *__restrict__ tpos,
+                                                      hf_halo *__restrict__ halos, int64_t cap) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= NC) return;
+    int nuc = h_nuc[s];
+    if (nuc < 0 || h_count[s] < (uint32_t)g.n_l1_min) return;
+    float4 p = spos[nuc];
+    uint32_t o = orig_of(p);
+    uint32_t row = tpos[o];
+    if ((int64_t)row >= cap) return;
+    hf_halo h;
+    h.id = (int32_t)o + 1;
+    h.nucleus = (int32_t)o;
+    h.l0_id = g_label[h_gid[s]];
+    h.n = (int32_t)h_count[s];
+    h.n_enclosed = h_ienc[s];
+    h.x = p.x;
+    h.y = p.y;
+    h.z = p.z;
+    h.r = (float)cbrt((double)h_ienc[s] / g.K);
+    h.mass = (float)h_count[s] * g.particle_mass;
+    halos[row] = h;
+}
+
+__global__ __launch_bounds__(kBlock) void k_out_particles(int64_t n, Geo g, const int32_t *__restrict__ owner,
+                                                          const int32_t *__restrict__ h_nuc,
+                                                          const uint32_t *__restrict__ h_count,
+                                                          const int32_t *__restrict__ gkey,
+                                                          const float4 *__restrict__ spos,
+                                                          int32_t *__restrict__ halo_id,
+                                                          int32_t *__restrict__ l0_out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t o = orig_of(spos[i]);
+    int own = owner[i];
+    int32_t hid = 0;
+    if (own >= 0 && h_count[own] >= (uint32_t)g.n_l1_min) hid = (int32_t)orig_of(spos[h_nuc[own]]) + 1;
+    halo_id[o] = hid;
+    if (l0_out) l0_out[o] = gkey[i] + 1;
+}
+
+}  // namespace
+
+void launch_segment(int64_t n, Work &w, hipStream_t s) {
+    fill_u32(w.gcnt, 0u, n + 1, s);
+    fill_u32(w.gfill, 0u, n + 1, s);
+    hipLaunchKernelGGL(k_seg_count, grid(n), dim3(kBlock), 0, s, n, w.gkey, w.gcnt);
+    scan_u32(w.gcnt, w.goff, n, w.scan_tmp, s);
+    hipLaunchKernelGGL(k_seg_flags, grid(n), dim3(kBlock), 0, s, n, w.gcnt, w.gflag);
+    scan_u32(w.gflag, w.gidx, n, w.scan_tmp, s);
+}
+
+void launch_segment_groups(int64_t n, int64_t G, Work &w, hipStream_t s) {
+    hipLaunchKernelGGL(k_seg_groups, grid(n), dim3(kBlock), 0, s, n, w.gcnt, w.goff, w.gidx, w.g_start,
+                       w.g_size, w.g_label);
+    hipLaunchKernelGGL(k_seg_scatter, grid(n), dim3(kBlock), 0, s, n, w.gkey, w.goff, w.gidx, w.gfill,
+                       w.mem, w.gid_of);
+    fill_u32(w.gccnt, 0u, G + 1, s);
+    fill_u32(w.gcfill, 0u, G + 1, s);
+}
+
+void launch_candidates(int64_t n, const Geo &g, Work &w, hipStream_t s) {
+    hipLaunchKernelGGL(k_candidates, grid(n), dim3(kBlock), 0, s, n, g, w.sloc, w.spos, w.off, w.dens_s,
+                       w.gkey, w.gid_of, w.gccnt, w.owner /* candidate flags */);
+}
+
+void launch_candidates_sort(int64_t n, int64_t G, int64_t NC, Work &w, hipStream_t s) {
+    // gcoff already holds the exclusive scan of gccnt
+    hipLaunchKernelGGL(k_cand_scatter, grid(n), dim3(kBlock), 0, s, n, w.owner, w.gid_of, w.gcoff,
+                       w.gcfill, w.cand);
+    if (NC > 0)
+        hipLaunchKernelGGL(k_cand_rank, grid(NC), dim3(kBlock), 0, s, NC, (int)G, w.gcoff, w.cand,
+                           w.dens_s, w.spos, w.cand_sorted);
+    if (G > 0)
+        hipLaunchKernelGGL(k_glist_flags, grid(G), dim3(kBlock), 0, s, (int)G, w.gccnt, w.gcflag);
+    scan_u32(w.gcflag, w.gcidx, G, w.scan_tmp, s);
+    if (G > 0)
+        hipLaunchKernelGGL(k_glist, grid(G), dim3(kBlock), 0, s, (int)G, w.gcflag, w.gcidx, w.glist);
+    fill_i32(w.h_nuc, -1, NC + 1, s);
+    fill_u32(w.h_count, 0u, NC + 1, s);
+    fill_i32(w.g_nh, 0, G + 1, s);
+}
+
+void launch_accept(int64_t NGC, const Geo &g, Work &w, hipStream_t s) {
+    if (NGC <= 0) return;
+    hipLaunchKernelGGL(k_accept, dim3((unsigned)NGC), dim3(kBlock), 0, s, g, w.glist, w.g_start, w.g_size,
+                       w.gcoff, w.cand_sorted, w.mem, w.spos, w.hist, w.h_nuc, w.h_ienc, w.h_gid,
+                       w.g_nh);
+}
+
+void launch_assign(int64_t n, const Geo &g, Work &w, hipStream_t s) {
+    hipLaunchKernelGGL(k_assign, grid(n), dim3(kBlock), 0, s, n, g, w.gid_of, w.gcoff, w.g_nh, w.h_nuc,
+                       w.h_ienc, w.spos, w.owner, w.h_count);
+}
+
+void launch_output_flags(int64_t n, int64_t NC, const Geo &g, Work &w, hipStream_t s) {
+    fill_u32(w.tflag, 0u, n + 1, s);
+    if (NC > 0)
+        hipLaunchKernelGGL(k_out_flags, grid(NC), dim3(kBlock), 0, s, NC, g, w.h_nuc, w.h_count, w.spos,
+                           w.tflag, w.counters);
+    scan_u32(w.tflag, w.tpos, n, w.scan_tmp, s);
+}
+
+void launch_output(int64_t n, int64_t NC, const Geo &g, Work &w, int32_t *halo_id, int32_t *l0_out,
+                   hf_halo *halos, int64_t cap, hipStream_t s) {
+    if (halos && NC > 0)
+        hipLaunchKernelGGL(k_out_table, grid(NC), dim3(kBlock), 0, s, NC, g, w.h_nuc, w.h_ienc, w.h_gid,
+                           w.h_count, w.g_label, w.spos, w.tpos, halos, cap);
+    hipLaunchKernelGGL(k_out_particles, grid(n), dim3(kBlock), 0, s, n, g, w.owner, w.h_nuc, w.h_count,
+                       w.gkey, w.spos, halo_id, l0_out);
+}
+
+}  // namespace hf

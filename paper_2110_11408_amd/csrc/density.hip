@@ -1,0 +1,125 @@
+// Kernel density (Sec. 2.2.1): Delta_i = norm * sum_{j != i, r_ij < b} (1 - r_ij^2/b^2),
+// norm = 15 / (8 pi b^3 nbar) so that a uniform field has Delta = 1 (App. B.2).
+//
+// One thread per particle in cell order; consecutive threads mostly share a cell
+// and therefore walk the same 27 neighbour cells in lockstep, so neighbour
+// reads are broadcasts from the same cache lines.  Coordinates are the
+// cell-local FP32 values in units of b; the periodic image of a neighbour cell
+// is the exact cell offset, so W = 1 - d^2 is evaluated as three FMAs on
+// (dx, dy, dz) and clamped at 0 (which also removes pairs beyond b).  The self
+// pair contributes exactly 1 and is subtracted at the end.  Partial sums run
+// over at most 64 neighbours in FP32 and are accumulated in FP64.
+#include "hf_internal.h"
+
+namespace hf {
+
+namespace {
+
+__global__ __launch_bounds__(kBlock) void k_density(int64_t n, Geo g,
+                                                    const float4 *__restrict__ sloc,
+                                                    const float4 *__restrict__ spos,
+                                                    const uint32_t *__restrict__ off,
+                                                    float *__restrict__ dens_s,
+                                                    float *__restrict__ dens_out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float4 li = sloc[i];
+    const uint32_t c = __float_as_uint(li.w);
+    const int nc = g.nc;
+    const int cx = (int)(c % (uint32_t)nc), cy = (int)((c / (uint32_t)nc) % (uint32_t)nc),
+              cz = (int)(c / ((uint32_t)nc * (uint32_t)nc));
+    double acc = 0.0;
+    for (int oz = -1; oz <= 1; oz++) {
+        const int z = wrapc(cz + oz, nc);
+        const float zs = li.z - (float)oz * g.cellb;
+        for (int oy = -1; oy <= 1; oy++) {
+            const int y = wrapc(cy + oy, nc);
+            const float ys = li.y - (float)oy * g.cellb;
+            const uint32_t row = ((uint32_t)z * (uint32_t)nc + (uint32_t)y) * (uint32_t)nc;
+            for (int ox = -1; ox <= 1; ox++) {
+                const int x = wrapc(cx + ox, nc);
+                const float xs = li.x - (float)ox * g.cellb;
+                const uint32_t nb = row + (uint32_t)x;
+                const uint32_t a = off[nb], b = off[nb + 1];
+                for (uint32_t j0 = a; j0 < b; j0 += 64) {
+                    const uint32_t e = min(j0 + 64u, b);
+                    float p = 0.0f;
+                    for (uint32_t j = j0; j < e; j++) {
+                        const float4 lj = sloc[j];
+                        const float dx = lj.x - xs, dy = lj.y - ys, dz = lj.z - zs;
+                        float t = fmaf(-dx, dx, 1.0f);
+                        t = fmaf(-dy, dy, t);
+                        t = fmaf(-dz, dz, t);
+                        p += fmaxf(t, 0.0f);
+                    }
+                    acc += (double)p;
+                }
+            }
+        }
+    }
+    const double S = acc - (g.self_count ? 0.0 : 1.0);
+    const float d = (float)(g.norm * S);
+    dens_s[i] = d;
+    if (dens_out) dens_out[orig_of(spos[i])] = d;
+}
+
+// Number of ordered pairs (i, j != i) closer than b, for the roofline's
+// algorithmic pair count (evaluated in the same FP32 local coordinates).
+__global__ __launch_bounds__(kBlock) void k_count_pairs(int64_t n, Geo g,
+                                                        const float4 *__restrict__ sloc,
+                                                        const uint32_t *__restrict__ off,
+                                                        unsigned long long *__restrict__ total) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t cnt = 0;
+    if (i < n) {
+        const float4 li = sloc[i];
+        const uint32_t c = __float_as_uint(li.w);
+        const int nc = g.nc;
+        const int cx = (int)(c % (uint32_t)nc), cy = (int)((c / (uint32_t)nc) % (uint32_t)nc),
+                  cz = (int)(c / ((uint32_t)nc * (uint32_t)nc));
+        for (int oz = -1; oz <= 1; oz++)
+            for (int oy = -1; oy <= 1; oy++)
+                for (int ox = -1; ox <= 1; ox++) {
+                    const uint32_t nb = ((uint32_t)wrapc(cz + oz, nc) * (uint32_t)nc +
+                                         (uint32_t)wrapc(cy + oy, nc)) * (uint32_t)nc +
+                                        (uint32_t)wrapc(cx + ox, nc);
+                    const float xs = li.x - (float)ox * g.cellb, ys = li.y - (float)oy * g.cellb,
+                                zs = li.z - (float)oz * g.cellb;
+                    for (uint32_t j = off[nb]; j < off[nb + 1]; j++) {
+                        const float4 lj = sloc[j];
+                        const float dx = lj.x - xs, dy = lj.y - ys, dz = lj.z - zs;
+                        cnt += (dx * dx + dy * dy + dz * dz < 1.0f) ? 1u : 0u;
+                    }
+                }
+        cnt -= 1;  // the particle itself
+    }
+    for (int d = 32; d >= 1; d >>= 1) cnt += __shfl_xor(cnt, d, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd(total, (unsigned long long)cnt);
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather_density(int64_t n, const float4 *__restrict__ spos,
+                                                           const float *__restrict__ dens_in,
+                                                           float *__restrict__ dens_s) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    dens_s[i] = dens_in[orig_of(spos[i])];
+}
+
+}  // namespace
+
+void launch_density(int64_t n, const Geo &g, Work &w, float *dens_out, hipStream_t s) {
+    hipLaunchKernelGGL(k_density, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, g, w.sloc,
+                       w.spos, w.off, w.dens_s, dens_out);
+}
+
+void launch_count_pairs(int64_t n, const Geo &g, Work &w, unsigned long long *total, hipStream_t s) {
+    hipLaunchKernelGGL(k_count_pairs, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, g, w.sloc,
+                       w.off, total);
+}
+
+void launch_gather_density(const float *dens_in, int64_t n, Work &w, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_density, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n,
+                       w.spos, dens_in, w.dens_s);
+}
+
+}  // namespace hf

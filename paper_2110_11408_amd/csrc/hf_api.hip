@@ -1,0 +1,482 @@
+// C ABI of libhf: argument checks, derived constants, the scratch arena of a
+// context, and the order of the stages for each entry point.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "hf_internal.h"
+
+#define HF_PI 3.14159265358979323846
+
+struct hf_ctx {
+    int device = 0;
+    void *arena = nullptr;
+    size_t arena_bytes = 0;
+    hipEvent_t ev[10] = {};
+    hf_stats stats = {};
+    std::string err;
+};
+
+namespace {
+
+using hf::Geo;
+using hf::Work;
+
+enum { D_NBAR, D_B, D_L, D_B2, D_L2, D_NORM, D_K, D_K2, D_FLOOR, D_A6, D_C3, D_COUNT };
+
+hf_status fail(hf_ctx *c, hf_status st, const std::string &msg) {
+    if (c) c->err = msg;
+    return st;
+}
+
+#define HIP_OK(ctx, expr)                                                               \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(ctx, HF_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+bool finite(double x) { return x == x && x != HUGE_VAL && x != -HUGE_VAL; }
+
+// Derived constants, in the same sequence of IEEE operations as documented in
+// hf.h (multiplications and divisions only, so no contraction can change them).
+hf_status derive(const hf_params *p, int64_t n, double *d) {
+    if (!p) return HF_ERR_INVALID;
+    const double v[] = {p->box, p->mean_density, p->b_kernel, p->l_fof, p->delta_l0_min,
+                        p->delta_l1, p->alpha_elig, p->c_roche, p->n_new_min, p->particle_mass};
+    for (double x : v)
+        if (!finite(x)) return HF_ERR_INVALID;
+    if (!(p->box > 0.0) || !(p->b_kernel > 0.0) || !(p->l_fof > 0.0) || !(p->delta_l1 > 0.0) ||
+        p->alpha_elig < 0.0 || p->c_roche < 0.0 || !(p->n_new_min > 0.0) || n < 0)
+        return HF_ERR_INVALID;
+    double box = p->box;
+    double nbar = p->mean_density > 0.0 ? p->mean_density : (double)n / ((box * box) * box);
+    if (!(nbar > 0.0)) return HF_ERR_INVALID;
+    double lmean = cbrt(1.0 / nbar);
+    double b = p->b_kernel * lmean;
+    double l = p->l_fof * lmean;
+    double K = ((4.0 * HF_PI) / 3.0) * p->delta_l1 * nbar;
+    double rnew = cbrt(p->n_new_min / K);
+    double a3 = (p->alpha_elig * p->alpha_elig) * p->alpha_elig;
+    d[D_NBAR] = nbar;
+    d[D_B] = b;
+    d[D_L] = l;
+    d[D_B2] = b * b;
+    d[D_L2] = l * l;
+    d[D_NORM] = 15.0 / (((8.0 * HF_PI) * ((b * b) * b)) * nbar);
+    d[D_K] = K;
+    d[D_K2] = K * K;
+    d[D_FLOOR] = ((5.0 * p->delta_l1) / 3.0) * (rnew * rnew) / (b * b);
+    d[D_A6] = a3 * a3;
+    d[D_C3] = (p->c_roche * p->c_roche) * p->c_roche;
+    return HF_OK;
+}
+
+hf_status make_geo(hf_ctx *c, const hf_params *p, int64_t n, Geo *g) {
+    double d[D_COUNT];
+    if (derive(p, n, d) != HF_OK) return fail(c, HF_ERR_INVALID, "invalid parameters");
+    if (n >= (int64_t)0x7fffffff) return fail(c, HF_ERR_INVALID, "n must be below 2^31 - 1");
+    double L = p->box;
+    double rmin = fmax(d[D_B], d[D_L]);
+    double ncd = floor(L / (rmin * (1.0 + 1e-6)));
+    if (!(ncd >= 3.0))
+        return fail(c, HF_ERR_INVALID, "box must be at least three cells of max(b, l) wide");
+    if (ncd > 1625.0) ncd = 1625.0;  // cell ids stay below 2^32; larger cells remain valid
+    g->nc = (int)ncd;
+    g->L = L;
+    g->half = 0.5 * L;
+    g->cell = L / g->nc;
+    g->inv_cell = (double)g->nc / L;
+    g->inv_b = 1.0 / d[D_B];
+    g->cellb = (float)(g->cell / d[D_B]);
+    // FP32 prefilter margin (units of b^2): 256 ulps of the largest local
+    // coordinate difference, ten times the error bound of the FP32 path.
+    double M = 2.0 * g->cellb + 1.0;
+    double margin = 256.0 * M * ldexp(1.0, -24);
+    double l2b = d[D_L2] / d[D_B2];
+    g->l2b_lo = (float)(l2b - margin);
+    g->l2b_hi = (float)(l2b + margin);
+    g->b2b_lo = (float)(1.0 - margin);
+    g->b2b_hi = (float)(1.0 + margin);
+    g->b2 = d[D_B2];
+    g->l2 = d[D_L2];
+    g->norm = d[D_NORM];
+    g->self_count = p->self_count ? 1 : 0;
+    g->dl0 = p->delta_l0_min;
+    g->floor_nuc = d[D_FLOOR];
+    g->K = d[D_K];
+    g->K2 = d[D_K2];
+    g->A6 = d[D_A6];
+    g->C3 = d[D_C3];
+    g->n_l1_min = p->n_l1_min;
+    g->particle_mass = (float)p->particle_mass;
+    return HF_OK;
+}
+
+// Scratch arena: every array of the pipeline carved from one allocation.
+struct Carver {
+    char *base;
+    size_t off = 0;
+    template <class T> T *take(int64_t count) {
+        off = (off + 255) & ~(size_t)255;
+        T *p = base ? (T *)(base + off) : nullptr;
+        off += (size_t)(count > 0 ? count : 1) * sizeof(T);
+        return p;
+    }
+};
+
+size_t carve(char *base, int64_t n, int64_t ncell, Work *w) {
+    Carver c{base};
+    int64_t n1 = n + 1;
+    w->key = c.take<uint32_t>(n);
+    w->ticket = c.take<uint32_t>(n);
+    w->cnt = c.take<uint32_t>(ncell + 1);
+    w->off = c.take<uint32_t>(ncell + 1);
+    w->tmp = c.take<uint32_t>(n);
+    w->spos = c.take<float4>(n);
+    w->sloc = c.take<float4>(n);
+    w->dens_s = c.take<float>(n);
+    w->parent = c.take<int32_t>(n);
+    w->minorig = c.take<int32_t>(n);
+    w->gkey = c.take<int32_t>(n);
+    w->gid_of = c.take<int32_t>(n);
+    w->owner = c.take<int32_t>(n);
+    w->gcnt = c.take<uint32_t>(n1);
+    w->goff = c.take<uint32_t>(n1);
+    w->gflag = c.take<uint32_t>(n1);
+    w->gidx = c.take<uint32_t>(n1);
+    w->gfill = c.take<uint32_t>(n1);
+    w->mem = c.take<int32_t>(n);
+    w->g_start = c.take<int32_t>(n1);
+    w->g_size = c.take<int32_t>(n1);
+    w->g_label = c.take<int32_t>(n1);
+    w->gccnt = c.take<uint32_t>(n1);
+    w->gcoff = c.take<uint32_t>(n1);
+    w->gcfill = c.take<uint32_t>(n1);
+    w->gcflag = c.take<uint32_t>(n1);
+    w->gcidx = c.take<uint32_t>(n1);
+    w->glist = c.take<int32_t>(n1);
+    w->cand = c.take<int32_t>(n1);
+    w->cand_sorted = c.take<int32_t>(n1);
+    w->h_nuc = c.take<int32_t>(n1);
+    w->h_ienc = c.take<int32_t>(n1);
+    w->h_gid = c.take<int32_t>(n1);
+    w->g_nh = c.take<int32_t>(n1);
+    w->h_count = c.take<uint32_t>(n1);
+    w->tflag = c.take<uint32_t>(n1);
+    w->tpos = c.take<uint32_t>(n1);
+    w->hist = c.take<uint32_t>(2 * n1);
+    w->scan_tmp = c.take<uint32_t>(hf::scan_tmp_words((ncell > n ? ncell : n) + 1));
+    w->counters = c.take<int32_t>(16);
+    w->err = c.take<int32_t>(4);
+    return c.off + 256;
+}
+
+hf_status prepare(hf_ctx *c, int64_t n, const Geo &g, Work *w) {
+    int64_t ncell = (int64_t)g.nc * g.nc * g.nc;
+    size_t need = carve(nullptr, n, ncell, w);
+    HIP_OK(c, hipSetDevice(c->device));
+    if (need > c->arena_bytes) {
+        if (c->arena) {
+            HIP_OK(c, hipDeviceSynchronize());
+            HIP_OK(c, hipFree(c->arena));
+            c->arena = nullptr;
+            c->arena_bytes = 0;
+        }
+        size_t want = need + need / 8;
+        if (hipMalloc(&c->arena, want) != hipSuccess) {
+            (void)hipGetLastError();
+            c->arena = nullptr;
+            return fail(c, HF_ERR_NOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+        }
+        c->arena_bytes = want;
+    }
+    carve((char *)c->arena, n, ncell, w);
+    c->stats = hf_stats{};
+    c->stats.n_cells = ncell;
+    return HF_OK;
+}
+
+hf_status check_pos_flags(hf_ctx *c, const Work &w, hipStream_t s) {
+    int32_t err = 0;
+    HIP_OK(c, hipMemcpyAsync(&err, w.err, sizeof(err), hipMemcpyDeviceToHost, s));
+    HIP_OK(c, hipStreamSynchronize(s));
+    if (err & 1) return fail(c, HF_ERR_INVALID, "positions must lie in [0, box)");
+    if (err & 2) return fail(c, HF_ERR_INVALID, "l0_id values must lie in [0, n]");
+    return HF_OK;
+}
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0.0f;
+    }
+    return ms;
+}
+
+// CompaSO on the binned particles with group keys in w.gkey.  Fills halo_id,
+// the table and the counts; records events ev[3..8].
+hf_status run_compaso(hf_ctx *c, int64_t n, const Geo &g, Work &w, int32_t *halo_id,
+                      int32_t *l0_out, hf_halo *halos, int64_t cap, int64_t *n_halos,
+                      hipStream_t s) {
+    HIP_OK(c, hipEventRecord(c->ev[3], s));
+    hf::launch_segment(n, w, s);
+    uint32_t G32 = 0;
+    HIP_OK(c, hipMemcpyAsync(&G32, w.gidx + n, sizeof(G32), hipMemcpyDeviceToHost, s));
+    HIP_OK(c, hipStreamSynchronize(s));
+    int64_t G = G32;
+    hf::launch_segment_groups(n, G, w, s);
+    HIP_OK(c, hipEventRecord(c->ev[4], s));
+    hf::launch_candidates(n, g, w, s);
+    hf::scan_u32(w.gccnt, w.gcoff, G, w.scan_tmp, s);
+    uint32_t NC32 = 0;
+    HIP_OK(c, hipMemcpyAsync(&NC32, w.gcoff + G, sizeof(NC32), hipMemcpyDeviceToHost, s));
+    HIP_OK(c, hipStreamSynchronize(s));
+    int64_t NC = NC32;
+    hf::launch_candidates_sort(n, G, NC, w, s);
+    uint32_t NGC32 = 0;
+    HIP_OK(c, hipMemcpyAsync(&NGC32, w.gcidx + G, sizeof(NGC32), hipMemcpyDeviceToHost, s));
+    HIP_OK(c, hipStreamSynchronize(s));
+    HIP_OK(c, hipEventRecord(c->ev[5], s));
+    hf::launch_accept(NGC32, g, w, s);
+    HIP_OK(c, hipEventRecord(c->ev[6], s));
+    hf::launch_assign(n, g, w, s);
+    HIP_OK(c, hipEventRecord(c->ev[7], s));
+    hf::launch_output_flags(n, NC, g, w, s);
+    uint32_t NH32 = 0;
+    HIP_OK(c, hipMemcpyAsync(&NH32, w.tpos + n, sizeof(NH32), hipMemcpyDeviceToHost, s));
+    HIP_OK(c, hipStreamSynchronize(s));
+    int64_t NH = NH32;
+    if (n_halos) *n_halos = NH;
+    bool fits = NH <= cap;
+    hf::launch_output(n, NC, g, w, halo_id, l0_out, fits ? halos : nullptr, cap, s);
+    HIP_OK(c, hipEventRecord(c->ev[8], s));
+    int32_t counters[16];
+    HIP_OK(c, hipMemcpyAsync(counters, w.counters, sizeof(counters), hipMemcpyDeviceToHost, s));
+    HIP_OK(c, hipStreamSynchronize(s));
+    c->stats.ms_segment = elapsed(c->ev[3], c->ev[4]);
+    c->stats.ms_candidates = elapsed(c->ev[4], c->ev[5]);
+    c->stats.ms_accept = elapsed(c->ev[5], c->ev[6]);
+    c->stats.ms_assign = elapsed(c->ev[6], c->ev[7]);
+    c->stats.ms_output = elapsed(c->ev[7], c->ev[8]);
+    c->stats.n_candidates = NC;
+    c->stats.n_found = counters[2];
+    c->stats.n_halos = NH;
+    if (!fits) return fail(c, HF_ERR_CAPACITY, "halos_cap is smaller than the number of halos");
+    return HF_OK;
+}
+
+hf_status begin(hf_ctx *c, const float *pos, int64_t n, const hf_params *p, Geo *g, Work *w,
+                hipStream_t s) {
+    if (!c) return HF_ERR_INVALID;
+    c->err.clear();
+    if (!p) return fail(c, HF_ERR_INVALID, "params is NULL");
+    hf_status st = make_geo(c, p, n, g);
+    if (st != HF_OK) return st;
+    if (n > 0 && !pos) return fail(c, HF_ERR_INVALID, "pos is NULL");
+    if (n == 0) return HF_OK;
+    st = prepare(c, n, *g, w);
+    if (st != HF_OK) return st;
+    hf::fill_i32(w->counters, 0, 16, s);
+    hf::fill_i32(w->err, 0, 4, s);
+    HIP_OK(c, hipEventRecord(c->ev[0], s));
+    hf::launch_bin(pos, n, *g, *w, s);
+    HIP_OK(c, hipEventRecord(c->ev[1], s));
+    return HF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void hf_default_params(hf_params *p) {
+    if (!p) return;
+    p->box = 1.0;
+    p->mean_density = 0.0;
+    p->b_kernel = 0.4;
+    p->l_fof = 0.25;
+    p->delta_l0_min = 60.0;
+    p->delta_l1 = 200.0;
+    p->alpha_elig = 0.8;
+    p->c_roche = 2.0;
+    p->n_new_min = 35.0;
+    p->particle_mass = 1.0;
+    p->n_l1_min = 35;
+    p->self_count = 0;
+}
+
+hf_status hf_derived(const hf_params *p, int64_t n, double *out) {
+    if (!out) return HF_ERR_INVALID;
+    return derive(p, n, out);
+}
+
+hf_status hf_create(hf_ctx **out, int device) {
+    if (!out) return HF_ERR_INVALID;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
+        (void)hipGetLastError();
+        return HF_ERR_UNSUPPORTED;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return HF_ERR_DEVICE;
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return HF_ERR_UNSUPPORTED;
+    hf_ctx *c = new hf_ctx();
+    c->device = device;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete c;
+        return HF_ERR_DEVICE;
+    }
+    for (auto &e : c->ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            delete c;
+            return HF_ERR_DEVICE;
+        }
+    *out = c;
+    return HF_OK;
+}
+
+void hf_destroy(hf_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->arena) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(c->arena);
+    }
+    for (auto &e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete c;
+}
+
+const char *hf_last_error(const hf_ctx *c) { return c ? c->err.c_str() : "no context"; }
+
+hf_status hf_get_stats(const hf_ctx *c, hf_stats *out) {
+    if (!c || !out) return HF_ERR_INVALID;
+    *out = c->stats;
+    return HF_OK;
+}
+
+hf_status hf_density(hf_ctx *c, const float *pos, int64_t n, const hf_params *p, float *density,
+                     void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    Geo g;
+    Work w;
+    hf_status st = begin(c, pos, n, p, &g, &w, s);
+    if (st != HF_OK || n == 0) return st;
+    if (!density) return fail(c, HF_ERR_INVALID, "density is NULL");
+    hf::launch_density(n, g, w, density, s);
+    HIP_OK(c, hipEventRecord(c->ev[2], s));
+    st = check_pos_flags(c, w, s);
+    c->stats.ms_bin = elapsed(c->ev[0], c->ev[1]);
+    c->stats.ms_density = elapsed(c->ev[1], c->ev[2]);
+    c->stats.ms_total = elapsed(c->ev[0], c->ev[2]);
+    return st;
+}
+
+hf_status hf_count_pairs(hf_ctx *c, const float *pos, int64_t n, const hf_params *p,
+                         int64_t *pairs, void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    Geo g;
+    Work w;
+    if (!pairs) return fail(c, HF_ERR_INVALID, "pairs is NULL");
+    *pairs = 0;
+    hf_status st = begin(c, pos, n, p, &g, &w, s);
+    if (st != HF_OK || n == 0) return st;
+    hf::fill_i32(w.counters + 4, 0, 2, s);
+    hf::launch_count_pairs(n, g, w, (unsigned long long *)(w.counters + 4), s);
+    HIP_OK(c, hipMemcpyAsync(pairs, w.counters + 4, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    return check_pos_flags(c, w, s);
+}
+
+hf_status hf_l0_fof(hf_ctx *c, const float *pos, const float *density, int64_t n,
+                    const hf_params *p, int32_t *l0_id, int64_t *n_groups, void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    Geo g;
+    Work w;
+    if (n > 0 && (!density || !l0_id)) return fail(c, HF_ERR_INVALID, "density / l0_id is NULL");
+    hf_status st = begin(c, pos, n, p, &g, &w, s);
+    if (st != HF_OK) return st;
+    if (n == 0) {
+        if (n_groups) *n_groups = 0;
+        return HF_OK;
+    }
+    hf::launch_gather_density(density, n, w, s);
+    HIP_OK(c, hipEventRecord(c->ev[2], s));
+    hf::launch_fof(n, g, w, s);
+    hf::launch_fof_labels(n, g, w, l0_id, s);
+    HIP_OK(c, hipEventRecord(c->ev[3], s));
+    int32_t counters[16];
+    HIP_OK(c, hipMemcpyAsync(counters, w.counters, sizeof(counters), hipMemcpyDeviceToHost, s));
+    st = check_pos_flags(c, w, s);
+    c->stats.ms_bin = elapsed(c->ev[0], c->ev[1]);
+    c->stats.ms_fof = elapsed(c->ev[2], c->ev[3]);
+    c->stats.ms_total = elapsed(c->ev[0], c->ev[3]);
+    c->stats.n_members = counters[0];
+    c->stats.n_groups = counters[1];
+    if (n_groups) *n_groups = counters[1];
+    return st;
+}
+
+hf_status hf_compaso(hf_ctx *c, const float *pos, const float *density, const int32_t *l0_id,
+                     int64_t n, const hf_params *p, int32_t *halo_id, hf_halo *halos,
+                     int64_t halos_cap, int64_t *n_halos, void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    Geo g;
+    Work w;
+    if (n > 0 && (!density || !l0_id || !halo_id))
+        return fail(c, HF_ERR_INVALID, "density / l0_id / halo_id is NULL");
+    if (halos_cap < 0 || (halos_cap > 0 && !halos)) return fail(c, HF_ERR_INVALID, "bad halos / halos_cap");
+    hf_status st = begin(c, pos, n, p, &g, &w, s);
+    if (st != HF_OK) return st;
+    if (n == 0) {
+        if (n_halos) *n_halos = 0;
+        return HF_OK;
+    }
+    hf::launch_gather_density(density, n, w, s);
+    hf::launch_keys_from_labels(l0_id, n, w, s);
+    HIP_OK(c, hipEventRecord(c->ev[2], s));
+    st = check_pos_flags(c, w, s);
+    if (st != HF_OK) return st;
+    st = run_compaso(c, n, g, w, halo_id, nullptr, halos, halos_cap, n_halos, s);
+    c->stats.ms_bin = elapsed(c->ev[0], c->ev[1]);
+    c->stats.ms_total = elapsed(c->ev[0], c->ev[8]);
+    return st;
+}
+
+hf_status hf_find(hf_ctx *c, const float *pos, int64_t n, const hf_params *p, float *density,
+                  int32_t *l0_id, int32_t *halo_id, hf_halo *halos, int64_t halos_cap,
+                  int64_t *n_halos, void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    Geo g;
+    Work w;
+    if (n > 0 && !halo_id) return fail(c, HF_ERR_INVALID, "halo_id is NULL");
+    if (halos_cap < 0 || (halos_cap > 0 && !halos)) return fail(c, HF_ERR_INVALID, "bad halos / halos_cap");
+    hf_status st = begin(c, pos, n, p, &g, &w, s);
+    if (st != HF_OK) return st;
+    if (n == 0) {
+        if (n_halos) *n_halos = 0;
+        return HF_OK;
+    }
+    hf::launch_density(n, g, w, density, s);
+    HIP_OK(c, hipEventRecord(c->ev[2], s));
+    hf::launch_fof(n, g, w, s);
+    hf::launch_fof_labels(n, g, w, l0_id, s);
+    HIP_OK(c, hipEventRecord(c->ev[9], s));
+    st = check_pos_flags(c, w, s);
+    if (st != HF_OK) return st;
+    st = run_compaso(c, n, g, w, halo_id, nullptr, halos, halos_cap, n_halos, s);
+    int32_t counters[16];
+    HIP_OK(c, hipMemcpy(counters, w.counters, sizeof(counters), hipMemcpyDeviceToHost));
+    c->stats.ms_bin = elapsed(c->ev[0], c->ev[1]);
+    c->stats.ms_density = elapsed(c->ev[1], c->ev[2]);
+    c->stats.ms_fof = elapsed(c->ev[2], c->ev[9]);
+    c->stats.ms_total = elapsed(c->ev[0], c->ev[8]);
+    c->stats.n_members = counters[0];
+    c->stats.n_groups = counters[1];
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,123 @@
+// Internal declarations of libhf: the geometry/constant block passed to every
+// kernel, device helpers for the canonical predicates, and the stage launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hf.h"
+
+namespace hf {
+
+constexpr int kBlock = 256;
+
+// Constants of one call, computed on the host (see hf_derived) and passed by
+// value to the kernels.
+struct Geo {
+    double L, half;        // periodic side and L/2 (minimum-image test)
+    double cell, inv_cell; // binning cell side (>= max(b, l)) and its inverse
+    double inv_b;          // 1/b: local coordinates are stored in units of b
+    float cellb;           // cell / b in FP32 (image offset of a neighbour cell)
+    int nc;                // cells per side (>= 3)
+    double b2, l2;         // FP64 squared radii of the peak test and of FoF links
+    float l2b_lo, l2b_hi;  // (l/b)^2 shrunk / grown by the FP32 prefilter margin
+    float b2b_lo, b2b_hi;  // 1 shrunk / grown by the same margin (peak test, units of b^2)
+    double norm;           // density normalisation 15/(8 pi b^3 nbar)
+    int self_count;
+    double dl0;            // L0 density threshold
+    double floor_nuc;      // nucleation floor
+    double K, K2, A6, C3;  // R^3 = i/K; alpha^6; c_Roche^3
+    int n_l1_min;
+    float particle_mass;
+};
+
+// ---------------------------------------------------------------- predicates
+// Canonical minimum-image squared distance in FP64: the same sequence of IEEE
+// operations as the definition (differences of the float32 inputs promoted to
+// double, one image fold per axis, (xx + yy) + zz) with no fused multiply-add.
+__device__ __forceinline__ double d2_exact(float4 a, float4 b, double L, double half) {
+#pragma clang fp contract(off)
+    double dx = (double)b.x - (double)a.x;
+    double dy = (double)b.y - (double)a.y;
+    double dz = (double)b.z - (double)a.z;
+    if (dx > half) dx -= L; else if (dx < -half) dx += L;
+    if (dy > half) dy -= L; else if (dy < -half) dy += L;
+    if (dz > half) dz -= L; else if (dz < -half) dz += L;
+    double xx = dx * dx;
+    double yy = dy * dy;
+    double zz = dz * dz;
+    double s = xx + yy;
+    return s + zz;
+}
+
+__device__ __forceinline__ double e3(double e) {
+#pragma clang fp contract(off)
+    double ee = e * e;
+    return ee * e;
+}
+
+__device__ __forceinline__ double ii(int64_t k) {
+#pragma clang fp contract(off)
+    double x = (double)k;
+    return x * x;
+}
+
+__device__ __forceinline__ uint32_t orig_of(float4 p) { return __float_as_uint(p.w); }
+
+// "Denser" total order of nuclei: higher density, ties to the lower index.
+__device__ __forceinline__ bool denser(float da, uint32_t ia, float db, uint32_t ib) {
+    return da > db || (da == db && ia < ib);
+}
+
+__device__ __forceinline__ int wrapc(int c, int nc) {
+    return c < 0 ? c + nc : (c >= nc ? c - nc : c);
+}
+
+// --------------------------------------------------------------- workspace
+struct Work {
+    // binning
+    uint32_t *key, *ticket, *cnt, *off, *tmp;
+    float4 *spos, *sloc;
+    // density / FoF / groups (sorted order unless noted)
+    float *dens_s;
+    int32_t *parent, *minorig, *gkey, *gid_of, *owner;
+    uint32_t *gcnt, *goff, *gflag, *gidx, *gfill;   // key space [0, n]
+    int32_t *mem;                                     // members grouped by group
+    int32_t *g_start, *g_size, *g_label;              // per group
+    uint32_t *gccnt, *gcoff, *gcfill, *gcflag, *gcidx; // candidates per group
+    int32_t *glist;                                    // groups with candidates
+    int32_t *cand, *cand_sorted;                       // candidates
+    int32_t *h_nuc, *h_ienc, *h_gid, *g_nh;            // halo slots (= candidate slots)
+    uint32_t *h_count;
+    uint32_t *tflag, *tpos;                            // table rows (original index space)
+    uint32_t *hist;                                    // R search histograms
+    uint32_t *scan_tmp;
+    int32_t *counters;                                 // small device counters
+    int32_t *err;
+};
+
+// ------------------------------------------------------------------ launchers
+void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+// Exclusive scan: out[0..n] with out[n] = total.  tmp: scan_tmp_words(n) words.
+void scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipStream_t s);
+int64_t scan_tmp_words(int64_t n);
+
+void launch_bin(const float *pos, int64_t n, const Geo &g, Work &w, hipStream_t s);
+void launch_density(int64_t n, const Geo &g, Work &w, float *dens_out, hipStream_t s);
+void launch_count_pairs(int64_t n, const Geo &g, Work &w, unsigned long long *total, hipStream_t s);
+void launch_gather_density(const float *dens_in, int64_t n, Work &w, hipStream_t s);
+void launch_fof(int64_t n, const Geo &g, Work &w, hipStream_t s);
+void launch_fof_labels(int64_t n, const Geo &g, Work &w, int32_t *l0_out, hipStream_t s);
+void launch_keys_from_labels(const int32_t *l0_in, int64_t n, Work &w, hipStream_t s);
+void launch_segment(int64_t n, Work &w, hipStream_t s);
+void launch_segment_groups(int64_t n, int64_t G, Work &w, hipStream_t s);
+void launch_candidates(int64_t n, const Geo &g, Work &w, hipStream_t s);
+void launch_candidates_sort(int64_t n, int64_t G, int64_t NC, Work &w, hipStream_t s);
+void launch_accept(int64_t NGC, const Geo &g, Work &w, hipStream_t s);
+void launch_assign(int64_t n, const Geo &g, Work &w, hipStream_t s);
+void launch_output_flags(int64_t n, int64_t NC, const Geo &g, Work &w, hipStream_t s);
+void launch_output(int64_t n, int64_t NC, const Geo &g, Work &w, int32_t *halo_id,
+                   int32_t *l0_out, hf_halo *halos, int64_t cap, hipStream_t s);
+
+}  // namespace hf

@@ -1,0 +1,153 @@
+// Device-wide exclusive prefix sum of uint32 arrays and fill kernels.
+//
+// Three passes per level: tile sums (coalesced reads), a recursive scan of the
+// tile sums, and a tile scan staged through LDS that adds each tile's offset.
+// Tiles are 256 threads x 16 items; LDS indices are padded by one word per 32
+// to keep the per-thread runs of 16 words off a single bank.
+#include "hf_internal.h"
+
+namespace hf {
+
+namespace {
+
+constexpr int kIpt = 16;
+constexpr int kTile = kBlock * kIpt;
+
+__device__ __forceinline__ int pad(int i) { return i + (i >> 5); }
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan of one value per thread across the 256-thread block; *total
+// receives the block sum.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total) {
+    __shared__ uint32_t wsum[kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint32_t inc = wave_incl_scan(v);
+    if (lane == 63) wsum[wid] = inc;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < kBlock / 64; k++) {
+        if (k < wid) pre += wsum[k];
+        tot += wsum[k];
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + inc - v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_tile_sums(const uint32_t *__restrict__ in, int64_t n,
+                                                      uint32_t *__restrict__ sums) {
+    int64_t base = (int64_t)blockIdx.x * kTile;
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kIpt; k++) {
+        int64_t i = base + k * kBlock + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    uint32_t tot;
+    block_excl_scan(s, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_tile_scan(const uint32_t *__restrict__ in,
+                                                      uint32_t *__restrict__ out, int64_t n,
+                                                      const uint32_t *__restrict__ tile_off) {
+    __shared__ uint32_t buf[kTile + kTile / 32];
+    int64_t base = (int64_t)blockIdx.x * kTile;
+#pragma unroll
+    for (int k = 0; k < kIpt; k++) {
+        int idx = k * kBlock + threadIdx.x;
+        int64_t i = base + idx;
+        buf[pad(idx)] = i < n ? in[i] : 0u;
+    }
+    __syncthreads();
+    uint32_t v[kIpt];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kIpt; k++) {
+        v[k] = buf[pad(threadIdx.x * kIpt + k)];
+        s += v[k];
+    }
+    uint32_t tot;
+    uint32_t run = block_excl_scan(s, &tot);
+    uint32_t toff = tile_off ? tile_off[blockIdx.x] : 0u;
+    run += toff;
+#pragma unroll
+    for (int k = 0; k < kIpt; k++) {
+        buf[pad(threadIdx.x * kIpt + k)] = run;
+        run += v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kIpt; k++) {
+        int idx = k * kBlock + threadIdx.x;
+        int64_t i = base + idx;
+        if (i < n) out[i] = buf[pad(idx)];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = toff + tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+int64_t grid_for(int64_t n, int64_t cap = 1 << 20) {
+    int64_t b = (n + kBlock - 1) / kBlock;
+    if (b < 1) b = 1;
+    return b < cap ? b : cap;
+}
+
+}  // namespace
+
+void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n)), dim3(kBlock), 0, s, p, v, n);
+}
+
+void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n)), dim3(kBlock), 0, s, p, v, n);
+}
+
+int64_t scan_tmp_words(int64_t n) {
+    int64_t w = 0;
+    while (n > kTile) {
+        int64_t t = (n + kTile - 1) / kTile;
+        w += 2 * (t + 1);
+        n = t;
+    }
+    return w + 16;
+}
+
+void scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipStream_t s) {
+    int64_t tiles = (n + kTile - 1) / kTile;
+    if (tiles < 1) tiles = 1;
+    if (tiles == 1) {
+        hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kBlock), 0, s, in, out, n, nullptr);
+        return;
+    }
+    uint32_t *sums = tmp;
+    uint32_t *sums_scan = tmp + tiles + 1;
+    hipLaunchKernelGGL(k_tile_sums, dim3(tiles), dim3(kBlock), 0, s, in, n, sums);
+    scan_u32(sums, sums_scan, tiles, tmp + 2 * (tiles + 1), s);
+    hipLaunchKernelGGL(k_tile_scan, dim3(tiles), dim3(kBlock), 0, s, in, out, n, sums_scan);
+}
+
+}  // namespace hf
