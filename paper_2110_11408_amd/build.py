@@ -14,7 +14,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhf.so")
-SOURCES = ["scan.hip", "bin.hip", "density.hip", "fof.hip", "compaso.hip", "hf_api.hip"]
+SOURCES = ["scan.hip", "bin.hip", "density.hip", "fof.hip", "candidates.hip", "compaso.hip",
+           "hf_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=off",

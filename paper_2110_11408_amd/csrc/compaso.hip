@@ -44,9 +44,9 @@ __device__ __forceinline__ void stu(uint32_t *p, uint32_t v) {
 __global__ __launch_bounds__(kBlock) void k_seg_count(int64_t n, const int32_t *__restrict__ gkey,
                                                       uint32_t *__restrict__ gcnt) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int k = gkey[i];
-    if (k >= 0) atomicAdd(&gcnt[k], 1u);
+    const int k = i < n ? gkey[i] : -1;
+    const WaveRun r = wave_run(k);
+    if (k >= 0 && r.rank == 0) atomicAdd(&gcnt[k], (uint32_t)r.len);
 }
 
 __global__ __launch_bounds__(kBlock) void k_seg_flags(int64_t n, const uint32_t *__restrict__ gcnt,
@@ -79,72 +79,18 @@ __global__ __launch_bounds__(kBlock) void k_seg_scatter(int64_t n, const int32_t
                                                         int32_t *__restrict__ mem,
                                                         int32_t *__restrict__ gid_of) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = i < n ? gkey[i] : -1;
+    const WaveRun r = wave_run(k);
+    uint32_t base = 0;
+    if (k >= 0 && r.rank == 0) base = atomicAdd(&gfill[k], (uint32_t)r.len);
+    base = __shfl(base, r.head, 64);
     if (i >= n) return;
-    int k = gkey[i];
     if (k < 0) {
         gid_of[i] = -1;
         return;
     }
-    uint32_t slot = goff[k] + atomicAdd(&gfill[k], 1u);
-    mem[slot] = (int32_t)i;
+    mem[goff[k] + base + (uint32_t)r.rank] = (int32_t)i;
     gid_of[i] = (int32_t)gidx[k];
-}
-
-// --------------------------------------------------------------- candidates
-// Step 2 peak condition + step 4 floor: density >= floor and no denser particle
-// of the same L0 group (eligible or not) within b.
-__global__ __launch_bounds__(kBlock) void k_candidates(int64_t n, Geo g, const float4 *__restrict__ sloc,
-                                                       const float4 *__restrict__ spos,
-                                                       const uint32_t *__restrict__ off,
-                                                       const float *__restrict__ dens_s,
-                                                       const int32_t *__restrict__ gkey,
-                                                       const int32_t *__restrict__ gid_of,
-                                                       uint32_t *__restrict__ gccnt,
-                                                       int32_t *__restrict__ cflag) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    cflag[i] = 0;
-    const int key = gkey[i];
-    if (key < 0) return;
-    const float di = dens_s[i];
-    if (!((double)di >= g.floor_nuc)) return;
-    const float4 li = sloc[i];
-    const float4 pi = spos[i];
-    const uint32_t oi = orig_of(pi);
-    const uint32_t c = __float_as_uint(li.w);
-    const int nc = g.nc;
-    const int cx = (int)(c % (uint32_t)nc), cy = (int)((c / (uint32_t)nc) % (uint32_t)nc),
-              cz = (int)(c / ((uint32_t)nc * (uint32_t)nc));
-    for (int oz = -1; oz <= 1; oz++) {
-        const int z = wrapc(cz + oz, nc);
-        const float zs = li.z - (float)oz * g.cellb;
-        for (int oy = -1; oy <= 1; oy++) {
-            const int y = wrapc(cy + oy, nc);
-            const float ys = li.y - (float)oy * g.cellb;
-            const uint32_t row = ((uint32_t)z * (uint32_t)nc + (uint32_t)y) * (uint32_t)nc;
-            for (int ox = -1; ox <= 1; ox++) {
-                const int x = wrapc(cx + ox, nc);
-                const float xs = li.x - (float)ox * g.cellb;
-                const uint32_t nb = row + (uint32_t)x;
-                const uint32_t a = off[nb], b = off[nb + 1];
-                for (uint32_t j = a; j < b; j++) {
-                    const float dj = dens_s[j];
-                    if (dj < di) continue;
-                    if (gkey[j] != key || (int64_t)j == i) continue;
-                    const float4 pj = spos[j];
-                    if (!denser(dj, orig_of(pj), di, oi)) continue;
-                    const float4 lj = sloc[j];
-                    const float dx = lj.x - xs, dy = lj.y - ys, dz = lj.z - zs;
-                    const float d2f = dx * dx + dy * dy + dz * dz;
-                    if (d2f >= g.b2b_hi) continue;
-                    if (d2f >= g.b2b_lo && !(d2_exact(pi, pj, g.L, g.half) < g.b2)) continue;
-                    return;  // a denser particle of the group lies within b
-                }
-            }
-        }
-    }
-    cflag[i] = 1;
-    atomicAdd(&gccnt[gid_of[i]], 1u);
 }
 
 __global__ __launch_bounds__(kBlock) void k_cand_scatter(int64_t n, const int32_t *__restrict__ cflag,
@@ -220,7 +166,44 @@ __device__ __forceinline__ int64_t bucket_of(double T, int64_t m) {
     return k;
 }
 
-// One workgroup per L0 group that has candidates.
+constexpr int kHistLds = 12288;   // groups up to this size keep their histogram in LDS
+constexpr int kScanIpt = 16;      // buckets per thread per scan step
+
+// Block-wide exclusive scan of one value per thread (256 threads).
+__device__ __forceinline__ uint32_t block_excl(uint32_t v, uint32_t *s_red, uint32_t *total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint32_t inc = v;
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t t = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += t;
+    }
+    if (lane == 63) s_red[wid] = inc;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+    for (int w = 0; w < kBlock / 64; w++) {
+        if (w < wid) pre += s_red[w];
+        tot += s_red[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + inc - v;
+}
+
+__device__ __forceinline__ int block_min(int v, int *s_min) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int d = 32; d >= 1; d >>= 1) v = min(v, __shfl_xor(v, d, 64));
+    if (lane == 0) s_min[wid] = v;
+    __syncthreads();
+    int best = s_min[0];
+    for (int w = 1; w < kBlock / 64; w++) best = min(best, s_min[w]);
+    __syncthreads();
+    return best;
+}
+
+// One workgroup per L0 group that has candidates: walk the candidates in
+// descending density; a candidate inside alpha R of an accepted nucleus is
+// ineligible; an eligible one is accepted and its enclosed count i found from
+// the bucket histogram of all particles of the group.
 __global__ __launch_bounds__(kBlock) void k_accept(Geo g, const int32_t *__restrict__ glist,
                                                    const int32_t *__restrict__ g_start,
                                                    const int32_t *__restrict__ g_size,
@@ -234,16 +217,17 @@ __global__ __launch_bounds__(kBlock) void k_accept(Geo g, const int32_t *__restr
                                                    int32_t *__restrict__ h_gid,
                                                    int32_t *__restrict__ g_nh) {
 #pragma clang fp contract(off)
+    __shared__ uint32_t s_hist[kHistLds + 1];
     __shared__ int s_nh;
-    __shared__ int s_flag;
     __shared__ uint32_t s_red[kBlock / 64];
     __shared__ int s_min[kBlock / 64];
     const int gi = glist[blockIdx.x];
     const int64_t start = g_start[gi];
     const int64_t m = g_size[gi];
     const uint32_t cs = gcoff[gi], ce = gcoff[gi + 1];
-    uint32_t *hist = hist_all + start + gi;  // m + 1 buckets, disjoint per group
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const bool in_lds = m + 1 <= kHistLds;
+    uint32_t *ghist = hist_all + start + gi;  // m + 1 buckets, disjoint per group
+    const int tid = threadIdx.x;
     if (tid == 0) s_nh = 0;
     __syncthreads();
     for (uint32_t r = cs; r < ce; r++) {
@@ -257,48 +241,47 @@ __global__ __launch_bounds__(kBlock) void k_accept(Geo g, const int32_t *__restr
             if (g.K2 * e3(e) < g.A6 * ii(ldi(h_ienc + cs + h))) inel = 1;
         }
         if (__syncthreads_or(inel)) continue;
-        // R: histogram of buckets over all particles of the group
-        for (int64_t k = tid; k <= m; k += kBlock) stu(hist + k, 0u);
-        __threadfence();
+        // histogram of buckets over all particles of the group
+        if (in_lds) {
+            for (int64_t k = tid; k <= m; k += kBlock) s_hist[k] = 0u;
+        } else {
+            for (int64_t k = tid; k <= m; k += kBlock) stu(ghist + k, 0u);
+            __threadfence();
+        }
         __syncthreads();
         for (int64_t t = tid; t < m; t += kBlock) {
             const double e = d2_exact(pc, spos[mem[start + t]], g.L, g.half);
             const int64_t bk = bucket_of(g.K2 * e3(e), m);
-            atomicAdd(hist + bk, 1u);
+            if (in_lds) atomicAdd(&s_hist[bk], 1u);
+            else atomicAdd(ghist + bk, 1u);
         }
-        __threadfence();
+        if (!in_lds) __threadfence();
         __syncthreads();
         // first k in [1, m-1] with C(k) <= k, C(k) = sum of buckets 0..k
         int64_t found = m;
         uint32_t run = 0;
-        for (int64_t base = 0; base < m; base += kBlock) {
-            const int64_t k = base + tid;
-            uint32_t v = k < m ? ldu(hist + k) : 0u;
-            // inclusive block scan
-            uint32_t inc = v;
-            for (int d = 1; d < 64; d <<= 1) {
-                uint32_t tv = __shfl_up(inc, d, 64);
-                if (lane >= d) inc += tv;
+        for (int64_t base = 0; base < m; base += (int64_t)kBlock * kScanIpt) {
+            const int64_t k0 = base + (int64_t)tid * kScanIpt;
+            uint32_t v[kScanIpt];
+            uint32_t sum = 0;
+#pragma unroll
+            for (int u = 0; u < kScanIpt; u++) {
+                const int64_t k = k0 + u;
+                v[u] = k < m ? (in_lds ? s_hist[k] : ldu(ghist + k)) : 0u;
+                sum += v[u];
             }
-            if (lane == 63) s_red[wid] = inc;
-            __syncthreads();
-            uint32_t pre = 0, tot = 0;
-            for (int w = 0; w < kBlock / 64; w++) {
-                if (w < wid) pre += s_red[w];
-                tot += s_red[w];
+            uint32_t tot;
+            uint32_t C = run + block_excl(sum, s_red, &tot);
+            int hit = 0x7fffffff;
+#pragma unroll
+            for (int u = 0; u < kScanIpt; u++) {
+                const int64_t k = k0 + u;
+                C += v[u];
+                if (hit == 0x7fffffff && k >= 1 && k < m && (int64_t)C <= k) hit = (int)(k - base);
             }
-            const uint32_t Ck = run + pre + inc;
-            const bool hit = k >= 1 && k < m && (int64_t)Ck <= k;
-            // block minimum of the hit positions
-            int cand_k = hit ? (int)(k - base) : kBlock;
-            for (int d = 32; d >= 1; d >>= 1) cand_k = min(cand_k, __shfl_xor(cand_k, d, 64));
-            if (lane == 0) s_min[wid] = cand_k;
-            __syncthreads();
-            int best = kBlock;
-            for (int w = 0; w < kBlock / 64; w++) best = min(best, s_min[w]);
-            __syncthreads();
+            const int best = block_min(hit, s_min);
             run += tot;
-            if (best < kBlock) {
+            if (best != 0x7fffffff) {
                 found = base + best;
                 break;
             }
@@ -328,8 +311,7 @@ __global__ __launch_bounds__(kBlock) void k_assign(int64_t n, Geo g, const int32
                                                    uint32_t *__restrict__ h_count) {
 #pragma clang fp contract(off)
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int gi = gid_of[i];
+    const int gi = i < n ? gid_of[i] : -1;
     int own = -1;
     if (gi >= 0) {
         const uint32_t cs = gcoff[gi];
@@ -354,9 +336,10 @@ __global__ __launch_bounds__(kBlock) void k_assign(int64_t n, Geo g, const int32
                 iown = ih;
             }
         }
-        if (own >= 0) atomicAdd(&h_count[own], 1u);
     }
-    owner[i] = own;
+    const WaveRun r = wave_run(own);
+    if (own >= 0 && r.rank == 0) atomicAdd(&h_count[own], (uint32_t)r.len);
+    if (i < n) owner[i] = own;
 }
 
 // ------------------------------------------------------------------- output
@@ -367,10 +350,10 @@ __global__ __launch_bounds__(kBlock) void k_out_flags(int64_t NC, Geo g, const i
                                                       uint32_t *__restrict__ tflag,
                                                       int32_t *__restrict__ counters) {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= NC) return;
-    int nuc = h_nuc[s];
+    const int nuc = s < NC ? h_nuc[s] : -1;
+    const uint64_t b = __ballot(nuc >= 0);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(&counters[2], __popcll(b));
     if (nuc < 0) return;
-    atomicAdd(&counters[2], 1);
     if (h_count[s] >= (uint32_t)g.n_l1_min) tflag[orig_of(spos[nuc])] = 1u;
 }
 
@@ -439,11 +422,6 @@ void launch_segment_groups(int64_t n, int64_t G, Work &w, hipStream_t s) {
                        w.mem, w.gid_of);
     fill_u32(w.gccnt, 0u, G + 1, s);
     fill_u32(w.gcfill, 0u, G + 1, s);
-}
-
-void launch_candidates(int64_t n, const Geo &g, Work &w, hipStream_t s) {
-    hipLaunchKernelGGL(k_candidates, grid(n), dim3(kBlock), 0, s, n, g, w.sloc, w.spos, w.off, w.dens_s,
-                       w.gkey, w.gid_of, w.gccnt, w.owner /* candidate flags */);
 }
 
 void launch_candidates_sort(int64_t n, int64_t G, int64_t NC, Work &w, hipStream_t s) {

@@ -1,28 +1,114 @@
 // Kernel density (Sec. 2.2.1): Delta_i = norm * sum_{j != i, r_ij < b} (1 - r_ij^2/b^2),
 // norm = 15 / (8 pi b^3 nbar) so that a uniform field has Delta = 1 (App. B.2).
 //
-// One thread per particle in cell order; consecutive threads mostly share a cell
-// and therefore walk the same 27 neighbour cells in lockstep, so neighbour
-// reads are broadcasts from the same cache lines.  Coordinates are the
-// cell-local FP32 values in units of b; the periodic image of a neighbour cell
-// is the exact cell offset, so W = 1 - d^2 is evaluated as three FMAs on
-// (dx, dy, dz) and clamped at 0 (which also removes pairs beyond b).  The self
-// pair contributes exactly 1 and is subtracted at the end.  Partial sums run
-// over at most 64 neighbours in FP32 and are accumulated in FP64.
+// Coordinates are the cell-local FP32 values in units of b; the periodic image
+// of a neighbour cell is the exact cell offset, so W = 1 - d^2 is three FMAs on
+// (dx, dy, dz) clamped at 0 (which also removes pairs beyond b).  The self pair
+// contributes exactly 1 and is subtracted at the end.  Partial sums run over at
+// most 64 neighbours in FP32 and are accumulated in FP64, in cell order, so the
+// result does not depend on the launch shape.
+//
+// Dense cells: one wavefront per chunk of <= 64 particles of the cell (one per
+// lane); the 27 neighbour cells are streamed in the same order by all lanes,
+// so neighbour coordinates are wave-uniform and come through the scalar cache
+// as SGPR operands of the FP32 FMAs.  Sparse cells: one thread per particle.
 #include "hf_internal.h"
 
 namespace hf {
 
 namespace {
 
-__global__ __launch_bounds__(kBlock) void k_density(int64_t n, Geo g,
-                                                    const float4 *__restrict__ sloc,
-                                                    const float4 *__restrict__ spos,
-                                                    const uint32_t *__restrict__ off,
-                                                    float *__restrict__ dens_s,
-                                                    float *__restrict__ dens_out) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// Accumulate one neighbour cell [a, b) for an i-particle at shifted local
+// coordinates (xs, ys, zs).  `a`, `b` are uniform in the dense kernel.
+__device__ __forceinline__ void accum_range(const float4 *__restrict__ sloc, uint32_t a, uint32_t b,
+                                            float xs, float ys, float zs, double &acc) {
+    for (uint32_t j0 = a; j0 < b; j0 += 64) {
+        const uint32_t e = min(j0 + 64u, b);
+        float p = 0.0f;
+        uint32_t j = j0;
+        for (; j + 4 <= e; j += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const float4 lj = sloc[j + u];
+                const float dx = lj.x - xs, dy = lj.y - ys, dz = lj.z - zs;
+                float t = fmaf(-dx, dx, 1.0f);
+                t = fmaf(-dy, dy, t);
+                t = fmaf(-dz, dz, t);
+                p += fmaxf(t, 0.0f);
+            }
+        }
+        for (; j < e; j++) {
+            const float4 lj = sloc[j];
+            const float dx = lj.x - xs, dy = lj.y - ys, dz = lj.z - zs;
+            float t = fmaf(-dx, dx, 1.0f);
+            t = fmaf(-dy, dy, t);
+            t = fmaf(-dz, dz, t);
+            p += fmaxf(t, 0.0f);
+        }
+        acc += (double)p;
+    }
+}
+
+__device__ __forceinline__ void write_density(int64_t i, double acc, const Geo &g,
+                                              const float4 *__restrict__ spos,
+                                              float *__restrict__ dens_s, float *__restrict__ dens_out) {
+    const double S = acc - (g.self_count ? 0.0 : 1.0);
+    const float d = (float)(g.norm * S);
+    dens_s[i] = d;
+    if (dens_out) dens_out[orig_of(spos[i])] = d;
+}
+
+__global__ __launch_bounds__(kBlock) void k_density_dense(int64_t nchunks, Geo g,
+                                                          const int32_t *__restrict__ chunks,
+                                                          const float4 *__restrict__ sloc,
+                                                          const float4 *__restrict__ spos,
+                                                          const uint32_t *__restrict__ off,
+                                                          float *__restrict__ dens_s,
+                                                          float *__restrict__ dens_out) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t q = (int64_t)blockIdx.x * (kBlock / 64) + wave;
+    if (q >= nchunks) return;
+    const int lane = threadIdx.x & 63;
+    const uint32_t h = (uint32_t)__builtin_amdgcn_readfirstlane(chunks[q]);
+    const uint32_t c = __builtin_amdgcn_readfirstlane(__float_as_uint(sloc[h].w));
+    const uint32_t cend = __builtin_amdgcn_readfirstlane(off[c + 1]);
+    const uint32_t end = min(h + 64u, cend);
+    const uint32_t i = h + (uint32_t)lane;
+    const bool active = i < end;
+    const float4 li = sloc[active ? i : h];
+    const int nc = g.nc;
+    const int cx = (int)(c % (uint32_t)nc), cy = (int)((c / (uint32_t)nc) % (uint32_t)nc),
+              cz = (int)(c / ((uint32_t)nc * (uint32_t)nc));
+    double acc = 0.0;
+    for (int oz = -1; oz <= 1; oz++) {
+        const int z = wrapc(cz + oz, nc);
+        const float zs = li.z - (float)oz * g.cellb;
+        for (int oy = -1; oy <= 1; oy++) {
+            const int y = wrapc(cy + oy, nc);
+            const float ys = li.y - (float)oy * g.cellb;
+            const uint32_t row = ((uint32_t)z * (uint32_t)nc + (uint32_t)y) * (uint32_t)nc;
+            for (int ox = -1; ox <= 1; ox++) {
+                const uint32_t nb = row + (uint32_t)wrapc(cx + ox, nc);
+                const float xs = li.x - (float)ox * g.cellb;
+                const uint32_t a = __builtin_amdgcn_readfirstlane(off[nb]);
+                const uint32_t b = __builtin_amdgcn_readfirstlane(off[nb + 1]);
+                accum_range(sloc, a, b, xs, ys, zs, acc);
+            }
+        }
+    }
+    if (active) write_density(i, acc, g, spos, dens_s, dens_out);
+}
+
+__global__ __launch_bounds__(kBlock) void k_density_sparse(int64_t nsparse, Geo g,
+                                                           const int32_t *__restrict__ sparse,
+                                                           const float4 *__restrict__ sloc,
+                                                           const float4 *__restrict__ spos,
+                                                           const uint32_t *__restrict__ off,
+                                                           float *__restrict__ dens_s,
+                                                           float *__restrict__ dens_out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nsparse) return;
+    const int64_t i = sparse[t];
     const float4 li = sloc[i];
     const uint32_t c = __float_as_uint(li.w);
     const int nc = g.nc;
@@ -37,30 +123,13 @@ __global__ __launch_bounds__(kBlock) void k_density(int64_t n, Geo g,
             const float ys = li.y - (float)oy * g.cellb;
             const uint32_t row = ((uint32_t)z * (uint32_t)nc + (uint32_t)y) * (uint32_t)nc;
             for (int ox = -1; ox <= 1; ox++) {
-                const int x = wrapc(cx + ox, nc);
+                const uint32_t nb = row + (uint32_t)wrapc(cx + ox, nc);
                 const float xs = li.x - (float)ox * g.cellb;
-                const uint32_t nb = row + (uint32_t)x;
-                const uint32_t a = off[nb], b = off[nb + 1];
-                for (uint32_t j0 = a; j0 < b; j0 += 64) {
-                    const uint32_t e = min(j0 + 64u, b);
-                    float p = 0.0f;
-                    for (uint32_t j = j0; j < e; j++) {
-                        const float4 lj = sloc[j];
-                        const float dx = lj.x - xs, dy = lj.y - ys, dz = lj.z - zs;
-                        float t = fmaf(-dx, dx, 1.0f);
-                        t = fmaf(-dy, dy, t);
-                        t = fmaf(-dz, dz, t);
-                        p += fmaxf(t, 0.0f);
-                    }
-                    acc += (double)p;
-                }
+                accum_range(sloc, off[nb], off[nb + 1], xs, ys, zs, acc);
             }
         }
     }
-    const double S = acc - (g.self_count ? 0.0 : 1.0);
-    const float d = (float)(g.norm * S);
-    dens_s[i] = d;
-    if (dens_out) dens_out[orig_of(spos[i])] = d;
+    write_density(i, acc, g, spos, dens_s, dens_out);
 }
 
 // Number of ordered pairs (i, j != i) closer than b, for the roofline's
@@ -108,8 +177,13 @@ __global__ __launch_bounds__(kBlock) void k_gather_density(int64_t n, const floa
 }  // namespace
 
 void launch_density(int64_t n, const Geo &g, Work &w, float *dens_out, hipStream_t s) {
-    hipLaunchKernelGGL(k_density, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, g, w.sloc,
-                       w.spos, w.off, w.dens_s, dens_out);
+    if (w.nchunks > 0)
+        hipLaunchKernelGGL(k_density_dense, dim3((unsigned)((w.nchunks + 3) / 4)), dim3(kBlock), 0, s,
+                           w.nchunks, g, w.chunks, w.sloc, w.spos, w.off, w.dens_s, dens_out);
+    if (w.nsparse > 0)
+        hipLaunchKernelGGL(k_density_sparse, dim3((unsigned)((w.nsparse + kBlock - 1) / kBlock)),
+                           dim3(kBlock), 0, s, w.nsparse, g, w.sparse, w.sloc, w.spos, w.off, w.dens_s,
+                           dens_out);
 }
 
 void launch_count_pairs(int64_t n, const Geo &g, Work &w, unsigned long long *total, hipStream_t s) {

@@ -91,6 +91,15 @@ hf_status make_geo(hf_ctx *c, const hf_params *p, int64_t n, Geo *g) {
     g->inv_cell = (double)g->nc / L;
     g->inv_b = 1.0 / d[D_B];
     g->cellb = (float)(g->cell / d[D_B]);
+    // sub-cells: diagonal below l (with a 0.1% margin), at most 6 per side
+    double kd = floor(g->cell * sqrt(3.0) / d[D_L] * (1.0 + 1e-3)) + 1.0;
+    if (kd > 6.0)
+        return fail(c, HF_ERR_INVALID, "l_fof must be at least 0.29 of the cell side (about 0.29 b)");
+    g->ksub = (int)kd;
+    g->inv_sub = g->ksub / g->cell;
+    g->sub2 = (g->cell / g->ksub) * (g->cell / g->ksub);
+    g->rsub = (int)ceil(d[D_L] * g->ksub / g->cell);
+    if (g->rsub > g->ksub) g->rsub = g->ksub;
     // FP32 prefilter margin (units of b^2): 256 ulps of the largest local
     // coordinate difference, ten times the error bound of the FP32 path.
     double M = 2.0 * g->cellb + 1.0;
@@ -127,16 +136,29 @@ struct Carver {
     }
 };
 
-size_t carve(char *base, int64_t n, int64_t ncell, Work *w) {
+size_t carve(char *base, int64_t n, int64_t ncell, int nsub, Work *w) {
     Carver c{base};
     int64_t n1 = n + 1;
     w->key = c.take<uint32_t>(n);
     w->ticket = c.take<uint32_t>(n);
     w->cnt = c.take<uint32_t>(ncell + 1);
     w->off = c.take<uint32_t>(ncell + 1);
-    w->tmp = c.take<uint32_t>(n);
+    w->tmp = c.take<uint64_t>(n);
+    w->subk = c.take<uint16_t>(n);
+    w->ssub = c.take<uint16_t>(n);
     w->spos = c.take<float4>(n);
     w->sloc = c.take<float4>(n);
+    w->f_chunk = c.take<uint32_t>(n1);
+    w->s_chunk = c.take<uint32_t>(n1);
+    w->f_dcell = c.take<uint32_t>(n1);
+    w->s_dcell = c.take<uint32_t>(n1);
+    w->f_sparse = c.take<uint32_t>(n1);
+    w->s_sparse = c.take<uint32_t>(n1);
+    w->chunks = c.take<int32_t>(n1);
+    w->sparse = c.take<int32_t>(n1);
+    w->dcells = c.take<uint32_t>(n1);
+    w->runlist = c.take<int32_t>(n1);
+    w->subtab = c.take<uint32_t>((n / hf::kDenseMin + 1) * (nsub + 1));
     w->dens_s = c.take<float>(n);
     w->parent = c.take<int32_t>(n);
     w->minorig = c.take<int32_t>(n);
@@ -176,7 +198,8 @@ size_t carve(char *base, int64_t n, int64_t ncell, Work *w) {
 
 hf_status prepare(hf_ctx *c, int64_t n, const Geo &g, Work *w) {
     int64_t ncell = (int64_t)g.nc * g.nc * g.nc;
-    size_t need = carve(nullptr, n, ncell, w);
+    const int nsub = g.ksub * g.ksub * g.ksub;
+    size_t need = carve(nullptr, n, ncell, nsub, w);
     HIP_OK(c, hipSetDevice(c->device));
     if (need > c->arena_bytes) {
         if (c->arena) {
@@ -193,7 +216,7 @@ hf_status prepare(hf_ctx *c, int64_t n, const Geo &g, Work *w) {
         }
         c->arena_bytes = want;
     }
-    carve((char *)c->arena, n, ncell, w);
+    carve((char *)c->arena, n, ncell, nsub, w);
     c->stats = hf_stats{};
     c->stats.n_cells = ncell;
     return HF_OK;
@@ -224,10 +247,13 @@ hf_status run_compaso(hf_ctx *c, int64_t n, const Geo &g, Work &w, int32_t *halo
                       hipStream_t s) {
     HIP_OK(c, hipEventRecord(c->ev[3], s));
     hf::launch_segment(n, w, s);
-    uint32_t G32 = 0;
+    uint32_t G32 = 0, M32 = 0;
     HIP_OK(c, hipMemcpyAsync(&G32, w.gidx + n, sizeof(G32), hipMemcpyDeviceToHost, s));
+    HIP_OK(c, hipMemcpyAsync(&M32, w.goff + n, sizeof(M32), hipMemcpyDeviceToHost, s));
     HIP_OK(c, hipStreamSynchronize(s));
     int64_t G = G32;
+    c->stats.n_groups = G;
+    c->stats.n_members = M32;
     hf::launch_segment_groups(n, G, w, s);
     HIP_OK(c, hipEventRecord(c->ev[4], s));
     hf::launch_candidates(n, g, w, s);
@@ -274,16 +300,34 @@ hf_status begin(hf_ctx *c, const float *pos, int64_t n, const hf_params *p, Geo 
     if (!c) return HF_ERR_INVALID;
     c->err.clear();
     if (!p) return fail(c, HF_ERR_INVALID, "params is NULL");
+    if (n < 0) return fail(c, HF_ERR_INVALID, "n is negative");
+    if (n == 0) {
+        // an empty input is valid; only the parameter values are checked
+        double d[D_COUNT];
+        hf_params q = *p;
+        if (!(q.mean_density > 0.0)) q.mean_density = 1.0;
+        if (derive(&q, 1, d) != HF_OK) return fail(c, HF_ERR_INVALID, "invalid parameters");
+        return HF_OK;
+    }
     hf_status st = make_geo(c, p, n, g);
     if (st != HF_OK) return st;
-    if (n > 0 && !pos) return fail(c, HF_ERR_INVALID, "pos is NULL");
-    if (n == 0) return HF_OK;
+    if (!pos) return fail(c, HF_ERR_INVALID, "pos is NULL");
     st = prepare(c, n, *g, w);
     if (st != HF_OK) return st;
     hf::fill_i32(w->counters, 0, 16, s);
     hf::fill_i32(w->err, 0, 4, s);
     HIP_OK(c, hipEventRecord(c->ev[0], s));
     hf::launch_bin(pos, n, *g, *w, s);
+    uint32_t counts[3] = {0, 0, 0};
+    HIP_OK(c, hipMemcpyAsync(&counts[0], w->s_chunk + n, 4, hipMemcpyDeviceToHost, s));
+    HIP_OK(c, hipMemcpyAsync(&counts[1], w->s_dcell + n, 4, hipMemcpyDeviceToHost, s));
+    HIP_OK(c, hipMemcpyAsync(&counts[2], w->s_sparse + n, 4, hipMemcpyDeviceToHost, s));
+    HIP_OK(c, hipStreamSynchronize(s));
+    w->nchunks = counts[0];
+    w->ndcells = counts[1];
+    w->nsparse = counts[2];
+    w->nruns = 0;
+    hf::launch_subtab(n, w->ndcells, *g, *w, s);
     HIP_OK(c, hipEventRecord(c->ev[1], s));
     return HF_OK;
 }
@@ -408,15 +452,17 @@ hf_status hf_l0_fof(hf_ctx *c, const float *pos, const float *density, int64_t n
     hf::launch_fof(n, g, w, s);
     hf::launch_fof_labels(n, g, w, l0_id, s);
     HIP_OK(c, hipEventRecord(c->ev[3], s));
-    int32_t counters[16];
-    HIP_OK(c, hipMemcpyAsync(counters, w.counters, sizeof(counters), hipMemcpyDeviceToHost, s));
+    hf::launch_segment(n, w, s);
+    uint32_t G32 = 0, M32 = 0;
+    HIP_OK(c, hipMemcpyAsync(&G32, w.gidx + n, sizeof(G32), hipMemcpyDeviceToHost, s));
+    HIP_OK(c, hipMemcpyAsync(&M32, w.goff + n, sizeof(M32), hipMemcpyDeviceToHost, s));
     st = check_pos_flags(c, w, s);
     c->stats.ms_bin = elapsed(c->ev[0], c->ev[1]);
     c->stats.ms_fof = elapsed(c->ev[2], c->ev[3]);
     c->stats.ms_total = elapsed(c->ev[0], c->ev[3]);
-    c->stats.n_members = counters[0];
-    c->stats.n_groups = counters[1];
-    if (n_groups) *n_groups = counters[1];
+    c->stats.n_members = M32;
+    c->stats.n_groups = G32;
+    if (n_groups) *n_groups = G32;
     return st;
 }
 
@@ -468,14 +514,10 @@ hf_status hf_find(hf_ctx *c, const float *pos, int64_t n, const hf_params *p, fl
     st = check_pos_flags(c, w, s);
     if (st != HF_OK) return st;
     st = run_compaso(c, n, g, w, halo_id, nullptr, halos, halos_cap, n_halos, s);
-    int32_t counters[16];
-    HIP_OK(c, hipMemcpy(counters, w.counters, sizeof(counters), hipMemcpyDeviceToHost));
     c->stats.ms_bin = elapsed(c->ev[0], c->ev[1]);
     c->stats.ms_density = elapsed(c->ev[1], c->ev[2]);
     c->stats.ms_fof = elapsed(c->ev[2], c->ev[9]);
     c->stats.ms_total = elapsed(c->ev[0], c->ev[8]);
-    c->stats.n_members = counters[0];
-    c->stats.n_groups = counters[1];
     return st;
 }
 

@@ -10,6 +10,7 @@
 namespace hf {
 
 constexpr int kBlock = 256;
+constexpr int kDenseMin = 8;   // a cell with at least this many particles is "dense"
 
 // Constants of one call, computed on the host (see hf_derived) and passed by
 // value to the kernels.
@@ -19,6 +20,10 @@ struct Geo {
     double inv_b;          // 1/b: local coordinates are stored in units of b
     float cellb;           // cell / b in FP32 (image offset of a neighbour cell)
     int nc;                // cells per side (>= 3)
+    int ksub;              // sub-cells per cell side (sub-cell diagonal < l)
+    int rsub;              // FoF reach in sub-cells: ceil(l / sub-cell side)
+    double inv_sub;        // ksub / cell
+    double sub2;           // squared sub-cell side
     double b2, l2;         // FP64 squared radii of the peak test and of FoF links
     float l2b_lo, l2b_hi;  // (l/b)^2 shrunk / grown by the FP32 prefilter margin
     float b2b_lo, b2b_hi;  // 1 shrunk / grown by the same margin (peak test, units of b^2)
@@ -73,11 +78,54 @@ __device__ __forceinline__ int wrapc(int c, int nc) {
     return c < 0 ? c + nc : (c >= nc ? c - nc : c);
 }
 
+__device__ __forceinline__ bool is_member(const float *dens_s, int64_t j, double dl0) {
+    return (double)dens_s[j] > dl0;
+}
+
+// Runs of equal keys among consecutive lanes of a wavefront: the lane of the
+// run's first element, this lane's rank in the run, and the run length.  Used
+// to aggregate atomics on sorted data (one atomic per run instead of per lane).
+struct WaveRun {
+    int head, rank, len;
+};
+
+__device__ __forceinline__ WaveRun wave_run(int key) {
+    const int lane = threadIdx.x & 63;
+    const int prev = __shfl_up(key, 1, 64);
+    const bool is_head = lane == 0 || prev != key;
+    const uint64_t heads = __ballot(is_head);
+    const uint64_t le = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
+    const int head = 63 - __clzll(heads & le);
+    const uint64_t upto_head = head == 63 ? ~0ull : ((2ull << head) - 1ull);
+    const uint64_t above = heads & ~upto_head;
+    const int next = above ? __ffsll((unsigned long long)above) - 1 : 64;
+    return WaveRun{head, lane - head, next - head};
+}
+
+// Minimum of v over the lane's run (valid in the run's head lane).
+__device__ __forceinline__ int32_t wave_run_min(int32_t v, const WaveRun &r) {
+    const int lane = threadIdx.x & 63;
+    const int end = r.head + r.len;
+    for (int d = 1; d < 64; d <<= 1) {
+        int32_t o = __shfl_down(v, d, 64);
+        if (lane + d < end) v = min(v, o);
+    }
+    return v;
+}
+
 // --------------------------------------------------------------- workspace
 struct Work {
     // binning
-    uint32_t *key, *ticket, *cnt, *off, *tmp;
+    uint32_t *key, *ticket, *cnt, *off;
+    uint64_t *tmp;
+    uint16_t *subk, *ssub;
     float4 *spos, *sloc;
+    // work decomposition (dense chunks, dense cells, sparse particles)
+    uint32_t *f_chunk, *s_chunk, *f_dcell, *s_dcell, *f_sparse, *s_sparse;
+    int32_t *chunks, *sparse;
+    uint32_t *dcells, *subtab;
+    int32_t *runlist;
+    int64_t nchunks, ndcells, nsparse, nruns;
     // density / FoF / groups (sorted order unless noted)
     float *dens_s;
     int32_t *parent, *minorig, *gkey, *gid_of, *owner;
@@ -104,6 +152,7 @@ void scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipSt
 int64_t scan_tmp_words(int64_t n);
 
 void launch_bin(const float *pos, int64_t n, const Geo &g, Work &w, hipStream_t s);
+void launch_subtab(int64_t n, int64_t ndc, const Geo &g, Work &w, hipStream_t s);
 void launch_density(int64_t n, const Geo &g, Work &w, float *dens_out, hipStream_t s);
 void launch_count_pairs(int64_t n, const Geo &g, Work &w, unsigned long long *total, hipStream_t s);
 void launch_gather_density(const float *dens_in, int64_t n, Work &w, hipStream_t s);
@@ -112,7 +161,7 @@ void launch_fof_labels(int64_t n, const Geo &g, Work &w, int32_t *l0_out, hipStr
 void launch_keys_from_labels(const int32_t *l0_in, int64_t n, Work &w, hipStream_t s);
 void launch_segment(int64_t n, Work &w, hipStream_t s);
 void launch_segment_groups(int64_t n, int64_t G, Work &w, hipStream_t s);
-void launch_candidates(int64_t n, const Geo &g, Work &w, hipStream_t s);
+void launch_candidates(int64_t n, const Geo &g, Work &w, hipStream_t s);   // candidates.hip
 void launch_candidates_sort(int64_t n, int64_t G, int64_t NC, Work &w, hipStream_t s);
 void launch_accept(int64_t NGC, const Geo &g, Work &w, hipStream_t s);
 void launch_assign(int64_t n, const Geo &g, Work &w, hipStream_t s);

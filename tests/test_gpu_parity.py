@@ -163,8 +163,11 @@ def test_edge_cases(ctx):
     # one particle
     _say("[gpu] edge: one particle")
     one = np.array([[1.0, 2.0, 3.0]], np.float32)
-    g = gpu_find(ctx, one, box=5.0)
+    g = gpu_find(ctx, one, box=5.0, mean_density=1.0)
     assert g["density"][0] == 0.0 and g["n_halos"] == 0 and g["l0"][0] == 0
+    # one particle alone sets l_mean = box, so b spans more than a third of the box
+    with pytest.raises(HfError):
+        gpu_find(ctx, one, box=5.0)
     # nothing above the L0 threshold
     _say("[gpu] edge: sparse")
     rng = np.random.default_rng(3)
