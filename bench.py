@@ -132,7 +132,10 @@ def main():
         "stages_ms": stages,
         "counts": {"pairs_within_b": pairs, "n_cells": st["n_cells"], "n_members": st["n_members"],
                    "n_groups": st["n_groups"], "n_candidates": st["n_candidates"],
-                   "n_found": st["n_found"], "n_halos": out["n_halos"]},
+                   "n_found": st["n_found"], "n_halos": out["n_halos"],
+                   "n_dense_cells": st["n_dense_cells"], "n_dense_chunks": st["n_dense_chunks"],
+                   "n_sparse": st["n_sparse"], "n_subcell_runs": st["n_subcell_runs"],
+                   "n_hard": st["n_hard"]},
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(args.cpu_seconds)

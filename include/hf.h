@@ -92,6 +92,11 @@ typedef struct {
     int64_t n_candidates;     /* nucleus candidates (local peaks above the floor) */
     int64_t n_found;          /* halos before the output cut                    */
     int64_t n_halos;          /* halos after the cut                            */
+    int64_t n_dense_cells;    /* cells holding >= 8 particles                   */
+    int64_t n_dense_chunks;   /* 64-particle wavefront chunks of dense cells    */
+    int64_t n_sparse;         /* particles of the other cells                   */
+    int64_t n_subcell_runs;   /* dense sub-cells holding an L0 member           */
+    int64_t n_hard;           /* candidate tests not settled by the own sub-cell */
 } hf_stats;
 
 typedef struct hf_ctx hf_ctx;

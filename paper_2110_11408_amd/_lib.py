@@ -42,7 +42,8 @@ class HfStats(ctypes.Structure):
                 ("ms_bin", "ms_density", "ms_fof", "ms_segment", "ms_candidates", "ms_accept",
                  "ms_assign", "ms_output", "ms_total")] + \
                [(k, ctypes.c_int64) for k in
-                ("n_cells", "n_members", "n_groups", "n_candidates", "n_found", "n_halos")]
+                ("n_cells", "n_members", "n_groups", "n_candidates", "n_found", "n_halos",
+                 "n_dense_cells", "n_dense_chunks", "n_sparse", "n_subcell_runs", "n_hard")]
 
 
 HALO_FIELDS = [f[0] for f in HfHalo._fields_]

@@ -84,7 +84,15 @@ __global__ __launch_bounds__(kBlock) void k_bin_stable(const float *__restrict__
     const uint32_t c = key[o];
     const uint32_t a = off[c], b = off[c + 1];
     uint32_t rank = 0;
-    for (uint32_t t = a; t < b; t++) rank += tmp[t] < me ? 1u : 0u;
+    // a wavefront whose slots all lie in one cell streams that cell once
+    // (wave-uniform loads); otherwise every lane walks its own cell
+    const uint32_t c0 = __builtin_amdgcn_readfirstlane(c);
+    if (__ballot(c != c0) == 0ull && s - (threadIdx.x & 63) + 63 < n) {
+        const uint32_t ua = __builtin_amdgcn_readfirstlane(a), ub = __builtin_amdgcn_readfirstlane(b);
+        for (uint32_t t = ua; t < ub; t++) rank += tmp[t] < me ? 1u : 0u;
+    } else {
+        for (uint32_t t = a; t < b; t++) rank += tmp[t] < me ? 1u : 0u;
+    }
     const uint32_t d = a + rank;
     float x = pos[3 * (int64_t)o + 0], y = pos[3 * (int64_t)o + 1], z = pos[3 * (int64_t)o + 2];
     spos[d] = make_float4(x, y, z, __uint_as_float(o));

@@ -5,10 +5,9 @@
 // the densities and the groups, so it is decided for all particles at once,
 // before the sequential part of CompaSO.
 //
-// Dense cells: one wavefront per chunk of <= 64 particles; every lane tests its
-// own particle against the same neighbour stream (own cell first, where a
-// denser neighbour is most likely), and the wave leaves as soon as every
-// active lane has found a denser neighbour.  Sparse cells: one thread each.
+// Two stages: most particles are settled by the densest particle of their own
+// sub-cell; the rest (sub-cell maxima and particles of sparse cells) search
+// their neighbourhood with sub-cell pruning.
 #include "hf_internal.h"
 
 namespace hf {
@@ -23,10 +22,19 @@ __device__ __forceinline__ void stencil_offset(int t, int &ox, int &oy, int &oz)
     oz = u / 9 - 1;
 }
 
-__device__ __forceinline__ bool denser_within_b(float dj, uint32_t oj, int kj, float4 lj, float4 pj,
-                                                int key, float di, uint32_t oi, float xs, float ys,
-                                                float zs, const float4 &pi, const Geo &g) {
-    if (kj != key || !denser(dj, oj, di, oi)) return false;
+// j is a denser particle of the same group within b (FP32 prefilter on the
+// cell-local coordinates, canonical FP64 distance in the undecided band).
+__device__ __forceinline__ bool denser_within_b(int64_t j, const float *__restrict__ dens_s,
+                                                const int32_t *__restrict__ gkey,
+                                                const float4 *__restrict__ sloc,
+                                                const float4 *__restrict__ spos, int key, float di,
+                                                uint32_t oi, float xs, float ys, float zs,
+                                                const float4 &pi, const Geo &g) {
+    const float dj = dens_s[j];
+    if (dj < di || gkey[j] != key) return false;
+    const float4 pj = spos[j];
+    if (!denser(dj, orig_of(pj), di, oi)) return false;
+    const float4 lj = sloc[j];
     const float dx = lj.x - xs, dy = lj.y - ys, dz = lj.z - zs;
     const float d2f = dx * dx + dy * dy + dz * dz;
     if (d2f >= g.b2b_hi) return false;
@@ -34,102 +42,146 @@ __device__ __forceinline__ bool denser_within_b(float dj, uint32_t oj, int kj, f
     return d2_exact(pi, pj, g.L, g.half) < g.b2;
 }
 
-__global__ __launch_bounds__(kBlock) void k_cand_dense(int64_t nchunks, Geo g,
-                                                       const int32_t *__restrict__ chunks,
-                                                       const float4 *__restrict__ sloc,
-                                                       const float4 *__restrict__ spos,
-                                                       const uint32_t *__restrict__ off,
-                                                       const float *__restrict__ dens_s,
-                                                       const int32_t *__restrict__ gkey,
-                                                       const int32_t *__restrict__ gid_of,
-                                                       uint32_t *__restrict__ gccnt,
-                                                       int32_t *__restrict__ cflag) {
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t q = (int64_t)blockIdx.x * (kBlock / 64) + wave;
-    if (q >= nchunks) return;
-    const int lane = threadIdx.x & 63;
-    const uint32_t h = (uint32_t)__builtin_amdgcn_readfirstlane(chunks[q]);
-    const uint32_t c = __builtin_amdgcn_readfirstlane(__float_as_uint(sloc[h].w));
-    const uint32_t end = min(h + 64u, (uint32_t)__builtin_amdgcn_readfirstlane(off[c + 1]));
-    const uint32_t i = h + (uint32_t)lane;
-    const bool inrange = i < end;
-    const uint32_t ii_ = inrange ? i : h;
-    const int key = inrange ? gkey[ii_] : -1;
-    const float di = dens_s[ii_];
-    const bool active = key >= 0 && (double)di >= g.floor_nuc;
-    if (inrange) cflag[i] = 0;
-    if (!__ballot(active)) return;
-    const float4 li = sloc[ii_];
-    const float4 pi = spos[ii_];
-    const uint32_t oi = orig_of(pi);
-    const int nc = g.nc;
-    const int cx = (int)(c % (uint32_t)nc), cy = (int)((c / (uint32_t)nc) % (uint32_t)nc),
-              cz = (int)(c / ((uint32_t)nc * (uint32_t)nc));
-    bool found = !active;
-    for (int t = 0; t < 27; t++) {
-        int ox, oy, oz;
-        stencil_offset(t, ox, oy, oz);
-        const uint32_t nb = ((uint32_t)wrapc(cz + oz, nc) * (uint32_t)nc + (uint32_t)wrapc(cy + oy, nc)) *
-                                (uint32_t)nc + (uint32_t)wrapc(cx + ox, nc);
-        const float xs = li.x - (float)ox * g.cellb, ys = li.y - (float)oy * g.cellb,
-                    zs = li.z - (float)oz * g.cellb;
-        const uint32_t a = __builtin_amdgcn_readfirstlane(off[nb]);
-        const uint32_t b = __builtin_amdgcn_readfirstlane(off[nb + 1]);
-        for (uint32_t j = a; j < b; j++) {
-            const float dj = dens_s[j];
-            const int kj = gkey[j];
-            const float4 lj = sloc[j];
-            const float4 pj = spos[j];
-            if (!found && denser_within_b(dj, orig_of(pj), kj, lj, pj, key, di, oi, xs, ys, zs, pi, g))
-                found = true;
-            if (((j - a) & 15u) == 15u && !__ballot(!found)) break;
-        }
-        if (!__ballot(!found)) break;
-    }
-    if (active && !found) {
-        cflag[i] = 1;
-        atomicAdd(&gccnt[gid_of[i]], 1u);
-    }
+// Densest particle of every sub-cell of a dense cell, as a packed key
+// (density bits, inverted original index): larger key = denser in the total
+// order (densities are >= 0, so their bit patterns order like the values).
+__device__ __forceinline__ uint64_t dkey(float d, uint32_t orig) {
+    return ((uint64_t)__float_as_uint(d) << 32) | (uint64_t)(0xffffffffu - orig);
 }
 
-__global__ __launch_bounds__(kBlock) void k_cand_sparse(int64_t nsparse, Geo g,
-                                                        const int32_t *__restrict__ sparse,
-                                                        const float4 *__restrict__ sloc,
-                                                        const float4 *__restrict__ spos,
-                                                        const uint32_t *__restrict__ off,
-                                                        const float *__restrict__ dens_s,
-                                                        const int32_t *__restrict__ gkey,
-                                                        const int32_t *__restrict__ gid_of,
-                                                        uint32_t *__restrict__ gccnt,
-                                                        int32_t *__restrict__ cflag) {
-    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t0 >= nsparse) return;
-    const int i = sparse[t0];
+__global__ __launch_bounds__(kBlock) void k_submax(int64_t nslots, int nsub,
+                                                   const uint32_t *__restrict__ subtab,
+                                                   const float *__restrict__ dens_s,
+                                                   const float4 *__restrict__ spos,
+                                                   uint64_t *__restrict__ submax,
+                                                   int32_t *__restrict__ subarg) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nslots) return;
+    const int64_t d = t / nsub;
+    const int s = (int)(t - d * nsub);
+    const uint32_t *tab = subtab + d * (nsub + 1);
+    uint64_t best = 0;
+    int32_t arg = -1;
+    for (uint32_t j = tab[s]; j < tab[s + 1]; j++) {
+        const uint64_t kk = dkey(dens_s[j], orig_of(spos[j]));
+        if (arg < 0 || kk > best) {
+            best = kk;
+            arg = (int32_t)j;
+        }
+    }
+    submax[d * (nsub + 1) + s] = best;
+    subarg[d * (nsub + 1) + s] = arg;
+}
+
+// Stage 1, one thread per particle: a member at or above the floor that is not
+// the densest particle of its sub-cell is decided at once when that densest
+// particle belongs to its group and lies within b (the usual case inside an L0
+// group, the sub-cell diagonal being below l).  Every other member at or above
+// the floor is flagged as a hard case.
+__global__ __launch_bounds__(kBlock) void k_cand_quick(int64_t n, Geo g, const float4 *__restrict__ sloc,
+                                                       const float4 *__restrict__ spos,
+                                                       const uint32_t *__restrict__ off,
+                                                       const uint16_t *__restrict__ ssub,
+                                                       const uint32_t *__restrict__ cellmap,
+                                                       const int32_t *__restrict__ subarg,
+                                                       const float *__restrict__ dens_s,
+                                                       const int32_t *__restrict__ gkey,
+                                                       int32_t *__restrict__ cflag,
+                                                       uint32_t *__restrict__ f_hard) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    bool is_hard = false;
     cflag[i] = 0;
     const int key = gkey[i];
-    if (key < 0) return;
     const float di = dens_s[i];
-    if (!((double)di >= g.floor_nuc)) return;
+    if (key >= 0 && (double)di >= g.floor_nuc) {
+        is_hard = true;
+        const float4 li = sloc[i];
+        const uint32_t c = __float_as_uint(li.w);
+        if (off[c + 1] - off[c] >= (uint32_t)kDenseMin) {
+            const int nsub = g.ksub * g.ksub * g.ksub;
+            const int32_t top = subarg[(int64_t)cellmap[c] * (nsub + 1) + ssub[i]];
+            if (top != (int32_t)i && gkey[top] == key) {
+                // top is denser than i: it is the maximum of i's sub-cell
+                const float4 lt = sloc[top];
+                const float dx = lt.x - li.x, dy = lt.y - li.y, dz = lt.z - li.z;
+                const float d2f = dx * dx + dy * dy + dz * dz;
+                if (d2f < g.b2b_lo || (d2f < g.b2b_hi && d2_exact(spos[i], spos[top], g.L, g.half) < g.b2))
+                    is_hard = false;
+            }
+        }
+    }
+    f_hard[i] = is_hard ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_hard_list(int64_t n, const uint32_t *__restrict__ f_hard,
+                                                      const uint32_t *__restrict__ s_hard,
+                                                      int32_t *__restrict__ hard) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && f_hard[i]) hard[s_hard[i]] = (int32_t)i;
+}
+
+// Stage 2, one thread per hard case: search the 27 neighbour cells (own cell
+// first).  In dense cells only sub-cells within b that hold a denser particle
+// are visited, their densest particle first.
+__global__ __launch_bounds__(kBlock) void k_cand_hard(const uint32_t *__restrict__ nhard_p, Geo g,
+                                                      const int32_t *__restrict__ hard,
+                                                      const float4 *__restrict__ sloc,
+                                                      const float4 *__restrict__ spos,
+                                                      const uint32_t *__restrict__ off,
+                                                      const uint32_t *__restrict__ cellmap,
+                                                      const uint32_t *__restrict__ subtab,
+                                                      const uint64_t *__restrict__ submax,
+                                                      const int32_t *__restrict__ subarg,
+                                                      const float *__restrict__ dens_s,
+                                                      const int32_t *__restrict__ gkey,
+                                                      const int32_t *__restrict__ gid_of,
+                                                      uint32_t *__restrict__ gccnt,
+                                                      int32_t *__restrict__ cflag) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)*nhard_p) return;
+    const int i = hard[t];
+    const int key = gkey[i];
+    const float di = dens_s[i];
     const float4 li = sloc[i];
     const float4 pi = spos[i];
     const uint32_t oi = orig_of(pi);
+    const uint64_t mykey = dkey(di, oi);
     const uint32_t c = __float_as_uint(li.w);
-    const int nc = g.nc;
+    const int nc = g.nc, k = g.ksub, nsub = k * k * k;
+    const float subb = g.cellb / (float)k;
     const int cx = (int)(c % (uint32_t)nc), cy = (int)((c / (uint32_t)nc) % (uint32_t)nc),
               cz = (int)(c / ((uint32_t)nc * (uint32_t)nc));
-    for (int t = 0; t < 27; t++) {
+    for (int tt = 0; tt < 27; tt++) {
         int ox, oy, oz;
-        stencil_offset(t, ox, oy, oz);
+        stencil_offset(tt, ox, oy, oz);
         const uint32_t nb = ((uint32_t)wrapc(cz + oz, nc) * (uint32_t)nc + (uint32_t)wrapc(cy + oy, nc)) *
                                 (uint32_t)nc + (uint32_t)wrapc(cx + ox, nc);
         const float xs = li.x - (float)ox * g.cellb, ys = li.y - (float)oy * g.cellb,
                     zs = li.z - (float)oz * g.cellb;
-        for (uint32_t j = off[nb]; j < off[nb + 1]; j++) {
-            const float dj = dens_s[j];
-            if (dj < di) continue;
-            const float4 pj = spos[j];
-            if (denser_within_b(dj, orig_of(pj), gkey[j], sloc[j], pj, key, di, oi, xs, ys, zs, pi, g))
-                return;
+        const uint32_t a = off[nb], b = off[nb + 1];
+        if (b - a < (uint32_t)kDenseMin) {
+            for (uint32_t j = a; j < b; j++) {
+                if ((int)j == i) continue;
+                if (denser_within_b(j, dens_s, gkey, sloc, spos, key, di, oi, xs, ys, zs, pi, g)) return;
+            }
+            continue;
+        }
+        const int64_t base = (int64_t)cellmap[nb] * (nsub + 1);
+        for (int s2 = 0; s2 < nsub; s2++) {
+            if (!(submax[base + s2] > mykey)) continue;
+            const int sx = s2 % k, sy = (s2 / k) % k, sz = s2 / (k * k);
+            const float gx = fmaxf(fmaxf(sx * subb - 1e-5f - xs, xs - (sx + 1) * subb - 1e-5f), 0.0f);
+            const float gy = fmaxf(fmaxf(sy * subb - 1e-5f - ys, ys - (sy + 1) * subb - 1e-5f), 0.0f);
+            const float gz = fmaxf(fmaxf(sz * subb - 1e-5f - zs, zs - (sz + 1) * subb - 1e-5f), 0.0f);
+            if (gx * gx + gy * gy + gz * gz >= g.b2b_hi) continue;
+            const int32_t top = subarg[base + s2];
+            if (denser_within_b(top, dens_s, gkey, sloc, spos, key, di, oi, xs, ys, zs, pi, g)) return;
+            const uint32_t u1 = subtab[base + s2 + 1];
+            for (uint32_t j = subtab[base + s2]; j < u1; j++) {
+                if ((int32_t)j == top || (int)j == i) continue;
+                if (denser_within_b(j, dens_s, gkey, sloc, spos, key, di, oi, xs, ys, zs, pi, g)) return;
+            }
         }
     }
     cflag[i] = 1;
@@ -139,14 +191,26 @@ __global__ __launch_bounds__(kBlock) void k_cand_sparse(int64_t nsparse, Geo g,
 }  // namespace
 
 void launch_candidates(int64_t n, const Geo &g, Work &w, hipStream_t s) {
-    if (w.nchunks > 0)
-        hipLaunchKernelGGL(k_cand_dense, dim3((unsigned)((w.nchunks + 3) / 4)), dim3(kBlock), 0, s,
-                           w.nchunks, g, w.chunks, w.sloc, w.spos, w.off, w.dens_s, w.gkey, w.gid_of,
-                           w.gccnt, w.owner /* candidate flags */);
-    if (w.nsparse > 0)
-        hipLaunchKernelGGL(k_cand_sparse, dim3((unsigned)((w.nsparse + kBlock - 1) / kBlock)), dim3(kBlock),
-                           0, s, w.nsparse, g, w.sparse, w.sloc, w.spos, w.off, w.dens_s, w.gkey, w.gid_of,
-                           w.gccnt, w.owner);
+    const int nsub = g.ksub * g.ksub * g.ksub;
+    const int64_t nslots = w.ndcells * nsub;
+    if (nslots > 0)
+        hipLaunchKernelGGL(k_submax, dim3((unsigned)((nslots + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                           nslots, nsub, w.subtab, w.dens_s, w.spos, w.submax, w.subarg);
+    const unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
+    // candidate flags live in the owner array until the assignment overwrites
+    // it; the hard-case flags, their scan and list reuse arrays of earlier stages
+    hipLaunchKernelGGL(k_cand_quick, dim3(blocks), dim3(kBlock), 0, s, n, g, w.sloc, w.spos, w.off, w.ssub,
+                       w.cnt, w.subarg, w.dens_s, w.gkey, w.owner, w.f_dcell);
+    scan_u32(w.f_dcell, w.s_dcell, n, w.scan_tmp, s);
+    hipLaunchKernelGGL(k_hard_list, dim3(blocks), dim3(kBlock), 0, s, n, w.f_dcell, w.s_dcell, w.runlist);
+    uint32_t nh = 0;
+    (void)hipMemcpyAsync(&nh, w.s_dcell + n, sizeof(nh), hipMemcpyDeviceToHost, s);
+    (void)hipStreamSynchronize(s);
+    w.nhard = nh;
+    if (nh > 0)
+        hipLaunchKernelGGL(k_cand_hard, dim3((unsigned)((nh + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                           w.s_dcell + n, g, w.runlist, w.sloc, w.spos, w.off, w.cnt, w.subtab, w.submax,
+                           w.subarg, w.dens_s, w.gkey, w.gid_of, w.gccnt, w.owner);
 }
 
 }  // namespace hf

@@ -114,18 +114,32 @@ __global__ __launch_bounds__(kBlock) void k_density_sparse(int64_t nsparse, Geo 
     const int nc = g.nc;
     const int cx = (int)(c % (uint32_t)nc), cy = (int)((c / (uint32_t)nc) % (uint32_t)nc),
               cz = (int)(c / ((uint32_t)nc * (uint32_t)nc));
+    const uint32_t x0 = (uint32_t)wrapc(cx - 1, nc), x1 = (uint32_t)cx, x2 = (uint32_t)wrapc(cx + 1, nc);
     double acc = 0.0;
     for (int oz = -1; oz <= 1; oz++) {
         const int z = wrapc(cz + oz, nc);
         const float zs = li.z - (float)oz * g.cellb;
+        // the 18 offsets of this plane are loaded together so their latencies overlap
+        uint32_t ra[9], rb[9];
+#pragma unroll
         for (int oy = -1; oy <= 1; oy++) {
-            const int y = wrapc(cy + oy, nc);
+            const uint32_t row = ((uint32_t)z * (uint32_t)nc + (uint32_t)wrapc(cy + oy, nc)) * (uint32_t)nc;
+            const int r = (oy + 1) * 3;
+            ra[r + 0] = off[row + x0];
+            rb[r + 0] = off[row + x0 + 1];
+            ra[r + 1] = off[row + x1];
+            rb[r + 1] = off[row + x1 + 1];
+            ra[r + 2] = off[row + x2];
+            rb[r + 2] = off[row + x2 + 1];
+        }
+#pragma unroll
+        for (int oy = -1; oy <= 1; oy++) {
             const float ys = li.y - (float)oy * g.cellb;
-            const uint32_t row = ((uint32_t)z * (uint32_t)nc + (uint32_t)y) * (uint32_t)nc;
+#pragma unroll
             for (int ox = -1; ox <= 1; ox++) {
-                const uint32_t nb = row + (uint32_t)wrapc(cx + ox, nc);
+                const int r = (oy + 1) * 3 + (ox + 1);
                 const float xs = li.x - (float)ox * g.cellb;
-                accum_range(sloc, off[nb], off[nb + 1], xs, ys, zs, acc);
+                accum_range(sloc, ra[r], rb[r], xs, ys, zs, acc);
             }
         }
     }

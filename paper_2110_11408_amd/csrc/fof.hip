@@ -46,6 +46,17 @@ __device__ int uf_find(int32_t *parent, int x) {
     }
 }
 
+// Root by plain (cacheable) loads, for filters only: a stale parent is an
+// earlier ancestor, so two particles reported in one set are in one set; a
+// "different" answer may be stale and is then settled by uf_unite.
+__device__ __forceinline__ int uf_find_hint(const int32_t *parent, int x) {
+    for (;;) {
+        const int p = parent[x];
+        if (p == x) return x;
+        x = p;
+    }
+}
+
 __device__ void uf_unite(int32_t *parent, int a, int b) {
     for (;;) {
         a = uf_find(parent, a);
@@ -57,13 +68,17 @@ __device__ void uf_unite(int32_t *parent, int a, int b) {
     }
 }
 
-__device__ __forceinline__ bool linked(float4 la, float xs, float ys, float zs, float4 lb,
-                                       const float4 &pa, const float4 &pb, const Geo &g) {
+// Friends test of a (shifted local coordinates xs, ys, zs) and b: FP32 prefilter,
+// canonical FP64 distance only in the undecided band.
+__device__ __forceinline__ bool linked(float xs, float ys, float zs, const float4 &pa,
+                                       const float4 *__restrict__ sloc, const float4 *__restrict__ spos,
+                                       uint32_t b, const Geo &g) {
+    const float4 lb = sloc[b];
     const float dx = lb.x - xs, dy = lb.y - ys, dz = lb.z - zs;
     const float d2f = dx * dx + dy * dy + dz * dz;
     if (d2f >= g.l2b_hi) return false;
     if (d2f < g.l2b_lo) return true;
-    return d2_exact(pa, pb, g.L, g.half) < g.l2;
+    return d2_exact(pa, spos[b], g.L, g.half) < g.l2;
 }
 
 __global__ __launch_bounds__(kBlock) void k_fof_init(int64_t n, Geo g, const float *__restrict__ dens_s,
@@ -155,7 +170,7 @@ __global__ __launch_bounds__(kBlock) void k_fof_runs(int64_t nruns, int pass, Ge
                 const uint32_t B1 = tabB[s2 + 1];
                 while (fb < B1 && !is_member(dens_s, fb, g.dl0)) fb++;
                 if (fb >= B1) continue;
-                if (uf_find(parent, f) == uf_find(parent, (int)fb)) continue;
+                if (uf_find_hint(parent, f) == uf_find_hint(parent, (int)fb)) continue;
                 const float ox = (float)ocx * g.cellb, oy = (float)ocy * g.cellb, oz = (float)ocz * g.cellb;
                 bool hit = false;
                 for (uint32_t a = (uint32_t)f; a < A1 && !hit; a++) {
@@ -165,7 +180,7 @@ __global__ __launch_bounds__(kBlock) void k_fof_runs(int64_t nruns, int pass, Ge
                     const float xs = la.x - ox, ys = la.y - oy, zs = la.z - oz;
                     for (uint32_t bb = fb; bb < B1; bb++) {
                         if (!is_member(dens_s, bb, g.dl0)) continue;
-                        if (linked(la, xs, ys, zs, sloc[bb], pa, spos[bb], g)) {
+                        if (linked(xs, ys, zs, pa, sloc, spos, bb, g)) {
                             hit = true;
                             break;
                         }
@@ -200,6 +215,7 @@ __global__ __launch_bounds__(kBlock) void k_fof_sparse(int64_t nsparse, Geo g,
     const float subb = g.cellb / (float)k;
     const int cx = (int)(c % (uint32_t)nc), cy = (int)((c / (uint32_t)nc) % (uint32_t)nc),
               cz = (int)(c / ((uint32_t)nc * (uint32_t)nc));
+    int ri = uf_find_hint(parent, i);
     for (int oz = -1; oz <= 1; oz++) {
         const int z = wrapc(cz + oz, nc);
         const float zs = li.z - (float)oz * g.cellb;
@@ -208,13 +224,18 @@ __global__ __launch_bounds__(kBlock) void k_fof_sparse(int64_t nsparse, Geo g,
             const float ys = li.y - (float)oy * g.cellb;
             const uint32_t row = ((uint32_t)z * (uint32_t)nc + (uint32_t)y) * (uint32_t)nc;
             for (int ox = -1; ox <= 1; ox++) {
+                // the neighbour cell must come closer than l to the particle
+                const float gx = ox < 0 ? li.x : (ox > 0 ? g.cellb - li.x : 0.0f);
+                const float gy = oy < 0 ? li.y : (oy > 0 ? g.cellb - li.y : 0.0f);
+                const float gz = oz < 0 ? li.z : (oz > 0 ? g.cellb - li.z : 0.0f);
+                if (gx * gx + gy * gy + gz * gz >= g.l2b_hi) continue;
                 const uint32_t nb = row + (uint32_t)wrapc(cx + ox, nc);
                 const float xs = li.x - (float)ox * g.cellb;
                 const uint32_t a = off[nb], b = off[nb + 1];
                 if (b - a < (uint32_t)kDenseMin) {
                     for (uint32_t j = a > (uint32_t)i ? a : (uint32_t)i + 1; j < b; j++) {
                         if (!is_member(dens_s, j, g.dl0)) continue;
-                        if (linked(li, xs, ys, zs, sloc[j], pi, spos[j], g)) uf_unite(parent, i, (int)j);
+                        if (linked(xs, ys, zs, pi, sloc, spos, j, g)) uf_unite(parent, i, (int)j);
                     }
                     continue;
                 }
@@ -235,8 +256,10 @@ __global__ __launch_bounds__(kBlock) void k_fof_sparse(int64_t nsparse, Geo g,
                             const uint32_t u1 = tab[s2 + 1];
                             for (uint32_t j = tab[s2]; j < u1; j++) {
                                 if (!is_member(dens_s, j, g.dl0)) continue;
-                                if (linked(li, xs, ys, zs, sloc[j], pi, spos[j], g)) {
+                                if (ri == parent[j]) break;  // already one set
+                                if (linked(xs, ys, zs, pi, sloc, spos, j, g)) {
                                     uf_unite(parent, i, (int)j);
+                                    ri = uf_find_hint(parent, i);
                                     break;
                                 }
                             }
@@ -321,6 +344,7 @@ void launch_fof(int64_t n, const Geo &g, Work &w, hipStream_t s) {
         hipLaunchKernelGGL(k_fof_flatten, grid(n), dim3(kBlock), 0, s, n, w.parent);
         hipLaunchKernelGGL(k_fof_runs, grid(w.nruns), dim3(kBlock), 0, s, w.nruns, 1, g, w.runlist, w.sloc,
                            w.spos, w.off, w.ssub, w.cnt, w.subtab, w.dens_s, w.parent);
+        hipLaunchKernelGGL(k_fof_flatten, grid(n), dim3(kBlock), 0, s, n, w.parent);
     }
     if (w.nsparse > 0)
         hipLaunchKernelGGL(k_fof_sparse, grid(w.nsparse), dim3(kBlock), 0, s, w.nsparse, g, w.sparse,

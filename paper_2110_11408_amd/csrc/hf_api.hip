@@ -159,6 +159,8 @@ size_t carve(char *base, int64_t n, int64_t ncell, int nsub, Work *w) {
     w->dcells = c.take<uint32_t>(n1);
     w->runlist = c.take<int32_t>(n1);
     w->subtab = c.take<uint32_t>((n / hf::kDenseMin + 1) * (nsub + 1));
+    w->submax = c.take<uint64_t>((n / hf::kDenseMin + 1) * (nsub + 1));
+    w->subarg = c.take<int32_t>((n / hf::kDenseMin + 1) * (nsub + 1));
     w->dens_s = c.take<float>(n);
     w->parent = c.take<int32_t>(n);
     w->minorig = c.take<int32_t>(n);
@@ -289,6 +291,11 @@ hf_status run_compaso(hf_ctx *c, int64_t n, const Geo &g, Work &w, int32_t *halo
     c->stats.ms_assign = elapsed(c->ev[6], c->ev[7]);
     c->stats.ms_output = elapsed(c->ev[7], c->ev[8]);
     c->stats.n_candidates = NC;
+    c->stats.n_dense_cells = w.ndcells;
+    c->stats.n_dense_chunks = w.nchunks;
+    c->stats.n_sparse = w.nsparse;
+    c->stats.n_subcell_runs = w.nruns;
+    c->stats.n_hard = w.nhard;
     c->stats.n_found = counters[2];
     c->stats.n_halos = NH;
     if (!fits) return fail(c, HF_ERR_CAPACITY, "halos_cap is smaller than the number of halos");
@@ -327,6 +334,7 @@ hf_status begin(hf_ctx *c, const float *pos, int64_t n, const hf_params *p, Geo 
     w->ndcells = counts[1];
     w->nsparse = counts[2];
     w->nruns = 0;
+    w->nhard = 0;
     hf::launch_subtab(n, w->ndcells, *g, *w, s);
     HIP_OK(c, hipEventRecord(c->ev[1], s));
     return HF_OK;

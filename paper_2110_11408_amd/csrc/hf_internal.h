@@ -124,8 +124,10 @@ struct Work {
     uint32_t *f_chunk, *s_chunk, *f_dcell, *s_dcell, *f_sparse, *s_sparse;
     int32_t *chunks, *sparse;
     uint32_t *dcells, *subtab;
+    uint64_t *submax;                                  // densest particle per dense sub-cell
+    int32_t *subarg;
     int32_t *runlist;
-    int64_t nchunks, ndcells, nsparse, nruns;
+    int64_t nchunks, ndcells, nsparse, nruns, nhard;
     // density / FoF / groups (sorted order unless noted)
     float *dens_s;
     int32_t *parent, *minorig, *gkey, *gid_of, *owner;
