@@ -15,6 +15,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -46,6 +47,67 @@ def _stage_models(n, stats, pairs):
         # FoF: read float4 x2 + density for every particle (36 B), parent r/w 8 B
         "fof": ("hbm", 44.0 * n / 1e9, HBM_PEAK_GBS, "GB/s"),
     }
+
+
+STAGE_KERNELS = {
+    "density": ("k_density_dense", "k_density_sparse"),
+    "fof": ("k_fof_init", "k_fof_phase_a", "k_fof_dense", "k_fof_sparse", "k_fof_roots",
+            "k_fof_minorig", "k_fof_keys"),
+}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def source_hash() -> str:
+    """Hash of the HIP sources and headers: measured traffic is valid only for them."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2110_11408_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            h.update(name.encode())
+            h.update(open(os.path.join(csrc, name), "rb").read())
+    h.update(open(os.path.join(ROOT, "include", "hf.h"), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def pmc_summary(fetch_csv: str, write_csv: str, copy_mib: int) -> dict:
+    """Per-call HBM bytes of each stage from two rocprofv3 --pmc runs (FETCH_SIZE,
+    WRITE_SIZE, KiB per dispatch) of `bench.py --steps 1 --warmup 0 --copy-probe MIB`,
+    each scaled so that the probe's plain copy reads and writes copy_mib MiB."""
+    import csv
+
+    def load(path):
+        rows = list(csv.DictReader(open(path)))
+        probe = [float(r["Counter_Value"]) for r in rows
+                 if "copyBuffer" in r["Kernel_Name"] and int(r["Grid_Size"]) > 4096]
+        scale = (copy_mib * 1024.0) / max(probe) if probe else 1.0
+        per = {}
+        for r in rows:
+            m = re.search(r"(k_[A-Za-z0-9_]+)\(", r["Kernel_Name"])
+            name = m.group(1) if m else r["Kernel_Name"]
+            per.setdefault(name, []).append(float(r["Counter_Value"]) * 1024.0 * scale)
+        return per, scale
+
+    fetch, fscale = load(fetch_csv)
+    write, wscale = load(write_csv)
+    out = {"source_hash": source_hash(), "fetch_scale": fscale, "write_scale": wscale,
+           "copy_probe_mib": copy_mib, "stages": {}}
+    for stage, kernels in STAGE_KERNELS.items():
+        rb = sum(sum(fetch.get(k, [])) for k in kernels)
+        wb = sum(sum(write.get(k, [])) for k in kernels)
+        out["stages"][stage] = {"read_bytes": rb, "write_bytes": wb, "bytes": rb + wb,
+                                "kernels": list(kernels)}
+    return out
+
+
+def measured_traffic(stage: str):
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != source_hash() or stage not in t.get("stages", {}):
+        return None
+    return t["stages"][stage]["bytes"]
 
 
 def cpu_baseline(target_s: float):
@@ -80,7 +142,19 @@ def main():
     ap.add_argument("--workload", default="plain256", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="first run one plain device-to-device copy of this many MiB (a traffic "
+                         "reference for hardware counters)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic.json from two rocprofv3 --pmc counter files "
+                         "and exit (no GPU needed)")
     args = ap.parse_args()
+    if args.pmc_summary:
+        t = pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.copy_probe or 1024)
+        with open(TRAFFIC_FILE, "w") as f:
+            json.dump(t, f, indent=1)
+        print(json.dumps(t))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (this build is "
               "single-GPU: the sharded design is described in DESIGN.md)", file=sys.stderr)
@@ -91,9 +165,16 @@ def main():
     from paper_2110_11408_amd import _lib, synth
     from paper_2110_11408_amd.api import Context
 
+    dev = torch.device("cuda:0")
+    if args.copy_probe > 0:
+        src = torch.ones(args.copy_probe << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     pos, L, _ = synth.named_box(args.workload)
     n = len(pos)
-    dev = torch.device("cuda:0")
     pos_d = torch.from_numpy(pos).to(dev)
     p = _lib.default_params(box=L)
     ctx = Context(0)
@@ -116,11 +197,13 @@ def main():
     ms_step = wall * 1e3 / args.steps
     stages = {k[3:]: acc[k] / args.steps for k in keys}
     models = _stage_models(n, st, pairs)
-    dom = max((k for k in models), key=lambda k: stages[k])
-    bound, work, peak, unit = models[dom]
-    achieved = work / (stages[dom] / 1e3)
-    roof = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": None}
+    lines = {}
+    for k, (bound, work, peak, unit) in models.items():
+        achieved = work / (stages[k] / 1e3)
+        lines[k] = {"bound": bound, "kernel": k, "ms": stages[k], "achieved": achieved, "peak": peak,
+                    "unit": unit, "frac": achieved / peak, "traffic": measured_traffic(k)}
+    dom = max(lines, key=lambda k: stages[k])
+    roof = lines[dom]
     res = {
         "metric": METRIC, "value": n / (ms_step / 1e3), "unit": "particles/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
@@ -129,13 +212,13 @@ def main():
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
                    "n_particles": n, "box": L, "path": "plain (hf_find, one box per call)"},
         "roofline": roof,
+        "stage_rooflines": lines,
         "stages_ms": stages,
         "counts": {"pairs_within_b": pairs, "n_cells": st["n_cells"], "n_members": st["n_members"],
                    "n_groups": st["n_groups"], "n_candidates": st["n_candidates"],
                    "n_found": st["n_found"], "n_halos": out["n_halos"],
                    "n_dense_cells": st["n_dense_cells"], "n_dense_chunks": st["n_dense_chunks"],
-                   "n_sparse": st["n_sparse"], "n_subcell_runs": st["n_subcell_runs"],
-                   "n_hard": st["n_hard"]},
+                   "n_sparse": st["n_sparse"], "n_hard": st["n_hard"]},
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(args.cpu_seconds)

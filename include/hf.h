@@ -95,7 +95,6 @@ typedef struct {
     int64_t n_dense_cells;    /* cells holding >= 8 particles                   */
     int64_t n_dense_chunks;   /* 64-particle wavefront chunks of dense cells    */
     int64_t n_sparse;         /* particles of the other cells                   */
-    int64_t n_subcell_runs;   /* dense sub-cells holding an L0 member           */
     int64_t n_hard;           /* candidate tests not settled by the own sub-cell */
 } hf_stats;
 

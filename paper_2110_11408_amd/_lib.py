@@ -43,7 +43,7 @@ class HfStats(ctypes.Structure):
                  "ms_assign", "ms_output", "ms_total")] + \
                [(k, ctypes.c_int64) for k in
                 ("n_cells", "n_members", "n_groups", "n_candidates", "n_found", "n_halos",
-                 "n_dense_cells", "n_dense_chunks", "n_sparse", "n_subcell_runs", "n_hard")]
+                 "n_dense_cells", "n_dense_chunks", "n_sparse", "n_hard")]
 
 
 HALO_FIELDS = [f[0] for f in HfHalo._fields_]

@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_stable(const float *__restrict__
                                                        float4 *__restrict__ spos,
                                                        float4 *__restrict__ sloc,
                                                        uint16_t *__restrict__ ssub) {
-    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t s = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const uint64_t me = tmp[s];
     const uint32_t o = (uint32_t)me;

@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kBlock) void k_cand_quick(int64_t n, Geo g, const f
                                                        const int32_t *__restrict__ gkey,
                                                        int32_t *__restrict__ cflag,
                                                        uint32_t *__restrict__ f_hard) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
     if (i >= n) return;
     bool is_hard = false;
     cflag[i] = 0;
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(kBlock) void k_cand_hard(const uint32_t *__restrict
                                                       const int32_t *__restrict__ gid_of,
                                                       uint32_t *__restrict__ gccnt,
                                                       int32_t *__restrict__ cflag) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
     if (t >= (int64_t)*nhard_p) return;
     const int i = hard[t];
     const int key = gkey[i];
@@ -198,18 +198,18 @@ void launch_candidates(int64_t n, const Geo &g, Work &w, hipStream_t s) {
                            nslots, nsub, w.subtab, w.dens_s, w.spos, w.submax, w.subarg);
     const unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
     // candidate flags live in the owner array until the assignment overwrites
-    // it; the hard-case flags, their scan and list reuse arrays of earlier stages
+    // it; the hard-case flags and their scan reuse the dense-cell flag arrays
     hipLaunchKernelGGL(k_cand_quick, dim3(blocks), dim3(kBlock), 0, s, n, g, w.sloc, w.spos, w.off, w.ssub,
                        w.cnt, w.subarg, w.dens_s, w.gkey, w.owner, w.f_dcell);
     scan_u32(w.f_dcell, w.s_dcell, n, w.scan_tmp, s);
-    hipLaunchKernelGGL(k_hard_list, dim3(blocks), dim3(kBlock), 0, s, n, w.f_dcell, w.s_dcell, w.runlist);
+    hipLaunchKernelGGL(k_hard_list, dim3(blocks), dim3(kBlock), 0, s, n, w.f_dcell, w.s_dcell, w.hardlist);
     uint32_t nh = 0;
     (void)hipMemcpyAsync(&nh, w.s_dcell + n, sizeof(nh), hipMemcpyDeviceToHost, s);
     (void)hipStreamSynchronize(s);
     w.nhard = nh;
     if (nh > 0)
         hipLaunchKernelGGL(k_cand_hard, dim3((unsigned)((nh + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                           w.s_dcell + n, g, w.runlist, w.sloc, w.spos, w.off, w.cnt, w.subtab, w.submax,
+                           w.s_dcell + n, g, w.hardlist, w.sloc, w.spos, w.off, w.cnt, w.subtab, w.submax,
                            w.subarg, w.dens_s, w.gkey, w.gid_of, w.gccnt, w.owner);
 }
 

@@ -66,7 +66,7 @@ __global__ __launch_bounds__(kBlock) void k_density_dense(int64_t nchunks, Geo g
                                                           float *__restrict__ dens_s,
                                                           float *__restrict__ dens_out) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t q = (int64_t)blockIdx.x * (kBlock / 64) + wave;
+    const int64_t q = (int64_t)xcd_block() * (kBlock / 64) + wave;
     if (q >= nchunks) return;
     const int lane = threadIdx.x & 63;
     const uint32_t h = (uint32_t)__builtin_amdgcn_readfirstlane(chunks[q]);
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(kBlock) void k_density_sparse(int64_t nsparse, Geo 
                                                            const uint32_t *__restrict__ off,
                                                            float *__restrict__ dens_s,
                                                            float *__restrict__ dens_out) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
     if (t >= nsparse) return;
     const int64_t i = sparse[t];
     const float4 li = sloc[i];

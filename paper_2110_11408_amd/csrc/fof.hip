@@ -2,19 +2,16 @@
 // two members are friends when their separation is less than l; L0 groups are
 // the connected components.
 //
-// Lock-free union-find in sorted (cell, sub-cell) order.  A sub-cell's diagonal
-// is below l, so all members of a sub-cell are friends; the link work is done
-// between sub-cells instead of between particles:
-//   phase A  in dense cells every member points at the first member of its
-//            sub-cell (a valid forest: parents never exceed their child);
-//   phase B  one thread per sub-cell of a dense cell visits the sub-cells of
-//            dense cells within reach (half stencil); if the two are not yet in
-//            one set it searches for one friend pair (FP32 prefilter on the
-//            cell-local coordinates, canonical FP64 distance for the undecided
-//            band) and unites them.  A first pass over face neighbours plus a
-//            compression makes most later checks a single root comparison;
-//   sparse   members of sparse cells link particle by particle to every member
-//            of a dense neighbour cell and to the later members of sparse ones;
+// Lock-free union-find in sorted (cell, sub-cell) order:
+//   phase A  a sub-cell's diagonal is below l, so all members of a sub-cell are
+//            friends: in dense cells every member points at the first member of
+//            its sub-cell;
+//   dense    one wavefront per dense chunk streams the neighbour members within
+//            reach (FP32 prefilter on the cell-local coordinates, canonical FP64
+//            distance for the undecided band) and joins each linked member's set
+//            to the sets of the lanes it links, with a per-lane root cache;
+//   sparse   members of sparse cells link to the later members of sparse
+//            neighbour cells;
 //   labels   compression, then 1 + the smallest ORIGINAL index of each set.
 // Hooks always attach the larger root under the smaller one, so the sets, and
 // therefore the labels, do not depend on thread scheduling.
@@ -88,18 +85,17 @@ __global__ __launch_bounds__(kBlock) void k_fof_init(int64_t n, Geo g, const flo
     parent[i] = is_member(dens_s, i, g.dl0) ? (int32_t)i : -1;
 }
 
-// Phase A: members of dense cells point at the first member of their sub-cell.
+// Phase A: members of dense cells point at the first member of their sub-cell
+// (a valid forest: every parent is a member with a smaller sorted index).
 __global__ __launch_bounds__(kBlock) void k_fof_phase_a(int64_t n, Geo g, const float4 *__restrict__ sloc,
                                                         const uint32_t *__restrict__ off,
                                                         const uint16_t *__restrict__ ssub,
                                                         const uint32_t *__restrict__ cellmap,
                                                         const uint32_t *__restrict__ subtab,
                                                         const float *__restrict__ dens_s,
-                                                        int32_t *__restrict__ parent,
-                                                        uint32_t *__restrict__ f_run) {
+                                                        int32_t *__restrict__ parent) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    f_run[i] = 0;
     if (!is_member(dens_s, i, g.dl0)) return;
     const uint32_t c = __float_as_uint(sloc[i].w);
     if (off[c + 1] - off[c] < (uint32_t)kDenseMin) return;
@@ -107,187 +103,237 @@ __global__ __launch_bounds__(kBlock) void k_fof_phase_a(int64_t n, Geo g, const 
     uint32_t f = subtab[(int64_t)cellmap[c] * (nsub + 1) + ssub[i]];
     while (f < (uint32_t)i && !is_member(dens_s, f, g.dl0)) f++;
     parent[i] = (int32_t)f;
-    f_run[i] = f == (uint32_t)i;
 }
 
-__global__ __launch_bounds__(kBlock) void k_list(int64_t n, const uint32_t *__restrict__ flag,
-                                                 const uint32_t *__restrict__ pos,
-                                                 int32_t *__restrict__ list) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || !flag[i]) return;
-    list[pos[i]] = (int32_t)i;
+// Join the lanes linked to a member of the set rj (rj: any node of that set)
+// to that set; every lane keeps the root of its own set in wr.  Returns the
+// root of the joined set.
+__device__ __forceinline__ int join_lanes(int32_t *parent, bool lk, int &wr, int rj) {
+    const int lane = threadIdx.x & 63;
+    bool need = lk && wr != rj;
+    uint64_t m;
+    while ((m = __ballot(need)) != 0ull) {
+        const int L = __ffsll((unsigned long long)m) - 1;
+        const int w = __shfl(wr, L, 64);
+        int r = 0;
+        if (lane == L) {
+            // fast path: both are usually current roots, so hooking the larger
+            // under the smaller is one compare-and-swap; otherwise a full union
+            const int lo = min(w, rj), hi = max(w, rj);
+            if (atomicCAS(parent + hi, hi, lo) == hi) {
+                r = lo;
+            } else {
+                uf_unite(parent, w, rj);
+                r = uf_find(parent, w);
+            }
+        }
+        r = __shfl(r, L, 64);
+        if (wr == w || wr == rj) wr = r;
+        rj = r;
+        need = lk && wr != rj;
+    }
+    return rj;
 }
 
-// Phase B: sub-cell to sub-cell links between dense cells.  pass 0 visits the
-// three positive face neighbours, pass 1 the whole positive half of the reach.
-__global__ __launch_bounds__(kBlock) void k_fof_runs(int64_t nruns, int pass, Geo g,
-                                                     const int32_t *__restrict__ runlist,
-                                                     const float4 *__restrict__ sloc,
-                                                     const float4 *__restrict__ spos,
-                                                     const uint32_t *__restrict__ off,
-                                                     const uint16_t *__restrict__ ssub,
-                                                     const uint32_t *__restrict__ cellmap,
-                                                     const uint32_t *__restrict__ subtab,
-                                                     const float *__restrict__ dens_s,
-                                                     int32_t *parent) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nruns) return;
-    const int f = runlist[t];
-    const int k = g.ksub, nsub = k * k * k, R = g.rsub, nc = g.nc;
-    const uint32_t c = __float_as_uint(sloc[f].w);
+// Dense chunks, one wavefront each (lanes = the chunk's particles).  The wave
+// visits the neighbour cells that come within l of some lane: sparse cells in
+// all 26 directions, dense cells only in the forward half (the backward ones
+// visit this cell themselves), and its own cell from the chunk start on.
+// Sparse cells are streamed particle by particle.  In a dense cell the lanes
+// first look at all sub-cells at once (one per lane): its range, first member
+// and that member's parent; a sub-cell already in the set every lane belongs
+// to is skipped (all its members are one set), and the others are streamed as
+// wave-uniform scalar loads and joined to the lanes they link.
+__global__ __launch_bounds__(kBlock) void k_fof_dense(int64_t nchunks, Geo g,
+                                                      const int32_t *__restrict__ chunks,
+                                                      const float4 *__restrict__ sloc,
+                                                      const float4 *__restrict__ spos,
+                                                      const uint32_t *__restrict__ off,
+                                                      const uint32_t *__restrict__ cellmap,
+                                                      const uint32_t *__restrict__ subtab,
+                                                      const float *__restrict__ dens_s,
+                                                      int32_t *parent) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t q = (int64_t)xcd_block() * (kBlock / 64) + wave;
+    if (q >= nchunks) return;
+    const int lane = threadIdx.x & 63;
+    const uint32_t h = (uint32_t)__builtin_amdgcn_readfirstlane(chunks[q]);
+    const uint32_t c = __builtin_amdgcn_readfirstlane(__float_as_uint(sloc[h].w));
+    const uint32_t cend = (uint32_t)__builtin_amdgcn_readfirstlane(off[c + 1]);
+    const uint32_t end = min(h + 64u, cend);
+    const uint32_t i = h + (uint32_t)lane;
+    const uint32_t ic = i < end ? i : h;
+    const bool active = i < end && is_member(dens_s, ic, g.dl0);
+    if (!__ballot(active)) return;
+    const float4 li = sloc[ic];
+    const float4 pi = spos[ic];
+    int wr = active ? uf_find_hint(parent, (int)ic) : -1;
+    const int nc = g.nc, k = g.ksub, nsub = k * k * k;
+    const float subb = g.cellb / (float)k;
     const int cx = (int)(c % (uint32_t)nc), cy = (int)((c / (uint32_t)nc) % (uint32_t)nc),
               cz = (int)(c / ((uint32_t)nc * (uint32_t)nc));
-    const int s = ssub[f];
-    const int sx = s % k, sy = (s / k) % k, sz = s / (k * k);
-    const uint32_t *tabA = subtab + (int64_t)cellmap[c] * (nsub + 1);
-    const uint32_t A1 = tabA[s + 1];
-    uint32_t last_c2 = 0xffffffffu;
-    bool last_dense = false;
-    const uint32_t *tabB = nullptr;
-    for (int dz = 0; dz <= R; dz++) {
-        for (int dy = (dz > 0 ? -R : 0); dy <= R; dy++) {
-            for (int dx = (dz > 0 || dy > 0 ? -R : 1); dx <= R; dx++) {
-                const int ax = dx < 0 ? -dx : dx, ay = dy < 0 ? -dy : dy, az = dz < 0 ? -dz : dz;
-                if (pass == 0 && ax + ay + az != 1) continue;
-                const int gx = ax > 0 ? ax - 1 : 0, gy = ay > 0 ? ay - 1 : 0, gz = az > 0 ? az - 1 : 0;
-                if ((double)(gx * gx + gy * gy + gz * gz) * g.sub2 >= g.l2) continue;
-                // neighbour sub-cell: cell offset (image) and sub index
-                const int fx = sx + dx, fy = sy + dy, fz = sz + dz;
-                const int ocx = fx < 0 ? -1 : (fx >= k ? 1 : 0);
-                const int ocy = fy < 0 ? -1 : (fy >= k ? 1 : 0);
-                const int ocz = fz < 0 ? -1 : (fz >= k ? 1 : 0);
-                const uint32_t c2 = ((uint32_t)wrapc(cz + ocz, nc) * (uint32_t)nc +
-                                     (uint32_t)wrapc(cy + ocy, nc)) * (uint32_t)nc +
-                                    (uint32_t)wrapc(cx + ocx, nc);
-                if (c2 != last_c2) {
-                    last_c2 = c2;
-                    last_dense = off[c2 + 1] - off[c2] >= (uint32_t)kDenseMin;
-                    if (last_dense) tabB = subtab + (int64_t)cellmap[c2] * (nsub + 1);
+    // chunk bounding box (active lanes), for sub-cell reach tests
+    float bx0 = active ? li.x : 1e30f, by0 = active ? li.y : 1e30f, bz0 = active ? li.z : 1e30f;
+    float bx1 = active ? li.x : -1e30f, by1 = active ? li.y : -1e30f, bz1 = active ? li.z : -1e30f;
+    for (int d = 32; d >= 1; d >>= 1) {
+        bx0 = fminf(bx0, __shfl_xor(bx0, d, 64));
+        by0 = fminf(by0, __shfl_xor(by0, d, 64));
+        bz0 = fminf(bz0, __shfl_xor(bz0, d, 64));
+        bx1 = fmaxf(bx1, __shfl_xor(bx1, d, 64));
+        by1 = fmaxf(by1, __shfl_xor(by1, d, 64));
+        bz1 = fmaxf(bz1, __shfl_xor(bz1, d, 64));
+    }
+    for (int oz = -1; oz <= 1; oz++) {
+        const float zs = li.z - (float)oz * g.cellb;
+        for (int oy = -1; oy <= 1; oy++) {
+            const float ys = li.y - (float)oy * g.cellb;
+            for (int ox = -1; ox <= 1; ox++) {
+                const float gx = ox < 0 ? li.x : (ox > 0 ? g.cellb - li.x : 0.0f);
+                const float gy = oy < 0 ? li.y : (oy > 0 ? g.cellb - li.y : 0.0f);
+                const float gz = oz < 0 ? li.z : (oz > 0 ? g.cellb - li.z : 0.0f);
+                if (!__ballot(active && gx * gx + gy * gy + gz * gz < g.l2b_hi)) continue;
+                const uint32_t nb = ((uint32_t)wrapc(cz + oz, nc) * (uint32_t)nc + (uint32_t)wrapc(cy + oy, nc)) *
+                                        (uint32_t)nc + (uint32_t)wrapc(cx + ox, nc);
+                const uint32_t a = (uint32_t)__builtin_amdgcn_readfirstlane(off[nb]);
+                const uint32_t b = (uint32_t)__builtin_amdgcn_readfirstlane(off[nb + 1]);
+                const bool own = ox == 0 && oy == 0 && oz == 0;
+                const bool forward = oz > 0 || (oz == 0 && (oy > 0 || (oy == 0 && ox > 0)));
+                const bool dense_nb = b - a >= (uint32_t)kDenseMin;
+                const float xs = li.x - (float)ox * g.cellb;
+                if (!dense_nb) {
+                    for (uint32_t j = a; j < b; j++) {
+                        if (!is_member(dens_s, j, g.dl0)) continue;
+                        const bool lk = active && linked(xs, ys, zs, pi, sloc, spos, j, g);
+                        if (!__ballot(lk)) continue;
+                        join_lanes(parent, lk, wr, uf_find_hint(parent, (int)j));
+                    }
+                    continue;
                 }
-                if (!last_dense) continue;  // the sparse side links it
-                const int s2 = ((fz - ocz * k) * k + (fy - ocy * k)) * k + (fx - ocx * k);
-                uint32_t fb = tabB[s2];
-                const uint32_t B1 = tabB[s2 + 1];
-                while (fb < B1 && !is_member(dens_s, fb, g.dl0)) fb++;
-                if (fb >= B1) continue;
-                if (uf_find_hint(parent, f) == uf_find_hint(parent, (int)fb)) continue;
-                const float ox = (float)ocx * g.cellb, oy = (float)ocy * g.cellb, oz = (float)ocz * g.cellb;
-                bool hit = false;
-                for (uint32_t a = (uint32_t)f; a < A1 && !hit; a++) {
-                    if (!is_member(dens_s, a, g.dl0)) continue;
-                    const float4 la = sloc[a];
-                    const float4 pa = spos[a];
-                    const float xs = la.x - ox, ys = la.y - oy, zs = la.z - oz;
-                    for (uint32_t bb = fb; bb < B1; bb++) {
-                        if (!is_member(dens_s, bb, g.dl0)) continue;
-                        if (linked(xs, ys, zs, pa, sloc, spos, bb, g)) {
-                            hit = true;
-                            break;
+                if (!own && !forward) continue;
+                // one sub-cell per lane (in batches of 64): range, first member,
+                // parent hint, reach
+                const int64_t base = (int64_t)__builtin_amdgcn_readfirstlane(cellmap[nb]) * (nsub + 1);
+                for (int s0 = 0; s0 < nsub; s0 += 64) {
+                    const int sl = s0 + lane;
+                    uint32_t u0 = 0, u1 = 0;
+                    int fs = -1, ps = -1;
+                    if (sl < nsub) {
+                        u0 = subtab[base + sl];
+                        u1 = subtab[base + sl + 1];
+                        if (own && u0 < h) u0 = h;
+                        const int sx = sl % k, sy = (sl / k) % k, sz = sl / (k * k);
+                        // sub-cell box (neighbour frame) shifted into the chunk's frame
+                        const float ex = fmaxf(fmaxf(sx * subb + (float)ox * g.cellb - bx1,
+                                                     bx0 - ((sx + 1) * subb + (float)ox * g.cellb)), 0.0f);
+                        const float ey = fmaxf(fmaxf(sy * subb + (float)oy * g.cellb - by1,
+                                                     by0 - ((sy + 1) * subb + (float)oy * g.cellb)), 0.0f);
+                        const float ez = fmaxf(fmaxf(sz * subb + (float)oz * g.cellb - bz1,
+                                                     bz0 - ((sz + 1) * subb + (float)oz * g.cellb)), 0.0f);
+                        if (ex * ex + ey * ey + ez * ez < g.l2b_hi + 1e-4f) {
+                            for (uint32_t j = u0; j < u1; j++)
+                                if (is_member(dens_s, j, g.dl0)) {
+                                    fs = (int)j;
+                                    break;
+                                }
+                            if (fs >= 0) ps = parent[fs];
+                        }
+                    }
+                    // the set shared by every active lane, if there is one
+                    const uint64_t am = __ballot(active);
+                    const int w0 = __shfl(wr, __ffsll((unsigned long long)am) - 1, 64);
+                    const int wcommon = __ballot(active && wr != w0) ? -2 : w0;
+                    uint64_t todo = __ballot(fs >= 0 && ps != wcommon);
+                    while (todo) {
+                        const int S = __ffsll((unsigned long long)todo) - 1;
+                        todo &= todo - 1;
+                        const int f = __shfl(fs, S, 64);
+                        const uint32_t e = (uint32_t)__shfl((int)u1, S, 64);
+                        int rS = uf_find_hint(parent, f);
+                        if (!__ballot(active && wr != rS)) continue;
+                        for (uint32_t j = (uint32_t)f; j < e; j++) {
+                            if (!is_member(dens_s, j, g.dl0)) continue;
+                            const bool lk = active && wr != rS && linked(xs, ys, zs, pi, sloc, spos, j, g);
+                            if (!__ballot(lk)) continue;
+                            rS = join_lanes(parent, lk, wr, rS);
+                            // the rest of the sub-cell is one set with it: done once
+                            // every lane is in that set
+                            if (!__ballot(active && wr != rS)) break;
                         }
                     }
                 }
-                if (hit) uf_unite(parent, f, (int)fb);
             }
         }
     }
 }
 
-// Members of sparse cells: link to the later members of sparse neighbour cells,
-// and to one member of every reachable sub-cell of a dense neighbour cell (the
-// members of a sub-cell are already one set).
+// Members of sparse cells: links to the later members of sparse neighbour
+// cells (pairs with dense cells are found by the dense chunks).
 __global__ __launch_bounds__(kBlock) void k_fof_sparse(int64_t nsparse, Geo g,
                                                        const int32_t *__restrict__ sparse,
                                                        const float4 *__restrict__ sloc,
                                                        const float4 *__restrict__ spos,
                                                        const uint32_t *__restrict__ off,
-                                                       const uint32_t *__restrict__ cellmap,
-                                                       const uint32_t *__restrict__ subtab,
                                                        const float *__restrict__ dens_s,
                                                        int32_t *parent) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
     if (t >= nsparse) return;
     const int i = sparse[t];
     if (!is_member(dens_s, i, g.dl0)) return;
     const float4 li = sloc[i];
     const float4 pi = spos[i];
     const uint32_t c = __float_as_uint(li.w);
-    const int nc = g.nc, k = g.ksub, nsub = k * k * k;
-    const float subb = g.cellb / (float)k;
+    const int nc = g.nc;
     const int cx = (int)(c % (uint32_t)nc), cy = (int)((c / (uint32_t)nc) % (uint32_t)nc),
               cz = (int)(c / ((uint32_t)nc * (uint32_t)nc));
     int ri = uf_find_hint(parent, i);
     for (int oz = -1; oz <= 1; oz++) {
-        const int z = wrapc(cz + oz, nc);
         const float zs = li.z - (float)oz * g.cellb;
         for (int oy = -1; oy <= 1; oy++) {
-            const int y = wrapc(cy + oy, nc);
             const float ys = li.y - (float)oy * g.cellb;
-            const uint32_t row = ((uint32_t)z * (uint32_t)nc + (uint32_t)y) * (uint32_t)nc;
             for (int ox = -1; ox <= 1; ox++) {
-                // the neighbour cell must come closer than l to the particle
                 const float gx = ox < 0 ? li.x : (ox > 0 ? g.cellb - li.x : 0.0f);
                 const float gy = oy < 0 ? li.y : (oy > 0 ? g.cellb - li.y : 0.0f);
                 const float gz = oz < 0 ? li.z : (oz > 0 ? g.cellb - li.z : 0.0f);
                 if (gx * gx + gy * gy + gz * gz >= g.l2b_hi) continue;
-                const uint32_t nb = row + (uint32_t)wrapc(cx + ox, nc);
+                const uint32_t nb = ((uint32_t)wrapc(cz + oz, nc) * (uint32_t)nc + (uint32_t)wrapc(cy + oy, nc)) *
+                                        (uint32_t)nc + (uint32_t)wrapc(cx + ox, nc);
+                uint32_t a = off[nb];
+                const uint32_t b = off[nb + 1];
+                if (b - a >= (uint32_t)kDenseMin) continue;
+                if (a <= (uint32_t)i) a = (uint32_t)i + 1;
                 const float xs = li.x - (float)ox * g.cellb;
-                const uint32_t a = off[nb], b = off[nb + 1];
-                if (b - a < (uint32_t)kDenseMin) {
-                    for (uint32_t j = a > (uint32_t)i ? a : (uint32_t)i + 1; j < b; j++) {
-                        if (!is_member(dens_s, j, g.dl0)) continue;
-                        if (linked(xs, ys, zs, pi, sloc, spos, j, g)) uf_unite(parent, i, (int)j);
-                    }
-                    continue;
-                }
-                const uint32_t *tab = subtab + (int64_t)cellmap[nb] * (nsub + 1);
-                for (int sz = 0; sz < k; sz++) {
-                    const float lz = sz * subb - 1e-5f, hz = lz + subb + 2e-5f;
-                    const float gz = fmaxf(fmaxf(lz - zs, zs - hz), 0.0f);
-                    if (gz * gz >= g.l2b_hi) continue;
-                    for (int sy = 0; sy < k; sy++) {
-                        const float ly = sy * subb - 1e-5f, hy = ly + subb + 2e-5f;
-                        const float gy = fmaxf(fmaxf(ly - ys, ys - hy), 0.0f);
-                        if (gz * gz + gy * gy >= g.l2b_hi) continue;
-                        for (int sx = 0; sx < k; sx++) {
-                            const float lx = sx * subb - 1e-5f, hx = lx + subb + 2e-5f;
-                            const float gx = fmaxf(fmaxf(lx - xs, xs - hx), 0.0f);
-                            if (gz * gz + gy * gy + gx * gx >= g.l2b_hi) continue;
-                            const int s2 = (sz * k + sy) * k + sx;
-                            const uint32_t u1 = tab[s2 + 1];
-                            for (uint32_t j = tab[s2]; j < u1; j++) {
-                                if (!is_member(dens_s, j, g.dl0)) continue;
-                                if (ri == parent[j]) break;  // already one set
-                                if (linked(xs, ys, zs, pi, sloc, spos, j, g)) {
-                                    uf_unite(parent, i, (int)j);
-                                    ri = uf_find_hint(parent, i);
-                                    break;
-                                }
-                            }
-                        }
-                    }
+                for (uint32_t j = a; j < b; j++) {
+                    if (!is_member(dens_s, j, g.dl0)) continue;
+                    if (!linked(xs, ys, zs, pi, sloc, spos, j, g)) continue;
+                    if (uf_find_hint(parent, (int)j) == ri) continue;
+                    uf_unite(parent, i, (int)j);
+                    ri = uf_find_hint(parent, i);
                 }
             }
         }
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_fof_flatten(int64_t n, int32_t *parent) {
+// Roots of all members, read-only: nothing writes the forest in this pass, so
+// every stored root is final (a compressing writer could otherwise replace a
+// stored root with an older ancestor).
+__global__ __launch_bounds__(kBlock) void k_fof_roots(int64_t n, const int32_t *__restrict__ parent,
+                                                      int32_t *__restrict__ root) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    if (ld(parent + i) < 0) return;
-    st(parent + i, uf_find(parent, (int)i));
+    int x = parent[i];
+    if (x >= 0) {
+        for (int p = parent[x]; p != x; p = parent[x]) x = p;
+    }
+    root[i] = x;
 }
 
-// Final compression and the smallest original index of every set.
-__global__ __launch_bounds__(kBlock) void k_fof_compress(int64_t n, int32_t *parent,
-                                                         const float4 *__restrict__ spos,
-                                                         int32_t *__restrict__ minorig) {
+// The smallest original index of every set, into minorig[root].
+__global__ __launch_bounds__(kBlock) void k_fof_minorig(int64_t n, const int32_t *__restrict__ root,
+                                                        const float4 *__restrict__ spos,
+                                                        int32_t *__restrict__ minorig) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int r = -1;
-    if (i < n && ld(parent + i) >= 0) {
-        r = uf_find(parent, (int)i);
-        st(parent + i, r);
-    }
+    const int r = i < n ? root[i] : -1;
     const WaveRun run = wave_run(r);
     const int32_t o = i < n ? (int32_t)orig_of(spos[i]) : 0x7fffffff;
     const int32_t m = wave_run_min(r >= 0 ? o : 0x7fffffff, run);
@@ -295,16 +341,22 @@ __global__ __launch_bounds__(kBlock) void k_fof_compress(int64_t n, int32_t *par
 }
 
 // Group key (smallest original index of the group) per sorted particle, and the
-// L0 label in original order.
-__global__ __launch_bounds__(kBlock) void k_fof_keys(int64_t n, const int32_t *__restrict__ parent,
+// L0 label in original order.  A key outside [0, n) would be an internal error;
+// it is flagged instead of being used as an index.
+__global__ __launch_bounds__(kBlock) void k_fof_keys(int64_t n, const int32_t *__restrict__ root,
                                                      const int32_t *__restrict__ minorig,
                                                      const float4 *__restrict__ spos,
                                                      int32_t *__restrict__ gkey,
-                                                     int32_t *__restrict__ l0_out) {
+                                                     int32_t *__restrict__ l0_out,
+                                                     int32_t *__restrict__ err) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    int p = parent[i];
-    int k = p < 0 ? -1 : minorig[p];
+    const int r = root[i];
+    int k = r < 0 ? -1 : minorig[r];
+    if (k >= n) {
+        atomicOr(err, 4);
+        k = -1;
+    }
     gkey[i] = k;
     if (l0_out) l0_out[orig_of(spos[i])] = k + 1;
 }
@@ -328,34 +380,23 @@ __global__ __launch_bounds__(kBlock) void k_keys_from_labels(int64_t n, const in
 
 void launch_fof(int64_t n, const Geo &g, Work &w, hipStream_t s) {
     hipLaunchKernelGGL(k_fof_init, grid(n), dim3(kBlock), 0, s, n, g, w.dens_s, w.parent);
-    // phase A + list of sub-cell representatives (reuses the chunk flag arrays)
     hipLaunchKernelGGL(k_fof_phase_a, grid(n), dim3(kBlock), 0, s, n, g, w.sloc, w.off, w.ssub, w.cnt,
-                       w.subtab, w.dens_s, w.parent, w.f_chunk);
-    scan_u32(w.f_chunk, w.s_chunk, n, w.scan_tmp, s);
-    hipLaunchKernelGGL(k_list, grid(n), dim3(kBlock), 0, s, n, w.f_chunk, w.s_chunk, w.runlist);
-    // the run count is bounded by n; threads beyond it exit on the device count
-    uint32_t nr = 0;
-    (void)hipMemcpyAsync(&nr, w.s_chunk + n, sizeof(nr), hipMemcpyDeviceToHost, s);
-    (void)hipStreamSynchronize(s);
-    w.nruns = nr;
-    if (w.nruns > 0) {
-        hipLaunchKernelGGL(k_fof_runs, grid(w.nruns), dim3(kBlock), 0, s, w.nruns, 0, g, w.runlist, w.sloc,
-                           w.spos, w.off, w.ssub, w.cnt, w.subtab, w.dens_s, w.parent);
-        hipLaunchKernelGGL(k_fof_flatten, grid(n), dim3(kBlock), 0, s, n, w.parent);
-        hipLaunchKernelGGL(k_fof_runs, grid(w.nruns), dim3(kBlock), 0, s, w.nruns, 1, g, w.runlist, w.sloc,
-                           w.spos, w.off, w.ssub, w.cnt, w.subtab, w.dens_s, w.parent);
-        hipLaunchKernelGGL(k_fof_flatten, grid(n), dim3(kBlock), 0, s, n, w.parent);
-    }
+                       w.subtab, w.dens_s, w.parent);
+    if (w.nchunks > 0)
+        hipLaunchKernelGGL(k_fof_dense, dim3((unsigned)((w.nchunks + 3) / 4)), dim3(kBlock), 0, s, w.nchunks, g,
+                           w.chunks, w.sloc, w.spos, w.off, w.cnt, w.subtab, w.dens_s, w.parent);
     if (w.nsparse > 0)
         hipLaunchKernelGGL(k_fof_sparse, grid(w.nsparse), dim3(kBlock), 0, s, w.nsparse, g, w.sparse,
-                           w.sloc, w.spos, w.off, w.cnt, w.subtab, w.dens_s, w.parent);
+                           w.sloc, w.spos, w.off, w.dens_s, w.parent);
+    // roots go to the owner array (free until the assignment stage)
+    hipLaunchKernelGGL(k_fof_roots, grid(n), dim3(kBlock), 0, s, n, w.parent, w.owner);
     fill_i32(w.minorig, 0x7fffffff, n, s);
-    hipLaunchKernelGGL(k_fof_compress, grid(n), dim3(kBlock), 0, s, n, w.parent, w.spos, w.minorig);
+    hipLaunchKernelGGL(k_fof_minorig, grid(n), dim3(kBlock), 0, s, n, w.owner, w.spos, w.minorig);
 }
 
 void launch_fof_labels(int64_t n, const Geo &, Work &w, int32_t *l0_out, hipStream_t s) {
-    hipLaunchKernelGGL(k_fof_keys, grid(n), dim3(kBlock), 0, s, n, w.parent, w.minorig, w.spos, w.gkey,
-                       l0_out);
+    hipLaunchKernelGGL(k_fof_keys, grid(n), dim3(kBlock), 0, s, n, w.owner, w.minorig, w.spos, w.gkey,
+                       l0_out, w.err);
 }
 
 void launch_keys_from_labels(const int32_t *l0_in, int64_t n, Work &w, hipStream_t s) {

@@ -157,7 +157,7 @@ size_t carve(char *base, int64_t n, int64_t ncell, int nsub, Work *w) {
     w->chunks = c.take<int32_t>(n1);
     w->sparse = c.take<int32_t>(n1);
     w->dcells = c.take<uint32_t>(n1);
-    w->runlist = c.take<int32_t>(n1);
+    w->hardlist = c.take<int32_t>(n1);
     w->subtab = c.take<uint32_t>((n / hf::kDenseMin + 1) * (nsub + 1));
     w->submax = c.take<uint64_t>((n / hf::kDenseMin + 1) * (nsub + 1));
     w->subarg = c.take<int32_t>((n / hf::kDenseMin + 1) * (nsub + 1));
@@ -230,6 +230,7 @@ hf_status check_pos_flags(hf_ctx *c, const Work &w, hipStream_t s) {
     HIP_OK(c, hipStreamSynchronize(s));
     if (err & 1) return fail(c, HF_ERR_INVALID, "positions must lie in [0, box)");
     if (err & 2) return fail(c, HF_ERR_INVALID, "l0_id values must lie in [0, n]");
+    if (err & 4) return fail(c, HF_ERR_DEVICE, "internal error: L0 group key out of range");
     return HF_OK;
 }
 
@@ -294,7 +295,6 @@ hf_status run_compaso(hf_ctx *c, int64_t n, const Geo &g, Work &w, int32_t *halo
     c->stats.n_dense_cells = w.ndcells;
     c->stats.n_dense_chunks = w.nchunks;
     c->stats.n_sparse = w.nsparse;
-    c->stats.n_subcell_runs = w.nruns;
     c->stats.n_hard = w.nhard;
     c->stats.n_found = counters[2];
     c->stats.n_halos = NH;
@@ -333,7 +333,6 @@ hf_status begin(hf_ctx *c, const float *pos, int64_t n, const hf_params *p, Geo 
     w->nchunks = counts[0];
     w->ndcells = counts[1];
     w->nsparse = counts[2];
-    w->nruns = 0;
     w->nhard = 0;
     hf::launch_subtab(n, w->ndcells, *g, *w, s);
     HIP_OK(c, hipEventRecord(c->ev[1], s));

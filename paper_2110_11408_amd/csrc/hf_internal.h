@@ -74,6 +74,20 @@ __device__ __forceinline__ bool denser(float da, uint32_t ia, float db, uint32_t
     return da > db || (da == db && ia < ib);
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup b runs on XCD
+// b mod 8), and each XCD has its own L2.  Work lists are in spatial order, so a
+// kernel whose neighbours overlap maps workgroup b to a logical index such that
+// every XCD gets one contiguous slice of the list and its L2 sees the reuse.
+constexpr unsigned kXcds = 8;
+
+__device__ __forceinline__ unsigned xcd_block() {
+    const unsigned b = blockIdx.x, nb = gridDim.x;
+    const unsigned per = nb / kXcds, rem = nb % kXcds;
+    const unsigned x = b % kXcds, k = b / kXcds;
+    const unsigned start = x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per;
+    return start + k;
+}
+
 __device__ __forceinline__ int wrapc(int c, int nc) {
     return c < 0 ? c + nc : (c >= nc ? c - nc : c);
 }
@@ -126,8 +140,8 @@ struct Work {
     uint32_t *dcells, *subtab;
     uint64_t *submax;                                  // densest particle per dense sub-cell
     int32_t *subarg;
-    int32_t *runlist;
-    int64_t nchunks, ndcells, nsparse, nruns, nhard;
+    int32_t *hardlist;                                 // candidate tests left after stage 1
+    int64_t nchunks, ndcells, nsparse, nhard;
     // density / FoF / groups (sorted order unless noted)
     float *dens_s;
     int32_t *parent, *minorig, *gkey, *gid_of, *owner;
