@@ -49,6 +49,23 @@ __device__ __forceinline__ void accum_range(const float4 *__restrict__ sloc, uin
     }
 }
 
+// Sum of v over the wavefront in a fixed order, wave-uniform: inclusive sums of
+// each 16-lane row by DPP row shifts, then the four row totals in row order.
+__device__ __forceinline__ float wave_sum(float v) {
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, true));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xf, 0xf, true));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xf, 0xf, true));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xf, 0xf, true));
+    const int b = __float_as_int(v);
+    return ((__int_as_float(__builtin_amdgcn_readlane(b, 15)) + __int_as_float(__builtin_amdgcn_readlane(b, 31))) +
+            __int_as_float(__builtin_amdgcn_readlane(b, 47))) +
+           __int_as_float(__builtin_amdgcn_readlane(b, 63));
+}
+
+// Dense-neighbour contributions of sparse particles are added in fixed point
+// (2^-32), so their order does not change the result.
+constexpr double kFixScale = 4294967296.0;
+
 __device__ __forceinline__ void write_density(int64_t i, double acc, const Geo &g,
                                               const float4 *__restrict__ spos,
                                               float *__restrict__ dens_s, float *__restrict__ dens_out) {
@@ -63,6 +80,8 @@ __global__ __launch_bounds__(kBlock) void k_density_dense(int64_t nchunks, Geo g
                                                           const float4 *__restrict__ sloc,
                                                           const float4 *__restrict__ spos,
                                                           const uint32_t *__restrict__ off,
+                                                          const uint32_t *__restrict__ s_sparse,
+                                                          uint64_t *__restrict__ dfx,
                                                           float *__restrict__ dens_s,
                                                           float *__restrict__ dens_out) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -92,18 +111,41 @@ __global__ __launch_bounds__(kBlock) void k_density_dense(int64_t nchunks, Geo g
                 const float xs = li.x - (float)ox * g.cellb;
                 const uint32_t a = __builtin_amdgcn_readfirstlane(off[nb]);
                 const uint32_t b = __builtin_amdgcn_readfirstlane(off[nb + 1]);
-                accum_range(sloc, a, b, xs, ys, zs, acc);
+                if (b - a >= (uint32_t)kDenseMin) {
+                    accum_range(sloc, a, b, xs, ys, zs, acc);
+                    continue;
+                }
+                // sparse neighbour cell: the pair weights also go to the
+                // sparse particle, summed over the chunk in a fixed order
+                float p = 0.0f;
+                for (uint32_t j = a; j < b; j++) {
+                    const float4 lj = sloc[j];
+                    const float dx = lj.x - xs, dy = lj.y - ys, dz = lj.z - zs;
+                    float t = fmaf(-dx, dx, 1.0f);
+                    t = fmaf(-dy, dy, t);
+                    t = fmaf(-dz, dz, t);
+                    t = active ? fmaxf(t, 0.0f) : 0.0f;
+                    p += t;
+                    const float sum = wave_sum(t);
+                    if (lane == 0 && sum > 0.0f)
+                        atomicAdd(reinterpret_cast<unsigned long long *>(&dfx[s_sparse[j]]),
+                                  (unsigned long long)__double2ll_rn((double)sum * kFixScale));
+                }
+                acc += (double)p;
             }
         }
     }
     if (active) write_density(i, acc, g, spos, dens_s, dens_out);
 }
 
+// Sparse cells: one particle per lane, sparse neighbour cells only; the pairs
+// with dense neighbour cells were summed by the dense kernel into dfx.
 __global__ __launch_bounds__(kBlock) void k_density_sparse(int64_t nsparse, Geo g,
                                                            const int32_t *__restrict__ sparse,
                                                            const float4 *__restrict__ sloc,
                                                            const float4 *__restrict__ spos,
                                                            const uint32_t *__restrict__ off,
+                                                           const uint64_t *__restrict__ dfx,
                                                            float *__restrict__ dens_s,
                                                            float *__restrict__ dens_out) {
     const int64_t t = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
@@ -138,11 +180,13 @@ __global__ __launch_bounds__(kBlock) void k_density_sparse(int64_t nsparse, Geo 
 #pragma unroll
             for (int ox = -1; ox <= 1; ox++) {
                 const int r = (oy + 1) * 3 + (ox + 1);
+                if (rb[r] - ra[r] >= (uint32_t)kDenseMin) continue;
                 const float xs = li.x - (float)ox * g.cellb;
                 accum_range(sloc, ra[r], rb[r], xs, ys, zs, acc);
             }
         }
     }
+    acc += (double)dfx[t] * (1.0 / kFixScale);
     write_density(i, acc, g, spos, dens_s, dens_out);
 }
 
@@ -191,12 +235,17 @@ __global__ __launch_bounds__(kBlock) void k_gather_density(int64_t n, const floa
 }  // namespace
 
 void launch_density(int64_t n, const Geo &g, Work &w, float *dens_out, hipStream_t s) {
+    // dfx: dense-neighbour sums of the sparse particles (fixed point), in the
+    // key/slot scratch that binning no longer needs
+    uint64_t *dfx = w.tmp;
+    if (w.nsparse > 0) fill_u32(reinterpret_cast<uint32_t *>(dfx), 0u, 2 * w.nsparse, s);
     if (w.nchunks > 0)
         hipLaunchKernelGGL(k_density_dense, dim3((unsigned)((w.nchunks + 3) / 4)), dim3(kBlock), 0, s,
-                           w.nchunks, g, w.chunks, w.sloc, w.spos, w.off, w.dens_s, dens_out);
+                           w.nchunks, g, w.chunks, w.sloc, w.spos, w.off, w.s_sparse, dfx, w.dens_s,
+                           dens_out);
     if (w.nsparse > 0)
         hipLaunchKernelGGL(k_density_sparse, dim3((unsigned)((w.nsparse + kBlock - 1) / kBlock)),
-                           dim3(kBlock), 0, s, w.nsparse, g, w.sparse, w.sloc, w.spos, w.off, w.dens_s,
+                           dim3(kBlock), 0, s, w.nsparse, g, w.sparse, w.sloc, w.spos, w.off, dfx, w.dens_s,
                            dens_out);
 }
 
