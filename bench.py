@@ -1,7 +1,7 @@
 """Benchmark of the CompaSO group-finding pass on one MI355X.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload plain256]
-                [--no-cpu-baseline] [--cpu-seconds S]
+                [--no-cpu-baseline] [--cpu-seconds S] [--no-batched] [--no-serving]
 
 A step is one hf_find call (binning, kernel density, L0 FoF, CompaSO L1 and the
 output cut) over the whole box, with positions already resident in HBM.  Prints
@@ -9,6 +9,13 @@ one JSON line with whole-job throughput in particles/s, the roofline of the
 dominant kernel (its average duration measured with HIP events on the stream it
 runs on, over the timed steps) and the FP64 CPU oracle timed on a bounded
 sample of the same generator.
+
+Two more workloads are reported in the same line:
+  batched  96 periodic sub-boxes of side log-uniform in 24..160 in one
+           hf_find_batch call, against one hf_find call per box;
+  serving  a Poisson stream of requests (boxes of 1e4..1e7 particles, log-uniform,
+           halo fraction 0.3..0.7) through hf_server, host arrays in and out,
+           against the same requests run one at a time on hf_find.
 """
 from __future__ import annotations
 
@@ -134,6 +141,122 @@ def cpu_baseline(target_s: float):
                       "the 256^3 box itself takes minutes on the host"}
 
 
+def _batched(ctx, np, torch, _lib, synth, reps=3, lanes=4):
+    """Batched workload: 96 boxes in one hf_find_batch call vs one hf_find per box."""
+    boxes = synth.batch_boxes()
+    pos = torch.from_numpy(np.concatenate([b[0] for b in boxes])).cuda()
+    sizes = np.array([len(b[0]) for b in boxes], np.int64)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    params = [_lib.default_params(box=b[1]) for b in boxes]
+    caps = np.maximum(sizes // 64, 64)
+    ctx.find_batch(pos, offs, params, halos_caps=caps, n_lanes=lanes, want_l0=False)
+    torch.cuda.synchronize()
+    t = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        ctx.find_batch(pos, offs, params, halos_caps=caps, n_lanes=lanes, want_l0=False)
+        torch.cuda.synchronize()
+        t.append(time.perf_counter() - t0)
+    views = [pos[offs[b]:offs[b + 1]] for b in range(len(boxes))]
+    for b in range(len(boxes)):
+        ctx.find(views[b], params[b], halos_cap=int(caps[b]), want_l0=False)
+    torch.cuda.synchronize()
+    tp = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        for b in range(len(boxes)):
+            ctx.find(views[b], params[b], halos_cap=int(caps[b]), want_l0=False)
+        torch.cuda.synchronize()
+        tp.append(time.perf_counter() - t0)
+    total = int(offs[-1])
+    tb, tpl = float(np.median(t)), float(np.median(tp))
+    return {"workload": "96 periodic boxes, side log-uniform in 24..160 (N = side^3, "
+                        f"{sizes.min()}..{sizes.max()}), half NFW haloes 35..20000",
+            "n_boxes": len(boxes), "n_particles": total, "lanes": lanes,
+            "value": total / tb, "unit": "particles/s", "ms": tb * 1e3,
+            "plain_value": total / tpl, "plain_ms": tpl * 1e3, "speedup": tpl / tb,
+            "reps": reps}
+
+
+def _fifo_latency(arrivals, service):
+    """Latencies of a one-at-a-time FIFO server with the given service times."""
+    done, lat = 0.0, []
+    for a, s in zip(arrivals, service):
+        start = max(a, done)
+        done = start + s
+        lat.append(done - a)
+    return lat
+
+
+def _serving(ctx, np, torch, _lib, synth, count=32, slots=4, budget_gb=64):
+    """Serving workload: Poisson arrivals at a rate that keeps the plain
+    one-at-a-time path fully busy; latency from submission to host results."""
+    from paper_2110_11408_amd.api import Server
+    reqs = synth.request_stream(count, rate_hz=1.0)
+    boxes = []
+    for r in reqs:
+        pos, L, _ = synth.make_box(synth.BoxRecipe(n=r["n"], side=r["side"], halo_frac=r["halo_frac"]),
+                                   r["seed"])
+        boxes.append((Server.pinned_positions(pos), L))
+    sizes = np.array([len(b[0]) for b in boxes], np.int64)
+    params = [_lib.default_params(box=b[1]) for b in boxes]
+    total = int(sizes.sum())
+    # plain path: host positions -> device, hf_find, results -> host, one at a time
+    def plain_one(b):
+        pos_h, _ = boxes[b]
+        d = pos_h.to("cuda", non_blocking=True)
+        out = ctx.find(d, params[b], want_density=False, want_l0=False)
+        out["halo_id"].cpu()
+        out["halos"].cpu()
+    plain_one(int(np.argmax(sizes)))
+    torch.cuda.synchronize()
+    service = []
+    for b in range(count):
+        t0 = time.perf_counter()
+        plain_one(b)
+        service.append(time.perf_counter() - t0)
+    mean_s = float(np.mean(service))
+    rate = 1.0 / mean_s            # the plain path's capacity in requests/s
+    gaps = np.diff(np.r_[0.0, [r["t"] for r in reqs]])  # exponential, mean 1 s
+    arrivals = np.cumsum(gaps / rate)
+    plain_lat = _fifo_latency(arrivals, service)
+    srv = Server(0, slots=slots, budget_bytes=int(budget_gb) << 30)
+    try:
+        # warm every slot once
+        for t in [srv.submit(boxes[b][0], params[b]) for b in np.argsort(sizes)[-slots:]]:
+            srv.wait(t)
+        # saturated: everything queued at once
+        t0 = srv.now()
+        tickets = [srv.submit(boxes[b][0], params[b]) for b in range(count)]
+        res = [srv.wait(t) for t in tickets]
+        sat = total / (max(r["t_done"] for r in res) - t0)
+        # open loop at the Poisson arrival times
+        base = time.perf_counter()
+        tickets = []
+        for b in range(count):
+            while time.perf_counter() - base < arrivals[b]:
+                time.sleep(min(0.0005, max(0.0, arrivals[b] - (time.perf_counter() - base))))
+            tickets.append(srv.submit(boxes[b][0], params[b]))
+        res = [srv.wait(t) for t in tickets]
+        lat = [r["t_done"] - r["t_submit"] for r in res]
+        span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
+        held = srv.held_bytes()
+    finally:
+        srv.close()
+    ms = lambda x: float(x) * 1e3  # noqa: E731
+    return {"workload": f"{count} requests, N log-uniform in 1e4..1e7 ({sizes.min()}..{sizes.max()}), "
+                        "halo fraction 0.3..0.7, side N^(1/3); host arrays in and out",
+            "requests": count, "n_particles": total, "slots": slots, "budget_gb": budget_gb,
+            "value": sat, "unit": "particles/s", "plain_value": total / float(np.sum(service)),
+            "rate_hz": rate, "open_loop_value": total / span,
+            "p50_ms": ms(np.percentile(lat, 50)), "p99_ms": ms(np.percentile(lat, 99)),
+            "plain_p50_ms": ms(np.percentile(plain_lat, 50)),
+            "plain_p99_ms": ms(np.percentile(plain_lat, 99)),
+            "plain_latency_model": "FIFO one at a time with the measured plain service times "
+                                   "at the same arrival times",
+            "held_gb": held / 2 ** 30}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +265,8 @@ def main():
     ap.add_argument("--workload", default="plain256", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of this many MiB (a traffic "
                          "reference for hardware counters)")
@@ -220,6 +345,10 @@ def main():
                    "n_dense_cells": st["n_dense_cells"], "n_dense_chunks": st["n_dense_chunks"],
                    "n_sparse": st["n_sparse"], "n_hard": st["n_hard"]},
     }
+    if not args.no_batched:
+        res["batched"] = _batched(ctx, np, torch, _lib, synth)
+    if not args.no_serving:
+        res["serving"] = _serving(ctx, np, torch, _lib, synth)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(res), flush=True)

@@ -156,6 +156,82 @@ hf_status hf_find(hf_ctx *ctx, const float *pos, int64_t n, const hf_params *p,
                   float *density, int32_t *l0_id, int32_t *halo_id, hf_halo *halos,
                   int64_t halos_cap, int64_t *n_halos, void *stream);
 
+/* ---- Many boxes per call ------------------------------------------------
+ * hf_find on n_boxes independent periodic boxes (Sec. 2.2 applied to each box
+ * on its own).  Box b holds particles [box_offsets[b], box_offsets[b+1]) of the
+ * concatenated device array pos (float32 [total][3]) and is found with
+ * params[b] (host array; its box side and mean density are the box's own).
+ * Outputs are concatenated in the same particle order: density (may be NULL),
+ * l0_id (may be NULL) and halo_id, with labels local to the box (1 + index
+ * within the box).  Box b's halo table goes to rows
+ * [halo_offsets[b], halo_offsets[b+1]) of halos (device); n_halos[b] (host)
+ * receives its count.  box_offsets and halo_offsets are host arrays of
+ * n_boxes + 1 non-decreasing values starting at 0.
+ *
+ * The boxes run on n_lanes pipelines at once (<= 0: 4; at most 16), each with
+ * its own stream and scratch arena held by the context, largest boxes first.
+ * Every box's outputs are identical to hf_find's on that box alone.  The call
+ * first waits for the caller's stream and returns when all boxes are done.
+ * Returns the first failing box's error (text names the box); if only halo
+ * capacities were too small, HF_ERR_CAPACITY with every n_halos[b] set to the
+ * required count (tables of boxes that fit are written). */
+hf_status hf_find_batch(hf_ctx *ctx, int32_t n_boxes, const int64_t *box_offsets,
+                        const float *pos, const hf_params *params, float *density,
+                        int32_t *l0_id, int32_t *halo_id, hf_halo *halos,
+                        const int64_t *halo_offsets, int64_t *n_halos, int32_t n_lanes,
+                        void *stream);
+
+/* ---- Request loop ----------------------------------------------------------
+ * A server runs halo-finding requests for boxes of different sizes as they
+ * arrive.  It owns n_slots pipelines (streams, scratch arenas and device
+ * buffers that stay allocated between requests) and one host thread per slot.
+ * A free slot takes the oldest waiting request when the device memory of all
+ * slots, with this request's need, stays within hbm_budget_bytes (idle slots
+ * give their memory back when that makes it fit); requests therefore overlap
+ * on the GPU while the budget allows.  Each request's result is identical to
+ * hf_find on the same box alone. */
+typedef struct hf_server hf_server;
+
+typedef struct {
+    const float *pos;   /* host float32 [n][3]; must stay valid until waited for
+                           (page-locked memory makes the copy asynchronous)   */
+    int64_t n;
+    hf_params params;
+    float *density;     /* host float32 [n] or NULL                            */
+    int32_t *l0_id;     /* host int32 [n] or NULL                              */
+    int32_t *halo_id;   /* host int32 [n]                                      */
+    hf_halo *halos;     /* host, halos_cap rows                                */
+    int64_t halos_cap;
+} hf_request;
+
+typedef struct {
+    int32_t status;     /* hf_status of the request (HF_ERR_CAPACITY: n_halos is
+                           the required capacity; halo_id is still written)   */
+    int32_t slot;       /* slot that ran it                                    */
+    int64_t n_halos;
+    double t_submit;    /* seconds on the server clock (hf_server_now)         */
+    double t_start;     /* taken by a slot                                     */
+    double t_done;      /* results written to the host buffers                 */
+    float ms_gpu;       /* device time of its pass (first to last stage event) */
+    char error[160];    /* error text when status != HF_OK                     */
+} hf_result;
+
+/* n_slots in 1..16.  HF_ERR_UNSUPPORTED when the device is not gfx950. */
+hf_status hf_server_create(hf_server **srv, int device, int32_t n_slots,
+                           uint64_t hbm_budget_bytes);
+/* Queue a request (the struct is copied; the buffers it points to are not).
+ * HF_ERR_NOMEM when the request alone needs more than the budget. */
+hf_status hf_server_submit(hf_server *srv, const hf_request *req, int64_t *ticket);
+/* Block until the request is done and return its result; a ticket is waited
+ * for once. */
+hf_status hf_server_wait(hf_server *srv, int64_t ticket, hf_result *res);
+double hf_server_now(const hf_server *srv);
+/* Device memory held by the slots now (arenas and request buffers). */
+uint64_t hf_server_held_bytes(hf_server *srv);
+const char *hf_server_last_error(const hf_server *srv);
+/* Finish every queued request, then free the slots. */
+void hf_server_destroy(hf_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,7 +18,9 @@ STATUS = {0: "HF_OK", 1: "HF_ERR_INVALID", 2: "HF_ERR_NOMEM", 3: "HF_ERR_CAPACIT
           4: "HF_ERR_DEVICE", 5: "HF_ERR_UNSUPPORTED"}
 
 EXPORTS = ["hf_default_params", "hf_derived", "hf_create", "hf_destroy", "hf_last_error",
-           "hf_get_stats", "hf_density", "hf_l0_fof", "hf_compaso", "hf_find", "hf_count_pairs"]
+           "hf_get_stats", "hf_density", "hf_l0_fof", "hf_compaso", "hf_find", "hf_count_pairs",
+           "hf_find_batch", "hf_server_create", "hf_server_submit", "hf_server_wait",
+           "hf_server_now", "hf_server_held_bytes", "hf_server_last_error", "hf_server_destroy"]
 
 
 class HfParams(ctypes.Structure):
@@ -44,6 +46,20 @@ class HfStats(ctypes.Structure):
                [(k, ctypes.c_int64) for k in
                 ("n_cells", "n_members", "n_groups", "n_candidates", "n_found", "n_halos",
                  "n_dense_cells", "n_dense_chunks", "n_sparse", "n_hard")]
+
+
+class HfRequest(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_void_p), ("n", ctypes.c_int64), ("params", HfParams),
+                ("density", ctypes.c_void_p), ("l0_id", ctypes.c_void_p),
+                ("halo_id", ctypes.c_void_p), ("halos", ctypes.c_void_p),
+                ("halos_cap", ctypes.c_int64)]
+
+
+class HfResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("slot", ctypes.c_int32), ("n_halos", ctypes.c_int64),
+                ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("ms_gpu", ctypes.c_float),
+                ("error", ctypes.c_char * 160)]
 
 
 HALO_FIELDS = [f[0] for f in HfHalo._fields_]
@@ -81,8 +97,22 @@ def load(path: str = LIB_PATH):
         lib.hf_compaso.argtypes = [P, P, P, P, I64, PP, P, P, I64, P, P]
         lib.hf_find.argtypes = [P, P, I64, PP, P, P, P, P, I64, P, P]
         lib.hf_count_pairs.argtypes = [P, P, I64, PP, P, P]
+        lib.hf_find_batch.argtypes = [P, ctypes.c_int32, P, P, P, P, P, P, P, P, P, ctypes.c_int32, P]
+        lib.hf_server_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), I32, ctypes.c_int32,
+                                         ctypes.c_uint64]
+        lib.hf_server_submit.argtypes = [P, ctypes.POINTER(HfRequest), ctypes.POINTER(ctypes.c_int64)]
+        lib.hf_server_wait.argtypes = [P, ctypes.c_int64, ctypes.POINTER(HfResult)]
+        lib.hf_server_now.argtypes = [P]
+        lib.hf_server_now.restype = ctypes.c_double
+        lib.hf_server_held_bytes.argtypes = [P]
+        lib.hf_server_held_bytes.restype = ctypes.c_uint64
+        lib.hf_server_last_error.argtypes = [P]
+        lib.hf_server_last_error.restype = ctypes.c_char_p
+        lib.hf_server_destroy.argtypes = [P]
+        lib.hf_server_destroy.restype = None
         for name in ("hf_derived", "hf_create", "hf_get_stats", "hf_density", "hf_l0_fof",
-                     "hf_compaso", "hf_find", "hf_count_pairs"):
+                     "hf_compaso", "hf_find", "hf_count_pairs", "hf_find_batch",
+                     "hf_server_create", "hf_server_submit", "hf_server_wait"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib

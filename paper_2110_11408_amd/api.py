@@ -1,7 +1,9 @@
-"""Torch-facing wrappers of the C ABI: hf_density, hf_l0_fof, hf_compaso, hf_find.
+"""Torch-facing wrappers of the C ABI: hf_density, hf_l0_fof, hf_compaso, hf_find,
+hf_find_batch and the hf_server request loop.
 
 Tensors must live on the GPU the context was created on; outputs are allocated
-with torch (device memory) and the work runs on torch's current stream.
+with torch (device memory) and the work runs on torch's current stream.  The
+server takes host arrays and returns host arrays.
 """
 from __future__ import annotations
 
@@ -10,7 +12,7 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import HfError, HfParams, HfStats, HALO_FIELDS, HALO_WORDS
+from ._lib import HfError, HfParams, HfRequest, HfResult, HfStats, HALO_FIELDS, HALO_WORDS
 
 
 def _ptr(t):
@@ -111,6 +113,44 @@ class Context:
                 _ptr(buf), cap, ctypes.byref(nh), _stream(pos.device)),
             halos_cap, n, pos.device, {"density": dens, "l0_id": l0, "halo_id": halo_id})
 
+    def find_batch(self, pos, offsets, params, halos_caps=None, n_lanes=0, want_density=True,
+                   want_l0=True):
+        """hf_find_batch over boxes concatenated in pos ([total, 3], device) with
+        box b = rows offsets[b]:offsets[b+1]; params: one HfParams per box.
+        Returns concatenated density / l0_id / halo_id (box-local labels),
+        n_halos per box and the list of per-box halo tables."""
+        import numpy as np
+        pos = _check_pos(pos)
+        offs = np.ascontiguousarray(offsets, dtype=np.int64)
+        nb = len(offs) - 1
+        if len(params) != nb:
+            raise ValueError("one HfParams per box")
+        total = int(offs[-1]) if nb > 0 else 0
+        if total != pos.shape[0]:
+            raise ValueError("offsets[-1] must equal the number of rows of pos")
+        pa = (HfParams * max(nb, 1))(*params)
+        sizes = np.diff(offs)
+        caps = np.maximum(sizes // 32, 1) if halos_caps is None else np.asarray(halos_caps, np.int64)
+        dens = torch.empty(total, dtype=torch.float32, device=pos.device) if want_density else None
+        l0 = torch.empty(total, dtype=torch.int32, device=pos.device) if want_l0 else None
+        halo_id = torch.empty(total, dtype=torch.int32, device=pos.device)
+        nh = np.zeros(max(nb, 1), dtype=np.int64)
+        for _ in range(2):
+            hoffs = np.ascontiguousarray(np.concatenate([[0], np.cumsum(caps)]), dtype=np.int64)
+            buf = torch.empty((max(int(hoffs[-1]), 1), HALO_WORDS), dtype=torch.int32, device=pos.device)
+            st = self.lib.hf_find_batch(self.h, nb, offs.ctypes.data, _ptr(pos), ctypes.byref(pa),
+                                        _ptr(dens), _ptr(l0), _ptr(halo_id), _ptr(buf),
+                                        hoffs.ctypes.data, nh.ctypes.data, int(n_lanes),
+                                        _stream(pos.device))
+            if st == _lib.HF_ERR_CAPACITY:
+                caps = np.maximum(caps, nh[:nb])
+                continue
+            self._raise(st)
+            tables = [buf[hoffs[b]: hoffs[b] + nh[b]] for b in range(nb)]
+            return {"density": dens, "l0_id": l0, "halo_id": halo_id, "n_halos": nh[:nb].copy(),
+                    "halos": tables}
+        raise HfError(_lib.HF_ERR_CAPACITY, "halo table capacity retry failed")
+
     def _with_table(self, call, cap, n, device, outs):
         cap = max(1, n // 32) if cap is None else int(cap)
         for _ in range(2):
@@ -125,6 +165,93 @@ class Context:
             outs["halos"] = buf[: nh.value]
             return outs
         raise HfError(_lib.HF_ERR_CAPACITY, "halo table capacity retry failed")
+
+
+class Server:
+    """An hf_server: requests (host positions) run on `slots` pipelines at once
+    within an HBM budget; results come back in page-locked host tensors."""
+
+    def __init__(self, device: int = 0, slots: int = 4, budget_bytes: int = 64 << 30):
+        self.lib = _lib.load()
+        self.device = int(device)
+        h = ctypes.c_void_p()
+        st = self.lib.hf_server_create(ctypes.byref(h), self.device, int(slots), int(budget_bytes))
+        if st:
+            raise HfError(st, "hf_server_create failed")
+        self.h = h
+        self._live = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.hf_server_destroy(self.h)
+            self.h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def now(self) -> float:
+        return float(self.lib.hf_server_now(self.h))
+
+    def held_bytes(self) -> int:
+        return int(self.lib.hf_server_held_bytes(self.h))
+
+    @staticmethod
+    def pinned_positions(pos) -> torch.Tensor:
+        """A page-locked float32 [n, 3] copy of pos (numpy or torch)."""
+        t = torch.as_tensor(pos, dtype=torch.float32).reshape(-1, 3)
+        out = torch.empty(t.shape, dtype=torch.float32, pin_memory=True)
+        out.copy_(t)
+        return out
+
+    def submit(self, pos, p: HfParams, halos_cap: int | None = None, want_density=False,
+               want_l0=False) -> int:
+        """Queue one box; pos is a host float32 [n, 3] array (page-locked when it
+        comes from pinned_positions, which makes the device copy asynchronous)."""
+        if isinstance(pos, torch.Tensor) and pos.is_pinned() and pos.dtype == torch.float32:
+            pos_h = pos.contiguous()
+        else:
+            pos_h = self.pinned_positions(pos)
+        n = pos_h.shape[0]
+        cap = max(1, n // 32) if halos_cap is None else int(halos_cap)
+        bufs = {"pos": pos_h,
+                "halo_id": torch.empty(n, dtype=torch.int32, pin_memory=True),
+                "halos": torch.empty((max(cap, 1), HALO_WORDS), dtype=torch.int32, pin_memory=True),
+                "density": torch.empty(n, dtype=torch.float32, pin_memory=True) if want_density else None,
+                "l0_id": torch.empty(n, dtype=torch.int32, pin_memory=True) if want_l0 else None}
+        req = HfRequest()
+        req.pos = pos_h.data_ptr() if n else None
+        req.n = n
+        req.params = p
+        req.density = bufs["density"].data_ptr() if want_density and n else None
+        req.l0_id = bufs["l0_id"].data_ptr() if want_l0 and n else None
+        req.halo_id = bufs["halo_id"].data_ptr() if n else None
+        req.halos = bufs["halos"].data_ptr()
+        req.halos_cap = cap
+        ticket = ctypes.c_int64(0)
+        st = self.lib.hf_server_submit(self.h, ctypes.byref(req), ctypes.byref(ticket))
+        if st:
+            raise HfError(st, self.lib.hf_server_last_error(self.h).decode())
+        self._live[ticket.value] = bufs
+        return ticket.value
+
+    def wait(self, ticket: int, check: bool = True) -> dict:
+        res = HfResult()
+        st = self.lib.hf_server_wait(self.h, int(ticket), ctypes.byref(res))
+        if st:
+            raise HfError(st, self.lib.hf_server_last_error(self.h).decode())
+        bufs = self._live.pop(ticket)
+        if check and res.status:
+            raise HfError(res.status, res.error.decode())
+        nh = int(res.n_halos)
+        return {"status": int(res.status), "error": res.error.decode(), "slot": int(res.slot),
+                "n_halos": nh, "halo_id": bufs["halo_id"], "density": bufs["density"],
+                "l0_id": bufs["l0_id"], "halos": bufs["halos"][:nh] if res.status == 0 else None,
+                "t_submit": res.t_submit, "t_start": res.t_start, "t_done": res.t_done,
+                "ms_gpu": float(res.ms_gpu)}
 
 
 def halo_table(rows: torch.Tensor) -> dict:

@@ -6,27 +6,19 @@
 
 #include <string>
 
-#include "hf_internal.h"
+#include "hf_lane.h"
 
 #define HF_PI 3.14159265358979323846
-
-struct hf_ctx {
-    int device = 0;
-    void *arena = nullptr;
-    size_t arena_bytes = 0;
-    hipEvent_t ev[10] = {};
-    hf_stats stats = {};
-    std::string err;
-};
 
 namespace {
 
 using hf::Geo;
+using hf::Lane;
 using hf::Work;
 
 enum { D_NBAR, D_B, D_L, D_B2, D_L2, D_NORM, D_K, D_K2, D_FLOOR, D_A6, D_C3, D_COUNT };
 
-hf_status fail(hf_ctx *c, hf_status st, const std::string &msg) {
+hf_status fail(Lane *c, hf_status st, const std::string &msg) {
     if (c) c->err = msg;
     return st;
 }
@@ -74,7 +66,7 @@ hf_status derive(const hf_params *p, int64_t n, double *d) {
     return HF_OK;
 }
 
-hf_status make_geo(hf_ctx *c, const hf_params *p, int64_t n, Geo *g) {
+hf_status make_geo(Lane *c, const hf_params *p, int64_t n, Geo *g) {
     double d[D_COUNT];
     if (derive(p, n, d) != HF_OK) return fail(c, HF_ERR_INVALID, "invalid parameters");
     if (n >= (int64_t)0x7fffffff) return fail(c, HF_ERR_INVALID, "n must be below 2^31 - 1");
@@ -198,14 +190,14 @@ size_t carve(char *base, int64_t n, int64_t ncell, int nsub, Work *w) {
     return c.off + 256;
 }
 
-hf_status prepare(hf_ctx *c, int64_t n, const Geo &g, Work *w) {
+hf_status prepare(Lane *c, int64_t n, const Geo &g, Work *w) {
     int64_t ncell = (int64_t)g.nc * g.nc * g.nc;
     const int nsub = g.ksub * g.ksub * g.ksub;
     size_t need = carve(nullptr, n, ncell, nsub, w);
     HIP_OK(c, hipSetDevice(c->device));
     if (need > c->arena_bytes) {
         if (c->arena) {
-            HIP_OK(c, hipDeviceSynchronize());
+            // every call ends synchronized with its stream, so the old arena is idle
             HIP_OK(c, hipFree(c->arena));
             c->arena = nullptr;
             c->arena_bytes = 0;
@@ -224,7 +216,7 @@ hf_status prepare(hf_ctx *c, int64_t n, const Geo &g, Work *w) {
     return HF_OK;
 }
 
-hf_status check_pos_flags(hf_ctx *c, const Work &w, hipStream_t s) {
+hf_status check_pos_flags(Lane *c, const Work &w, hipStream_t s) {
     int32_t err = 0;
     HIP_OK(c, hipMemcpyAsync(&err, w.err, sizeof(err), hipMemcpyDeviceToHost, s));
     HIP_OK(c, hipStreamSynchronize(s));
@@ -245,7 +237,7 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 
 // CompaSO on the binned particles with group keys in w.gkey.  Fills halo_id,
 // the table and the counts; records events ev[3..8].
-hf_status run_compaso(hf_ctx *c, int64_t n, const Geo &g, Work &w, int32_t *halo_id,
+hf_status run_compaso(Lane *c, int64_t n, const Geo &g, Work &w, int32_t *halo_id,
                       int32_t *l0_out, hf_halo *halos, int64_t cap, int64_t *n_halos,
                       hipStream_t s) {
     HIP_OK(c, hipEventRecord(c->ev[3], s));
@@ -302,7 +294,7 @@ hf_status run_compaso(hf_ctx *c, int64_t n, const Geo &g, Work &w, int32_t *halo
     return HF_OK;
 }
 
-hf_status begin(hf_ctx *c, const float *pos, int64_t n, const hf_params *p, Geo *g, Work *w,
+hf_status begin(Lane *c, const float *pos, int64_t n, const hf_params *p, Geo *g, Work *w,
                 hipStream_t s) {
     if (!c) return HF_ERR_INVALID;
     c->err.clear();
@@ -341,6 +333,75 @@ hf_status begin(hf_ctx *c, const float *pos, int64_t n, const hf_params *p, Geo 
 
 }  // namespace
 
+namespace hf {
+
+hf_status lane_init(Lane *L, int device, bool own_stream) {
+    L->device = device;
+    if (hipSetDevice(device) != hipSuccess) return HF_ERR_DEVICE;
+    for (auto &e : L->ev)
+        if (hipEventCreate(&e) != hipSuccess) return HF_ERR_DEVICE;
+    if (own_stream && hipStreamCreateWithFlags(&L->stream, hipStreamNonBlocking) != hipSuccess)
+        return HF_ERR_DEVICE;
+    return HF_OK;
+}
+
+void lane_release(Lane *L) {
+    if (L->arena) {
+        (void)hipSetDevice(L->device);
+        (void)hipFree(L->arena);
+    }
+    L->arena = nullptr;
+    L->arena_bytes = 0;
+}
+
+void lane_destroy(Lane *L) {
+    lane_release(L);
+    for (auto &e : L->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (L->stream) (void)hipStreamDestroy(L->stream);
+    L->stream = nullptr;
+}
+
+size_t lane_arena_bytes(const hf_params *p, int64_t n) {
+    if (n <= 0) return 0;
+    Geo g;
+    Work w;
+    if (make_geo(nullptr, p, n, &g) != HF_OK) return 0;
+    const int64_t ncell = (int64_t)g.nc * g.nc * g.nc;
+    const size_t need = carve(nullptr, n, ncell, g.ksub * g.ksub * g.ksub, &w);
+    return need + need / 8;
+}
+
+hf_status lane_find(Lane *c, const float *pos, int64_t n, const hf_params *p, float *density,
+                    int32_t *l0_id, int32_t *halo_id, hf_halo *halos, int64_t halos_cap,
+                    int64_t *n_halos, hipStream_t s) {
+    Geo g;
+    Work w;
+    if (n > 0 && !halo_id) return fail(c, HF_ERR_INVALID, "halo_id is NULL");
+    if (halos_cap < 0 || (halos_cap > 0 && !halos)) return fail(c, HF_ERR_INVALID, "bad halos / halos_cap");
+    hf_status st = begin(c, pos, n, p, &g, &w, s);
+    if (st != HF_OK) return st;
+    if (n == 0) {
+        if (n_halos) *n_halos = 0;
+        return HF_OK;
+    }
+    hf::launch_density(n, g, w, density, s);
+    HIP_OK(c, hipEventRecord(c->ev[2], s));
+    hf::launch_fof(n, g, w, s);
+    hf::launch_fof_labels(n, g, w, l0_id, s);
+    HIP_OK(c, hipEventRecord(c->ev[9], s));
+    st = check_pos_flags(c, w, s);
+    if (st != HF_OK) return st;
+    st = run_compaso(c, n, g, w, halo_id, nullptr, halos, halos_cap, n_halos, s);
+    c->stats.ms_bin = elapsed(c->ev[0], c->ev[1]);
+    c->stats.ms_density = elapsed(c->ev[1], c->ev[2]);
+    c->stats.ms_fof = elapsed(c->ev[2], c->ev[9]);
+    c->stats.ms_total = elapsed(c->ev[0], c->ev[8]);
+    return st;
+}
+
+}  // namespace hf
+
 extern "C" {
 
 void hf_default_params(hf_params *p) {
@@ -376,42 +437,33 @@ hf_status hf_create(hf_ctx **out, int device) {
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) return HF_ERR_DEVICE;
     if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return HF_ERR_UNSUPPORTED;
     hf_ctx *c = new hf_ctx();
-    c->device = device;
-    if (hipSetDevice(device) != hipSuccess) {
+    if (hf::lane_init(&c->main, device, false) != HF_OK) {
+        hf::lane_destroy(&c->main);
         delete c;
         return HF_ERR_DEVICE;
     }
-    for (auto &e : c->ev)
-        if (hipEventCreate(&e) != hipSuccess) {
-            delete c;
-            return HF_ERR_DEVICE;
-        }
     *out = c;
     return HF_OK;
 }
 
 void hf_destroy(hf_ctx *c) {
     if (!c) return;
-    (void)hipSetDevice(c->device);
-    if (c->arena) {
-        (void)hipDeviceSynchronize();
-        (void)hipFree(c->arena);
-    }
-    for (auto &e : c->ev)
-        if (e) (void)hipEventDestroy(e);
+    for (auto &L : c->pool) hf::lane_destroy(L.get());
+    hf::lane_destroy(&c->main);
     delete c;
 }
 
-const char *hf_last_error(const hf_ctx *c) { return c ? c->err.c_str() : "no context"; }
+const char *hf_last_error(const hf_ctx *c) { return c ? c->main.err.c_str() : "no context"; }
 
 hf_status hf_get_stats(const hf_ctx *c, hf_stats *out) {
     if (!c || !out) return HF_ERR_INVALID;
-    *out = c->stats;
+    *out = c->main.stats;
     return HF_OK;
 }
 
-hf_status hf_density(hf_ctx *c, const float *pos, int64_t n, const hf_params *p, float *density,
+hf_status hf_density(hf_ctx *ctx, const float *pos, int64_t n, const hf_params *p, float *density,
                      void *stream) {
+    Lane *c = ctx ? &ctx->main : nullptr;
     hipStream_t s = (hipStream_t)stream;
     Geo g;
     Work w;
@@ -427,8 +479,9 @@ hf_status hf_density(hf_ctx *c, const float *pos, int64_t n, const hf_params *p,
     return st;
 }
 
-hf_status hf_count_pairs(hf_ctx *c, const float *pos, int64_t n, const hf_params *p,
+hf_status hf_count_pairs(hf_ctx *ctx, const float *pos, int64_t n, const hf_params *p,
                          int64_t *pairs, void *stream) {
+    Lane *c = ctx ? &ctx->main : nullptr;
     hipStream_t s = (hipStream_t)stream;
     Geo g;
     Work w;
@@ -442,8 +495,9 @@ hf_status hf_count_pairs(hf_ctx *c, const float *pos, int64_t n, const hf_params
     return check_pos_flags(c, w, s);
 }
 
-hf_status hf_l0_fof(hf_ctx *c, const float *pos, const float *density, int64_t n,
+hf_status hf_l0_fof(hf_ctx *ctx, const float *pos, const float *density, int64_t n,
                     const hf_params *p, int32_t *l0_id, int64_t *n_groups, void *stream) {
+    Lane *c = ctx ? &ctx->main : nullptr;
     hipStream_t s = (hipStream_t)stream;
     Geo g;
     Work w;
@@ -473,9 +527,10 @@ hf_status hf_l0_fof(hf_ctx *c, const float *pos, const float *density, int64_t n
     return st;
 }
 
-hf_status hf_compaso(hf_ctx *c, const float *pos, const float *density, const int32_t *l0_id,
+hf_status hf_compaso(hf_ctx *ctx, const float *pos, const float *density, const int32_t *l0_id,
                      int64_t n, const hf_params *p, int32_t *halo_id, hf_halo *halos,
                      int64_t halos_cap, int64_t *n_halos, void *stream) {
+    Lane *c = ctx ? &ctx->main : nullptr;
     hipStream_t s = (hipStream_t)stream;
     Geo g;
     Work w;
@@ -499,33 +554,12 @@ hf_status hf_compaso(hf_ctx *c, const float *pos, const float *density, const in
     return st;
 }
 
-hf_status hf_find(hf_ctx *c, const float *pos, int64_t n, const hf_params *p, float *density,
+hf_status hf_find(hf_ctx *ctx, const float *pos, int64_t n, const hf_params *p, float *density,
                   int32_t *l0_id, int32_t *halo_id, hf_halo *halos, int64_t halos_cap,
                   int64_t *n_halos, void *stream) {
-    hipStream_t s = (hipStream_t)stream;
-    Geo g;
-    Work w;
-    if (n > 0 && !halo_id) return fail(c, HF_ERR_INVALID, "halo_id is NULL");
-    if (halos_cap < 0 || (halos_cap > 0 && !halos)) return fail(c, HF_ERR_INVALID, "bad halos / halos_cap");
-    hf_status st = begin(c, pos, n, p, &g, &w, s);
-    if (st != HF_OK) return st;
-    if (n == 0) {
-        if (n_halos) *n_halos = 0;
-        return HF_OK;
-    }
-    hf::launch_density(n, g, w, density, s);
-    HIP_OK(c, hipEventRecord(c->ev[2], s));
-    hf::launch_fof(n, g, w, s);
-    hf::launch_fof_labels(n, g, w, l0_id, s);
-    HIP_OK(c, hipEventRecord(c->ev[9], s));
-    st = check_pos_flags(c, w, s);
-    if (st != HF_OK) return st;
-    st = run_compaso(c, n, g, w, halo_id, nullptr, halos, halos_cap, n_halos, s);
-    c->stats.ms_bin = elapsed(c->ev[0], c->ev[1]);
-    c->stats.ms_density = elapsed(c->ev[1], c->ev[2]);
-    c->stats.ms_fof = elapsed(c->ev[2], c->ev[9]);
-    c->stats.ms_total = elapsed(c->ev[0], c->ev[8]);
-    return st;
+    if (!ctx) return HF_ERR_INVALID;
+    return hf::lane_find(&ctx->main, pos, n, p, density, l0_id, halo_id, halos, halos_cap, n_halos,
+                         (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -1,0 +1,46 @@
+// Host-side state of one pipeline instance ("lane"): its scratch arena, the
+// events that time its stages, the statistics and error text of its last call,
+// and, for the lanes of the batched and serving paths, a stream of its own.
+// A context owns one lane for its single-box calls and a pool of lanes for
+// hf_find_batch; a server owns one lane per slot.
+#pragma once
+
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "hf_internal.h"
+
+namespace hf {
+
+struct Lane {
+    int device = 0;
+    void *arena = nullptr;
+    size_t arena_bytes = 0;
+    hipEvent_t ev[10] = {};
+    hf_stats stats = {};
+    std::string err;
+    hipStream_t stream = nullptr;  // owned; null for a context's main lane
+};
+
+// Create the events (and a non-blocking stream of default priority when
+// own_stream).  Returns HF_ERR_DEVICE on failure.
+hf_status lane_init(Lane *L, int device, bool own_stream);
+// Free the arena (the lane stays usable; the next call allocates again).
+void lane_release(Lane *L);
+// Release, destroy events and the owned stream.
+void lane_destroy(Lane *L);
+// Bytes of arena a call of n particles under p needs (0 if p or n is invalid).
+size_t lane_arena_bytes(const hf_params *p, int64_t n);
+// The whole pass for one box on stream s (hf_find's contract).
+hf_status lane_find(Lane *L, const float *pos, int64_t n, const hf_params *p, float *density,
+                    int32_t *l0_id, int32_t *halo_id, hf_halo *halos, int64_t halos_cap,
+                    int64_t *n_halos, hipStream_t s);
+
+}  // namespace hf
+
+struct hf_ctx {
+    hf::Lane main;
+    std::vector<std::unique_ptr<hf::Lane>> pool;  // lanes of hf_find_batch, created on demand
+};

@@ -1,0 +1,401 @@
+// Many boxes per call (hf_find_batch) and a request loop (hf_server).
+//
+// Both run the single-box pipeline on several lanes at once, each lane with its
+// own stream, arena and host thread.  The pipeline reads a few counts back to
+// the host between stages; while one lane waits for its counts the other lanes'
+// kernels keep the GPU busy, and small boxes that cannot fill 256 CUs on their
+// own share the device.  Results do not depend on which lane runs a box or on
+// what runs beside it: every lane computes the same deterministic pass.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <string.h>
+#include <thread>
+#include <unordered_map>
+
+#include "hf_lane.h"
+
+namespace {
+
+constexpr int kDefaultLanes = 4;
+constexpr int kMaxLanes = 16;
+
+void add_stats(hf_stats &a, const hf_stats &b) {
+    a.ms_bin += b.ms_bin;
+    a.ms_density += b.ms_density;
+    a.ms_fof += b.ms_fof;
+    a.ms_segment += b.ms_segment;
+    a.ms_candidates += b.ms_candidates;
+    a.ms_accept += b.ms_accept;
+    a.ms_assign += b.ms_assign;
+    a.ms_output += b.ms_output;
+    a.n_cells += b.n_cells;
+    a.n_members += b.n_members;
+    a.n_groups += b.n_groups;
+    a.n_candidates += b.n_candidates;
+    a.n_found += b.n_found;
+    a.n_halos += b.n_halos;
+    a.n_dense_cells += b.n_dense_cells;
+    a.n_dense_chunks += b.n_dense_chunks;
+    a.n_sparse += b.n_sparse;
+    a.n_hard += b.n_hard;
+}
+
+hf_status batch_fail(hf_ctx *c, hf_status st, const std::string &msg) {
+    c->main.err = msg;
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+hf_status hf_find_batch(hf_ctx *ctx, int32_t n_boxes, const int64_t *box_offsets, const float *pos,
+                        const hf_params *params, float *density, int32_t *l0_id, int32_t *halo_id,
+                        hf_halo *halos, const int64_t *halo_offsets, int64_t *n_halos,
+                        int32_t n_lanes, void *stream) {
+    if (!ctx) return HF_ERR_INVALID;
+    ctx->main.err.clear();
+    ctx->main.stats = hf_stats{};
+    if (n_boxes < 0) return batch_fail(ctx, HF_ERR_INVALID, "n_boxes is negative");
+    if (n_boxes == 0) return HF_OK;
+    if (!box_offsets || !params || !halo_offsets || !n_halos)
+        return batch_fail(ctx, HF_ERR_INVALID, "box_offsets / params / halo_offsets / n_halos is NULL");
+    if (box_offsets[0] != 0 || halo_offsets[0] != 0)
+        return batch_fail(ctx, HF_ERR_INVALID, "box_offsets[0] and halo_offsets[0] must be 0");
+    for (int32_t b = 0; b < n_boxes; b++)
+        if (box_offsets[b + 1] < box_offsets[b] || halo_offsets[b + 1] < halo_offsets[b])
+            return batch_fail(ctx, HF_ERR_INVALID, "box_offsets / halo_offsets must not decrease");
+    const int64_t total = box_offsets[n_boxes];
+    if (total >= (int64_t)0x7fffffff) return batch_fail(ctx, HF_ERR_INVALID, "too many particles");
+    if (total > 0 && (!pos || !halo_id)) return batch_fail(ctx, HF_ERR_INVALID, "pos / halo_id is NULL");
+    if (halo_offsets[n_boxes] > 0 && !halos) return batch_fail(ctx, HF_ERR_INVALID, "halos is NULL");
+
+    const int k = std::min(std::min(n_lanes > 0 ? n_lanes : kDefaultLanes, kMaxLanes), (int)n_boxes);
+    while ((int)ctx->pool.size() < k) {
+        auto L = std::make_unique<hf::Lane>();
+        if (hf::lane_init(L.get(), ctx->main.device, true) != HF_OK) {
+            hf::lane_destroy(L.get());
+            return batch_fail(ctx, HF_ERR_DEVICE, "could not create a batch lane");
+        }
+        ctx->pool.push_back(std::move(L));
+    }
+    // work the caller queued on its stream (e.g. the copy of pos) comes first
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+        return batch_fail(ctx, HF_ERR_DEVICE, "hipStreamSynchronize of the caller's stream failed");
+
+    // largest boxes first, so that the tail of the batch is made of small ones
+    std::vector<int32_t> order(n_boxes);
+    for (int32_t b = 0; b < n_boxes; b++) order[b] = b;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return box_offsets[a + 1] - box_offsets[a] > box_offsets[b + 1] - box_offsets[b];
+    });
+    std::vector<hf_status> st(n_boxes, HF_OK);
+    std::vector<std::string> msg(n_boxes);
+    std::vector<hf_stats> lane_stats(k, hf_stats{});
+    std::atomic<int32_t> next{0};
+    const auto t0 = std::chrono::steady_clock::now();
+    auto work = [&](int t) {
+        hf::Lane *L = ctx->pool[t].get();
+        (void)hipSetDevice(L->device);
+        for (;;) {
+            const int32_t q = next.fetch_add(1);
+            if (q >= n_boxes) break;
+            const int32_t b = order[q];
+            const int64_t o = box_offsets[b], nb = box_offsets[b + 1] - o;
+            const int64_t ho = halo_offsets[b], cap = halo_offsets[b + 1] - ho;
+            n_halos[b] = 0;
+            st[b] = hf::lane_find(L, nb ? pos + 3 * o : nullptr, nb, &params[b], density ? density + o : nullptr,
+                                  l0_id ? l0_id + o : nullptr, halo_id + o, cap ? halos + ho : nullptr, cap,
+                                  &n_halos[b], L->stream);
+            if (st[b] != HF_OK) msg[b] = L->err;
+            add_stats(lane_stats[t], L->stats);
+        }
+    };
+    std::vector<std::thread> threads;
+    for (int t = 1; t < k; t++) threads.emplace_back(work, t);
+    work(0);
+    for (auto &th : threads) th.join();
+    const auto t1 = std::chrono::steady_clock::now();
+
+    for (int t = 0; t < k; t++) add_stats(ctx->main.stats, lane_stats[t]);
+    ctx->main.stats.ms_total = (float)std::chrono::duration<double, std::milli>(t1 - t0).count();
+    for (int32_t b = 0; b < n_boxes; b++)
+        if (st[b] != HF_OK && st[b] != HF_ERR_CAPACITY)
+            return batch_fail(ctx, st[b], "box " + std::to_string(b) + ": " + msg[b]);
+    for (int32_t b = 0; b < n_boxes; b++)
+        if (st[b] == HF_ERR_CAPACITY)
+            return batch_fail(ctx, HF_ERR_CAPACITY,
+                              "box " + std::to_string(b) + ": halo capacity too small (n_halos holds the "
+                              "required counts)");
+    return HF_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- server
+
+namespace {
+
+struct Pending {
+    int64_t ticket;
+    hf_request r;
+    double t_submit;
+    size_t need;
+};
+
+struct Slot {
+    hf::Lane lane;
+    void *io = nullptr;  // device copies of the request's input and outputs
+    size_t io_bytes = 0;
+    bool busy = false;
+    size_t reserved = 0;  // bytes granted at admission, counted while busy
+    size_t held() const { return lane.arena_bytes + io_bytes; }
+    // memory charged against the budget: a busy slot's worker may be growing its
+    // buffers outside the lock, so its grant is counted instead
+    size_t charged() const { return busy ? reserved : held(); }
+};
+
+size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t io_bytes_for(const hf_request &r) {
+    const size_t n = (size_t)r.n;
+    return round256(12 * n) + round256(4 * n) * 3 + round256(sizeof(hf_halo) * (size_t)(r.halos_cap > 0 ? r.halos_cap : 1));
+}
+
+}  // namespace
+
+struct hf_server {
+    int device = 0;
+    uint64_t budget = 0;
+    std::vector<std::unique_ptr<Slot>> slots;
+    std::vector<std::thread> workers;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Pending> queue;
+    std::unordered_map<int64_t, hf_result> done;
+    std::unordered_map<int64_t, bool> known;  // tickets submitted and not yet waited for
+    int64_t next_ticket = 1;
+    bool stop = false;
+    std::string err;
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+
+    double now() const {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    size_t held_total() const {
+        size_t s = 0;
+        for (auto &sl : slots) s += sl->charged();
+        return s;
+    }
+    // Whether slot t may take the request at the head of the queue within the
+    // memory budget; frees the memory of idle slots when that makes it fit.
+    bool admit(int t) {
+        const Pending &q = queue.front();
+        Slot &me = *slots[t];
+        auto fits = [&] { return held_total() - me.charged() + std::max(me.held(), q.need) <= budget; };
+        if (fits()) return true;
+        for (size_t u = 0; u < slots.size() && !fits(); u++) {
+            Slot &o = *slots[u];
+            if ((int)u == t || o.busy || o.held() == 0) continue;
+            hf::lane_release(&o.lane);
+            if (o.io) (void)hipFree(o.io);
+            o.io = nullptr;
+            o.io_bytes = 0;
+        }
+        if (fits()) return true;
+        // last resort: this slot's own memory is re-allocated at the needed size
+        if (held_total() - me.charged() + q.need <= budget) {
+            hf::lane_release(&me.lane);
+            if (me.io) (void)hipFree(me.io);
+            me.io = nullptr;
+            me.io_bytes = 0;
+            return true;
+        }
+        return false;
+    }
+    void run(int t, const Pending &q, hf_result &res);
+    void worker(int t);
+};
+
+void hf_server::run(int t, const Pending &q, hf_result &res) {
+    Slot &sl = *slots[t];
+    hf::Lane *L = &sl.lane;
+    const hf_request &r = q.r;
+    const hipStream_t s = L->stream;
+    auto set_err = [&](hf_status stt, const std::string &m) {
+        res.status = stt;
+        strncpy(res.error, m.c_str(), sizeof(res.error) - 1);
+    };
+    const size_t iob = io_bytes_for(r);
+    if (iob > sl.io_bytes) {
+        if (sl.io) (void)hipFree(sl.io);
+        sl.io = nullptr;
+        sl.io_bytes = 0;
+        if (hipMalloc(&sl.io, iob) != hipSuccess) {
+            (void)hipGetLastError();
+            sl.io = nullptr;
+            return set_err(HF_ERR_NOMEM, "hipMalloc of the request buffers failed");
+        }
+        sl.io_bytes = iob;
+    }
+    const size_t n = (size_t)r.n;
+    char *base = (char *)sl.io;
+    float *pos_d = (float *)base;
+    float *dens_d = (float *)(base + round256(12 * n));
+    int32_t *l0_d = (int32_t *)(base + round256(12 * n) + round256(4 * n));
+    int32_t *halo_d = (int32_t *)(base + round256(12 * n) + 2 * round256(4 * n));
+    hf_halo *halos_d = (hf_halo *)(base + round256(12 * n) + 3 * round256(4 * n));
+    if (n > 0 && hipMemcpyAsync(pos_d, r.pos, 12 * n, hipMemcpyHostToDevice, s) != hipSuccess)
+        return set_err(HF_ERR_DEVICE, "copy of positions to the device failed");
+    int64_t nh = 0;
+    hf_status st = hf::lane_find(L, n ? pos_d : nullptr, r.n, &r.params, r.density ? dens_d : nullptr,
+                                 r.l0_id ? l0_d : nullptr, halo_d, r.halos_cap > 0 ? halos_d : nullptr,
+                                 r.halos_cap, &nh, s);
+    res.n_halos = nh;
+    res.ms_gpu = L->stats.ms_total;
+    if (st != HF_OK && st != HF_ERR_CAPACITY) return set_err(st, L->err);
+    bool ok = true;
+    if (n > 0) {
+        ok &= hipMemcpyAsync(r.halo_id, halo_d, 4 * n, hipMemcpyDeviceToHost, s) == hipSuccess;
+        if (r.density) ok &= hipMemcpyAsync(r.density, dens_d, 4 * n, hipMemcpyDeviceToHost, s) == hipSuccess;
+        if (r.l0_id) ok &= hipMemcpyAsync(r.l0_id, l0_d, 4 * n, hipMemcpyDeviceToHost, s) == hipSuccess;
+    }
+    if (st == HF_OK && nh > 0)
+        ok &= hipMemcpyAsync(r.halos, halos_d, sizeof(hf_halo) * (size_t)nh, hipMemcpyDeviceToHost, s) ==
+              hipSuccess;
+    ok &= hipStreamSynchronize(s) == hipSuccess;
+    if (!ok) return set_err(HF_ERR_DEVICE, "copy of the results to the host failed");
+    if (st != HF_OK) return set_err(st, L->err);
+    res.status = HF_OK;
+}
+
+void hf_server::worker(int t) {
+    (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+        while (!(stop && queue.empty()) && (queue.empty() || slots[t]->busy || !admit(t))) cv_work.wait(lk);
+        if (queue.empty()) break;  // stopping and nothing left
+        Pending q = queue.front();
+        queue.pop_front();
+        slots[t]->reserved = std::max(slots[t]->held(), q.need);
+        slots[t]->busy = true;
+        lk.unlock();
+        hf_result res;
+        memset(&res, 0, sizeof(res));
+        res.slot = t;
+        res.t_submit = q.t_submit;
+        res.t_start = now();
+        run(t, q, res);
+        res.t_done = now();
+        lk.lock();
+        slots[t]->busy = false;
+        done[q.ticket] = res;
+        cv_done.notify_all();
+        cv_work.notify_all();
+    }
+}
+
+extern "C" {
+
+hf_status hf_server_create(hf_server **out, int device, int32_t n_slots, uint64_t hbm_budget_bytes) {
+    if (!out) return HF_ERR_INVALID;
+    *out = nullptr;
+    if (n_slots <= 0 || n_slots > kMaxLanes || hbm_budget_bytes == 0) return HF_ERR_INVALID;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
+        (void)hipGetLastError();
+        return HF_ERR_UNSUPPORTED;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return HF_ERR_DEVICE;
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return HF_ERR_UNSUPPORTED;
+    hf_server *srv = new hf_server();
+    srv->device = device;
+    srv->budget = hbm_budget_bytes;
+    for (int t = 0; t < n_slots; t++) {
+        auto sl = std::make_unique<Slot>();
+        if (hf::lane_init(&sl->lane, device, true) != HF_OK) {
+            hf::lane_destroy(&sl->lane);
+            for (auto &o : srv->slots) hf::lane_destroy(&o->lane);
+            delete srv;
+            return HF_ERR_DEVICE;
+        }
+        srv->slots.push_back(std::move(sl));
+    }
+    for (int t = 0; t < n_slots; t++) srv->workers.emplace_back(&hf_server::worker, srv, t);
+    *out = srv;
+    return HF_OK;
+}
+
+hf_status hf_server_submit(hf_server *srv, const hf_request *req, int64_t *ticket) {
+    if (!srv || !req || !ticket) return HF_ERR_INVALID;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (req->n < 0 || (req->n > 0 && (!req->pos || !req->halo_id)) || req->halos_cap < 0 ||
+        (req->halos_cap > 0 && !req->halos)) {
+        srv->err = "invalid request (n, pos, halo_id, halos / halos_cap)";
+        return HF_ERR_INVALID;
+    }
+    size_t need = 0;
+    if (req->n > 0) {
+        need = hf::lane_arena_bytes(&req->params, req->n);
+        if (need == 0) {
+            srv->err = "invalid parameters for this request";
+            return HF_ERR_INVALID;
+        }
+        need += io_bytes_for(*req);
+    }
+    if (need > srv->budget) {
+        srv->err = "request needs " + std::to_string(need) + " bytes, more than the HBM budget";
+        return HF_ERR_NOMEM;
+    }
+    const int64_t id = srv->next_ticket++;
+    srv->queue.push_back(Pending{id, *req, srv->now(), need});
+    srv->known[id] = true;
+    *ticket = id;
+    srv->cv_work.notify_all();
+    return HF_OK;
+}
+
+hf_status hf_server_wait(hf_server *srv, int64_t ticket, hf_result *res) {
+    if (!srv || !res) return HF_ERR_INVALID;
+    std::unique_lock<std::mutex> lk(srv->mu);
+    if (!srv->known.count(ticket)) {
+        srv->err = "unknown ticket";
+        return HF_ERR_INVALID;
+    }
+    srv->cv_done.wait(lk, [&] { return srv->done.count(ticket) != 0; });
+    *res = srv->done[ticket];
+    srv->done.erase(ticket);
+    srv->known.erase(ticket);
+    return HF_OK;
+}
+
+double hf_server_now(const hf_server *srv) { return srv ? srv->now() : 0.0; }
+
+uint64_t hf_server_held_bytes(hf_server *srv) {
+    if (!srv) return 0;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    return srv->held_total();
+}
+
+const char *hf_server_last_error(const hf_server *srv) { return srv ? srv->err.c_str() : "no server"; }
+
+void hf_server_destroy(hf_server *srv) {
+    if (!srv) return;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
+    }
+    srv->cv_work.notify_all();
+    for (auto &th : srv->workers) th.join();
+    for (auto &sl : srv->slots) {
+        hf::lane_destroy(&sl->lane);
+        if (sl->io) (void)hipFree(sl->io);
+    }
+    delete srv;
+}
+
+}  // extern "C"

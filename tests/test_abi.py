@@ -82,3 +82,67 @@ def test_create_without_gpu_is_unsupported(lib):
         pass
     h = ctypes.c_void_p()
     assert lib.hf_create(ctypes.byref(h), 0) == _lib.HF_ERR_UNSUPPORTED
+
+
+def _c_layout():
+    """sizeof / offsetof of the public structs as the C compiler lays them out."""
+    import subprocess
+    import tempfile
+    fields = {"hf_params": [f for f, _ in _lib.HfParams._fields_],
+              "hf_halo": [f for f, _ in _lib.HfHalo._fields_],
+              "hf_stats": [f for f, _ in _lib.HfStats._fields_],
+              "hf_request": [f for f, _ in _lib.HfRequest._fields_],
+              "hf_result": [f for f, _ in _lib.HfResult._fields_]}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hf.h"', "int main(void) {"]
+    for s, fs in fields.items():
+        lines.append(f'printf("{s} size %zu\\n", sizeof({s}));')
+        for f in fs:
+            lines.append(f'printf("{s} {f} %zu\\n", offsetof({s}, {f}));')
+    lines.append("return 0; }")
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "layout.c"), os.path.join(d, "layout")
+        open(src, "w").write("\n".join(lines))
+        subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), src, "-o", exe])
+        out = subprocess.check_output([exe]).decode().split("\n")
+    res = {}
+    for ln in out:
+        if ln:
+            s, f, v = ln.split()
+            res[(s, f)] = int(v)
+    return res
+
+
+def test_ctypes_structs_match_c_layout():
+    c = _c_layout()
+    for s, cls in (("hf_params", _lib.HfParams), ("hf_halo", _lib.HfHalo), ("hf_stats", _lib.HfStats),
+                   ("hf_request", _lib.HfRequest), ("hf_result", _lib.HfResult)):
+        assert c[(s, "size")] == ctypes.sizeof(cls), s
+        for f, _ in cls._fields_:
+            assert c[(s, f)] == getattr(cls, f).offset, (s, f)
+
+
+def test_batch_and_server_reject_bad_arguments(lib):
+    p = _lib.default_params(box=10.0)
+    offs = (ctypes.c_int64 * 2)(0, 0)
+    st = lib.hf_find_batch(None, 1, offs, None, ctypes.byref(p), None, None, None, None, offs,
+                           None, 0, None)
+    assert st == _lib.HF_ERR_INVALID
+    h = ctypes.c_void_p()
+    # slot count outside 1..16 and a zero budget are argument errors, checked first
+    assert lib.hf_server_create(ctypes.byref(h), 0, 0, 1 << 30) == _lib.HF_ERR_INVALID
+    assert lib.hf_server_create(ctypes.byref(h), 0, 17, 1 << 30) == _lib.HF_ERR_INVALID
+    assert lib.hf_server_create(ctypes.byref(h), 0, 2, 0) == _lib.HF_ERR_INVALID
+    assert lib.hf_server_submit(None, None, None) == _lib.HF_ERR_INVALID
+    assert lib.hf_server_wait(None, 1, None) == _lib.HF_ERR_INVALID
+    assert lib.hf_server_now(None) == 0.0
+
+
+def test_server_without_gpu_is_unsupported(lib):
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("GPU present")
+    except Exception:
+        pass
+    h = ctypes.c_void_p()
+    assert lib.hf_server_create(ctypes.byref(h), 0, 2, 1 << 30) == _lib.HF_ERR_UNSUPPORTED
