@@ -1,18 +1,25 @@
-// Cell binning: a stable counting sort of the particles by (cell, sub-cell).
+// Cell binning: a stable sort of the particles by (cell, sub-cell), ties in
+// original index order.
 //
 // The paper's host code receives particles already ordered by cell from the
 // N-body engine (Sec. 2.3.4); here the caller hands over an unordered float32
 // [n][3] array, so the library builds the order itself:
-//   1. cell key, sub-cell index and an atomic ticket inside the cell (counts);
-//   2. exclusive scan of the per-cell counts (cell offsets);
-//   3. scatter of (sub-cell, original index) to offset + ticket (unstable);
-//   4. stable rank inside the cell by (sub-cell, original index), and the final
-//      write of two float4 streams per particle:
+//   1. key = cell * k^3 + sub-cell per particle (range check of the input);
+//   2. least-significant-digit radix sort of (key, original index), digits of
+//      at most 11 bits; key and index share one 64-bit word when they fit.
+//      Each pass: a block counts the digits of its tile of 4096 consecutive
+//      elements; an exclusive scan of the digit-major [digit][tile] counts
+//      gives every (digit, tile) its output offset; the tile is then walked
+//      again in order, each element's rank among equal digits coming from the
+//      ballots of its digit bits (lower lanes first), so the pass is stable;
+//   3. the sorted order writes two float4 streams per particle:
 //        spos = (x, y, z, original index bits)    -- the paper's float quad with
 //               the index stored bitwise (Sec. 2.3.3), used by FP64 predicates;
 //        sloc = (x, y, z relative to the cell corner, in units of b; cell id
 //               bits) -- FP32 coordinates whose differences across a periodic
-//               face stay exact, used by the density loop and prefilters.
+//               face stay exact, used by the density loop and prefilters;
+//   4. cell offsets for every cell of the grid, written by the sorted
+//      particles that end each run of cells (coalesced, one wavefront per 64).
 // Cells are at least max(b, l) wide; each is split into k^3 sub-cells whose
 // diagonal is below l, so all particles of one sub-cell are friends.
 //
@@ -22,6 +29,8 @@
 // (one wavefront each); particles of the other cells form the "sparse" list
 // (one thread each).  The in-cell order, and therefore every summation order,
 // is fixed by the data, never by thread scheduling.
+#include <stdlib.h>
+
 #include "hf_internal.h"
 
 namespace hf {
@@ -40,11 +49,11 @@ __device__ __forceinline__ int sub_coord(float x, int c, const Geo &g) {
     return s < 0 ? 0 : (s >= g.ksub ? g.ksub - 1 : s);
 }
 
-__global__ __launch_bounds__(kBlock) void k_bin_key(const float *__restrict__ pos, int64_t n, Geo g,
-                                                    uint32_t *__restrict__ key,
-                                                    uint32_t *__restrict__ ticket,
-                                                    uint16_t *__restrict__ subk,
-                                                    uint32_t *__restrict__ cnt,
+// Sort key of particle i: cell * k^3 + sub-cell.  Packed mode stores
+// (key << ib) | i in one word (ib bits hold the index); otherwise the index
+// travels in a separate payload array.
+__global__ __launch_bounds__(kBlock) void k_bin_key(const float *__restrict__ pos, int64_t n, Geo g, int ib,
+                                                    uint64_t *__restrict__ key,
                                                     int32_t *__restrict__ err) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -55,54 +64,185 @@ __global__ __launch_bounds__(kBlock) void k_bin_key(const float *__restrict__ po
     int cx = cell_coord(x, g), cy = cell_coord(y, g), cz = cell_coord(z, g);
     uint32_t c = ((uint32_t)cz * (uint32_t)g.nc + (uint32_t)cy) * (uint32_t)g.nc + (uint32_t)cx;
     int k = g.ksub;
-    key[i] = c;
-    subk[i] = (uint16_t)((sub_coord(z, cz, g) * k + sub_coord(y, cy, g)) * k + sub_coord(x, cx, g));
-    ticket[i] = atomicAdd(&cnt[c], 1u);
+    uint32_t sub = (uint32_t)((sub_coord(z, cz, g) * k + sub_coord(y, cy, g)) * k + sub_coord(x, cx, g));
+    const uint64_t kk = (uint64_t)c * (uint64_t)(k * k * k) + sub;
+    key[i] = ib > 0 ? (kk << ib) | (uint64_t)i : kk;
 }
 
-__global__ __launch_bounds__(kBlock) void k_bin_scatter(int64_t n, const uint32_t *__restrict__ key,
-                                                        const uint32_t *__restrict__ ticket,
-                                                        const uint16_t *__restrict__ subk,
-                                                        const uint32_t *__restrict__ off,
-                                                        uint64_t *__restrict__ tmp) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    tmp[off[key[i]] + ticket[i]] = ((uint64_t)subk[i] << 32) | (uint64_t)i;
-}
+constexpr int kRadixMaxBits = 11;
+constexpr int kRadixWaves = 4;                      // wavefronts per tile
+constexpr int kRadixIters = 16;                     // 64-element steps per wavefront
+constexpr int64_t kTile = 64 * kRadixWaves * kRadixIters;  // 4096 elements per tile
 
-__global__ __launch_bounds__(kBlock) void k_bin_stable(const float *__restrict__ pos, int64_t n, Geo g,
-                                                       const uint32_t *__restrict__ key,
-                                                       const uint32_t *__restrict__ off,
-                                                       const uint64_t *__restrict__ tmp,
-                                                       float4 *__restrict__ spos,
-                                                       float4 *__restrict__ sloc,
-                                                       uint16_t *__restrict__ ssub) {
-    int64_t s = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const uint64_t me = tmp[s];
-    const uint32_t o = (uint32_t)me;
-    const uint32_t c = key[o];
-    const uint32_t a = off[c], b = off[c + 1];
-    uint32_t rank = 0;
-    // a wavefront whose slots all lie in one cell streams that cell once
-    // (wave-uniform loads); otherwise every lane walks its own cell
-    const uint32_t c0 = __builtin_amdgcn_readfirstlane(c);
-    if (__ballot(c != c0) == 0ull && s - (threadIdx.x & 63) + 63 < n) {
-        const uint32_t ua = __builtin_amdgcn_readfirstlane(a), ub = __builtin_amdgcn_readfirstlane(b);
-        for (uint32_t t = ua; t < ub; t++) rank += tmp[t] < me ? 1u : 0u;
-    } else {
-        for (uint32_t t = a; t < b; t++) rank += tmp[t] < me ? 1u : 0u;
+// Lanes holding the same D-bit digit as this lane (within `active`).
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, int D, uint64_t active) {
+    uint64_t m = active;
+    for (int b = 0; b < D; b++) {
+        const uint64_t bal = __ballot((d >> b) & 1u);
+        m &= ((d >> b) & 1u) ? bal : ~bal;
     }
-    const uint32_t d = a + rank;
-    float x = pos[3 * (int64_t)o + 0], y = pos[3 * (int64_t)o + 1], z = pos[3 * (int64_t)o + 2];
-    spos[d] = make_float4(x, y, z, __uint_as_float(o));
-    uint32_t nc = (uint32_t)g.nc;
-    uint32_t cx = c % nc, cy = (c / nc) % nc, cz = c / (nc * nc);
-    float xl = (float)(((double)x - (double)cx * g.cell) * g.inv_b);
-    float yl = (float)(((double)y - (double)cy * g.cell) * g.inv_b);
-    float zl = (float)(((double)z - (double)cz * g.cell) * g.inv_b);
-    sloc[d] = make_float4(xl, yl, zl, __uint_as_float(c));
-    ssub[d] = (uint16_t)(me >> 32);
+    return m;
+}
+
+__device__ __forceinline__ uint64_t lanes_below(int lane) {
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Digit counts of one tile, stored digit-major ([digit][tile]).  Wavefront w
+// of the tile owns elements [w * 1024, (w + 1) * 1024) of it and loads all 16
+// of its steps before counting.
+__global__ __launch_bounds__(256) void k_radix_count(const uint64_t *__restrict__ key, int64_t n, int shift,
+                                                     int D, int64_t ntiles, uint32_t *__restrict__ hist) {
+    __shared__ uint32_t h[1 << kRadixMaxBits];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t t = blockIdx.x;
+    const int nd = 1 << D;
+    for (int d = threadIdx.x; d < nd; d += 256) h[d] = 0u;
+    const int64_t base = t * kTile + (int64_t)w * (64 * kRadixIters) + lane;
+    uint64_t k[kRadixIters];
+#pragma unroll
+    for (int it = 0; it < kRadixIters; it++) {
+        const int64_t e = base + it * 64;
+        k[it] = e < n ? key[e] : 0ull;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kRadixIters; it++) {
+        const bool act = base + it * 64 < n;
+        const uint32_t d = (uint32_t)(k[it] >> shift) & (uint32_t)(nd - 1);
+        const uint64_t m = digit_peers(d, D, __ballot(act));
+        if (act && (m & lanes_below(lane)) == 0ull) atomicAdd(&h[d], (uint32_t)__popcll(m));
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < nd; d += 256) hist[(int64_t)d * ntiles + t] = h[d];
+}
+
+// Stable scatter of one tile.  Offsets of wavefront w for digit d: the scanned
+// (d, tile) offset plus the counts of d in wavefronts 0..w-1; inside a
+// wavefront, steps in order and lanes in order.
+template <bool kPacked>
+__global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t *__restrict__ kin,
+                                                       const uint32_t *__restrict__ vin, int64_t n, int shift,
+                                                       int D, int64_t ntiles, const uint32_t *__restrict__ hscan,
+                                                       uint64_t *__restrict__ kout, uint32_t *__restrict__ vout) {
+    __shared__ uint32_t o[kRadixWaves][1 << kRadixMaxBits];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t t = blockIdx.x;
+    const int nd = 1 << D;
+    for (int d = lane; d < nd; d += 64) o[w][d] = 0u;
+    const int64_t base = t * kTile + (int64_t)w * (64 * kRadixIters) + lane;
+    uint64_t k[kRadixIters];
+    uint32_t v[kPacked ? 1 : kRadixIters];
+#pragma unroll
+    for (int it = 0; it < kRadixIters; it++) {
+        const int64_t e = base + it * 64;
+        k[it] = e < n ? kin[e] : 0ull;
+        if (!kPacked) v[it] = e < n ? (vin ? vin[e] : (uint32_t)e) : 0u;
+    }
+    // counts of this wavefront (its own LDS row; leaders only, in step order)
+#pragma unroll
+    for (int it = 0; it < kRadixIters; it++) {
+        const bool act = base + it * 64 < n;
+        const uint32_t d = (uint32_t)(k[it] >> shift) & (uint32_t)(nd - 1);
+        const uint64_t m = digit_peers(d, D, __ballot(act));
+        if (act && (m & lanes_below(lane)) == 0ull) o[w][d] += (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < nd; d += 256) {
+        uint32_t b = hscan[(int64_t)d * ntiles + t];
+#pragma unroll
+        for (int x = 0; x < kRadixWaves; x++) {
+            const uint32_t c = o[x][d];
+            o[x][d] = b;
+            b += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kRadixIters; it++) {
+        const bool act = base + it * 64 < n;
+        const uint32_t d = (uint32_t)(k[it] >> shift) & (uint32_t)(nd - 1);
+        const uint64_t m = digit_peers(d, D, __ballot(act));
+        const uint32_t start = act ? o[w][d] : 0u;
+        if (act) {
+            const uint32_t dst = start + (uint32_t)__popcll(m & lanes_below(lane));
+            kout[dst] = k[it];
+            if (!kPacked) vout[dst] = v[it];
+        }
+        // LDS operations of one wavefront complete in order: every lane of the
+        // group has read `start` before the leader's update lands
+        if (act && (m & lanes_below(lane)) == 0ull) o[w][d] = start + (uint32_t)__popcll(m);
+    }
+}
+
+// Sorted slot s: the particle's two float4 records and its sub-cell.
+template <bool kPacked>
+__global__ __launch_bounds__(kBlock) void k_bin_place(const float *__restrict__ pos, int64_t n, Geo g, int ib,
+                                                      const uint64_t *__restrict__ key,
+                                                      const uint32_t *__restrict__ idx,
+                                                      float4 *__restrict__ spos, float4 *__restrict__ sloc,
+                                                      uint16_t *__restrict__ ssub) {
+    const int64_t s = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const uint64_t kw = key[s];
+    const uint64_t k = kPacked ? kw >> ib : kw;
+    const uint32_t o = kPacked ? (uint32_t)(kw & ((1ull << ib) - 1ull)) : idx[s];
+    const uint32_t nsub = (uint32_t)(g.ksub * g.ksub * g.ksub);
+    const uint32_t c = (uint32_t)(k / nsub);
+    const uint32_t sub = (uint32_t)(k - (uint64_t)c * nsub);
+    const float x = pos[3 * (int64_t)o + 0], y = pos[3 * (int64_t)o + 1], z = pos[3 * (int64_t)o + 2];
+    spos[s] = make_float4(x, y, z, __uint_as_float(o));
+    const uint32_t nc = (uint32_t)g.nc;
+    const uint32_t cx = c % nc, cy = (c / nc) % nc, cz = c / (nc * nc);
+    const float xl = (float)(((double)x - (double)cx * g.cell) * g.inv_b);
+    const float yl = (float)(((double)y - (double)cy * g.cell) * g.inv_b);
+    const float zl = (float)(((double)z - (double)cz * g.cell) * g.inv_b);
+    sloc[s] = make_float4(xl, yl, zl, __uint_as_float(c));
+    ssub[s] = (uint16_t)sub;
+}
+
+// Cell offsets: off[c] = first sorted particle of cell c (the next cell's
+// start when c is empty), off[ncell] = n.  With C(s) = cell of slot s,
+// C(-1) = -1 and C(n) = ncell, slot s owns the cells (C(s-1), C(s)].  Each
+// wavefront takes 64 consecutive slots (the last one slot n), numbers the
+// cells they own 0..G-1 by a prefix sum of the gaps, and writes them with
+// consecutive lanes on consecutive cells; the owner of cell q is the last slot
+// whose prefix is <= q (binary search over the 64 prefixes in LDS).
+__global__ __launch_bounds__(kBlock) void k_cell_offsets(int64_t n, int64_t ncell,
+                                                         const float4 *__restrict__ sloc,
+                                                         uint32_t *__restrict__ off) {
+    __shared__ int64_t pre[kBlock / 64][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t s0 = ((int64_t)blockIdx.x * (kBlock / 64) + w) * 64;
+    if (s0 > n) return;  // whole wavefront past slot n (uniform)
+    const int64_t s = s0 + lane;
+    auto C = [&](int64_t q) -> int64_t {
+        return q < 0 ? -1 : (q >= n ? ncell : (int64_t)__float_as_uint(sloc[q].w));
+    };
+    const int64_t hi = s <= n ? C(s) : ncell;
+    const int64_t lo = s <= n ? C(s - 1) : ncell;
+    int64_t g = hi - lo;  // cells owned by this slot
+    // inclusive prefix over the wavefront
+    int64_t incl = g;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int64_t y = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += y;
+    }
+    pre[w][lane] = incl - g;  // exclusive prefix
+    const int64_t G = __shfl(incl, 63, 64);
+    const int64_t first = __shfl(lo, 0, 64) + 1;  // first cell owned by the wavefront
+    // each wavefront reads only its own row, written above by the same
+    // wavefront (LDS operations of a wavefront complete in order)
+    __builtin_amdgcn_wave_barrier();
+    for (int64_t q = lane; q < G; q += 64) {
+        int a = 0, b = 63;  // last j with pre[j] <= q
+        while (a < b) {
+            const int mid = (a + b + 1) >> 1;
+            if (pre[w][mid] <= q) a = mid;
+            else b = mid - 1;
+        }
+        off[first + q] = (uint32_t)(s0 + a);
+    }
 }
 
 // Flags per sorted particle: head of a dense chunk, head of a dense cell, sparse.
@@ -181,16 +321,70 @@ __global__ __launch_bounds__(kBlock) void k_sub_fix(int64_t ndc, int nsub, uint3
 
 }  // namespace
 
+int bit_width(uint64_t x) {
+    int b = 0;
+    while (b < 64 && (x >> b)) b++;
+    return b;
+}
+
+// Radix pass plan: key bits, index bits when packed (0 = separate payload).
+struct RadixPlan {
+    int passes, D, ib;
+};
+
+RadixPlan radix_plan(int64_t n, const Geo &g) {
+    const uint64_t nkeys = (uint64_t)g.nc * g.nc * g.nc * (uint64_t)(g.ksub * g.ksub * g.ksub);
+    int bits = bit_width(nkeys - 1);
+    if (bits < 1) bits = 1;
+    RadixPlan r;
+    r.passes = (bits + kRadixMaxBits - 1) / kRadixMaxBits;
+    r.D = (bits + r.passes - 1) / r.passes;
+    int ib = bit_width((uint64_t)(n > 1 ? n - 1 : 1));
+    r.ib = ib + bits <= 64 ? ib : 0;
+    // HF_RADIX_PAYLOAD=1 forces the separate-payload form (used by tests; it
+    // is otherwise taken only when key and index need more than 64 bits)
+    const char *force = getenv("HF_RADIX_PAYLOAD");
+    if (force && force[0] == '1') r.ib = 0;
+    return r;
+}
+
+int64_t radix_hist_len(int64_t n, const Geo &g) {
+    const RadixPlan r = radix_plan(n, g);
+    const int64_t ntiles = (n + kTile - 1) / kTile;
+    return ((int64_t)1 << r.D) * (ntiles > 0 ? ntiles : 1) + 1;
+}
+
 void launch_bin(const float *pos, int64_t n, const Geo &g, Work &w, hipStream_t s) {
-    int64_t ncell = (int64_t)g.nc * g.nc * g.nc;
-    fill_u32(w.cnt, 0u, ncell, s);
-    hipLaunchKernelGGL(k_bin_key, dim3(blocks(n)), dim3(kBlock), 0, s, pos, n, g, w.key, w.ticket,
-                       w.subk, w.cnt, w.err);
-    scan_u32(w.cnt, w.off, ncell, w.scan_tmp, s);
-    hipLaunchKernelGGL(k_bin_scatter, dim3(blocks(n)), dim3(kBlock), 0, s, n, w.key, w.ticket, w.subk,
-                       w.off, w.tmp);
-    hipLaunchKernelGGL(k_bin_stable, dim3(blocks(n)), dim3(kBlock), 0, s, pos, n, g, w.key, w.off,
-                       w.tmp, w.spos, w.sloc, w.ssub);
+    const int64_t ncell = (int64_t)g.nc * g.nc * g.nc;
+    const RadixPlan r = radix_plan(n, g);
+    const bool packed = r.ib > 0;
+    hipLaunchKernelGGL(k_bin_key, dim3(blocks(n)), dim3(kBlock), 0, s, pos, n, g, r.ib, w.rkey[0], w.err);
+    const int64_t ntiles = (n + kTile - 1) / kTile;
+    const int64_t hl = ((int64_t)1 << r.D) * ntiles;
+    int cur = 0;
+    for (int p = 0; p < r.passes; p++) {
+        const int shift = r.ib + p * r.D;
+        hipLaunchKernelGGL(k_radix_count, dim3((unsigned)ntiles), dim3(256), 0, s, w.rkey[cur], n, shift, r.D,
+                           ntiles, w.rhist);
+        scan_u32(w.rhist, w.rscan, hl, w.scan_tmp, s);
+        if (packed)
+            hipLaunchKernelGGL(k_radix_scatter<true>, dim3((unsigned)ntiles), dim3(256), 0, s, w.rkey[cur],
+                               nullptr, n, shift, r.D, ntiles, w.rscan, w.rkey[cur ^ 1], nullptr);
+        else
+            hipLaunchKernelGGL(k_radix_scatter<false>, dim3((unsigned)ntiles), dim3(256), 0, s, w.rkey[cur],
+                               p == 0 ? nullptr : w.rval[cur], n, shift, r.D, ntiles, w.rscan,
+                               w.rkey[cur ^ 1], w.rval[cur ^ 1]);
+        cur ^= 1;
+    }
+    if (packed)
+        hipLaunchKernelGGL(k_bin_place<true>, dim3(blocks(n)), dim3(kBlock), 0, s, pos, n, g, r.ib, w.rkey[cur],
+                           nullptr, w.spos, w.sloc, w.ssub);
+    else
+        hipLaunchKernelGGL(k_bin_place<false>, dim3(blocks(n)), dim3(kBlock), 0, s, pos, n, g, 0, w.rkey[cur],
+                           w.rval[cur], w.spos, w.sloc, w.ssub);
+    // slots 0..n (slot n closes the grid): one wavefront per 64
+    hipLaunchKernelGGL(k_cell_offsets, dim3((unsigned)((n + 1 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n,
+                       ncell, w.sloc, w.off);
     hipLaunchKernelGGL(k_bin_flags, dim3(blocks(n)), dim3(kBlock), 0, s, n, w.sloc, w.off, w.f_chunk,
                        w.f_dcell, w.f_sparse);
     scan_u32(w.f_chunk, w.s_chunk, n, w.scan_tmp, s);

@@ -236,8 +236,8 @@ __global__ __launch_bounds__(kBlock) void k_gather_density(int64_t n, const floa
 
 void launch_density(int64_t n, const Geo &g, Work &w, float *dens_out, hipStream_t s) {
     // dfx: dense-neighbour sums of the sparse particles (fixed point), in the
-    // key/slot scratch that binning no longer needs
-    uint64_t *dfx = w.tmp;
+    // radix key array that binning no longer needs
+    uint64_t *dfx = w.rkey[0];
     if (w.nsparse > 0) fill_u32(reinterpret_cast<uint32_t *>(dfx), 0u, 2 * w.nsparse, s);
     if (w.nchunks > 0)
         hipLaunchKernelGGL(k_density_dense, dim3((unsigned)((w.nchunks + 3) / 4)), dim3(kBlock), 0, s,

@@ -128,15 +128,17 @@ struct Carver {
     }
 };
 
-size_t carve(char *base, int64_t n, int64_t ncell, int nsub, Work *w) {
+size_t carve(char *base, int64_t n, int64_t ncell, int nsub, int64_t rhl, Work *w) {
     Carver c{base};
     int64_t n1 = n + 1;
-    w->key = c.take<uint32_t>(n);
-    w->ticket = c.take<uint32_t>(n);
     w->cnt = c.take<uint32_t>(ncell + 1);
     w->off = c.take<uint32_t>(ncell + 1);
-    w->tmp = c.take<uint64_t>(n);
-    w->subk = c.take<uint16_t>(n);
+    w->rkey[0] = c.take<uint64_t>(n);
+    w->rkey[1] = c.take<uint64_t>(n);
+    w->rval[0] = c.take<uint32_t>(n);
+    w->rval[1] = c.take<uint32_t>(n);
+    w->rhist = c.take<uint32_t>(rhl);
+    w->rscan = c.take<uint32_t>(rhl);
     w->ssub = c.take<uint16_t>(n);
     w->spos = c.take<float4>(n);
     w->sloc = c.take<float4>(n);
@@ -184,7 +186,9 @@ size_t carve(char *base, int64_t n, int64_t ncell, int nsub, Work *w) {
     w->tflag = c.take<uint32_t>(n1);
     w->tpos = c.take<uint32_t>(n1);
     w->hist = c.take<uint32_t>(2 * n1);
-    w->scan_tmp = c.take<uint32_t>(hf::scan_tmp_words((ncell > n ? ncell : n) + 1));
+    int64_t scan_len = ncell > n ? ncell : n;
+    if (rhl > scan_len) scan_len = rhl;
+    w->scan_tmp = c.take<uint32_t>(hf::scan_tmp_words(scan_len + 1));
     w->counters = c.take<int32_t>(16);
     w->err = c.take<int32_t>(4);
     return c.off + 256;
@@ -193,7 +197,8 @@ size_t carve(char *base, int64_t n, int64_t ncell, int nsub, Work *w) {
 hf_status prepare(Lane *c, int64_t n, const Geo &g, Work *w) {
     int64_t ncell = (int64_t)g.nc * g.nc * g.nc;
     const int nsub = g.ksub * g.ksub * g.ksub;
-    size_t need = carve(nullptr, n, ncell, nsub, w);
+    const int64_t rhl = hf::radix_hist_len(n, g);
+    size_t need = carve(nullptr, n, ncell, nsub, rhl, w);
     HIP_OK(c, hipSetDevice(c->device));
     if (need > c->arena_bytes) {
         if (c->arena) {
@@ -210,7 +215,7 @@ hf_status prepare(Lane *c, int64_t n, const Geo &g, Work *w) {
         }
         c->arena_bytes = want;
     }
-    carve((char *)c->arena, n, ncell, nsub, w);
+    carve((char *)c->arena, n, ncell, nsub, rhl, w);
     c->stats = hf_stats{};
     c->stats.n_cells = ncell;
     return HF_OK;
@@ -368,7 +373,7 @@ size_t lane_arena_bytes(const hf_params *p, int64_t n) {
     Work w;
     if (make_geo(nullptr, p, n, &g) != HF_OK) return 0;
     const int64_t ncell = (int64_t)g.nc * g.nc * g.nc;
-    const size_t need = carve(nullptr, n, ncell, g.ksub * g.ksub * g.ksub, &w);
+    const size_t need = carve(nullptr, n, ncell, g.ksub * g.ksub * g.ksub, hf::radix_hist_len(n, g), &w);
     return need + need / 8;
 }
 

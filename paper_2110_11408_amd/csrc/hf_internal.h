@@ -130,9 +130,11 @@ __device__ __forceinline__ int32_t wave_run_min(int32_t v, const WaveRun &r) {
 // --------------------------------------------------------------- workspace
 struct Work {
     // binning
-    uint32_t *key, *ticket, *cnt, *off;
-    uint64_t *tmp;
-    uint16_t *subk, *ssub;
+    uint32_t *cnt, *off;             // cnt: cell -> dense-cell ordinal (dense cells only)
+    uint64_t *rkey[2];               // radix sort keys (ping-pong); rkey[0] is reused after binning
+    uint32_t *rval[2];               // radix sort payload: original index
+    uint32_t *rhist, *rscan;         // per-pass [digit][tile] counts and their scan
+    uint16_t *ssub;
     float4 *spos, *sloc;
     // work decomposition (dense chunks, dense cells, sparse particles)
     uint32_t *f_chunk, *s_chunk, *f_dcell, *s_dcell, *f_sparse, *s_sparse;
@@ -168,6 +170,8 @@ void scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipSt
 int64_t scan_tmp_words(int64_t n);
 
 void launch_bin(const float *pos, int64_t n, const Geo &g, Work &w, hipStream_t s);
+// Length of the radix count arrays for n particles on grid g.
+int64_t radix_hist_len(int64_t n, const Geo &g);
 void launch_subtab(int64_t n, int64_t ndc, const Geo &g, Work &w, hipStream_t s);
 void launch_density(int64_t n, const Geo &g, Work &w, float *dens_out, hipStream_t s);
 void launch_count_pairs(int64_t n, const Geo &g, Work &w, unsigned long long *total, hipStream_t s);

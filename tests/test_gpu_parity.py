@@ -266,3 +266,21 @@ def test_full_size_256(ctx):
     np.testing.assert_array_equal(tab["id"][in_pick], res["table"]["id"])
     np.testing.assert_array_equal(tab["n"][in_pick], res["table"]["n"])
     np.testing.assert_array_equal(tab["n_enclosed"][in_pick], res["table"]["ienc"])
+
+
+def test_separate_payload_sort_gives_same_result(ctx):
+    """The binning's radix sort keeps the original index in the key word when
+    both fit in 64 bits, else in a payload array; both forms give one result."""
+    import os
+    pos, L, _ = _case("s40123")
+    a = gpu_find(ctx, pos, box=L)
+    os.environ["HF_RADIX_PAYLOAD"] = "1"
+    try:
+        b = gpu_find(ctx, pos, box=L)
+    finally:
+        del os.environ["HF_RADIX_PAYLOAD"]
+    np.testing.assert_array_equal(a["density"], b["density"])
+    assert_same_labels(a, {"l0": b["l0"], "halo_id": b["halo_id"], "n_halos": b["n_halos"],
+                           "table": {"id": b["table"]["id"], "nucleus": b["table"]["nucleus"],
+                                     "l0": b["table"]["l0_id"], "n": b["table"]["n"],
+                                     "ienc": b["table"]["n_enclosed"]}})
