@@ -78,33 +78,6 @@ __device__ __forceinline__ bool linked(float xs, float ys, float zs, const float
     return d2_exact(pa, spos[b], g.L, g.half) < g.l2;
 }
 
-__global__ __launch_bounds__(kBlock) void k_fof_init(int64_t n, Geo g, const float *__restrict__ dens_s,
-                                                     int32_t *__restrict__ parent) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    parent[i] = is_member(dens_s, i, g.dl0) ? (int32_t)i : -1;
-}
-
-// Phase A: members of dense cells point at the first member of their sub-cell
-// (a valid forest: every parent is a member with a smaller sorted index).
-__global__ __launch_bounds__(kBlock) void k_fof_phase_a(int64_t n, Geo g, const float4 *__restrict__ sloc,
-                                                        const uint32_t *__restrict__ off,
-                                                        const uint16_t *__restrict__ ssub,
-                                                        const uint32_t *__restrict__ cellmap,
-                                                        const uint32_t *__restrict__ subtab,
-                                                        const float *__restrict__ dens_s,
-                                                        int32_t *__restrict__ parent) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    if (!is_member(dens_s, i, g.dl0)) return;
-    const uint32_t c = __float_as_uint(sloc[i].w);
-    if (off[c + 1] - off[c] < (uint32_t)kDenseMin) return;
-    const int nsub = g.ksub * g.ksub * g.ksub;
-    uint32_t f = subtab[(int64_t)cellmap[c] * (nsub + 1) + ssub[i]];
-    while (f < (uint32_t)i && !is_member(dens_s, f, g.dl0)) f++;
-    parent[i] = (int32_t)f;
-}
-
 // Join the lanes linked to a member of the set rj (rj: any node of that set)
 // to that set; every lane keeps the root of its own set in wr.  Returns the
 // root of the joined set.
@@ -135,14 +108,99 @@ __device__ __forceinline__ int join_lanes(int32_t *parent, bool lk, int &wr, int
     return rj;
 }
 
+// Friends test from FP32 differences already taken in one frame (dx = x_b - x_a):
+// FP32 prefilter, canonical FP64 distance of the original positions in the
+// undecided band.
+__device__ __forceinline__ bool linked_d(float dx, float dy, float dz, const float4 &pa,
+                                         const float4 *__restrict__ spos, uint32_t b, const Geo &g) {
+    const float d2f = dx * dx + dy * dy + dz * dz;
+    if (d2f >= g.l2b_hi) return false;
+    if (d2f < g.l2b_lo) return true;
+    return d2_exact(pa, spos[b], g.L, g.half) < g.l2;
+}
+
+// Joins the members j of [a, b) (a neighbour range at stencil offset
+// (ox, oy, oz) from the chunk's cell) to the lanes they link.  The range is
+// loaded 64 particles at a time, one per lane (membership, coordinates moved
+// into the chunk's frame, root hint); its members are then broadcast in
+// order.  With `one_set` the range is known to be a single set: it stops as
+// soon as every lane is in that set.  Returns whether any join was made.
+__device__ __forceinline__ bool stream_range(int32_t *parent, const float *__restrict__ dens_s,
+                                             const float4 *__restrict__ sloc,
+                                             const float4 *__restrict__ spos, const Geo &g, bool active,
+                                             const float4 &li, const float4 &pi, int &wr, uint32_t a,
+                                             uint32_t b, int ox, int oy, int oz, bool one_set, int rset) {
+    const int lane = threadIdx.x & 63;
+    bool joined = false;
+    for (uint32_t jb = a; jb < b; jb += 64) {
+        const uint32_t j = jb + (uint32_t)lane;
+        const bool mem = j < b && is_member(dens_s, j, g.dl0);
+        float xj = 0.0f, yj = 0.0f, zj = 0.0f;
+        int rj = -1;
+        if (mem) {
+            const float4 lj = sloc[j];
+            xj = lj.x + (float)ox * g.cellb;
+            yj = lj.y + (float)oy * g.cellb;
+            zj = lj.z + (float)oz * g.cellb;
+            rj = one_set ? rset : uf_find_hint(parent, (int)j);
+        }
+        uint64_t mm = __ballot(mem);
+        while (mm) {
+            const int J = __ffsll((unsigned long long)mm) - 1;
+            mm &= mm - 1;
+            int r = __shfl(one_set ? rset : rj, J, 64);
+            if (!__ballot(active && wr != r)) continue;
+            const float dx = __shfl(xj, J, 64) - li.x, dy = __shfl(yj, J, 64) - li.y,
+                        dz = __shfl(zj, J, 64) - li.z;
+            const bool lk = active && wr != r && linked_d(dx, dy, dz, pi, spos, jb + (uint32_t)J, g);
+            if (!__ballot(lk)) continue;
+            r = join_lanes(parent, lk, wr, r);
+            joined = true;
+            if (one_set) {
+                rset = r;
+                if (!__ballot(active && wr != rset)) return true;
+            }
+        }
+    }
+    return joined;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fof_init(int64_t n, Geo g, const float *__restrict__ dens_s,
+                                                     int32_t *__restrict__ parent) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    parent[i] = is_member(dens_s, i, g.dl0) ? (int32_t)i : -1;
+}
+
+// Phase A: members of dense cells point at the first member of their sub-cell
+// (a valid forest: every parent is a member with a smaller sorted index).
+__global__ __launch_bounds__(kBlock) void k_fof_phase_a(int64_t n, Geo g, const float4 *__restrict__ sloc,
+                                                        const uint32_t *__restrict__ off,
+                                                        const uint16_t *__restrict__ ssub,
+                                                        const uint32_t *__restrict__ cellmap,
+                                                        const uint32_t *__restrict__ subtab,
+                                                        const float *__restrict__ dens_s,
+                                                        int32_t *__restrict__ parent) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (!is_member(dens_s, i, g.dl0)) return;
+    const uint32_t c = __float_as_uint(sloc[i].w);
+    if (off[c + 1] - off[c] < (uint32_t)kDenseMin) return;
+    const int nsub = g.ksub * g.ksub * g.ksub;
+    uint32_t f = subtab[(int64_t)cellmap[c] * (nsub + 1) + ssub[i]];
+    while (f < (uint32_t)i && !is_member(dens_s, f, g.dl0)) f++;
+    parent[i] = (int32_t)f;
+}
+
 // Dense chunks, one wavefront each (lanes = the chunk's particles).  The wave
 // visits the neighbour cells that come within l of some lane: sparse cells in
 // all 26 directions, dense cells only in the forward half (the backward ones
 // visit this cell themselves), and its own cell from the chunk start on.
-// Sparse cells are streamed particle by particle.  In a dense cell the lanes
-// first look at all sub-cells at once (one per lane): its range, first member
-// and that member's parent; a sub-cell already in the set every lane belongs
-// to is skipped (all its members are one set), and the others are streamed as
+// The 27 cell ranges are loaded at once (one stencil cell per lane); sparse
+// cells are then streamed particle by particle.  The sub-cells of all visited
+// dense cells are examined 64 at a time (one per lane): range, first member and
+// that member's parent; a sub-cell already in the set every lane belongs to is
+// skipped (all its members are one set), and the others are streamed as
 // wave-uniform scalar loads and joined to the lanes they link.
 __global__ __launch_bounds__(kBlock) void k_fof_dense(int64_t nchunks, Geo g,
                                                       const int32_t *__restrict__ chunks,
@@ -153,6 +211,8 @@ __global__ __launch_bounds__(kBlock) void k_fof_dense(int64_t nchunks, Geo g,
                                                       const uint32_t *__restrict__ subtab,
                                                       const float *__restrict__ dens_s,
                                                       int32_t *parent) {
+    __shared__ int64_t dbase[kBlock / 64][27];  // visited dense cells: sub-table base
+    __shared__ int8_t doff[kBlock / 64][27];    // and stencil index
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t q = (int64_t)xcd_block() * (kBlock / 64) + wave;
     if (q >= nchunks) return;
@@ -172,6 +232,49 @@ __global__ __launch_bounds__(kBlock) void k_fof_dense(int64_t nchunks, Geo g,
     const float subb = g.cellb / (float)k;
     const int cx = (int)(c % (uint32_t)nc), cy = (int)((c / (uint32_t)nc) % (uint32_t)nc),
               cz = (int)(c / ((uint32_t)nc * (uint32_t)nc));
+    // stencil cells within reach of some lane: bit t for offset
+    // (t % 3 - 1, t / 3 % 3 - 1, t / 9 - 1)
+    uint32_t reach = 0;
+    for (int t = 0; t < 27; t++) {
+        const int ox = t % 3 - 1, oy = (t / 3) % 3 - 1, oz = t / 9 - 1;
+        const float gx = ox < 0 ? li.x : (ox > 0 ? g.cellb - li.x : 0.0f);
+        const float gy = oy < 0 ? li.y : (oy > 0 ? g.cellb - li.y : 0.0f);
+        const float gz = oz < 0 ? li.z : (oz > 0 ? g.cellb - li.z : 0.0f);
+        if (__ballot(active && gx * gx + gy * gy + gz * gz < g.l2b_hi)) reach |= 1u << t;
+    }
+    // one stencil cell per lane: its range
+    const int tl = lane < 27 ? lane : 13;
+    const int lx = tl % 3 - 1, ly = (tl / 3) % 3 - 1, lz = tl / 9 - 1;
+    const uint32_t nbl = ((uint32_t)wrapc(cz + lz, nc) * (uint32_t)nc + (uint32_t)wrapc(cy + ly, nc)) *
+                             (uint32_t)nc + (uint32_t)wrapc(cx + lx, nc);
+    const bool lreach = lane < 27 && ((reach >> lane) & 1u);
+    uint32_t la = 0, lb = 0;
+    if (lreach) {
+        la = off[nbl];
+        lb = off[nbl + 1];
+    }
+    const bool ldense = lb - la >= (uint32_t)kDenseMin;
+    const bool lforward = lz > 0 || (lz == 0 && (ly > 0 || (ly == 0 && lx >= 0)));  // own cell included
+    const bool lvisit = lreach && ldense && lforward;
+    if (lvisit) {
+        const uint64_t vm = __ballot(lvisit);
+        const int slot = __popcll(vm & ((1ull << lane) - 1ull));
+        dbase[wave][slot] = (int64_t)cellmap[nbl] * (nsub + 1);
+        doff[wave][slot] = (int8_t)lane;
+    }
+    const uint64_t visit = __ballot(lvisit);
+    const int nvisit = __popcll(visit);
+    // sparse neighbour cells, 64 particles at a time
+    uint64_t sm = __ballot(lreach && !ldense && lb > la);
+    while (sm) {
+        const int t = __ffsll((unsigned long long)sm) - 1;
+        sm &= sm - 1;
+        const uint32_t a = (uint32_t)__shfl((int)la, t, 64), b = (uint32_t)__shfl((int)lb, t, 64);
+        stream_range(parent, dens_s, sloc, spos, g, active, li, pi, wr, a, b, t % 3 - 1, (t / 3) % 3 - 1,
+                     t / 9 - 1, false, -1);
+    }
+    if (nvisit == 0) return;
+    __builtin_amdgcn_wave_barrier();
     // chunk bounding box (active lanes), for sub-cell reach tests
     float bx0 = active ? li.x : 1e30f, by0 = active ? li.y : 1e30f, bz0 = active ? li.z : 1e30f;
     float bx1 = active ? li.x : -1e30f, by1 = active ? li.y : -1e30f, bz1 = active ? li.z : -1e30f;
@@ -183,91 +286,63 @@ __global__ __launch_bounds__(kBlock) void k_fof_dense(int64_t nchunks, Geo g,
         by1 = fmaxf(by1, __shfl_xor(by1, d, 64));
         bz1 = fmaxf(bz1, __shfl_xor(bz1, d, 64));
     }
-    for (int oz = -1; oz <= 1; oz++) {
-        const float zs = li.z - (float)oz * g.cellb;
-        for (int oy = -1; oy <= 1; oy++) {
-            const float ys = li.y - (float)oy * g.cellb;
-            for (int ox = -1; ox <= 1; ox++) {
-                const float gx = ox < 0 ? li.x : (ox > 0 ? g.cellb - li.x : 0.0f);
-                const float gy = oy < 0 ? li.y : (oy > 0 ? g.cellb - li.y : 0.0f);
-                const float gz = oz < 0 ? li.z : (oz > 0 ? g.cellb - li.z : 0.0f);
-                if (!__ballot(active && gx * gx + gy * gy + gz * gz < g.l2b_hi)) continue;
-                const uint32_t nb = ((uint32_t)wrapc(cz + oz, nc) * (uint32_t)nc + (uint32_t)wrapc(cy + oy, nc)) *
-                                        (uint32_t)nc + (uint32_t)wrapc(cx + ox, nc);
-                const uint32_t a = (uint32_t)__builtin_amdgcn_readfirstlane(off[nb]);
-                const uint32_t b = (uint32_t)__builtin_amdgcn_readfirstlane(off[nb + 1]);
-                const bool own = ox == 0 && oy == 0 && oz == 0;
-                const bool forward = oz > 0 || (oz == 0 && (oy > 0 || (oy == 0 && ox > 0)));
-                const bool dense_nb = b - a >= (uint32_t)kDenseMin;
-                const float xs = li.x - (float)ox * g.cellb;
-                if (!dense_nb) {
-                    for (uint32_t j = a; j < b; j++) {
-                        if (!is_member(dens_s, j, g.dl0)) continue;
-                        const bool lk = active && linked(xs, ys, zs, pi, sloc, spos, j, g);
-                        if (!__ballot(lk)) continue;
-                        join_lanes(parent, lk, wr, uf_find_hint(parent, (int)j));
+    // (visited dense cell, sub-cell) pairs, 64 at a time
+    const int ntask = nvisit * nsub;
+    for (int t0 = 0; t0 < ntask; t0 += 64) {
+        const int tq = t0 + lane;
+        uint32_t u0 = 0, u1 = 0;
+        int fs = -1, st = 0;
+        if (tq < ntask) {
+            const int r = tq / nsub, sl = tq - r * nsub;
+            st = doff[wave][r];
+            const int64_t base = dbase[wave][r];
+            const int ox = st % 3 - 1, oy = (st / 3) % 3 - 1, oz = st / 9 - 1;
+            u0 = subtab[base + sl];
+            u1 = subtab[base + sl + 1];
+            if (st == 13 && u0 < h) u0 = h;  // own cell: from the chunk start on
+            const int sx = sl % k, sy = (sl / k) % k, sz = sl / (k * k);
+            // sub-cell box (neighbour frame) shifted into the chunk's frame
+            const float ex = fmaxf(fmaxf(sx * subb + (float)ox * g.cellb - bx1,
+                                         bx0 - ((sx + 1) * subb + (float)ox * g.cellb)), 0.0f);
+            const float ey = fmaxf(fmaxf(sy * subb + (float)oy * g.cellb - by1,
+                                         by0 - ((sy + 1) * subb + (float)oy * g.cellb)), 0.0f);
+            const float ez = fmaxf(fmaxf(sz * subb + (float)oz * g.cellb - bz1,
+                                         bz0 - ((sz + 1) * subb + (float)oz * g.cellb)), 0.0f);
+            if (ex * ex + ey * ey + ez * ez < g.l2b_hi + 1e-4f) {
+                for (uint32_t j = u0; j < u1; j++)
+                    if (is_member(dens_s, j, g.dl0)) {
+                        fs = (int)j;
+                        break;
                     }
-                    continue;
-                }
-                if (!own && !forward) continue;
-                // one sub-cell per lane (in batches of 64): range, first member,
-                // parent hint, reach
-                const int64_t base = (int64_t)__builtin_amdgcn_readfirstlane(cellmap[nb]) * (nsub + 1);
-                for (int s0 = 0; s0 < nsub; s0 += 64) {
-                    const int sl = s0 + lane;
-                    uint32_t u0 = 0, u1 = 0;
-                    int fs = -1, ps = -1;
-                    if (sl < nsub) {
-                        u0 = subtab[base + sl];
-                        u1 = subtab[base + sl + 1];
-                        if (own && u0 < h) u0 = h;
-                        const int sx = sl % k, sy = (sl / k) % k, sz = sl / (k * k);
-                        // sub-cell box (neighbour frame) shifted into the chunk's frame
-                        const float ex = fmaxf(fmaxf(sx * subb + (float)ox * g.cellb - bx1,
-                                                     bx0 - ((sx + 1) * subb + (float)ox * g.cellb)), 0.0f);
-                        const float ey = fmaxf(fmaxf(sy * subb + (float)oy * g.cellb - by1,
-                                                     by0 - ((sy + 1) * subb + (float)oy * g.cellb)), 0.0f);
-                        const float ez = fmaxf(fmaxf(sz * subb + (float)oz * g.cellb - bz1,
-                                                     bz0 - ((sz + 1) * subb + (float)oz * g.cellb)), 0.0f);
-                        if (ex * ex + ey * ey + ez * ez < g.l2b_hi + 1e-4f) {
-                            for (uint32_t j = u0; j < u1; j++)
-                                if (is_member(dens_s, j, g.dl0)) {
-                                    fs = (int)j;
-                                    break;
-                                }
-                            if (fs >= 0) ps = parent[fs];
-                        }
-                    }
-                    // the set shared by every active lane, if there is one
-                    const uint64_t am = __ballot(active);
-                    const int w0 = __shfl(wr, __ffsll((unsigned long long)am) - 1, 64);
-                    const int wcommon = __ballot(active && wr != w0) ? -2 : w0;
-                    uint64_t todo = __ballot(fs >= 0 && ps != wcommon);
-                    while (todo) {
-                        const int S = __ffsll((unsigned long long)todo) - 1;
-                        todo &= todo - 1;
-                        const int f = __shfl(fs, S, 64);
-                        const uint32_t e = (uint32_t)__shfl((int)u1, S, 64);
-                        int rS = uf_find_hint(parent, f);
-                        if (!__ballot(active && wr != rS)) continue;
-                        for (uint32_t j = (uint32_t)f; j < e; j++) {
-                            if (!is_member(dens_s, j, g.dl0)) continue;
-                            const bool lk = active && wr != rS && linked(xs, ys, zs, pi, sloc, spos, j, g);
-                            if (!__ballot(lk)) continue;
-                            rS = join_lanes(parent, lk, wr, rS);
-                            // the rest of the sub-cell is one set with it: done once
-                            // every lane is in that set
-                            if (!__ballot(active && wr != rS)) break;
-                        }
-                    }
-                }
             }
+        }
+        // root hints of all sub-cells at once; a sub-cell whose set is the one
+        // every active lane belongs to needs nothing
+        int rL = fs >= 0 ? uf_find_hint(parent, fs) : -1;
+        const uint64_t am = __ballot(active);
+        for (;;) {
+            const int w0 = __shfl(wr, __ffsll((unsigned long long)am) - 1, 64);
+            const int wcommon = __ballot(active && wr != w0) ? -2 : w0;
+            const uint64_t todo = __ballot(fs >= 0 && rL != wcommon);
+            if (!todo) break;
+            const int S = __ffsll((unsigned long long)todo) - 1;
+            const int f = __shfl(fs, S, 64);
+            const uint32_t e = (uint32_t)__shfl((int)u1, S, 64);
+            const int sts = __shfl(st, S, 64);
+            const int rS = __shfl(rL, S, 64);
+            if (lane == S) fs = -1;  // done with it
+            if (!__ballot(active && wr != rS)) continue;
+            const bool joined = stream_range(parent, dens_s, sloc, spos, g, active, li, pi, wr, (uint32_t)f, e,
+                                             sts % 3 - 1, (sts / 3) % 3 - 1, sts / 9 - 1, true, rS);
+            // after a join the remaining hints may be stale: refresh them
+            if (joined && fs >= 0) rL = uf_find_hint(parent, fs);
         }
     }
 }
 
 // Members of sparse cells: links to the later members of sparse neighbour
-// cells (pairs with dense cells are found by the dense chunks).
+// cells (pairs with dense cells are found by the dense chunks).  The offsets
+// of a stencil plane are loaded together.
 __global__ __launch_bounds__(kBlock) void k_fof_sparse(int64_t nsparse, Geo g,
                                                        const int32_t *__restrict__ sparse,
                                                        const float4 *__restrict__ sloc,
@@ -285,20 +360,36 @@ __global__ __launch_bounds__(kBlock) void k_fof_sparse(int64_t nsparse, Geo g,
     const int nc = g.nc;
     const int cx = (int)(c % (uint32_t)nc), cy = (int)((c / (uint32_t)nc) % (uint32_t)nc),
               cz = (int)(c / ((uint32_t)nc * (uint32_t)nc));
+    const uint32_t x0 = (uint32_t)wrapc(cx - 1, nc), x1 = (uint32_t)cx, x2 = (uint32_t)wrapc(cx + 1, nc);
     int ri = uf_find_hint(parent, i);
     for (int oz = -1; oz <= 1; oz++) {
         const float zs = li.z - (float)oz * g.cellb;
+        const float gz = oz < 0 ? li.z : (oz > 0 ? g.cellb - li.z : 0.0f);
+        if (gz * gz >= g.l2b_hi) continue;
+        const int z = wrapc(cz + oz, nc);
+        uint32_t ra[9], rb[9];
+#pragma unroll
+        for (int oy = -1; oy <= 1; oy++) {
+            const uint32_t row = ((uint32_t)z * (uint32_t)nc + (uint32_t)wrapc(cy + oy, nc)) * (uint32_t)nc;
+            const int r = (oy + 1) * 3;
+            ra[r + 0] = off[row + x0];
+            rb[r + 0] = off[row + x0 + 1];
+            ra[r + 1] = off[row + x1];
+            rb[r + 1] = off[row + x1 + 1];
+            ra[r + 2] = off[row + x2];
+            rb[r + 2] = off[row + x2 + 1];
+        }
+#pragma unroll
         for (int oy = -1; oy <= 1; oy++) {
             const float ys = li.y - (float)oy * g.cellb;
+#pragma unroll
             for (int ox = -1; ox <= 1; ox++) {
+                const int r = (oy + 1) * 3 + (ox + 1);
                 const float gx = ox < 0 ? li.x : (ox > 0 ? g.cellb - li.x : 0.0f);
                 const float gy = oy < 0 ? li.y : (oy > 0 ? g.cellb - li.y : 0.0f);
-                const float gz = oz < 0 ? li.z : (oz > 0 ? g.cellb - li.z : 0.0f);
                 if (gx * gx + gy * gy + gz * gz >= g.l2b_hi) continue;
-                const uint32_t nb = ((uint32_t)wrapc(cz + oz, nc) * (uint32_t)nc + (uint32_t)wrapc(cy + oy, nc)) *
-                                        (uint32_t)nc + (uint32_t)wrapc(cx + ox, nc);
-                uint32_t a = off[nb];
-                const uint32_t b = off[nb + 1];
+                uint32_t a = ra[r];
+                const uint32_t b = rb[r];
                 if (b - a >= (uint32_t)kDenseMin) continue;
                 if (a <= (uint32_t)i) a = (uint32_t)i + 1;
                 const float xs = li.x - (float)ox * g.cellb;
