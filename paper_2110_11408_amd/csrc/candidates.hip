@@ -14,9 +14,13 @@ namespace hf {
 
 namespace {
 
-// Neighbour cell t of 27, own cell first.
+// Neighbour cell t of 27 in order of distance: own cell, the 6 face
+// neighbours, the 12 edge neighbours, the 8 corners.
+__constant__ int8_t kStencil[27] = {13, 4, 10, 12, 14, 16, 22, 1,  3,  5,  7,  9,  11, 15,
+                                    17, 19, 21, 23, 25, 0, 2,  6,  8,  18, 20, 24, 26};
+
 __device__ __forceinline__ void stencil_offset(int t, int &ox, int &oy, int &oz) {
-    const int u = t == 0 ? 13 : (t <= 13 ? t - 1 : t);
+    const int u = kStencil[t];
     ox = u % 3 - 1;
     oy = (u / 3) % 3 - 1;
     oz = u / 9 - 1;
@@ -121,10 +125,97 @@ __global__ __launch_bounds__(kBlock) void k_hard_list(int64_t n, const uint32_t 
     if (i < n && f_hard[i]) hard[s_hard[i]] = (int32_t)i;
 }
 
-// Stage 2, one thread per hard case: search the 27 neighbour cells (own cell
-// first).  In dense cells only sub-cells within b that hold a denser particle
-// are visited, their densest particle first.
-__global__ __launch_bounds__(kBlock) void k_cand_hard(const uint32_t *__restrict__ nhard_p, Geo g,
+// Whether particle i has a denser particle of its group within b in the
+// stencil cells tt0..tt1-1 (cell 0 of the order is its own).  In dense cells
+// only sub-cells within b that hold a denser particle are visited, their
+// densest particle first.
+__device__ bool has_denser_within_b(int i, int tt0, int tt1, const Geo &g, const float4 *__restrict__ sloc,
+                                    const float4 *__restrict__ spos, const uint32_t *__restrict__ off,
+                                    const uint32_t *__restrict__ cellmap, const uint32_t *__restrict__ subtab,
+                                    const uint64_t *__restrict__ submax, const int32_t *__restrict__ subarg,
+                                    const float *__restrict__ dens_s, const int32_t *__restrict__ gkey) {
+    const int key = gkey[i];
+    const float di = dens_s[i];
+    const float4 li = sloc[i];
+    const float4 pi = spos[i];
+    const uint32_t oi = orig_of(pi);
+    const uint64_t mykey = dkey(di, oi);
+    const uint32_t c = __float_as_uint(li.w);
+    const int nc = g.nc, k = g.ksub, nsub = k * k * k;
+    const float subb = g.cellb / (float)k;
+    const int cx = (int)(c % (uint32_t)nc), cy = (int)((c / (uint32_t)nc) % (uint32_t)nc),
+              cz = (int)(c / ((uint32_t)nc * (uint32_t)nc));
+    for (int tt = tt0; tt < tt1; tt++) {
+        int ox, oy, oz;
+        stencil_offset(tt, ox, oy, oz);
+        const float xs = li.x - (float)ox * g.cellb, ys = li.y - (float)oy * g.cellb,
+                    zs = li.z - (float)oz * g.cellb;
+        // nothing of this cell lies within b
+        const float gx = ox < 0 ? li.x : (ox > 0 ? g.cellb - li.x : 0.0f);
+        const float gy = oy < 0 ? li.y : (oy > 0 ? g.cellb - li.y : 0.0f);
+        const float gz = oz < 0 ? li.z : (oz > 0 ? g.cellb - li.z : 0.0f);
+        if (gx * gx + gy * gy + gz * gz >= g.b2b_hi) continue;
+        const uint32_t nb = ((uint32_t)wrapc(cz + oz, nc) * (uint32_t)nc + (uint32_t)wrapc(cy + oy, nc)) *
+                                (uint32_t)nc + (uint32_t)wrapc(cx + ox, nc);
+        const uint32_t a = off[nb], b = off[nb + 1];
+        if (b - a < (uint32_t)kDenseMin) {
+            // sparse cell: the densities first (all loads together), then the
+            // few denser ones in full
+            float dj[kDenseMin];
+#pragma unroll
+            for (int u = 0; u < kDenseMin; u++) dj[u] = a + u < b ? dens_s[a + u] : -1.0f;
+#pragma unroll
+            for (int u = 0; u < kDenseMin; u++) {
+                const uint32_t j = a + u;
+                if (dj[u] < di || (int)j == i) continue;
+                if (denser_within_b(j, dens_s, gkey, sloc, spos, key, di, oi, xs, ys, zs, pi, g)) return true;
+            }
+            continue;
+        }
+        const int64_t base = (int64_t)cellmap[nb] * (nsub + 1);
+        for (int s0 = 0; s0 < nsub; s0 += 9) {
+            // nine sub-cell maxima per round of loads
+            uint64_t mx[9];
+#pragma unroll
+            for (int u = 0; u < 9; u++) mx[u] = s0 + u < nsub ? submax[base + s0 + u] : 0ull;
+#pragma unroll
+            for (int u = 0; u < 9; u++) {
+                const int s2 = s0 + u;
+                if (!(mx[u] > mykey)) continue;
+                const int sx = s2 % k, sy = (s2 / k) % k, sz = s2 / (k * k);
+                const float ex = fmaxf(fmaxf(sx * subb - 1e-5f - xs, xs - (sx + 1) * subb - 1e-5f), 0.0f);
+                const float ey = fmaxf(fmaxf(sy * subb - 1e-5f - ys, ys - (sy + 1) * subb - 1e-5f), 0.0f);
+                const float ez = fmaxf(fmaxf(sz * subb - 1e-5f - zs, zs - (sz + 1) * subb - 1e-5f), 0.0f);
+                if (ex * ex + ey * ey + ez * ez >= g.b2b_hi) continue;
+                const int32_t top = subarg[base + s2];
+                if (denser_within_b(top, dens_s, gkey, sloc, spos, key, di, oi, xs, ys, zs, pi, g)) return true;
+                // the rest of the sub-cell: densities 16 at a time, then the
+                // denser ones in full
+                const uint32_t u1 = subtab[base + s2 + 1];
+                for (uint32_t j0 = subtab[base + s2]; j0 < u1; j0 += 16) {
+                    float dj[16];
+#pragma unroll
+                    for (int v = 0; v < 16; v++) dj[v] = j0 + v < u1 ? dens_s[j0 + v] : -1.0f;
+#pragma unroll
+                    for (int v = 0; v < 16; v++) {
+                        const uint32_t j = j0 + v;
+                        if (dj[v] < di || (int32_t)j == top || (int)j == i) continue;
+                        if (denser_within_b(j, dens_s, gkey, sloc, spos, key, di, oi, xs, ys, zs, pi, g))
+                            return true;
+                    }
+                }
+            }
+        }
+    }
+    return false;
+}
+
+// Stage 2, one thread per hard case, in two launches: the first searches the
+// particle's own cell, where a denser neighbour is nearly always found; the
+// cases left (mostly the actual candidates, which need the whole stencil) are
+// appended to a second list and searched in the 26 other cells, so that waves
+// are not held up by a few exhaustive searches.
+__global__ __launch_bounds__(kBlock) void k_cand_hard(const uint32_t *__restrict__ nhard_p, int stage, Geo g,
                                                       const int32_t *__restrict__ hard,
                                                       const float4 *__restrict__ sloc,
                                                       const float4 *__restrict__ spos,
@@ -137,55 +228,34 @@ __global__ __launch_bounds__(kBlock) void k_cand_hard(const uint32_t *__restrict
                                                       const int32_t *__restrict__ gkey,
                                                       const int32_t *__restrict__ gid_of,
                                                       uint32_t *__restrict__ gccnt,
-                                                      int32_t *__restrict__ cflag) {
-    const int64_t t = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)*nhard_p) return;
-    const int i = hard[t];
-    const int key = gkey[i];
-    const float di = dens_s[i];
-    const float4 li = sloc[i];
-    const float4 pi = spos[i];
-    const uint32_t oi = orig_of(pi);
-    const uint64_t mykey = dkey(di, oi);
-    const uint32_t c = __float_as_uint(li.w);
-    const int nc = g.nc, k = g.ksub, nsub = k * k * k;
-    const float subb = g.cellb / (float)k;
-    const int cx = (int)(c % (uint32_t)nc), cy = (int)((c / (uint32_t)nc) % (uint32_t)nc),
-              cz = (int)(c / ((uint32_t)nc * (uint32_t)nc));
-    for (int tt = 0; tt < 27; tt++) {
-        int ox, oy, oz;
-        stencil_offset(tt, ox, oy, oz);
-        const uint32_t nb = ((uint32_t)wrapc(cz + oz, nc) * (uint32_t)nc + (uint32_t)wrapc(cy + oy, nc)) *
-                                (uint32_t)nc + (uint32_t)wrapc(cx + ox, nc);
-        const float xs = li.x - (float)ox * g.cellb, ys = li.y - (float)oy * g.cellb,
-                    zs = li.z - (float)oz * g.cellb;
-        const uint32_t a = off[nb], b = off[nb + 1];
-        if (b - a < (uint32_t)kDenseMin) {
-            for (uint32_t j = a; j < b; j++) {
-                if ((int)j == i) continue;
-                if (denser_within_b(j, dens_s, gkey, sloc, spos, key, di, oi, xs, ys, zs, pi, g)) return;
-            }
-            continue;
-        }
-        const int64_t base = (int64_t)cellmap[nb] * (nsub + 1);
-        for (int s2 = 0; s2 < nsub; s2++) {
-            if (!(submax[base + s2] > mykey)) continue;
-            const int sx = s2 % k, sy = (s2 / k) % k, sz = s2 / (k * k);
-            const float gx = fmaxf(fmaxf(sx * subb - 1e-5f - xs, xs - (sx + 1) * subb - 1e-5f), 0.0f);
-            const float gy = fmaxf(fmaxf(sy * subb - 1e-5f - ys, ys - (sy + 1) * subb - 1e-5f), 0.0f);
-            const float gz = fmaxf(fmaxf(sz * subb - 1e-5f - zs, zs - (sz + 1) * subb - 1e-5f), 0.0f);
-            if (gx * gx + gy * gy + gz * gz >= g.b2b_hi) continue;
-            const int32_t top = subarg[base + s2];
-            if (denser_within_b(top, dens_s, gkey, sloc, spos, key, di, oi, xs, ys, zs, pi, g)) return;
-            const uint32_t u1 = subtab[base + s2 + 1];
-            for (uint32_t j = subtab[base + s2]; j < u1; j++) {
-                if ((int32_t)j == top || (int)j == i) continue;
-                if (denser_within_b(j, dens_s, gkey, sloc, spos, key, di, oi, xs, ys, zs, pi, g)) return;
-            }
+                                                      int32_t *__restrict__ cflag,
+                                                      int32_t *__restrict__ rest,
+                                                      uint32_t *__restrict__ nrest) {
+    // the second list fills only the first blocks of its grid: those are
+    // spread over all XCDs by the plain block order, not gathered on one
+    const int64_t t = (int64_t)(stage == 1 ? xcd_block() : blockIdx.x) * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const bool valid = t < (int64_t)*nhard_p;
+    const int i = valid ? hard[t] : -1;
+    bool left = false;
+    if (valid && !has_denser_within_b(i, stage == 1 ? 0 : 1, stage == 1 ? 1 : 27, g, sloc, spos, off, cellmap,
+                                      subtab, submax, subarg, dens_s, gkey)) {
+        if (stage == 1) {
+            left = true;
+        } else {
+            cflag[i] = 1;
+            atomicAdd(&gccnt[gid_of[i]], 1u);
         }
     }
-    cflag[i] = 1;
-    atomicAdd(&gccnt[gid_of[i]], 1u);
+    if (stage != 1) return;
+    // append the cases left: one atomic per wavefront
+    const uint64_t m = __ballot(left);
+    if (m == 0ull) return;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(nrest, (uint32_t)__popcll(m));
+    base = (uint32_t)__shfl((int)base, leader, 64);
+    if (left) rest[base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = i;
 }
 
 }  // namespace
@@ -207,10 +277,21 @@ void launch_candidates(int64_t n, const Geo &g, Work &w, hipStream_t s) {
     (void)hipMemcpyAsync(&nh, w.s_dcell + n, sizeof(nh), hipMemcpyDeviceToHost, s);
     (void)hipStreamSynchronize(s);
     w.nhard = nh;
-    if (nh > 0)
-        hipLaunchKernelGGL(k_cand_hard, dim3((unsigned)((nh + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                           w.s_dcell + n, g, w.hardlist, w.sloc, w.spos, w.off, w.cnt, w.subtab, w.submax,
-                           w.subarg, w.dens_s, w.gkey, w.gid_of, w.gccnt, w.owner);
+    if (nh > 0) {
+        // cases left after the own-cell search: list in the (free) chunk-flag
+        // array, count in counters[8]; the second launch reads the count on
+        // the device and its surplus threads exit
+        int32_t *rest = reinterpret_cast<int32_t *>(w.f_chunk);
+        uint32_t *nrest = reinterpret_cast<uint32_t *>(w.counters + 8);
+        fill_u32(nrest, 0u, 1, s);
+        const dim3 grid((unsigned)((nh + kBlock - 1) / kBlock));
+        hipLaunchKernelGGL(k_cand_hard, grid, dim3(kBlock), 0, s, w.s_dcell + n, 1, g, w.hardlist, w.sloc,
+                           w.spos, w.off, w.cnt, w.subtab, w.submax, w.subarg, w.dens_s, w.gkey, w.gid_of,
+                           w.gccnt, w.owner, rest, nrest);
+        hipLaunchKernelGGL(k_cand_hard, grid, dim3(kBlock), 0, s, nrest, 2, g, rest, w.sloc, w.spos, w.off,
+                           w.cnt, w.subtab, w.submax, w.subarg, w.dens_s, w.gkey, w.gid_of, w.gccnt, w.owner,
+                           nullptr, nullptr);
+    }
 }
 
 }  // namespace hf
