@@ -340,20 +340,39 @@ __global__ __launch_bounds__(kBlock) void k_fof_dense(int64_t nchunks, Geo g,
     }
 }
 
-// Members of sparse cells: links to the later members of sparse neighbour
-// cells (pairs with dense cells are found by the dense chunks).  The offsets
-// of a stencil plane are loaded together.
-__global__ __launch_bounds__(kBlock) void k_fof_sparse(int64_t nsparse, Geo g,
+// Members among the sparse-cell particles (about one in ten), compacted so
+// that the linking kernel runs without idle lanes.
+__global__ __launch_bounds__(kBlock) void k_fof_sparse_flags(int64_t nsparse, Geo g,
+                                                             const int32_t *__restrict__ sparse,
+                                                             const float *__restrict__ dens_s,
+                                                             uint32_t *__restrict__ flag) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nsparse) flag[t] = is_member(dens_s, sparse[t], g.dl0) ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fof_sparse_list(int64_t nsparse, const int32_t *__restrict__ sparse,
+                                                            const uint32_t *__restrict__ flag,
+                                                            const uint32_t *__restrict__ at,
+                                                            int32_t *__restrict__ list) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nsparse && flag[t]) list[at[t]] = sparse[t];
+}
+
+// Members of sparse cells (the compacted list, its length on the device):
+// links to the later members of sparse neighbour cells (pairs with dense cells
+// are found by the dense chunks).  The offsets of a stencil plane are loaded
+// together.  The list fills only the first blocks of the grid, which the plain
+// block order spreads over all XCDs.
+__global__ __launch_bounds__(kBlock) void k_fof_sparse(const uint32_t *__restrict__ count_p, Geo g,
                                                        const int32_t *__restrict__ sparse,
                                                        const float4 *__restrict__ sloc,
                                                        const float4 *__restrict__ spos,
                                                        const uint32_t *__restrict__ off,
                                                        const float *__restrict__ dens_s,
                                                        int32_t *parent) {
-    const int64_t t = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
-    if (t >= nsparse) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)*count_p) return;
     const int i = sparse[t];
-    if (!is_member(dens_s, i, g.dl0)) return;
     const float4 li = sloc[i];
     const float4 pi = spos[i];
     const uint32_t c = __float_as_uint(li.w);
@@ -476,9 +495,17 @@ void launch_fof(int64_t n, const Geo &g, Work &w, hipStream_t s) {
     if (w.nchunks > 0)
         hipLaunchKernelGGL(k_fof_dense, dim3((unsigned)((w.nchunks + 3) / 4)), dim3(kBlock), 0, s, w.nchunks, g,
                            w.chunks, w.sloc, w.spos, w.off, w.cnt, w.subtab, w.dens_s, w.parent);
-    if (w.nsparse > 0)
-        hipLaunchKernelGGL(k_fof_sparse, grid(w.nsparse), dim3(kBlock), 0, s, w.nsparse, g, w.sparse,
-                           w.sloc, w.spos, w.off, w.dens_s, w.parent);
+    if (w.nsparse > 0) {
+        // sparse members: flags, positions and list in arrays that are free
+        // during this stage (chunk flags of the binning, the hard-case list)
+        hipLaunchKernelGGL(k_fof_sparse_flags, grid(w.nsparse), dim3(kBlock), 0, s, w.nsparse, g, w.sparse,
+                           w.dens_s, w.f_chunk);
+        scan_u32(w.f_chunk, w.s_chunk, w.nsparse, w.scan_tmp, s);
+        hipLaunchKernelGGL(k_fof_sparse_list, grid(w.nsparse), dim3(kBlock), 0, s, w.nsparse, w.sparse,
+                           w.f_chunk, w.s_chunk, w.hardlist);
+        hipLaunchKernelGGL(k_fof_sparse, grid(w.nsparse), dim3(kBlock), 0, s, w.s_chunk + w.nsparse, g,
+                           w.hardlist, w.sloc, w.spos, w.off, w.dens_s, w.parent);
+    }
     // roots go to the owner array (free until the assignment stage)
     hipLaunchKernelGGL(k_fof_roots, grid(n), dim3(kBlock), 0, s, n, w.parent, w.owner);
     fill_i32(w.minorig, 0x7fffffff, n, s);
