@@ -48,9 +48,10 @@ def _stage_models(n, stats, pairs):
     return {
         # density: useful pairs x 11 flops, FP32 vector ALU
         "density": ("alu", pairs * FLOPS_PER_PAIR / 1e12, FP32_PEAK_TFLOPS, "TFLOP/s"),
-        # binning: read xyz 12 + key/ticket 16 + sorted float4 x2 32 + reads of keys 8 = 68 B/particle,
-        # plus count/offset arrays 12 B per cell
-        "bin": ("hbm", (68.0 * n + 12.0 * ncell) / 1e9, HBM_PEAK_GBS, "GB/s"),
+        # binning: read xyz 12 + sort key written and read once 16 + two sorted
+        # float4 records 32 + sub-cell index 2 = 62 B per particle, plus the
+        # cell offset 4 B per cell of the grid
+        "bin": ("hbm", (62.0 * n + 4.0 * ncell) / 1e9, HBM_PEAK_GBS, "GB/s"),
         # FoF: read float4 x2 + density for every particle (36 B), parent r/w 8 B
         "fof": ("hbm", 44.0 * n / 1e9, HBM_PEAK_GBS, "GB/s"),
     }
@@ -58,8 +59,10 @@ def _stage_models(n, stats, pairs):
 
 STAGE_KERNELS = {
     "density": ("k_density_dense", "k_density_sparse"),
-    "fof": ("k_fof_init", "k_fof_phase_a", "k_fof_dense", "k_fof_sparse", "k_fof_roots",
-            "k_fof_minorig", "k_fof_keys"),
+    "bin": ("k_bin_key", "k_radix_count", "k_radix_scatter", "k_bin_place", "k_cell_offsets",
+            "k_bin_flags", "k_bin_lists", "k_sub_init", "k_sub_starts", "k_sub_fix"),
+    "fof": ("k_fof_init", "k_fof_phase_a", "k_fof_dense", "k_fof_sparse_flags", "k_fof_sparse_list",
+            "k_fof_sparse", "k_fof_roots", "k_fof_minorig", "k_fof_keys"),
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
@@ -90,7 +93,7 @@ def pmc_summary(fetch_csv: str, write_csv: str, copy_mib: int) -> dict:
         scale = (copy_mib * 1024.0) / max(probe) if probe else 1.0
         per = {}
         for r in rows:
-            m = re.search(r"(k_[A-Za-z0-9_]+)\(", r["Kernel_Name"])
+            m = re.search(r"(k_[A-Za-z0-9_]+)(?:<[^>]*>)?\(", r["Kernel_Name"])
             name = m.group(1) if m else r["Kernel_Name"]
             per.setdefault(name, []).append(float(r["Counter_Value"]) * 1024.0 * scale)
         return per, scale
@@ -100,10 +103,13 @@ def pmc_summary(fetch_csv: str, write_csv: str, copy_mib: int) -> dict:
     out = {"source_hash": source_hash(), "fetch_scale": fscale, "write_scale": wscale,
            "copy_probe_mib": copy_mib, "stages": {}}
     for stage, kernels in STAGE_KERNELS.items():
-        rb = sum(sum(fetch.get(k, [])) for k in kernels)
-        wb = sum(sum(write.get(k, [])) for k in kernels)
+        # per call of the stage: the first kernel runs once per call (the
+        # binning also runs for the pair count, so it is seen twice)
+        calls = max(len(fetch.get(kernels[0], [])), 1)
+        rb = sum(sum(fetch.get(k, [])) for k in kernels) / calls
+        wb = sum(sum(write.get(k, [])) for k in kernels) / calls
         out["stages"][stage] = {"read_bytes": rb, "write_bytes": wb, "bytes": rb + wb,
-                                "kernels": list(kernels)}
+                                "calls_seen": calls, "kernels": list(kernels)}
     return out
 
 
