@@ -60,6 +60,7 @@ typedef struct {
     double l_fof;          /* L0 linking length, units of l_mean: 0.25 [FoFLinkingLength] */
     double delta_l0_min;   /* L0 density threshold: 60 [L0DensityThreshold]           */
     double delta_l1;       /* L1 SO threshold: 200 [SODensityL1]                      */
+    double delta_l2;       /* L2 SO threshold: 800 [SODensityL2] (hf_halo_stats)      */
     double alpha_elig;     /* eligibility radius / R_L1: 0.8 [SO_alpha_eligible]      */
     double c_roche;        /* reassignment factor: 2 [SO_RocheCoeff]                  */
     double n_new_min;      /* nucleation floor from a SIS of this many particles: 35
@@ -102,6 +103,16 @@ typedef struct hf_ctx hf_ctx;
 
 /* Fill p with the paper's defaults (Table 1, Einstein-de Sitter thresholds). */
 void hf_default_params(hf_params *p);
+
+/* Thresholds at redshift z (Sec. 2.3.1) for a flat universe of matter (Omega_m0
+ * today) and a cosmological constant: with Omega_m(z) = Om (1+z)^3 /
+ * (Om (1+z)^3 + 1 - Om) and x = Omega_m(z) - 1, the fitting function
+ * 18 pi^2 + 82 x - 39 x^2 (relative to the critical density) divided by
+ * 18 pi^2 Omega_m(z) scales delta_l1, delta_l2 and delta_l0_min of in; l_fof is
+ * divided by the cube root of that factor; b_kernel and the rest are copied.
+ * Table 1 (Omega_m0 = 0.315, z = 0.5): 258.2, 1033.0, 77.5 from 200, 800, 60.
+ * HF_ERR_INVALID unless 0 < omega_m0 <= 1 and z > -1.  Host only. */
+hf_status hf_params_at_redshift(const hf_params *in, double omega_m0, double z, hf_params *out);
 
 /* Derived constants for n particles under p, computed on the host exactly as the
  * kernels use them (out[11]): nbar, b, l, b^2, l^2, density normalisation

@@ -36,9 +36,12 @@ DEFAULTS = {
     "particle_mass": 1.0,
     "n_l1_min": 35,           # MinL1HaloNP
     "self_count": 0,          # include W(0) = 1 for the particle itself
+    "delta_l2": 800.0,        # SODensityL2
 }
 _ORDER = ["box", "mean_density", "b_kernel", "l_fof", "delta_l0_min", "delta_l1",
-          "alpha_elig", "c_roche", "n_new_min", "particle_mass", "n_l1_min", "self_count"]
+          "alpha_elig", "c_roche", "n_new_min", "particle_mass", "n_l1_min", "self_count",
+          "delta_l2"]
+PCT = [10, 25, 33, 50, 67, 75, 90, 95, 98]   # the r_XX percentiles of l2_stats
 DERIVED = ["nbar", "b", "l", "b2", "l2", "norm", "K", "K2", "floor", "A6", "C3"]
 
 
@@ -66,6 +69,8 @@ def _load():
         lib.orc_fof.argtypes = [I64, P, P, P, ctypes.c_int, P, P]
         lib.orc_compaso.argtypes = [I64, P, P, P, P, ctypes.c_int, P, P, I64,
                                     P, P, P, P, P, P, P, I64, P, P, P, P]
+        lib.orc_params_at_redshift.argtypes = [P, ctypes.c_double, ctypes.c_double, P]
+        lib.orc_l2_stats.argtypes = [I64, P, P, P, P, ctypes.c_int, I64, P, P, P, I64, P, P, P, P, P]
         lib.orc_num_threads.restype = ctypes.c_int
         lib.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -181,3 +186,45 @@ def find(pos, mode: str = "cells", density_override=None, **kw) -> dict:
     res = compaso(pos, dens, l0, mode=mode, **kw)
     res.update({"density": dens, "l0": l0, "n_groups": ng})
     return res
+
+
+def params_at_redshift(omega_m0: float, z: float, **kw) -> dict:
+    """Thresholds at redshift z (Sec. 2.3.1): see orc_params_at_redshift."""
+    p = params_vector(**kw)
+    out = np.zeros_like(p)
+    if _load().orc_params_at_redshift(_ptr(p), float(omega_m0), float(z), _ptr(out)) != 0:
+        raise ValueError("invalid cosmology")
+    return {k: (int(v) if k in ("n_l1_min", "self_count") else float(v)) for k, v in zip(_ORDER, out)}
+
+
+def l2_stats(pos, dens, halo_id, mode: str = "cells", **kw) -> dict:
+    """Level 2 inside every L1 halo and the Table 1 position statistics (end of
+    Sec. 2.2.2): see orc_l2_stats.  Per-halo arrays are in ascending L1 id."""
+    pos = _pos(pos)
+    n = len(pos)
+    dens = np.ascontiguousarray(dens, dtype=np.float64)
+    halo_id = np.ascontiguousarray(halo_id, dtype=np.int32)
+    p = params_vector(**kw)
+    cap = int(len(np.unique(halo_id[halo_id > 0])))
+    si = np.zeros((max(cap, 1), 5), np.int32)
+    sf = np.zeros((max(cap, 1), 22), np.float64)
+    l2 = np.zeros((max(n, 1), 4), np.int32)
+    members = np.zeros(max(n, 1), np.int32)
+    l2_owner = np.zeros(max(n, 1), np.int32)
+    gstart = np.zeros(cap + 1, np.int64)
+    nl1 = np.zeros(1, np.int64)
+    nl2 = np.zeros(1, np.int64)
+    rc = _load().orc_l2_stats(n, _ptr(pos), _ptr(p), _ptr(dens), _ptr(halo_id),
+                              0 if mode == "brute" else 1, cap, _ptr(nl1), _ptr(si), _ptr(sf), n,
+                              _ptr(l2), _ptr(nl2), _ptr(l2_owner), _ptr(members), _ptr(gstart))
+    if rc:
+        raise RuntimeError(f"orc_l2_stats failed ({rc})")
+    k = int(nl1[0])
+    si, sf = si[:k], sf[:k]
+    return {"id": si[:, 0].copy(), "n": si[:, 1].copy(), "n_l2": si[:, 2].copy(),
+            "l2max_nucleus": si[:, 3].copy(), "l2max_n": si[:, 4].copy(),
+            "x_com": sf[:, 0:3].copy(), "x_l2com": sf[:, 3:6].copy(), "l2_mass": sf[:, 6:11].copy(),
+            "r_pct": sf[:, 11:20].copy(), "vcirc_max": sf[:, 20].copy(), "rvcirc_max": sf[:, 21].copy(),
+            "l2": l2[:int(nl2[0])].copy(), "l2_owner": l2_owner[:n].copy(),
+            "members": members[:int(gstart[k])].copy(),
+            "gstart": gstart.copy()}

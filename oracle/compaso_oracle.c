@@ -31,6 +31,7 @@
  *   [0] box  [1] mean_density (<=0: N/L^3)  [2] b_kernel (units of l_mean)
  *   [3] l_fof (units of l_mean)  [4] delta_l0_min  [5] delta_l1  [6] alpha_elig
  *   [7] c_roche  [8] n_new_min  [9] particle_mass  [10] n_l1_min  [11] self_count
+ *   [12] delta_l2
  * Derived vector (orc_derive):
  *   [0] nbar [1] b [2] l [3] b2 [4] l2 [5] norm [6] K [7] K2 [8] floor [9] A6 [10] C3
  */
@@ -45,7 +46,7 @@
 #define ORC_PI 3.14159265358979323846
 
 enum { P_BOX, P_NBAR, P_B, P_L, P_DL0, P_DL1, P_ALPHA, P_CROCHE, P_NNEW, P_MASS,
-       P_NL1MIN, P_SELF, P_COUNT };
+       P_NL1MIN, P_SELF, P_DL2, P_COUNT };
 enum { D_NBAR, D_B, D_L, D_B2, D_L2, D_NORM, D_K, D_K2, D_FLOOR, D_A6, D_C3, D_COUNT };
 
 /* ---------------------------------------------------------------- constants */
@@ -578,6 +579,225 @@ int orc_compaso(int64_t n, const float *pos, const double *p, const double *dens
     *n_halos = kept;
     if (n_found) *n_found = found;
     free(keep_flag); free(hN); free(hI); free(hL);
+    free(gh); free(gnh); free(own);
+    if (use_grid) grid_free(&g);
+    free(mem); free(gstart); free(glab);
+    return 0;
+}
+
+/* ------------------------------------------------------ redshift scaling */
+
+/* Thresholds at redshift z (Sec. 2.3.1) for a flat universe of matter and a
+ * cosmological constant: Omega_m(z) = Om (1+z)^3 / (Om (1+z)^3 + 1 - Om).
+ * The Bryan & Norman fitting function Delta_base = 18 pi^2 + 82 x - 39 x^2,
+ * x = Omega_m(z) - 1, is relative to the critical density; relative to the
+ * mean it is Delta_base / Omega_m(z).  The EdS thresholds are multiplied by
+ * s = Delta_base / (18 pi^2 Omega_m(z)) (s = 1 for Om = 1): Delta_L1 (200 ->
+ * 258.2 at z = 0.5, Om = 0.315, Table 1), Delta_L2 (800 -> 1033.0) and the L0
+ * threshold (60 -> 77.5, Table 1); the FoF linking length by s^(-1/3); the
+ * kernel radius b is unchanged. */
+int orc_params_at_redshift(const double *pin, double om0, double z, double *pout)
+{
+    if (!(om0 > 0.0 && om0 <= 1.0) || !(z > -1.0)) return 1;
+    for (int k = 0; k < P_COUNT; k++) pout[k] = pin[k];
+    double a = 1.0 + z;
+    double m = om0 * ((a * a) * a);
+    double omz = m / (m + (1.0 - om0));
+    double x = omz - 1.0;
+    double tpi2 = 18.0 * ORC_PI * ORC_PI;
+    double base = tpi2 + 82.0 * x - 39.0 * (x * x);
+    double scale = base / (tpi2 * omz);
+    pout[P_DL1] = pin[P_DL1] * scale;
+    pout[P_DL2] = pin[P_DL2] * scale;
+    pout[P_DL0] = pin[P_DL0] * scale;
+    pout[P_L] = pin[P_L] / cbrt(scale);
+    return 0;
+}
+
+/* -------------------------------------------- level 2 and halo statistics */
+
+static int cmp_float(const void *a, const void *b)
+{
+    float x = *(const float *)a, y = *(const float *)b;
+    return (x > y) - (x < y);
+}
+
+static int cmp_desc_i64(const void *a, const void *b)
+{
+    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return (x < y) - (x > y);
+}
+
+/* Centre of mass of the particles mem[t] with own[t] == sel (sel < 0: all),
+ * about the particle ref: each minimum-image offset is rounded to a multiple
+ * of 2^-32 and the multiples are summed exactly in 64-bit integers, so the
+ * mean does not depend on the order of summation; the result is wrapped into
+ * [0, L). */
+static void com_about(const float *pos, double L, const int64_t *mem, const int64_t *own,
+                      int64_t m, int64_t sel, int64_t ref, double out[3])
+{
+    int64_t S[3] = {0, 0, 0};
+    int64_t cnt = 0;
+    for (int64_t t = 0; t < m; t++) {
+        if (sel >= 0 && own[t] != sel) continue;
+        int64_t j = mem[t];
+        for (int a = 0; a < 3; a++) {
+            double dx = (double)pos[3 * j + a] - (double)pos[3 * ref + a];
+            if (dx > 0.5 * L) dx -= L;
+            else if (dx < -0.5 * L) dx += L;
+            S[a] += llrint(dx * 4294967296.0);
+        }
+        cnt++;
+    }
+    for (int a = 0; a < 3; a++) {
+        double c = (double)S[a];
+        c = c / (double)cnt;
+        c = c * (1.0 / 4294967296.0);
+        double x = (double)pos[3 * ref + a] + c;
+        if (x < 0.0) x += L;
+        else if (x >= L) x -= L;
+        out[a] = x;
+    }
+}
+
+static const int kPct[9] = {10, 25, 33, 50, 67, 75, 90, 95, 98};
+
+/* Level 2 (end of Sec. 2.2.2): inside every L1 halo the competitive SO steps
+ * are repeated with Delta_L2 in place of Delta_L1 everywhere (enclosed
+ * density, nucleation floor), the L1 halo's members playing the part of the
+ * L0 group (peak test, enclosed counts, assignment).  Then per L1 halo, in
+ * ascending id (Table 1):
+ *   si[5*k..]  id, N, number of L2 halos, first L2 nucleus (-1 if none), its N
+ *   sf[22*k..] x_com[3] (L1 centre of mass), x_L2com[3] (centre of mass of the
+ *              first L2 halo, = x_com if none), masses of the 5 largest L2
+ *              halos (descending, 0 beyond their number), r_XX about x_L2com
+ *              for XX = 10 25 33 50 67 75 90 95 98, vcirc_max, rvcirc_max.
+ * r_XX: the k-th smallest distance, k = ceil(XX N / 100), of the L1 members
+ * from x_L2com (squared distances in FP64, then rounded to float32 and sorted).
+ * vcirc: with the members sorted by that distance, k of them lie within r_k;
+ * the circular velocity sqrt(G m_p k / r_k) (G = 1) is largest at the first
+ * position maximising k^2 / r_k^2 (members at r = 0 are skipped).
+ * l2: every L2 halo (L1 id, nucleus, enclosed count, N) in L1 order and
+ * creation order; l2_owner (optional): per particle 1 + the nucleus index of
+ * its L2 halo, 0 if none; members/gstart: the L1 members grouped by halo
+ * (ascending id, ascending index).  Returns 3 if the number of L1 halos
+ * exceeds cap. */
+int orc_l2_stats(int64_t n, const float *pos, const double *p, const double *dens,
+                 const int32_t *halo_id, int mode, int64_t cap, int64_t *n_l1,
+                 int32_t *si, double *sf, int64_t l2cap, int32_t *l2, int64_t *n_l2_total,
+                 int32_t *l2_owner, int32_t *members, int64_t *gstart_out)
+{
+    double q[P_COUNT], d[D_COUNT];
+    for (int k = 0; k < P_COUNT; k++) q[k] = p[k];
+    q[P_DL1] = p[P_DL2];
+    if (orc_derive(q, n, d)) return 1;
+    double L = p[P_BOX];
+    int64_t *cnt = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    int64_t *mem = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    if (!cnt || !mem) { free(cnt); free(mem); return 2; }
+    for (int64_t i = 0; i < n; i++) if (halo_id[i] > 0) cnt[halo_id[i]]++;
+    int64_t ng = 0;
+    for (int64_t k = 1; k <= n; k++) if (cnt[k]) ng++;
+    *n_l1 = ng;
+    if (ng > cap) { free(cnt); free(mem); return 3; }
+    int64_t *gstart = (int64_t *)malloc((size_t)(ng + 1) * sizeof(int64_t));
+    int64_t *glab = (int64_t *)malloc((size_t)(ng > 0 ? ng : 1) * sizeof(int64_t));
+    int64_t *off = (int64_t *)calloc((size_t)n + 2, sizeof(int64_t));
+    int64_t gi = 0, acc = 0;
+    for (int64_t k = 1; k <= n; k++)
+        if (cnt[k]) { glab[gi] = k; gstart[gi] = acc; off[k] = acc; acc += cnt[k]; gi++; }
+    gstart[ng] = acc;
+    for (int64_t i = 0; i < n; i++) if (halo_id[i] > 0) mem[off[halo_id[i]]++] = i;
+    free(off);
+    free(cnt);
+    grid_t g;
+    int use_grid = 0;
+    if (mode == 1) {
+        int rc = grid_build(&g, n, pos, L, d[D_B]);
+        if (rc == 2) { free(mem); free(gstart); free(glab); return 2; }
+        use_grid = rc == 0;
+    }
+    ctx_t c = { pos, dens, halo_id, L, d, use_grid ? &g : NULL, n };
+    halo_t **gh = (halo_t **)calloc((size_t)(ng > 0 ? ng : 1), sizeof(halo_t *));
+    int64_t *gnh = (int64_t *)calloc((size_t)(ng > 0 ? ng : 1), sizeof(int64_t));
+    int64_t *own = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < ng; k++) {
+        int64_t s0 = gstart[k], m = gstart[k + 1] - s0;
+        gnh[k] = compaso_group(&c, mem + s0, m, &gh[k], own + s0);
+        int64_t nuc = glab[k] - 1;
+        double com[3], com2[3];
+        com_about(pos, L, mem + s0, own + s0, m, -1, nuc, com);
+        if (gnh[k] > 0) com_about(pos, L, mem + s0, own + s0, m, 0, gh[k][0].nucleus, com2);
+        else for (int a = 0; a < 3; a++) com2[a] = com[a];
+        float *fd = (float *)malloc((size_t)m * sizeof(float));
+        for (int64_t t = 0; t < m; t++) {
+            int64_t j = mem[s0 + t];
+            double dd[3];
+            for (int a = 0; a < 3; a++) {
+                double dx = (double)pos[3 * j + a] - com2[a];
+                if (dx > 0.5 * L) dx -= L;
+                else if (dx < -0.5 * L) dx += L;
+                dd[a] = dx;
+            }
+            fd[t] = (float)((dd[0] * dd[0] + dd[1] * dd[1]) + dd[2] * dd[2]);
+        }
+        qsort(fd, (size_t)m, sizeof(float), cmp_float);
+        int32_t *I = si + 5 * k;
+        double *F = sf + 22 * k;
+        I[0] = (int32_t)glab[k];
+        I[1] = (int32_t)m;
+        I[2] = (int32_t)gnh[k];
+        I[3] = gnh[k] > 0 ? (int32_t)gh[k][0].nucleus : -1;
+        I[4] = gnh[k] > 0 ? (int32_t)gh[k][0].count : 0;
+        for (int a = 0; a < 3; a++) { F[a] = com[a]; F[3 + a] = com2[a]; }
+        int64_t *counts = (int64_t *)malloc((size_t)(gnh[k] > 0 ? gnh[k] : 1) * sizeof(int64_t));
+        for (int64_t h = 0; h < gnh[k]; h++) counts[h] = gh[k][h].count;
+        qsort(counts, (size_t)gnh[k], sizeof(int64_t), cmp_desc_i64);
+        for (int u = 0; u < 5; u++) F[6 + u] = u < gnh[k] ? (double)counts[u] * p[P_MASS] : 0.0;
+        free(counts);
+        for (int u = 0; u < 9; u++) {
+            int64_t kk = ((int64_t)kPct[u] * m + 99) / 100;
+            F[11 + u] = sqrt((double)fd[kk - 1]);
+        }
+        int64_t best = -1;
+        double vbest = 0.0;
+        for (int64_t t = 0; t < m; t++) {
+            if (!(fd[t] > 0.0f)) continue;
+            double v = ((double)(t + 1) * (double)(t + 1)) / (double)fd[t];
+            if (best < 0 || v > vbest) { best = t; vbest = v; }
+        }
+        if (best >= 0) {
+            double r = sqrt((double)fd[best]);
+            F[20] = sqrt((p[P_MASS] * (double)(best + 1)) / r);
+            F[21] = r;
+        } else {
+            F[20] = 0.0;
+            F[21] = 0.0;
+        }
+        free(fd);
+    }
+    if (l2_owner) {
+        for (int64_t i = 0; i < n; i++) l2_owner[i] = 0;
+        for (int64_t k = 0; k < ng; k++)
+            for (int64_t t = gstart[k]; t < gstart[k + 1]; t++)
+                if (own[t] >= 0) l2_owner[mem[t]] = (int32_t)(gh[k][own[t]].nucleus + 1);
+    }
+    int64_t w = 0;
+    for (int64_t k = 0; k < ng; k++) {
+        for (int64_t h = 0; h < gnh[k]; h++, w++)
+            if (w < l2cap) {
+                l2[4 * w + 0] = (int32_t)glab[k];
+                l2[4 * w + 1] = (int32_t)gh[k][h].nucleus;
+                l2[4 * w + 2] = (int32_t)gh[k][h].ienc;
+                l2[4 * w + 3] = (int32_t)gh[k][h].count;
+            }
+        free(gh[k]);
+    }
+    *n_l2_total = w;
+    if (members) for (int64_t t = 0; t < acc; t++) members[t] = (int32_t)mem[t];
+    if (gstart_out) for (int64_t k = 0; k <= ng; k++) gstart_out[k] = gstart[k];
     free(gh); free(gnh); free(own);
     if (use_grid) grid_free(&g);
     free(mem); free(gstart); free(glab);

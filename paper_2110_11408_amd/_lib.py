@@ -17,7 +17,7 @@ HF_OK, HF_ERR_INVALID, HF_ERR_NOMEM, HF_ERR_CAPACITY, HF_ERR_DEVICE, HF_ERR_UNSU
 STATUS = {0: "HF_OK", 1: "HF_ERR_INVALID", 2: "HF_ERR_NOMEM", 3: "HF_ERR_CAPACITY",
           4: "HF_ERR_DEVICE", 5: "HF_ERR_UNSUPPORTED"}
 
-EXPORTS = ["hf_default_params", "hf_derived", "hf_create", "hf_destroy", "hf_last_error",
+EXPORTS = ["hf_default_params", "hf_params_at_redshift", "hf_derived", "hf_create", "hf_destroy", "hf_last_error",
            "hf_get_stats", "hf_density", "hf_l0_fof", "hf_compaso", "hf_find", "hf_count_pairs",
            "hf_find_batch", "hf_server_create", "hf_server_submit", "hf_server_wait",
            "hf_server_now", "hf_server_held_bytes", "hf_server_last_error", "hf_server_destroy"]
@@ -27,6 +27,7 @@ class HfParams(ctypes.Structure):
     _fields_ = [("box", ctypes.c_double), ("mean_density", ctypes.c_double),
                 ("b_kernel", ctypes.c_double), ("l_fof", ctypes.c_double),
                 ("delta_l0_min", ctypes.c_double), ("delta_l1", ctypes.c_double),
+                ("delta_l2", ctypes.c_double),
                 ("alpha_elig", ctypes.c_double), ("c_roche", ctypes.c_double),
                 ("n_new_min", ctypes.c_double), ("particle_mass", ctypes.c_double),
                 ("n_l1_min", ctypes.c_int32), ("self_count", ctypes.c_int32)]
@@ -86,6 +87,7 @@ def load(path: str = LIB_PATH):
         lib.hf_default_params.argtypes = [PP]
         lib.hf_default_params.restype = None
         lib.hf_derived.argtypes = [PP, I64, P]
+        lib.hf_params_at_redshift.argtypes = [PP, ctypes.c_double, ctypes.c_double, PP]
         lib.hf_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), I32]
         lib.hf_destroy.argtypes = [P]
         lib.hf_destroy.restype = None
@@ -110,7 +112,7 @@ def load(path: str = LIB_PATH):
         lib.hf_server_last_error.restype = ctypes.c_char_p
         lib.hf_server_destroy.argtypes = [P]
         lib.hf_server_destroy.restype = None
-        for name in ("hf_derived", "hf_create", "hf_get_stats", "hf_density", "hf_l0_fof",
+        for name in ("hf_derived", "hf_params_at_redshift", "hf_create", "hf_get_stats", "hf_density", "hf_l0_fof",
                      "hf_compaso", "hf_find", "hf_count_pairs", "hf_find_batch",
                      "hf_server_create", "hf_server_submit", "hf_server_wait"):
             getattr(lib, name).restype = ctypes.c_int
@@ -126,6 +128,15 @@ def default_params(**kw) -> HfParams:
             raise KeyError(k)
         setattr(p, k, v)
     return p
+
+
+def params_at_redshift(p: HfParams, omega_m0: float, z: float) -> HfParams:
+    """hf_params_at_redshift: thresholds scaled to redshift z."""
+    out = HfParams()
+    st = load().hf_params_at_redshift(ctypes.byref(p), float(omega_m0), float(z), ctypes.byref(out))
+    if st:
+        raise HfError(st, "invalid cosmology")
+    return out
 
 
 def derived(p: HfParams, n: int) -> dict:

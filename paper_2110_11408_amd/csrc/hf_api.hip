@@ -37,10 +37,12 @@ bool finite(double x) { return x == x && x != HUGE_VAL && x != -HUGE_VAL; }
 hf_status derive(const hf_params *p, int64_t n, double *d) {
     if (!p) return HF_ERR_INVALID;
     const double v[] = {p->box, p->mean_density, p->b_kernel, p->l_fof, p->delta_l0_min,
-                        p->delta_l1, p->alpha_elig, p->c_roche, p->n_new_min, p->particle_mass};
+                        p->delta_l1, p->delta_l2, p->alpha_elig, p->c_roche, p->n_new_min,
+                        p->particle_mass};
     for (double x : v)
         if (!finite(x)) return HF_ERR_INVALID;
     if (!(p->box > 0.0) || !(p->b_kernel > 0.0) || !(p->l_fof > 0.0) || !(p->delta_l1 > 0.0) ||
+        !(p->delta_l2 > 0.0) ||
         p->alpha_elig < 0.0 || p->c_roche < 0.0 || !(p->n_new_min > 0.0) || n < 0)
         return HF_ERR_INVALID;
     double box = p->box;
@@ -417,12 +419,32 @@ void hf_default_params(hf_params *p) {
     p->l_fof = 0.25;
     p->delta_l0_min = 60.0;
     p->delta_l1 = 200.0;
+    p->delta_l2 = 800.0;
     p->alpha_elig = 0.8;
     p->c_roche = 2.0;
     p->n_new_min = 35.0;
     p->particle_mass = 1.0;
     p->n_l1_min = 35;
     p->self_count = 0;
+}
+
+hf_status hf_params_at_redshift(const hf_params *in, double omega_m0, double z, hf_params *out) {
+    if (!in || !out || !(omega_m0 > 0.0 && omega_m0 <= 1.0) || !(z > -1.0)) return HF_ERR_INVALID;
+    // flat matter + Lambda: Omega_m(z) = Om (1+z)^3 / (Om (1+z)^3 + 1 - Om)
+    const double a = 1.0 + z;
+    const double mz = omega_m0 * ((a * a) * a);
+    const double omz = mz / (mz + (1.0 - omega_m0));
+    const double x = omz - 1.0;
+    const double c = 18.0 * HF_PI * HF_PI;
+    // fitting function relative to the critical density, then to the mean
+    const double factor = (c + 82.0 * x - 39.0 * (x * x)) / (c * omz);
+    hf_params p = *in;
+    p.delta_l1 = in->delta_l1 * factor;
+    p.delta_l2 = in->delta_l2 * factor;
+    p.delta_l0_min = in->delta_l0_min * factor;
+    p.l_fof = in->l_fof / cbrt(factor);
+    *out = p;
+    return HF_OK;
 }
 
 hf_status hf_derived(const hf_params *p, int64_t n, double *out) {

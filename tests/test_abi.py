@@ -36,7 +36,7 @@ def test_exports_every_declared_function(lib):
 
 
 def test_struct_layouts():
-    assert ctypes.sizeof(_lib.HfParams) == 10 * 8 + 2 * 4
+    assert ctypes.sizeof(_lib.HfParams) == 11 * 8 + 2 * 4
     assert ctypes.sizeof(_lib.HfHalo) == 40
     assert _lib.HALO_WORDS == 10
 
@@ -146,3 +146,15 @@ def test_server_without_gpu_is_unsupported(lib):
         pass
     h = ctypes.c_void_p()
     assert lib.hf_server_create(ctypes.byref(h), 0, 2, 1 << 30) == _lib.HF_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("om, z", [(0.315, 0.5), (1.0, 2.0), (0.3, 0.0), (0.25, 3.0)])
+def test_params_at_redshift_matches_oracle(lib, om, z):
+    """The library's redshift scaling (host code) against the oracle's own."""
+    p = _lib.default_params(box=50.0)
+    mine = _lib.params_at_redshift(p, om, z)
+    ref = oracle.params_at_redshift(om, z, box=50.0)
+    for k in ("delta_l1", "delta_l2", "delta_l0_min", "l_fof", "b_kernel", "alpha_elig"):
+        assert getattr(mine, k) == pytest.approx(ref[k], rel=1e-14), k
+    bad = _lib.HfParams()
+    assert lib.hf_params_at_redshift(ctypes.byref(p), 0.0, 0.5, ctypes.byref(bad)) == _lib.HF_ERR_INVALID
