@@ -82,6 +82,27 @@ typedef struct {
     float mass;          /* n * particle_mass                                         */
 } hf_halo;
 
+/* Level 2 summary and position statistics of one L1 halo (end of Sec. 2.2.2,
+ * Table 1), from hf_halo_stats.  Distances are minimum-image. */
+typedef struct {
+    int32_t id;             /* L1 halo id (1 + nucleus, as in hf_halo)                 */
+    int32_t n;              /* members N                                               */
+    int32_t n_l2;           /* L2 halos found inside it                                */
+    int32_t l2max_nucleus;  /* original index of the first L2 halo's nucleus
+                               [SO_L2max_central_particle]; -1 if none                 */
+    int32_t l2max_n;        /* members of the first L2 halo                            */
+    float x_com[3];         /* centre of mass of the members [x_com]                   */
+    float x_l2com[3];       /* centre of mass of the first L2 halo [x_L2com];
+                               x_com if there is none                                  */
+    float l2_mass[5];       /* masses of the 5 largest L2 halos, descending; 0 beyond  */
+    float r_pct[9];         /* r_XX about x_L2com for XX = 10 25 33 50 67 75 90 95 98:
+                               the k-th smallest member distance, k = ceil(XX N/100)
+                               [r_XX_L2com]                                            */
+    float vcirc_max;        /* max over members of sqrt(m_p k / r_k), k members within
+                               r_k of x_L2com, G = 1 [vcirc_max_L2com]                 */
+    float rvcirc_max;       /* the r_k where it is reached [rvcirc_max_L2com]          */
+} hf_halo_summary;
+
 /* Per-call statistics of the last call on a context (device event timings of
  * each stage on the call's stream, and work counters). */
 typedef struct {
@@ -159,6 +180,23 @@ hf_status hf_compaso(hf_ctx *ctx, const float *pos, const float *density,
  * (host).  Used to express the density kernel's work in pair-interactions. */
 hf_status hf_count_pairs(hf_ctx *ctx, const float *pos, int64_t n, const hf_params *p,
                          int64_t *pairs, void *stream);
+
+/* Level 2 and position statistics of the L1 halos (end of Sec. 2.2.2, Table 1).
+ * halo_id (device int32 [n], original order): an L1 labelling such as
+ * hf_find's (1 + nucleus index, 0 = none); density: the field it was found on
+ * (device float32 [n]).  Inside every L1 halo the competitive SO steps are
+ * repeated with delta_l2 in place of delta_l1 everywhere (nucleation floor,
+ * enclosed counts, eligibility and reassignment), the halo's members taking the
+ * place of the L0 group.  n_halos must equal the number of distinct non-zero
+ * labels (HF_ERR_INVALID otherwise).  stats (device, n_halos rows) are in
+ * ascending id.  group_start (device int32 [n_halos + 1], may be NULL) and
+ * group_members (device int32 [number of labelled particles], may be NULL)
+ * receive the members grouped by halo: ascending id, ascending original index
+ * inside a halo (the halo-ordered particle list of Sec. 2.3.5). */
+hf_status hf_halo_stats(hf_ctx *ctx, const float *pos, const float *density,
+                        const int32_t *halo_id, int64_t n, const hf_params *p,
+                        int64_t n_halos, hf_halo_summary *stats, int32_t *group_start,
+                        int32_t *group_members, void *stream);
 
 /* The whole pass: density, L0 FoF and CompaSO L1 with the output cut, sharing one
  * cell binning.  Outputs as in the three calls above; density and l0_id may be

@@ -19,6 +19,7 @@ STATUS = {0: "HF_OK", 1: "HF_ERR_INVALID", 2: "HF_ERR_NOMEM", 3: "HF_ERR_CAPACIT
 
 EXPORTS = ["hf_default_params", "hf_params_at_redshift", "hf_derived", "hf_create", "hf_destroy", "hf_last_error",
            "hf_get_stats", "hf_density", "hf_l0_fof", "hf_compaso", "hf_find", "hf_count_pairs",
+           "hf_halo_stats",
            "hf_find_batch", "hf_server_create", "hf_server_submit", "hf_server_wait",
            "hf_server_now", "hf_server_held_bytes", "hf_server_last_error", "hf_server_destroy"]
 
@@ -47,6 +48,17 @@ class HfStats(ctypes.Structure):
                [(k, ctypes.c_int64) for k in
                 ("n_cells", "n_members", "n_groups", "n_candidates", "n_found", "n_halos",
                  "n_dense_cells", "n_dense_chunks", "n_sparse", "n_hard")]
+
+
+class HfHaloSummary(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int32), ("n", ctypes.c_int32), ("n_l2", ctypes.c_int32),
+                ("l2max_nucleus", ctypes.c_int32), ("l2max_n", ctypes.c_int32),
+                ("x_com", ctypes.c_float * 3), ("x_l2com", ctypes.c_float * 3),
+                ("l2_mass", ctypes.c_float * 5), ("r_pct", ctypes.c_float * 9),
+                ("vcirc_max", ctypes.c_float), ("rvcirc_max", ctypes.c_float)]
+
+
+PCT = [10, 25, 33, 50, 67, 75, 90, 95, 98]   # the r_XX of hf_halo_summary.r_pct
 
 
 class HfRequest(ctypes.Structure):
@@ -99,6 +111,7 @@ def load(path: str = LIB_PATH):
         lib.hf_compaso.argtypes = [P, P, P, P, I64, PP, P, P, I64, P, P]
         lib.hf_find.argtypes = [P, P, I64, PP, P, P, P, P, I64, P, P]
         lib.hf_count_pairs.argtypes = [P, P, I64, PP, P, P]
+        lib.hf_halo_stats.argtypes = [P, P, P, P, I64, PP, I64, P, P, P, P]
         lib.hf_find_batch.argtypes = [P, ctypes.c_int32, P, P, P, P, P, P, P, P, P, ctypes.c_int32, P]
         lib.hf_server_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), I32, ctypes.c_int32,
                                          ctypes.c_uint64]
@@ -113,7 +126,7 @@ def load(path: str = LIB_PATH):
         lib.hf_server_destroy.argtypes = [P]
         lib.hf_server_destroy.restype = None
         for name in ("hf_derived", "hf_params_at_redshift", "hf_create", "hf_get_stats", "hf_density", "hf_l0_fof",
-                     "hf_compaso", "hf_find", "hf_count_pairs", "hf_find_batch",
+                     "hf_compaso", "hf_find", "hf_count_pairs", "hf_halo_stats", "hf_find_batch",
                      "hf_server_create", "hf_server_submit", "hf_server_wait"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib

@@ -12,7 +12,8 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import HfError, HfParams, HfRequest, HfResult, HfStats, HALO_FIELDS, HALO_WORDS
+from ._lib import (HfError, HfHaloSummary, HfParams, HfRequest, HfResult, HfStats, HALO_FIELDS,
+                   HALO_WORDS)
 
 
 def _ptr(t):
@@ -112,6 +113,35 @@ class Context:
                 self.h, _ptr(pos), n, ctypes.byref(p), _ptr(dens), _ptr(l0), _ptr(halo_id),
                 _ptr(buf), cap, ctypes.byref(nh), _stream(pos.device)),
             halos_cap, n, pos.device, {"density": dens, "l0_id": l0, "halo_id": halo_id})
+
+    def halo_stats(self, pos, density, halo_id, p: HfParams, n_halos: int, want_members=True):
+        """hf_halo_stats: level 2 inside the L1 halos labelled by halo_id and the
+        Table 1 position statistics.  Returns a dict of numpy columns (one row
+        per halo, ascending id) and, with want_members, the halo-ordered member
+        list and its offsets (device tensors)."""
+        import numpy as np
+        pos = _check_pos(pos)
+        n = pos.shape[0]
+        density = density.contiguous()
+        halo_id = halo_id.contiguous()
+        words = ctypes.sizeof(HfHaloSummary) // 4
+        rows = torch.empty((max(int(n_halos), 1), words), dtype=torch.int32, device=pos.device)
+        gstart = torch.empty(int(n_halos) + 1, dtype=torch.int32, device=pos.device) if want_members else None
+        nmem = int((halo_id > 0).sum().item()) if want_members else 0
+        members = torch.empty(max(nmem, 1), dtype=torch.int32, device=pos.device) if want_members else None
+        self._raise(self.lib.hf_halo_stats(self.h, _ptr(pos), _ptr(density), _ptr(halo_id), n,
+                                           ctypes.byref(p), int(n_halos), _ptr(rows), _ptr(gstart),
+                                           _ptr(members), _stream(pos.device)))
+        a = np.ascontiguousarray(rows[: int(n_halos)].cpu().numpy())
+        f = a.view(np.float32)
+        out = {"id": a[:, 0].copy(), "n": a[:, 1].copy(), "n_l2": a[:, 2].copy(),
+               "l2max_nucleus": a[:, 3].copy(), "l2max_n": a[:, 4].copy(),
+               "x_com": f[:, 5:8].copy(), "x_l2com": f[:, 8:11].copy(), "l2_mass": f[:, 11:16].copy(),
+               "r_pct": f[:, 16:25].copy(), "vcirc_max": f[:, 25].copy(), "rvcirc_max": f[:, 26].copy()}
+        if want_members:
+            out["group_start"] = gstart
+            out["members"] = members[:nmem]
+        return out
 
     def find_batch(self, pos, offsets, params, halos_caps=None, n_lanes=0, want_density=True,
                    want_l0=True):

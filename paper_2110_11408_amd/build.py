@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhf.so")
 SOURCES = ["scan.hip", "bin.hip", "density.hip", "fof.hip", "candidates.hip", "compaso.hip",
-           "hf_api.hip", "serve.hip"]
+           "stats.hip", "hf_api.hip", "serve.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=off",

@@ -348,10 +348,31 @@ RadixPlan radix_plan(int64_t n, const Geo &g) {
     return r;
 }
 
-int64_t radix_hist_len(int64_t n, const Geo &g) {
-    const RadixPlan r = radix_plan(n, g);
+int64_t radix_hist_len(int64_t n, const Geo &) {
+    // room for the widest digit, so that every sort of up to n keys fits
     const int64_t ntiles = (n + kTile - 1) / kTile;
-    return ((int64_t)1 << r.D) * (ntiles > 0 ? ntiles : 1) + 1;
+    return ((int64_t)1 << kRadixMaxBits) * (ntiles > 0 ? ntiles : 1) + 1;
+}
+
+uint64_t *radix_sort_keys(uint64_t *a, uint64_t *b, int64_t n, int lo, int bits, Work &w, hipStream_t s) {
+    if (n <= 1 || bits <= 0) return a;
+    const int passes = (bits + kRadixMaxBits - 1) / kRadixMaxBits;
+    const int D = (bits + passes - 1) / passes;
+    const int64_t ntiles = (n + kTile - 1) / kTile;
+    const int64_t hl = ((int64_t)1 << D) * ntiles;
+    uint64_t *cur = a, *nxt = b;
+    for (int p = 0; p < passes; p++) {
+        const int shift = lo + p * D;
+        hipLaunchKernelGGL(k_radix_count, dim3((unsigned)ntiles), dim3(256), 0, s, cur, n, shift, D, ntiles,
+                           w.rhist);
+        scan_u32(w.rhist, w.rscan, hl, w.scan_tmp, s);
+        hipLaunchKernelGGL(k_radix_scatter<true>, dim3((unsigned)ntiles), dim3(256), 0, s, cur, nullptr, n, shift,
+                           D, ntiles, w.rscan, nxt, nullptr);
+        uint64_t *t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    return cur;
 }
 
 void launch_bin(const float *pos, int64_t n, const Geo &g, Work &w, hipStream_t s) {

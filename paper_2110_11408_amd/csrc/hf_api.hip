@@ -130,7 +130,7 @@ struct Carver {
     }
 };
 
-size_t carve(char *base, int64_t n, int64_t ncell, int nsub, int64_t rhl, Work *w) {
+size_t carve(char *base, int64_t n, int64_t ncell, int nsub, int64_t rhl, bool extra, Work *w) {
     Carver c{base};
     int64_t n1 = n + 1;
     w->cnt = c.take<uint32_t>(ncell + 1);
@@ -193,14 +193,16 @@ size_t carve(char *base, int64_t n, int64_t ncell, int nsub, int64_t rhl, Work *
     w->scan_tmp = c.take<uint32_t>(hf::scan_tmp_words(scan_len + 1));
     w->counters = c.take<int32_t>(16);
     w->err = c.take<int32_t>(4);
+    w->gcom = extra ? c.take<double>(6 * n1) : nullptr;
+    w->ordk = extra ? c.take<int32_t>(n1) : nullptr;
     return c.off + 256;
 }
 
-hf_status prepare(Lane *c, int64_t n, const Geo &g, Work *w) {
+hf_status prepare(Lane *c, int64_t n, const Geo &g, Work *w, bool extra) {
     int64_t ncell = (int64_t)g.nc * g.nc * g.nc;
     const int nsub = g.ksub * g.ksub * g.ksub;
     const int64_t rhl = hf::radix_hist_len(n, g);
-    size_t need = carve(nullptr, n, ncell, nsub, rhl, w);
+    size_t need = carve(nullptr, n, ncell, nsub, rhl, extra, w);
     HIP_OK(c, hipSetDevice(c->device));
     if (need > c->arena_bytes) {
         if (c->arena) {
@@ -217,7 +219,7 @@ hf_status prepare(Lane *c, int64_t n, const Geo &g, Work *w) {
         }
         c->arena_bytes = want;
     }
-    carve((char *)c->arena, n, ncell, nsub, rhl, w);
+    carve((char *)c->arena, n, ncell, nsub, rhl, extra, w);
     c->stats = hf_stats{};
     c->stats.n_cells = ncell;
     return HF_OK;
@@ -302,7 +304,7 @@ hf_status run_compaso(Lane *c, int64_t n, const Geo &g, Work &w, int32_t *halo_i
 }
 
 hf_status begin(Lane *c, const float *pos, int64_t n, const hf_params *p, Geo *g, Work *w,
-                hipStream_t s) {
+                hipStream_t s, bool extra = false) {
     if (!c) return HF_ERR_INVALID;
     c->err.clear();
     if (!p) return fail(c, HF_ERR_INVALID, "params is NULL");
@@ -318,7 +320,7 @@ hf_status begin(Lane *c, const float *pos, int64_t n, const hf_params *p, Geo *g
     hf_status st = make_geo(c, p, n, g);
     if (st != HF_OK) return st;
     if (!pos) return fail(c, HF_ERR_INVALID, "pos is NULL");
-    st = prepare(c, n, *g, w);
+    st = prepare(c, n, *g, w, extra);
     if (st != HF_OK) return st;
     hf::fill_i32(w->counters, 0, 16, s);
     hf::fill_i32(w->err, 0, 4, s);
@@ -375,7 +377,7 @@ size_t lane_arena_bytes(const hf_params *p, int64_t n) {
     Work w;
     if (make_geo(nullptr, p, n, &g) != HF_OK) return 0;
     const int64_t ncell = (int64_t)g.nc * g.nc * g.nc;
-    const size_t need = carve(nullptr, n, ncell, g.ksub * g.ksub * g.ksub, hf::radix_hist_len(n, g), &w);
+    const size_t need = carve(nullptr, n, ncell, g.ksub * g.ksub * g.ksub, hf::radix_hist_len(n, g), false, &w);
     return need + need / 8;
 }
 
@@ -579,6 +581,71 @@ hf_status hf_compaso(hf_ctx *ctx, const float *pos, const float *density, const 
     c->stats.ms_bin = elapsed(c->ev[0], c->ev[1]);
     c->stats.ms_total = elapsed(c->ev[0], c->ev[8]);
     return st;
+}
+
+hf_status hf_halo_stats(hf_ctx *ctx, const float *pos, const float *density, const int32_t *halo_id,
+                        int64_t n, const hf_params *p, int64_t n_halos, hf_halo_summary *stats,
+                        int32_t *group_start, int32_t *group_members, void *stream) {
+    Lane *c = ctx ? &ctx->main : nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    Geo g, g2;
+    Work w;
+    if (n > 0 && (!density || !halo_id)) return fail(c, HF_ERR_INVALID, "density / halo_id is NULL");
+    if (n_halos < 0 || (n_halos > 0 && !stats)) return fail(c, HF_ERR_INVALID, "bad stats / n_halos");
+    hf_status st = begin(c, pos, n, p, &g, &w, s, true);
+    if (st != HF_OK) return st;
+    if (n == 0) {
+        if (n_halos != 0) return fail(c, HF_ERR_INVALID, "n_halos must be 0 for an empty input");
+        return HF_OK;
+    }
+    // level 2: the same steps with delta_l2 in place of delta_l1
+    hf_params p2 = *p;
+    p2.delta_l1 = p->delta_l2;
+    st = make_geo(c, &p2, n, &g2);
+    if (st != HF_OK) return st;
+    hf::launch_gather_density(density, n, w, s);
+    hf::launch_keys_from_labels(halo_id, n, w, s);
+    HIP_OK(c, hipEventRecord(c->ev[2], s));
+    st = check_pos_flags(c, w, s);
+    if (st != HF_OK) return st;
+    HIP_OK(c, hipEventRecord(c->ev[3], s));
+    hf::launch_segment(n, w, s);
+    uint32_t G32 = 0, M32 = 0;
+    HIP_OK(c, hipMemcpyAsync(&G32, w.gidx + n, sizeof(G32), hipMemcpyDeviceToHost, s));
+    HIP_OK(c, hipMemcpyAsync(&M32, w.goff + n, sizeof(M32), hipMemcpyDeviceToHost, s));
+    HIP_OK(c, hipStreamSynchronize(s));
+    const int64_t G = G32, M = M32;
+    if (G != n_halos) return fail(c, HF_ERR_INVALID, "n_halos differs from the number of halo_id labels");
+    c->stats.n_groups = G;
+    c->stats.n_members = M;
+    hf::launch_segment_groups(n, G, w, s);
+    HIP_OK(c, hipEventRecord(c->ev[4], s));
+    hf::launch_candidates(n, g2, w, s);
+    hf::scan_u32(w.gccnt, w.gcoff, G, w.scan_tmp, s);
+    uint32_t NC32 = 0;
+    HIP_OK(c, hipMemcpyAsync(&NC32, w.gcoff + G, sizeof(NC32), hipMemcpyDeviceToHost, s));
+    HIP_OK(c, hipStreamSynchronize(s));
+    hf::launch_candidates_sort(n, G, NC32, w, s);
+    uint32_t NGC32 = 0;
+    HIP_OK(c, hipMemcpyAsync(&NGC32, w.gcidx + G, sizeof(NGC32), hipMemcpyDeviceToHost, s));
+    HIP_OK(c, hipStreamSynchronize(s));
+    HIP_OK(c, hipEventRecord(c->ev[5], s));
+    hf::launch_accept(NGC32, g2, w, s);
+    HIP_OK(c, hipEventRecord(c->ev[6], s));
+    hf::launch_assign(n, g2, w, s);
+    HIP_OK(c, hipEventRecord(c->ev[7], s));
+    hf::launch_halo_stats(n, G, M, g2, p->particle_mass, pos, halo_id, w, stats, group_start, group_members, s);
+    HIP_OK(c, hipEventRecord(c->ev[8], s));
+    HIP_OK(c, hipStreamSynchronize(s));
+    c->stats.n_candidates = NC32;
+    c->stats.ms_bin = elapsed(c->ev[0], c->ev[1]);
+    c->stats.ms_segment = elapsed(c->ev[3], c->ev[4]);
+    c->stats.ms_candidates = elapsed(c->ev[4], c->ev[5]);
+    c->stats.ms_accept = elapsed(c->ev[5], c->ev[6]);
+    c->stats.ms_assign = elapsed(c->ev[6], c->ev[7]);
+    c->stats.ms_output = elapsed(c->ev[7], c->ev[8]);
+    c->stats.ms_total = elapsed(c->ev[0], c->ev[8]);
+    return HF_OK;
 }
 
 hf_status hf_find(hf_ctx *ctx, const float *pos, int64_t n, const hf_params *p, float *density,

@@ -158,6 +158,8 @@ struct Work {
     uint32_t *tflag, *tpos;                            // table rows (original index space)
     uint32_t *hist;                                    // R search histograms
     uint32_t *scan_tmp;
+    double *gcom;                    // halo statistics only: centres per group (6 doubles)
+    int32_t *ordk;                   // halo statistics only: group ordinal per key
     int32_t *counters;                                 // small device counters
     int32_t *err;
 };
@@ -170,8 +172,16 @@ void scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipSt
 int64_t scan_tmp_words(int64_t n);
 
 void launch_bin(const float *pos, int64_t n, const Geo &g, Work &w, hipStream_t s);
+// Level 2 summaries and position statistics after an L2 pass (stats.hip).
+void launch_halo_stats(int64_t n, int64_t G, int64_t M, const Geo &g, double particle_mass, const float *pos,
+                       const int32_t *halo_id, Work &w, hf_halo_summary *out, int32_t *group_start,
+                       int32_t *group_members, hipStream_t s);
 // Length of the radix count arrays for n particles on grid g.
 int64_t radix_hist_len(int64_t n, const Geo &g);
+// Stable LSD radix sort of n 64-bit keys a[] by their bits [lo, lo + bits),
+// using b[] as the second buffer and w's count arrays; returns the buffer
+// (a or b) that holds the result.
+uint64_t *radix_sort_keys(uint64_t *a, uint64_t *b, int64_t n, int lo, int bits, Work &w, hipStream_t s);
 void launch_subtab(int64_t n, int64_t ndc, const Geo &g, Work &w, hipStream_t s);
 void launch_density(int64_t n, const Geo &g, Work &w, float *dens_out, hipStream_t s);
 void launch_count_pairs(int64_t n, const Geo &g, Work &w, unsigned long long *total, hipStream_t s);

@@ -92,6 +92,7 @@ def _c_layout():
               "hf_halo": [f for f, _ in _lib.HfHalo._fields_],
               "hf_stats": [f for f, _ in _lib.HfStats._fields_],
               "hf_request": [f for f, _ in _lib.HfRequest._fields_],
+              "hf_halo_summary": [f for f, _ in _lib.HfHaloSummary._fields_],
               "hf_result": [f for f, _ in _lib.HfResult._fields_]}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hf.h"', "int main(void) {"]
     for s, fs in fields.items():
@@ -115,7 +116,8 @@ def _c_layout():
 def test_ctypes_structs_match_c_layout():
     c = _c_layout()
     for s, cls in (("hf_params", _lib.HfParams), ("hf_halo", _lib.HfHalo), ("hf_stats", _lib.HfStats),
-                   ("hf_request", _lib.HfRequest), ("hf_result", _lib.HfResult)):
+                   ("hf_request", _lib.HfRequest), ("hf_result", _lib.HfResult),
+                   ("hf_halo_summary", _lib.HfHaloSummary)):
         assert c[(s, "size")] == ctypes.sizeof(cls), s
         for f, _ in cls._fields_:
             assert c[(s, f)] == getattr(cls, f).offset, (s, f)
