@@ -10,7 +10,8 @@ dominant kernel (its average duration measured with HIP events on the stream it
 runs on, over the timed steps) and the FP64 CPU oracle timed on a bounded
 sample of the same generator.
 
-Two more workloads are reported in the same line:
+The same box also times hf_halo_stats (level 2 inside every L1 halo and the
+position statistics).  Two more workloads are reported in the same line:
   batched  96 periodic sub-boxes of side log-uniform in 24..160 in one
            hf_find_batch call, against one hf_find call per box;
   serving  a Poisson stream of requests (boxes of 1e4..1e7 particles, log-uniform,
@@ -184,6 +185,26 @@ def _batched(ctx, np, torch, _lib, synth, reps=3, lanes=4):
             "reps": reps}
 
 
+def _halo_stats(ctx, pos_d, p, out, np, torch, reps=3):
+    """hf_halo_stats on the benchmark box: level 2 inside every L1 halo and the
+    Table 1 position statistics (fresh binning included)."""
+    nh = out["n_halos"]
+    ctx.halo_stats(pos_d, out["density"], out["halo_id"], p, nh)
+    torch.cuda.synchronize()
+    t = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        res = ctx.halo_stats(pos_d, out["density"], out["halo_id"], p, nh)
+        torch.cuda.synchronize()
+        t.append(time.perf_counter() - t0)
+    st = ctx.stats()
+    ms = float(np.median(t)) * 1e3
+    return {"ms": ms, "value": len(pos_d) / (ms / 1e3), "unit": "particles/s", "n_halos": nh,
+            "n_l2": int(np.sum(res["n_l2"])), "reps": reps,
+            "stages_ms": {k[3:]: st[k] for k in ("ms_bin", "ms_segment", "ms_candidates", "ms_accept",
+                                                  "ms_assign", "ms_output", "ms_total")}}
+
+
 def _fifo_latency(arrivals, service):
     """Latencies of a one-at-a-time FIFO server with the given service times."""
     done, lat = 0.0, []
@@ -351,6 +372,7 @@ def main():
                    "n_dense_cells": st["n_dense_cells"], "n_dense_chunks": st["n_dense_chunks"],
                    "n_sparse": st["n_sparse"], "n_hard": st["n_hard"]},
     }
+    res["halo_stats"] = _halo_stats(ctx, pos_d, p, out, np, torch)
     if not args.no_batched:
         res["batched"] = _batched(ctx, np, torch, _lib, synth)
     if not args.no_serving:

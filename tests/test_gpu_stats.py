@@ -110,3 +110,31 @@ def test_halo_stats_argument_errors(ctx):
     zero = torch.zeros_like(f["halo_id"])
     out = ctx.halo_stats(t, f["density"], zero, p, 0)
     assert len(out["id"]) == 0
+
+
+def test_halo_stats_full_size_256_sampled(ctx):
+    """The 256^3 box: every halo's level 2 and statistics depend on its own
+    members only, so the oracle run on a labelling restricted to 200 halos (the
+    20 largest and 180 random ones) must reproduce their rows exactly."""
+    import torch
+    from paper_2110_11408_amd import _lib
+    pos, L, _ = synth.named_box("plain256")
+    _say(f"[gpu] hf_halo_stats full size n={len(pos)}")
+    p = _lib.default_params(box=L)
+    t = torch.from_numpy(pos).cuda()
+    f = ctx.find(t, p, halos_cap=len(pos) // 64)
+    st = ctx.halo_stats(t, f["density"], f["halo_id"], p, f["n_halos"], want_members=False)
+    hid = f["halo_id"].cpu().numpy()
+    dens = f["density"].cpu().numpy().astype(np.float64)
+    del t, f
+    torch.cuda.empty_cache()
+    rng = np.random.default_rng(256)
+    nh = len(st["id"])
+    pick = np.union1d(np.argsort(-st["n"], kind="stable")[:20], rng.choice(nh, 180, replace=False))
+    keep = np.isin(hid, st["id"][pick])
+    ref = oracle.l2_stats(pos, dens, np.where(keep, hid, 0), box=L)
+    np.testing.assert_array_equal(ref["id"], st["id"][pick])
+    for k in ("n", "n_l2", "l2max_nucleus", "l2max_n"):
+        np.testing.assert_array_equal(st[k][pick], ref[k], err_msg=k)
+    for k in ("x_com", "x_l2com", "l2_mass", "r_pct", "vcirc_max", "rvcirc_max"):
+        np.testing.assert_array_equal(st[k][pick], ref[k].astype(np.float32), err_msg=k)
