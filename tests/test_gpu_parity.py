@@ -284,3 +284,39 @@ def test_separate_payload_sort_gives_same_result(ctx):
                            "table": {"id": b["table"]["id"], "nucleus": b["table"]["nucleus"],
                                      "l0": b["table"]["l0_id"], "n": b["table"]["n"],
                                      "ienc": b["table"]["n_enclosed"]}})
+
+
+def test_full_size_512_sampled(ctx):
+    """The 512^3 box (134M particles, 70 % in haloes up to 200 000 particles, in
+    pairs and triples): sampled densities against the oracle, the L0 membership
+    rule and labels, and the oracle's CompaSO on sampled L0 groups (the largest
+    below 300 000 members, whose histograms do not fit in LDS, and random ones)
+    with the GPU densities."""
+    pos, L, _ = synth.named_box("large512")
+    _say(f"[gpu] hf_find large512 n={len(pos)}")
+    g = gpu_find(ctx, pos, box=L)
+    _say("[gpu] large512: sampled densities")
+    rng = np.random.default_rng(512)
+    which = np.unique(np.concatenate([rng.choice(len(pos), 20000, replace=False),
+                                      np.argsort(g["density"])[-2000:]]))
+    ref = oracle.density_sample(pos, which, box=L)
+    assert len(density_violations(g["density"][which], ref)) == 0
+    l0 = g["l0"]
+    dens = g["density"].astype(np.float64)
+    assert np.all((l0 > 0) == (dens > 60.0))
+    labels, first, counts = np.unique(l0[l0 > 0], return_index=True, return_counts=True)
+    assert np.all(labels == np.nonzero(l0 > 0)[0][first] + 1)      # 1 + smallest index
+    _say("[gpu] large512: CompaSO on sampled groups")
+    ok = counts < 300000
+    big = labels[ok][np.argsort(counts[ok])[-8:]]
+    pick = np.unique(np.concatenate([big, rng.choice(labels, 100, replace=False)]))
+    pick = pick[np.isin(pick, labels[ok])]
+    mask = np.isin(l0, pick)
+    res = oracle.compaso(pos, dens, np.where(mask, l0, 0).astype(np.int32), box=L)
+    np.testing.assert_array_equal(g["halo_id"][mask], res["halo_id"][mask])
+    tab = g["table"]
+    in_pick = np.isin(tab["l0_id"], pick)
+    np.testing.assert_array_equal(tab["id"][in_pick], res["table"]["id"])
+    np.testing.assert_array_equal(tab["n"][in_pick], res["table"]["n"])
+    np.testing.assert_array_equal(tab["n_enclosed"][in_pick], res["table"]["ienc"])
+    assert counts[np.isin(labels, big)].max() > 12288
