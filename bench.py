@@ -40,6 +40,8 @@ WORKLOADS = {
                 "half NFW haloes (c=8, R200) of 35..20000 particles (dn/dN ~ N^-1.9), 20% of "
                 "haloes in pairs at 0.5-1.5 R200; b=0.4, l=0.25, Delta_L0=60, Delta_L1=200, N>=35",
     "plain64": "64^3 = 262,144 FP32 particles, periodic box 64, same generator without pairs",
+    "large512": "512^3 = 134,217,728 FP32 particles, periodic box 512, 70% in NFW haloes (c=8) of "
+                "35..200000 particles, 30% of haloes in pairs and 15% in triples at 0.3-1.2 R200",
 }
 
 
