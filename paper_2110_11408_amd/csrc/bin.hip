@@ -6,12 +6,13 @@
 // [n][3] array, so the library builds the order itself:
 //   1. key = cell * k^3 + sub-cell per particle (range check of the input);
 //   2. least-significant-digit radix sort of (key, original index), digits of
-//      at most 11 bits; key and index share one 64-bit word when they fit.
+//      at most 8 bits; key and index share one 64-bit word when they fit.
 //      Each pass: a block counts the digits of its tile of 4096 consecutive
 //      elements; an exclusive scan of the digit-major [digit][tile] counts
 //      gives every (digit, tile) its output offset; the tile is then walked
 //      again in order, each element's rank among equal digits coming from the
-//      ballots of its digit bits (lower lanes first), so the pass is stable;
+//      ballots of its digit bits (lower lanes first), so the pass is stable,
+//      and written out through LDS in digit order (coalesced runs);
 //   3. the sorted order writes two float4 streams per particle:
 //        spos = (x, y, z, original index bits)    -- the paper's float quad with
 //               the index stored bitwise (Sec. 2.3.3), used by FP64 predicates;
@@ -69,7 +70,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_key(const float *__restrict__ po
     key[i] = ib > 0 ? (kk << ib) | (uint64_t)i : kk;
 }
 
-constexpr int kRadixMaxBits = 11;
+constexpr int kRadixMaxBits = 8;
 constexpr int kRadixWaves = 4;                      // wavefronts per tile
 constexpr int kRadixIters = 16;                     // 64-element steps per wavefront
 constexpr int64_t kTile = 64 * kRadixWaves * kRadixIters;  // 4096 elements per tile
@@ -117,18 +118,41 @@ __global__ __launch_bounds__(256) void k_radix_count(const uint64_t *__restrict_
     for (int d = threadIdx.x; d < nd; d += 256) hist[(int64_t)d * ntiles + t] = h[d];
 }
 
-// Stable scatter of one tile.  Offsets of wavefront w for digit d: the scanned
-// (d, tile) offset plus the counts of d in wavefronts 0..w-1; inside a
-// wavefront, steps in order and lanes in order.
+// Block-wide exclusive scan of one value per thread (256 threads).
+__device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t *s_tot) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t inc = v;
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += y;
+    }
+    if (lane == 63) s_tot[w] = inc;
+    __syncthreads();
+    uint32_t pre = 0;
+    for (int x = 0; x < w; x++) pre += s_tot[x];
+    return pre + inc - v;
+}
+
+// Stable scatter of one tile.  Every element's position inside the tile's
+// digit-sorted order is its digit's start in the tile plus the count of equal
+// digits before it (earlier wavefronts, earlier steps, lower lanes); the tile
+// is first placed in LDS in that order and then written out in order, so
+// consecutive threads write consecutive addresses of one digit's run (the
+// digit's global offset for this tile comes from the scanned counts).
 template <bool kPacked>
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t *__restrict__ kin,
                                                        const uint32_t *__restrict__ vin, int64_t n, int shift,
                                                        int D, int64_t ntiles, const uint32_t *__restrict__ hscan,
                                                        uint64_t *__restrict__ kout, uint32_t *__restrict__ vout) {
     __shared__ uint32_t o[kRadixWaves][1 << kRadixMaxBits];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __shared__ uint32_t lstart[1 << kRadixMaxBits], gbase[1 << kRadixMaxBits];
+    __shared__ uint32_t s_tot[kRadixWaves];
+    __shared__ uint64_t sk[kTile];
+    __shared__ uint32_t sv[kPacked ? 1 : kTile];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, tid = threadIdx.x;
     const int64_t t = blockIdx.x;
     const int nd = 1 << D;
+    const uint32_t dmask = (uint32_t)(nd - 1);
     for (int d = lane; d < nd; d += 64) o[w][d] = 0u;
     const int64_t base = t * kTile + (int64_t)w * (64 * kRadixIters) + lane;
     uint64_t k[kRadixIters];
@@ -143,17 +167,23 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t *__restric
 #pragma unroll
     for (int it = 0; it < kRadixIters; it++) {
         const bool act = base + it * 64 < n;
-        const uint32_t d = (uint32_t)(k[it] >> shift) & (uint32_t)(nd - 1);
+        const uint32_t d = (uint32_t)(k[it] >> shift) & dmask;
         const uint64_t m = digit_peers(d, D, __ballot(act));
         if (act && (m & lanes_below(lane)) == 0ull) o[w][d] += (uint32_t)__popcll(m);
     }
     __syncthreads();
-    for (int d = threadIdx.x; d < nd; d += 256) {
-        uint32_t b = hscan[(int64_t)d * ntiles + t];
-#pragma unroll
+    // digit starts inside the tile, then every wavefront's start per digit
+    uint32_t tot = 0;
+    if (tid < nd)
+        for (int x = 0; x < kRadixWaves; x++) tot += o[x][tid];
+    const uint32_t ex = block_scan_excl(tot, s_tot);
+    if (tid < nd) {
+        lstart[tid] = ex;
+        gbase[tid] = hscan[(int64_t)tid * ntiles + t];
+        uint32_t b = ex;
         for (int x = 0; x < kRadixWaves; x++) {
-            const uint32_t c = o[x][d];
-            o[x][d] = b;
+            const uint32_t c = o[x][tid];
+            o[x][tid] = b;
             b += c;
         }
     }
@@ -161,17 +191,27 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t *__restric
 #pragma unroll
     for (int it = 0; it < kRadixIters; it++) {
         const bool act = base + it * 64 < n;
-        const uint32_t d = (uint32_t)(k[it] >> shift) & (uint32_t)(nd - 1);
+        const uint32_t d = (uint32_t)(k[it] >> shift) & dmask;
         const uint64_t m = digit_peers(d, D, __ballot(act));
         const uint32_t start = act ? o[w][d] : 0u;
         if (act) {
-            const uint32_t dst = start + (uint32_t)__popcll(m & lanes_below(lane));
-            kout[dst] = k[it];
-            if (!kPacked) vout[dst] = v[it];
+            const uint32_t lp = start + (uint32_t)__popcll(m & lanes_below(lane));
+            sk[lp] = k[it];
+            if (!kPacked) sv[lp] = v[it];
         }
         // LDS operations of one wavefront complete in order: every lane of the
         // group has read `start` before the leader's update lands
         if (act && (m & lanes_below(lane)) == 0ull) o[w][d] = start + (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    const int64_t rem = n - t * kTile;
+    const int cnt = rem < kTile ? (int)rem : (int)kTile;
+    for (int lp = tid; lp < cnt; lp += 256) {
+        const uint64_t key = sk[lp];
+        const uint32_t d = (uint32_t)(key >> shift) & dmask;
+        const uint32_t dst = gbase[d] + ((uint32_t)lp - lstart[d]);
+        kout[dst] = key;
+        if (!kPacked) vout[dst] = sv[lp];
     }
 }
 
