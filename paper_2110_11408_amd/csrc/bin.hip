@@ -285,16 +285,31 @@ __global__ __launch_bounds__(kBlock) void k_cell_offsets(int64_t n, int64_t ncel
     }
 }
 
-// Flags per sorted particle: head of a dense chunk, head of a dense cell, sparse.
+// Flags per sorted particle: head of a dense chunk, head of a dense cell,
+// sparse.  A wavefront takes 64 consecutive particles and finds the bounds of
+// their cells from the cell ids of neighbouring particles (cell changes are
+// found by ballot); only a cell that starts before, or ends after, the
+// wavefront's particles reads its offset from the grid.
 __global__ __launch_bounds__(kBlock) void k_bin_flags(int64_t n, const float4 *__restrict__ sloc,
                                                       const uint32_t *__restrict__ off,
                                                       uint32_t *__restrict__ f_chunk,
                                                       uint32_t *__restrict__ f_dcell,
                                                       uint32_t *__restrict__ f_sparse) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t c = __float_as_uint(sloc[i].w);
-    const uint32_t a = off[c], b = off[c + 1];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int64_t s0 = i - lane;
+    const bool act = i < n;
+    const uint32_t c = act ? __float_as_uint(sloc[i].w) : 0xffffffffu;
+    uint32_t cprev = __shfl_up(c, 1, 64), cnext = __shfl_down(c, 1, 64);
+    if (lane == 0) cprev = s0 > 0 ? __float_as_uint(sloc[s0 - 1].w) : 0xfffffffeu;
+    if (lane == 63) cnext = s0 + 64 < n ? __float_as_uint(sloc[s0 + 64].w) : 0xfffffffdu;
+    const uint64_t heads = __ballot(act && c != cprev);
+    const uint64_t tails = __ballot(act && c != cnext);
+    if (!act) return;
+    const uint64_t le = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
+    const uint64_t h = heads & le, t = tails & ~(le >> 1);  // heads at or below, tails at or above
+    const uint32_t a = h ? (uint32_t)(s0 + 63 - __clzll((long long)h)) : off[c];
+    const uint32_t b = t ? (uint32_t)(s0 + __ffsll((unsigned long long)t)) : off[c + 1];
     const bool dense = b - a >= (uint32_t)kDenseMin;
     f_chunk[i] = dense && (((uint32_t)i - a) % 64u == 0u);
     f_dcell[i] = dense && (uint32_t)i == a;
@@ -338,17 +353,17 @@ __global__ __launch_bounds__(kBlock) void k_sub_init(int64_t ndc, int nsub,
 
 __global__ __launch_bounds__(kBlock) void k_sub_starts(int64_t n, int nsub,
                                                        const float4 *__restrict__ sloc,
-                                                       const uint32_t *__restrict__ off,
+                                                       const uint32_t *__restrict__ f_sparse,
                                                        const uint16_t *__restrict__ ssub,
                                                        const uint32_t *__restrict__ cellmap,
                                                        uint32_t *__restrict__ subtab) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || f_sparse[i]) return;
     const uint32_t c = __float_as_uint(sloc[i].w);
-    const uint32_t a = off[c], b = off[c + 1];
-    if (b - a < (uint32_t)kDenseMin) return;
     const uint16_t s = ssub[i];
-    if ((uint32_t)i == a || ssub[i - 1] != s) subtab[(int64_t)cellmap[c] * (nsub + 1) + s] = (uint32_t)i;
+    // first particle of its cell, or of a new sub-cell inside the cell
+    if (i == 0 || __float_as_uint(sloc[i - 1].w) != c || ssub[i - 1] != s)
+        subtab[(int64_t)cellmap[c] * (nsub + 1) + s] = (uint32_t)i;
 }
 
 __global__ __launch_bounds__(kBlock) void k_sub_fix(int64_t ndc, int nsub, uint32_t *__restrict__ subtab) {
@@ -461,7 +476,7 @@ void launch_subtab(int64_t n, int64_t ndc, const Geo &g, Work &w, hipStream_t s)
     const int nsub = g.ksub * g.ksub * g.ksub;
     hipLaunchKernelGGL(k_sub_init, dim3(blocks(ndc)), dim3(kBlock), 0, s, ndc, nsub, w.dcells, w.off,
                        w.subtab);
-    hipLaunchKernelGGL(k_sub_starts, dim3(blocks(n)), dim3(kBlock), 0, s, n, nsub, w.sloc, w.off, w.ssub,
+    hipLaunchKernelGGL(k_sub_starts, dim3(blocks(n)), dim3(kBlock), 0, s, n, nsub, w.sloc, w.f_sparse, w.ssub,
                        w.cnt, w.subtab);
     hipLaunchKernelGGL(k_sub_fix, dim3(blocks(ndc)), dim3(kBlock), 0, s, ndc, nsub, w.subtab);
 }

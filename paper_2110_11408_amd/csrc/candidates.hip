@@ -84,7 +84,7 @@ __global__ __launch_bounds__(kBlock) void k_submax(int64_t nslots, int nsub,
 // the floor is flagged as a hard case.
 __global__ __launch_bounds__(kBlock) void k_cand_quick(int64_t n, Geo g, const float4 *__restrict__ sloc,
                                                        const float4 *__restrict__ spos,
-                                                       const uint32_t *__restrict__ off,
+                                                       const uint32_t *__restrict__ f_sparse,
                                                        const uint16_t *__restrict__ ssub,
                                                        const uint32_t *__restrict__ cellmap,
                                                        const int32_t *__restrict__ subarg,
@@ -102,7 +102,7 @@ __global__ __launch_bounds__(kBlock) void k_cand_quick(int64_t n, Geo g, const f
         is_hard = true;
         const float4 li = sloc[i];
         const uint32_t c = __float_as_uint(li.w);
-        if (off[c + 1] - off[c] >= (uint32_t)kDenseMin) {
+        if (!f_sparse[i]) {
             const int nsub = g.ksub * g.ksub * g.ksub;
             const int32_t top = subarg[(int64_t)cellmap[c] * (nsub + 1) + ssub[i]];
             if (top != (int32_t)i && gkey[top] == key) {
@@ -269,7 +269,7 @@ void launch_candidates(int64_t n, const Geo &g, Work &w, hipStream_t s) {
     const unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
     // candidate flags live in the owner array until the assignment overwrites
     // it; the hard-case flags and their scan reuse the dense-cell flag arrays
-    hipLaunchKernelGGL(k_cand_quick, dim3(blocks), dim3(kBlock), 0, s, n, g, w.sloc, w.spos, w.off, w.ssub,
+    hipLaunchKernelGGL(k_cand_quick, dim3(blocks), dim3(kBlock), 0, s, n, g, w.sloc, w.spos, w.f_sparse, w.ssub,
                        w.cnt, w.subarg, w.dens_s, w.gkey, w.owner, w.f_dcell);
     scan_u32(w.f_dcell, w.s_dcell, n, w.scan_tmp, s);
     hipLaunchKernelGGL(k_hard_list, dim3(blocks), dim3(kBlock), 0, s, n, w.f_dcell, w.s_dcell, w.hardlist);

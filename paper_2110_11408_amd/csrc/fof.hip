@@ -175,7 +175,7 @@ __global__ __launch_bounds__(kBlock) void k_fof_init(int64_t n, Geo g, const flo
 // Phase A: members of dense cells point at the first member of their sub-cell
 // (a valid forest: every parent is a member with a smaller sorted index).
 __global__ __launch_bounds__(kBlock) void k_fof_phase_a(int64_t n, Geo g, const float4 *__restrict__ sloc,
-                                                        const uint32_t *__restrict__ off,
+                                                        const uint32_t *__restrict__ f_sparse,
                                                         const uint16_t *__restrict__ ssub,
                                                         const uint32_t *__restrict__ cellmap,
                                                         const uint32_t *__restrict__ subtab,
@@ -184,8 +184,8 @@ __global__ __launch_bounds__(kBlock) void k_fof_phase_a(int64_t n, Geo g, const 
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     if (!is_member(dens_s, i, g.dl0)) return;
+    if (f_sparse[i]) return;
     const uint32_t c = __float_as_uint(sloc[i].w);
-    if (off[c + 1] - off[c] < (uint32_t)kDenseMin) return;
     const int nsub = g.ksub * g.ksub * g.ksub;
     uint32_t f = subtab[(int64_t)cellmap[c] * (nsub + 1) + ssub[i]];
     while (f < (uint32_t)i && !is_member(dens_s, f, g.dl0)) f++;
@@ -490,7 +490,7 @@ __global__ __launch_bounds__(kBlock) void k_keys_from_labels(int64_t n, const in
 
 void launch_fof(int64_t n, const Geo &g, Work &w, hipStream_t s) {
     hipLaunchKernelGGL(k_fof_init, grid(n), dim3(kBlock), 0, s, n, g, w.dens_s, w.parent);
-    hipLaunchKernelGGL(k_fof_phase_a, grid(n), dim3(kBlock), 0, s, n, g, w.sloc, w.off, w.ssub, w.cnt,
+    hipLaunchKernelGGL(k_fof_phase_a, grid(n), dim3(kBlock), 0, s, n, g, w.sloc, w.f_sparse, w.ssub, w.cnt,
                        w.subtab, w.dens_s, w.parent);
     if (w.nchunks > 0)
         hipLaunchKernelGGL(k_fof_dense, dim3((unsigned)((w.nchunks + 3) / 4)), dim3(kBlock), 0, s, w.nchunks, g,
