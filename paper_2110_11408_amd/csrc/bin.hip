@@ -274,7 +274,10 @@ __global__ __launch_bounds__(kBlock) void k_cell_offsets(int64_t n, int64_t ncel
     // each wavefront reads only its own row, written above by the same
     // wavefront (LDS operations of a wavefront complete in order)
     __builtin_amdgcn_wave_barrier();
-    for (int64_t q = lane; q < G; q += 64) {
+    // four consecutive cells per lane and iteration; the cells before the first
+    // 16-byte boundary of off[] are written one by one
+    const int64_t head = ((4 - ((first & 3))) & 3) < G ? ((4 - (first & 3)) & 3) : G;
+    for (int64_t q = lane; q < head; q += 64) {
         int a = 0, b = 63;  // last j with pre[j] <= q
         while (a < b) {
             const int mid = (a + b + 1) >> 1;
@@ -282,6 +285,25 @@ __global__ __launch_bounds__(kBlock) void k_cell_offsets(int64_t n, int64_t ncel
             else b = mid - 1;
         }
         off[first + q] = (uint32_t)(s0 + a);
+    }
+    for (int64_t q4 = head + 4 * (int64_t)lane; q4 < G; q4 += 256) {
+        int a = 0, b = 63;  // owner of cell q4
+        while (a < b) {
+            const int mid = (a + b + 1) >> 1;
+            if (pre[w][mid] <= q4) a = mid;
+            else b = mid - 1;
+        }
+        uint32_t v[4];
+        v[0] = (uint32_t)(s0 + a);
+        for (int u = 1; u < 4; u++) {
+            while (a < 63 && pre[w][a + 1] <= q4 + u) a++;
+            v[u] = (uint32_t)(s0 + a);
+        }
+        if (q4 + 4 <= G) {
+            *reinterpret_cast<uint4 *>(off + first + q4) = make_uint4(v[0], v[1], v[2], v[3]);
+        } else {
+            for (int u = 0; u < 4 && q4 + u < G; u++) off[first + q4 + u] = v[u];
+        }
     }
 }
 
