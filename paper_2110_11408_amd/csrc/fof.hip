@@ -165,6 +165,74 @@ __device__ __forceinline__ bool stream_range(int32_t *parent, const float *__res
     return joined;
 }
 
+// All sparse neighbour cells of a chunk at once: lane t < 27 holds stencil
+// cell t's range [la, lb) and whether it is to be visited; their particles are
+// numbered through a prefix sum and loaded 64 at a time (each lane finds its
+// particle's cell in the per-wavefront table spre/sla), then broadcast in
+// order and joined to the lanes they link.
+__device__ __forceinline__ void stream_sparse_cells(int32_t *parent, const float *__restrict__ dens_s,
+                                                    const float4 *__restrict__ sloc,
+                                                    const float4 *__restrict__ spos, const Geo &g,
+                                                    bool active, const float4 &li, const float4 &pi,
+                                                    int &wr, bool visit, uint32_t la, uint32_t lb,
+                                                    int32_t *spre, int32_t *sla) {
+    const int lane = threadIdx.x & 63;
+    const int cntl = visit ? (int)(lb - la) : 0;
+    int incl = cntl;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += y;
+    }
+    const int P = __shfl(incl, 63, 64);
+    if (P == 0) return;
+    if (lane < 27) {
+        spre[lane] = cntl > 0 ? incl - cntl : 0x7fffffff;  // start of cell lane's particles
+        sla[lane] = (int)la;
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int p0 = 0; p0 < P; p0 += 64) {
+        const int p = p0 + lane;
+        bool mem = false;
+        uint32_t j = 0;
+        float xj = 0.0f, yj = 0.0f, zj = 0.0f;
+        int rj = -1;
+        if (p < P) {
+            // the visited cell whose particles include number p: the last
+            // stencil cell with start <= p (cells without particles never qualify)
+            int t = -1, best = -1;
+            for (int u = 0; u < 27; u++) {
+                const int st = spre[u];
+                if (st <= p && st >= best) {
+                    best = st;
+                    t = u;
+                }
+            }
+            j = (uint32_t)(sla[t] + (p - best));
+            mem = is_member(dens_s, j, g.dl0);
+            if (mem) {
+                const float4 lj = sloc[j];
+                xj = lj.x + (float)(t % 3 - 1) * g.cellb;
+                yj = lj.y + (float)((t / 3) % 3 - 1) * g.cellb;
+                zj = lj.z + (float)(t / 9 - 1) * g.cellb;
+                rj = uf_find_hint(parent, (int)j);
+            }
+        }
+        uint64_t mm = __ballot(mem);
+        while (mm) {
+            const int J = __ffsll((unsigned long long)mm) - 1;
+            mm &= mm - 1;
+            int r = __shfl(rj, J, 64);
+            if (!__ballot(active && wr != r)) continue;
+            const uint32_t jj = (uint32_t)__shfl((int)j, J, 64);
+            const float dx = __shfl(xj, J, 64) - li.x, dy = __shfl(yj, J, 64) - li.y,
+                        dz = __shfl(zj, J, 64) - li.z;
+            const bool lk = active && wr != r && linked_d(dx, dy, dz, pi, spos, jj, g);
+            if (!__ballot(lk)) continue;
+            join_lanes(parent, lk, wr, r);
+        }
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_fof_init(int64_t n, Geo g, const float *__restrict__ dens_s,
                                                      int32_t *__restrict__ parent) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -213,6 +281,7 @@ __global__ __launch_bounds__(kBlock) void k_fof_dense(int64_t nchunks, Geo g,
                                                       int32_t *parent) {
     __shared__ int64_t dbase[kBlock / 64][27];  // visited dense cells: sub-table base
     __shared__ int8_t doff[kBlock / 64][27];    // and stencil index
+    __shared__ int32_t s_spre[kBlock / 64][27], s_sla[kBlock / 64][27];  // sparse neighbour cells
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t q = (int64_t)xcd_block() * (kBlock / 64) + wave;
     if (q >= nchunks) return;
@@ -264,15 +333,9 @@ __global__ __launch_bounds__(kBlock) void k_fof_dense(int64_t nchunks, Geo g,
     }
     const uint64_t visit = __ballot(lvisit);
     const int nvisit = __popcll(visit);
-    // sparse neighbour cells, 64 particles at a time
-    uint64_t sm = __ballot(lreach && !ldense && lb > la);
-    while (sm) {
-        const int t = __ffsll((unsigned long long)sm) - 1;
-        sm &= sm - 1;
-        const uint32_t a = (uint32_t)__shfl((int)la, t, 64), b = (uint32_t)__shfl((int)lb, t, 64);
-        stream_range(parent, dens_s, sloc, spos, g, active, li, pi, wr, a, b, t % 3 - 1, (t / 3) % 3 - 1,
-                     t / 9 - 1, false, -1);
-    }
+    // sparse neighbour cells, all together
+    stream_sparse_cells(parent, dens_s, sloc, spos, g, active, li, pi, wr, lreach && !ldense && lb > la, la, lb,
+                        s_spre[wave], s_sla[wave]);
     if (nvisit == 0) return;
     __builtin_amdgcn_wave_barrier();
     // chunk bounding box (active lanes), for sub-cell reach tests
