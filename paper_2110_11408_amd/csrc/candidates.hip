@@ -274,8 +274,9 @@ void launch_candidates(int64_t n, const Geo &g, Work &w, hipStream_t s) {
     scan_u32(w.f_dcell, w.s_dcell, n, w.scan_tmp, s);
     hipLaunchKernelGGL(k_hard_list, dim3(blocks), dim3(kBlock), 0, s, n, w.f_dcell, w.s_dcell, w.hardlist);
     uint32_t nh = 0;
-    (void)hipMemcpyAsync(&nh, w.s_dcell + n, sizeof(nh), hipMemcpyDeviceToHost, s);
-    (void)hipStreamSynchronize(s);
+    WordSrc src{};
+    src.p[0] = w.s_dcell + n;
+    if (read_words(src, 1, w.host, &nh, s) != hipSuccess) nh = 0;  // the caller's next read reports it
     w.nhard = nh;
     if (nh > 0) {
         // cases left after the own-cell search: list in the (free) chunk-flag

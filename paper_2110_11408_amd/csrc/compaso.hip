@@ -204,7 +204,8 @@ __device__ __forceinline__ int block_min(int v, int *s_min) {
 // descending density; a candidate inside alpha R of an accepted nucleus is
 // ineligible; an eligible one is accepted and its enclosed count i found from
 // the bucket histogram of all particles of the group.
-__global__ __launch_bounds__(kBlock) void k_accept(Geo g, const int32_t *__restrict__ glist,
+__global__ __launch_bounds__(kBlock) void k_accept(const uint32_t *__restrict__ ngc_p, Geo g,
+                                                   const int32_t *__restrict__ glist,
                                                    const int32_t *__restrict__ g_start,
                                                    const int32_t *__restrict__ g_size,
                                                    const uint32_t *__restrict__ gcoff,
@@ -221,6 +222,8 @@ __global__ __launch_bounds__(kBlock) void k_accept(Geo g, const int32_t *__restr
     __shared__ int s_nh;
     __shared__ uint32_t s_red[kBlock / 64];
     __shared__ int s_min[kBlock / 64];
+    // the grid is an upper bound; the number of groups with candidates is read here
+    if (blockIdx.x >= *ngc_p) return;
     const int gi = glist[blockIdx.x];
     const int64_t start = g_start[gi];
     const int64_t m = g_size[gi];
@@ -441,10 +444,12 @@ void launch_candidates_sort(int64_t n, int64_t G, int64_t NC, Work &w, hipStream
     fill_i32(w.g_nh, 0, G + 1, s);
 }
 
-void launch_accept(int64_t NGC, const Geo &g, Work &w, hipStream_t s) {
-    if (NGC <= 0) return;
-    hipLaunchKernelGGL(k_accept, dim3((unsigned)NGC), dim3(kBlock), 0, s, g, w.glist, w.g_start, w.g_size,
-                       w.gcoff, w.cand_sorted, w.mem, w.spos, w.hist, w.h_nuc, w.h_ienc, w.h_gid,
+void launch_accept(int64_t G, int64_t NC, const Geo &g, Work &w, hipStream_t s) {
+    // one workgroup per group with candidates; there are at most min(G, NC)
+    const int64_t bound = G < NC ? G : NC;
+    if (bound <= 0) return;
+    hipLaunchKernelGGL(k_accept, dim3((unsigned)bound), dim3(kBlock), 0, s, w.gcidx + G, g, w.glist, w.g_start,
+                       w.g_size, w.gcoff, w.cand_sorted, w.mem, w.spos, w.hist, w.h_nuc, w.h_ienc, w.h_gid,
                        w.g_nh);
 }
 

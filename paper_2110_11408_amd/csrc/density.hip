@@ -189,22 +189,36 @@ __global__ __launch_bounds__(kBlock) void k_density_sparse(int64_t nsparse, Geo 
     const int cx = (int)(c % (uint32_t)nc), cy = (int)((c / (uint32_t)nc) % (uint32_t)nc),
               cz = (int)(c / ((uint32_t)nc * (uint32_t)nc));
     const uint32_t x0 = (uint32_t)wrapc(cx - 1, nc), x1 = (uint32_t)cx, x2 = (uint32_t)wrapc(cx + 1, nc);
+    // away from the periodic x edges the three cells of a stencil row are
+    // consecutive: their four bounding offsets are one 16-byte load
+    const bool inner = cx > 0 && cx < nc - 1;
     double acc = 0.0;
     for (int oz = -1; oz <= 1; oz++) {
         const int z = wrapc(cz + oz, nc);
         const float zs = li.z - (float)oz * g.cellb;
-        // the 18 offsets of this plane are loaded together so their latencies overlap
+        // the offsets of this plane are loaded together so their latencies overlap
         uint32_t ra[9], rb[9];
 #pragma unroll
         for (int oy = -1; oy <= 1; oy++) {
             const uint32_t row = ((uint32_t)z * (uint32_t)nc + (uint32_t)wrapc(cy + oy, nc)) * (uint32_t)nc;
             const int r = (oy + 1) * 3;
-            ra[r + 0] = off[row + x0];
-            rb[r + 0] = off[row + x0 + 1];
-            ra[r + 1] = off[row + x1];
-            rb[r + 1] = off[row + x1 + 1];
-            ra[r + 2] = off[row + x2];
-            rb[r + 2] = off[row + x2 + 1];
+            if (inner) {
+                const uint32_t *p = off + row + x0;
+                const uint32_t o0 = p[0], o1 = p[1], o2 = p[2], o3 = p[3];
+                ra[r + 0] = o0;
+                rb[r + 0] = o1;
+                ra[r + 1] = o1;
+                rb[r + 1] = o2;
+                ra[r + 2] = o2;
+                rb[r + 2] = o3;
+            } else {
+                ra[r + 0] = off[row + x0];
+                rb[r + 0] = off[row + x0 + 1];
+                ra[r + 1] = off[row + x1];
+                rb[r + 1] = off[row + x1 + 1];
+                ra[r + 2] = off[row + x2];
+                rb[r + 2] = off[row + x2 + 1];
+            }
         }
 #pragma unroll
         for (int oy = -1; oy <= 1; oy++) {

@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <initializer_list>
 #include <string>
 
 #include "hf_lane.h"
@@ -220,19 +221,33 @@ hf_status prepare(Lane *c, int64_t n, const Geo &g, Work *w, bool extra) {
         c->arena_bytes = want;
     }
     carve((char *)c->arena, n, ncell, nsub, rhl, extra, w);
+    w->host = c->host;
     c->stats = hf_stats{};
     c->stats.n_cells = ncell;
     return HF_OK;
 }
 
-hf_status check_pos_flags(Lane *c, const Work &w, hipStream_t s) {
-    int32_t err = 0;
-    HIP_OK(c, hipMemcpyAsync(&err, w.err, sizeof(err), hipMemcpyDeviceToHost, s));
-    HIP_OK(c, hipStreamSynchronize(s));
+// Device words read back in one dispatch and one wait (the lane's pinned host
+// words); out[i] = *src[i].
+hf_status read_dev(Lane *c, hipStream_t s, std::initializer_list<const void *> src, uint32_t *out) {
+    hf::WordSrc w{};
+    int k = 0;
+    for (const void *p : src) w.p[k++] = static_cast<const uint32_t *>(p);
+    HIP_OK(c, hf::read_words(w, k, c->host, out, s));
+    return HF_OK;
+}
+
+hf_status err_status(Lane *c, uint32_t err) {
     if (err & 1) return fail(c, HF_ERR_INVALID, "positions must lie in [0, box)");
     if (err & 2) return fail(c, HF_ERR_INVALID, "l0_id values must lie in [0, n]");
     if (err & 4) return fail(c, HF_ERR_DEVICE, "internal error: L0 group key out of range");
     return HF_OK;
+}
+
+hf_status check_pos_flags(Lane *c, const Work &w, hipStream_t s) {
+    uint32_t err = 0;
+    hf_status st = read_dev(c, s, {w.err}, &err);
+    return st != HF_OK ? st : err_status(c, err);
 }
 
 float elapsed(hipEvent_t a, hipEvent_t b) {
@@ -251,41 +266,38 @@ hf_status run_compaso(Lane *c, int64_t n, const Geo &g, Work &w, int32_t *halo_i
                       hipStream_t s) {
     HIP_OK(c, hipEventRecord(c->ev[3], s));
     hf::launch_segment(n, w, s);
-    uint32_t G32 = 0, M32 = 0;
-    HIP_OK(c, hipMemcpyAsync(&G32, w.gidx + n, sizeof(G32), hipMemcpyDeviceToHost, s));
-    HIP_OK(c, hipMemcpyAsync(&M32, w.goff + n, sizeof(M32), hipMemcpyDeviceToHost, s));
-    HIP_OK(c, hipStreamSynchronize(s));
-    int64_t G = G32;
+    // group and member counts, and the error flags of the steps so far (the
+    // kernels before this point clamp what they index, whatever the flags)
+    uint32_t r[3];
+    hf_status st = read_dev(c, s, {w.gidx + n, w.goff + n, w.err}, r);
+    if (st == HF_OK) st = err_status(c, r[2]);
+    if (st != HF_OK) return st;
+    int64_t G = r[0];
     c->stats.n_groups = G;
-    c->stats.n_members = M32;
+    c->stats.n_members = r[1];
     hf::launch_segment_groups(n, G, w, s);
     HIP_OK(c, hipEventRecord(c->ev[4], s));
     hf::launch_candidates(n, g, w, s);
     hf::scan_u32(w.gccnt, w.gcoff, G, w.scan_tmp, s);
     uint32_t NC32 = 0;
-    HIP_OK(c, hipMemcpyAsync(&NC32, w.gcoff + G, sizeof(NC32), hipMemcpyDeviceToHost, s));
-    HIP_OK(c, hipStreamSynchronize(s));
+    st = read_dev(c, s, {w.gcoff + G}, &NC32);
+    if (st != HF_OK) return st;
     int64_t NC = NC32;
     hf::launch_candidates_sort(n, G, NC, w, s);
-    uint32_t NGC32 = 0;
-    HIP_OK(c, hipMemcpyAsync(&NGC32, w.gcidx + G, sizeof(NGC32), hipMemcpyDeviceToHost, s));
-    HIP_OK(c, hipStreamSynchronize(s));
     HIP_OK(c, hipEventRecord(c->ev[5], s));
-    hf::launch_accept(NGC32, g, w, s);
+    hf::launch_accept(G, NC, g, w, s);
     HIP_OK(c, hipEventRecord(c->ev[6], s));
     hf::launch_assign(n, g, w, s);
     HIP_OK(c, hipEventRecord(c->ev[7], s));
     hf::launch_output_flags(n, NC, g, w, s);
-    uint32_t NH32 = 0;
-    HIP_OK(c, hipMemcpyAsync(&NH32, w.tpos + n, sizeof(NH32), hipMemcpyDeviceToHost, s));
-    HIP_OK(c, hipStreamSynchronize(s));
-    int64_t NH = NH32;
+    uint32_t r2[2];  // table rows; nuclei accepted (counter 2)
+    st = read_dev(c, s, {w.tpos + n, w.counters + 2}, r2);
+    if (st != HF_OK) return st;
+    int64_t NH = r2[0];
     if (n_halos) *n_halos = NH;
     bool fits = NH <= cap;
     hf::launch_output(n, NC, g, w, halo_id, l0_out, fits ? halos : nullptr, cap, s);
     HIP_OK(c, hipEventRecord(c->ev[8], s));
-    int32_t counters[16];
-    HIP_OK(c, hipMemcpyAsync(counters, w.counters, sizeof(counters), hipMemcpyDeviceToHost, s));
     HIP_OK(c, hipStreamSynchronize(s));
     c->stats.ms_segment = elapsed(c->ev[3], c->ev[4]);
     c->stats.ms_candidates = elapsed(c->ev[4], c->ev[5]);
@@ -297,7 +309,7 @@ hf_status run_compaso(Lane *c, int64_t n, const Geo &g, Work &w, int32_t *halo_i
     c->stats.n_dense_chunks = w.nchunks;
     c->stats.n_sparse = w.nsparse;
     c->stats.n_hard = w.nhard;
-    c->stats.n_found = counters[2];
+    c->stats.n_found = r2[1];
     c->stats.n_halos = NH;
     if (!fits) return fail(c, HF_ERR_CAPACITY, "halos_cap is smaller than the number of halos");
     return HF_OK;
@@ -326,11 +338,12 @@ hf_status begin(Lane *c, const float *pos, int64_t n, const hf_params *p, Geo *g
     hf::fill_i32(w->err, 0, 4, s);
     HIP_OK(c, hipEventRecord(c->ev[0], s));
     hf::launch_bin(pos, n, *g, *w, s);
-    uint32_t counts[3] = {0, 0, 0};
-    HIP_OK(c, hipMemcpyAsync(&counts[0], w->s_chunk + n, 4, hipMemcpyDeviceToHost, s));
-    HIP_OK(c, hipMemcpyAsync(&counts[1], w->s_dcell + n, 4, hipMemcpyDeviceToHost, s));
-    HIP_OK(c, hipMemcpyAsync(&counts[2], w->s_sparse + n, 4, hipMemcpyDeviceToHost, s));
-    HIP_OK(c, hipStreamSynchronize(s));
+    // dense chunks, dense cells, sparse particles, and the range flag of the
+    // positions (binning clamps cells, so nothing it wrote is out of bounds)
+    uint32_t counts[4];
+    st = read_dev(c, s, {w->s_chunk + n, w->s_dcell + n, w->s_sparse + n, w->err}, counts);
+    if (st == HF_OK) st = err_status(c, counts[3]);
+    if (st != HF_OK) return st;
     w->nchunks = counts[0];
     w->ndcells = counts[1];
     w->nsparse = counts[2];
@@ -347,6 +360,11 @@ namespace hf {
 hf_status lane_init(Lane *L, int device, bool own_stream) {
     L->device = device;
     if (hipSetDevice(device) != hipSuccess) return HF_ERR_DEVICE;
+    if (hipHostMalloc(reinterpret_cast<void **>(&L->host), 64 * sizeof(uint32_t), hipHostMallocCoherent) !=
+        hipSuccess) {
+        L->host = nullptr;
+        return HF_ERR_DEVICE;
+    }
     for (auto &e : L->ev)
         if (hipEventCreate(&e) != hipSuccess) return HF_ERR_DEVICE;
     if (own_stream && hipStreamCreateWithFlags(&L->stream, hipStreamNonBlocking) != hipSuccess)
@@ -365,6 +383,8 @@ void lane_release(Lane *L) {
 
 void lane_destroy(Lane *L) {
     lane_release(L);
+    if (L->host) (void)hipHostFree(L->host);
+    L->host = nullptr;
     for (auto &e : L->ev)
         if (e) (void)hipEventDestroy(e);
     if (L->stream) (void)hipStreamDestroy(L->stream);
@@ -399,8 +419,6 @@ hf_status lane_find(Lane *c, const float *pos, int64_t n, const hf_params *p, fl
     hf::launch_fof(n, g, w, s);
     hf::launch_fof_labels(n, g, w, l0_id, s);
     HIP_OK(c, hipEventRecord(c->ev[9], s));
-    st = check_pos_flags(c, w, s);
-    if (st != HF_OK) return st;
     st = run_compaso(c, n, g, w, halo_id, nullptr, halos, halos_cap, n_halos, s);
     c->stats.ms_bin = elapsed(c->ev[0], c->ev[1]);
     c->stats.ms_density = elapsed(c->ev[1], c->ev[2]);
@@ -543,10 +561,10 @@ hf_status hf_l0_fof(hf_ctx *ctx, const float *pos, const float *density, int64_t
     hf::launch_fof_labels(n, g, w, l0_id, s);
     HIP_OK(c, hipEventRecord(c->ev[3], s));
     hf::launch_segment(n, w, s);
-    uint32_t G32 = 0, M32 = 0;
-    HIP_OK(c, hipMemcpyAsync(&G32, w.gidx + n, sizeof(G32), hipMemcpyDeviceToHost, s));
-    HIP_OK(c, hipMemcpyAsync(&M32, w.goff + n, sizeof(M32), hipMemcpyDeviceToHost, s));
-    st = check_pos_flags(c, w, s);
+    uint32_t r[3] = {0, 0, 0};
+    st = read_dev(c, s, {w.gidx + n, w.goff + n, w.err}, r);
+    if (st == HF_OK) st = err_status(c, r[2]);
+    const uint32_t G32 = r[0], M32 = r[1];
     c->stats.ms_bin = elapsed(c->ev[0], c->ev[1]);
     c->stats.ms_fof = elapsed(c->ev[2], c->ev[3]);
     c->stats.ms_total = elapsed(c->ev[0], c->ev[3]);
@@ -575,8 +593,6 @@ hf_status hf_compaso(hf_ctx *ctx, const float *pos, const float *density, const 
     hf::launch_gather_density(density, n, w, s);
     hf::launch_keys_from_labels(l0_id, n, w, s);
     HIP_OK(c, hipEventRecord(c->ev[2], s));
-    st = check_pos_flags(c, w, s);
-    if (st != HF_OK) return st;
     st = run_compaso(c, n, g, w, halo_id, nullptr, halos, halos_cap, n_halos, s);
     c->stats.ms_bin = elapsed(c->ev[0], c->ev[1]);
     c->stats.ms_total = elapsed(c->ev[0], c->ev[8]);
@@ -606,15 +622,13 @@ hf_status hf_halo_stats(hf_ctx *ctx, const float *pos, const float *density, con
     hf::launch_gather_density(density, n, w, s);
     hf::launch_keys_from_labels(halo_id, n, w, s);
     HIP_OK(c, hipEventRecord(c->ev[2], s));
-    st = check_pos_flags(c, w, s);
-    if (st != HF_OK) return st;
     HIP_OK(c, hipEventRecord(c->ev[3], s));
     hf::launch_segment(n, w, s);
-    uint32_t G32 = 0, M32 = 0;
-    HIP_OK(c, hipMemcpyAsync(&G32, w.gidx + n, sizeof(G32), hipMemcpyDeviceToHost, s));
-    HIP_OK(c, hipMemcpyAsync(&M32, w.goff + n, sizeof(M32), hipMemcpyDeviceToHost, s));
-    HIP_OK(c, hipStreamSynchronize(s));
-    const int64_t G = G32, M = M32;
+    uint32_t r[3];
+    st = read_dev(c, s, {w.gidx + n, w.goff + n, w.err}, r);
+    if (st == HF_OK) st = err_status(c, r[2]);
+    if (st != HF_OK) return st;
+    const int64_t G = r[0], M = r[1];
     if (G != n_halos) return fail(c, HF_ERR_INVALID, "n_halos differs from the number of halo_id labels");
     c->stats.n_groups = G;
     c->stats.n_members = M;
@@ -623,14 +637,11 @@ hf_status hf_halo_stats(hf_ctx *ctx, const float *pos, const float *density, con
     hf::launch_candidates(n, g2, w, s);
     hf::scan_u32(w.gccnt, w.gcoff, G, w.scan_tmp, s);
     uint32_t NC32 = 0;
-    HIP_OK(c, hipMemcpyAsync(&NC32, w.gcoff + G, sizeof(NC32), hipMemcpyDeviceToHost, s));
-    HIP_OK(c, hipStreamSynchronize(s));
+    st = read_dev(c, s, {w.gcoff + G}, &NC32);
+    if (st != HF_OK) return st;
     hf::launch_candidates_sort(n, G, NC32, w, s);
-    uint32_t NGC32 = 0;
-    HIP_OK(c, hipMemcpyAsync(&NGC32, w.gcidx + G, sizeof(NGC32), hipMemcpyDeviceToHost, s));
-    HIP_OK(c, hipStreamSynchronize(s));
     HIP_OK(c, hipEventRecord(c->ev[5], s));
-    hf::launch_accept(NGC32, g2, w, s);
+    hf::launch_accept(G, NC32, g2, w, s);
     HIP_OK(c, hipEventRecord(c->ev[6], s));
     hf::launch_assign(n, g2, w, s);
     HIP_OK(c, hipEventRecord(c->ev[7], s));

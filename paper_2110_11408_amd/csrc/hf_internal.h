@@ -162,9 +162,19 @@ struct Work {
     int32_t *ordk;                   // halo statistics only: group ordinal per key
     int32_t *counters;                                 // small device counters
     int32_t *err;
+    uint32_t *host;                                    // the lane's pinned host words (read_words)
 };
 
 // ------------------------------------------------------------------ launchers
+// Device words to read back to the host in one go.
+struct WordSrc {
+    static constexpr int kMax = 8;
+    const uint32_t *p[kMax];
+};
+// One small kernel copies *src.p[0..k) into the pinned host buffer `host`
+// (at least kMax words), the stream is synchronized and out[0..k) receives
+// the values: one dispatch and one wait for all the counts a step needs.
+hipError_t read_words(const WordSrc &src, int k, uint32_t *host, uint32_t *out, hipStream_t s);
 void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 // Exclusive scan: out[0..n] with out[n] = total.  tmp: scan_tmp_words(n) words.
@@ -193,7 +203,8 @@ void launch_segment(int64_t n, Work &w, hipStream_t s);
 void launch_segment_groups(int64_t n, int64_t G, Work &w, hipStream_t s);
 void launch_candidates(int64_t n, const Geo &g, Work &w, hipStream_t s);   // candidates.hip
 void launch_candidates_sort(int64_t n, int64_t G, int64_t NC, Work &w, hipStream_t s);
-void launch_accept(int64_t NGC, const Geo &g, Work &w, hipStream_t s);
+// Groups with candidates: their count is read on the device (grid bound min(G, NC)).
+void launch_accept(int64_t G, int64_t NC, const Geo &g, Work &w, hipStream_t s);
 void launch_assign(int64_t n, const Geo &g, Work &w, hipStream_t s);
 void launch_output_flags(int64_t n, int64_t NC, const Geo &g, Work &w, hipStream_t s);
 void launch_output(int64_t n, int64_t NC, const Geo &g, Work &w, int32_t *halo_id,

@@ -22,14 +22,15 @@ struct Lane {
     hf_stats stats = {};
     std::string err;
     hipStream_t stream = nullptr;  // owned; null for a context's main lane
+    uint32_t *host = nullptr;      // pinned, coherent host words for count read-backs
 };
 
-// Create the events (and a non-blocking stream of default priority when
-// own_stream).  Returns HF_ERR_DEVICE on failure.
+// Create the events, the pinned host words (and a non-blocking stream of
+// default priority when own_stream).  Returns HF_ERR_DEVICE on failure.
 hf_status lane_init(Lane *L, int device, bool own_stream);
 // Free the arena (the lane stays usable; the next call allocates again).
 void lane_release(Lane *L);
-// Release, destroy events and the owned stream.
+// Release, destroy events, the host words and the owned stream.
 void lane_destroy(Lane *L);
 // Bytes of arena a call of n particles under p needs (0 if p or n is invalid).
 size_t lane_arena_bytes(const hf_params *p, int64_t n);

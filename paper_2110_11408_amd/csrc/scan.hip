@@ -108,6 +108,13 @@ __global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t *p, int32_t v, int6
         p[i] = v;
 }
 
+// Copies k device words into pinned host memory with system-scope stores, so
+// the host sees them once the stream has drained.
+__global__ void k_publish(WordSrc src, int k, uint32_t *host) {
+    const int t = threadIdx.x;
+    if (t < k) __hip_atomic_store(host + t, *src.p[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 int64_t grid_for(int64_t n, int64_t cap = 1 << 20) {
     int64_t b = (n + kBlock - 1) / kBlock;
     if (b < 1) b = 1;
@@ -124,6 +131,17 @@ void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
 void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n)), dim3(kBlock), 0, s, p, v, n);
+}
+
+hipError_t read_words(const WordSrc &src, int k, uint32_t *host, uint32_t *out, hipStream_t s) {
+    if (k < 1 || k > WordSrc::kMax) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, src, k, host);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    for (int i = 0; i < k; i++) out[i] = __atomic_load_n(host + i, __ATOMIC_ACQUIRE);
+    return hipSuccess;
 }
 
 int64_t scan_tmp_words(int64_t n) {
