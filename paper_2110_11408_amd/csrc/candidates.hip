@@ -210,12 +210,14 @@ __device__ bool has_denser_within_b(int i, int tt0, int tt1, const Geo &g, const
     return false;
 }
 
-// Stage 2, one thread per hard case, in two launches: the first searches the
-// particle's own cell, where a denser neighbour is nearly always found; the
-// cases left (mostly the actual candidates, which need the whole stencil) are
-// appended to a second list and searched in the 26 other cells, so that waves
-// are not held up by a few exhaustive searches.
-__global__ __launch_bounds__(kBlock) void k_cand_hard(const uint32_t *__restrict__ nhard_p, int stage, Geo g,
+// Hard cases, one thread each, searching the stencil cells tt0..tt1-1: the
+// particle's own cell (stage 1, where a denser neighbour is nearly always
+// found), then the face neighbours (stage 2).  With `rest`, the cases left are
+// appended to it (one atomic per wavefront), so that the few exhaustive
+// searches (mostly the actual candidates) do not hold up waves of quick ones;
+// without it, the cases left are candidates.
+__global__ __launch_bounds__(kBlock) void k_cand_hard(const uint32_t *__restrict__ nhard_p, int stage, int tt0,
+                                                      int tt1, Geo g,
                                                       const int32_t *__restrict__ hard,
                                                       const float4 *__restrict__ sloc,
                                                       const float4 *__restrict__ spos,
@@ -231,23 +233,24 @@ __global__ __launch_bounds__(kBlock) void k_cand_hard(const uint32_t *__restrict
                                                       int32_t *__restrict__ cflag,
                                                       int32_t *__restrict__ rest,
                                                       uint32_t *__restrict__ nrest) {
-    // the second list fills only the first blocks of its grid: those are
-    // spread over all XCDs by the plain block order, not gathered on one
+    // a list built on the device fills only the first blocks of its grid:
+    // those are spread over all XCDs by the plain block order, not gathered
+    // on one
     const int64_t t = (int64_t)(stage == 1 ? xcd_block() : blockIdx.x) * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const bool valid = t < (int64_t)*nhard_p;
     const int i = valid ? hard[t] : -1;
     bool left = false;
-    if (valid && !has_denser_within_b(i, stage == 1 ? 0 : 1, stage == 1 ? 1 : 27, g, sloc, spos, off, cellmap,
-                                      subtab, submax, subarg, dens_s, gkey)) {
-        if (stage == 1) {
+    if (valid && !has_denser_within_b(i, tt0, tt1, g, sloc, spos, off, cellmap, subtab, submax, subarg, dens_s,
+                                      gkey)) {
+        if (rest) {
             left = true;
         } else {
             cflag[i] = 1;
             atomicAdd(&gccnt[gid_of[i]], 1u);
         }
     }
-    if (stage != 1) return;
+    if (!rest) return;
     // append the cases left: one atomic per wavefront
     const uint64_t m = __ballot(left);
     if (m == 0ull) return;
@@ -256,6 +259,129 @@ __global__ __launch_bounds__(kBlock) void k_cand_hard(const uint32_t *__restrict
     if (lane == leader) base = atomicAdd(nrest, (uint32_t)__popcll(m));
     base = (uint32_t)__shfl((int)base, leader, 64);
     if (left) rest[base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = i;
+}
+
+// Stage 3, one wavefront per case (grid-stride over the list, its length read
+// on the device): the stencil cells tt0..26 are searched by all lanes at once.
+// A lane takes one stencil cell (its range; the particles of a sparse cell),
+// then the sub-cells of the dense cells are taken 64 at a time (densest
+// particle first, then the rest of the sub-cell); the wavefront stops at the
+// first denser particle of the group within b.  The cases that reach this
+// stage are mostly the true candidates, which need every cell.
+__global__ __launch_bounds__(kBlock) void k_cand_wave(const uint32_t *__restrict__ ncase_p, int tt0, Geo g,
+                                                      const int32_t *__restrict__ cases,
+                                                      const float4 *__restrict__ sloc,
+                                                      const float4 *__restrict__ spos,
+                                                      const uint32_t *__restrict__ off,
+                                                      const uint32_t *__restrict__ cellmap,
+                                                      const uint32_t *__restrict__ subtab,
+                                                      const uint64_t *__restrict__ submax,
+                                                      const int32_t *__restrict__ subarg,
+                                                      const float *__restrict__ dens_s,
+                                                      const int32_t *__restrict__ gkey,
+                                                      const int32_t *__restrict__ gid_of,
+                                                      uint32_t *__restrict__ gccnt,
+                                                      int32_t *__restrict__ cflag) {
+    __shared__ int64_t s_base[kBlock / 64][27];  // sub-table base of the lane's dense cells
+    __shared__ int8_t s_tt[kBlock / 64][27];     // and their stencil order index
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const uint32_t ncase = *ncase_p;
+    const uint32_t nwaves = gridDim.x * (kBlock / 64);
+    const int nc = g.nc, k = g.ksub, nsub = k * k * k;
+    const float subb = g.cellb / (float)k;
+    for (uint32_t q = blockIdx.x * (kBlock / 64) + (uint32_t)wave; q < ncase; q += nwaves) {
+        const int i = __builtin_amdgcn_readfirstlane(cases[q]);
+        const int key = gkey[i];
+        const float di = dens_s[i];
+        const float4 li = sloc[i];
+        const float4 pi = spos[i];
+        const uint32_t oi = orig_of(pi);
+        const uint64_t mykey = dkey(di, oi);
+        const uint32_t c = __float_as_uint(li.w);
+        const int cx = (int)(c % (uint32_t)nc), cy = (int)((c / (uint32_t)nc) % (uint32_t)nc),
+                  cz = (int)(c / ((uint32_t)nc * (uint32_t)nc));
+        // one stencil cell per lane
+        const int tt = tt0 + lane;
+        bool in_reach = false, dense = false, found = false;
+        float xs = 0.0f, ys = 0.0f, zs = 0.0f;
+        uint32_t a = 0, b = 0, nb = 0;
+        if (tt < 27) {
+            int ox, oy, oz;
+            stencil_offset(tt, ox, oy, oz);
+            xs = li.x - (float)ox * g.cellb;
+            ys = li.y - (float)oy * g.cellb;
+            zs = li.z - (float)oz * g.cellb;
+            const float gx = ox < 0 ? li.x : (ox > 0 ? g.cellb - li.x : 0.0f);
+            const float gy = oy < 0 ? li.y : (oy > 0 ? g.cellb - li.y : 0.0f);
+            const float gz = oz < 0 ? li.z : (oz > 0 ? g.cellb - li.z : 0.0f);
+            in_reach = gx * gx + gy * gy + gz * gz < g.b2b_hi;
+            if (in_reach) {
+                nb = ((uint32_t)wrapc(cz + oz, nc) * (uint32_t)nc + (uint32_t)wrapc(cy + oy, nc)) * (uint32_t)nc +
+                     (uint32_t)wrapc(cx + ox, nc);
+                a = off[nb];
+                b = off[nb + 1];
+                dense = b - a >= (uint32_t)kDenseMin;
+            }
+        }
+        // sparse cells: the lane's own particles
+        if (in_reach && !dense) {
+            for (uint32_t j = a; j < b && !found; j++)
+                if ((int)j != i && dens_s[j] >= di &&
+                    denser_within_b(j, dens_s, gkey, sloc, spos, key, di, oi, xs, ys, zs, pi, g))
+                    found = true;
+        }
+        if (__ballot(found)) continue;
+        // dense cells: their sub-table bases, then (cell, sub-cell) tasks
+        const uint64_t dm = __ballot(in_reach && dense);
+        if (dm == 0ull) {
+            if (lane == 0) {
+                cflag[i] = 1;
+                atomicAdd(&gccnt[gid_of[i]], 1u);
+            }
+            continue;
+        }
+        if (in_reach && dense) {
+            const int slot = __popcll(dm & ((1ull << lane) - 1ull));
+            s_base[wave][slot] = (int64_t)cellmap[nb] * (nsub + 1);
+            s_tt[wave][slot] = (int8_t)tt;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        const int ntask = __popcll(dm) * nsub;
+        for (int t0 = 0; t0 < ntask; t0 += 64) {
+            const int tq = t0 + lane;
+            if (tq < ntask) {
+                const int r = tq / nsub, sl = tq - r * nsub;
+                const int64_t base = s_base[wave][r];
+                if (submax[base + sl] > mykey) {
+                    int ox, oy, oz;
+                    stencil_offset(s_tt[wave][r], ox, oy, oz);
+                    const float txs = li.x - (float)ox * g.cellb, tys = li.y - (float)oy * g.cellb,
+                                tzs = li.z - (float)oz * g.cellb;
+                    const int sx = sl % k, sy = (sl / k) % k, sz = sl / (k * k);
+                    const float ex = fmaxf(fmaxf(sx * subb - 1e-5f - txs, txs - (sx + 1) * subb - 1e-5f), 0.0f);
+                    const float ey = fmaxf(fmaxf(sy * subb - 1e-5f - tys, tys - (sy + 1) * subb - 1e-5f), 0.0f);
+                    const float ez = fmaxf(fmaxf(sz * subb - 1e-5f - tzs, tzs - (sz + 1) * subb - 1e-5f), 0.0f);
+                    if (ex * ex + ey * ey + ez * ez < g.b2b_hi) {
+                        const int32_t top = subarg[base + sl];
+                        found = denser_within_b(top, dens_s, gkey, sloc, spos, key, di, oi, txs, tys, tzs, pi, g);
+                        const uint32_t u1 = subtab[base + sl + 1];
+                        for (uint32_t j = subtab[base + sl]; j < u1 && !found; j++)
+                            if ((int32_t)j != top && (int)j != i && dens_s[j] >= di &&
+                                denser_within_b(j, dens_s, gkey, sloc, spos, key, di, oi, txs, tys, tzs, pi, g))
+                                found = true;
+                    }
+                }
+            }
+            if (__ballot(found)) break;
+        }
+        if (!__ballot(found) && lane == 0) {
+            cflag[i] = 1;
+            atomicAdd(&gccnt[gid_of[i]], 1u);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
 }
 
 }  // namespace
@@ -271,7 +397,7 @@ void launch_candidates(int64_t n, const Geo &g, Work &w, hipStream_t s) {
     // it; the hard-case flags and their scan reuse the dense-cell flag arrays
     hipLaunchKernelGGL(k_cand_quick, dim3(blocks), dim3(kBlock), 0, s, n, g, w.sloc, w.spos, w.f_sparse, w.ssub,
                        w.cnt, w.subarg, w.dens_s, w.gkey, w.owner, w.f_dcell);
-    scan_u32(w.f_dcell, w.s_dcell, n, w.scan_tmp, s);
+    scan_u32(w.f_dcell, w.s_dcell, n, w.scan_tmp, s, w.err);
     hipLaunchKernelGGL(k_hard_list, dim3(blocks), dim3(kBlock), 0, s, n, w.f_dcell, w.s_dcell, w.hardlist);
     uint32_t nh = 0;
     WordSrc src{};
@@ -279,19 +405,29 @@ void launch_candidates(int64_t n, const Geo &g, Work &w, hipStream_t s) {
     if (read_words(src, 1, w.host, &nh, s) != hipSuccess) nh = 0;  // the caller's next read reports it
     w.nhard = nh;
     if (nh > 0) {
-        // cases left after the own-cell search: list in the (free) chunk-flag
-        // array, count in counters[8]; the second launch reads the count on
-        // the device and its surplus threads exit
-        int32_t *rest = reinterpret_cast<int32_t *>(w.f_chunk);
-        uint32_t *nrest = reinterpret_cast<uint32_t *>(w.counters + 8);
-        fill_u32(nrest, 0u, 1, s);
+        // three stages, each on the cases the one before left, listed on the
+        // device (counts in counters[8] and [10]; surplus threads exit):
+        // the own cell and the 6 face neighbours one thread per case, then the
+        // 20 edge and corner neighbours one wavefront per case.  The first
+        // list is kept in the (free) chunk-flag array, the second in the hard
+        // list, which stage 1 has read by then.
+        int32_t *rest1 = reinterpret_cast<int32_t *>(w.f_chunk);
+        int32_t *rest2 = w.hardlist;
+        uint32_t *n1 = reinterpret_cast<uint32_t *>(w.counters + 8);
+        uint32_t *n2 = reinterpret_cast<uint32_t *>(w.counters + 10);
+        fill_u32(n1, 0u, 3, s);  // counters 8..10 (9 is the acceptance's, also zero here)
         const dim3 grid((unsigned)((nh + kBlock - 1) / kBlock));
-        hipLaunchKernelGGL(k_cand_hard, grid, dim3(kBlock), 0, s, w.s_dcell + n, 1, g, w.hardlist, w.sloc,
+        hipLaunchKernelGGL(k_cand_hard, grid, dim3(kBlock), 0, s, w.s_dcell + n, 1, 0, 1, g, w.hardlist, w.sloc,
                            w.spos, w.off, w.cnt, w.subtab, w.submax, w.subarg, w.dens_s, w.gkey, w.gid_of,
-                           w.gccnt, w.owner, rest, nrest);
-        hipLaunchKernelGGL(k_cand_hard, grid, dim3(kBlock), 0, s, nrest, 2, g, rest, w.sloc, w.spos, w.off,
+                           w.gccnt, w.owner, rest1, n1);
+        hipLaunchKernelGGL(k_cand_hard, grid, dim3(kBlock), 0, s, n1, 2, 1, 7, g, rest1, w.sloc, w.spos, w.off,
                            w.cnt, w.subtab, w.submax, w.subarg, w.dens_s, w.gkey, w.gid_of, w.gccnt, w.owner,
-                           nullptr, nullptr);
+                           rest2, n2);
+        // a fixed grid of wavefronts striding over the list
+        const int64_t waves = nh < 8192 ? nh : 8192;
+        hipLaunchKernelGGL(k_cand_wave, dim3((unsigned)((waves + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), 0,
+                           s, n2, 7, g, rest2, w.sloc, w.spos, w.off, w.cnt, w.subtab, w.submax, w.subarg,
+                           w.dens_s, w.gkey, w.gid_of, w.gccnt, w.owner);
     }
 }
 

@@ -200,10 +200,110 @@ __device__ __forceinline__ int block_min(int v, int *s_min) {
     return best;
 }
 
-// One workgroup per L0 group that has candidates: walk the candidates in
-// descending density; a candidate inside alpha R of an accepted nucleus is
-// ineligible; an eligible one is accepted and its enclosed count i found from
-// the bucket histogram of all particles of the group.
+constexpr int kWaveHist = 1024;   // groups below this size run one per wavefront
+constexpr int kWaveNuc = 64;      // ... when they have at most this many candidates
+
+// Groups with candidates, one wavefront each (four per workgroup), for the
+// groups of fewer than kWaveHist particles with at most kWaveNuc candidates:
+// the same walk as k_accept with the histogram, the accepted nuclei and their
+// positions in the wavefront's LDS and wave-level scans instead of workgroup
+// barriers, so that many small groups run on a CU at once.  The other groups
+// are appended to big_list (count in *big_count) for k_accept.
+__global__ __launch_bounds__(kBlock) void k_accept_small(const uint32_t *__restrict__ ngc_p, Geo g,
+                                                         const int32_t *__restrict__ glist,
+                                                         const int32_t *__restrict__ g_start,
+                                                         const int32_t *__restrict__ g_size,
+                                                         const uint32_t *__restrict__ gcoff,
+                                                         const int32_t *__restrict__ cand_sorted,
+                                                         const int32_t *__restrict__ mem,
+                                                         const float4 *__restrict__ spos,
+                                                         int32_t *__restrict__ h_nuc,
+                                                         int32_t *__restrict__ h_ienc,
+                                                         int32_t *__restrict__ h_gid,
+                                                         int32_t *__restrict__ g_nh,
+                                                         int32_t *__restrict__ big_list,
+                                                         uint32_t *__restrict__ big_count) {
+#pragma clang fp contract(off)
+    __shared__ uint32_t s_hist[kBlock / 64][kWaveHist];
+    __shared__ float4 s_hp[kBlock / 64][kWaveNuc];
+    __shared__ int32_t s_hi[kBlock / 64][kWaveNuc];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const uint32_t q = blockIdx.x * (kBlock / 64) + (uint32_t)wave;
+    if (q >= *ngc_p) return;
+    const int gi = glist[q];
+    const int64_t start = g_start[gi];
+    const int64_t m = g_size[gi];
+    const uint32_t cs = gcoff[gi], ce = gcoff[gi + 1];
+    if (m + 1 > kWaveHist || ce - cs > (uint32_t)kWaveNuc) {
+        if (lane == 0) big_list[atomicAdd(big_count, 1u)] = gi;
+        return;
+    }
+    uint32_t *hist = s_hist[wave];
+    int nh = 0;
+    for (uint32_t r = cs; r < ce; r++) {
+        const int c = cand_sorted[r];
+        const float4 pc = spos[c];
+        // eligibility: not inside alpha R of any accepted nucleus (nh <= 64)
+        bool inel = false;
+        if (lane < nh) {
+            const double e = d2_exact(pc, s_hp[wave][lane], g.L, g.half);
+            inel = g.K2 * e3(e) < g.A6 * ii(s_hi[wave][lane]);
+        }
+        if (__ballot(inel)) continue;
+        // bucket histogram over all m particles of the group
+        for (int64_t k = lane; k <= m; k += 64) hist[k] = 0u;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        for (int64_t t = lane; t < m; t += 64) {
+            const double e = d2_exact(pc, spos[mem[start + t]], g.L, g.half);
+            atomicAdd(&hist[bucket_of(g.K2 * e3(e), m)], 1u);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        // first k in [1, m-1] with C(k) <= k, C(k) = sum of buckets 0..k;
+        // lane L covers buckets 16L .. 16L + 15 (m < 1024)
+        uint32_t v[16];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int u = 0; u < 16; u++) {
+            const int64_t k = (int64_t)lane * 16 + u;
+            v[u] = k < m ? hist[k] : 0u;
+            sum += v[u];
+        }
+        uint32_t incl = sum;
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t y = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += y;
+        }
+        uint32_t C = incl - sum;
+        int hit = -1;
+#pragma unroll
+        for (int u = 0; u < 16; u++) {
+            const int64_t k = (int64_t)lane * 16 + u;
+            C += v[u];
+            if (hit < 0 && k >= 1 && k < m && (int64_t)C <= k) hit = (int)k;
+        }
+        const uint64_t hm = __ballot(hit >= 0);
+        const int64_t found = hm ? (int64_t)__shfl(hit, __ffsll((unsigned long long)hm) - 1, 64) : m;
+        if (lane == 0) {
+            h_nuc[cs + nh] = c;
+            h_ienc[cs + nh] = (int32_t)found;
+            h_gid[cs + nh] = gi;
+            s_hp[wave][nh] = pc;
+            s_hi[wave][nh] = (int32_t)found;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        nh++;
+    }
+    if (lane == 0) g_nh[gi] = nh;
+}
+
+// One workgroup per L0 group in `list` (count on the device): walk the
+// candidates in descending density; a candidate inside alpha R of an accepted
+// nucleus is ineligible; an eligible one is accepted and its enclosed count i
+// found from the bucket histogram of all particles of the group.
 __global__ __launch_bounds__(kBlock) void k_accept(const uint32_t *__restrict__ ngc_p, Geo g,
                                                    const int32_t *__restrict__ glist,
                                                    const int32_t *__restrict__ g_start,
@@ -413,9 +513,9 @@ void launch_segment(int64_t n, Work &w, hipStream_t s) {
     fill_u32(w.gcnt, 0u, n + 1, s);
     fill_u32(w.gfill, 0u, n + 1, s);
     hipLaunchKernelGGL(k_seg_count, grid(n), dim3(kBlock), 0, s, n, w.gkey, w.gcnt);
-    scan_u32(w.gcnt, w.goff, n, w.scan_tmp, s);
+    scan_u32(w.gcnt, w.goff, n, w.scan_tmp, s, w.err);
     hipLaunchKernelGGL(k_seg_flags, grid(n), dim3(kBlock), 0, s, n, w.gcnt, w.gflag);
-    scan_u32(w.gflag, w.gidx, n, w.scan_tmp, s);
+    scan_u32(w.gflag, w.gidx, n, w.scan_tmp, s, w.err);
 }
 
 void launch_segment_groups(int64_t n, int64_t G, Work &w, hipStream_t s) {
@@ -436,7 +536,7 @@ void launch_candidates_sort(int64_t n, int64_t G, int64_t NC, Work &w, hipStream
                            w.dens_s, w.spos, w.cand_sorted);
     if (G > 0)
         hipLaunchKernelGGL(k_glist_flags, grid(G), dim3(kBlock), 0, s, (int)G, w.gccnt, w.gcflag);
-    scan_u32(w.gcflag, w.gcidx, G, w.scan_tmp, s);
+    scan_u32(w.gcflag, w.gcidx, G, w.scan_tmp, s, w.err);
     if (G > 0)
         hipLaunchKernelGGL(k_glist, grid(G), dim3(kBlock), 0, s, (int)G, w.gcflag, w.gcidx, w.glist);
     fill_i32(w.h_nuc, -1, NC + 1, s);
@@ -444,11 +544,22 @@ void launch_candidates_sort(int64_t n, int64_t G, int64_t NC, Work &w, hipStream
     fill_i32(w.g_nh, 0, G + 1, s);
 }
 
-void launch_accept(int64_t G, int64_t NC, const Geo &g, Work &w, hipStream_t s) {
-    // one workgroup per group with candidates; there are at most min(G, NC)
+void launch_accept(int64_t G, int64_t NC, int64_t M, const Geo &g, Work &w, hipStream_t s) {
+    // groups with candidates (at most min(G, NC)), one wavefront each; the
+    // large ones are listed (in the free chunk-flag array, count in
+    // counters[9], zero since the call began) for one workgroup each: at most
+    // M / kWaveHist groups of kWaveHist particles or more and NC / (kWaveNuc + 1)
+    // groups with more than kWaveNuc candidates
     const int64_t bound = G < NC ? G : NC;
     if (bound <= 0) return;
-    hipLaunchKernelGGL(k_accept, dim3((unsigned)bound), dim3(kBlock), 0, s, w.gcidx + G, g, w.glist, w.g_start,
+    int32_t *big_list = reinterpret_cast<int32_t *>(w.f_chunk);
+    uint32_t *big_count = reinterpret_cast<uint32_t *>(w.counters + 9);
+    hipLaunchKernelGGL(k_accept_small, dim3((unsigned)((bound + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), 0,
+                       s, w.gcidx + G, g, w.glist, w.g_start, w.g_size, w.gcoff, w.cand_sorted, w.mem, w.spos,
+                       w.h_nuc, w.h_ienc, w.h_gid, w.g_nh, big_list, big_count);
+    int64_t nbig = M / kWaveHist + NC / (kWaveNuc + 1) + 1;
+    if (nbig > bound) nbig = bound;
+    hipLaunchKernelGGL(k_accept, dim3((unsigned)nbig), dim3(kBlock), 0, s, big_count, g, big_list, w.g_start,
                        w.g_size, w.gcoff, w.cand_sorted, w.mem, w.spos, w.hist, w.h_nuc, w.h_ienc, w.h_gid,
                        w.g_nh);
 }
@@ -463,7 +574,7 @@ void launch_output_flags(int64_t n, int64_t NC, const Geo &g, Work &w, hipStream
     if (NC > 0)
         hipLaunchKernelGGL(k_out_flags, grid(NC), dim3(kBlock), 0, s, NC, g, w.h_nuc, w.h_count, w.spos,
                            w.tflag, w.counters);
-    scan_u32(w.tflag, w.tpos, n, w.scan_tmp, s);
+    scan_u32(w.tflag, w.tpos, n, w.scan_tmp, s, w.err);
 }
 
 void launch_output(int64_t n, int64_t NC, const Geo &g, Work &w, int32_t *halo_id, int32_t *l0_out,

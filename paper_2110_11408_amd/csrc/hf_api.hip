@@ -241,6 +241,7 @@ hf_status err_status(Lane *c, uint32_t err) {
     if (err & 1) return fail(c, HF_ERR_INVALID, "positions must lie in [0, box)");
     if (err & 2) return fail(c, HF_ERR_INVALID, "l0_id values must lie in [0, n]");
     if (err & 4) return fail(c, HF_ERR_DEVICE, "internal error: L0 group key out of range");
+    if (err & 8) return fail(c, HF_ERR_DEVICE, "internal error: a prefix scan did not complete");
     return HF_OK;
 }
 
@@ -278,20 +279,21 @@ hf_status run_compaso(Lane *c, int64_t n, const Geo &g, Work &w, int32_t *halo_i
     hf::launch_segment_groups(n, G, w, s);
     HIP_OK(c, hipEventRecord(c->ev[4], s));
     hf::launch_candidates(n, g, w, s);
-    hf::scan_u32(w.gccnt, w.gcoff, G, w.scan_tmp, s);
+    hf::scan_u32(w.gccnt, w.gcoff, G, w.scan_tmp, s, w.err);
     uint32_t NC32 = 0;
     st = read_dev(c, s, {w.gcoff + G}, &NC32);
     if (st != HF_OK) return st;
     int64_t NC = NC32;
     hf::launch_candidates_sort(n, G, NC, w, s);
     HIP_OK(c, hipEventRecord(c->ev[5], s));
-    hf::launch_accept(G, NC, g, w, s);
+    hf::launch_accept(G, NC, c->stats.n_members, g, w, s);
     HIP_OK(c, hipEventRecord(c->ev[6], s));
     hf::launch_assign(n, g, w, s);
     HIP_OK(c, hipEventRecord(c->ev[7], s));
     hf::launch_output_flags(n, NC, g, w, s);
-    uint32_t r2[2];  // table rows; nuclei accepted (counter 2)
-    st = read_dev(c, s, {w.tpos + n, w.counters + 2}, r2);
+    uint32_t r2[3];  // table rows; nuclei accepted (counter 2); error flags
+    st = read_dev(c, s, {w.tpos + n, w.counters + 2, w.err}, r2);
+    if (st == HF_OK) st = err_status(c, r2[2]);
     if (st != HF_OK) return st;
     int64_t NH = r2[0];
     if (n_halos) *n_halos = NH;
@@ -635,13 +637,13 @@ hf_status hf_halo_stats(hf_ctx *ctx, const float *pos, const float *density, con
     hf::launch_segment_groups(n, G, w, s);
     HIP_OK(c, hipEventRecord(c->ev[4], s));
     hf::launch_candidates(n, g2, w, s);
-    hf::scan_u32(w.gccnt, w.gcoff, G, w.scan_tmp, s);
+    hf::scan_u32(w.gccnt, w.gcoff, G, w.scan_tmp, s, w.err);
     uint32_t NC32 = 0;
     st = read_dev(c, s, {w.gcoff + G}, &NC32);
     if (st != HF_OK) return st;
     hf::launch_candidates_sort(n, G, NC32, w, s);
     HIP_OK(c, hipEventRecord(c->ev[5], s));
-    hf::launch_accept(G, NC32, g2, w, s);
+    hf::launch_accept(G, NC32, M, g2, w, s);
     HIP_OK(c, hipEventRecord(c->ev[6], s));
     hf::launch_assign(n, g2, w, s);
     HIP_OK(c, hipEventRecord(c->ev[7], s));
