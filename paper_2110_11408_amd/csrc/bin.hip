@@ -442,7 +442,7 @@ uint64_t *radix_sort_keys(uint64_t *a, uint64_t *b, int64_t n, int lo, int bits,
         const int shift = lo + p * D;
         hipLaunchKernelGGL(k_radix_count, dim3((unsigned)ntiles), dim3(256), 0, s, cur, n, shift, D, ntiles,
                            w.rhist);
-        scan_u32(w.rhist, w.rscan, hl, w.scan_tmp, s, w.err);
+        scan_u32(w.rhist, w.rscan, hl, w.scan_tmp, s);
         hipLaunchKernelGGL(k_radix_scatter<true>, dim3((unsigned)ntiles), dim3(256), 0, s, cur, nullptr, n, shift,
                            D, ntiles, w.rscan, nxt, nullptr);
         uint64_t *t = cur;
@@ -464,7 +464,7 @@ void launch_bin(const float *pos, int64_t n, const Geo &g, Work &w, hipStream_t 
         const int shift = r.ib + p * r.D;
         hipLaunchKernelGGL(k_radix_count, dim3((unsigned)ntiles), dim3(256), 0, s, w.rkey[cur], n, shift, r.D,
                            ntiles, w.rhist);
-        scan_u32(w.rhist, w.rscan, hl, w.scan_tmp, s, w.err);
+        scan_u32(w.rhist, w.rscan, hl, w.scan_tmp, s);
         if (packed)
             hipLaunchKernelGGL(k_radix_scatter<true>, dim3((unsigned)ntiles), dim3(256), 0, s, w.rkey[cur],
                                nullptr, n, shift, r.D, ntiles, w.rscan, w.rkey[cur ^ 1], nullptr);
@@ -485,9 +485,9 @@ void launch_bin(const float *pos, int64_t n, const Geo &g, Work &w, hipStream_t 
                        ncell, w.sloc, w.off);
     hipLaunchKernelGGL(k_bin_flags, dim3(blocks(n)), dim3(kBlock), 0, s, n, w.sloc, w.off, w.f_chunk,
                        w.f_dcell, w.f_sparse);
-    scan_u32(w.f_chunk, w.s_chunk, n, w.scan_tmp, s, w.err);
-    scan_u32(w.f_dcell, w.s_dcell, n, w.scan_tmp, s, w.err);
-    scan_u32(w.f_sparse, w.s_sparse, n, w.scan_tmp, s, w.err);
+    scan_u32(w.f_chunk, w.s_chunk, n, w.scan_tmp, s);
+    scan_u32(w.f_dcell, w.s_dcell, n, w.scan_tmp, s);
+    scan_u32(w.f_sparse, w.s_sparse, n, w.scan_tmp, s);
     hipLaunchKernelGGL(k_bin_lists, dim3(blocks(n)), dim3(kBlock), 0, s, n, w.f_chunk, w.s_chunk,
                        w.f_dcell, w.s_dcell, w.f_sparse, w.s_sparse, w.sloc, w.chunks, w.dcells,
                        w.sparse, w.cnt);

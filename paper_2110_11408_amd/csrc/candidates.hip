@@ -397,7 +397,7 @@ void launch_candidates(int64_t n, const Geo &g, Work &w, hipStream_t s) {
     // it; the hard-case flags and their scan reuse the dense-cell flag arrays
     hipLaunchKernelGGL(k_cand_quick, dim3(blocks), dim3(kBlock), 0, s, n, g, w.sloc, w.spos, w.f_sparse, w.ssub,
                        w.cnt, w.subarg, w.dens_s, w.gkey, w.owner, w.f_dcell);
-    scan_u32(w.f_dcell, w.s_dcell, n, w.scan_tmp, s, w.err);
+    scan_u32(w.f_dcell, w.s_dcell, n, w.scan_tmp, s);
     hipLaunchKernelGGL(k_hard_list, dim3(blocks), dim3(kBlock), 0, s, n, w.f_dcell, w.s_dcell, w.hardlist);
     uint32_t nh = 0;
     WordSrc src{};

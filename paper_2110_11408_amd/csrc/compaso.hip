@@ -352,11 +352,25 @@ __global__ __launch_bounds__(kBlock) void k_accept(const uint32_t *__restrict__ 
             __threadfence();
         }
         __syncthreads();
-        for (int64_t t = tid; t < m; t += kBlock) {
-            const double e = d2_exact(pc, spos[mem[start + t]], g.L, g.half);
-            const int64_t bk = bucket_of(g.K2 * e3(e), m);
-            if (in_lds) atomicAdd(&s_hist[bk], 1u);
-            else atomicAdd(ghist + bk, 1u);
+        // eight members per thread and round, their loads issued together
+        for (int64_t t0 = tid; t0 < m; t0 += 8 * kBlock) {
+            int32_t id[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const int64_t t = t0 + (int64_t)u * kBlock;
+                id[u] = t < m ? mem[start + t] : -1;
+            }
+            float4 pm[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) pm[u] = id[u] >= 0 ? spos[id[u]] : pc;
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                if (id[u] < 0) continue;
+                const double e = d2_exact(pc, pm[u], g.L, g.half);
+                const int64_t bk = bucket_of(g.K2 * e3(e), m);
+                if (in_lds) atomicAdd(&s_hist[bk], 1u);
+                else atomicAdd(ghist + bk, 1u);
+            }
         }
         if (!in_lds) __threadfence();
         __syncthreads();
@@ -513,9 +527,9 @@ void launch_segment(int64_t n, Work &w, hipStream_t s) {
     fill_u32(w.gcnt, 0u, n + 1, s);
     fill_u32(w.gfill, 0u, n + 1, s);
     hipLaunchKernelGGL(k_seg_count, grid(n), dim3(kBlock), 0, s, n, w.gkey, w.gcnt);
-    scan_u32(w.gcnt, w.goff, n, w.scan_tmp, s, w.err);
+    scan_u32(w.gcnt, w.goff, n, w.scan_tmp, s);
     hipLaunchKernelGGL(k_seg_flags, grid(n), dim3(kBlock), 0, s, n, w.gcnt, w.gflag);
-    scan_u32(w.gflag, w.gidx, n, w.scan_tmp, s, w.err);
+    scan_u32(w.gflag, w.gidx, n, w.scan_tmp, s);
 }
 
 void launch_segment_groups(int64_t n, int64_t G, Work &w, hipStream_t s) {
@@ -536,7 +550,7 @@ void launch_candidates_sort(int64_t n, int64_t G, int64_t NC, Work &w, hipStream
                            w.dens_s, w.spos, w.cand_sorted);
     if (G > 0)
         hipLaunchKernelGGL(k_glist_flags, grid(G), dim3(kBlock), 0, s, (int)G, w.gccnt, w.gcflag);
-    scan_u32(w.gcflag, w.gcidx, G, w.scan_tmp, s, w.err);
+    scan_u32(w.gcflag, w.gcidx, G, w.scan_tmp, s);
     if (G > 0)
         hipLaunchKernelGGL(k_glist, grid(G), dim3(kBlock), 0, s, (int)G, w.gcflag, w.gcidx, w.glist);
     fill_i32(w.h_nuc, -1, NC + 1, s);
@@ -574,7 +588,7 @@ void launch_output_flags(int64_t n, int64_t NC, const Geo &g, Work &w, hipStream
     if (NC > 0)
         hipLaunchKernelGGL(k_out_flags, grid(NC), dim3(kBlock), 0, s, NC, g, w.h_nuc, w.h_count, w.spos,
                            w.tflag, w.counters);
-    scan_u32(w.tflag, w.tpos, n, w.scan_tmp, s, w.err);
+    scan_u32(w.tflag, w.tpos, n, w.scan_tmp, s);
 }
 
 void launch_output(int64_t n, int64_t NC, const Geo &g, Work &w, int32_t *halo_id, int32_t *l0_out,

@@ -192,40 +192,45 @@ __global__ __launch_bounds__(kBlock) void k_density_sparse(int64_t nsparse, Geo 
     // away from the periodic x edges the three cells of a stencil row are
     // consecutive: their four bounding offsets are one 16-byte load
     const bool inner = cx > 0 && cx < nc - 1;
-    // all 27 offsets are loaded before any neighbour is streamed, so that
-    // their latencies overlap
-    uint32_t ra[27], rb[27];
-#pragma unroll
-    for (int r9 = 0; r9 < 9; r9++) {
-        const int oz = r9 / 3 - 1, oy = r9 % 3 - 1;
-        const uint32_t row = ((uint32_t)wrapc(cz + oz, nc) * (uint32_t)nc + (uint32_t)wrapc(cy + oy, nc)) *
-                             (uint32_t)nc;
-        const int r = r9 * 3;
-        if (inner) {
-            const uint32_t *p = off + row + x0;
-            const uint32_t o0 = p[0], o1 = p[1], o2 = p[2], o3 = p[3];
-            ra[r + 0] = o0;
-            rb[r + 0] = o1;
-            ra[r + 1] = o1;
-            rb[r + 1] = o2;
-            ra[r + 2] = o2;
-            rb[r + 2] = o3;
-        } else {
-            ra[r + 0] = off[row + x0];
-            rb[r + 0] = off[row + x0 + 1];
-            ra[r + 1] = off[row + x1];
-            rb[r + 1] = off[row + x1 + 1];
-            ra[r + 2] = off[row + x2];
-            rb[r + 2] = off[row + x2 + 1];
-        }
-    }
     double acc = 0.0;
+    for (int oz = -1; oz <= 1; oz++) {
+        const int z = wrapc(cz + oz, nc);
+        const float zs = li.z - (float)oz * g.cellb;
+        // the offsets of this plane are loaded together so their latencies overlap
+        uint32_t ra[9], rb[9];
 #pragma unroll
-    for (int r = 0; r < 27; r++) {
-        const int ox = r % 3 - 1, oy = (r / 3) % 3 - 1, oz = r / 9 - 1;
-        if (rb[r] - ra[r] >= (uint32_t)kDenseMin) continue;
-        accum_range(sloc, ra[r], rb[r], li.x - (float)ox * g.cellb, li.y - (float)oy * g.cellb,
-                    li.z - (float)oz * g.cellb, acc);
+        for (int oy = -1; oy <= 1; oy++) {
+            const uint32_t row = ((uint32_t)z * (uint32_t)nc + (uint32_t)wrapc(cy + oy, nc)) * (uint32_t)nc;
+            const int r = (oy + 1) * 3;
+            if (inner) {
+                const uint32_t *p = off + row + x0;
+                const uint32_t o0 = p[0], o1 = p[1], o2 = p[2], o3 = p[3];
+                ra[r + 0] = o0;
+                rb[r + 0] = o1;
+                ra[r + 1] = o1;
+                rb[r + 1] = o2;
+                ra[r + 2] = o2;
+                rb[r + 2] = o3;
+            } else {
+                ra[r + 0] = off[row + x0];
+                rb[r + 0] = off[row + x0 + 1];
+                ra[r + 1] = off[row + x1];
+                rb[r + 1] = off[row + x1 + 1];
+                ra[r + 2] = off[row + x2];
+                rb[r + 2] = off[row + x2 + 1];
+            }
+        }
+#pragma unroll
+        for (int oy = -1; oy <= 1; oy++) {
+            const float ys = li.y - (float)oy * g.cellb;
+#pragma unroll
+            for (int ox = -1; ox <= 1; ox++) {
+                const int r = (oy + 1) * 3 + (ox + 1);
+                if (rb[r] - ra[r] >= (uint32_t)kDenseMin) continue;
+                const float xs = li.x - (float)ox * g.cellb;
+                accum_range(sloc, ra[r], rb[r], xs, ys, zs, acc);
+            }
+        }
     }
     acc += (double)dfx[t] * (1.0 / kFixScale);
     write_density(i, acc, g, spos, dens_s, dens_out);

@@ -563,7 +563,7 @@ void launch_fof(int64_t n, const Geo &g, Work &w, hipStream_t s) {
         // during this stage (chunk flags of the binning, the hard-case list)
         hipLaunchKernelGGL(k_fof_sparse_flags, grid(w.nsparse), dim3(kBlock), 0, s, w.nsparse, g, w.sparse,
                            w.dens_s, w.f_chunk);
-        scan_u32(w.f_chunk, w.s_chunk, w.nsparse, w.scan_tmp, s, w.err);
+        scan_u32(w.f_chunk, w.s_chunk, w.nsparse, w.scan_tmp, s);
         hipLaunchKernelGGL(k_fof_sparse_list, grid(w.nsparse), dim3(kBlock), 0, s, w.nsparse, w.sparse,
                            w.f_chunk, w.s_chunk, w.hardlist);
         hipLaunchKernelGGL(k_fof_sparse, grid(w.nsparse), dim3(kBlock), 0, s, w.s_chunk + w.nsparse, g,

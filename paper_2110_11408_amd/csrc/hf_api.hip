@@ -241,7 +241,6 @@ hf_status err_status(Lane *c, uint32_t err) {
     if (err & 1) return fail(c, HF_ERR_INVALID, "positions must lie in [0, box)");
     if (err & 2) return fail(c, HF_ERR_INVALID, "l0_id values must lie in [0, n]");
     if (err & 4) return fail(c, HF_ERR_DEVICE, "internal error: L0 group key out of range");
-    if (err & 8) return fail(c, HF_ERR_DEVICE, "internal error: a prefix scan did not complete");
     return HF_OK;
 }
 
@@ -279,7 +278,7 @@ hf_status run_compaso(Lane *c, int64_t n, const Geo &g, Work &w, int32_t *halo_i
     hf::launch_segment_groups(n, G, w, s);
     HIP_OK(c, hipEventRecord(c->ev[4], s));
     hf::launch_candidates(n, g, w, s);
-    hf::scan_u32(w.gccnt, w.gcoff, G, w.scan_tmp, s, w.err);
+    hf::scan_u32(w.gccnt, w.gcoff, G, w.scan_tmp, s);
     uint32_t NC32 = 0;
     st = read_dev(c, s, {w.gcoff + G}, &NC32);
     if (st != HF_OK) return st;
@@ -637,7 +636,7 @@ hf_status hf_halo_stats(hf_ctx *ctx, const float *pos, const float *density, con
     hf::launch_segment_groups(n, G, w, s);
     HIP_OK(c, hipEventRecord(c->ev[4], s));
     hf::launch_candidates(n, g2, w, s);
-    hf::scan_u32(w.gccnt, w.gcoff, G, w.scan_tmp, s, w.err);
+    hf::scan_u32(w.gccnt, w.gcoff, G, w.scan_tmp, s);
     uint32_t NC32 = 0;
     st = read_dev(c, s, {w.gcoff + G}, &NC32);
     if (st != HF_OK) return st;

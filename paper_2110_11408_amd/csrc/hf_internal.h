@@ -177,10 +177,8 @@ struct WordSrc {
 hipError_t read_words(const WordSrc &src, int k, uint32_t *host, uint32_t *out, hipStream_t s);
 void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
-// Exclusive scan: out[0..n] with out[n] = total (in may equal out).  tmp:
-// scan_tmp_words(n) words, 8-byte aligned.  A look-back that does not complete
-// sets bit 8 of *err (never expected; reported as an internal error).
-void scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipStream_t s, int32_t *err);
+// Exclusive scan: out[0..n] with out[n] = total.  tmp: scan_tmp_words(n) words.
+void scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipStream_t s);
 int64_t scan_tmp_words(int64_t n);
 
 void launch_bin(const float *pos, int64_t n, const Geo &g, Work &w, hipStream_t s);

@@ -1,13 +1,12 @@
 // Device-wide exclusive prefix sum of uint32 arrays and fill kernels.
 //
-// One pass with decoupled look-back: every tile of 256 threads x 16 items
-// takes a ticket in launch order, scans its items staged through LDS,
-// publishes its sum, and adds the sum of all earlier tiles, read back from
-// their published sums and inclusive prefixes (each status word holds a flag
-// and a value).  A tile only waits for tiles with smaller tickets, which have
-// started before it, so every wait ends; the wait is bounded anyway and a
-// timeout is reported through the error word.  LDS indices are padded by one
-// word per 32 to keep the per-thread runs of 16 words off a single bank.
+// Three passes per level: tile sums (coalesced reads), a recursive scan of the
+// tile sums, and a tile scan staged through LDS that adds each tile's offset.
+// (A single pass with decoupled look-back was slower here: on this chip the
+// chain of status words between thousands of tiles goes through memory that
+// every XCD must see, a few microseconds per link.)
+// Tiles are 256 threads x 16 items; LDS indices are padded by one word per 32
+// to keep the per-thread runs of 16 words off a single bank.
 #include "hf_internal.h"
 
 namespace hf {
@@ -48,16 +47,56 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total)
     return pre + inc - v;
 }
 
+// Full tiles are moved as 16-byte vectors (in and out are 16-byte aligned:
+// arena arrays, and the tile-sum arrays below are padded to four words); the
+// last, partial tile word by word.
+__global__ __launch_bounds__(kBlock) void k_tile_sums(const uint32_t *__restrict__ in, int64_t n,
+                                                      uint32_t *__restrict__ sums) {
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    uint32_t s = 0;
+    if (base + kTile <= n) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(in + base);
+#pragma unroll
+        for (int k = 0; k < kIpt / 4; k++) {
+            const uint4 v = p[k * kBlock + threadIdx.x];
+            s += (v.x + v.y) + (v.z + v.w);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kIpt; k++) {
+            const int64_t i = base + k * kBlock + threadIdx.x;
+            if (i < n) s += in[i];
+        }
+    }
+    uint32_t tot;
+    block_excl_scan(s, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
 __global__ __launch_bounds__(kBlock) void k_tile_scan(const uint32_t *__restrict__ in,
                                                       uint32_t *__restrict__ out, int64_t n,
                                                       const uint32_t *__restrict__ tile_off) {
     __shared__ uint32_t buf[kTile + kTile / 32];
-    int64_t base = (int64_t)blockIdx.x * kTile;
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    const bool full = base + kTile <= n;
+    if (full) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(in + base);
 #pragma unroll
-    for (int k = 0; k < kIpt; k++) {
-        int idx = k * kBlock + threadIdx.x;
-        int64_t i = base + idx;
-        buf[pad(idx)] = i < n ? in[i] : 0u;
+        for (int k = 0; k < kIpt / 4; k++) {
+            const int q = k * kBlock + threadIdx.x;
+            const uint4 v = p[q];
+            buf[pad(4 * q + 0)] = v.x;
+            buf[pad(4 * q + 1)] = v.y;
+            buf[pad(4 * q + 2)] = v.z;
+            buf[pad(4 * q + 3)] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kIpt; k++) {
+            const int idx = k * kBlock + threadIdx.x;
+            const int64_t i = base + idx;
+            buf[pad(idx)] = i < n ? in[i] : 0u;
+        }
     }
     __syncthreads();
     uint32_t v[kIpt];
@@ -69,7 +108,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_scan(const uint32_t *__restrict
     }
     uint32_t tot;
     uint32_t run = block_excl_scan(s, &tot);
-    uint32_t toff = tile_off ? tile_off[blockIdx.x] : 0u;
+    const uint32_t toff = tile_off ? tile_off[blockIdx.x] : 0u;
     run += toff;
 #pragma unroll
     for (int k = 0; k < kIpt; k++) {
@@ -77,88 +116,22 @@ __global__ __launch_bounds__(kBlock) void k_tile_scan(const uint32_t *__restrict
         run += v[k];
     }
     __syncthreads();
+    if (full) {
+        uint4 *p = reinterpret_cast<uint4 *>(out + base);
 #pragma unroll
-    for (int k = 0; k < kIpt; k++) {
-        int idx = k * kBlock + threadIdx.x;
-        int64_t i = base + idx;
-        if (i < n) out[i] = buf[pad(idx)];
+        for (int k = 0; k < kIpt / 4; k++) {
+            const int q = k * kBlock + threadIdx.x;
+            p[q] = make_uint4(buf[pad(4 * q + 0)], buf[pad(4 * q + 1)], buf[pad(4 * q + 2)], buf[pad(4 * q + 3)]);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kIpt; k++) {
+            const int idx = k * kBlock + threadIdx.x;
+            const int64_t i = base + idx;
+            if (i < n) out[i] = buf[pad(idx)];
+        }
     }
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = toff + tot;
-}
-
-constexpr uint64_t kAggregate = 1ull << 32;  // status flag: the tile's own sum
-constexpr uint64_t kInclusive = 2ull << 32;  // status flag: sum of the tiles up to this one
-constexpr uint32_t kSpinLimit = 1u << 22;
-
-__global__ __launch_bounds__(kBlock) void k_scan_onepass(const uint32_t *in, uint32_t *out, int64_t n,
-                                                         uint32_t *__restrict__ ticket,
-                                                         uint64_t *__restrict__ status,
-                                                         int32_t *__restrict__ err) {
-    __shared__ uint32_t buf[kTile + kTile / 32];
-    __shared__ uint32_t s_tile, s_prefix;
-    if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
-    __syncthreads();
-    const uint32_t tile = s_tile;
-    const int64_t base = (int64_t)tile * kTile;
-#pragma unroll
-    for (int k = 0; k < kIpt; k++) {
-        const int idx = k * kBlock + threadIdx.x;
-        const int64_t i = base + idx;
-        buf[pad(idx)] = i < n ? in[i] : 0u;
-    }
-    __syncthreads();
-    uint32_t v[kIpt];
-    uint32_t sum = 0;
-#pragma unroll
-    for (int k = 0; k < kIpt; k++) {
-        v[k] = buf[pad(threadIdx.x * kIpt + k)];
-        sum += v[k];
-    }
-    uint32_t tot;
-    uint32_t run = block_excl_scan(sum, &tot);
-    if (threadIdx.x == 0) {
-        uint32_t prefix = 0;
-        if (tile == 0) {
-            __hip_atomic_store(status, kInclusive | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            __hip_atomic_store(status + tile, kAggregate | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            int64_t j = (int64_t)tile - 1;
-            uint32_t spins = 0;
-            while (j >= 0) {
-                const uint64_t st = __hip_atomic_load(status + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const uint64_t flag = st & (3ull << 32);
-                if (flag == 0) {
-                    if (++spins > kSpinLimit) {
-                        if (err) atomicOr(err, 8);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
-                }
-                prefix += (uint32_t)st;
-                if (flag == kInclusive) break;
-                j--;
-            }
-            __hip_atomic_store(status + tile, kInclusive | (uint32_t)(prefix + tot), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        }
-        s_prefix = prefix;
-    }
-    __syncthreads();
-    run += s_prefix;
-#pragma unroll
-    for (int k = 0; k < kIpt; k++) {
-        buf[pad(threadIdx.x * kIpt + k)] = run;
-        run += v[k];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < kIpt; k++) {
-        const int idx = k * kBlock + threadIdx.x;
-        const int64_t i = base + idx;
-        if (i < n) out[i] = buf[pad(idx)];
-    }
-    if (base + kTile >= n && threadIdx.x == 0) out[n] = s_prefix + tot;
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
@@ -209,23 +182,31 @@ hipError_t read_words(const WordSrc &src, int k, uint32_t *host, uint32_t *out, 
     return hipSuccess;
 }
 
+// Words of one tile-sum array (tiles + 1), rounded up to keep 16-byte alignment.
+static int64_t sums_words(int64_t tiles) { return (tiles + 1 + 3) & ~(int64_t)3; }
+
 int64_t scan_tmp_words(int64_t n) {
-    // ticket (padded to 8 bytes) and one 64-bit status word per tile
-    const int64_t tiles = (n + kTile - 1) / kTile;
-    return 2 * (tiles + 1) + 16;
+    int64_t w = 0;
+    while (n > kTile) {
+        int64_t t = (n + kTile - 1) / kTile;
+        w += 2 * sums_words(t);
+        n = t;
+    }
+    return w + 16;
 }
 
-void scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipStream_t s, int32_t *err) {
+void scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipStream_t s) {
     int64_t tiles = (n + kTile - 1) / kTile;
     if (tiles < 1) tiles = 1;
     if (tiles == 1) {
         hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kBlock), 0, s, in, out, n, nullptr);
         return;
     }
-    // tmp (256-byte aligned): ticket in word 0, status words from word 2
-    fill_u32(tmp, 0u, 2 * (tiles + 1), s);
-    hipLaunchKernelGGL(k_scan_onepass, dim3((unsigned)tiles), dim3(kBlock), 0, s, in, out, n, tmp,
-                       reinterpret_cast<uint64_t *>(tmp + 2), err);
+    uint32_t *sums = tmp;
+    uint32_t *sums_scan = tmp + sums_words(tiles);
+    hipLaunchKernelGGL(k_tile_sums, dim3(tiles), dim3(kBlock), 0, s, in, n, sums);
+    scan_u32(sums, sums_scan, tiles, tmp + 2 * sums_words(tiles), s);
+    hipLaunchKernelGGL(k_tile_scan, dim3(tiles), dim3(kBlock), 0, s, in, out, n, sums_scan);
 }
 
 }  // namespace hf

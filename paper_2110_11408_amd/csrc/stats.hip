@@ -266,7 +266,7 @@ void launch_halo_stats(int64_t n, int64_t G, int64_t M, const Geo &g, double par
     uint64_t *lk = nullptr;
     if (group_members) {
         hipLaunchKernelGGL(k_members_flags, grid(n), dim3(kBlock), 0, s, n, halo_id, w.f_chunk);
-        scan_u32(w.f_chunk, w.s_chunk, n, w.scan_tmp, s, w.err);
+        scan_u32(w.f_chunk, w.s_chunk, n, w.scan_tmp, s);
         hipLaunchKernelGGL(k_members_keys, grid(n), dim3(kBlock), 0, s, n, halo_id, w.ordk, w.f_chunk, w.s_chunk,
                            w.rkey[0]);
         // the index bits are already in order: sort by the ordinal bits only
