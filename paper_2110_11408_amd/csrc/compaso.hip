@@ -166,10 +166,12 @@ __device__ __forceinline__ int64_t bucket_of(double T, int64_t m) {
     return k;
 }
 
-constexpr int kHistLds = 12288;   // groups up to this size keep their histogram in LDS
+constexpr int kHistMid = 12288;   // histogram buckets of a medium group counted in LDS (48 KB)
+constexpr int kHistBig = 36864;   // histogram buckets of a large group counted in LDS (144 KB)
 constexpr int kScanIpt = 16;      // buckets per thread per scan step
 
-// Block-wide exclusive scan of one value per thread (256 threads).
+// Block-wide exclusive scan of one value per thread (NT threads).
+template <int NT>
 __device__ __forceinline__ uint32_t block_excl(uint32_t v, uint32_t *s_red, uint32_t *total) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     uint32_t inc = v;
@@ -180,7 +182,7 @@ __device__ __forceinline__ uint32_t block_excl(uint32_t v, uint32_t *s_red, uint
     if (lane == 63) s_red[wid] = inc;
     __syncthreads();
     uint32_t pre = 0, tot = 0;
-    for (int w = 0; w < kBlock / 64; w++) {
+    for (int w = 0; w < NT / 64; w++) {
         if (w < wid) pre += s_red[w];
         tot += s_red[w];
     }
@@ -189,13 +191,14 @@ __device__ __forceinline__ uint32_t block_excl(uint32_t v, uint32_t *s_red, uint
     return pre + inc - v;
 }
 
+template <int NT>
 __device__ __forceinline__ int block_min(int v, int *s_min) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int d = 32; d >= 1; d >>= 1) v = min(v, __shfl_xor(v, d, 64));
     if (lane == 0) s_min[wid] = v;
     __syncthreads();
     int best = s_min[0];
-    for (int w = 1; w < kBlock / 64; w++) best = min(best, s_min[w]);
+    for (int w = 1; w < NT / 64; w++) best = min(best, s_min[w]);
     __syncthreads();
     return best;
 }
@@ -208,7 +211,8 @@ constexpr int kWaveNuc = 64;      // ... when they have at most this many candid
 // the same walk as k_accept with the histogram, the accepted nuclei and their
 // positions in the wavefront's LDS and wave-level scans instead of workgroup
 // barriers, so that many small groups run on a CU at once.  The other groups
-// are appended to big_list (count in *big_count) for k_accept.
+// are appended to mid_list (fewer than kHistMid particles) or big_list, with
+// their counts in *mid_count and *big_count, for k_accept.
 __global__ __launch_bounds__(kBlock) void k_accept_small(const uint32_t *__restrict__ ngc_p, Geo g,
                                                          const int32_t *__restrict__ glist,
                                                          const int32_t *__restrict__ g_start,
@@ -221,6 +225,8 @@ __global__ __launch_bounds__(kBlock) void k_accept_small(const uint32_t *__restr
                                                          int32_t *__restrict__ h_ienc,
                                                          int32_t *__restrict__ h_gid,
                                                          int32_t *__restrict__ g_nh,
+                                                         int32_t *__restrict__ mid_list,
+                                                         uint32_t *__restrict__ mid_count,
                                                          int32_t *__restrict__ big_list,
                                                          uint32_t *__restrict__ big_count) {
 #pragma clang fp contract(off)
@@ -236,7 +242,10 @@ __global__ __launch_bounds__(kBlock) void k_accept_small(const uint32_t *__restr
     const int64_t m = g_size[gi];
     const uint32_t cs = gcoff[gi], ce = gcoff[gi + 1];
     if (m + 1 > kWaveHist || ce - cs > (uint32_t)kWaveNuc) {
-        if (lane == 0) big_list[atomicAdd(big_count, 1u)] = gi;
+        if (lane == 0) {
+            if (m + 1 <= kHistMid) mid_list[atomicAdd(mid_count, 1u)] = gi;
+            else big_list[atomicAdd(big_count, 1u)] = gi;
+        }
         return;
     }
     uint32_t *hist = s_hist[wave];
@@ -304,8 +313,9 @@ __global__ __launch_bounds__(kBlock) void k_accept_small(const uint32_t *__restr
 // candidates in descending density; a candidate inside alpha R of an accepted
 // nucleus is ineligible; an eligible one is accepted and its enclosed count i
 // found from the bucket histogram of all particles of the group.
-__global__ __launch_bounds__(kBlock) void k_accept(const uint32_t *__restrict__ ngc_p, Geo g,
-                                                   const int32_t *__restrict__ glist,
+template <int NT, int HL>
+__global__ __launch_bounds__(NT) void k_accept(const uint32_t *__restrict__ ngc_p, Geo g,
+                                               const int32_t *__restrict__ glist,
                                                    const int32_t *__restrict__ g_start,
                                                    const int32_t *__restrict__ g_size,
                                                    const uint32_t *__restrict__ gcoff,
@@ -318,18 +328,22 @@ __global__ __launch_bounds__(kBlock) void k_accept(const uint32_t *__restrict__ 
                                                    int32_t *__restrict__ h_gid,
                                                    int32_t *__restrict__ g_nh) {
 #pragma clang fp contract(off)
-    __shared__ uint32_t s_hist[kHistLds + 1];
+    __shared__ uint32_t s_hist[HL + 1];
     __shared__ int s_nh;
-    __shared__ uint32_t s_red[kBlock / 64];
-    __shared__ int s_min[kBlock / 64];
+    __shared__ uint32_t s_red[NT / 64];
+    __shared__ int s_min[NT / 64];
     // the grid is an upper bound; the number of groups with candidates is read here
     if (blockIdx.x >= *ngc_p) return;
     const int gi = glist[blockIdx.x];
     const int64_t start = g_start[gi];
     const int64_t m = g_size[gi];
     const uint32_t cs = gcoff[gi], ce = gcoff[gi + 1];
-    const bool in_lds = m + 1 <= kHistLds;
-    uint32_t *ghist = hist_all + start + gi;  // m + 1 buckets, disjoint per group
+    // buckets below HL live in LDS; a group with more buckets keeps the
+    // rest in its own global region (m + 1 words, disjoint per group).  The
+    // small buckets are where the particles of a dense core pile up, so the
+    // global atomics are only the sparse outer ones.
+    const bool spill = m + 1 > HL;
+    uint32_t *ghist = hist_all + start + gi;
     const int tid = threadIdx.x;
     if (tid == 0) s_nh = 0;
     __syncthreads();
@@ -339,64 +353,65 @@ __global__ __launch_bounds__(kBlock) void k_accept(const uint32_t *__restrict__ 
         const int nh = s_nh;
         // eligibility: not inside alpha R of any accepted nucleus
         int inel = 0;
-        for (int h = tid; h < nh; h += kBlock) {
+        for (int h = tid; h < nh; h += NT) {
             const double e = d2_exact(pc, spos[ldi(h_nuc + cs + h)], g.L, g.half);
             if (g.K2 * e3(e) < g.A6 * ii(ldi(h_ienc + cs + h))) inel = 1;
         }
         if (__syncthreads_or(inel)) continue;
         // histogram of buckets over all particles of the group
-        if (in_lds) {
-            for (int64_t k = tid; k <= m; k += kBlock) s_hist[k] = 0u;
-        } else {
-            for (int64_t k = tid; k <= m; k += kBlock) stu(ghist + k, 0u);
+        for (int64_t k = tid; k <= m && k < HL; k += NT) s_hist[k] = 0u;
+        if (spill) {
+            for (int64_t k = HL + tid; k <= m; k += NT) stu(ghist + k, 0u);
             __threadfence();
         }
         __syncthreads();
-        // eight members per thread and round, their loads issued together
-        for (int64_t t0 = tid; t0 < m; t0 += 8 * kBlock) {
-            int32_t id[8];
+        // UB members per thread and round, their loads issued together
+        constexpr int UB = NT >= 1024 ? 4 : 8;
+        for (int64_t t0 = tid; t0 < m; t0 += UB * NT) {
+            int32_t id[UB];
 #pragma unroll
-            for (int u = 0; u < 8; u++) {
-                const int64_t t = t0 + (int64_t)u * kBlock;
+            for (int u = 0; u < UB; u++) {
+                const int64_t t = t0 + (int64_t)u * NT;
                 id[u] = t < m ? mem[start + t] : -1;
             }
-            float4 pm[8];
+            float4 pm[UB];
 #pragma unroll
-            for (int u = 0; u < 8; u++) pm[u] = id[u] >= 0 ? spos[id[u]] : pc;
+            for (int u = 0; u < UB; u++) pm[u] = id[u] >= 0 ? spos[id[u]] : pc;
 #pragma unroll
-            for (int u = 0; u < 8; u++) {
+            for (int u = 0; u < UB; u++) {
                 if (id[u] < 0) continue;
                 const double e = d2_exact(pc, pm[u], g.L, g.half);
                 const int64_t bk = bucket_of(g.K2 * e3(e), m);
-                if (in_lds) atomicAdd(&s_hist[bk], 1u);
+                if (bk < HL) atomicAdd(&s_hist[bk], 1u);
                 else atomicAdd(ghist + bk, 1u);
             }
         }
-        if (!in_lds) __threadfence();
+        if (spill) __threadfence();
         __syncthreads();
         // first k in [1, m-1] with C(k) <= k, C(k) = sum of buckets 0..k
+        constexpr int SI = NT >= 1024 ? kScanIpt / 2 : kScanIpt;
         int64_t found = m;
         uint32_t run = 0;
-        for (int64_t base = 0; base < m; base += (int64_t)kBlock * kScanIpt) {
-            const int64_t k0 = base + (int64_t)tid * kScanIpt;
-            uint32_t v[kScanIpt];
+        for (int64_t base = 0; base < m; base += (int64_t)NT * SI) {
+            const int64_t k0 = base + (int64_t)tid * SI;
+            uint32_t v[SI];
             uint32_t sum = 0;
 #pragma unroll
-            for (int u = 0; u < kScanIpt; u++) {
+            for (int u = 0; u < SI; u++) {
                 const int64_t k = k0 + u;
-                v[u] = k < m ? (in_lds ? s_hist[k] : ldu(ghist + k)) : 0u;
+                v[u] = k < m ? (k < HL ? s_hist[k] : ldu(ghist + k)) : 0u;
                 sum += v[u];
             }
             uint32_t tot;
-            uint32_t C = run + block_excl(sum, s_red, &tot);
+            uint32_t C = run + block_excl<NT>(sum, s_red, &tot);
             int hit = 0x7fffffff;
 #pragma unroll
-            for (int u = 0; u < kScanIpt; u++) {
+            for (int u = 0; u < SI; u++) {
                 const int64_t k = k0 + u;
                 C += v[u];
                 if (hit == 0x7fffffff && k >= 1 && k < m && (int64_t)C <= k) hit = (int)(k - base);
             }
-            const int best = block_min(hit, s_min);
+            const int best = block_min<NT>(hit, s_min);
             run += tot;
             if (best != 0x7fffffff) {
                 found = base + best;
@@ -558,24 +573,34 @@ void launch_candidates_sort(int64_t n, int64_t G, int64_t NC, Work &w, hipStream
     fill_i32(w.g_nh, 0, G + 1, s);
 }
 
-void launch_accept(int64_t G, int64_t NC, int64_t M, const Geo &g, Work &w, hipStream_t s) {
+void launch_accept(int64_t n, int64_t G, int64_t NC, int64_t M, const Geo &g, Work &w, hipStream_t s) {
     // groups with candidates (at most min(G, NC)), one wavefront each; the
-    // large ones are listed (in the free chunk-flag array, count in
-    // counters[9], zero since the call began) for one workgroup each: at most
-    // M / kWaveHist groups of kWaveHist particles or more and NC / (kWaveNuc + 1)
-    // groups with more than kWaveNuc candidates
+    // others are listed (in the free chunk-flag array, counts in counters[9]
+    // and [11], zero since the call began) for one workgroup each: medium
+    // groups (at most M / kWaveHist of kWaveHist particles or more, and
+    // NC / (kWaveNuc + 1) with more than kWaveNuc candidates) and large ones
+    // (at most M / kHistMid), whose list starts halfway through the array
     const int64_t bound = G < NC ? G : NC;
     if (bound <= 0) return;
-    int32_t *big_list = reinterpret_cast<int32_t *>(w.f_chunk);
-    uint32_t *big_count = reinterpret_cast<uint32_t *>(w.counters + 9);
+    int32_t *mid_list = reinterpret_cast<int32_t *>(w.f_chunk);
+    int32_t *big_list = reinterpret_cast<int32_t *>(w.f_chunk) + n / 2;
+    uint32_t *mid_count = reinterpret_cast<uint32_t *>(w.counters + 9);
+    uint32_t *big_count = reinterpret_cast<uint32_t *>(w.counters + 11);
     hipLaunchKernelGGL(k_accept_small, dim3((unsigned)((bound + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), 0,
                        s, w.gcidx + G, g, w.glist, w.g_start, w.g_size, w.gcoff, w.cand_sorted, w.mem, w.spos,
-                       w.h_nuc, w.h_ienc, w.h_gid, w.g_nh, big_list, big_count);
-    int64_t nbig = M / kWaveHist + NC / (kWaveNuc + 1) + 1;
+                       w.h_nuc, w.h_ienc, w.h_gid, w.g_nh, mid_list, mid_count, big_list, big_count);
+    int64_t nmid = M / kWaveHist + NC / (kWaveNuc + 1) + 1;
+    if (nmid > bound) nmid = bound;
+    hipLaunchKernelGGL((k_accept<kBlock, kHistMid>), dim3((unsigned)nmid), dim3(kBlock), 0, s, mid_count, g,
+                       mid_list, w.g_start, w.g_size, w.gcoff, w.cand_sorted, w.mem, w.spos, w.hist, w.h_nuc,
+                       w.h_ienc, w.h_gid, w.g_nh);
+    int64_t nbig = M / kHistMid + 1;
     if (nbig > bound) nbig = bound;
-    hipLaunchKernelGGL(k_accept, dim3((unsigned)nbig), dim3(kBlock), 0, s, big_count, g, big_list, w.g_start,
-                       w.g_size, w.gcoff, w.cand_sorted, w.mem, w.spos, w.hist, w.h_nuc, w.h_ienc, w.h_gid,
-                       w.g_nh);
+    // the large groups are few and each is a serial walk: 1024 threads and a
+    // 144 KB LDS histogram each (one workgroup per CU)
+    hipLaunchKernelGGL((k_accept<1024, kHistBig>), dim3((unsigned)nbig), dim3(1024), 0, s, big_count, g,
+                       big_list, w.g_start, w.g_size, w.gcoff, w.cand_sorted, w.mem, w.spos, w.hist, w.h_nuc,
+                       w.h_ienc, w.h_gid, w.g_nh);
 }
 
 void launch_assign(int64_t n, const Geo &g, Work &w, hipStream_t s) {

@@ -285,7 +285,7 @@ hf_status run_compaso(Lane *c, int64_t n, const Geo &g, Work &w, int32_t *halo_i
     int64_t NC = NC32;
     hf::launch_candidates_sort(n, G, NC, w, s);
     HIP_OK(c, hipEventRecord(c->ev[5], s));
-    hf::launch_accept(G, NC, c->stats.n_members, g, w, s);
+    hf::launch_accept(n, G, NC, c->stats.n_members, g, w, s);
     HIP_OK(c, hipEventRecord(c->ev[6], s));
     hf::launch_assign(n, g, w, s);
     HIP_OK(c, hipEventRecord(c->ev[7], s));
@@ -642,7 +642,7 @@ hf_status hf_halo_stats(hf_ctx *ctx, const float *pos, const float *density, con
     if (st != HF_OK) return st;
     hf::launch_candidates_sort(n, G, NC32, w, s);
     HIP_OK(c, hipEventRecord(c->ev[5], s));
-    hf::launch_accept(G, NC32, M, g2, w, s);
+    hf::launch_accept(n, G, NC32, M, g2, w, s);
     HIP_OK(c, hipEventRecord(c->ev[6], s));
     hf::launch_assign(n, g2, w, s);
     HIP_OK(c, hipEventRecord(c->ev[7], s));

@@ -204,8 +204,8 @@ void launch_segment_groups(int64_t n, int64_t G, Work &w, hipStream_t s);
 void launch_candidates(int64_t n, const Geo &g, Work &w, hipStream_t s);   // candidates.hip
 void launch_candidates_sort(int64_t n, int64_t G, int64_t NC, Work &w, hipStream_t s);
 // Groups with candidates (their count is read on the device; grid bound
-// min(G, NC)); M = members of all groups.
-void launch_accept(int64_t G, int64_t NC, int64_t M, const Geo &g, Work &w, hipStream_t s);
+// min(G, NC)); M = members of all groups, n = particles.
+void launch_accept(int64_t n, int64_t G, int64_t NC, int64_t M, const Geo &g, Work &w, hipStream_t s);
 void launch_assign(int64_t n, const Geo &g, Work &w, hipStream_t s);
 void launch_output_flags(int64_t n, int64_t NC, const Geo &g, Work &w, hipStream_t s);
 void launch_output(int64_t n, int64_t NC, const Geo &g, Work &w, int32_t *halo_id,
