@@ -9,9 +9,10 @@
 // result does not depend on the launch shape.
 //
 // Dense cells: one wavefront per chunk of <= 64 particles of the cell (one per
-// lane); the 27 neighbour cells are streamed in the same order by all lanes,
-// so neighbour coordinates are wave-uniform and come through the scalar cache
-// as SGPR operands of the FP32 FMAs.  Sparse cells: one thread per particle.
+// lane), or per pair of small x-adjacent dense cells; the neighbour cells are
+// streamed in the same order by all lanes, so neighbour coordinates are
+// wave-uniform and come through the scalar cache as SGPR operands of the FP32
+// FMAs.  Sparse cells: one thread per particle.
 #include "hf_internal.h"
 
 namespace hf {
@@ -123,13 +124,36 @@ __global__ __launch_bounds__(kBlock) void k_density_dense(int64_t nchunks, Geo g
     const uint32_t h = (uint32_t)__builtin_amdgcn_readfirstlane(chunks[q]);
     const uint32_t c = __builtin_amdgcn_readfirstlane(__float_as_uint(sloc[h].w));
     const uint32_t cend = __builtin_amdgcn_readfirstlane(off[c + 1]);
-    const uint32_t end = min(h + 64u, cend);
-    const uint32_t i = h + (uint32_t)lane;
-    const bool active = i < end;
-    const float4 li = sloc[active ? i : h];
     const int nc = g.nc;
     const int cx = (int)(c % (uint32_t)nc), cy = (int)((c / (uint32_t)nc) % (uint32_t)nc),
               cz = (int)(c / ((uint32_t)nc * (uint32_t)nc));
+    uint32_t end = min(h + 64u, cend);
+    // Two x-adjacent cells (even x, and x + 1 in the same row) that are both
+    // dense and together hold at most 64 particles share one wavefront: their
+    // particles are consecutive, the stream covers x offsets -1..2 from the
+    // even cell, and each lane shifts the neighbours by its own cell's offset
+    // (a pair outside a lane's 27 cells is at least one cell width apart and
+    // weighs exactly 0).  The odd cell's wavefront finds the same pair and exits.
+    int xmax = 1;
+    // only a cell that is a single chunk pairs (the chunk starts the cell)
+    if (cend - h <= 64u && h == (uint32_t)__builtin_amdgcn_readfirstlane(off[c])) {
+        const uint32_t mine = cend - h;
+        if (cx & 1) {
+            const uint32_t left = h - (uint32_t)__builtin_amdgcn_readfirstlane(off[c - 1]);
+            if (left >= (uint32_t)kDenseMin && left <= 64u && left + mine <= 64u) return;
+        } else if (cx + 1 < nc) {
+            const uint32_t e2 = (uint32_t)__builtin_amdgcn_readfirstlane(off[c + 2]);
+            const uint32_t right = e2 - cend;
+            if (right >= (uint32_t)kDenseMin && right <= 64u && mine + right <= 64u) {
+                end = e2;
+                xmax = 2;
+            }
+        }
+    }
+    const uint32_t i = h + (uint32_t)lane;
+    const bool active = i < end;
+    const float4 li = sloc[active ? i : h];
+    const float du = i >= cend ? 1.0f : 0.0f;  // x offset of the lane's cell in a pair
     double acc = 0.0;
     for (int oz = -1; oz <= 1; oz++) {
         const int z = wrapc(cz + oz, nc);
@@ -138,9 +162,9 @@ __global__ __launch_bounds__(kBlock) void k_density_dense(int64_t nchunks, Geo g
             const int y = wrapc(cy + oy, nc);
             const float ys = li.y - (float)oy * g.cellb;
             const uint32_t row = ((uint32_t)z * (uint32_t)nc + (uint32_t)y) * (uint32_t)nc;
-            for (int ox = -1; ox <= 1; ox++) {
+            for (int ox = -1; ox <= xmax; ox++) {
                 const uint32_t nb = row + (uint32_t)wrapc(cx + ox, nc);
-                const float xs = li.x - (float)ox * g.cellb;
+                const float xs = li.x - ((float)ox - du) * g.cellb;
                 const uint32_t a = __builtin_amdgcn_readfirstlane(off[nb]);
                 const uint32_t b = __builtin_amdgcn_readfirstlane(off[nb + 1]);
                 if (b - a >= (uint32_t)kDenseMin) {
