@@ -150,7 +150,7 @@ def cpu_baseline(target_s: float):
                       "the 256^3 box itself takes minutes on the host"}
 
 
-def _batched(ctx, np, torch, _lib, synth, reps=3, lanes=4):
+def _batched(ctx, np, torch, _lib, synth, reps=3, lanes=8):
     """Batched workload: 96 boxes in one hf_find_batch call vs one hf_find per box."""
     boxes = synth.batch_boxes()
     pos = torch.from_numpy(np.concatenate([b[0] for b in boxes])).cuda()

@@ -217,7 +217,7 @@ hf_status hf_find(hf_ctx *ctx, const float *pos, int64_t n, const hf_params *p,
  * receives its count.  box_offsets and halo_offsets are host arrays of
  * n_boxes + 1 non-decreasing values starting at 0.
  *
- * The boxes run on n_lanes pipelines at once (<= 0: 4; at most 16), each with
+ * The boxes run on n_lanes pipelines at once (<= 0: 8; at most 16), each with
  * its own stream and scratch arena held by the context, largest boxes first.
  * Every box's outputs are identical to hf_find's on that box alone.  The call
  * first waits for the caller's stream and returns when all boxes are done.

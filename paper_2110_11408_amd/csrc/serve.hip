@@ -19,7 +19,7 @@
 
 namespace {
 
-constexpr int kDefaultLanes = 4;
+constexpr int kDefaultLanes = 8;
 constexpr int kMaxLanes = 16;
 
 void add_stats(hf_stats &a, const hf_stats &b) {
