@@ -361,39 +361,38 @@ __global__ __launch_bounds__(kBlock) void k_bin_lists(int64_t n, const uint32_t 
     }
 }
 
-// Sub-cell offsets of every dense cell: entry s is the first particle of
-// sub-cell s (the next non-empty one for empty sub-cells), entry k^3 the cell end.
-__global__ __launch_bounds__(kBlock) void k_sub_init(int64_t ndc, int nsub,
-                                                     const uint32_t *__restrict__ dcells,
-                                                     const uint32_t *__restrict__ off,
-                                                     uint32_t *__restrict__ subtab) {
-    int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Sub-cell table of the dense cells, one wavefront per cell: entry s of cell
+// d is the first particle of the cell whose sub-cell is s or later, that is
+// the cell start plus the number of its particles in sub-cells below s (an
+// empty sub-cell gets the start of the next non-empty one; entry nsub is the
+// cell end).  The cell's particles are sorted by sub-cell; each 64-particle
+// step counts, for 64 values of s at a time, the particles below s by ballot.
+__global__ __launch_bounds__(kBlock) void k_sub_table(int64_t ndc, int nsub,
+                                                      const uint32_t *__restrict__ dcells,
+                                                      const uint32_t *__restrict__ off,
+                                                      const uint16_t *__restrict__ ssub,
+                                                      uint32_t *__restrict__ subtab) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t d = (int64_t)blockIdx.x * (kBlock / 64) + wave;
     if (d >= ndc) return;
-    const uint32_t end = off[dcells[d] + 1];
-    for (int s = 0; s <= nsub; s++) subtab[d * (nsub + 1) + s] = end;
-}
-
-__global__ __launch_bounds__(kBlock) void k_sub_starts(int64_t n, int nsub,
-                                                       const float4 *__restrict__ sloc,
-                                                       const uint32_t *__restrict__ f_sparse,
-                                                       const uint16_t *__restrict__ ssub,
-                                                       const uint32_t *__restrict__ cellmap,
-                                                       uint32_t *__restrict__ subtab) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || f_sparse[i]) return;
-    const uint32_t c = __float_as_uint(sloc[i].w);
-    const uint16_t s = ssub[i];
-    // first particle of its cell, or of a new sub-cell inside the cell
-    if (i == 0 || __float_as_uint(sloc[i - 1].w) != c || ssub[i - 1] != s)
-        subtab[(int64_t)cellmap[c] * (nsub + 1) + s] = (uint32_t)i;
-}
-
-__global__ __launch_bounds__(kBlock) void k_sub_fix(int64_t ndc, int nsub, uint32_t *__restrict__ subtab) {
-    int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (d >= ndc) return;
+    const int lane = threadIdx.x & 63;
+    const uint32_t c = (uint32_t)__builtin_amdgcn_readfirstlane(dcells[d]);
+    const uint32_t a = (uint32_t)__builtin_amdgcn_readfirstlane(off[c]);
+    const uint32_t b = (uint32_t)__builtin_amdgcn_readfirstlane(off[c + 1]);
     uint32_t *t = subtab + d * (nsub + 1);
-    for (int s = nsub - 1; s >= 0; s--)
-        if (t[s] > t[s + 1]) t[s] = t[s + 1];
+    for (int s0 = 0; s0 <= nsub; s0 += 64) {
+        const int ns = min(64, nsub + 1 - s0);
+        uint32_t below = 0;  // for s = s0 + lane
+        for (uint32_t j0 = a; j0 < b; j0 += 64) {
+            const uint32_t j = j0 + (uint32_t)lane;
+            const int v = j < b ? (int)ssub[j] : 0x7fffffff;
+            for (int u = 0; u < ns; u++) {
+                const uint32_t cnt = (uint32_t)__popcll(__ballot(v < s0 + u));
+                if (lane == u) below += cnt;
+            }
+        }
+        if (lane < ns) t[s0 + lane] = a + below;
+    }
 }
 
 }  // namespace
@@ -493,14 +492,11 @@ void launch_bin(const float *pos, int64_t n, const Geo &g, Work &w, hipStream_t 
                        w.sparse, w.cnt);
 }
 
-void launch_subtab(int64_t n, int64_t ndc, const Geo &g, Work &w, hipStream_t s) {
+void launch_subtab(int64_t, int64_t ndc, const Geo &g, Work &w, hipStream_t s) {
     if (ndc <= 0) return;
     const int nsub = g.ksub * g.ksub * g.ksub;
-    hipLaunchKernelGGL(k_sub_init, dim3(blocks(ndc)), dim3(kBlock), 0, s, ndc, nsub, w.dcells, w.off,
-                       w.subtab);
-    hipLaunchKernelGGL(k_sub_starts, dim3(blocks(n)), dim3(kBlock), 0, s, n, nsub, w.sloc, w.f_sparse, w.ssub,
-                       w.cnt, w.subtab);
-    hipLaunchKernelGGL(k_sub_fix, dim3(blocks(ndc)), dim3(kBlock), 0, s, ndc, nsub, w.subtab);
+    hipLaunchKernelGGL(k_sub_table, dim3((unsigned)((ndc + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), 0, s,
+                       ndc, nsub, w.dcells, w.off, w.ssub, w.subtab);
 }
 
 }  // namespace hf
