@@ -77,6 +77,61 @@ __global__ __launch_bounds__(kBlock) void k_submax(int64_t nslots, int nsub,
     subarg[d * (nsub + 1) + s] = arg;
 }
 
+// The same table with one wavefront per dense cell, for at most 64 sub-cells:
+// the cell's particles are sorted by sub-cell, so each 64-particle step
+// reduces the runs of equal sub-cells (maximum key and its particle) and the
+// first lane of each run merges the result into the cell's row in LDS.
+__global__ __launch_bounds__(kBlock) void k_submax_wave(int64_t ndc, int nsub,
+                                                        const uint32_t *__restrict__ dcells,
+                                                        const uint32_t *__restrict__ off,
+                                                        const uint16_t *__restrict__ ssub,
+                                                        const float *__restrict__ dens_s,
+                                                        const float4 *__restrict__ spos,
+                                                        uint64_t *__restrict__ submax,
+                                                        int32_t *__restrict__ subarg) {
+    __shared__ uint64_t s_best[kBlock / 64][64];
+    __shared__ int32_t s_arg[kBlock / 64][64];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t d = (int64_t)blockIdx.x * (kBlock / 64) + wave;
+    if (d >= ndc) return;
+    const int lane = threadIdx.x & 63;
+    const uint32_t c = (uint32_t)__builtin_amdgcn_readfirstlane(dcells[d]);
+    const uint32_t a = (uint32_t)__builtin_amdgcn_readfirstlane(off[c]);
+    const uint32_t b = (uint32_t)__builtin_amdgcn_readfirstlane(off[c + 1]);
+    s_best[wave][lane] = 0ull;
+    s_arg[wave][lane] = -1;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t j0 = a; j0 < b; j0 += 64) {
+        const uint32_t j = j0 + (uint32_t)lane;
+        const bool act = j < b;
+        const int v = act ? (int)ssub[j] : -1 - lane;  // inactive lanes: runs of their own
+        uint64_t kk = act ? dkey(dens_s[j], orig_of(spos[j])) : 0ull;
+        int32_t jj = (int32_t)j;
+        const WaveRun run = wave_run(v);
+        const int end = run.head + run.len;
+        for (int dd = 1; dd < 64; dd <<= 1) {
+            const uint32_t olo = __shfl_down((uint32_t)kk, dd, 64), ohi = __shfl_down((uint32_t)(kk >> 32), dd, 64);
+            const int32_t oj = __shfl_down(jj, dd, 64);
+            const uint64_t ok = ((uint64_t)ohi << 32) | olo;
+            if (lane + dd < end && ok > kk) {
+                kk = ok;
+                jj = oj;
+            }
+        }
+        if (act && run.rank == 0 && (s_arg[wave][v] < 0 || kk > s_best[wave][v])) {
+            s_best[wave][v] = kk;
+            s_arg[wave][v] = jj;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (lane < nsub) {
+        submax[d * (nsub + 1) + lane] = s_best[wave][lane];
+        subarg[d * (nsub + 1) + lane] = s_arg[wave][lane];
+    }
+}
+
 // Stage 1, one thread per particle: a member at or above the floor that is not
 // the densest particle of its sub-cell is decided at once when that densest
 // particle belongs to its group and lies within b (the usual case inside an L0
@@ -389,7 +444,11 @@ __global__ __launch_bounds__(kBlock) void k_cand_wave(const uint32_t *__restrict
 void launch_candidates(int64_t n, const Geo &g, Work &w, hipStream_t s) {
     const int nsub = g.ksub * g.ksub * g.ksub;
     const int64_t nslots = w.ndcells * nsub;
-    if (nslots > 0)
+    if (nslots > 0 && nsub <= 64)
+        hipLaunchKernelGGL(k_submax_wave, dim3((unsigned)((w.ndcells + kBlock / 64 - 1) / (kBlock / 64))),
+                           dim3(kBlock), 0, s, w.ndcells, nsub, w.dcells, w.off, w.ssub, w.dens_s, w.spos, w.submax,
+                           w.subarg);
+    else if (nslots > 0)
         hipLaunchKernelGGL(k_submax, dim3((unsigned)((nslots + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
                            nslots, nsub, w.subtab, w.dens_s, w.spos, w.submax, w.subarg);
     const unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
