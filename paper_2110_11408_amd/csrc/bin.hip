@@ -244,14 +244,16 @@ __global__ __launch_bounds__(kBlock) void k_bin_place(const float *__restrict__ 
 // Cell offsets: off[c] = first sorted particle of cell c (the next cell's
 // start when c is empty), off[ncell] = n.  With C(s) = cell of slot s,
 // C(-1) = -1 and C(n) = ncell, slot s owns the cells (C(s-1), C(s)].  Each
-// wavefront takes 64 consecutive slots (the last one slot n), numbers the
-// cells they own 0..G-1 by a prefix sum of the gaps, and writes them with
-// consecutive lanes on consecutive cells; the owner of cell q is the last slot
-// whose prefix is <= q (binary search over the 64 prefixes in LDS).
+// wavefront takes 64 consecutive slots (the last one slot n) and writes the
+// cells they own with consecutive lanes on consecutive cells (16-byte stores);
+// the owner of a cell is the last slot that owns cells and starts at or before
+// it, found from a bitmask of the starts in each 256-cell window (a count of
+// set bits gives its rank among those slots) and a rank -> slot table.
 __global__ __launch_bounds__(kBlock) void k_cell_offsets(int64_t n, int64_t ncell,
                                                          const float4 *__restrict__ sloc,
                                                          uint32_t *__restrict__ off) {
-    __shared__ int64_t pre[kBlock / 64][64];
+    __shared__ uint64_t s_bits[kBlock / 64][4];   // starts inside the current 256-cell window
+    __shared__ uint8_t s_slot[kBlock / 64][64];   // slot of each rank
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t s0 = ((int64_t)blockIdx.x * (kBlock / 64) + w) * 64;
     if (s0 > n) return;  // whole wavefront past slot n (uniform)
@@ -261,49 +263,64 @@ __global__ __launch_bounds__(kBlock) void k_cell_offsets(int64_t n, int64_t ncel
     };
     const int64_t hi = s <= n ? C(s) : ncell;
     const int64_t lo = s <= n ? C(s - 1) : ncell;
-    int64_t g = hi - lo;  // cells owned by this slot
-    // inclusive prefix over the wavefront
-    int64_t incl = g;
+    // cells owned by this slot, and their exclusive prefix over the wavefront
+    // (32-bit: the grid has fewer than 2^32 cells)
+    const uint32_t g = (uint32_t)(hi - lo);
+    uint32_t incl = g;
     for (int d = 1; d < 64; d <<= 1) {
-        const int64_t y = __shfl_up(incl, d, 64);
+        const uint32_t y = __shfl_up(incl, d, 64);
         if (lane >= d) incl += y;
     }
-    pre[w][lane] = incl - g;  // exclusive prefix
-    const int64_t G = __shfl(incl, 63, 64);
-    const int64_t first = __shfl(lo, 0, 64) + 1;  // first cell owned by the wavefront
-    // each wavefront reads only its own row, written above by the same
-    // wavefront (LDS operations of a wavefront complete in order)
-    __builtin_amdgcn_wave_barrier();
-    // four consecutive cells per lane and iteration; the cells before the first
-    // 16-byte boundary of off[] are written one by one
-    const int64_t head = ((4 - ((first & 3))) & 3) < G ? ((4 - (first & 3)) & 3) : G;
-    for (int64_t q = lane; q < head; q += 64) {
-        int a = 0, b = 63;  // last j with pre[j] <= q
-        while (a < b) {
-            const int mid = (a + b + 1) >> 1;
-            if (pre[w][mid] <= q) a = mid;
-            else b = mid - 1;
+    const uint32_t pre = incl - g;
+    const uint32_t G = __shfl(incl, 63, 64);
+    // first cell owned by the wavefront: one past the cell of the slot before it
+    const int64_t first = s0 == 0 ? 0 : (int64_t)__float_as_uint(sloc[s0 - 1].w) + 1;
+    const int64_t end = first + (int64_t)G;
+    // the slots that own cells, in order: rank -> slot
+    const uint64_t owners = __ballot(g > 0);
+    if (g > 0) s_slot[w][__popcll(owners & lanes_below(lane))] = (uint8_t)lane;
+    // windows of 256 cells aligned to 4, four consecutive cells per lane; the
+    // owner of a cell is the slot of rank (number of owned starts at or before
+    // it) - 1, counted from a bitmask of the starts in the window
+    uint32_t before = 0;  // starts in earlier windows
+    for (int64_t w0 = first & ~(int64_t)3; w0 < end; w0 += 256) {
+        if (lane < 4) s_bits[w][lane] = 0ull;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        const int64_t st = first + (int64_t)pre;
+        if (g > 0 && st >= w0 && st < w0 + 256) {
+            const int r = (int)(st - w0);
+            atomicOr(reinterpret_cast<unsigned long long *>(&s_bits[w][r >> 6]), 1ull << (r & 63));
         }
-        off[first + q] = (uint32_t)(s0 + a);
-    }
-    for (int64_t q4 = head + 4 * (int64_t)lane; q4 < G; q4 += 256) {
-        int a = 0, b = 63;  // owner of cell q4
-        while (a < b) {
-            const int mid = (a + b + 1) >> 1;
-            if (pre[w][mid] <= q4) a = mid;
-            else b = mid - 1;
-        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        const uint64_t b0 = s_bits[w][0], b1 = s_bits[w][1], b2 = s_bits[w][2], b3 = s_bits[w][3];
+        const int p = 4 * lane, k = p >> 6;
+        const uint64_t wk = k == 0 ? b0 : (k == 1 ? b1 : (k == 2 ? b2 : b3));
+        const uint32_t lower = before + (k > 0 ? (uint32_t)__popcll(b0) : 0u) + (k > 1 ? (uint32_t)__popcll(b1) : 0u) +
+                               (k > 2 ? (uint32_t)__popcll(b2) : 0u);
         uint32_t v[4];
-        v[0] = (uint32_t)(s0 + a);
-        for (int u = 1; u < 4; u++) {
-            while (a < 63 && pre[w][a + 1] <= q4 + u) a++;
-            v[u] = (uint32_t)(s0 + a);
+        bool all = true;
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int pu = (p + u) & 63;
+            const uint64_t upto = pu == 63 ? ~0ull : ((2ull << pu) - 1ull);
+            const uint32_t cnt = lower + (uint32_t)__popcll(wk & upto);
+            const int64_t cell = w0 + p + u;
+            const bool valid = cell >= first && cell < end;
+            all = all && valid;
+            v[u] = valid ? (uint32_t)(s0 + s_slot[w][cnt > 0u ? cnt - 1u : 0u]) : 0u;
         }
-        if (q4 + 4 <= G) {
-            *reinterpret_cast<uint4 *>(off + first + q4) = make_uint4(v[0], v[1], v[2], v[3]);
+        if (all) {
+            *reinterpret_cast<uint4 *>(off + w0 + p) = make_uint4(v[0], v[1], v[2], v[3]);
         } else {
-            for (int u = 0; u < 4 && q4 + u < G; u++) off[first + q4 + u] = v[u];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int64_t cell = w0 + p + u;
+                if (cell >= first && cell < end) off[cell] = v[u];
+            }
         }
+        before += (uint32_t)(__popcll(b0) + __popcll(b1) + __popcll(b2) + __popcll(b3));
     }
 }
 
