@@ -140,10 +140,14 @@ __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *p, uint32_t v, in
         p[i] = v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+// 16-byte stores for a 16-byte-aligned array of n4 words x4, then the tail.
+__global__ __launch_bounds__(kBlock) void k_fill_u32x4(uint4 *p, uint32_t v, int64_t n4, uint32_t *tail,
+                                                       int ntail) {
+    const uint4 q = make_uint4(v, v, v, v);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
          i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = v;
+        p[i] = q;
+    if (blockIdx.x == 0 && (int)threadIdx.x < ntail) tail[threadIdx.x] = v;
 }
 
 // Copies k device words into pinned host memory with system-scope stores, so
@@ -163,12 +167,17 @@ int64_t grid_for(int64_t n, int64_t cap = 1 << 20) {
 
 void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
     if (n <= 0) return;
+    if ((reinterpret_cast<uintptr_t>(p) & 15u) == 0 && n >= 1024) {
+        const int64_t n4 = n / 4;
+        hipLaunchKernelGGL(k_fill_u32x4, dim3(grid_for(n4)), dim3(kBlock), 0, s, reinterpret_cast<uint4 *>(p), v, n4,
+                           p + 4 * n4, (int)(n - 4 * n4));
+        return;
+    }
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n)), dim3(kBlock), 0, s, p, v, n);
 }
 
 void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n)), dim3(kBlock), 0, s, p, v, n);
+    fill_u32(reinterpret_cast<uint32_t *>(p), (uint32_t)v, n, s);
 }
 
 hipError_t read_words(const WordSrc &src, int k, uint32_t *host, uint32_t *out, hipStream_t s) {
