@@ -64,8 +64,8 @@ STAGE_KERNELS = {
     "density": ("k_density_dense", "k_density_sparse"),
     "bin": ("k_bin_key", "k_radix_count", "k_radix_scatter", "k_bin_place", "k_cell_offsets",
             "k_bin_flags", "k_bin_lists", "k_sub_table"),
-    "fof": ("k_fof_init", "k_fof_phase_a", "k_fof_dense", "k_fof_sparse_flags", "k_fof_sparse_list",
-            "k_fof_sparse", "k_fof_roots", "k_fof_minorig", "k_fof_keys"),
+    "fof": ("k_fof_phase_a", "k_fof_dense", "k_fof_sparse_flags", "k_fof_sparse_list", "k_fof_sparse",
+            "k_fof_roots", "k_fof_keys"),
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 

@@ -233,15 +233,10 @@ __device__ __forceinline__ void stream_sparse_cells(int32_t *parent, const float
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_fof_init(int64_t n, Geo g, const float *__restrict__ dens_s,
-                                                     int32_t *__restrict__ parent) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    parent[i] = is_member(dens_s, i, g.dl0) ? (int32_t)i : -1;
-}
-
-// Phase A: members of dense cells point at the first member of their sub-cell
-// (a valid forest: every parent is a member with a smaller sorted index).
+// Phase A, which also initializes the forest: non-members get -1, members of
+// sparse cells are roots, and members of dense cells point at the first member
+// of their sub-cell (a valid forest: every parent is a member with a smaller
+// or equal sorted index).
 __global__ __launch_bounds__(kBlock) void k_fof_phase_a(int64_t n, Geo g, const float4 *__restrict__ sloc,
                                                         const uint32_t *__restrict__ f_sparse,
                                                         const uint16_t *__restrict__ ssub,
@@ -251,8 +246,14 @@ __global__ __launch_bounds__(kBlock) void k_fof_phase_a(int64_t n, Geo g, const 
                                                         int32_t *__restrict__ parent) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    if (!is_member(dens_s, i, g.dl0)) return;
-    if (f_sparse[i]) return;
+    if (!is_member(dens_s, i, g.dl0)) {
+        parent[i] = -1;
+        return;
+    }
+    if (f_sparse[i]) {
+        parent[i] = (int32_t)i;
+        return;
+    }
     const uint32_t c = __float_as_uint(sloc[i].w);
     const int nsub = g.ksub * g.ksub * g.ksub;
     uint32_t f = subtab[(int64_t)cellmap[c] * (nsub + 1) + ssub[i]];
@@ -490,23 +491,22 @@ __global__ __launch_bounds__(kBlock) void k_fof_sparse(const uint32_t *__restric
 // Roots of all members, read-only: nothing writes the forest in this pass, so
 // every stored root is final (a compressing writer could otherwise replace a
 // stored root with an older ancestor).
+// The root of every particle's set into root[], and the smallest original
+// index of every set into minorig[root] (one atomic per run of equal roots
+// among consecutive lanes).
 __global__ __launch_bounds__(kBlock) void k_fof_roots(int64_t n, const int32_t *__restrict__ parent,
-                                                      int32_t *__restrict__ root) {
+                                                      const float4 *__restrict__ spos,
+                                                      int32_t *__restrict__ root,
+                                                      int32_t *__restrict__ minorig) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int x = parent[i];
-    if (x >= 0) {
-        for (int p = parent[x]; p != x; p = parent[x]) x = p;
+    int r = -1;
+    if (i < n) {
+        r = parent[i];
+        if (r >= 0) {
+            for (int p = parent[r]; p != r; p = parent[r]) r = p;
+        }
+        root[i] = r;
     }
-    root[i] = x;
-}
-
-// The smallest original index of every set, into minorig[root].
-__global__ __launch_bounds__(kBlock) void k_fof_minorig(int64_t n, const int32_t *__restrict__ root,
-                                                        const float4 *__restrict__ spos,
-                                                        int32_t *__restrict__ minorig) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int r = i < n ? root[i] : -1;
     const WaveRun run = wave_run(r);
     const int32_t o = i < n ? (int32_t)orig_of(spos[i]) : 0x7fffffff;
     const int32_t m = wave_run_min(r >= 0 ? o : 0x7fffffff, run);
@@ -552,7 +552,6 @@ __global__ __launch_bounds__(kBlock) void k_keys_from_labels(int64_t n, const in
 }  // namespace
 
 void launch_fof(int64_t n, const Geo &g, Work &w, hipStream_t s) {
-    hipLaunchKernelGGL(k_fof_init, grid(n), dim3(kBlock), 0, s, n, g, w.dens_s, w.parent);
     hipLaunchKernelGGL(k_fof_phase_a, grid(n), dim3(kBlock), 0, s, n, g, w.sloc, w.f_sparse, w.ssub, w.cnt,
                        w.subtab, w.dens_s, w.parent);
     if (w.nchunks > 0)
@@ -570,9 +569,8 @@ void launch_fof(int64_t n, const Geo &g, Work &w, hipStream_t s) {
                            w.hardlist, w.sloc, w.spos, w.off, w.dens_s, w.parent);
     }
     // roots go to the owner array (free until the assignment stage)
-    hipLaunchKernelGGL(k_fof_roots, grid(n), dim3(kBlock), 0, s, n, w.parent, w.owner);
     fill_i32(w.minorig, 0x7fffffff, n, s);
-    hipLaunchKernelGGL(k_fof_minorig, grid(n), dim3(kBlock), 0, s, n, w.owner, w.spos, w.minorig);
+    hipLaunchKernelGGL(k_fof_roots, grid(n), dim3(kBlock), 0, s, n, w.parent, w.spos, w.owner, w.minorig);
 }
 
 void launch_fof_labels(int64_t n, const Geo &, Work &w, int32_t *l0_out, hipStream_t s) {
