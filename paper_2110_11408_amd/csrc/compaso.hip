@@ -49,13 +49,6 @@ __global__ __launch_bounds__(kBlock) void k_seg_count(int64_t n, const int32_t *
     if (k >= 0 && r.rank == 0) atomicAdd(&gcnt[k], (uint32_t)r.len);
 }
 
-__global__ __launch_bounds__(kBlock) void k_seg_flags(int64_t n, const uint32_t *__restrict__ gcnt,
-                                                      uint32_t *__restrict__ gflag) {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    gflag[k] = gcnt[k] > 0 ? 1u : 0u;
-}
-
 __global__ __launch_bounds__(kBlock) void k_seg_groups(int64_t n, const uint32_t *__restrict__ gcnt,
                                                        const uint32_t *__restrict__ goff,
                                                        const uint32_t *__restrict__ gidx,
@@ -72,17 +65,20 @@ __global__ __launch_bounds__(kBlock) void k_seg_groups(int64_t n, const uint32_t
     g_label[g] = (int32_t)k + 1;
 }
 
+// Members into group order: each run of equal keys among consecutive lanes
+// takes a slice of its group by counting the group's count down (the order of
+// members inside a group is not used).
 __global__ __launch_bounds__(kBlock) void k_seg_scatter(int64_t n, const int32_t *__restrict__ gkey,
                                                         const uint32_t *__restrict__ goff,
                                                         const uint32_t *__restrict__ gidx,
-                                                        uint32_t *__restrict__ gfill,
+                                                        uint32_t *__restrict__ gcnt,
                                                         int32_t *__restrict__ mem,
                                                         int32_t *__restrict__ gid_of) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int k = i < n ? gkey[i] : -1;
     const WaveRun r = wave_run(k);
     uint32_t base = 0;
-    if (k >= 0 && r.rank == 0) base = atomicAdd(&gfill[k], (uint32_t)r.len);
+    if (k >= 0 && r.rank == 0) base = atomicSub(&gcnt[k], (uint32_t)r.len) - (uint32_t)r.len;
     base = __shfl(base, r.head, 64);
     if (i >= n) return;
     if (k < 0) {
@@ -137,19 +133,12 @@ __global__ __launch_bounds__(kBlock) void k_cand_rank(int64_t NC, int G, const u
     cand_sorted[a + rank] = me;
 }
 
-__global__ __launch_bounds__(kBlock) void k_glist_flags(int G, const uint32_t *__restrict__ gccnt,
-                                                        uint32_t *__restrict__ flag) {
-    int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= G) return;
-    flag[g] = gccnt[g] > 0 ? 1u : 0u;
-}
-
-__global__ __launch_bounds__(kBlock) void k_glist(int G, const uint32_t *__restrict__ flag,
+__global__ __launch_bounds__(kBlock) void k_glist(int G, const uint32_t *__restrict__ gccnt,
                                                   const uint32_t *__restrict__ idx,
                                                   int32_t *__restrict__ glist) {
     int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= G) return;
-    if (flag[g]) glist[idx[g]] = g;
+    if (gccnt[g]) glist[idx[g]] = g;
 }
 
 // ------------------------------------------------------ acceptance and R
@@ -540,17 +529,15 @@ __global__ __launch_bounds__(kBlock) void k_out_particles(int64_t n, Geo g, cons
 
 void launch_segment(int64_t n, Work &w, hipStream_t s) {
     fill_u32(w.gcnt, 0u, n + 1, s);
-    fill_u32(w.gfill, 0u, n + 1, s);
     hipLaunchKernelGGL(k_seg_count, grid(n), dim3(kBlock), 0, s, n, w.gkey, w.gcnt);
     scan_u32(w.gcnt, w.goff, n, w.scan_tmp, s);
-    hipLaunchKernelGGL(k_seg_flags, grid(n), dim3(kBlock), 0, s, n, w.gcnt, w.gflag);
-    scan_u32(w.gflag, w.gidx, n, w.scan_tmp, s);
+    scan_nz_u32(w.gcnt, w.gidx, n, w.scan_tmp, s);  // group ordinal of every key
 }
 
 void launch_segment_groups(int64_t n, int64_t G, Work &w, hipStream_t s) {
     hipLaunchKernelGGL(k_seg_groups, grid(n), dim3(kBlock), 0, s, n, w.gcnt, w.goff, w.gidx, w.g_start,
                        w.g_size, w.g_label);
-    hipLaunchKernelGGL(k_seg_scatter, grid(n), dim3(kBlock), 0, s, n, w.gkey, w.goff, w.gidx, w.gfill,
+    hipLaunchKernelGGL(k_seg_scatter, grid(n), dim3(kBlock), 0, s, n, w.gkey, w.goff, w.gidx, w.gcnt,
                        w.mem, w.gid_of);
     fill_u32(w.gccnt, 0u, G + 1, s);
     fill_u32(w.gcfill, 0u, G + 1, s);
@@ -563,11 +550,9 @@ void launch_candidates_sort(int64_t n, int64_t G, int64_t NC, Work &w, hipStream
     if (NC > 0)
         hipLaunchKernelGGL(k_cand_rank, grid(NC), dim3(kBlock), 0, s, NC, (int)G, w.gcoff, w.cand,
                            w.dens_s, w.spos, w.cand_sorted);
+    scan_nz_u32(w.gccnt, w.gcidx, G, w.scan_tmp, s);  // ordinal of every group with candidates
     if (G > 0)
-        hipLaunchKernelGGL(k_glist_flags, grid(G), dim3(kBlock), 0, s, (int)G, w.gccnt, w.gcflag);
-    scan_u32(w.gcflag, w.gcidx, G, w.scan_tmp, s);
-    if (G > 0)
-        hipLaunchKernelGGL(k_glist, grid(G), dim3(kBlock), 0, s, (int)G, w.gcflag, w.gcidx, w.glist);
+        hipLaunchKernelGGL(k_glist, grid(G), dim3(kBlock), 0, s, (int)G, w.gccnt, w.gcidx, w.glist);
     fill_i32(w.h_nuc, -1, NC + 1, s);
     fill_u32(w.h_count, 0u, NC + 1, s);
     fill_i32(w.g_nh, 0, G + 1, s);

@@ -166,9 +166,7 @@ size_t carve(char *base, int64_t n, int64_t ncell, int nsub, int64_t rhl, bool e
     w->owner = c.take<int32_t>(n);
     w->gcnt = c.take<uint32_t>(n1);
     w->goff = c.take<uint32_t>(n1);
-    w->gflag = c.take<uint32_t>(n1);
     w->gidx = c.take<uint32_t>(n1);
-    w->gfill = c.take<uint32_t>(n1);
     w->mem = c.take<int32_t>(n);
     w->g_start = c.take<int32_t>(n1);
     w->g_size = c.take<int32_t>(n1);
@@ -176,7 +174,6 @@ size_t carve(char *base, int64_t n, int64_t ncell, int nsub, int64_t rhl, bool e
     w->gccnt = c.take<uint32_t>(n1);
     w->gcoff = c.take<uint32_t>(n1);
     w->gcfill = c.take<uint32_t>(n1);
-    w->gcflag = c.take<uint32_t>(n1);
     w->gcidx = c.take<uint32_t>(n1);
     w->glist = c.take<int32_t>(n1);
     w->cand = c.take<int32_t>(n1);

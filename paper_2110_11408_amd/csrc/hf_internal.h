@@ -147,10 +147,10 @@ struct Work {
     // density / FoF / groups (sorted order unless noted)
     float *dens_s;
     int32_t *parent, *minorig, *gkey, *gid_of, *owner;
-    uint32_t *gcnt, *goff, *gflag, *gidx, *gfill;   // key space [0, n]
+    uint32_t *gcnt, *goff, *gidx;                     // key space [0, n]
     int32_t *mem;                                     // members grouped by group
     int32_t *g_start, *g_size, *g_label;              // per group
-    uint32_t *gccnt, *gcoff, *gcfill, *gcflag, *gcidx; // candidates per group
+    uint32_t *gccnt, *gcoff, *gcfill, *gcidx;          // candidates per group
     int32_t *glist;                                    // groups with candidates
     int32_t *cand, *cand_sorted;                       // candidates
     int32_t *h_nuc, *h_ienc, *h_gid, *g_nh;            // halo slots (= candidate slots)
@@ -179,6 +179,8 @@ void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 // Exclusive scan: out[0..n] with out[n] = total.  tmp: scan_tmp_words(n) words.
 void scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipStream_t s);
+// Exclusive scan of the indicator in[i] != 0 (same layout and tmp as scan_u32).
+void scan_nz_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipStream_t s);
 int64_t scan_tmp_words(int64_t n);
 
 void launch_bin(const float *pos, int64_t n, const Geo &g, Work &w, hipStream_t s);

@@ -50,6 +50,11 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total)
 // Full tiles are moved as 16-byte vectors (in and out are 16-byte aligned:
 // arena arrays, and the tile-sum arrays below are padded to four words); the
 // last, partial tile word by word.
+// kNz: scan the indicator in[i] != 0 instead of the values.
+template <bool kNz>
+__device__ __forceinline__ uint32_t val(uint32_t x) { return kNz ? (x != 0u ? 1u : 0u) : x; }
+
+template <bool kNz>
 __global__ __launch_bounds__(kBlock) void k_tile_sums(const uint32_t *__restrict__ in, int64_t n,
                                                       uint32_t *__restrict__ sums) {
     const int64_t base = (int64_t)blockIdx.x * kTile;
@@ -59,13 +64,13 @@ __global__ __launch_bounds__(kBlock) void k_tile_sums(const uint32_t *__restrict
 #pragma unroll
         for (int k = 0; k < kIpt / 4; k++) {
             const uint4 v = p[k * kBlock + threadIdx.x];
-            s += (v.x + v.y) + (v.z + v.w);
+            s += (val<kNz>(v.x) + val<kNz>(v.y)) + (val<kNz>(v.z) + val<kNz>(v.w));
         }
     } else {
 #pragma unroll
         for (int k = 0; k < kIpt; k++) {
             const int64_t i = base + k * kBlock + threadIdx.x;
-            if (i < n) s += in[i];
+            if (i < n) s += val<kNz>(in[i]);
         }
     }
     uint32_t tot;
@@ -73,6 +78,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_sums(const uint32_t *__restrict
     if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
+template <bool kNz>
 __global__ __launch_bounds__(kBlock) void k_tile_scan(const uint32_t *__restrict__ in,
                                                       uint32_t *__restrict__ out, int64_t n,
                                                       const uint32_t *__restrict__ tile_off) {
@@ -85,17 +91,17 @@ __global__ __launch_bounds__(kBlock) void k_tile_scan(const uint32_t *__restrict
         for (int k = 0; k < kIpt / 4; k++) {
             const int q = k * kBlock + threadIdx.x;
             const uint4 v = p[q];
-            buf[pad(4 * q + 0)] = v.x;
-            buf[pad(4 * q + 1)] = v.y;
-            buf[pad(4 * q + 2)] = v.z;
-            buf[pad(4 * q + 3)] = v.w;
+            buf[pad(4 * q + 0)] = val<kNz>(v.x);
+            buf[pad(4 * q + 1)] = val<kNz>(v.y);
+            buf[pad(4 * q + 2)] = val<kNz>(v.z);
+            buf[pad(4 * q + 3)] = val<kNz>(v.w);
         }
     } else {
 #pragma unroll
         for (int k = 0; k < kIpt; k++) {
             const int idx = k * kBlock + threadIdx.x;
             const int64_t i = base + idx;
-            buf[pad(idx)] = i < n ? in[i] : 0u;
+            buf[pad(idx)] = i < n ? val<kNz>(in[i]) : 0u;
         }
     }
     __syncthreads();
@@ -204,18 +210,27 @@ int64_t scan_tmp_words(int64_t n) {
     return w + 16;
 }
 
-void scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipStream_t s) {
+template <bool kNz>
+void scan_impl(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipStream_t s) {
     int64_t tiles = (n + kTile - 1) / kTile;
     if (tiles < 1) tiles = 1;
     if (tiles == 1) {
-        hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kBlock), 0, s, in, out, n, nullptr);
+        hipLaunchKernelGGL(k_tile_scan<kNz>, dim3(1), dim3(kBlock), 0, s, in, out, n, nullptr);
         return;
     }
     uint32_t *sums = tmp;
     uint32_t *sums_scan = tmp + sums_words(tiles);
-    hipLaunchKernelGGL(k_tile_sums, dim3(tiles), dim3(kBlock), 0, s, in, n, sums);
-    scan_u32(sums, sums_scan, tiles, tmp + 2 * sums_words(tiles), s);
-    hipLaunchKernelGGL(k_tile_scan, dim3(tiles), dim3(kBlock), 0, s, in, out, n, sums_scan);
+    hipLaunchKernelGGL(k_tile_sums<kNz>, dim3(tiles), dim3(kBlock), 0, s, in, n, sums);
+    scan_impl<false>(sums, sums_scan, tiles, tmp + 2 * sums_words(tiles), s);
+    hipLaunchKernelGGL(k_tile_scan<kNz>, dim3(tiles), dim3(kBlock), 0, s, in, out, n, sums_scan);
+}
+
+void scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipStream_t s) {
+    scan_impl<false>(in, out, n, tmp, s);
+}
+
+void scan_nz_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipStream_t s) {
+    scan_impl<true>(in, out, n, tmp, s);
 }
 
 }  // namespace hf
