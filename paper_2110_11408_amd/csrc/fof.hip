@@ -534,14 +534,20 @@ __global__ __launch_bounds__(kBlock) void k_fof_keys(int64_t n, const int32_t *_
     if (l0_out) l0_out[orig_of(spos[i])] = k + 1;
 }
 
-// Group keys from caller-provided labels (1..n, 0 = none), in sorted order.
+// Group keys from caller-provided labels (1..n, 0 = none), in sorted order,
+// and with dens_in the caller's densities gathered into sorted order too (one
+// pass over the sorted records for both).
 __global__ __launch_bounds__(kBlock) void k_keys_from_labels(int64_t n, const int32_t *__restrict__ l0_in,
+                                                             const float *__restrict__ dens_in,
                                                              const float4 *__restrict__ spos,
                                                              int32_t *__restrict__ gkey,
+                                                             float *__restrict__ dens_s,
                                                              int32_t *__restrict__ err) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    int32_t lab = l0_in[orig_of(spos[i])];
+    const uint32_t o = orig_of(spos[i]);
+    if (dens_in) dens_s[i] = dens_in[o];
+    int32_t lab = l0_in[o];
     if (lab < 0 || (int64_t)lab > n) {
         atomicOr(err, 2);
         lab = 0;
@@ -578,9 +584,9 @@ void launch_fof_labels(int64_t n, const Geo &, Work &w, int32_t *l0_out, hipStre
                        l0_out, w.err);
 }
 
-void launch_keys_from_labels(const int32_t *l0_in, int64_t n, Work &w, hipStream_t s) {
-    hipLaunchKernelGGL(k_keys_from_labels, grid(n), dim3(kBlock), 0, s, n, l0_in, w.spos, w.gkey,
-                       w.err);
+void launch_keys_from_labels(const int32_t *l0_in, const float *dens_in, int64_t n, Work &w, hipStream_t s) {
+    hipLaunchKernelGGL(k_keys_from_labels, grid(n), dim3(kBlock), 0, s, n, l0_in, dens_in, w.spos, w.gkey,
+                       w.dens_s, w.err);
 }
 
 }  // namespace hf

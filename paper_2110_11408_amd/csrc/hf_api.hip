@@ -588,8 +588,7 @@ hf_status hf_compaso(hf_ctx *ctx, const float *pos, const float *density, const 
         if (n_halos) *n_halos = 0;
         return HF_OK;
     }
-    hf::launch_gather_density(density, n, w, s);
-    hf::launch_keys_from_labels(l0_id, n, w, s);
+    hf::launch_keys_from_labels(l0_id, density, n, w, s);  // also gathers the densities
     HIP_OK(c, hipEventRecord(c->ev[2], s));
     st = run_compaso(c, n, g, w, halo_id, nullptr, halos, halos_cap, n_halos, s);
     c->stats.ms_bin = elapsed(c->ev[0], c->ev[1]);
@@ -617,8 +616,7 @@ hf_status hf_halo_stats(hf_ctx *ctx, const float *pos, const float *density, con
     p2.delta_l1 = p->delta_l2;
     st = make_geo(c, &p2, n, &g2);
     if (st != HF_OK) return st;
-    hf::launch_gather_density(density, n, w, s);
-    hf::launch_keys_from_labels(halo_id, n, w, s);
+    hf::launch_keys_from_labels(halo_id, density, n, w, s);  // also gathers the densities
     HIP_OK(c, hipEventRecord(c->ev[2], s));
     HIP_OK(c, hipEventRecord(c->ev[3], s));
     hf::launch_segment(n, w, s);

@@ -200,7 +200,7 @@ void launch_count_pairs(int64_t n, const Geo &g, Work &w, unsigned long long *to
 void launch_gather_density(const float *dens_in, int64_t n, Work &w, hipStream_t s);
 void launch_fof(int64_t n, const Geo &g, Work &w, hipStream_t s);
 void launch_fof_labels(int64_t n, const Geo &g, Work &w, int32_t *l0_out, hipStream_t s);
-void launch_keys_from_labels(const int32_t *l0_in, int64_t n, Work &w, hipStream_t s);
+void launch_keys_from_labels(const int32_t *l0_in, const float *dens_in, int64_t n, Work &w, hipStream_t s);
 void launch_segment(int64_t n, Work &w, hipStream_t s);
 void launch_segment_groups(int64_t n, int64_t G, Work &w, hipStream_t s);
 void launch_candidates(int64_t n, const Geo &g, Work &w, hipStream_t s);   // candidates.hip
