@@ -215,14 +215,17 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t *__restric
     }
 }
 
-// Sorted slot s: the particle's two float4 records and its sub-cell.
+// Sorted slot s: the particle's two float4 records, its sub-cell and, when
+// densities follow, its density record.
 template <bool kPacked>
 __global__ __launch_bounds__(kBlock) void k_bin_place(const float *__restrict__ pos, int64_t n, Geo g, int ib,
                                                       const uint64_t *__restrict__ key,
                                                       const uint32_t *__restrict__ idx,
                                                       float4 *__restrict__ spos, float4 *__restrict__ sloc,
-                                                      uint16_t *__restrict__ ssub) {
+                                                      float4 *__restrict__ pq, uint16_t *__restrict__ ssub) {
     const int64_t s = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
+    // pq's padding (read past a cell's end by the density kernel, never used)
+    if (pq && s < 32) pq[n + s] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     if (s >= n) return;
     const uint64_t kw = key[s];
     const uint64_t k = kPacked ? kw >> ib : kw;
@@ -238,6 +241,12 @@ __global__ __launch_bounds__(kBlock) void k_bin_place(const float *__restrict__ 
     const float yl = (float)(((double)y - (double)cy * g.cell) * g.inv_b);
     const float zl = (float)(((double)z - (double)cz * g.cell) * g.inv_b);
     sloc[s] = make_float4(xl, yl, zl, __uint_as_float(c));
+    if (pq) {
+        // coordinates about the cell centre and minus their squared norm
+        const float c0 = 0.5f * g.cellb;
+        const float xc = xl - c0, yc = yl - c0, zc = zl - c0;
+        pq[s] = make_float4(xc, yc, zc, -(xc * xc + yc * yc + zc * zc));
+    }
     ssub[s] = (uint16_t)sub;
 }
 
@@ -492,10 +501,10 @@ void launch_bin(const float *pos, int64_t n, const Geo &g, Work &w, hipStream_t 
     }
     if (packed)
         hipLaunchKernelGGL(k_bin_place<true>, dim3(blocks(n)), dim3(kBlock), 0, s, pos, n, g, r.ib, w.rkey[cur],
-                           nullptr, w.spos, w.sloc, w.ssub);
+                           nullptr, w.spos, w.sloc, w.pq, w.ssub);
     else
         hipLaunchKernelGGL(k_bin_place<false>, dim3(blocks(n)), dim3(kBlock), 0, s, pos, n, g, 0, w.rkey[cur],
-                           w.rval[cur], w.spos, w.sloc, w.ssub);
+                           w.rval[cur], w.spos, w.sloc, w.pq, w.ssub);
     // slots 0..n (slot n closes the grid): one wavefront per 64
     hipLaunchKernelGGL(k_cell_offsets, dim3((unsigned)((n + 1 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n,
                        ncell, w.sloc, w.off);

@@ -2,17 +2,18 @@
 // norm = 15 / (8 pi b^3 nbar) so that a uniform field has Delta = 1 (App. B.2).
 //
 // Coordinates are the cell-local FP32 values in units of b; the periodic image
-// of a neighbour cell is the exact cell offset, so W = 1 - d^2 is three FMAs on
-// (dx, dy, dz) clamped at 0 (which also removes pairs beyond b).  The self pair
-// contributes exactly 1 and is subtracted at the end.  Partial sums run over at
-// most 64 neighbours in FP32 and are accumulated in FP64, in cell order, so the
-// result does not depend on the launch shape.
+// of a neighbour cell is the exact cell offset, so a pair's weight is
+// 1 - d^2 clamped at 0 (which also removes pairs beyond b).
 //
-// Dense cells: one wavefront per chunk of <= 64 particles of the cell (one per
-// lane), or per pair of small x-adjacent dense cells; the neighbour cells are
-// streamed in the same order by all lanes, so neighbour coordinates are
-// wave-uniform and come through the scalar cache as SGPR operands of the FP32
-// FMAs.  Sparse cells: one thread per particle.
+// Dense cells (>= 8 particles): one wavefront per chunk of <= 64 consecutive
+// particles of the cell.  The weights of 16 i-particles against 16 neighbours
+// come from one FP32 matrix-core product (the squared distance expanded into
+// a rank-4 inner product), so the vector ALU only clamps and sums; blocks of
+// 16 lanes that hold no particle are skipped.  The self pair is masked out and
+// added back as exactly 1 when it counts.  Sparse cells: one thread per
+// particle, the difference form d = x_j - x_i on the vector ALU.  Partial sums
+// run in FP32 over bounded stretches and are accumulated in FP64 in a fixed
+// order, so the result does not depend on the launch shape.
 #include "hf_internal.h"
 
 namespace hf {
@@ -50,51 +51,6 @@ __device__ __forceinline__ void accum_range(const float4 *__restrict__ sloc, uin
     }
 }
 
-// accum_range for a wave-uniform range: the neighbours are read through a
-// pointer with constant offsets so that eight of them arrive in two 64-byte
-// scalar loads behind one wait.
-__device__ __forceinline__ void accum_range_uniform(const float4 *__restrict__ sloc, uint32_t a, uint32_t b,
-                                                    float xs, float ys, float zs, double &acc) {
-    for (uint32_t j0 = a; j0 < b; j0 += 64) {
-        const float4 *pj = sloc + j0;
-        uint32_t m = min(64u, b - j0);
-        float p = 0.0f;
-        for (; m >= 8; m -= 8, pj += 8) {
-#pragma unroll
-            for (int u = 0; u < 8; u++) {
-                const float4 lj = pj[u];
-                const float dx = lj.x - xs, dy = lj.y - ys, dz = lj.z - zs;
-                float t = fmaf(-dx, dx, 1.0f);
-                t = fmaf(-dy, dy, t);
-                t = fmaf(-dz, dz, t);
-                p += fmaxf(t, 0.0f);
-            }
-        }
-        for (; m > 0; m--, pj++) {
-            const float4 lj = *pj;
-            const float dx = lj.x - xs, dy = lj.y - ys, dz = lj.z - zs;
-            float t = fmaf(-dx, dx, 1.0f);
-            t = fmaf(-dy, dy, t);
-            t = fmaf(-dz, dz, t);
-            p += fmaxf(t, 0.0f);
-        }
-        acc += (double)p;
-    }
-}
-
-// Sum of v over the wavefront in a fixed order, wave-uniform: inclusive sums of
-// each 16-lane row by DPP row shifts, then the four row totals in row order.
-__device__ __forceinline__ float wave_sum(float v) {
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, true));
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xf, 0xf, true));
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xf, 0xf, true));
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xf, 0xf, true));
-    const int b = __float_as_int(v);
-    return ((__int_as_float(__builtin_amdgcn_readlane(b, 15)) + __int_as_float(__builtin_amdgcn_readlane(b, 31))) +
-            __int_as_float(__builtin_amdgcn_readlane(b, 47))) +
-           __int_as_float(__builtin_amdgcn_readlane(b, 63));
-}
-
 // Dense-neighbour contributions of sparse particles are added in fixed point
 // (2^-32), so their order does not change the result.
 constexpr double kFixScale = 4294967296.0;
@@ -108,90 +64,334 @@ __device__ __forceinline__ void write_density(int64_t i, double acc, const Geo &
     if (dens_out) dens_out[orig_of(spos[i])] = d;
 }
 
-__global__ __launch_bounds__(kBlock) void k_density_dense(int64_t nchunks, Geo g,
-                                                          const int32_t *__restrict__ chunks,
-                                                          const float4 *__restrict__ sloc,
-                                                          const float4 *__restrict__ spos,
-                                                          const uint32_t *__restrict__ off,
-                                                          const uint32_t *__restrict__ s_sparse,
-                                                          uint64_t *__restrict__ dfx,
-                                                          float *__restrict__ dens_s,
-                                                          float *__restrict__ dens_out) {
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t q = (int64_t)xcd_block() * (kBlock / 64) + wave;
-    if (q >= nchunks) return;
-    const int lane = threadIdx.x & 63;
-    const uint32_t h = (uint32_t)__builtin_amdgcn_readfirstlane(chunks[q]);
-    const uint32_t c = __builtin_amdgcn_readfirstlane(__float_as_uint(sloc[h].w));
-    const uint32_t cend = __builtin_amdgcn_readfirstlane(off[c + 1]);
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// max(x, 0) for a finite float as one integer maximum: negative values (and
+// -0) have the sign bit set.
+__device__ __forceinline__ float clamp0(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
+// Dense chunk with R = ceil(active lanes / 16) row blocks of 16 i-particles.
+//
+// pq holds per sorted particle the cell-centred coordinates x_c (units of b)
+// and -|x_c|^2.  For a neighbour cell at image offset s (a multiple of the
+// cell width) the pair weight before clamping is
+//   1 - |x_i - s - x_j|^2 = (1 - |x_i - s|^2) + 2 (x_i - s).x_j - |x_j|^2,
+// a rank-4 product: one v_mfma_f32_16x16x4_f32 per 16x16 block of pairs with
+// A = (2 (x_i - s), 1), B = (x_j, -|x_j|^2) straight from pq and the
+// accumulator input 1 - |x_i - s|^2, itself one product per cell
+// ((2 x_i, 1) against (s, -|s|^2) added to 1 - |x_i|^2).  The vector ALU only
+// clamps and sums.  For the pairs that count every term is below about 4 in
+// magnitude, so a weight is within a few 1e-7 of the difference form.
+//
+// Layouts of the 16x16x4 FP32 instruction (one block): lane l holds
+// A[l % 16][l / 16] and B[l / 16][l % 16]; result register v of lane l is
+// D[4 (l / 16) + v][l % 16].  Lane l therefore sums, for the rows
+// 16 r + 4 (l / 16) + v, the neighbours in column l % 16; the 16 lanes of a
+// row group are reduced at the end.  Neighbours stream in blocks of 16
+// consecutive sorted particles per cell; a column past the cell's end gets
+// B = (., ., ., -1e30) and weighs 0 (pq is padded so that the load stays in
+// bounds).
+template <int R, bool kNarrow>
+__device__ __forceinline__ void density_chunk(const Geo &g, uint32_t h, uint32_t c, uint32_t end,
+                                              const float *__restrict__ pq,
+                                              const float4 *__restrict__ spos,
+                                              const uint32_t *__restrict__ off,
+                                              const uint32_t *__restrict__ s_sparse,
+                                              uint64_t *__restrict__ dfx, float *__restrict__ dens_s,
+                                              float *__restrict__ dens_out, float (*colsum)[64]) {
+    const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
+    const int loff = 4 * col + grp;  // this lane's word of a block of 16 pq records
+    // this lane's word of the block of 16 records from j0, as a buffer load
+    // (scalar address arithmetic only; the lane offset is a constant VGPR):
+    // one descriptor at pq with the block's byte offset in an SGPR while the
+    // offsets fit in 32 bits, else a descriptor at the block itself
+    const __amdgpu_buffer_rsrc_t rs0 =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(pq), 0, (int)0xffffffffu, 0x00020000);
+    auto ld = [&](uint32_t j0) -> float {
+        if (kNarrow)
+            return __builtin_bit_cast(float,
+                                      __builtin_amdgcn_raw_buffer_load_b32(rs0, loff * 4, (int)(j0 * 16u), 0));
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float *>(pq + 4 * (size_t)j0), 0, 256, 0x00020000);
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, loff * 4, 0, 0));
+    };
     const int nc = g.nc;
     const int cx = (int)(c % (uint32_t)nc), cy = (int)((c / (uint32_t)nc) % (uint32_t)nc),
               cz = (int)(c / ((uint32_t)nc * (uint32_t)nc));
-    uint32_t end = min(h + 64u, cend);
-    // Two x-adjacent cells (even x, and x + 1 in the same row) that are both
-    // dense and together hold at most 64 particles share one wavefront: their
-    // particles are consecutive, the stream covers x offsets -1..2 from the
-    // even cell, and each lane shifts the neighbours by its own cell's offset
-    // (a pair outside a lane's 27 cells is at least one cell width apart and
-    // weighs exactly 0).  The odd cell's wavefront finds the same pair and exits.
-    int xmax = 1;
-    // only a cell that is a single chunk pairs (the chunk starts the cell)
-    if (cend - h <= 64u && h == (uint32_t)__builtin_amdgcn_readfirstlane(off[c])) {
-        const uint32_t mine = cend - h;
-        if (cx & 1) {
-            const uint32_t left = h - (uint32_t)__builtin_amdgcn_readfirstlane(off[c - 1]);
-            if (left >= (uint32_t)kDenseMin && left <= 64u && left + mine <= 64u) return;
-        } else if (cx + 1 < nc) {
-            const uint32_t e2 = (uint32_t)__builtin_amdgcn_readfirstlane(off[c + 2]);
-            const uint32_t right = e2 - cend;
-            if (right >= (uint32_t)kDenseMin && right <= 64u && mine + right <= 64u) {
-                end = e2;
-                xmax = 2;
-            }
+    // the chunk's rows: A = (2 x_i, 1), accumulator input 1 - |x_i|^2; rows
+    // past the chunk get A = (0, 0, 0, 1) and -1, so all their weights clamp
+    // to exactly 0
+    float A[R];
+    f32x4 C[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const uint32_t ir = h + 16u * (uint32_t)r + (uint32_t)col;
+        const float v = pq[4 * (size_t)min(ir, end - 1u) + grp];
+        A[r] = grp == 3 ? 1.0f : (ir < end ? v + v : 0.0f);
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const uint32_t iu = h + 16u * (uint32_t)r + 4u * (uint32_t)grp + (uint32_t)u;
+            const float q = pq[4 * (size_t)min(iu, end - 1u) + 3];
+            C[r][u] = iu < end ? 1.0f + q : -1.0f;
         }
     }
-    const uint32_t i = h + (uint32_t)lane;
-    const bool active = i < end;
-    const float4 li = sloc[active ? i : h];
-    const float du = i >= cend ? 1.0f : 0.0f;  // x offset of the lane's cell in a pair
+    // neighbour ranges, one per lane: lanes 0..26 the stencil cells (lane
+    // 9 (oz+1) + 3 (oy+1) + ox+1); the chunk's own cell (lane 13) is cut
+    // around the chunk's diagonal blocks, its tail is range 27
+    uint32_t ra = 0, rb = 0, sb = 0;
+    bool sp = false;
+    if (lane < 27) {
+        const int ox = lane % 3 - 1, oy = (lane / 3) % 3 - 1, oz = lane / 9 - 1;
+        const uint32_t nb = ((uint32_t)wrapc(cz + oz, nc) * (uint32_t)nc + (uint32_t)wrapc(cy + oy, nc)) *
+                                (uint32_t)nc +
+                            (uint32_t)wrapc(cx + ox, nc);
+        ra = off[nb];
+        rb = off[nb + 1];
+        // a sparse cell's particles have consecutive sparse ordinals
+        sp = rb > ra && rb - ra < (uint32_t)kDenseMin;
+        if (sp) sb = s_sparse[ra];
+    }
+    const uint32_t cend = (uint32_t)__builtin_amdgcn_readlane((int)rb, 13);
+    const uint32_t tail = h + 16u * (uint32_t)R;
+    if (lane == 13) rb = h;
+    if (lane == 27) {
+        ra = tail;
+        rb = cend > tail ? cend : tail;
+    }
+    const uint64_t spm = __ballot(sp);
+    uint64_t todo = __ballot(lane < 28 && rb > ra);
+
+    // FP32 partials over at most 16 blocks.  A flush sums them over the 16
+    // lanes of each row group (halving exchanges in a fixed order; afterwards
+    // lane col holds entry m = col: row block m / 4, register m % 4) and adds
+    // that row total to the lane's FP64 sum.
+    float pf[4 * R];
+#pragma unroll
+    for (int m = 0; m < 4 * R; m++) pf[m] = 0.0f;
     double acc = 0.0;
-    for (int oz = -1; oz <= 1; oz++) {
-        const int z = wrapc(cz + oz, nc);
-        const float zs = li.z - (float)oz * g.cellb;
-        for (int oy = -1; oy <= 1; oy++) {
-            const int y = wrapc(cy + oy, nc);
-            const float ys = li.y - (float)oy * g.cellb;
-            const uint32_t row = ((uint32_t)z * (uint32_t)nc + (uint32_t)y) * (uint32_t)nc;
-            for (int ox = -1; ox <= xmax; ox++) {
-                const uint32_t nb = row + (uint32_t)wrapc(cx + ox, nc);
-                const float xs = li.x - ((float)ox - du) * g.cellb;
-                const uint32_t a = __builtin_amdgcn_readfirstlane(off[nb]);
-                const uint32_t b = __builtin_amdgcn_readfirstlane(off[nb + 1]);
-                if (b - a >= (uint32_t)kDenseMin) {
-                    accum_range_uniform(sloc, a, b, xs, ys, zs, acc);
-                    continue;
-                }
-                // sparse neighbour cell: the pair weights also go to the
-                // sparse particle, summed over the chunk in a fixed order
-                float p = 0.0f;
-                for (uint32_t j = a; j < b; j++) {
-                    const float4 lj = sloc[j];
-                    const float dx = lj.x - xs, dy = lj.y - ys, dz = lj.z - zs;
-                    float t = fmaf(-dx, dx, 1.0f);
-                    t = fmaf(-dy, dy, t);
-                    t = fmaf(-dz, dz, t);
-                    t = active ? fmaxf(t, 0.0f) : 0.0f;
-                    p += t;
-                    const float sum = wave_sum(t);
-                    if (lane == 0 && sum > 0.0f)
-                        atomicAdd(reinterpret_cast<unsigned long long *>(&dfx[s_sparse[j]]),
-                                  (unsigned long long)__double2ll_rn((double)sum * kFixScale));
-                }
-                acc += (double)p;
+    auto reduce = [&]() {
+        float t[16];
+#pragma unroll
+        for (int m = 0; m < 16; m++) t[m] = m < 4 * R ? pf[m] : 0.0f;
+#pragma unroll
+        for (int half = 8; half >= 1; half >>= 1) {
+            const bool upper = (col & half) != 0;
+#pragma unroll
+            for (int m = 0; m < half; m++) {
+                if (m >= 4 * R && m + half >= 4 * R) continue;  // both zero
+                const float keep = upper ? t[m + half] : t[m];
+                const float send = upper ? t[m] : t[m + half];
+                t[m] = keep + __shfl_xor(send, half);
             }
         }
+        acc += (double)t[0];
+#pragma unroll
+        for (int m = 0; m < 4 * R; m++) pf[m] = 0.0f;
+    };
+    int nt = 0;
+    auto flush = [&]() {
+        if (++nt == 16) {
+            reduce();
+            nt = 0;
+        }
+    };
+
+    // the chunk's own blocks: the self pairs sit on the diagonal of block
+    // r = rd; their accumulator input is -1e30 so they weigh 0
+    const int dv = col - 4 * grp;
+#pragma unroll
+    for (int rd = 0; rd < R; rd++) {
+        const uint32_t j0 = h + 16u * (uint32_t)rd;
+        const float val = ld(j0);
+        const float bv = (grp == 3 && (uint32_t)col >= cend - j0) ? -1e30f : val;
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            f32x4 cin = C[r];
+            if (r == rd) {
+#pragma unroll
+                for (int u = 0; u < 4; u++) cin[u] = dv == u ? -1e30f : cin[u];
+            }
+            const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x4f32(A[r], bv, cin, 0, 0, 0);
+#pragma unroll
+            for (int u = 0; u < 4; u++) pf[4 * r + u] += clamp0(d[u]);
+        }
+        flush();
     }
-    if (active) write_density(i, acc, g, spos, dens_s, dens_out);
+
+    if (todo) {
+        float As[R];
+        f32x4 Cs[R];
+        int k = __builtin_ctzll(todo);
+        todo &= todo - 1;
+        uint32_t j0 = (uint32_t)__builtin_amdgcn_readlane((int)ra, k);
+        uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)rb, k);
+        auto setup = [&](int kk) {
+            const int ks = kk == 27 ? 13 : kk;
+            const float sx = (float)(ks % 3 - 1) * g.cellb, sy = (float)((ks / 3) % 3 - 1) * g.cellb,
+                        sz = (float)(ks / 9 - 1) * g.cellb;
+            const float sg = grp == 0 ? sx : (grp == 1 ? sy : sz);
+            const float bs = grp == 3 ? -(sx * sx + sy * sy + sz * sz) : sg;
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                As[r] = grp == 3 ? 1.0f : A[r] - (sg + sg);
+                Cs[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[r], bs, C[r], 0, 0, 0);
+            }
+        };
+        setup(k);
+        // one block: 16 neighbours [j0, j0 + 16) of range k (ending at b),
+        // this lane's component val
+        auto block = [&](uint32_t j0, uint32_t b, int k, bool sparse, float val) {
+            const uint32_t rem = b - j0;
+            const float bv = (grp == 3 && (uint32_t)col >= rem) ? -1e30f : val;
+            if (sparse) {
+                // sparse cell: the column's weights also go to its particle.
+                // Each lane keeps the sum of its column entries (a fixed
+                // tree) in LDS; the four row groups are added at the end.
+                float part[R];
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x4f32(As[r], bv, Cs[r], 0, 0, 0);
+                    float w[4];
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        w[u] = clamp0(d[u]);
+                        pf[4 * r + u] += w[u];
+                    }
+                    part[r] = (w[0] + w[1]) + (w[2] + w[3]);
+                }
+                float cs = part[0];
+                if (R == 2) cs = part[0] + part[1];
+                if (R == 3) cs = (part[0] + part[1]) + part[2];
+                if (R == 4) cs = (part[0] + part[1]) + (part[2] + part[3]);
+                colsum[k][lane] = cs;
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x4f32(As[r], bv, Cs[r], 0, 0, 0);
+#pragma unroll
+                    for (int u = 0; u < 4; u++) pf[4 * r + u] += clamp0(d[u]);
+                }
+            }
+            flush();
+        };
+        // The blocks in stream order come from a generator (range gk, next
+        // block gj, range end gb); four of them are loaded ahead in a ring.
+        int gk = k;
+        uint32_t gj = j0, gb = b;
+        auto gen = [&](int &ko, uint32_t &jo) {
+            ko = gk;
+            jo = gj;
+            if (gk < 0) return;
+            gj += 16u;
+            if (gj >= gb) {
+                if (todo) {
+                    gk = __builtin_ctzll(todo);
+                    todo &= todo - 1;
+                    gj = (uint32_t)__builtin_amdgcn_readlane((int)ra, gk);
+                    gb = (uint32_t)__builtin_amdgcn_readlane((int)rb, gk);
+                } else {
+                    gk = -1;
+                }
+            }
+        };
+        // Blocks go in batches of four: the loads of the next batch are
+        // issued before the current one is summed (two register sets in
+        // turn).  A position past the stream's end loads the chunk's own
+        // first block instead and is skipped.
+        bool sparse = ((spm >> k) & 1ull) != 0;  // the current range is a sparse cell
+        auto use = [&](int bk, uint32_t bj, float v) {
+            if (bk < 0) return;
+            if (bk != k) {
+                k = bk;
+                b = (uint32_t)__builtin_amdgcn_readlane((int)rb, k);
+                sparse = ((spm >> k) & 1ull) != 0;
+                setup(k);
+            }
+            block(bj, b, k, sparse, v);
+        };
+        int ka[4], kb[4];
+        uint32_t ja[4], jb[4];
+        float va[4], vb[4];
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            gen(ka[t], ja[t]);
+            va[t] = ld(ka[t] >= 0 ? ja[t] : h);
+        }
+        while (true) {
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                gen(kb[t], jb[t]);
+                vb[t] = ld(kb[t] >= 0 ? jb[t] : h);
+            }
+#pragma unroll
+            for (int t = 0; t < 4; t++) use(ka[t], ja[t], va[t]);
+            if (kb[0] < 0) break;
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                gen(ka[t], ja[t]);
+                va[t] = ld(ka[t] >= 0 ? ja[t] : h);
+            }
+#pragma unroll
+            for (int t = 0; t < 4; t++) use(kb[t], jb[t], vb[t]);
+            if (ka[0] < 0) break;
+        }
+    }
+    // the sparse particles' shares, in fixed point
+    for (uint64_t m = spm; m;) {
+        const int k = __builtin_ctzll(m);
+        m &= m - 1;
+        const uint32_t cnt = (uint32_t)__builtin_amdgcn_readlane((int)rb, k) -
+                             (uint32_t)__builtin_amdgcn_readlane((int)ra, k);
+        const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)sb, k);
+        if ((uint32_t)lane < cnt) {
+            const float v = (colsum[k][lane] + colsum[k][lane + 16]) + (colsum[k][lane + 32] + colsum[k][lane + 48]);
+            if (v > 0.0f)
+                atomicAdd(reinterpret_cast<unsigned long long *>(&dfx[base + (uint32_t)lane]),
+                          (unsigned long long)__double2ll_rn((double)v * kFixScale));
+        }
+    }
+    reduce();
+    const uint32_t ii = h + 16u * (uint32_t)(col >> 2) + 4u * (uint32_t)grp + (uint32_t)(col & 3);
+    if (ii < end) {
+        // the self pair weighs exactly 1 when it counts
+        const double S = acc + (g.self_count ? 1.0 : 0.0);
+        const float dd = (float)(g.norm * S);
+        dens_s[ii] = dd;
+        if (dens_out) dens_out[orig_of(spos[ii])] = dd;
+    }
+}
+
+// One wavefront per workgroup: chunk costs differ widely, and a finished
+// wavefront frees its slot at once.
+__global__ __launch_bounds__(64) void k_density_dense(int64_t nchunks, Geo g, bool narrow,
+                                                      const int32_t *__restrict__ chunks,
+                                                      const float4 *__restrict__ sloc,
+                                                      const float4 *__restrict__ pq,
+                                                      const float4 *__restrict__ spos,
+                                                      const uint32_t *__restrict__ off,
+                                                      const uint32_t *__restrict__ s_sparse,
+                                                      uint64_t *__restrict__ dfx,
+                                                      float *__restrict__ dens_s,
+                                                      float *__restrict__ dens_out) {
+    const int64_t q = (int64_t)xcd_block();
+    if (q >= nchunks) return;
+    const uint32_t h = (uint32_t)__builtin_amdgcn_readfirstlane(chunks[q]);
+    const uint32_t c = __builtin_amdgcn_readfirstlane(__float_as_uint(sloc[h].w));
+    const uint32_t cend = __builtin_amdgcn_readfirstlane(off[c + 1]);
+    const uint32_t end = min(h + 64u, cend);
+    const float *p = reinterpret_cast<const float *>(pq);
+    // per-lane column sums of the sparse neighbour cells
+    __shared__ float cs[27][64];
+#define HF_DENSITY_CHUNK(RR)                                                                            \
+    (narrow ? density_chunk<RR, true>(g, h, c, end, p, spos, off, s_sparse, dfx, dens_s, dens_out, cs) \
+            : density_chunk<RR, false>(g, h, c, end, p, spos, off, s_sparse, dfx, dens_s, dens_out, cs))
+    switch ((end - h + 15u) >> 4) {
+    case 1: HF_DENSITY_CHUNK(1); break;
+    case 2: HF_DENSITY_CHUNK(2); break;
+    case 3: HF_DENSITY_CHUNK(3); break;
+    default: HF_DENSITY_CHUNK(4); break;
+    }
+#undef HF_DENSITY_CHUNK
 }
 
 // Sparse cells: one particle per lane, sparse neighbour cells only; the pairs
@@ -310,8 +510,9 @@ void launch_density(int64_t n, const Geo &g, Work &w, float *dens_out, hipStream
     uint64_t *dfx = w.rkey[0];
     if (w.nsparse > 0) fill_u32(reinterpret_cast<uint32_t *>(dfx), 0u, 2 * w.nsparse, s);
     if (w.nchunks > 0)
-        hipLaunchKernelGGL(k_density_dense, dim3((unsigned)((w.nchunks + 3) / 4)), dim3(kBlock), 0, s,
-                           w.nchunks, g, w.chunks, w.sloc, w.spos, w.off, w.s_sparse, dfx, w.dens_s,
+        hipLaunchKernelGGL(k_density_dense, dim3((unsigned)w.nchunks), dim3(64), 0, s, w.nchunks, g,
+                           (n + 32) * 16 <= (int64_t)0xffffff00, w.chunks, w.sloc, w.pq, w.spos, w.off,
+                           w.s_sparse, dfx, w.dens_s,
                            dens_out);
     if (w.nsparse > 0)
         hipLaunchKernelGGL(k_density_sparse, dim3((unsigned)((w.nsparse + kBlock - 1) / kBlock)),

@@ -145,6 +145,7 @@ size_t carve(char *base, int64_t n, int64_t ncell, int nsub, int64_t rhl, bool e
     w->ssub = c.take<uint16_t>(n);
     w->spos = c.take<float4>(n);
     w->sloc = c.take<float4>(n);
+    w->pq = c.take<float4>(n + 32);
     w->f_chunk = c.take<uint32_t>(n1);
     w->s_chunk = c.take<uint32_t>(n1);
     w->f_dcell = c.take<uint32_t>(n1);
@@ -313,8 +314,10 @@ hf_status run_compaso(Lane *c, int64_t n, const Geo &g, Work &w, int32_t *halo_i
     return HF_OK;
 }
 
+// dens: the call computes densities (binning also writes the records the
+// density kernel reads); extra: halo statistics buffers.
 hf_status begin(Lane *c, const float *pos, int64_t n, const hf_params *p, Geo *g, Work *w,
-                hipStream_t s, bool extra = false) {
+                hipStream_t s, bool dens, bool extra = false) {
     if (!c) return HF_ERR_INVALID;
     c->err.clear();
     if (!p) return fail(c, HF_ERR_INVALID, "params is NULL");
@@ -332,6 +335,7 @@ hf_status begin(Lane *c, const float *pos, int64_t n, const hf_params *p, Geo *g
     if (!pos) return fail(c, HF_ERR_INVALID, "pos is NULL");
     st = prepare(c, n, *g, w, extra);
     if (st != HF_OK) return st;
+    if (!dens) w->pq = nullptr;
     hf::fill_i32(w->counters, 0, 16, s);
     hf::fill_i32(w->err, 0, 4, s);
     HIP_OK(c, hipEventRecord(c->ev[0], s));
@@ -406,7 +410,7 @@ hf_status lane_find(Lane *c, const float *pos, int64_t n, const hf_params *p, fl
     Work w;
     if (n > 0 && !halo_id) return fail(c, HF_ERR_INVALID, "halo_id is NULL");
     if (halos_cap < 0 || (halos_cap > 0 && !halos)) return fail(c, HF_ERR_INVALID, "bad halos / halos_cap");
-    hf_status st = begin(c, pos, n, p, &g, &w, s);
+    hf_status st = begin(c, pos, n, p, &g, &w, s, true);
     if (st != HF_OK) return st;
     if (n == 0) {
         if (n_halos) *n_halos = 0;
@@ -512,7 +516,7 @@ hf_status hf_density(hf_ctx *ctx, const float *pos, int64_t n, const hf_params *
     hipStream_t s = (hipStream_t)stream;
     Geo g;
     Work w;
-    hf_status st = begin(c, pos, n, p, &g, &w, s);
+    hf_status st = begin(c, pos, n, p, &g, &w, s, true);
     if (st != HF_OK || n == 0) return st;
     if (!density) return fail(c, HF_ERR_INVALID, "density is NULL");
     hf::launch_density(n, g, w, density, s);
@@ -532,7 +536,7 @@ hf_status hf_count_pairs(hf_ctx *ctx, const float *pos, int64_t n, const hf_para
     Work w;
     if (!pairs) return fail(c, HF_ERR_INVALID, "pairs is NULL");
     *pairs = 0;
-    hf_status st = begin(c, pos, n, p, &g, &w, s);
+    hf_status st = begin(c, pos, n, p, &g, &w, s, false);
     if (st != HF_OK || n == 0) return st;
     hf::fill_i32(w.counters + 4, 0, 2, s);
     hf::launch_count_pairs(n, g, w, (unsigned long long *)(w.counters + 4), s);
@@ -547,7 +551,7 @@ hf_status hf_l0_fof(hf_ctx *ctx, const float *pos, const float *density, int64_t
     Geo g;
     Work w;
     if (n > 0 && (!density || !l0_id)) return fail(c, HF_ERR_INVALID, "density / l0_id is NULL");
-    hf_status st = begin(c, pos, n, p, &g, &w, s);
+    hf_status st = begin(c, pos, n, p, &g, &w, s, false);
     if (st != HF_OK) return st;
     if (n == 0) {
         if (n_groups) *n_groups = 0;
@@ -582,7 +586,7 @@ hf_status hf_compaso(hf_ctx *ctx, const float *pos, const float *density, const 
     if (n > 0 && (!density || !l0_id || !halo_id))
         return fail(c, HF_ERR_INVALID, "density / l0_id / halo_id is NULL");
     if (halos_cap < 0 || (halos_cap > 0 && !halos)) return fail(c, HF_ERR_INVALID, "bad halos / halos_cap");
-    hf_status st = begin(c, pos, n, p, &g, &w, s);
+    hf_status st = begin(c, pos, n, p, &g, &w, s, false);
     if (st != HF_OK) return st;
     if (n == 0) {
         if (n_halos) *n_halos = 0;
@@ -605,7 +609,7 @@ hf_status hf_halo_stats(hf_ctx *ctx, const float *pos, const float *density, con
     Work w;
     if (n > 0 && (!density || !halo_id)) return fail(c, HF_ERR_INVALID, "density / halo_id is NULL");
     if (n_halos < 0 || (n_halos > 0 && !stats)) return fail(c, HF_ERR_INVALID, "bad stats / n_halos");
-    hf_status st = begin(c, pos, n, p, &g, &w, s, true);
+    hf_status st = begin(c, pos, n, p, &g, &w, s, false, true);
     if (st != HF_OK) return st;
     if (n == 0) {
         if (n_halos != 0) return fail(c, HF_ERR_INVALID, "n_halos must be 0 for an empty input");

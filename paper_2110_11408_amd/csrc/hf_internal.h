@@ -136,6 +136,7 @@ struct Work {
     uint32_t *rhist, *rscan;         // per-pass [digit][tile] counts and their scan
     uint16_t *ssub;
     float4 *spos, *sloc;
+    float4 *pq;                      // density only: cell-centred (x, y, z, -|x|^2), n + 32 entries
     // work decomposition (dense chunks, dense cells, sparse particles)
     uint32_t *f_chunk, *s_chunk, *f_dcell, *s_dcell, *f_sparse, *s_sparse;
     int32_t *chunks, *sparse;
