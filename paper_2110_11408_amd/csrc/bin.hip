@@ -281,7 +281,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_offsets(int64_t n, int64_t ncel
         if (lane >= d) incl += y;
     }
     const uint32_t pre = incl - g;
-    const uint32_t G = __shfl(incl, 63, 64);
+    const uint32_t G = lane_get(incl, 63);
     // first cell owned by the wavefront: one past the cell of the slot before it
     const int64_t first = s0 == 0 ? 0 : (int64_t)__float_as_uint(sloc[s0 - 1].w) + 1;
     const int64_t end = first + (int64_t)G;

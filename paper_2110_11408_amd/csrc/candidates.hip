@@ -312,7 +312,7 @@ __global__ __launch_bounds__(kBlock) void k_cand_hard(const uint32_t *__restrict
     const int leader = __ffsll((unsigned long long)m) - 1;
     uint32_t base = 0;
     if (lane == leader) base = atomicAdd(nrest, (uint32_t)__popcll(m));
-    base = (uint32_t)__shfl((int)base, leader, 64);
+    base = lane_get(base, leader);
     if (left) rest[base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = i;
 }
 

@@ -283,7 +283,7 @@ __global__ __launch_bounds__(kBlock) void k_accept_small(const uint32_t *__restr
             if (hit < 0 && k >= 1 && k < m && (int64_t)C <= k) hit = (int)k;
         }
         const uint64_t hm = __ballot(hit >= 0);
-        const int64_t found = hm ? (int64_t)__shfl(hit, __ffsll((unsigned long long)hm) - 1, 64) : m;
+        const int64_t found = hm ? (int64_t)lane_get(hit, __ffsll((unsigned long long)hm) - 1) : m;
         if (lane == 0) {
             h_nuc[cs + nh] = c;
             h_ienc[cs + nh] = (int32_t)found;

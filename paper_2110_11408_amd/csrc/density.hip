@@ -161,7 +161,7 @@ __device__ __forceinline__ void density_chunk(const Geo &g, uint32_t h, uint32_t
     const uint64_t spm = __ballot(sp);
     uint64_t todo = __ballot(lane < 28 && rb > ra);
 
-    // FP32 partials over at most 16 blocks.  A flush sums them over the 16
+    // FP32 partials over at most 32 blocks.  A flush sums them over the 16
     // lanes of each row group (halving exchanges in a fixed order; afterwards
     // lane col holds entry m = col: row block m / 4, register m % 4) and adds
     // that row total to the lane's FP64 sum.
@@ -190,7 +190,7 @@ __device__ __forceinline__ void density_chunk(const Geo &g, uint32_t h, uint32_t
     };
     int nt = 0;
     auto flush = [&]() {
-        if (++nt == 16) {
+        if (++nt == 32) {
             reduce();
             nt = 0;
         }

@@ -87,7 +87,7 @@ __device__ __forceinline__ int join_lanes(int32_t *parent, bool lk, int &wr, int
     uint64_t m;
     while ((m = __ballot(need)) != 0ull) {
         const int L = __ffsll((unsigned long long)m) - 1;
-        const int w = __shfl(wr, L, 64);
+        const int w = lane_get(wr, L);
         int r = 0;
         if (lane == L) {
             // fast path: both are usually current roots, so hooking the larger
@@ -100,7 +100,7 @@ __device__ __forceinline__ int join_lanes(int32_t *parent, bool lk, int &wr, int
                 r = uf_find(parent, w);
             }
         }
-        r = __shfl(r, L, 64);
+        r = lane_get(r, L);
         if (wr == w || wr == rj) wr = r;
         rj = r;
         need = lk && wr != rj;
@@ -148,10 +148,10 @@ __device__ __forceinline__ bool stream_range(int32_t *parent, const float *__res
         while (mm) {
             const int J = __ffsll((unsigned long long)mm) - 1;
             mm &= mm - 1;
-            int r = __shfl(one_set ? rset : rj, J, 64);
+            int r = one_set ? rset : lane_get(rj, J);
             if (!__ballot(active && wr != r)) continue;
-            const float dx = __shfl(xj, J, 64) - li.x, dy = __shfl(yj, J, 64) - li.y,
-                        dz = __shfl(zj, J, 64) - li.z;
+            const float dx = lane_get(xj, J) - li.x, dy = lane_get(yj, J) - li.y,
+                        dz = lane_get(zj, J) - li.z;
             const bool lk = active && wr != r && linked_d(dx, dy, dz, pi, spos, jb + (uint32_t)J, g);
             if (!__ballot(lk)) continue;
             r = join_lanes(parent, lk, wr, r);
@@ -183,7 +183,7 @@ __device__ __forceinline__ void stream_sparse_cells(int32_t *parent, const float
         const int y = __shfl_up(incl, d, 64);
         if (lane >= d) incl += y;
     }
-    const int P = __shfl(incl, 63, 64);
+    const int P = lane_get(incl, 63);
     if (P == 0) return;
     if (lane < 27) {
         spre[lane] = cntl > 0 ? incl - cntl : 0x7fffffff;  // start of cell lane's particles
@@ -221,11 +221,11 @@ __device__ __forceinline__ void stream_sparse_cells(int32_t *parent, const float
         while (mm) {
             const int J = __ffsll((unsigned long long)mm) - 1;
             mm &= mm - 1;
-            int r = __shfl(rj, J, 64);
+            int r = lane_get(rj, J);
             if (!__ballot(active && wr != r)) continue;
-            const uint32_t jj = (uint32_t)__shfl((int)j, J, 64);
-            const float dx = __shfl(xj, J, 64) - li.x, dy = __shfl(yj, J, 64) - li.y,
-                        dz = __shfl(zj, J, 64) - li.z;
+            const uint32_t jj = lane_get(j, J);
+            const float dx = lane_get(xj, J) - li.x, dy = lane_get(yj, J) - li.y,
+                        dz = lane_get(zj, J) - li.z;
             const bool lk = active && wr != r && linked_d(dx, dy, dz, pi, spos, jj, g);
             if (!__ballot(lk)) continue;
             join_lanes(parent, lk, wr, r);
@@ -385,15 +385,15 @@ __global__ __launch_bounds__(kBlock) void k_fof_dense(int64_t nchunks, Geo g,
         int rL = fs >= 0 ? uf_find_hint(parent, fs) : -1;
         const uint64_t am = __ballot(active);
         for (;;) {
-            const int w0 = __shfl(wr, __ffsll((unsigned long long)am) - 1, 64);
+            const int w0 = lane_get(wr, __ffsll((unsigned long long)am) - 1);
             const int wcommon = __ballot(active && wr != w0) ? -2 : w0;
             const uint64_t todo = __ballot(fs >= 0 && rL != wcommon);
             if (!todo) break;
             const int S = __ffsll((unsigned long long)todo) - 1;
-            const int f = __shfl(fs, S, 64);
-            const uint32_t e = (uint32_t)__shfl((int)u1, S, 64);
-            const int sts = __shfl(st, S, 64);
-            const int rS = __shfl(rL, S, 64);
+            const int f = lane_get(fs, S);
+            const uint32_t e = lane_get(u1, S);
+            const int sts = lane_get(st, S);
+            const int rS = lane_get(rL, S);
             if (lane == S) fs = -1;  // done with it
             if (!__ballot(active && wr != rS)) continue;
             const bool joined = stream_range(parent, dens_s, sloc, spos, g, active, li, pi, wr, (uint32_t)f, e,

@@ -88,6 +88,16 @@ __device__ __forceinline__ unsigned xcd_block() {
     return start + k;
 }
 
+// Value of lane L (L wave-uniform): a v_readlane into a scalar register,
+// without the LDS round trip of a general shuffle.
+__device__ __forceinline__ int lane_get(int v, int L) { return __builtin_amdgcn_readlane(v, L); }
+__device__ __forceinline__ uint32_t lane_get(uint32_t v, int L) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, L);
+}
+__device__ __forceinline__ float lane_get(float v, int L) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), L));
+}
+
 __device__ __forceinline__ int wrapc(int c, int nc) {
     return c < 0 ? c + nc : (c >= nc ? c - nc : c);
 }
