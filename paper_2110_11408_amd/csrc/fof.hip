@@ -119,50 +119,38 @@ __device__ __forceinline__ bool linked_d(float dx, float dy, float dz, const flo
     return d2_exact(pa, spos[b], g.L, g.half) < g.l2;
 }
 
-// Joins the members j of [a, b) (a neighbour range at stencil offset
-// (ox, oy, oz) from the chunk's cell) to the lanes they link.  The range is
-// loaded 64 particles at a time, one per lane (membership, coordinates moved
-// into the chunk's frame, root hint); its members are then broadcast in
-// order.  With `one_set` the range is known to be a single set: it stops as
-// soon as every lane is in that set.  Returns whether any join was made.
+// Joins the lanes linked to any member of [a, b) to that range's set rset
+// (the range is one sub-cell, so its members are one set).  Every lane tests
+// the members in order (wave-uniform loads, coordinates as scalar operands)
+// and keeps whether it links to any of them, with the canonical FP64
+// distance in the FP32 prefilter's undecided band.  The linked lanes are
+// then joined in one go.  Returns whether any join was made.
 __device__ __forceinline__ bool stream_range(int32_t *parent, const float *__restrict__ dens_s,
                                              const float4 *__restrict__ sloc,
                                              const float4 *__restrict__ spos, const Geo &g, bool active,
                                              const float4 &li, const float4 &pi, int &wr, uint32_t a,
-                                             uint32_t b, int ox, int oy, int oz, bool one_set, int rset) {
-    const int lane = threadIdx.x & 63;
-    bool joined = false;
-    for (uint32_t jb = a; jb < b; jb += 64) {
-        const uint32_t j = jb + (uint32_t)lane;
-        const bool mem = j < b && is_member(dens_s, j, g.dl0);
-        float xj = 0.0f, yj = 0.0f, zj = 0.0f;
-        int rj = -1;
-        if (mem) {
-            const float4 lj = sloc[j];
-            xj = lj.x + (float)ox * g.cellb;
-            yj = lj.y + (float)oy * g.cellb;
-            zj = lj.z + (float)oz * g.cellb;
-            rj = one_set ? rset : uf_find_hint(parent, (int)j);
-        }
-        uint64_t mm = __ballot(mem);
-        while (mm) {
-            const int J = __ffsll((unsigned long long)mm) - 1;
-            mm &= mm - 1;
-            int r = one_set ? rset : lane_get(rj, J);
-            if (!__ballot(active && wr != r)) continue;
-            const float dx = lane_get(xj, J) - li.x, dy = lane_get(yj, J) - li.y,
-                        dz = lane_get(zj, J) - li.z;
-            const bool lk = active && wr != r && linked_d(dx, dy, dz, pi, spos, jb + (uint32_t)J, g);
-            if (!__ballot(lk)) continue;
-            r = join_lanes(parent, lk, wr, r);
-            joined = true;
-            if (one_set) {
-                rset = r;
-                if (!__ballot(active && wr != rset)) return true;
-            }
+                                             uint32_t b, int ox, int oy, int oz, int rset) {
+    // the lane's coordinates in the neighbour cell's frame
+    const float xs = li.x - (float)ox * g.cellb, ys = li.y - (float)oy * g.cellb,
+                zs = li.z - (float)oz * g.cellb;
+    const bool want = active && wr != rset;
+    bool any = false;
+    for (uint32_t j = a; j < b; j++) {
+        if (!is_member(dens_s, j, g.dl0)) continue;
+        const float4 lj = sloc[j];
+        const float dx = lj.x - xs, dy = lj.y - ys, dz = lj.z - zs;
+        const float d2f = dx * dx + dy * dy + dz * dz;
+        if (d2f < g.l2b_lo) {
+            any = true;
+        } else if (d2f < g.l2b_hi && want && !any) {
+            // the undecided band: canonical FP64 distance
+            if (d2_exact(pi, spos[j], g.L, g.half) < g.l2) any = true;
         }
     }
-    return joined;
+    const bool lk = want && any;
+    if (!__ballot(lk)) return false;
+    join_lanes(parent, lk, wr, rset);
+    return true;
 }
 
 // All sparse neighbour cells of a chunk at once: lane t < 27 holds stencil
@@ -397,7 +385,7 @@ __global__ __launch_bounds__(kBlock) void k_fof_dense(int64_t nchunks, Geo g,
             if (lane == S) fs = -1;  // done with it
             if (!__ballot(active && wr != rS)) continue;
             const bool joined = stream_range(parent, dens_s, sloc, spos, g, active, li, pi, wr, (uint32_t)f, e,
-                                             sts % 3 - 1, (sts / 3) % 3 - 1, sts / 9 - 1, true, rS);
+                                             sts % 3 - 1, (sts / 3) % 3 - 1, sts / 9 - 1, rS);
             // after a join the remaining hints may be stale: refresh them
             if (joined && fs >= 0) rL = uf_find_hint(parent, fs);
         }
