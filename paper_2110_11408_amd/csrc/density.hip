@@ -336,17 +336,35 @@ __device__ __forceinline__ void density_chunk(const Geo &g, uint32_t h, uint32_t
             if (ka[0] < 0) break;
         }
     }
-    // the sparse particles' shares, in fixed point
-    for (uint64_t m = spm; m;) {
+    // The sparse particles' shares, in fixed point: the columns of all
+    // sparse ranges are numbered in range order and handled 64 per pass, one
+    // per lane (its range and column found by one scalar walk over the
+    // ranges), so the conversion and the atomic run once per pass.
+    uint32_t ntot = 0;
+    for (uint64_t m = spm; m; m &= m - 1) {
         const int k = __builtin_ctzll(m);
-        m &= m - 1;
-        const uint32_t cnt = (uint32_t)__builtin_amdgcn_readlane((int)rb, k) -
-                             (uint32_t)__builtin_amdgcn_readlane((int)ra, k);
-        const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)sb, k);
-        if ((uint32_t)lane < cnt) {
-            const float v = (colsum[k][lane] + colsum[k][lane + 16]) + (colsum[k][lane + 32] + colsum[k][lane + 48]);
+        ntot += (uint32_t)__builtin_amdgcn_readlane((int)rb, k) - (uint32_t)__builtin_amdgcn_readlane((int)ra, k);
+    }
+    for (uint32_t p0 = 0; p0 < ntot; p0 += 64) {
+        const uint32_t q = p0 + (uint32_t)lane;  // this lane's column number
+        int kk = 0;
+        uint32_t cc = 0, dst = 0;
+        uint32_t pre = 0;
+        for (uint64_t m = spm; m; m &= m - 1) {
+            const int k = __builtin_ctzll(m);
+            const uint32_t cnt = (uint32_t)__builtin_amdgcn_readlane((int)rb, k) -
+                                 (uint32_t)__builtin_amdgcn_readlane((int)ra, k);
+            if (q >= pre && q < pre + cnt) {
+                kk = k;
+                cc = q - pre;
+                dst = (uint32_t)__builtin_amdgcn_readlane((int)sb, k) + cc;
+            }
+            pre += cnt;
+        }
+        if (q < ntot) {
+            const float v = (colsum[kk][cc] + colsum[kk][cc + 16]) + (colsum[kk][cc + 32] + colsum[kk][cc + 48]);
             if (v > 0.0f)
-                atomicAdd(reinterpret_cast<unsigned long long *>(&dfx[base + (uint32_t)lane]),
+                atomicAdd(reinterpret_cast<unsigned long long *>(&dfx[dst]),
                           (unsigned long long)__double2ll_rn((double)v * kFixScale));
         }
     }

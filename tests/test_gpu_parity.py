@@ -139,10 +139,14 @@ def test_run_to_run_determinism(ctx, runs):
 
 def test_params_variants(ctx):
     """Non-default parameters (z = 0.5 thresholds of Table 1 scaled as the paper
-    does, other alpha / c_Roche / kernel radius) stay bit-exact."""
+    does, other alpha / c_Roche / kernel radius, a linking length above the
+    kernel radius) stay bit-exact."""
     pos, L, _ = _case("s9001")
     for kw in (dict(delta_l0_min=77.5, delta_l1=258.2), dict(alpha_elig=0.7, c_roche=1.5),
-               dict(b_kernel=0.5, l_fof=0.3, n_l1_min=20), dict(self_count=1)):
+               dict(b_kernel=0.5, l_fof=0.3, n_l1_min=20), dict(self_count=1),
+               # l > b: cells wider than b (larger terms in the density's
+               # matrix-core form)
+               dict(b_kernel=0.3, l_fof=0.5)):
         _say(f"[gpu] params {kw}")
         g = gpu_find(ctx, pos, box=L, **kw)
         ref = oracle.find(pos, box=L, density_override=g["density"].astype(np.float64), **kw)
