@@ -525,8 +525,19 @@ __global__ __launch_bounds__(kBlock) void k_fof_keys(int64_t n, const int32_t *_
 // Group keys from caller-provided labels (1..n, 0 = none), in sorted order,
 // and with dens_in the caller's densities gathered into sorted order too (one
 // pass over the sorted records for both).
+// Label and density of each particle side by side, in input order (one
+// coalesced pass), so that the gather into sorted order below reads one
+// 8-byte element per particle instead of two random 4-byte ones.
+__global__ __launch_bounds__(kBlock) void k_pack_labels(int64_t n, const int32_t *__restrict__ l0_in,
+                                                        const float *__restrict__ dens_in,
+                                                        uint2 *__restrict__ packed) {
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= n) return;
+    packed[o] = make_uint2((uint32_t)l0_in[o], __float_as_uint(dens_in[o]));
+}
+
 __global__ __launch_bounds__(kBlock) void k_keys_from_labels(int64_t n, const int32_t *__restrict__ l0_in,
-                                                             const float *__restrict__ dens_in,
+                                                             const uint2 *__restrict__ packed,
                                                              const float4 *__restrict__ spos,
                                                              int32_t *__restrict__ gkey,
                                                              float *__restrict__ dens_s,
@@ -534,8 +545,14 @@ __global__ __launch_bounds__(kBlock) void k_keys_from_labels(int64_t n, const in
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint32_t o = orig_of(spos[i]);
-    if (dens_in) dens_s[i] = dens_in[o];
-    int32_t lab = l0_in[o];
+    int32_t lab;
+    if (packed) {
+        const uint2 v = packed[o];
+        lab = (int32_t)v.x;
+        dens_s[i] = __uint_as_float(v.y);
+    } else {
+        lab = l0_in[o];
+    }
     if (lab < 0 || (int64_t)lab > n) {
         atomicOr(err, 2);
         lab = 0;
@@ -573,7 +590,13 @@ void launch_fof_labels(int64_t n, const Geo &, Work &w, int32_t *l0_out, hipStre
 }
 
 void launch_keys_from_labels(const int32_t *l0_in, const float *dens_in, int64_t n, Work &w, hipStream_t s) {
-    hipLaunchKernelGGL(k_keys_from_labels, grid(n), dim3(kBlock), 0, s, n, l0_in, dens_in, w.spos, w.gkey,
+    // the packed copy lives in the second radix key array (free after binning)
+    uint2 *packed = nullptr;
+    if (dens_in) {
+        packed = reinterpret_cast<uint2 *>(w.rkey[1]);
+        hipLaunchKernelGGL(k_pack_labels, grid(n), dim3(kBlock), 0, s, n, l0_in, dens_in, packed);
+    }
+    hipLaunchKernelGGL(k_keys_from_labels, grid(n), dim3(kBlock), 0, s, n, l0_in, packed, w.spos, w.gkey,
                        w.dens_s, w.err);
 }
 
