@@ -71,6 +71,8 @@ __global__ __launch_bounds__(kBlock) void k_bin_key(const float *__restrict__ po
 }
 
 constexpr int kRadixMaxBits = 8;
+// k_radix_scatter scans the digit counts with one digit per thread of its 256
+static_assert((1 << kRadixMaxBits) <= 256, "at most 256 digits per radix pass");
 constexpr int kRadixWaves = 4;                      // wavefronts per tile
 constexpr int kRadixIters = 16;                     // 64-element steps per wavefront
 constexpr int64_t kTile = 64 * kRadixWaves * kRadixIters;  // 4096 elements per tile
