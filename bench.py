@@ -51,10 +51,11 @@ def _stage_models(n, stats, pairs):
     return {
         # density: useful pairs x 11 flops, FP32 vector ALU
         "density": ("alu", pairs * FLOPS_PER_PAIR / 1e12, FP32_PEAK_TFLOPS, "TFLOP/s"),
-        # binning: read xyz 12 + sort key written and read once 16 + two sorted
-        # float4 records 32 + sub-cell index 2 = 62 B per particle, plus the
-        # cell offset 4 B per cell of the grid
-        "bin": ("hbm", (62.0 * n + 4.0 * ncell) / 1e9, HBM_PEAK_GBS, "GB/s"),
+        # binning: read xyz 12 + sort key written and read once 16 + three
+        # sorted float4 records (positions, cell-local, density operand) 48 +
+        # sub-cell index 2 = 78 B per particle, plus the cell offset 4 B per
+        # cell of the grid
+        "bin": ("hbm", (78.0 * n + 4.0 * ncell) / 1e9, HBM_PEAK_GBS, "GB/s"),
         # FoF: read float4 x2 + density for every particle (36 B), parent r/w 8 B
         "fof": ("hbm", 44.0 * n / 1e9, HBM_PEAK_GBS, "GB/s"),
     }
