@@ -290,22 +290,28 @@ __global__ __launch_bounds__(kBlock) void k_fof_dense(int64_t nchunks, Geo g,
     const float subb = g.cellb / (float)k;
     const int cx = (int)(c % (uint32_t)nc), cy = (int)((c / (uint32_t)nc) % (uint32_t)nc),
               cz = (int)(c / ((uint32_t)nc * (uint32_t)nc));
-    // stencil cells within reach of some lane: bit t for offset
-    // (t % 3 - 1, t / 3 % 3 - 1, t / 9 - 1)
-    uint32_t reach = 0;
-    for (int t = 0; t < 27; t++) {
-        const int ox = t % 3 - 1, oy = (t / 3) % 3 - 1, oz = t / 9 - 1;
-        const float gx = ox < 0 ? li.x : (ox > 0 ? g.cellb - li.x : 0.0f);
-        const float gy = oy < 0 ? li.y : (oy > 0 ? g.cellb - li.y : 0.0f);
-        const float gz = oz < 0 ? li.z : (oz > 0 ? g.cellb - li.z : 0.0f);
-        if (__ballot(active && gx * gx + gy * gy + gz * gz < g.l2b_hi)) reach |= 1u << t;
+    // chunk bounding box (active lanes), for the reach tests of stencil cells
+    // and sub-cells
+    float bx0 = active ? li.x : 1e30f, by0 = active ? li.y : 1e30f, bz0 = active ? li.z : 1e30f;
+    float bx1 = active ? li.x : -1e30f, by1 = active ? li.y : -1e30f, bz1 = active ? li.z : -1e30f;
+    for (int d = 32; d >= 1; d >>= 1) {
+        bx0 = fminf(bx0, __shfl_xor(bx0, d, 64));
+        by0 = fminf(by0, __shfl_xor(by0, d, 64));
+        bz0 = fminf(bz0, __shfl_xor(bz0, d, 64));
+        bx1 = fmaxf(bx1, __shfl_xor(bx1, d, 64));
+        by1 = fmaxf(by1, __shfl_xor(by1, d, 64));
+        bz1 = fmaxf(bz1, __shfl_xor(bz1, d, 64));
     }
-    // one stencil cell per lane: its range
+    // one stencil cell per lane (offset (t % 3 - 1, t / 3 % 3 - 1, t / 9 - 1)):
+    // its range, if it comes within l of the chunk's box
     const int tl = lane < 27 ? lane : 13;
     const int lx = tl % 3 - 1, ly = (tl / 3) % 3 - 1, lz = tl / 9 - 1;
     const uint32_t nbl = ((uint32_t)wrapc(cz + lz, nc) * (uint32_t)nc + (uint32_t)wrapc(cy + ly, nc)) *
                              (uint32_t)nc + (uint32_t)wrapc(cx + lx, nc);
-    const bool lreach = lane < 27 && ((reach >> lane) & 1u);
+    const float gx = lx < 0 ? bx0 : (lx > 0 ? g.cellb - bx1 : 0.0f);
+    const float gy = ly < 0 ? by0 : (ly > 0 ? g.cellb - by1 : 0.0f);
+    const float gz = lz < 0 ? bz0 : (lz > 0 ? g.cellb - bz1 : 0.0f);
+    const bool lreach = lane < 27 && gx * gx + gy * gy + gz * gz < g.l2b_hi;
     uint32_t la = 0, lb = 0;
     if (lreach) {
         la = off[nbl];
@@ -327,17 +333,6 @@ __global__ __launch_bounds__(kBlock) void k_fof_dense(int64_t nchunks, Geo g,
                         s_spre[wave], s_sla[wave]);
     if (nvisit == 0) return;
     __builtin_amdgcn_wave_barrier();
-    // chunk bounding box (active lanes), for sub-cell reach tests
-    float bx0 = active ? li.x : 1e30f, by0 = active ? li.y : 1e30f, bz0 = active ? li.z : 1e30f;
-    float bx1 = active ? li.x : -1e30f, by1 = active ? li.y : -1e30f, bz1 = active ? li.z : -1e30f;
-    for (int d = 32; d >= 1; d >>= 1) {
-        bx0 = fminf(bx0, __shfl_xor(bx0, d, 64));
-        by0 = fminf(by0, __shfl_xor(by0, d, 64));
-        bz0 = fminf(bz0, __shfl_xor(bz0, d, 64));
-        bx1 = fmaxf(bx1, __shfl_xor(bx1, d, 64));
-        by1 = fmaxf(by1, __shfl_xor(by1, d, 64));
-        bz1 = fmaxf(bz1, __shfl_xor(bz1, d, 64));
-    }
     // (visited dense cell, sub-cell) pairs, 64 at a time
     const int ntask = nvisit * nsub;
     for (int t0 = 0; t0 < ntask; t0 += 64) {
