@@ -156,14 +156,13 @@ __device__ __forceinline__ bool stream_range(int32_t *parent, const float *__res
 // All sparse neighbour cells of a chunk at once: lane t < 27 holds stencil
 // cell t's range [la, lb) and whether it is to be visited; their particles are
 // numbered through a prefix sum and loaded 64 at a time (each lane finds its
-// particle's cell in the per-wavefront table spre/sla), then broadcast in
-// order and joined to the lanes they link.
+// particle's cell by one walk over the cells that hold particles), then
+// broadcast in order and joined to the lanes they link.
 __device__ __forceinline__ void stream_sparse_cells(int32_t *parent, const float *__restrict__ dens_s,
                                                     const float4 *__restrict__ sloc,
                                                     const float4 *__restrict__ spos, const Geo &g,
                                                     bool active, const float4 &li, const float4 &pi,
-                                                    int &wr, bool visit, uint32_t la, uint32_t lb,
-                                                    int32_t *spre, int32_t *sla) {
+                                                    int &wr, bool visit, uint32_t la, uint32_t lb) {
     const int lane = threadIdx.x & 63;
     const int cntl = visit ? (int)(lb - la) : 0;
     int incl = cntl;
@@ -173,29 +172,28 @@ __device__ __forceinline__ void stream_sparse_cells(int32_t *parent, const float
     }
     const int P = lane_get(incl, 63);
     if (P == 0) return;
-    if (lane < 27) {
-        spre[lane] = cntl > 0 ? incl - cntl : 0x7fffffff;  // start of cell lane's particles
-        sla[lane] = (int)la;
-    }
-    __builtin_amdgcn_wave_barrier();
+    // the visited cells that hold particles (lane t for stencil cell t)
+    const uint64_t cells = __ballot(cntl > 0);
     for (int p0 = 0; p0 < P; p0 += 64) {
         const int p = p0 + lane;
         bool mem = false;
         uint32_t j = 0;
         float xj = 0.0f, yj = 0.0f, zj = 0.0f;
         int rj = -1;
-        if (p < P) {
-            // the visited cell whose particles include number p: the last
-            // stencil cell with start <= p (cells without particles never qualify)
-            int t = -1, best = -1;
-            for (int u = 0; u < 27; u++) {
-                const int st = spre[u];
-                if (st <= p && st >= best) {
-                    best = st;
-                    t = u;
-                }
+        // the visited cell whose particles include number p, found by one
+        // walk over the cells with particles (their starts are scalars)
+        int t = 0;
+        uint32_t jt = 0;
+        for (uint64_t m = cells; m; m &= m - 1) {
+            const int u = __builtin_ctzll(m);
+            const int st = lane_get(incl, u) - lane_get(cntl, u);
+            if (p >= st) {
+                t = u;
+                jt = lane_get(la, u) + (uint32_t)(p - st);
             }
-            j = (uint32_t)(sla[t] + (p - best));
+        }
+        if (p < P) {
+            j = jt;
             mem = is_member(dens_s, j, g.dl0);
             if (mem) {
                 const float4 lj = sloc[j];
@@ -270,7 +268,6 @@ __global__ __launch_bounds__(kBlock) void k_fof_dense(int64_t nchunks, Geo g,
                                                       int32_t *parent) {
     __shared__ int64_t dbase[kBlock / 64][27];  // visited dense cells: sub-table base
     __shared__ int8_t doff[kBlock / 64][27];    // and stencil index
-    __shared__ int32_t s_spre[kBlock / 64][27], s_sla[kBlock / 64][27];  // sparse neighbour cells
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t q = (int64_t)xcd_block() * (kBlock / 64) + wave;
     if (q >= nchunks) return;
@@ -329,8 +326,7 @@ __global__ __launch_bounds__(kBlock) void k_fof_dense(int64_t nchunks, Geo g,
     const uint64_t visit = __ballot(lvisit);
     const int nvisit = __popcll(visit);
     // sparse neighbour cells, all together
-    stream_sparse_cells(parent, dens_s, sloc, spos, g, active, li, pi, wr, lreach && !ldense && lb > la, la, lb,
-                        s_spre[wave], s_sla[wave]);
+    stream_sparse_cells(parent, dens_s, sloc, spos, g, active, li, pi, wr, lreach && !ldense && lb > la, la, lb);
     if (nvisit == 0) return;
     __builtin_amdgcn_wave_barrier();
     // (visited dense cell, sub-cell) pairs, 64 at a time
