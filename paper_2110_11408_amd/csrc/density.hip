@@ -21,7 +21,7 @@ namespace hf {
 namespace {
 
 // Accumulate one neighbour cell [a, b) for an i-particle at shifted local
-// coordinates (xs, ys, zs) (the sparse-cell kernel, one particle per lane).
+// coordinates (xs, ys, zs).  `a`, `b` are uniform in the dense kernel.
 __device__ __forceinline__ void accum_range(const float4 *__restrict__ sloc, uint32_t a, uint32_t b,
                                             float xs, float ys, float zs, double &acc) {
     for (uint32_t j0 = a; j0 < b; j0 += 64) {
