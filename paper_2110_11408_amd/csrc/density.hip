@@ -14,6 +14,8 @@
 // particle, the difference form d = x_j - x_i on the vector ALU.  Partial sums
 // run in FP32 over bounded stretches and are accumulated in FP64 in a fixed
 // order, so the result does not depend on the launch shape.
+#include <stdlib.h>
+
 #include "hf_internal.h"
 
 namespace hf {
@@ -527,11 +529,16 @@ void launch_density(int64_t n, const Geo &g, Work &w, float *dens_out, hipStream
     // radix key array that binning no longer needs
     uint64_t *dfx = w.rkey[0];
     if (w.nsparse > 0) fill_u32(reinterpret_cast<uint32_t *>(dfx), 0u, 2 * w.nsparse, s);
-    if (w.nchunks > 0)
-        hipLaunchKernelGGL(k_density_dense, dim3((unsigned)w.nchunks), dim3(64), 0, s, w.nchunks, g,
-                           (n + 32) * 16 <= (int64_t)0xffffff00, w.chunks, w.sloc, w.pq, w.spos, w.off,
-                           w.s_sparse, dfx, w.dens_s,
-                           dens_out);
+    if (w.nchunks > 0) {
+        // one buffer descriptor for all record loads while the byte offsets
+        // fit in 32 bits; HF_DENSITY_WIDE=1 forces the per-block descriptors
+        // of larger inputs (used by tests)
+        bool narrow = (n + 32) * 16 <= (int64_t)0xffffff00;
+        const char *force = getenv("HF_DENSITY_WIDE");
+        if (force && force[0] == '1') narrow = false;
+        hipLaunchKernelGGL(k_density_dense, dim3((unsigned)w.nchunks), dim3(64), 0, s, w.nchunks, g, narrow,
+                           w.chunks, w.sloc, w.pq, w.spos, w.off, w.s_sparse, dfx, w.dens_s, dens_out);
+    }
     if (w.nsparse > 0)
         hipLaunchKernelGGL(k_density_sparse, dim3((unsigned)((w.nsparse + kBlock - 1) / kBlock)),
                            dim3(kBlock), 0, s, w.nsparse, g, w.sparse, w.sloc, w.spos, w.off, dfx, w.dens_s,

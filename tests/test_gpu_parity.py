@@ -290,6 +290,23 @@ def test_separate_payload_sort_gives_same_result(ctx):
                                      "ienc": b["table"]["n_enclosed"]}})
 
 
+def test_density_wide_record_loads_give_same_result(ctx):
+    """The dense-cell density loads its records through one buffer descriptor
+    while the byte offsets fit in 32 bits (below about 2.7e8 particles), else
+    through a descriptor per block; both forms give bit-identical densities."""
+    import os
+    pos, L, _ = _case("s40123")
+    a = gpu_find(ctx, pos, box=L)
+    os.environ["HF_DENSITY_WIDE"] = "1"
+    try:
+        b = gpu_find(ctx, pos, box=L)
+    finally:
+        del os.environ["HF_DENSITY_WIDE"]
+    np.testing.assert_array_equal(a["density"], b["density"])
+    np.testing.assert_array_equal(a["l0"], b["l0"])
+    np.testing.assert_array_equal(a["halo_id"], b["halo_id"])
+
+
 def _many_peaks_box(radius, grid, seed):
     """A uniform background with one ball at 100x the mean density (a single L0
     group) holding a grid of compact 30-particle clumps 0.85 apart: every clump
