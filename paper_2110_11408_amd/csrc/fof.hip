@@ -72,7 +72,7 @@ __device__ __forceinline__ bool linked(float xs, float ys, float zs, const float
                                        uint32_t b, const Geo &g) {
     const float4 lb = sloc[b];
     const float dx = lb.x - xs, dy = lb.y - ys, dz = lb.z - zs;
-    const float d2f = dx * dx + dy * dy + dz * dz;
+    const float d2f = d2_f32(dx, dy, dz);
     if (d2f >= g.l2b_hi) return false;
     if (d2f < g.l2b_lo) return true;
     return d2_exact(pa, spos[b], g.L, g.half) < g.l2;
@@ -113,7 +113,7 @@ __device__ __forceinline__ int join_lanes(int32_t *parent, bool lk, int &wr, int
 // undecided band.
 __device__ __forceinline__ bool linked_d(float dx, float dy, float dz, const float4 &pa,
                                          const float4 *__restrict__ spos, uint32_t b, const Geo &g) {
-    const float d2f = dx * dx + dy * dy + dz * dz;
+    const float d2f = d2_f32(dx, dy, dz);
     if (d2f >= g.l2b_hi) return false;
     if (d2f < g.l2b_lo) return true;
     return d2_exact(pa, spos[b], g.L, g.half) < g.l2;
@@ -134,18 +134,20 @@ __device__ __forceinline__ bool stream_range(int32_t *parent, const float *__res
     const float xs = li.x - (float)ox * g.cellb, ys = li.y - (float)oy * g.cellb,
                 zs = li.z - (float)oz * g.cellb;
     const bool want = active && wr != rset;
-    bool any = false;
+    // the smallest FP32 squared distance to a member (one minimum per member,
+    // no branch); only a lane whose minimum falls in the prefilter's
+    // undecided band repeats the range with the canonical FP64 distance
+    float mind = 3.0e38f;
     for (uint32_t j = a; j < b; j++) {
         if (!is_member(dens_s, j, g.dl0)) continue;
         const float4 lj = sloc[j];
         const float dx = lj.x - xs, dy = lj.y - ys, dz = lj.z - zs;
-        const float d2f = dx * dx + dy * dy + dz * dz;
-        if (d2f < g.l2b_lo) {
-            any = true;
-        } else if (d2f < g.l2b_hi && want && !any) {
-            // the undecided band: canonical FP64 distance
-            if (d2_exact(pi, spos[j], g.L, g.half) < g.l2) any = true;
-        }
+        mind = fminf(mind, d2_f32(dx, dy, dz));
+    }
+    bool any = mind < g.l2b_lo;
+    if (want && !any && mind < g.l2b_hi) {
+        for (uint32_t j = a; j < b && !any; j++)
+            if (is_member(dens_s, j, g.dl0) && d2_exact(pi, spos[j], g.L, g.half) < g.l2) any = true;
     }
     const bool lk = want && any;
     if (!__ballot(lk)) return false;

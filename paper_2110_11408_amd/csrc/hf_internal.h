@@ -88,6 +88,12 @@ __device__ __forceinline__ unsigned xcd_block() {
     return start + k;
 }
 
+// FP32 squared distance for the prefilters (one multiply and two fused
+// multiply-adds); their margins are far above the rounding of either form.
+__device__ __forceinline__ float d2_f32(float dx, float dy, float dz) {
+    return fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+}
+
 // Value of lane L (L wave-uniform): a v_readlane into a scalar register,
 // without the LDS round trip of a general shuffle.
 __device__ __forceinline__ int lane_get(int v, int L) { return __builtin_amdgcn_readlane(v, L); }
