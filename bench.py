@@ -46,7 +46,7 @@ WORKLOADS = {
 
 
 def _stage_models(n, stats, pairs):
-    """Algorithmic work per launch of each stage (roofline)."""
+    """Algorithmic work per launch of each stage (bound, work, peak, unit)."""
     ncell = stats["n_cells"]
     return {
         # density: useful pairs x 11 flops, FP32 vector ALU
@@ -311,8 +311,8 @@ def main():
         print(json.dumps(t))
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (this build is "
-              "single-GPU: the sharded design is described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the library runs "
+              "each box on a single device", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
