@@ -23,16 +23,19 @@ namespace hf {
 namespace {
 
 // Accumulate one neighbour cell [a, b) for an i-particle at shifted local
-// coordinates (xs, ys, zs).  `a`, `b` are uniform in the dense kernel.
+// coordinates (xs, ys, zs) (the sparse-cell kernel, one particle per lane).
+// Two neighbours per step keep that kernel at eight wavefronts per SIMD; it
+// waits on memory, and the extra wavefronts hide more than four loads in
+// flight per lane would.
 __device__ __forceinline__ void accum_range(const float4 *__restrict__ sloc, uint32_t a, uint32_t b,
                                             float xs, float ys, float zs, double &acc) {
     for (uint32_t j0 = a; j0 < b; j0 += 64) {
         const uint32_t e = min(j0 + 64u, b);
         float p = 0.0f;
         uint32_t j = j0;
-        for (; j + 4 <= e; j += 4) {
+        for (; j + 2 <= e; j += 2) {
 #pragma unroll
-            for (int u = 0; u < 4; u++) {
+            for (int u = 0; u < 2; u++) {
                 const float4 lj = sloc[j + u];
                 const float dx = lj.x - xs, dy = lj.y - ys, dz = lj.z - zs;
                 float t = fmaf(-dx, dx, 1.0f);
