@@ -228,13 +228,15 @@ __device__ bool has_denser_within_b(int i, int tt0, int tt1, const Geo &g, const
             continue;
         }
         const int64_t base = (int64_t)cellmap[nb] * (nsub + 1);
-        for (int s0 = 0; s0 < nsub; s0 += 9) {
-            // nine sub-cell maxima per round of loads
-            uint64_t mx[9];
+        for (int s0 = 0; s0 < nsub; s0 += 3) {
+            // three sub-cell maxima per round of loads (small batches keep the
+            // thread-per-case kernel at 74 VGPRs: it waits on memory, and
+            // six wavefronts per SIMD hide more than longer batches would)
+            uint64_t mx[3];
 #pragma unroll
-            for (int u = 0; u < 9; u++) mx[u] = s0 + u < nsub ? submax[base + s0 + u] : 0ull;
+            for (int u = 0; u < 3; u++) mx[u] = s0 + u < nsub ? submax[base + s0 + u] : 0ull;
 #pragma unroll
-            for (int u = 0; u < 9; u++) {
+            for (int u = 0; u < 3; u++) {
                 const int s2 = s0 + u;
                 if (!(mx[u] > mykey)) continue;
                 const int sx = s2 % k, sy = (s2 / k) % k, sz = s2 / (k * k);
@@ -244,15 +246,15 @@ __device__ bool has_denser_within_b(int i, int tt0, int tt1, const Geo &g, const
                 if (ex * ex + ey * ey + ez * ez >= g.b2b_hi) continue;
                 const int32_t top = subarg[base + s2];
                 if (denser_within_b(top, dens_s, gkey, sloc, spos, key, di, oi, xs, ys, zs, pi, g)) return true;
-                // the rest of the sub-cell: densities 16 at a time, then the
+                // the rest of the sub-cell: densities 8 at a time, then the
                 // denser ones in full
                 const uint32_t u1 = subtab[base + s2 + 1];
-                for (uint32_t j0 = subtab[base + s2]; j0 < u1; j0 += 16) {
-                    float dj[16];
+                for (uint32_t j0 = subtab[base + s2]; j0 < u1; j0 += 8) {
+                    float dj[8];
 #pragma unroll
-                    for (int v = 0; v < 16; v++) dj[v] = j0 + v < u1 ? dens_s[j0 + v] : -1.0f;
+                    for (int v = 0; v < 8; v++) dj[v] = j0 + v < u1 ? dens_s[j0 + v] : -1.0f;
 #pragma unroll
-                    for (int v = 0; v < 16; v++) {
+                    for (int v = 0; v < 8; v++) {
                         const uint32_t j = j0 + v;
                         if (dj[v] < di || (int32_t)j == top || (int)j == i) continue;
                         if (denser_within_b(j, dens_s, gkey, sloc, spos, key, di, oi, xs, ys, zs, pi, g))

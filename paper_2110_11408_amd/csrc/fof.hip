@@ -407,8 +407,10 @@ __global__ __launch_bounds__(kBlock) void k_fof_sparse_list(int64_t nsparse, con
 // links to the later members of sparse neighbour cells (pairs with dense cells
 // are found by the dense chunks).  The offsets of a stencil plane are loaded
 // together.  The list fills only the first blocks of the grid, which the plain
-// block order spreads over all XCDs.
-__global__ __launch_bounds__(kBlock) void k_fof_sparse(const uint32_t *__restrict__ count_p, Geo g,
+// block order spreads over all XCDs.  The kernel waits on memory: it is held
+// to 64 VGPRs (eight wavefronts per SIMD; the compiler fits it without
+// spilling).
+__global__ __launch_bounds__(kBlock, 8) void k_fof_sparse(const uint32_t *__restrict__ count_p, Geo g,
                                                        const int32_t *__restrict__ sparse,
                                                        const float4 *__restrict__ sloc,
                                                        const float4 *__restrict__ spos,
