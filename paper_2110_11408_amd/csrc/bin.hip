@@ -7,7 +7,7 @@
 //   1. key = cell * k^3 + sub-cell per particle (range check of the input);
 //   2. least-significant-digit radix sort of (key, original index), digits of
 //      at most 8 bits; key and index share one 64-bit word when they fit.
-//      Each pass: a block counts the digits of its tile of 4096 consecutive
+//      Each pass: a block counts the digits of its tile of 2048 consecutive
 //      elements; an exclusive scan of the digit-major [digit][tile] counts
 //      gives every (digit, tile) its output offset; the tile is then walked
 //      again in order, each element's rank among equal digits coming from the
@@ -74,8 +74,10 @@ constexpr int kRadixMaxBits = 8;
 // k_radix_scatter scans the digit counts with one digit per thread of its 256
 static_assert((1 << kRadixMaxBits) <= 256, "at most 256 digits per radix pass");
 constexpr int kRadixWaves = 4;                      // wavefronts per tile
-constexpr int kRadixIters = 16;                     // 64-element steps per wavefront
-constexpr int64_t kTile = 64 * kRadixWaves * kRadixIters;  // 4096 elements per tile
+constexpr int kRadixIters = 8;                      // 64-element steps per wavefront
+// 2048 elements per tile: the scatter's LDS tile (16 KB of keys) then lets
+// seven blocks share a CU, twice as many as with 4096
+constexpr int64_t kTile = 64 * kRadixWaves * kRadixIters;
 
 // Lanes holding the same D-bit digit as this lane (within `active`).
 __device__ __forceinline__ uint64_t digit_peers(uint32_t d, int D, uint64_t active) {
@@ -92,8 +94,8 @@ __device__ __forceinline__ uint64_t lanes_below(int lane) {
 }
 
 // Digit counts of one tile, stored digit-major ([digit][tile]).  Wavefront w
-// of the tile owns elements [w * 1024, (w + 1) * 1024) of it and loads all 16
-// of its steps before counting.
+// of the tile owns elements [w * 512, (w + 1) * 512) of it and loads all 8 of
+// its steps before counting.
 __global__ __launch_bounds__(256) void k_radix_count(const uint64_t *__restrict__ key, int64_t n, int shift,
                                                      int D, int64_t ntiles, uint32_t *__restrict__ hist) {
     __shared__ uint32_t h[1 << kRadixMaxBits];
