@@ -103,7 +103,8 @@ __device__ __forceinline__ void density_chunk(const Geo &g, uint32_t h, uint32_t
                                               const uint32_t *__restrict__ off,
                                               const uint32_t *__restrict__ s_sparse,
                                               uint64_t *__restrict__ dfx, float *__restrict__ dens_s,
-                                              float *__restrict__ dens_out, float (*colsum)[64]) {
+                                              float *__restrict__ dens_out, float (*colsum)[16],
+                                              float *__restrict__ cl) {
     const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
     const int loff = 4 * col + grp;  // this lane's word of a block of 16 pq records
     // this lane's word of the block of 16 records from j0, as a buffer load
@@ -127,7 +128,14 @@ __device__ __forceinline__ void density_chunk(const Geo &g, uint32_t h, uint32_t
     // past the chunk get A = (0, 0, 0, 1) and -1, so all their weights clamp
     // to exactly 0
     float A[R];
-    f32x4 C[R];
+    // the accumulator inputs 1 - |x_i|^2 stay in LDS (read once per stencil
+    // cell), which keeps the kernel at six wavefronts per SIMD
+    auto Cget = [&](int r) -> f32x4 {
+        f32x4 v;
+#pragma unroll
+        for (int u = 0; u < 4; u++) v[u] = cl[(4 * r + u) * 64 + lane];
+        return v;
+    };
 #pragma unroll
     for (int r = 0; r < R; r++) {
         const uint32_t ir = h + 16u * (uint32_t)r + (uint32_t)col;
@@ -137,7 +145,7 @@ __device__ __forceinline__ void density_chunk(const Geo &g, uint32_t h, uint32_t
         for (int u = 0; u < 4; u++) {
             const uint32_t iu = h + 16u * (uint32_t)r + 4u * (uint32_t)grp + (uint32_t)u;
             const float q = pq[4 * (size_t)min(iu, end - 1u) + 3];
-            C[r][u] = iu < end ? 1.0f + q : -1.0f;
+            cl[(4 * r + u) * 64 + lane] = iu < end ? 1.0f + q : -1.0f;
         }
     }
     // neighbour ranges, one per lane: lanes 0..26 the stencil cells (lane
@@ -211,7 +219,7 @@ __device__ __forceinline__ void density_chunk(const Geo &g, uint32_t h, uint32_t
         const float bv = (grp == 3 && (uint32_t)col >= cend - j0) ? -1e30f : val;
 #pragma unroll
         for (int r = 0; r < R; r++) {
-            f32x4 cin = C[r];
+            f32x4 cin = Cget(r);
             if (r == rd) {
 #pragma unroll
                 for (int u = 0; u < 4; u++) cin[u] = dv == u ? -1e30f : cin[u];
@@ -239,7 +247,7 @@ __device__ __forceinline__ void density_chunk(const Geo &g, uint32_t h, uint32_t
 #pragma unroll
             for (int r = 0; r < R; r++) {
                 As[r] = grp == 3 ? 1.0f : A[r] - (sg + sg);
-                Cs[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[r], bs, C[r], 0, 0, 0);
+                Cs[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[r], bs, Cget(r), 0, 0, 0);
             }
         };
         setup(k);
@@ -250,8 +258,9 @@ __device__ __forceinline__ void density_chunk(const Geo &g, uint32_t h, uint32_t
             const float bv = (grp == 3 && (uint32_t)col >= rem) ? -1e30f : val;
             if (sparse) {
                 // sparse cell: the column's weights also go to its particle.
-                // Each lane keeps the sum of its column entries (a fixed
-                // tree) in LDS; the four row groups are added at the end.
+                // Each lane sums its column entries (a fixed tree), the four
+                // row groups are added by two exchanges, and the column's
+                // total waits in LDS for the atomics after the last block.
                 float part[R];
 #pragma unroll
                 for (int r = 0; r < R; r++) {
@@ -268,7 +277,9 @@ __device__ __forceinline__ void density_chunk(const Geo &g, uint32_t h, uint32_t
                 if (R == 2) cs = part[0] + part[1];
                 if (R == 3) cs = (part[0] + part[1]) + part[2];
                 if (R == 4) cs = (part[0] + part[1]) + (part[2] + part[3]);
-                colsum[k][lane] = cs;
+                cs += __shfl_xor(cs, 16);
+                cs += __shfl_xor(cs, 32);
+                if (grp == 0) colsum[k][col] = cs;
             } else {
 #pragma unroll
                 for (int r = 0; r < R; r++) {
@@ -299,10 +310,11 @@ __device__ __forceinline__ void density_chunk(const Geo &g, uint32_t h, uint32_t
                 }
             }
         };
-        // Blocks go in batches of four: the loads of the next batch are
+        // Blocks go in batches of two: the loads of the next batch are
         // issued before the current one is summed (two register sets in
-        // turn).  A position past the stream's end loads the chunk's own
-        // first block instead and is skipped.
+        // turn; longer batches would cost the sixth wavefront per SIMD).  A
+        // position past the stream's end loads the chunk's own first block
+        // instead and is skipped.
         bool sparse = ((spm >> k) & 1ull) != 0;  // the current range is a sparse cell
         auto use = [&](int bk, uint32_t bj, float v) {
             if (bk < 0) return;
@@ -314,30 +326,31 @@ __device__ __forceinline__ void density_chunk(const Geo &g, uint32_t h, uint32_t
             }
             block(bj, b, k, sparse, v);
         };
-        int ka[4], kb[4];
-        uint32_t ja[4], jb[4];
-        float va[4], vb[4];
+        constexpr int kB = 2;  // blocks per batch
+        int ka[kB], kb[kB];
+        uint32_t ja[kB], jb[kB];
+        float va[kB], vb[kB];
 #pragma unroll
-        for (int t = 0; t < 4; t++) {
+        for (int t = 0; t < kB; t++) {
             gen(ka[t], ja[t]);
             va[t] = ld(ka[t] >= 0 ? ja[t] : h);
         }
         while (true) {
 #pragma unroll
-            for (int t = 0; t < 4; t++) {
+            for (int t = 0; t < kB; t++) {
                 gen(kb[t], jb[t]);
                 vb[t] = ld(kb[t] >= 0 ? jb[t] : h);
             }
 #pragma unroll
-            for (int t = 0; t < 4; t++) use(ka[t], ja[t], va[t]);
+            for (int t = 0; t < kB; t++) use(ka[t], ja[t], va[t]);
             if (kb[0] < 0) break;
 #pragma unroll
-            for (int t = 0; t < 4; t++) {
+            for (int t = 0; t < kB; t++) {
                 gen(ka[t], ja[t]);
                 va[t] = ld(ka[t] >= 0 ? ja[t] : h);
             }
 #pragma unroll
-            for (int t = 0; t < 4; t++) use(kb[t], jb[t], vb[t]);
+            for (int t = 0; t < kB; t++) use(kb[t], jb[t], vb[t]);
             if (ka[0] < 0) break;
         }
     }
@@ -367,7 +380,7 @@ __device__ __forceinline__ void density_chunk(const Geo &g, uint32_t h, uint32_t
             pre += cnt;
         }
         if (q < ntot) {
-            const float v = (colsum[kk][cc] + colsum[kk][cc + 16]) + (colsum[kk][cc + 32] + colsum[kk][cc + 48]);
+            const float v = colsum[kk][cc];
             if (v > 0.0f)
                 atomicAdd(reinterpret_cast<unsigned long long *>(&dfx[dst]),
                           (unsigned long long)__double2ll_rn((double)v * kFixScale));
@@ -386,7 +399,7 @@ __device__ __forceinline__ void density_chunk(const Geo &g, uint32_t h, uint32_t
 
 // One wavefront per workgroup: chunk costs differ widely, and a finished
 // wavefront frees its slot at once.
-__global__ __launch_bounds__(64) void k_density_dense(int64_t nchunks, Geo g, bool narrow,
+__global__ __launch_bounds__(64, 6) void k_density_dense(int64_t nchunks, Geo g, bool narrow,
                                                       const int32_t *__restrict__ chunks,
                                                       const float4 *__restrict__ sloc,
                                                       const float4 *__restrict__ pq,
@@ -403,11 +416,13 @@ __global__ __launch_bounds__(64) void k_density_dense(int64_t nchunks, Geo g, bo
     const uint32_t cend = __builtin_amdgcn_readfirstlane(off[c + 1]);
     const uint32_t end = min(h + 64u, cend);
     const float *p = reinterpret_cast<const float *>(pq);
-    // per-lane column sums of the sparse neighbour cells
-    __shared__ float cs[27][64];
+    // column sums of the sparse neighbour cells, and the rows' accumulator
+    // inputs
+    __shared__ float cs[27][16];
+    __shared__ float cl[16 * 64];
 #define HF_DENSITY_CHUNK(RR)                                                                            \
-    (narrow ? density_chunk<RR, true>(g, h, c, end, p, spos, off, s_sparse, dfx, dens_s, dens_out, cs) \
-            : density_chunk<RR, false>(g, h, c, end, p, spos, off, s_sparse, dfx, dens_s, dens_out, cs))
+    (narrow ? density_chunk<RR, true>(g, h, c, end, p, spos, off, s_sparse, dfx, dens_s, dens_out, cs, cl) \
+            : density_chunk<RR, false>(g, h, c, end, p, spos, off, s_sparse, dfx, dens_s, dens_out, cs, cl))
     switch ((end - h + 15u) >> 4) {
     case 1: HF_DENSITY_CHUNK(1); break;
     case 2: HF_DENSITY_CHUNK(2); break;
