@@ -271,7 +271,7 @@ __global__ __launch_bounds__(kBlock) void k_fof_dense(int64_t nchunks, Geo g,
     __shared__ int64_t dbase[kBlock / 64][27];  // visited dense cells: sub-table base
     __shared__ int8_t doff[kBlock / 64][27];    // and stencil index
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t q = (int64_t)xcd_block() * (kBlock / 64) + wave;
+    const int64_t q = (int64_t)xcd_block() * (int64_t)(blockDim.x >> 6) + wave;
     if (q >= nchunks) return;
     const int lane = threadIdx.x & 63;
     const uint32_t h = (uint32_t)__builtin_amdgcn_readfirstlane(chunks[q]);
@@ -561,7 +561,9 @@ void launch_fof(int64_t n, const Geo &g, Work &w, hipStream_t s) {
     hipLaunchKernelGGL(k_fof_phase_a, grid(n), dim3(kBlock), 0, s, n, g, w.sloc, w.f_sparse, w.ssub, w.cnt,
                        w.subtab, w.dens_s, w.parent);
     if (w.nchunks > 0)
-        hipLaunchKernelGGL(k_fof_dense, dim3((unsigned)((w.nchunks + 3) / 4)), dim3(kBlock), 0, s, w.nchunks, g,
+        // one wavefront per workgroup: chunk costs differ widely, and a
+        // finished wavefront's slot is free at once
+        hipLaunchKernelGGL(k_fof_dense, dim3((unsigned)w.nchunks), dim3(64), 0, s, w.nchunks, g,
                            w.chunks, w.sloc, w.spos, w.off, w.cnt, w.subtab, w.dens_s, w.parent);
     if (w.nsparse > 0) {
         // sparse members: flags, positions and list in arrays that are free
