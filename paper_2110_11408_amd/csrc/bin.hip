@@ -391,20 +391,16 @@ __global__ __launch_bounds__(kBlock) void k_bin_lists(int64_t n, const uint32_t 
     }
 }
 
-// Sub-cell table of the dense cells, one wavefront per cell: entry s of cell
-// d is the first particle of the cell whose sub-cell is s or later, that is
-// the cell start plus the number of its particles in sub-cells below s (an
-// empty sub-cell gets the start of the next non-empty one; entry nsub is the
-// cell end).  The cell's particles are sorted by sub-cell; each 64-particle
-// step counts, for 64 values of s at a time, the particles below s by ballot.
-__global__ __launch_bounds__(kBlock) void k_sub_table(int64_t ndc, int nsub,
-                                                      const uint32_t *__restrict__ dcells,
-                                                      const uint32_t *__restrict__ off,
-                                                      const uint16_t *__restrict__ ssub,
-                                                      uint32_t *__restrict__ subtab) {
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t d = (int64_t)blockIdx.x * (kBlock / 64) + wave;
-    if (d >= ndc) return;
+// Sub-cell table of one dense cell d, by one wavefront: entry s is the first
+// particle of the cell whose sub-cell is s or later, that is the cell start
+// plus the number of its particles in sub-cells below s (an empty sub-cell
+// gets the start of the next non-empty one; entry nsub is the cell end).  The
+// cell's particles are sorted by sub-cell; each 64-particle step counts, for
+// 64 values of s at a time, the particles below s by ballot.
+__device__ __forceinline__ void sub_table_cell(int64_t d, int nsub, const uint32_t *__restrict__ dcells,
+                                               const uint32_t *__restrict__ off,
+                                               const uint16_t *__restrict__ ssub,
+                                               uint32_t *__restrict__ subtab) {
     const int lane = threadIdx.x & 63;
     const uint32_t c = (uint32_t)__builtin_amdgcn_readfirstlane(dcells[d]);
     const uint32_t a = (uint32_t)__builtin_amdgcn_readfirstlane(off[c]);
@@ -423,6 +419,20 @@ __global__ __launch_bounds__(kBlock) void k_sub_table(int64_t ndc, int nsub,
         }
         if (lane < ns) t[s0 + lane] = a + below;
     }
+}
+
+// The sub-cell tables of all dense cells, one wavefront per cell over a grid
+// that strides the cells; the cell count *ndc_p is read on the device.
+__global__ __launch_bounds__(kBlock) void k_sub_table(const uint32_t *__restrict__ ndc_p, int nsub,
+                                                      const uint32_t *__restrict__ dcells,
+                                                      const uint32_t *__restrict__ off,
+                                                      const uint16_t *__restrict__ ssub,
+                                                      uint32_t *__restrict__ subtab) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t ndc = *ndc_p;
+    const int64_t stride = (int64_t)gridDim.x * (kBlock / 64);
+    for (int64_t d = (int64_t)blockIdx.x * (kBlock / 64) + wave; d < ndc; d += stride)
+        sub_table_cell(d, nsub, dcells, off, ssub, subtab);
 }
 
 }  // namespace
@@ -522,11 +532,16 @@ void launch_bin(const float *pos, int64_t n, const Geo &g, Work &w, hipStream_t 
                        w.sparse, w.cnt);
 }
 
-void launch_subtab(int64_t, int64_t ndc, const Geo &g, Work &w, hipStream_t s) {
-    if (ndc <= 0) return;
+void launch_subtab(int64_t n, const uint32_t *ndc_p, const Geo &g, Work &w, hipStream_t s) {
+    if (n <= 0) return;
     const int nsub = g.ksub * g.ksub * g.ksub;
-    hipLaunchKernelGGL(k_sub_table, dim3((unsigned)((ndc + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), 0, s,
-                       ndc, nsub, w.dcells, w.off, w.ssub, w.subtab);
+    // the count is read on the device; a dense cell holds at least kDenseMin
+    // particles, and a grid of at most 16384 workgroups strides over the cells
+    const int64_t ub = n / kDenseMin + 1;
+    int64_t blocks = (ub + kBlock / 64 - 1) / (kBlock / 64);
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_sub_table, dim3((unsigned)blocks), dim3(kBlock), 0, s, ndc_p, nsub, w.dcells, w.off,
+                       w.ssub, w.subtab);
 }
 
 }  // namespace hf

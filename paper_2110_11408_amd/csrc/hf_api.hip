@@ -341,16 +341,27 @@ hf_status begin(Lane *c, const float *pos, int64_t n, const hf_params *p, Geo *g
     HIP_OK(c, hipEventRecord(c->ev[0], s));
     hf::launch_bin(pos, n, *g, *w, s);
     // dense chunks, dense cells, sparse particles, and the range flag of the
-    // positions (binning clamps cells, so nothing it wrote is out of bounds)
+    // positions (binning clamps cells, so nothing it wrote is out of bounds).
+    // The sub-cell tables take their cell count on the device and are
+    // enqueued before the host waits for these words, so the device keeps
+    // working while the host reads them and enqueues the next stage.
+    hf::WordSrc src{};
+    src.p[0] = w->s_chunk + n;
+    src.p[1] = w->s_dcell + n;
+    src.p[2] = w->s_sparse + n;
+    src.p[3] = reinterpret_cast<const uint32_t *>(w->err);
+    HIP_OK(c, hf::publish_words(src, 4, c->host, s));
+    HIP_OK(c, hipEventRecord(c->pub, s));
+    hf::launch_subtab(n, w->s_dcell + n, *g, *w, s);
+    HIP_OK(c, hipEventSynchronize(c->pub));
     uint32_t counts[4];
-    st = read_dev(c, s, {w->s_chunk + n, w->s_dcell + n, w->s_sparse + n, w->err}, counts);
-    if (st == HF_OK) st = err_status(c, counts[3]);
+    hf::collect_words(c->host, 4, counts);
+    st = err_status(c, counts[3]);
     if (st != HF_OK) return st;
     w->nchunks = counts[0];
     w->ndcells = counts[1];
     w->nsparse = counts[2];
     w->nhard = 0;
-    hf::launch_subtab(n, w->ndcells, *g, *w, s);
     HIP_OK(c, hipEventRecord(c->ev[1], s));
     return HF_OK;
 }
@@ -369,6 +380,7 @@ hf_status lane_init(Lane *L, int device, bool own_stream) {
     }
     for (auto &e : L->ev)
         if (hipEventCreate(&e) != hipSuccess) return HF_ERR_DEVICE;
+    if (hipEventCreateWithFlags(&L->pub, hipEventDisableTiming) != hipSuccess) return HF_ERR_DEVICE;
     if (own_stream && hipStreamCreateWithFlags(&L->stream, hipStreamNonBlocking) != hipSuccess)
         return HF_ERR_DEVICE;
     return HF_OK;
@@ -389,6 +401,8 @@ void lane_destroy(Lane *L) {
     L->host = nullptr;
     for (auto &e : L->ev)
         if (e) (void)hipEventDestroy(e);
+    if (L->pub) (void)hipEventDestroy(L->pub);
+    L->pub = nullptr;
     if (L->stream) (void)hipStreamDestroy(L->stream);
     L->stream = nullptr;
 }

@@ -192,6 +192,11 @@ struct WordSrc {
 // (at least kMax words), the stream is synchronized and out[0..k) receives
 // the values: one dispatch and one wait for all the counts a step needs.
 hipError_t read_words(const WordSrc &src, int k, uint32_t *host, uint32_t *out, hipStream_t s);
+// The same in two halves: the copy is enqueued on s, and the words are read
+// once the caller has waited for it (an event recorded right after it), so
+// that later work can be enqueued first.
+hipError_t publish_words(const WordSrc &src, int k, uint32_t *host, hipStream_t s);
+void collect_words(const uint32_t *host, int k, uint32_t *out);
 void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 // Exclusive scan: out[0..n] with out[n] = total.  tmp: scan_tmp_words(n) words.
@@ -211,7 +216,7 @@ int64_t radix_hist_len(int64_t n, const Geo &g);
 // using b[] as the second buffer and w's count arrays; returns the buffer
 // (a or b) that holds the result.
 uint64_t *radix_sort_keys(uint64_t *a, uint64_t *b, int64_t n, int lo, int bits, Work &w, hipStream_t s);
-void launch_subtab(int64_t n, int64_t ndc, const Geo &g, Work &w, hipStream_t s);
+void launch_subtab(int64_t n, const uint32_t *ndc_p, const Geo &g, Work &w, hipStream_t s);
 void launch_density(int64_t n, const Geo &g, Work &w, float *dens_out, hipStream_t s);
 void launch_count_pairs(int64_t n, const Geo &g, Work &w, unsigned long long *total, hipStream_t s);
 void launch_gather_density(const float *dens_in, int64_t n, Work &w, hipStream_t s);

@@ -23,6 +23,7 @@ struct Lane {
     std::string err;
     hipStream_t stream = nullptr;  // owned; null for a context's main lane
     uint32_t *host = nullptr;      // pinned, coherent host words for count read-backs
+    hipEvent_t pub = nullptr;      // marks a copy into host whose words are read while later work runs
 };
 
 // Create the events, the pinned host words (and a non-blocking stream of

@@ -186,14 +186,22 @@ void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
     fill_u32(reinterpret_cast<uint32_t *>(p), (uint32_t)v, n, s);
 }
 
-hipError_t read_words(const WordSrc &src, int k, uint32_t *host, uint32_t *out, hipStream_t s) {
+hipError_t publish_words(const WordSrc &src, int k, uint32_t *host, hipStream_t s) {
     if (k < 1 || k > WordSrc::kMax) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, src, k, host);
-    hipError_t e = hipGetLastError();
+    return hipGetLastError();
+}
+
+void collect_words(const uint32_t *host, int k, uint32_t *out) {
+    for (int i = 0; i < k; i++) out[i] = __atomic_load_n(host + i, __ATOMIC_ACQUIRE);
+}
+
+hipError_t read_words(const WordSrc &src, int k, uint32_t *host, uint32_t *out, hipStream_t s) {
+    hipError_t e = publish_words(src, k, host, s);
     if (e != hipSuccess) return e;
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return e;
-    for (int i = 0; i < k; i++) out[i] = __atomic_load_n(host + i, __ATOMIC_ACQUIRE);
+    collect_words(host, k, out);
     return hipSuccess;
 }
 
