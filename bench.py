@@ -1,22 +1,26 @@
 """Benchmark of the CompaSO group-finding pass on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload plain256]
-                [--no-cpu-baseline] [--cpu-seconds S] [--no-batched] [--no-serving]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batched96]
+                [--no-cpu-baseline] [--cpu-seconds S] [--no-plain256] [--no-serving]
+                [--large] [--only-steps] [--lanes L]
 
-A step is one hf_find call (binning, kernel density, L0 FoF, CompaSO L1 and the
-output cut) over the whole box, with positions already resident in HBM.  Prints
-one JSON line with whole-job throughput in particles/s, the roofline of the
-dominant kernel (its average duration measured with HIP events on the stream it
-runs on, over the timed steps) and the FP64 CPU oracle timed on a bounded
-sample of the same generator.
-
-The same box also times hf_halo_stats (level 2 inside every L1 halo and the
-position statistics).  Two more workloads are reported in the same line:
-  batched  96 periodic sub-boxes of side log-uniform in 24..160 in one
-           hf_find_batch call, against one hf_find call per box;
-  serving  a Poisson stream of requests (boxes of 1e4..1e7 particles, log-uniform,
-           halo fraction 0.3..0.7) through hf_server, host arrays in and out,
-           against the same requests run one at a time on hf_find.
+Headline workload (``batched96``): 96 independent periodic sub-boxes of side
+log-uniform in 24..160 (about 60M particles), found in one ``hf_find_batch``
+call per step, positions already resident in HBM.  Whole-job particles/s over
+the K timed steps is ``value``; ``plain_value`` is the same boxes found one
+``hf_find`` call at a time.  The line also carries:
+  roofline      the dominant stage over the batch's boxes, timed with HIP events
+                on the stream each box runs on (boxes one at a time, so that no
+                other box shares the device during a stage);
+  serving       Poisson streams of requests (boxes of 1e4..1e7 particles) at
+                three rates through ``hf_server``, host arrays in and out,
+                against the same requests run one at a time on ``hf_find`` at
+                the same arrival times: p50/p99 latency and particles/s of both;
+  plain256      the 256^3 box (16.8M particles) as a single ``hf_find`` call,
+                with its stage rooflines and ``hf_halo_stats``;
+  large512      (``--large``) the 512^3 box (134M particles);
+  cpu_baseline  the FP64 oracle on a bounded sample of the headline workload's
+                boxes, per stage, on all host threads and on one.
 """
 from __future__ import annotations
 
@@ -36,6 +40,10 @@ FP32_PEAK_TFLOPS = 157.3
 FLOPS_PER_PAIR = 11          # 3 sub + 3 fma (6 flops) + max + add
 
 WORKLOADS = {
+    "batched96": "96 independent periodic boxes in one call, side log-uniform in 24..160 (N = side^3, "
+                 "14k..3.5M particles, 59.7M in all), each half uniform background and half NFW haloes "
+                 "(c=8, R200) of 35..20000 particles (dn/dN ~ N^-1.9); b=0.4, l=0.25, Delta_L0=60, "
+                 "Delta_L1=200, N>=35",
     "plain256": "256^3 = 16,777,216 FP32 particles, periodic box 256, half uniform background, "
                 "half NFW haloes (c=8, R200) of 35..20000 particles (dn/dN ~ N^-1.9), 20% of "
                 "haloes in pairs at 0.5-1.5 R200; b=0.4, l=0.25, Delta_L0=60, Delta_L1=200, N>=35",
@@ -44,12 +52,29 @@ WORKLOADS = {
                 "35..200000 particles, 30% of haloes in pairs and 15% in triples at 0.3-1.2 R200",
 }
 
+STAGE_KEYS = ("ms_bin", "ms_density", "ms_fof", "ms_segment", "ms_candidates", "ms_accept",
+              "ms_assign", "ms_output", "ms_total")
+STAGE_KERNELS = {
+    "density": ("k_density_dense", "k_density_sparse"),
+    "bin": ("k_bin_key", "k_radix_count", "k_radix_scatter", "k_bin_place", "k_cell_offsets",
+            "k_bin_flags", "k_bin_lists", "k_sub_table"),
+    "fof": ("k_fof_phase_a", "k_fof_dense", "k_fof_sparse_flags", "k_fof_sparse_list", "k_fof_sparse",
+            "k_fof_roots", "k_fof_keys"),
+}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
-def _stage_models(n, stats, pairs):
-    """Algorithmic work per launch of each stage (bound, work, peak, unit)."""
-    ncell = stats["n_cells"]
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------------------ rooflines
+
+def stage_work(n, ncell, pairs):
+    """Algorithmic work of each stage for n particles on a grid of ncell cells
+    with `pairs` ordered pairs within b: (bound, work, peak, unit)."""
     return {
-        # density: useful pairs x 11 flops, FP32 vector ALU
+        # density: useful pairs x 11 flops on the FP32 ALU
         "density": ("alu", pairs * FLOPS_PER_PAIR / 1e12, FP32_PEAK_TFLOPS, "TFLOP/s"),
         # binning: read xyz 12 + sort key written and read once 16 + three
         # sorted float4 records (positions, cell-local, density operand) 48 +
@@ -59,16 +84,6 @@ def _stage_models(n, stats, pairs):
         # FoF: read float4 x2 + density for every particle (36 B), parent r/w 8 B
         "fof": ("hbm", 44.0 * n / 1e9, HBM_PEAK_GBS, "GB/s"),
     }
-
-
-STAGE_KERNELS = {
-    "density": ("k_density_dense", "k_density_sparse"),
-    "bin": ("k_bin_key", "k_radix_count", "k_radix_scatter", "k_bin_place", "k_cell_offsets",
-            "k_bin_flags", "k_bin_lists", "k_sub_table"),
-    "fof": ("k_fof_phase_a", "k_fof_dense", "k_fof_sparse_flags", "k_fof_sparse_list", "k_fof_sparse",
-            "k_fof_roots", "k_fof_keys"),
-}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def source_hash() -> str:
@@ -84,10 +99,12 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def pmc_summary(fetch_csv: str, write_csv: str, copy_mib: int) -> dict:
-    """Per-call HBM bytes of each stage from two rocprofv3 --pmc runs (FETCH_SIZE,
-    WRITE_SIZE, KiB per dispatch) of `bench.py --steps 1 --warmup 0 --copy-probe MIB`,
-    each scaled so that the probe's plain copy reads and writes copy_mib MiB."""
+def pmc_summary(fetch_csv: str, write_csv: str, copy_mib: int, workload: str, steps: int) -> dict:
+    """Per-step HBM bytes of each stage from two rocprofv3 --pmc runs (FETCH_SIZE,
+    WRITE_SIZE, KiB per dispatch) of `bench.py --workload W --steps S --warmup 0
+    --only-steps --copy-probe MIB`, each scaled so that the probe's plain copy
+    reads and writes copy_mib MiB.  Every dispatch of a stage's kernels in that
+    run belongs to one of the S steps."""
     import csv
 
     def load(path):
@@ -105,124 +122,218 @@ def pmc_summary(fetch_csv: str, write_csv: str, copy_mib: int) -> dict:
     fetch, fscale = load(fetch_csv)
     write, wscale = load(write_csv)
     out = {"source_hash": source_hash(), "fetch_scale": fscale, "write_scale": wscale,
-           "copy_probe_mib": copy_mib, "stages": {}}
+           "copy_probe_mib": copy_mib, "steps": steps, "stages": {}}
     for stage, kernels in STAGE_KERNELS.items():
-        # per call of the stage: the first kernel runs once per call (the
-        # binning also runs for the pair count, so it is seen twice)
-        calls = max(len(fetch.get(kernels[0], [])), 1)
-        rb = sum(sum(fetch.get(k, [])) for k in kernels) / calls
-        wb = sum(sum(write.get(k, [])) for k in kernels) / calls
+        rb = sum(sum(fetch.get(k, [])) for k in kernels) / steps
+        wb = sum(sum(write.get(k, [])) for k in kernels) / steps
         out["stages"][stage] = {"read_bytes": rb, "write_bytes": wb, "bytes": rb + wb,
-                                "calls_seen": calls, "kernels": list(kernels)}
+                                "kernels": list(kernels)}
     return out
 
 
-def measured_traffic(stage: str):
+def measured_traffic(workload: str, stage: str):
+    """HBM bytes per step of a stage, from profiles/traffic.json, when they were
+    measured on this workload with the current sources; else None."""
     try:
-        t = json.load(open(TRAFFIC_FILE))
+        t = json.load(open(TRAFFIC_FILE)).get(workload)
     except (OSError, ValueError):
         return None
-    if t.get("source_hash") != source_hash() or stage not in t.get("stages", {}):
+    if not t or t.get("source_hash") != source_hash() or stage not in t.get("stages", {}):
         return None
     return t["stages"][stage]["bytes"]
 
 
-def cpu_baseline(target_s: float):
-    import numpy as np  # noqa: F401
+def rooflines(workload, n, ncell, pairs, stages_ms):
+    lines = {}
+    for k, (bound, work, peak, unit) in stage_work(n, ncell, pairs).items():
+        achieved = work / (stages_ms[k] / 1e3)
+        lines[k] = {"bound": bound, "kernel": k, "ms": stages_ms[k], "achieved": achieved, "peak": peak,
+                    "unit": unit, "frac": achieved / peak, "traffic": measured_traffic(workload, k)}
+    dom = max(lines, key=lambda k: stages_ms[k])
+    return lines[dom], lines
+
+
+# ------------------------------------------------------------------ CPU baseline
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(boxes, target_s: float):
+    """The FP64 oracle as it stands (density, L0 FoF, literal CompaSO and the
+    cut), per stage, on a seeded sample of the workload's boxes: all host threads
+    for about target_s seconds, then one thread for about a quarter of that."""
+    import numpy as np
     import oracle
-    from paper_2110_11408_amd import synth
     oracle.build(force=False)
+    order = np.random.default_rng(7).permutation(len(boxes))
+
+    def run(budget_s):
+        t0 = time.perf_counter()
+        st = {"density": 0.0, "fof": 0.0, "compaso": 0.0}
+        done = used = 0
+        for b in order:
+            pos, L = boxes[b][0], boxes[b][1]
+            t = time.perf_counter()
+            d = oracle.density(pos, box=L)
+            t1 = time.perf_counter()
+            l0, _ = oracle.fof(pos, d, box=L)
+            t2 = time.perf_counter()
+            oracle.compaso(pos, d, l0, box=L)
+            t3 = time.perf_counter()
+            st["density"] += t1 - t
+            st["fof"] += t2 - t1
+            st["compaso"] += t3 - t2
+            done += len(pos)
+            used += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        wall = time.perf_counter() - t0
+        return done, used, wall, st
+
     threads = oracle.num_threads()
-    done = 0
-    t0 = time.perf_counter()
-    k = 0
-    while True:
-        pos, L, _ = synth.named_box("plain64", k)
-        t = time.perf_counter()
-        oracle.find(pos, box=L)
-        done += len(pos)
-        k += 1
-        if time.perf_counter() - t0 > target_s or k >= 64:
-            break
-    wall = time.perf_counter() - t0
+    done, used, wall, st = run(target_s)
+    oracle.set_threads(1)
+    try:
+        done1, used1, wall1, st1 = run(target_s / 4)
+    finally:
+        oracle.set_threads(threads)
     return {"value": done / wall, "unit": "particles/s", "cores": threads, "kind": "oracle",
-            "sample": f"full FP64 oracle pass (density, L0 FoF, literal CompaSO, cut) on {k} "
-                      f"64^3 boxes of the same generator ({done} particles, {wall:.1f} s); "
-                      "the 256^3 box itself takes minutes on the host"}
+            "sample": f"full FP64 oracle pass (density, L0 FoF, literal CompaSO, cut) on {used} of the "
+                      f"workload's boxes in a seeded order ({done} particles, {wall:.1f} s)",
+            "stages_s": st, "value_1thread": done1 / wall1,
+            "sample_1thread": f"{used1} boxes ({done1} particles, {wall1:.1f} s) on one thread",
+            "stages_s_1thread": st1, "nproc": os.cpu_count(), "cpu_model": cpu_model()}
 
 
-def _batched(ctx, np, torch, _lib, synth, reps=3, lanes=8):
-    """Batched workload: 96 boxes in one hf_find_batch call vs one hf_find per box."""
-    boxes = synth.batch_boxes()
+# ------------------------------------------------------------------ workloads
+
+def _boxes_on_device(boxes, torch, np):
     pos = torch.from_numpy(np.concatenate([b[0] for b in boxes])).cuda()
     sizes = np.array([len(b[0]) for b in boxes], np.int64)
     offs = np.concatenate([[0], np.cumsum(sizes)])
+    return pos, sizes, offs
+
+
+def batched(ctx, boxes, args, np, torch, _lib):
+    """The headline: K timed hf_find_batch steps over the boxes; the same boxes
+    one hf_find call at a time; the stage rooflines over the boxes."""
+    pos, sizes, offs = _boxes_on_device(boxes, torch, np)
     params = [_lib.default_params(box=b[1]) for b in boxes]
     caps = np.maximum(sizes // 64, 64)
-    ctx.find_batch(pos, offs, params, halos_caps=caps, n_lanes=lanes, want_l0=False)
-    torch.cuda.synchronize()
-    t = []
-    for _ in range(reps):
-        t0 = time.perf_counter()
+    lanes = args.lanes
+    for _ in range(args.warmup):
         ctx.find_batch(pos, offs, params, halos_caps=caps, n_lanes=lanes, want_l0=False)
-        torch.cuda.synchronize()
-        t.append(time.perf_counter() - t0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = ctx.find_batch(pos, offs, params, halos_caps=caps, n_lanes=lanes, want_l0=False)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total = int(offs[-1])
+    res = {"value": total * args.steps / wall, "ms_per_step": wall * 1e3 / args.steps,
+           "n_halos": int(np.sum(out["n_halos"]))}
+    if args.only_steps:
+        return res
+    # one hf_find per box, in the same order, as the plain comparison
     views = [pos[offs[b]:offs[b + 1]] for b in range(len(boxes))]
     for b in range(len(boxes)):
         ctx.find(views[b], params[b], halos_cap=int(caps[b]), want_l0=False)
     torch.cuda.synchronize()
     tp = []
-    for _ in range(reps):
+    for _ in range(3):
         t0 = time.perf_counter()
         for b in range(len(boxes)):
             ctx.find(views[b], params[b], halos_cap=int(caps[b]), want_l0=False)
         torch.cuda.synchronize()
         tp.append(time.perf_counter() - t0)
-    total = int(offs[-1])
-    tb, tpl = float(np.median(t)), float(np.median(tp))
-    return {"workload": "96 periodic boxes, side log-uniform in 24..160 (N = side^3, "
-                        f"{sizes.min()}..{sizes.max()}), half NFW haloes 35..20000",
-            "n_boxes": len(boxes), "n_particles": total, "lanes": lanes,
-            "value": total / tb, "unit": "particles/s", "ms": tb * 1e3,
-            "plain_value": total / tpl, "plain_ms": tpl * 1e3, "speedup": tpl / tb,
-            "reps": reps}
-
-
-def _halo_stats(ctx, pos_d, p, out, np, torch, reps=3):
-    """hf_halo_stats on the benchmark box: level 2 inside every L1 halo and the
-    Table 1 position statistics (fresh binning included)."""
-    nh = out["n_halos"]
-    ctx.halo_stats(pos_d, out["density"], out["halo_id"], p, nh)
+    tpl = float(np.median(tp))
+    res.update({"plain_value": total / tpl, "plain_ms": tpl * 1e3,
+                "speedup_vs_plain": tpl / (wall / args.steps)})
+    # stage times of every box with no other box on the device (one lane), and
+    # the work of every box
+    ctx.find_batch(pos, offs, params, halos_caps=caps, n_lanes=1, want_l0=False)
     torch.cuda.synchronize()
-    t = []
-    for _ in range(reps):
-        t0 = time.perf_counter()
-        res = ctx.halo_stats(pos_d, out["density"], out["halo_id"], p, nh)
-        torch.cuda.synchronize()
-        t.append(time.perf_counter() - t0)
     st = ctx.stats()
-    ms = float(np.median(t)) * 1e3
-    return {"ms": ms, "value": len(pos_d) / (ms / 1e3), "unit": "particles/s", "n_halos": nh,
-            "n_l2": int(np.sum(res["n_l2"])), "reps": reps,
-            "stages_ms": {k[3:]: st[k] for k in ("ms_bin", "ms_segment", "ms_candidates", "ms_accept",
-                                                  "ms_assign", "ms_output", "ms_total")}}
+    pairs = sum(ctx.count_pairs(views[b], params[b]) for b in range(len(boxes)))
+    stages = {k[3:]: st[k] for k in STAGE_KEYS}
+    roof, lines = rooflines("batched96", total, st["n_cells"], pairs, stages)
+    res.update({"roofline": roof, "stage_rooflines": lines, "stages_ms_one_lane": stages,
+                "counts": {"pairs_within_b": pairs, "n_cells": st["n_cells"],
+                           "n_members": st["n_members"], "n_groups": st["n_groups"],
+                           "n_candidates": st["n_candidates"], "n_halos": st["n_halos"]}})
+    return res
 
 
-def _fifo_latency(arrivals, service):
-    """Latencies of a one-at-a-time FIFO server with the given service times."""
-    done, lat = 0.0, []
-    for a, s in zip(arrivals, service):
-        start = max(a, done)
-        done = start + s
-        lat.append(done - a)
-    return lat
+def single_box(ctx, name, steps, warmup, np, torch, _lib, synth, halo_stats=False):
+    """One box found by one hf_find call per step, with its stage rooflines."""
+    pos, L, _ = synth.named_box(name)
+    n = len(pos)
+    pos_d = torch.from_numpy(pos).cuda()
+    p = _lib.default_params(box=L)
+    pairs = ctx.count_pairs(pos_d, p)
+    cap = max(1024, n // 64)
+    for _ in range(warmup):
+        ctx.find(pos_d, p, halos_cap=cap)
+    torch.cuda.synchronize()
+    acc = {k: 0.0 for k in STAGE_KEYS}
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = ctx.find(pos_d, p, halos_cap=cap)
+        st = ctx.stats()
+        for k in STAGE_KEYS:
+            acc[k] += st[k]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stages = {k[3:]: acc[k] / steps for k in STAGE_KEYS}
+    roof, lines = rooflines(name, n, st["n_cells"], pairs, stages)
+    res = {"workload": name, "description": WORKLOADS[name], "n_particles": n,
+           "value": n * steps / wall, "unit": "particles/s", "ms_per_step": wall * 1e3 / steps,
+           "steps": steps, "roofline": roof, "stage_rooflines": lines, "stages_ms": stages,
+           "counts": {"pairs_within_b": pairs, "n_cells": st["n_cells"], "n_members": st["n_members"],
+                      "n_groups": st["n_groups"], "n_candidates": st["n_candidates"],
+                      "n_found": st["n_found"], "n_halos": out["n_halos"],
+                      "n_dense_cells": st["n_dense_cells"], "n_dense_chunks": st["n_dense_chunks"],
+                      "n_sparse": st["n_sparse"], "n_hard": st["n_hard"]}}
+    if halo_stats:
+        nh = out["n_halos"]
+        ctx.halo_stats(pos_d, out["density"], out["halo_id"], p, nh)
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            r = ctx.halo_stats(pos_d, out["density"], out["halo_id"], p, nh)
+            torch.cuda.synchronize()
+            t.append(time.perf_counter() - t0)
+        ms = float(np.median(t)) * 1e3
+        res["halo_stats"] = {"ms": ms, "value": n / (ms / 1e3), "unit": "particles/s", "n_halos": nh,
+                             "n_l2": int(np.sum(r["n_l2"]))}
+    del pos_d
+    torch.cuda.empty_cache()
+    return res
 
 
-def _serving(ctx, np, torch, _lib, synth, count=32, slots=4, budget_gb=64):
-    """Serving workload: Poisson arrivals at a rate that keeps the plain
-    one-at-a-time path fully busy; latency from submission to host results."""
+def _pct(x, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(x) * 1e3, q))
+
+
+def serving(ctx, np, torch, _lib, synth, count=200, pool=24, slots=4, budget_gb=64,
+            loads=(0.5, 0.9, 1.3)):
+    """Poisson request streams at several rates (fractions of the plain path's
+    capacity).  Requests are drawn (seeded) from a pool of distinct boxes of
+    1e4..1e7 particles (log-uniform, halo fraction 0.3..0.7).  The served path
+    is hf_server; the plain path runs the same requests one at a time on hf_find
+    (host positions in, halo ids and table out) at the same arrival times.
+    Latency is from arrival to results in host memory, both measured."""
     from paper_2110_11408_amd.api import Server
-    reqs = synth.request_stream(count, rate_hz=1.0)
+    reqs = synth.request_stream(pool, rate_hz=1.0)
     boxes = []
     for r in reqs:
         pos, L, _ = synth.make_box(synth.BoxRecipe(n=r["n"], side=r["side"], halo_frac=r["halo_frac"]),
@@ -230,61 +341,79 @@ def _serving(ctx, np, torch, _lib, synth, count=32, slots=4, budget_gb=64):
         boxes.append((Server.pinned_positions(pos), L))
     sizes = np.array([len(b[0]) for b in boxes], np.int64)
     params = [_lib.default_params(box=b[1]) for b in boxes]
-    total = int(sizes.sum())
-    # plain path: host positions -> device, hf_find, results -> host, one at a time
+    halo_host = {b: torch.empty(int(sizes[b]), dtype=torch.int32).pin_memory() for b in range(pool)}
+
     def plain_one(b):
         pos_h, _ = boxes[b]
         d = pos_h.to("cuda", non_blocking=True)
         out = ctx.find(d, params[b], want_density=False, want_l0=False)
-        out["halo_id"].cpu()
+        halo_host[b].copy_(out["halo_id"], non_blocking=True)
         out["halos"].cpu()
-    plain_one(int(np.argmax(sizes)))
+
+    for b in range(pool):
+        plain_one(b)
     torch.cuda.synchronize()
     service = []
-    for b in range(count):
+    for b in range(pool):
         t0 = time.perf_counter()
         plain_one(b)
         service.append(time.perf_counter() - t0)
-    mean_s = float(np.mean(service))
-    rate = 1.0 / mean_s            # the plain path's capacity in requests/s
-    gaps = np.diff(np.r_[0.0, [r["t"] for r in reqs]])  # exponential, mean 1 s
-    arrivals = np.cumsum(gaps / rate)
-    plain_lat = _fifo_latency(arrivals, service)
+    mean_n = float(sizes.mean())
+    capacity = 1.0 / float(np.mean(service))   # requests/s of the plain path on the pool
+    rng = np.random.default_rng(77)
+    which = rng.integers(0, pool, count)
+    gaps = rng.exponential(1.0, count)
     srv = Server(0, slots=slots, budget_bytes=int(budget_gb) << 30)
+    out = {"workload": f"{count} requests per rate drawn from {pool} distinct boxes of "
+                       f"{sizes.min()}..{sizes.max()} particles (N log-uniform in 1e4..1e7, halo fraction "
+                       "0.3..0.7, side N^(1/3)); host arrays in and out",
+           "requests_per_rate": count, "slots": slots, "budget_gb": budget_gb,
+           "plain_capacity_hz": capacity, "rates": []}
     try:
-        # warm every slot once
-        for t in [srv.submit(boxes[b][0], params[b]) for b in np.argsort(sizes)[-slots:]]:
-            srv.wait(t)
-        # saturated: everything queued at once
+        for b in np.argsort(sizes)[-slots:]:
+            srv.wait(srv.submit(boxes[b][0], params[b]))
+        for load in loads:
+            rate = load * capacity
+            arrivals = np.cumsum(gaps / rate)
+            total = int(sizes[which].sum())
+            # served
+            base = time.perf_counter()
+            tickets = []
+            for k in range(count):
+                while time.perf_counter() - base < arrivals[k]:
+                    time.sleep(min(0.0005, max(0.0, arrivals[k] - (time.perf_counter() - base))))
+                tickets.append(srv.submit(boxes[which[k]][0], params[which[k]]))
+            res = [srv.wait(t) for t in tickets]
+            lat = [r["t_done"] - r["t_submit"] for r in res]
+            span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
+            # plain, one at a time at the same arrival times
+            base = time.perf_counter()
+            plat = []
+            last = 0.0
+            for k in range(count):
+                now = time.perf_counter() - base
+                if now < arrivals[k]:
+                    time.sleep(arrivals[k] - now)
+                plain_one(int(which[k]))
+                torch.cuda.synchronize()
+                last = time.perf_counter() - base
+                plat.append(last - arrivals[k])
+            out["rates"].append({
+                "load": load, "rate_hz": rate, "n_particles": total,
+                "served_value": total / span, "served_p50_ms": _pct(lat, 50), "served_p99_ms": _pct(lat, 99),
+                "plain_value": total / last, "plain_p50_ms": _pct(plat, 50), "plain_p99_ms": _pct(plat, 99)})
+            _say(f"[bench] serving load {load}: served p50/p99 {_pct(lat, 50):.2f}/{_pct(lat, 99):.2f} ms, "
+                 f"plain {_pct(plat, 50):.2f}/{_pct(plat, 99):.2f} ms")
+        out["held_gb"] = srv.held_bytes() / 2 ** 30
+        # saturated: every request of the stream queued at once
         t0 = srv.now()
-        tickets = [srv.submit(boxes[b][0], params[b]) for b in range(count)]
+        tickets = [srv.submit(boxes[which[k]][0], params[which[k]]) for k in range(count)]
         res = [srv.wait(t) for t in tickets]
-        sat = total / (max(r["t_done"] for r in res) - t0)
-        # open loop at the Poisson arrival times
-        base = time.perf_counter()
-        tickets = []
-        for b in range(count):
-            while time.perf_counter() - base < arrivals[b]:
-                time.sleep(min(0.0005, max(0.0, arrivals[b] - (time.perf_counter() - base))))
-            tickets.append(srv.submit(boxes[b][0], params[b]))
-        res = [srv.wait(t) for t in tickets]
-        lat = [r["t_done"] - r["t_submit"] for r in res]
-        span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
-        held = srv.held_bytes()
+        out["saturated_value"] = int(sizes[which].sum()) / (max(r["t_done"] for r in res) - t0)
     finally:
         srv.close()
-    ms = lambda x: float(x) * 1e3  # noqa: E731
-    return {"workload": f"{count} requests, N log-uniform in 1e4..1e7 ({sizes.min()}..{sizes.max()}), "
-                        "halo fraction 0.3..0.7, side N^(1/3); host arrays in and out",
-            "requests": count, "n_particles": total, "slots": slots, "budget_gb": budget_gb,
-            "value": sat, "unit": "particles/s", "plain_value": total / float(np.sum(service)),
-            "rate_hz": rate, "open_loop_value": total / span,
-            "p50_ms": ms(np.percentile(lat, 50)), "p99_ms": ms(np.percentile(lat, 99)),
-            "plain_p50_ms": ms(np.percentile(plain_lat, 50)),
-            "plain_p99_ms": ms(np.percentile(plain_lat, 99)),
-            "plain_latency_model": "FIFO one at a time with the measured plain service times "
-                                   "at the same arrival times",
-            "held_gb": held / 2 ** 30}
+    out["mean_request_particles"] = mean_n
+    return out
 
 
 def main():
@@ -292,27 +421,37 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="plain256", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="batched96", choices=sorted(WORKLOADS))
+    ap.add_argument("--lanes", type=int, default=0, help="pipelines of hf_find_batch (0: the library's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-plain256", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--large", action="store_true", help="also time the 512^3 box")
+    ap.add_argument("--only-steps", action="store_true",
+                    help="run the warmup and timed steps of the workload and nothing else (for counters)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of this many MiB (a traffic "
                          "reference for hardware counters)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="write profiles/traffic.json from two rocprofv3 --pmc counter files "
-                         "and exit (no GPU needed)")
+                    help="record the per-step stage traffic of --workload in profiles/traffic.json from "
+                         "two rocprofv3 --pmc counter files of an --only-steps run and exit (no GPU needed)")
     args = ap.parse_args()
     if args.pmc_summary:
-        t = pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.copy_probe or 1024)
+        try:
+            allt = json.load(open(TRAFFIC_FILE))
+        except (OSError, ValueError):
+            allt = {}
+        allt = {k: v for k, v in allt.items() if k in WORKLOADS}
+        allt[args.workload] = pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.copy_probe or 1024,
+                                          args.workload, args.steps + args.warmup)
         with open(TRAFFIC_FILE, "w") as f:
-            json.dump(t, f, indent=1)
-        print(json.dumps(t))
+            json.dump(allt, f, indent=1)
+        print(json.dumps(allt[args.workload]))
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the library runs "
-              "each box on a single device", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: every box and request "
+              "runs on a single device (the multi-GPU sharding is a design, not a build)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -328,60 +467,48 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    pos, L, _ = synth.named_box(args.workload)
-    n = len(pos)
-    pos_d = torch.from_numpy(pos).to(dev)
-    p = _lib.default_params(box=L)
     ctx = Context(0)
-    pairs = ctx.count_pairs(pos_d, p)
-    cap = max(1024, n // 64)
-    for _ in range(args.warmup):
-        ctx.find(pos_d, p, halos_cap=cap)
-    torch.cuda.synchronize()
-    keys = ("ms_bin", "ms_density", "ms_fof", "ms_segment", "ms_candidates", "ms_accept",
-            "ms_assign", "ms_output", "ms_total")
-    acc = {k: 0.0 for k in keys}
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        out = ctx.find(pos_d, p, halos_cap=cap)
-        st = ctx.stats()
-        for k in keys:
-            acc[k] += st[k]
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_step = wall * 1e3 / args.steps
-    stages = {k[3:]: acc[k] / args.steps for k in keys}
-    models = _stage_models(n, st, pairs)
-    lines = {}
-    for k, (bound, work, peak, unit) in models.items():
-        achieved = work / (stages[k] / 1e3)
-        lines[k] = {"bound": bound, "kernel": k, "ms": stages[k], "achieved": achieved, "peak": peak,
-                    "unit": unit, "frac": achieved / peak, "traffic": measured_traffic(k)}
-    dom = max(lines, key=lambda k: stages[k])
-    roof = lines[dom]
-    res = {
-        "metric": METRIC, "value": n / (ms_step / 1e3), "unit": "particles/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
-                   "n_particles": n, "box": L, "path": "plain (hf_find, one box per call)"},
-        "roofline": roof,
-        "stage_rooflines": lines,
-        "stages_ms": stages,
-        "counts": {"pairs_within_b": pairs, "n_cells": st["n_cells"], "n_members": st["n_members"],
-                   "n_groups": st["n_groups"], "n_candidates": st["n_candidates"],
-                   "n_found": st["n_found"], "n_halos": out["n_halos"],
-                   "n_dense_cells": st["n_dense_cells"], "n_dense_chunks": st["n_dense_chunks"],
-                   "n_sparse": st["n_sparse"], "n_hard": st["n_hard"]},
-    }
-    res["halo_stats"] = _halo_stats(ctx, pos_d, p, out, np, torch)
-    if not args.no_batched:
-        res["batched"] = _batched(ctx, np, torch, _lib, synth)
+    res = {"metric": METRIC, "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic"}
+    if args.workload == "batched96":
+        _say("[bench] generating the 96 boxes")
+        boxes = synth.batch_boxes()
+        _say("[bench] batched steps")
+        b = batched(ctx, boxes, args, np, torch, _lib)
+        res.update({"value": b.pop("value"), "ms_per_step": b.pop("ms_per_step"),
+                    "config": {"workload": "batched96", "description": WORKLOADS["batched96"],
+                               "n_boxes": len(boxes), "n_particles": int(sum(len(x[0]) for x in boxes)),
+                               "path": "hf_find_batch (all boxes in one call)"}})
+        if "roofline" in b:
+            res["roofline"] = b.pop("roofline")
+        res["batched"] = b
+    else:
+        s = single_box(ctx, args.workload, args.steps, args.warmup, np, torch, _lib, synth,
+                       halo_stats=not args.only_steps)
+        res.update({"value": s.pop("value"), "ms_per_step": s.pop("ms_per_step"), "roofline": s.pop("roofline"),
+                    "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
+                               "n_particles": s["n_particles"], "path": "hf_find (one box per call)"}})
+        res["plain"] = s
+        boxes = None
+    if args.only_steps:
+        print(json.dumps(res), flush=True)
+        return
+    if args.workload == "batched96" and not args.no_plain256:
+        _say("[bench] plain256")
+        res["plain256"] = single_box(ctx, "plain256", 5, 2, np, torch, _lib, synth, halo_stats=True)
+    if args.large:
+        _say("[bench] large512")
+        res["large512"] = single_box(ctx, "large512", 3, 1, np, torch, _lib, synth)
     if not args.no_serving:
-        res["serving"] = _serving(ctx, np, torch, _lib, synth)
+        _say("[bench] serving")
+        res["serving"] = serving(ctx, np, torch, _lib, synth)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        _say("[bench] cpu baseline")
+        if boxes is None:
+            pos, L, _ = synth.named_box("plain64")
+            boxes = [(pos, L)]
+        res["cpu_baseline"] = cpu_baseline(boxes, args.cpu_seconds)
     print(json.dumps(res), flush=True)
 
 

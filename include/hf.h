@@ -143,9 +143,12 @@ hf_status hf_params_at_redshift(const hf_params *in, double omega_m0, double z, 
  * App. B.2), alpha^6 and c_Roche^3. */
 hf_status hf_derived(const hf_params *p, int64_t n, double *out);
 
-/* Create a context on HIP device `device`.  Fails with HF_ERR_UNSUPPORTED when the
- * device is not gfx950. */
-hf_status hf_create(hf_ctx **ctx, int device);
+/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the device
+ * memory the context's scratch arenas may hold together (its single-box arena
+ * and the lanes of hf_find_batch; 0 = no bound): a call whose arena would pass
+ * it returns HF_ERR_NOMEM before anything is enqueued.  Fails with
+ * HF_ERR_UNSUPPORTED when the device is not gfx950. */
+hf_status hf_create(hf_ctx **ctx, int device, uint64_t hbm_budget_bytes);
 void hf_destroy(hf_ctx *ctx);
 const char *hf_last_error(const hf_ctx *ctx);
 hf_status hf_get_stats(const hf_ctx *ctx, hf_stats *out);

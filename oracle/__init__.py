@@ -71,6 +71,7 @@ def _load():
                                     P, P, P, P, P, P, P, I64, P, P, P, P]
         lib.orc_params_at_redshift.argtypes = [P, ctypes.c_double, ctypes.c_double, P]
         lib.orc_l2_stats.argtypes = [I64, P, P, P, P, ctypes.c_int, I64, P, P, P, I64, P, P, P, P, P]
+        lib.orc_events.argtypes = [I64, P, P, P, P, ctypes.c_int, ctypes.c_double, P]
         lib.orc_num_threads.restype = ctypes.c_int
         lib.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -186,6 +187,27 @@ def find(pos, mode: str = "cells", density_override=None, **kw) -> dict:
     res = compaso(pos, dens, l0, mode=mode, **kw)
     res.update({"density": dens, "l0": l0, "n_groups": ng})
     return res
+
+
+# bits of events(): see orc_events
+EV_L0CUT, EV_FLOOR, EV_PEAK, EV_ORDER, EV_GROUP = 1, 2, 4, 8, 128
+
+
+def events(pos, dens, l0, tol: float = 1e-5, mode: str = "cells", **kw) -> np.ndarray:
+    """Near-threshold events per particle (uint8 bits EV_*): where a density
+    field within tol * max(Delta, 1) of ``dens`` can change the labels (the L0
+    cut of Sec. 2.2.1, the floor, peak test and nucleus order of Sec. 2.2.2).
+    ``l0`` is the L0 labelling of ``dens``."""
+    pos = _pos(pos)
+    dens = np.ascontiguousarray(dens, dtype=np.float64)
+    l0 = np.ascontiguousarray(l0, dtype=np.int32)
+    p = params_vector(**kw)
+    out = np.zeros(len(pos), np.uint8)
+    rc = _load().orc_events(len(pos), _ptr(pos), _ptr(p), _ptr(dens), _ptr(l0),
+                            0 if mode == "brute" else 1, float(tol), _ptr(out))
+    if rc:
+        raise RuntimeError(f"orc_events failed ({rc})")
+    return out
 
 
 def params_at_redshift(omega_m0: float, z: float, **kw) -> dict:

@@ -15,6 +15,10 @@
  *     competitive reassignment, density floor), with the flat-rotation-curve
  *     enclosed density of Sec. 2.3.2 and squared distances as in Sec. 2.3.3.
  *   - output cut at the minimum L1 halo size (end of Sec. 2.2.2, Table 1).
+ *   - the near-threshold events through which a slightly different density
+ *     field can change the labels (orc_events; used to attribute label
+ *     differences against a float32 field to the density comparisons of
+ *     Sec. 2.2.1 and 2.2.2).
  *
  * Neighbour search has two modes that must agree exactly: brute force over all
  * pairs (mode 0) and a cell list (mode 1) whose cells are at least the search
@@ -270,11 +274,45 @@ static void uf_union(int64_t *parent, int64_t a, int64_t b)
     if (ra < rb) parent[rb] = ra; else parent[ra] = rb;
 }
 
+/* Whether the ball of squared radius r2 around particle i can reach stencil
+ * cell t (offset (t % 3 - 1, t / 3 % 3 - 1, t / 9 - 1) from i's cell): the
+ * squared gap between i and that cell's slab along each axis, with a relative
+ * margin of 1e-6 so that rounding never drops a pair. */
+static int cell_in_reach(const grid_t *g, const float *pos, int64_t i, int t, double r2)
+{
+    double gap2 = 0.0;
+    int off[3] = { t % 3 - 1, (t / 3) % 3 - 1, t / 9 - 1 };
+    for (int a = 0; a < 3; a++) {
+        if (off[a] == 0) continue;
+        double x = (double)pos[3 * i + a];
+        int c = cell_coord(x, g->cell, g->nc);
+        double gap = off[a] < 0 ? x - (double)c * g->cell : (double)(c + 1) * g->cell - x;
+        if (gap > 0.0) gap2 += gap * gap;
+    }
+    return gap2 < r2 * (1.0 + 1e-6);
+}
+
+typedef struct { int32_t *a; int64_t len, cap; } links_t;
+
+static void links_push(links_t *b, int64_t i, int64_t j)
+{
+    if (b->len + 2 > b->cap) {
+        b->cap = b->cap ? 2 * b->cap : 1 << 16;
+        b->a = (int32_t *)realloc(b->a, (size_t)b->cap * sizeof(int32_t));
+    }
+    b->a[b->len++] = (int32_t)i;
+    b->a[b->len++] = (int32_t)j;
+}
+
 /* L0 groups: friends-of-friends with linking length l over the particles whose
  * density exceeds delta_l0_min (Sec. 2.2.1); two members are friends when their
  * separation is less than l (FoF definition, Sec. 1).  l0[i] = 1 + minimum
  * original index of i's group for members, 0 for non-members.  n_groups counts
- * groups including single-member ones. */
+ * groups including single-member ones.
+ * The groups are the connected components of the friend pairs, which do not
+ * depend on the order in which pairs are joined: in cell-list mode the pairs
+ * (i, j > i) of a block of particles are listed by several threads at once and
+ * then joined one by one; brute force joins them as it finds them. */
 int orc_fof(int64_t n, const float *pos, const double *p, const double *dens,
             int mode, int32_t *l0, int64_t *n_groups)
 {
@@ -291,18 +329,43 @@ int orc_fof(int64_t n, const float *pos, const double *p, const double *dens,
         if (rc == 2) { free(parent); return 2; }
         use_grid = rc == 0;
     }
-    for (int64_t i = 0; i < n; i++) {
-        if (!(dens[i] > dmin)) continue;
-        if (use_grid) {
-            int64_t st[27];
-            grid_stencil(&g, pos, i, st);
-            for (int t = 0; t < 27; t++)
-                for (int64_t k = g.start[st[t]]; k < g.start[st[t] + 1]; k++) {
-                    int64_t j = g.items[k];
-                    if (j <= i || !(dens[j] > dmin)) continue;
-                    if (d2_periodic(pos, i, j, L) < l2) uf_union(parent, i, j);
+    if (use_grid) {
+        int nt = 1;
+#ifdef _OPENMP
+        nt = omp_get_max_threads();
+#endif
+        links_t *buf = (links_t *)calloc((size_t)nt, sizeof(links_t));
+        const int64_t block = (int64_t)1 << 16;
+        for (int64_t i0 = 0; i0 < n; i0 += block) {
+            int64_t i1 = i0 + block < n ? i0 + block : n;
+            #pragma omp parallel for schedule(dynamic, 256)
+            for (int64_t i = i0; i < i1; i++) {
+                if (!(dens[i] > dmin)) continue;
+                int tid = 0;
+#ifdef _OPENMP
+                tid = omp_get_thread_num();
+#endif
+                int64_t st[27];
+                grid_stencil(&g, pos, i, st);
+                for (int t = 0; t < 27; t++) {
+                    if (!cell_in_reach(&g, pos, i, t, l2)) continue;
+                    for (int64_t k = g.start[st[t]]; k < g.start[st[t] + 1]; k++) {
+                        int64_t j = g.items[k];
+                        if (j <= i || !(dens[j] > dmin)) continue;
+                        if (d2_periodic(pos, i, j, L) < l2) links_push(&buf[tid], i, j);
+                    }
                 }
-        } else {
+            }
+            for (int t = 0; t < nt; t++) {
+                for (int64_t k = 0; k < buf[t].len; k += 2) uf_union(parent, buf[t].a[k], buf[t].a[k + 1]);
+                buf[t].len = 0;
+            }
+        }
+        for (int t = 0; t < nt; t++) free(buf[t].a);
+        free(buf);
+    } else {
+        for (int64_t i = 0; i < n; i++) {
+            if (!(dens[i] > dmin)) continue;
             for (int64_t j = i + 1; j < n; j++) {
                 if (!(dens[j] > dmin)) continue;
                 if (d2_periodic(pos, i, j, L) < l2) uf_union(parent, i, j);
@@ -582,6 +645,129 @@ int orc_compaso(int64_t n, const float *pos, const double *p, const double *dens
     free(gh); free(gnh); free(own);
     if (use_grid) grid_free(&g);
     free(mem); free(gstart); free(glab);
+    return 0;
+}
+
+/* ------------------------------------------------- near-threshold events */
+
+/* Where a density field that differs from this one by at most
+ * tol * max(Delta, 1) per particle (the float32 field of another
+ * implementation, say) can change the labels.  Every label predicate is exact
+ * given the densities, so labels can only change through a density comparison:
+ *   EV_L0CUT  |Delta_i - Delta_L0,min| <= tol max(Delta_L0,min, 1): i may enter
+ *             or leave the L0 members (Sec. 2.2.1);
+ *   EV_FLOOR  a member with |Delta_i - floor| <= tol max(floor, 1): it may cross
+ *             the nucleation floor (Sec. 2.2.2 step 4);
+ *   EV_PEAK   a member at or above floor - tol max(floor, 1) whose densest other
+ *             group member within b, at density M, has
+ *             |Delta_i - M| <= 2 tol max(Delta_i, M, 1): the peak test of
+ *             Sec. 2.2.2 step 2 may flip;
+ *   EV_ORDER  a nucleus candidate (at or above the floor, denser than every
+ *             other group member within b) within 2 tol max(., ., 1) of another
+ *             candidate of its group: the order in which nuclei are taken
+ *             (Sec. 2.2.2 step 1) may flip;
+ *   EV_GROUP  a member of an L0 group that holds a member with EV_FLOOR,
+ *             EV_PEAK or EV_ORDER, or that has a member within l of (or equal
+ *             to) a particle with EV_L0CUT.
+ * l0 is the L0 labelling of this field (1 + minimum index, 0 = not a member).
+ * mode 0: brute force; mode 1: cell list.  ev[n] receives the bits. */
+enum { EV_L0CUT = 1, EV_FLOOR = 2, EV_PEAK = 4, EV_ORDER = 8, EV_GROUP = 128 };
+
+typedef struct { int32_t lab; double dens; int64_t idx; } cand_t;
+
+static int cmp_cand(const void *a, const void *b)
+{
+    const cand_t *x = (const cand_t *)a, *y = (const cand_t *)b;
+    if (x->lab != y->lab) return x->lab < y->lab ? -1 : 1;
+    if (x->dens != y->dens) return x->dens > y->dens ? -1 : 1;
+    return (x->idx > y->idx) - (x->idx < y->idx);
+}
+
+static double fmax3(double a, double b, double c) { return fmax(fmax(a, b), c); }
+
+int orc_events(int64_t n, const float *pos, const double *p, const double *dens,
+               const int32_t *l0, int mode, double tol, uint8_t *ev)
+{
+    double d[D_COUNT];
+    if (orc_derive(p, n, d)) return 1;
+    double L = p[P_BOX], b2 = d[D_B2], l2 = d[D_L2], dl0 = p[P_DL0], fl = d[D_FLOOR];
+    double tcut = tol * fmax(dl0, 1.0), tfl = tol * fmax(fl, 1.0);
+    grid_t g;
+    int rc = mode == 1 ? grid_build(&g, n, pos, L, fmax(d[D_B], d[D_L])) : 1;
+    if (rc == 2) return 2;
+    const grid_t *gp = rc == 0 ? &g : NULL;
+    unsigned char *cand = (unsigned char *)calloc((size_t)(n > 0 ? n : 1), 1);
+    unsigned char *gflag = (unsigned char *)calloc((size_t)n + 1, 1);
+    if (!cand || !gflag) { free(cand); free(gflag); if (gp) grid_free(&g); return 2; }
+
+    #pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; i++) {
+        uint8_t e = 0;
+        if (fabs(dens[i] - dl0) <= tcut) e |= EV_L0CUT;
+        if (l0[i] > 0) {
+            if (fabs(dens[i] - fl) <= tfl) e |= EV_FLOOR;
+            if (dens[i] >= fl - tfl) {
+                /* densest other member of the group within b, and whether a
+                 * denser one (total order) exists */
+                double M = -HUGE_VAL;
+                int denser_near = 0;
+                int64_t st[27];
+                int nt = 1;
+                if (gp) { grid_stencil(gp, pos, i, st); nt = 27; }
+                for (int t = 0; t < nt; t++) {
+                    int64_t k0 = gp ? gp->start[st[t]] : 0, k1 = gp ? gp->start[st[t] + 1] : n;
+                    for (int64_t k = k0; k < k1; k++) {
+                        int64_t j = gp ? gp->items[k] : k;
+                        if (j == i || l0[j] != l0[i]) continue;
+                        if (!(d2_periodic(pos, i, j, L) < b2)) continue;
+                        if (dens[j] > M) M = dens[j];
+                        if (dens[j] > dens[i] || (dens[j] == dens[i] && j < i)) denser_near = 1;
+                    }
+                }
+                if (M > -HUGE_VAL && fabs(dens[i] - M) <= 2.0 * tol * fmax3(dens[i], M, 1.0)) e |= EV_PEAK;
+                if (dens[i] >= fl && !denser_near) cand[i] = 1;
+            }
+        }
+        ev[i] = e;
+    }
+    /* candidates of one group in descending density: neighbours in that order
+     * closer than the tolerance may swap */
+    int64_t nc = 0;
+    for (int64_t i = 0; i < n; i++) nc += cand[i];
+    cand_t *cs = (cand_t *)malloc((size_t)(nc > 0 ? nc : 1) * sizeof(cand_t));
+    nc = 0;
+    for (int64_t i = 0; i < n; i++)
+        if (cand[i]) { cs[nc].lab = l0[i]; cs[nc].dens = dens[i]; cs[nc].idx = i; nc++; }
+    qsort(cs, (size_t)nc, sizeof(cand_t), cmp_cand);
+    for (int64_t k = 0; k + 1 < nc; k++)
+        if (cs[k].lab == cs[k + 1].lab &&
+            fabs(cs[k].dens - cs[k + 1].dens) <= 2.0 * tol * fmax3(cs[k].dens, cs[k + 1].dens, 1.0)) {
+            ev[cs[k].idx] |= EV_ORDER;
+            ev[cs[k + 1].idx] |= EV_ORDER;
+        }
+    free(cs);
+    /* groups touched by an event */
+    for (int64_t i = 0; i < n; i++)
+        if (l0[i] > 0 && (ev[i] & (EV_FLOOR | EV_PEAK | EV_ORDER))) gflag[l0[i]] = 1;
+    for (int64_t i = 0; i < n; i++) {
+        if (!(ev[i] & EV_L0CUT)) continue;
+        if (l0[i] > 0) gflag[l0[i]] = 1;
+        int64_t st[27];
+        int nt = 1;
+        if (gp) { grid_stencil(gp, pos, i, st); nt = 27; }
+        for (int t = 0; t < nt; t++) {
+            int64_t k0 = gp ? gp->start[st[t]] : 0, k1 = gp ? gp->start[st[t] + 1] : n;
+            for (int64_t k = k0; k < k1; k++) {
+                int64_t j = gp ? gp->items[k] : k;
+                if (l0[j] > 0 && d2_periodic(pos, i, j, L) < l2) gflag[l0[j]] = 1;
+            }
+        }
+    }
+    for (int64_t i = 0; i < n; i++)
+        if (l0[i] > 0 && gflag[l0[i]]) ev[i] |= EV_GROUP;
+    free(cand);
+    free(gflag);
+    if (gp) grid_free(&g);
     return 0;
 }
 

@@ -100,7 +100,7 @@ def load(path: str = LIB_PATH):
         lib.hf_default_params.restype = None
         lib.hf_derived.argtypes = [PP, I64, P]
         lib.hf_params_at_redshift.argtypes = [PP, ctypes.c_double, ctypes.c_double, PP]
-        lib.hf_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), I32]
+        lib.hf_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), I32, ctypes.c_uint64]
         lib.hf_destroy.argtypes = [P]
         lib.hf_destroy.restype = None
         lib.hf_last_error.argtypes = [P]

@@ -32,13 +32,14 @@ def _check_pos(pos):
 
 
 class Context:
-    """An hf_ctx on one GPU (owns the scratch arena)."""
+    """An hf_ctx on one GPU (owns the scratch arena).  budget_bytes bounds the
+    device memory its arenas may hold together (0 = no bound)."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, budget_bytes: int = 0):
         self.lib = _lib.load()
         self.device = int(device)
         h = ctypes.c_void_p()
-        st = self.lib.hf_create(ctypes.byref(h), self.device)
+        st = self.lib.hf_create(ctypes.byref(h), self.device, int(budget_bytes))
         if st:
             raise HfError(st, "hf_create failed (needs a gfx950 GPU)")
         self.h = h

@@ -141,6 +141,97 @@ __global__ __launch_bounds__(kBlock) void k_glist(int G, const uint32_t *__restr
     if (gccnt[g]) glist[idx[g]] = g;
 }
 
+// ------------------------------------------------------- group extent
+// Every distance is a minimum image, which stands for the distance inside an
+// L0 group only while the group spans less than half the box along each axis.
+// A group whose extent reaches L/2 makes the call fail (HF_ERR_INVALID) rather
+// than return labels computed with the wrong images.  The extent is measured
+// from the group's first member r: with o_q the minimum-image offset of member
+// q from r along an axis, extent = max o - min o.  Offsets below L/4 in every
+// axis bound it below L/2, so a first pass flags the groups with a member at
+// L/4 or more and the exact extent is taken for those only.
+
+// Minimum-image offset b - a along one axis (the canonical fold).
+__device__ __forceinline__ double mi_off(float a, float b, double L, double half) {
+    double d = (double)b - (double)a;
+    if (d > half) d -= L; else if (d < -half) d += L;
+    return d;
+}
+
+__global__ __launch_bounds__(kBlock) void k_extent_far(int64_t M, Geo g, const int32_t *__restrict__ mem,
+                                                       const int32_t *__restrict__ gid_of,
+                                                       const int32_t *__restrict__ g_start,
+                                                       const float4 *__restrict__ spos,
+                                                       int32_t *__restrict__ gflag,
+                                                       int32_t *__restrict__ farlist,
+                                                       uint32_t *__restrict__ nfar) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= M) return;
+    const int i = mem[t];
+    const int gi = gid_of[i];
+    const float4 pr = spos[mem[g_start[gi]]];
+    const float4 pi = spos[i];
+    const double q = 0.25 * g.L;
+    const bool far = fabs(mi_off(pr.x, pi.x, g.L, g.half)) >= q || fabs(mi_off(pr.y, pi.y, g.L, g.half)) >= q ||
+                     fabs(mi_off(pr.z, pi.z, g.L, g.half)) >= q;
+    if (far && atomicCAS(&gflag[gi], 0, 1) == 0) farlist[atomicAdd(nfar, 1u)] = gi;
+}
+
+// The exact extent of the flagged groups, one workgroup per group (grid-stride
+// over the list, its length read on the device).
+__global__ __launch_bounds__(kBlock) void k_extent_span(const uint32_t *__restrict__ nfar_p, Geo g,
+                                                        const int32_t *__restrict__ farlist,
+                                                        const int32_t *__restrict__ g_start,
+                                                        const int32_t *__restrict__ g_size,
+                                                        const int32_t *__restrict__ mem,
+                                                        const float4 *__restrict__ spos,
+                                                        int32_t *__restrict__ err) {
+    __shared__ double s_lo[3][kBlock / 64], s_hi[3][kBlock / 64];
+    const uint32_t nfar = *nfar_p;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (uint32_t f = blockIdx.x; f < nfar; f += gridDim.x) {
+        const int gi = farlist[f];
+        const int64_t start = g_start[gi], m = g_size[gi];
+        const float4 pr = spos[mem[start]];
+        double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
+        for (int64_t t = threadIdx.x; t < m; t += blockDim.x) {
+            const float4 pq = spos[mem[start + t]];
+            const double o[3] = {mi_off(pr.x, pq.x, g.L, g.half), mi_off(pr.y, pq.y, g.L, g.half),
+                                 mi_off(pr.z, pq.z, g.L, g.half)};
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                lo[a] = fmin(lo[a], o[a]);
+                hi[a] = fmax(hi[a], o[a]);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            for (int d = 32; d >= 1; d >>= 1) {
+                lo[a] = fmin(lo[a], __shfl_xor(lo[a], d, 64));
+                hi[a] = fmax(hi[a], __shfl_xor(hi[a], d, 64));
+            }
+            if (lane == 0) {
+                s_lo[a][wid] = lo[a];
+                s_hi[a][wid] = hi[a];
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            bool wide = false;
+            for (int a = 0; a < 3; a++) {
+                double l = s_lo[a][0], h = s_hi[a][0];
+                for (int w = 1; w < kBlock / 64; w++) {
+                    l = fmin(l, s_lo[a][w]);
+                    h = fmax(h, s_hi[a][w]);
+                }
+                wide = wide || h - l >= g.half;
+            }
+            if (wide) atomicOr(err, 8);
+        }
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------ acceptance and R
 // Smallest integer k >= 0 with T <= k^2 (both sides as the FP64 expressions
 // T and ii(k)); m when T > ii(m - 1) (beyond every k the search inspects).
@@ -541,6 +632,19 @@ void launch_segment_groups(int64_t n, int64_t G, Work &w, hipStream_t s) {
                        w.mem, w.gid_of);
     fill_u32(w.gccnt, 0u, G + 1, s);
     fill_u32(w.gcfill, 0u, G + 1, s);
+}
+
+void launch_extent(int64_t G, int64_t M, const Geo &g, Work &w, hipStream_t s) {
+    if (M <= 0) return;
+    // flags per group in g_nh and the flagged groups in glist (both free until
+    // the candidate stage fills them), their count in counters[12]
+    fill_i32(w.g_nh, 0, G + 1, s);
+    hipLaunchKernelGGL(k_extent_far, grid(M), dim3(kBlock), 0, s, M, g, w.mem, w.gid_of, w.g_start, w.spos,
+                       w.g_nh, w.glist, reinterpret_cast<uint32_t *>(w.counters + 12));
+    const int64_t blocks = G < 1024 ? G : 1024;
+    hipLaunchKernelGGL(k_extent_span, dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                       reinterpret_cast<const uint32_t *>(w.counters + 12), g, w.glist, w.g_start, w.g_size,
+                       w.mem, w.spos, w.err);
 }
 
 void launch_candidates_sort(int64_t n, int64_t G, int64_t NC, Work &w, hipStream_t s) {

@@ -544,7 +544,15 @@ __global__ __launch_bounds__(kBlock) void k_keys_from_labels(int64_t n, const in
     if (packed) {
         const uint2 v = packed[o];
         lab = (int32_t)v.x;
-        dens_s[i] = __uint_as_float(v.y);
+        // the candidate search orders densities by their bit patterns, which
+        // matches their values for non-negative numbers only: -0 becomes +0
+        // (the same value), NaN and negative values are rejected
+        uint32_t db = v.y == 0x80000000u ? 0u : v.y;
+        if ((db >> 31) != 0u || (db & 0x7fffffffu) > 0x7f800000u) {
+            atomicOr(err, 16);
+            db = 0u;
+        }
+        dens_s[i] = __uint_as_float(db);
     } else {
         lab = l0_in[o];
     }

@@ -207,13 +207,23 @@ hf_status prepare(Lane *c, int64_t n, const Geo &g, Work *w, bool extra) {
         if (c->arena) {
             // every call ends synchronized with its stream, so the old arena is idle
             HIP_OK(c, hipFree(c->arena));
+            if (c->budget) c->budget->give(c->arena_bytes);
             c->arena = nullptr;
             c->arena_bytes = 0;
         }
         size_t want = need + need / 8;
+        if (c->budget && !c->budget->take(want)) {
+            want = need;  // no headroom for the next, larger call
+            if (!c->budget->take(want))
+                return fail(c, HF_ERR_NOMEM,
+                            "the scratch arena of " + std::to_string(need) + " bytes exceeds the context's HBM budget (" +
+                                std::to_string(c->budget->held.load()) + " of " + std::to_string(c->budget->limit) +
+                                " bytes held)");
+        }
         if (hipMalloc(&c->arena, want) != hipSuccess) {
             (void)hipGetLastError();
             c->arena = nullptr;
+            if (c->budget) c->budget->give(want);
             return fail(c, HF_ERR_NOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed");
         }
         c->arena_bytes = want;
@@ -238,6 +248,11 @@ hf_status read_dev(Lane *c, hipStream_t s, std::initializer_list<const void *> s
 hf_status err_status(Lane *c, uint32_t err) {
     if (err & 1) return fail(c, HF_ERR_INVALID, "positions must lie in [0, box)");
     if (err & 2) return fail(c, HF_ERR_INVALID, "l0_id values must lie in [0, n]");
+    if (err & 16) return fail(c, HF_ERR_INVALID, "densities must be non-negative numbers");
+    if (err & 8)
+        return fail(c, HF_ERR_INVALID,
+                    "an L0 group spans half the periodic box or more along an axis (minimum-image "
+                    "distances would be ambiguous)");
     if (err & 4) return fail(c, HF_ERR_DEVICE, "internal error: L0 group key out of range");
     return HF_OK;
 }
@@ -274,6 +289,7 @@ hf_status run_compaso(Lane *c, int64_t n, const Geo &g, Work &w, int32_t *halo_i
     c->stats.n_groups = G;
     c->stats.n_members = r[1];
     hf::launch_segment_groups(n, G, w, s);
+    hf::launch_extent(G, c->stats.n_members, g, w, s);
     HIP_OK(c, hipEventRecord(c->ev[4], s));
     hf::launch_candidates(n, g, w, s);
     hf::scan_u32(w.gccnt, w.gcoff, G, w.scan_tmp, s);
@@ -357,7 +373,12 @@ hf_status begin(Lane *c, const float *pos, int64_t n, const hf_params *p, Geo *g
     uint32_t counts[4];
     hf::collect_words(c->host, 4, counts);
     st = err_status(c, counts[3]);
-    if (st != HF_OK) return st;
+    if (st != HF_OK) {
+        // the sub-cell tables may still run on s: a failed call also ends
+        // synchronized with its stream, so the arena is idle when it returns
+        HIP_OK(c, hipStreamSynchronize(s));
+        return st;
+    }
     w->nchunks = counts[0];
     w->ndcells = counts[1];
     w->nsparse = counts[2];
@@ -390,6 +411,7 @@ void lane_release(Lane *L) {
     if (L->arena) {
         (void)hipSetDevice(L->device);
         (void)hipFree(L->arena);
+        if (L->budget) L->budget->give(L->arena_bytes);
     }
     L->arena = nullptr;
     L->arena_bytes = 0;
@@ -488,7 +510,7 @@ hf_status hf_derived(const hf_params *p, int64_t n, double *out) {
     return derive(p, n, out);
 }
 
-hf_status hf_create(hf_ctx **out, int device) {
+hf_status hf_create(hf_ctx **out, int device, uint64_t hbm_budget_bytes) {
     if (!out) return HF_ERR_INVALID;
     *out = nullptr;
     int count = 0;
@@ -500,6 +522,8 @@ hf_status hf_create(hf_ctx **out, int device) {
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) return HF_ERR_DEVICE;
     if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return HF_ERR_UNSUPPORTED;
     hf_ctx *c = new hf_ctx();
+    c->budget.limit = hbm_budget_bytes;
+    c->main.budget = &c->budget;
     if (hf::lane_init(&c->main, device, false) != HF_OK) {
         hf::lane_destroy(&c->main);
         delete c;

@@ -225,6 +225,9 @@ void launch_fof_labels(int64_t n, const Geo &g, Work &w, int32_t *l0_out, hipStr
 void launch_keys_from_labels(const int32_t *l0_in, const float *dens_in, int64_t n, Work &w, hipStream_t s);
 void launch_segment(int64_t n, Work &w, hipStream_t s);
 void launch_segment_groups(int64_t n, int64_t G, Work &w, hipStream_t s);
+// Extent check of the L0 groups (sets err bit 8 when a group spans half the
+// box or more along an axis); M members in G groups.
+void launch_extent(int64_t G, int64_t M, const Geo &g, Work &w, hipStream_t s);
 void launch_candidates(int64_t n, const Geo &g, Work &w, hipStream_t s);   // candidates.hip
 void launch_candidates_sort(int64_t n, int64_t G, int64_t NC, Work &w, hipStream_t s);
 // Groups with candidates (their count is read on the device; grid bound

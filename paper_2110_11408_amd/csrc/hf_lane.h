@@ -5,6 +5,7 @@
 // hf_find_batch; a server owns one lane per slot.
 #pragma once
 
+#include <atomic>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -14,8 +15,24 @@
 
 namespace hf {
 
+// Device memory budget shared by the lanes of one context: arenas grow only
+// while the bytes held by all of them stay within the limit (0: no limit).
+struct Budget {
+    uint64_t limit = 0;
+    std::atomic<uint64_t> held{0};
+    bool take(uint64_t b) {
+        uint64_t cur = held.load();
+        do {
+            if (limit && cur + b > limit) return false;
+        } while (!held.compare_exchange_weak(cur, cur + b));
+        return true;
+    }
+    void give(uint64_t b) { held.fetch_sub(b); }
+};
+
 struct Lane {
     int device = 0;
+    Budget *budget = nullptr;      // the owning context's, or null (no accounting)
     void *arena = nullptr;
     size_t arena_bytes = 0;
     hipEvent_t ev[10] = {};
@@ -43,6 +60,7 @@ hf_status lane_find(Lane *L, const float *pos, int64_t n, const hf_params *p, fl
 }  // namespace hf
 
 struct hf_ctx {
+    hf::Budget budget;
     hf::Lane main;
     std::vector<std::unique_ptr<hf::Lane>> pool;  // lanes of hf_find_batch, created on demand
 };

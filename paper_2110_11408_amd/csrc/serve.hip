@@ -76,6 +76,7 @@ hf_status hf_find_batch(hf_ctx *ctx, int32_t n_boxes, const int64_t *box_offsets
     const int k = std::min(std::min(n_lanes > 0 ? n_lanes : kDefaultLanes, kMaxLanes), (int)n_boxes);
     while ((int)ctx->pool.size() < k) {
         auto L = std::make_unique<hf::Lane>();
+        L->budget = &ctx->budget;
         if (hf::lane_init(L.get(), ctx->main.device, true) != HF_OK) {
             hf::lane_destroy(L.get());
             return batch_fail(ctx, HF_ERR_DEVICE, "could not create a batch lane");

@@ -39,10 +39,9 @@ def assert_same_labels(gpu, ref):
     np.testing.assert_array_equal(t["n_enclosed"], r["ienc"])
 
 
-def matched_agreement(lab_a, lab_b):
-    """Fraction of particles whose label in a maps to their label in b, where each
-    label of a is mapped to the label of b it shares most particles with (0 maps
-    to 0).  Returns (fraction, mismatched particle indices)."""
+def label_mapping(lab_a, lab_b):
+    """Each label of a mapped to the label of b it shares most particles with
+    (0 maps to 0)."""
     n = len(lab_a)
     mapping = {0: 0}
     order = np.lexsort((lab_b, lab_a))
@@ -55,7 +54,38 @@ def matched_agreement(lab_a, lab_b):
             continue
         vals, cnt = np.unique(b_s[s:e], return_counts=True)
         mapping[la] = int(vals[np.argmax(cnt)])
-    mapped = np.array([mapping[int(x)] for x in lab_a]) if n < 200000 else \
-        np.vectorize(mapping.get)(lab_a)
+    return mapping
+
+
+def _apply(mapping, lab):
+    keys = np.fromiter(mapping.keys(), np.int64, len(mapping))
+    vals = np.fromiter(mapping.values(), np.int64, len(mapping))
+    order = np.argsort(keys)
+    keys, vals = keys[order], vals[order]
+    idx = np.searchsorted(keys, lab)
+    return vals[idx]
+
+
+def matched_agreement(lab_a, lab_b):
+    """Fraction of particles whose label in a maps to their label in b, where each
+    label of a is mapped to the label of b it shares most particles with (0 maps
+    to 0).  Returns (fraction, mismatched particle indices)."""
+    n = len(lab_a)
+    mapped = _apply(label_mapping(lab_a, lab_b), lab_a)
     bad = np.nonzero(mapped != lab_b)[0]
     return 1.0 - len(bad) / max(n, 1), bad
+
+
+def explained_mismatches(bad, l0_other, l0_ref, ev):
+    """For each mismatched particle q (indices ``bad``) whether the oracle's
+    near-threshold events ``ev`` (computed on the reference field, whose L0
+    labels are ``l0_ref``) explain it: q itself sits at the L0 cut, or its
+    reference L0 group is touched by an event, or the other side's L0 group of
+    q maps to such a group."""
+    import oracle
+    bad = np.asarray(bad, dtype=np.int64)
+    flagged = np.unique(l0_ref[(ev & oracle.EV_GROUP) != 0])
+    flagged = flagged[flagged > 0]
+    mapped = _apply(label_mapping(l0_other, l0_ref), l0_other[bad])
+    return (((ev[bad] & oracle.EV_L0CUT) != 0) | np.isin(l0_ref[bad], flagged) |
+            np.isin(mapped, flagged))

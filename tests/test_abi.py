@@ -81,7 +81,7 @@ def test_create_without_gpu_is_unsupported(lib):
     except Exception:
         pass
     h = ctypes.c_void_p()
-    assert lib.hf_create(ctypes.byref(h), 0) == _lib.HF_ERR_UNSUPPORTED
+    assert lib.hf_create(ctypes.byref(h), 0, 0) == _lib.HF_ERR_UNSUPPORTED
 
 
 def _c_layout():

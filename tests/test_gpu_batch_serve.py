@@ -21,9 +21,13 @@ from tests.gpu_helpers import assert_same_labels, density_violations
 
 pytestmark = pytest.mark.gpu
 
-# (n, seed, nmax, halo_frac); n = 0 is an empty box of side 10
+# (n, seed, nmax, halo_frac); n = 0 is an empty box of side 10.  The last box
+# (3.2M particles, haloes up to 20000 particles) is of the size of the largest
+# batched boxes and served requests: its largest L0 groups keep part of their
+# acceptance histograms in global memory.
 SPECS = [(3000, 201, 500, 0.5), (0, 0, 0, 0.0), (20000, 202, 3000, 0.6), (700, 203, 200, 0.4),
-         (9001, 204, 1500, 0.5), (45000, 205, 6000, 0.3)]
+         (9001, 204, 1500, 0.5), (45000, 205, 6000, 0.3), (3200000, 206, 20000, 0.6)]
+BIG = 6
 
 
 def _say(*a):
@@ -155,7 +159,8 @@ def test_server_mix_equals_single_calls(boxes, singles):
     from paper_2110_11408_amd.api import Server
     srv = Server(0, slots=3, budget_bytes=8 << 30)
     try:
-        order = [0, 2, 3, 4, 5, 0, 5, 4, 3, 2]   # repeats share the device with others
+        # repeats share the device with others; the 3.2M box runs beside small ones
+        order = [0, 2, BIG, 3, 4, 5, 0, 5, BIG, 4, 3, 2]
         tickets = []
         for b in order:
             pos, L = boxes[b]
