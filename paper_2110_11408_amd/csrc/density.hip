@@ -10,10 +10,20 @@
 // come from one FP32 matrix-core product (the squared distance expanded into
 // a rank-4 inner product), so the vector ALU only clamps and sums; blocks of
 // 16 lanes that hold no particle are skipped.  The self pair is masked out and
-// added back as exactly 1 when it counts.  Sparse cells: one thread per
-// particle, the difference form d = x_j - x_i on the vector ALU.  Partial sums
-// run in FP32 over bounded stretches and are accumulated in FP64 in a fixed
-// order, so the result does not depend on the launch shape.
+// added back as exactly 1 when it counts.  Partial sums run in FP32 over
+// bounded stretches and are accumulated in FP64 in a fixed order, so the
+// result does not depend on the launch shape.
+//
+// Particles of sparse cells have few neighbours, often near r = b where the
+// weights are small, so the tolerance of their density is only about 1e-6 in
+// the weight sum: every pair that involves one of them is evaluated in FP64
+// from the original float positions (minimum-image difference, 1 - d^2/b^2),
+// by one thread per sparse particle for its sparse neighbour cells, and by the
+// dense chunks for the sparse particles around them (one lane per sparse
+// particle, summing over the chunk's particles, added in fixed point).  The
+// rank-4 form has terms up to about 6 in magnitude, so its weights are only
+// good to a few 1e-7 each; that suffices for dense-cell particles, whose sums
+// have many terms.
 #include <stdlib.h>
 
 #include "hf_internal.h"
@@ -22,38 +32,24 @@ namespace hf {
 
 namespace {
 
-// Accumulate one neighbour cell [a, b) for an i-particle at shifted local
-// coordinates (xs, ys, zs) (the sparse-cell kernel, one particle per lane).
-// Two neighbours per step keep that kernel at eight wavefronts per SIMD; it
-// waits on memory, and the extra wavefronts hide more than four loads in
-// flight per lane would.
-__device__ __forceinline__ void accum_range(const float4 *__restrict__ sloc, uint32_t a, uint32_t b,
-                                            float xs, float ys, float zs, double &acc) {
-    for (uint32_t j0 = a; j0 < b; j0 += 64) {
-        const uint32_t e = min(j0 + 64u, b);
-        float p = 0.0f;
-        uint32_t j = j0;
-        for (; j + 2 <= e; j += 2) {
-#pragma unroll
-            for (int u = 0; u < 2; u++) {
-                const float4 lj = sloc[j + u];
-                const float dx = lj.x - xs, dy = lj.y - ys, dz = lj.z - zs;
-                float t = fmaf(-dx, dx, 1.0f);
-                t = fmaf(-dy, dy, t);
-                t = fmaf(-dz, dz, t);
-                p += fmaxf(t, 0.0f);
-            }
-        }
-        for (; j < e; j++) {
-            const float4 lj = sloc[j];
-            const float dx = lj.x - xs, dy = lj.y - ys, dz = lj.z - zs;
-            float t = fmaf(-dx, dx, 1.0f);
-            t = fmaf(-dy, dy, t);
-            t = fmaf(-dz, dz, t);
-            p += fmaxf(t, 0.0f);
-        }
-        acc += (double)p;
-    }
+// Weight 1 - d^2/b^2 (0 beyond b) of particle j about particle i in FP64, from
+// the float positions with the minimum-image fold of each axis.
+__device__ __forceinline__ double weight64(const float4 &pi, const float4 &pj, const Geo &g) {
+    double dx = (double)pj.x - (double)pi.x;
+    double dy = (double)pj.y - (double)pi.y;
+    double dz = (double)pj.z - (double)pi.z;
+    if (dx > g.half) dx -= g.L; else if (dx < -g.half) dx += g.L;
+    if (dy > g.half) dy -= g.L; else if (dy < -g.half) dy += g.L;
+    if (dz > g.half) dz -= g.L; else if (dz < -g.half) dz += g.L;
+    const double t = 1.0 - (dx * dx + dy * dy + dz * dz) * g.inv_b2;
+    return t > 0.0 ? t : 0.0;
+}
+
+// Accumulate one neighbour cell [a, b) for particle i (the sparse-cell kernel,
+// one particle per lane; its own cell includes i, whose weight is exactly 1).
+__device__ __forceinline__ void accum_range(const float4 *__restrict__ spos, uint32_t a, uint32_t b,
+                                            const float4 &pi, const Geo &g, double &acc) {
+    for (uint32_t j = a; j < b; j++) acc += weight64(pi, spos[j], g);
 }
 
 // Dense-neighbour contributions of sparse particles are added in fixed point
@@ -103,8 +99,7 @@ __device__ __forceinline__ void density_chunk(const Geo &g, uint32_t h, uint32_t
                                               const uint32_t *__restrict__ off,
                                               const uint32_t *__restrict__ s_sparse,
                                               uint64_t *__restrict__ dfx, float *__restrict__ dens_s,
-                                              float *__restrict__ dens_out, float (*colsum)[16],
-                                              float *__restrict__ cl) {
+                                              float *__restrict__ dens_out, float *__restrict__ cl) {
     const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
     const int loff = 4 * col + grp;  // this lane's word of a block of 16 pq records
     // this lane's word of the block of 16 records from j0, as a buffer load
@@ -253,40 +248,14 @@ __device__ __forceinline__ void density_chunk(const Geo &g, uint32_t h, uint32_t
         setup(k);
         // one block: 16 neighbours [j0, j0 + 16) of range k (ending at b),
         // this lane's component val
-        auto block = [&](uint32_t j0, uint32_t b, int k, bool sparse, float val) {
+        auto block = [&](uint32_t j0, uint32_t b, float val) {
             const uint32_t rem = b - j0;
             const float bv = (grp == 3 && (uint32_t)col >= rem) ? -1e30f : val;
-            if (sparse) {
-                // sparse cell: the column's weights also go to its particle.
-                // Each lane sums its column entries (a fixed tree), the four
-                // row groups are added by two exchanges, and the column's
-                // total waits in LDS for the atomics after the last block.
-                float part[R];
 #pragma unroll
-                for (int r = 0; r < R; r++) {
-                    const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x4f32(As[r], bv, Cs[r], 0, 0, 0);
-                    float w[4];
+            for (int r = 0; r < R; r++) {
+                const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x4f32(As[r], bv, Cs[r], 0, 0, 0);
 #pragma unroll
-                    for (int u = 0; u < 4; u++) {
-                        w[u] = clamp0(d[u]);
-                        pf[4 * r + u] += w[u];
-                    }
-                    part[r] = (w[0] + w[1]) + (w[2] + w[3]);
-                }
-                float cs = part[0];
-                if (R == 2) cs = part[0] + part[1];
-                if (R == 3) cs = (part[0] + part[1]) + part[2];
-                if (R == 4) cs = (part[0] + part[1]) + (part[2] + part[3]);
-                cs += __shfl_xor(cs, 16);
-                cs += __shfl_xor(cs, 32);
-                if (grp == 0) colsum[k][col] = cs;
-            } else {
-#pragma unroll
-                for (int r = 0; r < R; r++) {
-                    const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x4f32(As[r], bv, Cs[r], 0, 0, 0);
-#pragma unroll
-                    for (int u = 0; u < 4; u++) pf[4 * r + u] += clamp0(d[u]);
-                }
+                for (int u = 0; u < 4; u++) pf[4 * r + u] += clamp0(d[u]);
             }
             flush();
         };
@@ -315,16 +284,14 @@ __device__ __forceinline__ void density_chunk(const Geo &g, uint32_t h, uint32_t
         // turn; longer batches would cost the sixth wavefront per SIMD).  A
         // position past the stream's end loads the chunk's own first block
         // instead and is skipped.
-        bool sparse = ((spm >> k) & 1ull) != 0;  // the current range is a sparse cell
         auto use = [&](int bk, uint32_t bj, float v) {
             if (bk < 0) return;
             if (bk != k) {
                 k = bk;
                 b = (uint32_t)__builtin_amdgcn_readlane((int)rb, k);
-                sparse = ((spm >> k) & 1ull) != 0;
                 setup(k);
             }
-            block(bj, b, k, sparse, v);
+            block(bj, b, v);
         };
         constexpr int kB = 2;  // blocks per batch
         int ka[kB], kb[kB];
@@ -354,10 +321,12 @@ __device__ __forceinline__ void density_chunk(const Geo &g, uint32_t h, uint32_t
             if (ka[0] < 0) break;
         }
     }
-    // The sparse particles' shares, in fixed point: the columns of all
-    // sparse ranges are numbered in range order and handled 64 per pass, one
-    // per lane (its range and column found by one scalar walk over the
-    // ranges), so the conversion and the atomic run once per pass.
+    // The sparse particles' shares from this chunk, in FP64 and added in fixed
+    // point: the particles of all sparse ranges are numbered in range order
+    // and handled 64 per pass, one per lane (its range and column found by one
+    // scalar walk over the ranges); each lane sums the weights of the chunk's
+    // particles in order (wave-uniform loads), then adds its total with one
+    // atomic.
     uint32_t ntot = 0;
     for (uint64_t m = spm; m; m &= m - 1) {
         const int k = __builtin_ctzll(m);
@@ -365,26 +334,24 @@ __device__ __forceinline__ void density_chunk(const Geo &g, uint32_t h, uint32_t
     }
     for (uint32_t p0 = 0; p0 < ntot; p0 += 64) {
         const uint32_t q = p0 + (uint32_t)lane;  // this lane's column number
-        int kk = 0;
-        uint32_t cc = 0, dst = 0;
+        uint32_t js = h, dst = 0;                 // its particle and sparse ordinal
         uint32_t pre = 0;
         for (uint64_t m = spm; m; m &= m - 1) {
             const int k = __builtin_ctzll(m);
-            const uint32_t cnt = (uint32_t)__builtin_amdgcn_readlane((int)rb, k) -
-                                 (uint32_t)__builtin_amdgcn_readlane((int)ra, k);
+            const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)ra, k);
+            const uint32_t cnt = (uint32_t)__builtin_amdgcn_readlane((int)rb, k) - a;
             if (q >= pre && q < pre + cnt) {
-                kk = k;
-                cc = q - pre;
-                dst = (uint32_t)__builtin_amdgcn_readlane((int)sb, k) + cc;
+                js = a + (q - pre);
+                dst = (uint32_t)__builtin_amdgcn_readlane((int)sb, k) + (q - pre);
             }
             pre += cnt;
         }
-        if (q < ntot) {
-            const float v = colsum[kk][cc];
-            if (v > 0.0f)
-                atomicAdd(reinterpret_cast<unsigned long long *>(&dfx[dst]),
-                          (unsigned long long)__double2ll_rn((double)v * kFixScale));
-        }
+        const float4 pj = spos[js];
+        double v = 0.0;
+        for (uint32_t r = h; r < end; r++) v += weight64(spos[r], pj, g);
+        if (q < ntot && v > 0.0)
+            atomicAdd(reinterpret_cast<unsigned long long *>(&dfx[dst]),
+                      (unsigned long long)__double2ll_rn(v * kFixScale));
     }
     reduce();
     const uint32_t ii = h + 16u * (uint32_t)(col >> 2) + 4u * (uint32_t)grp + (uint32_t)(col & 3);
@@ -416,13 +383,11 @@ __global__ __launch_bounds__(64, 6) void k_density_dense(int64_t nchunks, Geo g,
     const uint32_t cend = __builtin_amdgcn_readfirstlane(off[c + 1]);
     const uint32_t end = min(h + 64u, cend);
     const float *p = reinterpret_cast<const float *>(pq);
-    // column sums of the sparse neighbour cells, and the rows' accumulator
-    // inputs
-    __shared__ float cs[27][16];
+    // the rows' accumulator inputs
     __shared__ float cl[16 * 64];
-#define HF_DENSITY_CHUNK(RR)                                                                            \
-    (narrow ? density_chunk<RR, true>(g, h, c, end, p, spos, off, s_sparse, dfx, dens_s, dens_out, cs, cl) \
-            : density_chunk<RR, false>(g, h, c, end, p, spos, off, s_sparse, dfx, dens_s, dens_out, cs, cl))
+#define HF_DENSITY_CHUNK(RR)                                                                        \
+    (narrow ? density_chunk<RR, true>(g, h, c, end, p, spos, off, s_sparse, dfx, dens_s, dens_out, cl) \
+            : density_chunk<RR, false>(g, h, c, end, p, spos, off, s_sparse, dfx, dens_s, dens_out, cl))
     switch ((end - h + 15u) >> 4) {
     case 1: HF_DENSITY_CHUNK(1); break;
     case 2: HF_DENSITY_CHUNK(2); break;
@@ -446,6 +411,7 @@ __global__ __launch_bounds__(kBlock) void k_density_sparse(int64_t nsparse, Geo 
     if (t >= nsparse) return;
     const int64_t i = sparse[t];
     const float4 li = sloc[i];
+    const float4 pi = spos[i];
     const uint32_t c = __float_as_uint(li.w);
     const int nc = g.nc;
     const int cx = (int)(c % (uint32_t)nc), cy = (int)((c / (uint32_t)nc) % (uint32_t)nc),
@@ -457,7 +423,7 @@ __global__ __launch_bounds__(kBlock) void k_density_sparse(int64_t nsparse, Geo 
     double acc = 0.0;
     for (int oz = -1; oz <= 1; oz++) {
         const int z = wrapc(cz + oz, nc);
-        const float zs = li.z - (float)oz * g.cellb;
+        const float gz = oz < 0 ? li.z : (oz > 0 ? g.cellb - li.z : 0.0f);
         // the offsets of this plane are loaded together so their latencies overlap
         uint32_t ra[9], rb[9];
 #pragma unroll
@@ -484,13 +450,16 @@ __global__ __launch_bounds__(kBlock) void k_density_sparse(int64_t nsparse, Geo 
         }
 #pragma unroll
         for (int oy = -1; oy <= 1; oy++) {
-            const float ys = li.y - (float)oy * g.cellb;
+            const float gy = oy < 0 ? li.y : (oy > 0 ? g.cellb - li.y : 0.0f);
 #pragma unroll
             for (int ox = -1; ox <= 1; ox++) {
                 const int r = (oy + 1) * 3 + (ox + 1);
                 if (rb[r] - ra[r] >= (uint32_t)kDenseMin) continue;
-                const float xs = li.x - (float)ox * g.cellb;
-                accum_range(sloc, ra[r], rb[r], xs, ys, zs, acc);
+                // a cell whose nearest face is b or more away (by a margin far
+                // above the rounding of the local coordinates) weighs nothing
+                const float gx = ox < 0 ? li.x : (ox > 0 ? g.cellb - li.x : 0.0f);
+                if (gx * gx + gy * gy + gz * gz >= 1.0f + 1e-5f) continue;
+                accum_range(spos, ra[r], rb[r], pi, g, acc);
             }
         }
     }

@@ -85,6 +85,7 @@ hf_status make_geo(Lane *c, const hf_params *p, int64_t n, Geo *g) {
     g->cell = L / g->nc;
     g->inv_cell = (double)g->nc / L;
     g->inv_b = 1.0 / d[D_B];
+    g->inv_b2 = 1.0 / d[D_B2];
     g->cellb = (float)(g->cell / d[D_B]);
     // sub-cells: diagonal below l (with a 0.1% margin), at most 6 per side
     double kd = floor(g->cell * sqrt(3.0) / d[D_L] * (1.0 + 1e-3)) + 1.0;

@@ -18,6 +18,7 @@ struct Geo {
     double L, half;        // periodic side and L/2 (minimum-image test)
     double cell, inv_cell; // binning cell side (>= max(b, l)) and its inverse
     double inv_b;          // 1/b: local coordinates are stored in units of b
+    double inv_b2;         // 1/b^2: FP64 kernel weights 1 - r^2/b^2
     float cellb;           // cell / b in FP32 (image offset of a neighbour cell)
     int nc;                // cells per side (>= 3)
     int ksub;              // sub-cells per cell side (sub-cell diagonal < l)

@@ -394,16 +394,45 @@ def test_full_size_256_labels_bit_exact(run256):
     np.testing.assert_array_equal(tab["n_enclosed"][in_pick], res["table"]["ienc"])
 
 
+@pytest.fixture(scope="module")
+def d64_256(run256):
+    pos, L, _ = run256
+    _say("[gpu] plain256: oracle FP64 densities over the whole box")
+    return oracle.density(pos, box=L)
+
+
+def _cell_counts(pos, L, rmin):
+    """Particles in each particle's binning cell (cells of side >= rmin)."""
+    nc = int(np.floor(L / (rmin * (1 + 1e-6))))
+    c = np.minimum(np.floor(pos.astype(np.float64) * (nc / L)).astype(np.int64), nc - 1)
+    key = (c[:, 2] * nc + c[:, 1]) * nc + c[:, 0]
+    _, inv, cnt = np.unique(key, return_inverse=True, return_counts=True)
+    return cnt[inv]
+
+
 @pytest.mark.timeout(900)
-def test_full_size_256_fp64_attribution(run256):
+def test_full_size_256_density_every_particle(run256, d64_256):
+    """Every one of the 16.8M densities within 1e-5 max(Delta, 1) of the
+    oracle's FP64 value; the worst error relative to that bound is reported for
+    particles of dense cells (matrix-core sums) and of sparse ones (FP64)."""
+    pos, L, g = run256
+    err = np.abs(g["density"].astype(np.float64) - d64_256) / (DENS_REL * np.maximum(np.abs(d64_256), 1.0))
+    dense = _cell_counts(pos, L, 0.4) >= 8
+    _say(f"[gpu] plain256 density error / bound: dense max {err[dense].max():.3f} "
+         f"(p99.99 {np.percentile(err[dense], 99.99):.3f}), sparse max {err[~dense].max():.3f}")
+    worst = int(np.argmax(err))
+    assert err[worst] <= 1.0, (worst, g["density"][worst], d64_256[worst], bool(dense[worst]))
+
+
+@pytest.mark.timeout(900)
+def test_full_size_256_fp64_attribution(run256, d64_256):
     """Against the oracle's FP64 field on the whole 256^3 box: L0 labels agree
     to >= 99.99% and every mismatch is explained by a near-threshold event; on
     sampled L0 groups (the oracle's CompaSO on its own FP64 groups) every halo
     label mismatch is explained too."""
     pos, L, g = run256
-    _say("[gpu] plain256: oracle FP64 densities, FoF and events over the whole box")
-    d64 = oracle.density(pos, box=L)
-    assert len(density_violations(g["density"], d64)) == 0
+    d64 = d64_256
+    _say("[gpu] plain256: oracle FP64 FoF and events over the whole box")
     l0_64, _ = oracle.fof(pos, d64, box=L)
     ev = oracle.events(pos, d64, l0_64, tol=DENS_REL, box=L)
     frac, bad = matched_agreement(g["l0"], l0_64)
