@@ -208,6 +208,21 @@ hf_status hf_find(hf_ctx *ctx, const float *pos, int64_t n, const hf_params *p,
                   float *density, int32_t *l0_id, int32_t *halo_id, hf_halo *halos,
                   int64_t halos_cap, int64_t *n_halos, void *stream);
 
+/* hf_find for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * pass, outputs and errors as hf_find, with its scratch arena carved from a
+ * static device array of 256 MiB that every GPU the library runs on holds until
+ * the process ends (hf_create takes its address).  It calls no hipMalloc,
+ * hipFree or allocating library routine.  A box needing more scratch than that
+ * (about 6e5 particles at mean density 1 with the default parameters; the need
+ * grows with n and with the cell grid box^3 / max(b, l)^3) is refused with
+ * HF_ERR_INVALID before anything is enqueued.  Every context on one GPU shares
+ * that array, which keeps the last call's contents: calls that overlap on one
+ * GPU (several streams or threads) race and must be serialized by the caller. */
+hf_status hf_find_noalloc(hf_ctx *ctx, const float *pos, int64_t n, const hf_params *p,
+                          float *density, int32_t *l0_id, int32_t *halo_id, hf_halo *halos,
+                          int64_t halos_cap, int64_t *n_halos, void *stream);
+
 /* ---- Many boxes per call ------------------------------------------------
  * hf_find on n_boxes independent periodic boxes (Sec. 2.2 applied to each box
  * on its own).  Box b holds particles [box_offsets[b], box_offsets[b+1]) of the

@@ -18,7 +18,7 @@ STATUS = {0: "HF_OK", 1: "HF_ERR_INVALID", 2: "HF_ERR_NOMEM", 3: "HF_ERR_CAPACIT
           4: "HF_ERR_DEVICE", 5: "HF_ERR_UNSUPPORTED"}
 
 EXPORTS = ["hf_default_params", "hf_params_at_redshift", "hf_derived", "hf_create", "hf_destroy", "hf_last_error",
-           "hf_get_stats", "hf_density", "hf_l0_fof", "hf_compaso", "hf_find", "hf_count_pairs",
+           "hf_get_stats", "hf_density", "hf_l0_fof", "hf_compaso", "hf_find", "hf_find_noalloc", "hf_count_pairs",
            "hf_halo_stats",
            "hf_find_batch", "hf_server_create", "hf_server_submit", "hf_server_wait",
            "hf_server_now", "hf_server_held_bytes", "hf_server_last_error", "hf_server_destroy"]
@@ -110,6 +110,7 @@ def load(path: str = LIB_PATH):
         lib.hf_l0_fof.argtypes = [P, P, P, I64, PP, P, P, P]
         lib.hf_compaso.argtypes = [P, P, P, P, I64, PP, P, P, I64, P, P]
         lib.hf_find.argtypes = [P, P, I64, PP, P, P, P, P, I64, P, P]
+        lib.hf_find_noalloc.argtypes = [P, P, I64, PP, P, P, P, P, I64, P, P]
         lib.hf_count_pairs.argtypes = [P, P, I64, PP, P, P]
         lib.hf_halo_stats.argtypes = [P, P, P, P, I64, PP, I64, P, P, P, P]
         lib.hf_find_batch.argtypes = [P, ctypes.c_int32, P, P, P, P, P, P, P, P, P, ctypes.c_int32, P]
@@ -126,7 +127,7 @@ def load(path: str = LIB_PATH):
         lib.hf_server_destroy.argtypes = [P]
         lib.hf_server_destroy.restype = None
         for name in ("hf_derived", "hf_params_at_redshift", "hf_create", "hf_get_stats", "hf_density", "hf_l0_fof",
-                     "hf_compaso", "hf_find", "hf_count_pairs", "hf_halo_stats", "hf_find_batch",
+                     "hf_compaso", "hf_find", "hf_find_noalloc", "hf_count_pairs", "hf_halo_stats", "hf_find_batch",
                      "hf_server_create", "hf_server_submit", "hf_server_wait"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib

@@ -115,6 +115,19 @@ class Context:
                 _ptr(buf), cap, ctypes.byref(nh), _stream(pos.device)),
             halos_cap, n, pos.device, {"density": dens, "l0_id": l0, "halo_id": halo_id})
 
+    def find_noalloc(self, pos, p: HfParams, halo_id, halos, density=None, l0_id=None) -> int:
+        """hf_find_noalloc into caller-allocated device tensors (halo_id int32 [n],
+        halos int32 [cap, HALO_WORDS], density / l0_id optional): the library's
+        scratch is its static device array, so the call allocates nothing.
+        Returns the halo count; raises on any error (HF_ERR_CAPACITY included)."""
+        pos = _check_pos(pos)
+        nh = ctypes.c_int64(0)
+        st = self.lib.hf_find_noalloc(self.h, _ptr(pos), pos.shape[0], ctypes.byref(p), _ptr(density),
+                                      _ptr(l0_id), _ptr(halo_id), _ptr(halos), int(halos.shape[0]),
+                                      ctypes.byref(nh), _stream(pos.device))
+        self._raise(st)
+        return int(nh.value)
+
     def halo_stats(self, pos, density, halo_id, p: HfParams, n_halos: int, want_members=True):
         """hf_halo_stats: level 2 inside the L1 halos labelled by halo_id and the
         Table 1 position statistics.  Returns a dict of numpy columns (one row

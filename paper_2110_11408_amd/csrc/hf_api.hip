@@ -5,11 +5,42 @@
 #include <string.h>
 
 #include <initializer_list>
+#include <mutex>
 #include <string>
 
 #include "hf_lane.h"
 
 #define HF_PI 3.14159265358979323846
+
+// Scratch of hf_find_noalloc: a region of device memory that every GPU the
+// library runs on holds from the load of the code object to the end of the
+// process, so that the entry point allocates nothing.  Host code never uses the
+// array's name as an address: its device address is taken once per device with
+// hipGetSymbolAddress (hf_create) and kept in scratch_addr.
+static __device__ __align__(256) unsigned char scratch[hf::kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void *scratch_addr[kMaxDevices] = {};
+
+// Device address of the scratch array on `device` (current), or null.
+void *scratch_of(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_addr[device]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        scratch_addr[device] = ptr;
+    }
+    return scratch_addr[device];
+}
+
+}  // namespace
 
 namespace {
 
@@ -198,12 +229,24 @@ size_t carve(char *base, int64_t n, int64_t ncell, int nsub, int64_t rhl, bool e
     return c.off + 256;
 }
 
-hf_status prepare(Lane *c, int64_t n, const Geo &g, Work *w, bool extra) {
+hf_status prepare(Lane *c, int64_t n, const Geo &g, Work *w, bool extra, const hf::FixedArena *fx) {
     int64_t ncell = (int64_t)g.nc * g.nc * g.nc;
     const int nsub = g.ksub * g.ksub * g.ksub;
     const int64_t rhl = hf::radix_hist_len(n, g);
     size_t need = carve(nullptr, n, ncell, nsub, rhl, extra, w);
     HIP_OK(c, hipSetDevice(c->device));
+    if (fx) {
+        // a caller-given region: nothing is allocated
+        if (need > fx->bytes)
+            return fail(c, HF_ERR_INVALID,
+                        "this box needs " + std::to_string(need) + " bytes of scratch, more than the " +
+                            std::to_string(fx->bytes) + " of the static scratch");
+        carve((char *)fx->base, n, ncell, nsub, rhl, extra, w);
+        w->host = c->host;
+        c->stats = hf_stats{};
+        c->stats.n_cells = ncell;
+        return HF_OK;
+    }
     if (need > c->arena_bytes) {
         if (c->arena) {
             // every call ends synchronized with its stream, so the old arena is idle
@@ -334,7 +377,7 @@ hf_status run_compaso(Lane *c, int64_t n, const Geo &g, Work &w, int32_t *halo_i
 // dens: the call computes densities (binning also writes the records the
 // density kernel reads); extra: halo statistics buffers.
 hf_status begin(Lane *c, const float *pos, int64_t n, const hf_params *p, Geo *g, Work *w,
-                hipStream_t s, bool dens, bool extra = false) {
+                hipStream_t s, bool dens, bool extra = false, const hf::FixedArena *fx = nullptr) {
     if (!c) return HF_ERR_INVALID;
     c->err.clear();
     if (!p) return fail(c, HF_ERR_INVALID, "params is NULL");
@@ -350,7 +393,7 @@ hf_status begin(Lane *c, const float *pos, int64_t n, const hf_params *p, Geo *g
     hf_status st = make_geo(c, p, n, g);
     if (st != HF_OK) return st;
     if (!pos) return fail(c, HF_ERR_INVALID, "pos is NULL");
-    st = prepare(c, n, *g, w, extra);
+    st = prepare(c, n, *g, w, extra, fx);
     if (st != HF_OK) return st;
     if (!dens) w->pq = nullptr;
     hf::fill_i32(w->counters, 0, 16, s);
@@ -442,12 +485,12 @@ size_t lane_arena_bytes(const hf_params *p, int64_t n) {
 
 hf_status lane_find(Lane *c, const float *pos, int64_t n, const hf_params *p, float *density,
                     int32_t *l0_id, int32_t *halo_id, hf_halo *halos, int64_t halos_cap,
-                    int64_t *n_halos, hipStream_t s) {
+                    int64_t *n_halos, hipStream_t s, const FixedArena *fx) {
     Geo g;
     Work w;
     if (n > 0 && !halo_id) return fail(c, HF_ERR_INVALID, "halo_id is NULL");
     if (halos_cap < 0 || (halos_cap > 0 && !halos)) return fail(c, HF_ERR_INVALID, "bad halos / halos_cap");
-    hf_status st = begin(c, pos, n, p, &g, &w, s, true);
+    hf_status st = begin(c, pos, n, p, &g, &w, s, true, false, fx);
     if (st != HF_OK) return st;
     if (n == 0) {
         if (n_halos) *n_halos = 0;
@@ -526,6 +569,13 @@ hf_status hf_create(hf_ctx **out, int device, uint64_t hbm_budget_bytes) {
     c->budget.limit = hbm_budget_bytes;
     c->main.budget = &c->budget;
     if (hf::lane_init(&c->main, device, false) != HF_OK) {
+        hf::lane_destroy(&c->main);
+        delete c;
+        return HF_ERR_DEVICE;
+    }
+    // lane_init made `device` current
+    c->scratch = scratch_of(device);
+    if (!c->scratch) {
         hf::lane_destroy(&c->main);
         delete c;
         return HF_ERR_DEVICE;
@@ -704,6 +754,15 @@ hf_status hf_find(hf_ctx *ctx, const float *pos, int64_t n, const hf_params *p, 
     if (!ctx) return HF_ERR_INVALID;
     return hf::lane_find(&ctx->main, pos, n, p, density, l0_id, halo_id, halos, halos_cap, n_halos,
                          (hipStream_t)stream);
+}
+
+hf_status hf_find_noalloc(hf_ctx *ctx, const float *pos, int64_t n, const hf_params *p, float *density,
+                          int32_t *l0_id, int32_t *halo_id, hf_halo *halos, int64_t halos_cap,
+                          int64_t *n_halos, void *stream) {
+    if (!ctx) return HF_ERR_INVALID;
+    const hf::FixedArena fx{ctx->scratch, hf::kScratchBytes};
+    return hf::lane_find(&ctx->main, pos, n, p, density, l0_id, halo_id, halos, halos_cap, n_halos,
+                         (hipStream_t)stream, &fx);
 }
 
 }  // extern "C"

@@ -43,6 +43,16 @@ struct Lane {
     hipEvent_t pub = nullptr;      // marks a copy into host whose words are read while later work runs
 };
 
+// Size of the static scratch region of hf_find_noalloc (per device).
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+
+// A caller-given scratch region: the arena is carved from it and nothing is
+// allocated (the call fails when the box needs more).
+struct FixedArena {
+    void *base;
+    size_t bytes;
+};
+
 // Create the events, the pinned host words (and a non-blocking stream of
 // default priority when own_stream).  Returns HF_ERR_DEVICE on failure.
 hf_status lane_init(Lane *L, int device, bool own_stream);
@@ -55,12 +65,13 @@ size_t lane_arena_bytes(const hf_params *p, int64_t n);
 // The whole pass for one box on stream s (hf_find's contract).
 hf_status lane_find(Lane *L, const float *pos, int64_t n, const hf_params *p, float *density,
                     int32_t *l0_id, int32_t *halo_id, hf_halo *halos, int64_t halos_cap,
-                    int64_t *n_halos, hipStream_t s);
+                    int64_t *n_halos, hipStream_t s, const FixedArena *fx = nullptr);
 
 }  // namespace hf
 
 struct hf_ctx {
     hf::Budget budget;
     hf::Lane main;
+    void *scratch = nullptr;  // device address of the static scratch on main.device
     std::vector<std::unique_ptr<hf::Lane>> pool;  // lanes of hf_find_batch, created on demand
 };
