@@ -22,7 +22,10 @@
 //   4. cell offsets for every cell of the grid, written by the sorted
 //      particles that end each run of cells (coalesced, one wavefront per 64).
 // Cells are at least max(b, l) wide; each is split into k^3 sub-cells whose
-// diagonal is below l, so all particles of one sub-cell are friends.
+// diagonal is below l, so all particles of one sub-cell are friends.  The
+// boxes of one call are binned together: their cells are numbered box after
+// box, so the sorted order is box-major and box b keeps the slots of its
+// input range.
 //
 // Work decomposition shared by the neighbour-loop kernels: a cell holding at
 // least kDenseMin particles is "dense".  Dense cells get a table of their
@@ -50,23 +53,26 @@ __device__ __forceinline__ int sub_coord(float x, int c, const Geo &g) {
     return s < 0 ? 0 : (s >= g.ksub ? g.ksub - 1 : s);
 }
 
-// Sort key of particle i: cell * k^3 + sub-cell.  Packed mode stores
-// (key << ib) | i in one word (ib bits hold the index); otherwise the index
-// travels in a separate payload array.
-__global__ __launch_bounds__(kBlock) void k_bin_key(const float *__restrict__ pos, int64_t n, Geo g, int ib,
+// Sort key of particle i: cell * nsub_max + sub-cell, the cell numbered in the
+// call's numbering (box after box).  Packed mode stores (key << ib) | i in one
+// word (ib bits hold the index); otherwise the index travels in a separate
+// payload array.
+__global__ __launch_bounds__(kBlock) void k_bin_key(const float *__restrict__ pos, int64_t n, Boxes bx, int ib,
                                                     uint64_t *__restrict__ key,
                                                     int32_t *__restrict__ err) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const int box = box_of(bx, (uint32_t)i);
+    const Geo &g = bx.geo[box];
     float x = pos[3 * i + 0], y = pos[3 * i + 1], z = pos[3 * i + 2];
     float Lf = (float)g.L;
     bool ok = x >= 0.0f && x < Lf && y >= 0.0f && y < Lf && z >= 0.0f && z < Lf;
-    if (!ok) atomicOr(err, 1);
+    if (!ok) flag_error(err, 1, box);
     int cx = cell_coord(x, g), cy = cell_coord(y, g), cz = cell_coord(z, g);
-    uint32_t c = ((uint32_t)cz * (uint32_t)g.nc + (uint32_t)cy) * (uint32_t)g.nc + (uint32_t)cx;
+    uint32_t c = g.cell_base + ((uint32_t)cz * (uint32_t)g.nc + (uint32_t)cy) * (uint32_t)g.nc + (uint32_t)cx;
     int k = g.ksub;
     uint32_t sub = (uint32_t)((sub_coord(z, cz, g) * k + sub_coord(y, cy, g)) * k + sub_coord(x, cx, g));
-    const uint64_t kk = (uint64_t)c * (uint64_t)(k * k * k) + sub;
+    const uint64_t kk = (uint64_t)c * (uint64_t)bx.nsub_max + sub;
     key[i] = ib > 0 ? (kk << ib) | (uint64_t)i : kk;
 }
 
@@ -222,7 +228,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t *__restric
 // Sorted slot s: the particle's two float4 records, its sub-cell and, when
 // densities follow, its density record.
 template <bool kPacked>
-__global__ __launch_bounds__(kBlock) void k_bin_place(const float *__restrict__ pos, int64_t n, Geo g, int ib,
+__global__ __launch_bounds__(kBlock) void k_bin_place(const float *__restrict__ pos, int64_t n, Boxes bx, int ib,
                                                       const uint64_t *__restrict__ key,
                                                       const uint32_t *__restrict__ idx,
                                                       float4 *__restrict__ spos, float4 *__restrict__ sloc,
@@ -234,13 +240,14 @@ __global__ __launch_bounds__(kBlock) void k_bin_place(const float *__restrict__ 
     const uint64_t kw = key[s];
     const uint64_t k = kPacked ? kw >> ib : kw;
     const uint32_t o = kPacked ? (uint32_t)(kw & ((1ull << ib) - 1ull)) : idx[s];
-    const uint32_t nsub = (uint32_t)(g.ksub * g.ksub * g.ksub);
+    const uint32_t nsub = (uint32_t)bx.nsub_max;
     const uint32_t c = (uint32_t)(k / nsub);
     const uint32_t sub = (uint32_t)(k - (uint64_t)c * nsub);
+    const Geo &g = bx.geo[box_of(bx, (uint32_t)s)];
     const float x = pos[3 * (int64_t)o + 0], y = pos[3 * (int64_t)o + 1], z = pos[3 * (int64_t)o + 2];
     spos[s] = make_float4(x, y, z, __uint_as_float(o));
-    const uint32_t nc = (uint32_t)g.nc;
-    const uint32_t cx = c % nc, cy = (c / nc) % nc, cz = c / (nc * nc);
+    const uint32_t nc = (uint32_t)g.nc, lc = c - g.cell_base;
+    const uint32_t cx = lc % nc, cy = (lc / nc) % nc, cz = lc / (nc * nc);
     const float xl = (float)(((double)x - (double)cx * g.cell) * g.inv_b);
     const float yl = (float)(((double)y - (double)cy * g.cell) * g.inv_b);
     const float zl = (float)(((double)z - (double)cz * g.cell) * g.inv_b);
@@ -397,7 +404,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_lists(int64_t n, const uint32_t 
 // gets the start of the next non-empty one; entry nsub is the cell end).  The
 // cell's particles are sorted by sub-cell; each 64-particle step counts, for
 // 64 values of s at a time, the particles below s by ballot.
-__device__ __forceinline__ void sub_table_cell(int64_t d, int nsub, const uint32_t *__restrict__ dcells,
+__device__ __forceinline__ void sub_table_cell(int64_t d, const Boxes &bx, const uint32_t *__restrict__ dcells,
                                                const uint32_t *__restrict__ off,
                                                const uint16_t *__restrict__ ssub,
                                                uint32_t *__restrict__ subtab) {
@@ -405,7 +412,8 @@ __device__ __forceinline__ void sub_table_cell(int64_t d, int nsub, const uint32
     const uint32_t c = (uint32_t)__builtin_amdgcn_readfirstlane(dcells[d]);
     const uint32_t a = (uint32_t)__builtin_amdgcn_readfirstlane(off[c]);
     const uint32_t b = (uint32_t)__builtin_amdgcn_readfirstlane(off[c + 1]);
-    uint32_t *t = subtab + d * (nsub + 1);
+    const int nsub = __builtin_amdgcn_readfirstlane(bx.geo[box_of(bx, a)].nsub);
+    uint32_t *t = subtab + d * (bx.nsub_max + 1);
     for (int s0 = 0; s0 <= nsub; s0 += 64) {
         const int ns = min(64, nsub + 1 - s0);
         uint32_t below = 0;  // for s = s0 + lane
@@ -423,7 +431,7 @@ __device__ __forceinline__ void sub_table_cell(int64_t d, int nsub, const uint32
 
 // The sub-cell tables of all dense cells, one wavefront per cell over a grid
 // that strides the cells; the cell count *ndc_p is read on the device.
-__global__ __launch_bounds__(kBlock) void k_sub_table(const uint32_t *__restrict__ ndc_p, int nsub,
+__global__ __launch_bounds__(kBlock) void k_sub_table(const uint32_t *__restrict__ ndc_p, Boxes bx,
                                                       const uint32_t *__restrict__ dcells,
                                                       const uint32_t *__restrict__ off,
                                                       const uint16_t *__restrict__ ssub,
@@ -432,7 +440,7 @@ __global__ __launch_bounds__(kBlock) void k_sub_table(const uint32_t *__restrict
     const int64_t ndc = *ndc_p;
     const int64_t stride = (int64_t)gridDim.x * (kBlock / 64);
     for (int64_t d = (int64_t)blockIdx.x * (kBlock / 64) + wave; d < ndc; d += stride)
-        sub_table_cell(d, nsub, dcells, off, ssub, subtab);
+        sub_table_cell(d, bx, dcells, off, ssub, subtab);
 }
 
 }  // namespace
@@ -448,8 +456,8 @@ struct RadixPlan {
     int passes, D, ib;
 };
 
-RadixPlan radix_plan(int64_t n, const Geo &g) {
-    const uint64_t nkeys = (uint64_t)g.nc * g.nc * g.nc * (uint64_t)(g.ksub * g.ksub * g.ksub);
+RadixPlan radix_plan(int64_t n, int64_t ncell, int nsub_max) {
+    const uint64_t nkeys = (uint64_t)ncell * (uint64_t)nsub_max;
     int bits = bit_width(nkeys - 1);
     if (bits < 1) bits = 1;
     RadixPlan r;
@@ -464,7 +472,7 @@ RadixPlan radix_plan(int64_t n, const Geo &g) {
     return r;
 }
 
-int64_t radix_hist_len(int64_t n, const Geo &) {
+int64_t radix_hist_len(int64_t n) {
     // room for the widest digit, so that every sort of up to n keys fits
     const int64_t ntiles = (n + kTile - 1) / kTile;
     return ((int64_t)1 << kRadixMaxBits) * (ntiles > 0 ? ntiles : 1) + 1;
@@ -491,11 +499,10 @@ uint64_t *radix_sort_keys(uint64_t *a, uint64_t *b, int64_t n, int lo, int bits,
     return cur;
 }
 
-void launch_bin(const float *pos, int64_t n, const Geo &g, Work &w, hipStream_t s) {
-    const int64_t ncell = (int64_t)g.nc * g.nc * g.nc;
-    const RadixPlan r = radix_plan(n, g);
+void launch_bin(const float *pos, int64_t n, int64_t ncell, const Boxes &bx, Work &w, hipStream_t s) {
+    const RadixPlan r = radix_plan(n, ncell, bx.nsub_max);
     const bool packed = r.ib > 0;
-    hipLaunchKernelGGL(k_bin_key, dim3(blocks(n)), dim3(kBlock), 0, s, pos, n, g, r.ib, w.rkey[0], w.err);
+    hipLaunchKernelGGL(k_bin_key, dim3(blocks(n)), dim3(kBlock), 0, s, pos, n, bx, r.ib, w.rkey[0], w.err);
     const int64_t ntiles = (n + kTile - 1) / kTile;
     const int64_t hl = ((int64_t)1 << r.D) * ntiles;
     int cur = 0;
@@ -514,10 +521,10 @@ void launch_bin(const float *pos, int64_t n, const Geo &g, Work &w, hipStream_t 
         cur ^= 1;
     }
     if (packed)
-        hipLaunchKernelGGL(k_bin_place<true>, dim3(blocks(n)), dim3(kBlock), 0, s, pos, n, g, r.ib, w.rkey[cur],
+        hipLaunchKernelGGL(k_bin_place<true>, dim3(blocks(n)), dim3(kBlock), 0, s, pos, n, bx, r.ib, w.rkey[cur],
                            nullptr, w.spos, w.sloc, w.pq, w.ssub);
     else
-        hipLaunchKernelGGL(k_bin_place<false>, dim3(blocks(n)), dim3(kBlock), 0, s, pos, n, g, 0, w.rkey[cur],
+        hipLaunchKernelGGL(k_bin_place<false>, dim3(blocks(n)), dim3(kBlock), 0, s, pos, n, bx, 0, w.rkey[cur],
                            w.rval[cur], w.spos, w.sloc, w.pq, w.ssub);
     // slots 0..n (slot n closes the grid): one wavefront per 64
     hipLaunchKernelGGL(k_cell_offsets, dim3((unsigned)((n + 1 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n,
@@ -532,15 +539,14 @@ void launch_bin(const float *pos, int64_t n, const Geo &g, Work &w, hipStream_t 
                        w.sparse, w.cnt);
 }
 
-void launch_subtab(int64_t n, const uint32_t *ndc_p, const Geo &g, Work &w, hipStream_t s) {
+void launch_subtab(int64_t n, const uint32_t *ndc_p, const Boxes &bx, Work &w, hipStream_t s) {
     if (n <= 0) return;
-    const int nsub = g.ksub * g.ksub * g.ksub;
     // the count is read on the device; a dense cell holds at least kDenseMin
     // particles, and a grid of at most 16384 workgroups strides over the cells
     const int64_t ub = n / kDenseMin + 1;
     int64_t blocks = (ub + kBlock / 64 - 1) / (kBlock / 64);
     if (blocks > 16384) blocks = 16384;
-    hipLaunchKernelGGL(k_sub_table, dim3((unsigned)blocks), dim3(kBlock), 0, s, ndc_p, nsub, w.dcells, w.off,
+    hipLaunchKernelGGL(k_sub_table, dim3((unsigned)blocks), dim3(kBlock), 0, s, ndc_p, bx, w.dcells, w.off,
                        w.ssub, w.subtab);
 }
 

@@ -53,7 +53,11 @@ __device__ __forceinline__ uint64_t dkey(float d, uint32_t orig) {
     return ((uint64_t)__float_as_uint(d) << 32) | (uint64_t)(0xffffffffu - orig);
 }
 
-__global__ __launch_bounds__(kBlock) void k_submax(int64_t nslots, int nsub,
+// Slot t = (dense cell d, sub-cell s < nsub_max); sub-cells beyond the cell's
+// own box's count are left alone.
+__global__ __launch_bounds__(kBlock) void k_submax(int64_t nslots, Boxes bx,
+                                                   const uint32_t *__restrict__ dcells,
+                                                   const uint32_t *__restrict__ off,
                                                    const uint32_t *__restrict__ subtab,
                                                    const float *__restrict__ dens_s,
                                                    const float4 *__restrict__ spos,
@@ -61,8 +65,10 @@ __global__ __launch_bounds__(kBlock) void k_submax(int64_t nslots, int nsub,
                                                    int32_t *__restrict__ subarg) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nslots) return;
+    const int nsub = bx.nsub_max;
     const int64_t d = t / nsub;
     const int s = (int)(t - d * nsub);
+    if (s >= bx.geo[box_of(bx, off[dcells[d]])].nsub) return;
     const uint32_t *tab = subtab + d * (nsub + 1);
     uint64_t best = 0;
     int32_t arg = -1;
@@ -81,7 +87,7 @@ __global__ __launch_bounds__(kBlock) void k_submax(int64_t nslots, int nsub,
 // the cell's particles are sorted by sub-cell, so each 64-particle step
 // reduces the runs of equal sub-cells (maximum key and its particle) and the
 // first lane of each run merges the result into the cell's row in LDS.
-__global__ __launch_bounds__(kBlock) void k_submax_wave(int64_t ndc, int nsub,
+__global__ __launch_bounds__(kBlock) void k_submax_wave(int64_t ndc, Boxes bx,
                                                         const uint32_t *__restrict__ dcells,
                                                         const uint32_t *__restrict__ off,
                                                         const uint16_t *__restrict__ ssub,
@@ -98,6 +104,8 @@ __global__ __launch_bounds__(kBlock) void k_submax_wave(int64_t ndc, int nsub,
     const uint32_t c = (uint32_t)__builtin_amdgcn_readfirstlane(dcells[d]);
     const uint32_t a = (uint32_t)__builtin_amdgcn_readfirstlane(off[c]);
     const uint32_t b = (uint32_t)__builtin_amdgcn_readfirstlane(off[c + 1]);
+    const int nsub = __builtin_amdgcn_readfirstlane(bx.geo[box_of(bx, a)].nsub);
+    const int64_t row = d * (bx.nsub_max + 1);
     s_best[wave][lane] = 0ull;
     s_arg[wave][lane] = -1;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -127,8 +135,8 @@ __global__ __launch_bounds__(kBlock) void k_submax_wave(int64_t ndc, int nsub,
         __builtin_amdgcn_wave_barrier();
     }
     if (lane < nsub) {
-        submax[d * (nsub + 1) + lane] = s_best[wave][lane];
-        subarg[d * (nsub + 1) + lane] = s_arg[wave][lane];
+        submax[row + lane] = s_best[wave][lane];
+        subarg[row + lane] = s_arg[wave][lane];
     }
 }
 
@@ -137,7 +145,7 @@ __global__ __launch_bounds__(kBlock) void k_submax_wave(int64_t ndc, int nsub,
 // particle belongs to its group and lies within b (the usual case inside an L0
 // group, the sub-cell diagonal being below l).  Every other member at or above
 // the floor is flagged as a hard case.
-__global__ __launch_bounds__(kBlock) void k_cand_quick(int64_t n, Geo g, const float4 *__restrict__ sloc,
+__global__ __launch_bounds__(kBlock) void k_cand_quick(int64_t n, Boxes bx, const float4 *__restrict__ sloc,
                                                        const float4 *__restrict__ spos,
                                                        const uint32_t *__restrict__ f_sparse,
                                                        const uint16_t *__restrict__ ssub,
@@ -149,6 +157,7 @@ __global__ __launch_bounds__(kBlock) void k_cand_quick(int64_t n, Geo g, const f
                                                        uint32_t *__restrict__ f_hard) {
     const int64_t i = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const Geo &g = bx.geo[box_of(bx, (uint32_t)i)];
     bool is_hard = false;
     cflag[i] = 0;
     const int key = gkey[i];
@@ -158,10 +167,12 @@ __global__ __launch_bounds__(kBlock) void k_cand_quick(int64_t n, Geo g, const f
         const float4 li = sloc[i];
         const uint32_t c = __float_as_uint(li.w);
         if (!f_sparse[i]) {
-            const int nsub = g.ksub * g.ksub * g.ksub;
-            const int32_t top = subarg[(int64_t)cellmap[c] * (nsub + 1) + ssub[i]];
-            if (top != (int32_t)i && gkey[top] == key) {
-                // top is denser than i: it is the maximum of i's sub-cell
+            const int32_t top = subarg[(int64_t)cellmap[c] * (bx.nsub_max + 1) + ssub[i]];
+            // top, the maximum of i's sub-cell, is denser than i (the bit
+            // order of the key matches the values for the non-negative
+            // densities the stage works on; checked anyway)
+            if (top != (int32_t)i && gkey[top] == key &&
+                denser(dens_s[top], orig_of(spos[top]), di, orig_of(spos[i]))) {
                 const float4 lt = sloc[top];
                 const float dx = lt.x - li.x, dy = lt.y - li.y, dz = lt.z - li.z;
                 const float d2f = dx * dx + dy * dy + dz * dz;
@@ -184,7 +195,8 @@ __global__ __launch_bounds__(kBlock) void k_hard_list(int64_t n, const uint32_t 
 // stencil cells tt0..tt1-1 (cell 0 of the order is its own).  In dense cells
 // only sub-cells within b that hold a denser particle are visited, their
 // densest particle first.
-__device__ bool has_denser_within_b(int i, int tt0, int tt1, const Geo &g, const float4 *__restrict__ sloc,
+__device__ bool has_denser_within_b(int i, int tt0, int tt1, const Geo &g, int tstride,
+                                    const float4 *__restrict__ sloc,
                                     const float4 *__restrict__ spos, const uint32_t *__restrict__ off,
                                     const uint32_t *__restrict__ cellmap, const uint32_t *__restrict__ subtab,
                                     const uint64_t *__restrict__ submax, const int32_t *__restrict__ subarg,
@@ -196,10 +208,10 @@ __device__ bool has_denser_within_b(int i, int tt0, int tt1, const Geo &g, const
     const uint32_t oi = orig_of(pi);
     const uint64_t mykey = dkey(di, oi);
     const uint32_t c = __float_as_uint(li.w);
-    const int nc = g.nc, k = g.ksub, nsub = k * k * k;
+    const int k = g.ksub, nsub = g.nsub;
     const float subb = g.cellb / (float)k;
-    const int cx = (int)(c % (uint32_t)nc), cy = (int)((c / (uint32_t)nc) % (uint32_t)nc),
-              cz = (int)(c / ((uint32_t)nc * (uint32_t)nc));
+    int cx, cy, cz;
+    cell_xyz(g, c, cx, cy, cz);
     for (int tt = tt0; tt < tt1; tt++) {
         int ox, oy, oz;
         stencil_offset(tt, ox, oy, oz);
@@ -210,8 +222,7 @@ __device__ bool has_denser_within_b(int i, int tt0, int tt1, const Geo &g, const
         const float gy = oy < 0 ? li.y : (oy > 0 ? g.cellb - li.y : 0.0f);
         const float gz = oz < 0 ? li.z : (oz > 0 ? g.cellb - li.z : 0.0f);
         if (gx * gx + gy * gy + gz * gz >= g.b2b_hi) continue;
-        const uint32_t nb = ((uint32_t)wrapc(cz + oz, nc) * (uint32_t)nc + (uint32_t)wrapc(cy + oy, nc)) *
-                                (uint32_t)nc + (uint32_t)wrapc(cx + ox, nc);
+        const uint32_t nb = cell_id(g, cx + ox, cy + oy, cz + oz);
         const uint32_t a = off[nb], b = off[nb + 1];
         if (b - a < (uint32_t)kDenseMin) {
             // sparse cell: the densities first (all loads together), then the
@@ -227,7 +238,7 @@ __device__ bool has_denser_within_b(int i, int tt0, int tt1, const Geo &g, const
             }
             continue;
         }
-        const int64_t base = (int64_t)cellmap[nb] * (nsub + 1);
+        const int64_t base = (int64_t)cellmap[nb] * tstride;
         for (int s0 = 0; s0 < nsub; s0 += 3) {
             // three sub-cell maxima per round of loads (small batches keep the
             // thread-per-case kernel at 74 VGPRs: it waits on memory, and
@@ -274,7 +285,7 @@ __device__ bool has_denser_within_b(int i, int tt0, int tt1, const Geo &g, const
 // searches (mostly the actual candidates) do not hold up waves of quick ones;
 // without it, the cases left are candidates.
 __global__ __launch_bounds__(kBlock) void k_cand_hard(const uint32_t *__restrict__ nhard_p, int stage, int tt0,
-                                                      int tt1, Geo g,
+                                                      int tt1, Boxes bx,
                                                       const int32_t *__restrict__ hard,
                                                       const float4 *__restrict__ sloc,
                                                       const float4 *__restrict__ spos,
@@ -298,8 +309,8 @@ __global__ __launch_bounds__(kBlock) void k_cand_hard(const uint32_t *__restrict
     const bool valid = t < (int64_t)*nhard_p;
     const int i = valid ? hard[t] : -1;
     bool left = false;
-    if (valid && !has_denser_within_b(i, tt0, tt1, g, sloc, spos, off, cellmap, subtab, submax, subarg, dens_s,
-                                      gkey)) {
+    if (valid && !has_denser_within_b(i, tt0, tt1, bx.geo[box_of(bx, (uint32_t)i)], bx.nsub_max + 1, sloc, spos,
+                                      off, cellmap, subtab, submax, subarg, dens_s, gkey)) {
         if (rest) {
             left = true;
         } else {
@@ -325,7 +336,7 @@ __global__ __launch_bounds__(kBlock) void k_cand_hard(const uint32_t *__restrict
 // particle first, then the rest of the sub-cell); the wavefront stops at the
 // first denser particle of the group within b.  The cases that reach this
 // stage are mostly the true candidates, which need every cell.
-__global__ __launch_bounds__(kBlock) void k_cand_wave(const uint32_t *__restrict__ ncase_p, int tt0, Geo g,
+__global__ __launch_bounds__(kBlock) void k_cand_wave(const uint32_t *__restrict__ ncase_p, int tt0, Boxes bx,
                                                       const int32_t *__restrict__ cases,
                                                       const float4 *__restrict__ sloc,
                                                       const float4 *__restrict__ spos,
@@ -345,10 +356,12 @@ __global__ __launch_bounds__(kBlock) void k_cand_wave(const uint32_t *__restrict
     const int lane = threadIdx.x & 63;
     const uint32_t ncase = *ncase_p;
     const uint32_t nwaves = gridDim.x * (kBlock / 64);
-    const int nc = g.nc, k = g.ksub, nsub = k * k * k;
-    const float subb = g.cellb / (float)k;
+    const int tstride = bx.nsub_max + 1;
     for (uint32_t q = blockIdx.x * (kBlock / 64) + (uint32_t)wave; q < ncase; q += nwaves) {
         const int i = __builtin_amdgcn_readfirstlane(cases[q]);
+        const Geo &g = bx.geo[__builtin_amdgcn_readfirstlane(box_of(bx, (uint32_t)i))];
+        const int k = g.ksub, nsub = g.nsub;
+        const float subb = g.cellb / (float)k;
         const int key = gkey[i];
         const float di = dens_s[i];
         const float4 li = sloc[i];
@@ -356,8 +369,8 @@ __global__ __launch_bounds__(kBlock) void k_cand_wave(const uint32_t *__restrict
         const uint32_t oi = orig_of(pi);
         const uint64_t mykey = dkey(di, oi);
         const uint32_t c = __float_as_uint(li.w);
-        const int cx = (int)(c % (uint32_t)nc), cy = (int)((c / (uint32_t)nc) % (uint32_t)nc),
-                  cz = (int)(c / ((uint32_t)nc * (uint32_t)nc));
+        int cx, cy, cz;
+        cell_xyz(g, c, cx, cy, cz);
         // one stencil cell per lane
         const int tt = tt0 + lane;
         bool in_reach = false, dense = false, found = false;
@@ -374,8 +387,7 @@ __global__ __launch_bounds__(kBlock) void k_cand_wave(const uint32_t *__restrict
             const float gz = oz < 0 ? li.z : (oz > 0 ? g.cellb - li.z : 0.0f);
             in_reach = gx * gx + gy * gy + gz * gz < g.b2b_hi;
             if (in_reach) {
-                nb = ((uint32_t)wrapc(cz + oz, nc) * (uint32_t)nc + (uint32_t)wrapc(cy + oy, nc)) * (uint32_t)nc +
-                     (uint32_t)wrapc(cx + ox, nc);
+                nb = cell_id(g, cx + ox, cy + oy, cz + oz);
                 a = off[nb];
                 b = off[nb + 1];
                 dense = b - a >= (uint32_t)kDenseMin;
@@ -400,7 +412,7 @@ __global__ __launch_bounds__(kBlock) void k_cand_wave(const uint32_t *__restrict
         }
         if (in_reach && dense) {
             const int slot = __popcll(dm & ((1ull << lane) - 1ull));
-            s_base[wave][slot] = (int64_t)cellmap[nb] * (nsub + 1);
+            s_base[wave][slot] = (int64_t)cellmap[nb] * tstride;
             s_tt[wave][slot] = (int8_t)tt;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -443,20 +455,20 @@ __global__ __launch_bounds__(kBlock) void k_cand_wave(const uint32_t *__restrict
 
 }  // namespace
 
-void launch_candidates(int64_t n, const Geo &g, Work &w, hipStream_t s) {
-    const int nsub = g.ksub * g.ksub * g.ksub;
+void launch_candidates(int64_t n, const Boxes &bx, Work &w, hipStream_t s) {
+    const int nsub = bx.nsub_max;
     const int64_t nslots = w.ndcells * nsub;
     if (nslots > 0 && nsub <= 64)
         hipLaunchKernelGGL(k_submax_wave, dim3((unsigned)((w.ndcells + kBlock / 64 - 1) / (kBlock / 64))),
-                           dim3(kBlock), 0, s, w.ndcells, nsub, w.dcells, w.off, w.ssub, w.dens_s, w.spos, w.submax,
+                           dim3(kBlock), 0, s, w.ndcells, bx, w.dcells, w.off, w.ssub, w.dens_s, w.spos, w.submax,
                            w.subarg);
     else if (nslots > 0)
         hipLaunchKernelGGL(k_submax, dim3((unsigned)((nslots + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                           nslots, nsub, w.subtab, w.dens_s, w.spos, w.submax, w.subarg);
+                           nslots, bx, w.dcells, w.off, w.subtab, w.dens_s, w.spos, w.submax, w.subarg);
     const unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
     // candidate flags live in the owner array until the assignment overwrites
     // it; the hard-case flags and their scan reuse the dense-cell flag arrays
-    hipLaunchKernelGGL(k_cand_quick, dim3(blocks), dim3(kBlock), 0, s, n, g, w.sloc, w.spos, w.f_sparse, w.ssub,
+    hipLaunchKernelGGL(k_cand_quick, dim3(blocks), dim3(kBlock), 0, s, n, bx, w.sloc, w.spos, w.f_sparse, w.ssub,
                        w.cnt, w.subarg, w.dens_s, w.gkey, w.owner, w.f_dcell);
     scan_u32(w.f_dcell, w.s_dcell, n, w.scan_tmp, s);
     hipLaunchKernelGGL(k_hard_list, dim3(blocks), dim3(kBlock), 0, s, n, w.f_dcell, w.s_dcell, w.hardlist);
@@ -478,16 +490,16 @@ void launch_candidates(int64_t n, const Geo &g, Work &w, hipStream_t s) {
         uint32_t *n2 = reinterpret_cast<uint32_t *>(w.counters + 10);
         fill_u32(n1, 0u, 3, s);  // counters 8..10 (9 is the acceptance's, also zero here)
         const dim3 grid((unsigned)((nh + kBlock - 1) / kBlock));
-        hipLaunchKernelGGL(k_cand_hard, grid, dim3(kBlock), 0, s, w.s_dcell + n, 1, 0, 1, g, w.hardlist, w.sloc,
+        hipLaunchKernelGGL(k_cand_hard, grid, dim3(kBlock), 0, s, w.s_dcell + n, 1, 0, 1, bx, w.hardlist, w.sloc,
                            w.spos, w.off, w.cnt, w.subtab, w.submax, w.subarg, w.dens_s, w.gkey, w.gid_of,
                            w.gccnt, w.owner, rest1, n1);
-        hipLaunchKernelGGL(k_cand_hard, grid, dim3(kBlock), 0, s, n1, 2, 1, 7, g, rest1, w.sloc, w.spos, w.off,
+        hipLaunchKernelGGL(k_cand_hard, grid, dim3(kBlock), 0, s, n1, 2, 1, 7, bx, rest1, w.sloc, w.spos, w.off,
                            w.cnt, w.subtab, w.submax, w.subarg, w.dens_s, w.gkey, w.gid_of, w.gccnt, w.owner,
                            rest2, n2);
         // a fixed grid of wavefronts striding over the list
         const int64_t waves = nh < 8192 ? nh : 8192;
         hipLaunchKernelGGL(k_cand_wave, dim3((unsigned)((waves + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), 0,
-                           s, n2, 7, g, rest2, w.sloc, w.spos, w.off, w.cnt, w.subtab, w.submax, w.subarg,
+                           s, n2, 7, bx, rest2, w.sloc, w.spos, w.off, w.cnt, w.subtab, w.submax, w.subarg,
                            w.dens_s, w.gkey, w.gid_of, w.gccnt, w.owner);
     }
 }

@@ -158,7 +158,7 @@ __device__ __forceinline__ double mi_off(float a, float b, double L, double half
     return d;
 }
 
-__global__ __launch_bounds__(kBlock) void k_extent_far(int64_t M, Geo g, const int32_t *__restrict__ mem,
+__global__ __launch_bounds__(kBlock) void k_extent_far(int64_t M, Boxes bx, const int32_t *__restrict__ mem,
                                                        const int32_t *__restrict__ gid_of,
                                                        const int32_t *__restrict__ g_start,
                                                        const float4 *__restrict__ spos,
@@ -168,6 +168,7 @@ __global__ __launch_bounds__(kBlock) void k_extent_far(int64_t M, Geo g, const i
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= M) return;
     const int i = mem[t];
+    const Geo &g = bx.geo[box_of(bx, (uint32_t)i)];
     const int gi = gid_of[i];
     const float4 pr = spos[mem[g_start[gi]]];
     const float4 pi = spos[i];
@@ -179,7 +180,7 @@ __global__ __launch_bounds__(kBlock) void k_extent_far(int64_t M, Geo g, const i
 
 // The exact extent of the flagged groups, one workgroup per group (grid-stride
 // over the list, its length read on the device).
-__global__ __launch_bounds__(kBlock) void k_extent_span(const uint32_t *__restrict__ nfar_p, Geo g,
+__global__ __launch_bounds__(kBlock) void k_extent_span(const uint32_t *__restrict__ nfar_p, Boxes bx,
                                                         const int32_t *__restrict__ farlist,
                                                         const int32_t *__restrict__ g_start,
                                                         const int32_t *__restrict__ g_size,
@@ -192,6 +193,8 @@ __global__ __launch_bounds__(kBlock) void k_extent_span(const uint32_t *__restri
     for (uint32_t f = blockIdx.x; f < nfar; f += gridDim.x) {
         const int gi = farlist[f];
         const int64_t start = g_start[gi], m = g_size[gi];
+        const int box = __builtin_amdgcn_readfirstlane(box_of(bx, (uint32_t)mem[start]));
+        const Geo &g = bx.geo[box];
         const float4 pr = spos[mem[start]];
         double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
         for (int64_t t = threadIdx.x; t < m; t += blockDim.x) {
@@ -226,7 +229,7 @@ __global__ __launch_bounds__(kBlock) void k_extent_span(const uint32_t *__restri
                 }
                 wide = wide || h - l >= g.half;
             }
-            if (wide) atomicOr(err, 8);
+            if (wide) flag_error(err, 8, box);
         }
         __syncthreads();
     }
@@ -293,7 +296,7 @@ constexpr int kWaveNuc = 64;      // ... when they have at most this many candid
 // barriers, so that many small groups run on a CU at once.  The other groups
 // are appended to mid_list (fewer than kHistMid particles) or big_list, with
 // their counts in *mid_count and *big_count, for k_accept.
-__global__ __launch_bounds__(kBlock) void k_accept_small(const uint32_t *__restrict__ ngc_p, Geo g,
+__global__ __launch_bounds__(kBlock) void k_accept_small(const uint32_t *__restrict__ ngc_p, Boxes bx,
                                                          const int32_t *__restrict__ glist,
                                                          const int32_t *__restrict__ g_start,
                                                          const int32_t *__restrict__ g_size,
@@ -320,6 +323,7 @@ __global__ __launch_bounds__(kBlock) void k_accept_small(const uint32_t *__restr
     const int gi = glist[q];
     const int64_t start = g_start[gi];
     const int64_t m = g_size[gi];
+    const Geo &g = bx.geo[__builtin_amdgcn_readfirstlane(box_of(bx, (uint32_t)mem[start]))];
     const uint32_t cs = gcoff[gi], ce = gcoff[gi + 1];
     if (m + 1 > kWaveHist || ce - cs > (uint32_t)kWaveNuc) {
         if (lane == 0) {
@@ -394,7 +398,7 @@ __global__ __launch_bounds__(kBlock) void k_accept_small(const uint32_t *__restr
 // nucleus is ineligible; an eligible one is accepted and its enclosed count i
 // found from the bucket histogram of all particles of the group.
 template <int NT, int HL>
-__global__ __launch_bounds__(NT) void k_accept(const uint32_t *__restrict__ ngc_p, Geo g,
+__global__ __launch_bounds__(NT) void k_accept(const uint32_t *__restrict__ ngc_p, Boxes bx,
                                                const int32_t *__restrict__ glist,
                                                    const int32_t *__restrict__ g_start,
                                                    const int32_t *__restrict__ g_size,
@@ -418,6 +422,7 @@ __global__ __launch_bounds__(NT) void k_accept(const uint32_t *__restrict__ ngc_
     const int64_t start = g_start[gi];
     const int64_t m = g_size[gi];
     const uint32_t cs = gcoff[gi], ce = gcoff[gi + 1];
+    const Geo &g = bx.geo[__builtin_amdgcn_readfirstlane(box_of(bx, (uint32_t)mem[start]))];
     // buckets below HL live in LDS; a group with more buckets keeps the
     // rest in its own global region (m + 1 words, disjoint per group).  The
     // small buckets are where the particles of a dense core pile up, so the
@@ -513,7 +518,7 @@ __global__ __launch_bounds__(NT) void k_accept(const uint32_t *__restrict__ ngc_
 // Step 3 as a per-particle fold over the group's halos in creation order, with
 // the flat-rotation-curve enclosed density Delta_L1 R^2 / r^2 (Sec. 2.3.2)
 // compared in cubed form: i_new^2 e_own^3 >= c^3 i_own^2 e_new^3.
-__global__ __launch_bounds__(kBlock) void k_assign(int64_t n, Geo g, const int32_t *__restrict__ gid_of,
+__global__ __launch_bounds__(kBlock) void k_assign(int64_t n, Boxes bx, const int32_t *__restrict__ gid_of,
                                                    const uint32_t *__restrict__ gcoff,
                                                    const int32_t *__restrict__ g_nh,
                                                    const int32_t *__restrict__ h_nuc,
@@ -526,6 +531,7 @@ __global__ __launch_bounds__(kBlock) void k_assign(int64_t n, Geo g, const int32
     const int gi = i < n ? gid_of[i] : -1;
     int own = -1;
     if (gi >= 0) {
+        const Geo &g = bx.geo[box_of(bx, (uint32_t)i)];
         const uint32_t cs = gcoff[gi];
         const int nh = g_nh[gi];
         const float4 pi = spos[i];
@@ -556,7 +562,7 @@ __global__ __launch_bounds__(kBlock) void k_assign(int64_t n, Geo g, const int32
 
 // ------------------------------------------------------------------- output
 
-__global__ __launch_bounds__(kBlock) void k_out_flags(int64_t NC, Geo g, const int32_t *__restrict__ h_nuc,
+__global__ __launch_bounds__(kBlock) void k_out_flags(int64_t NC, Boxes bx, const int32_t *__restrict__ h_nuc,
                                                       const uint32_t *__restrict__ h_count,
                                                       const float4 *__restrict__ spos,
                                                       uint32_t *__restrict__ tflag,
@@ -566,29 +572,43 @@ __global__ __launch_bounds__(kBlock) void k_out_flags(int64_t NC, Geo g, const i
     const uint64_t b = __ballot(nuc >= 0);
     if ((threadIdx.x & 63) == 0 && b) atomicAdd(&counters[2], __popcll(b));
     if (nuc < 0) return;
-    if (h_count[s] >= (uint32_t)g.n_l1_min) tflag[orig_of(spos[nuc])] = 1u;
+    if (h_count[s] >= (uint32_t)bx.geo[box_of(bx, (uint32_t)nuc)].n_l1_min) tflag[orig_of(spos[nuc])] = 1u;
 }
 
-__global__ __launch_bounds__(kBlock) void k_out_table(int64_t NC, Geo g, const int32_t *__restrict__ h_nuc,
+// Rows of the halo table of every box: the kept halos are flagged at their
+// nucleus's original index, so a box's rows are the flags in its index range.
+__global__ __launch_bounds__(kBlock) void k_box_rows(Boxes bx, const uint32_t *__restrict__ tpos,
+                                                     int64_t *__restrict__ box_rows) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= bx.nbox) return;
+    box_rows[b] = (int64_t)tpos[bx.base[b + 1]] - (int64_t)tpos[bx.base[b]];
+}
+
+// A halo's row in its box's table (ascending id); a box whose rows exceed its
+// table's capacity gets none written.  Ids and labels are box-local.
+__global__ __launch_bounds__(kBlock) void k_out_table(int64_t NC, Boxes bx, const int32_t *__restrict__ h_nuc,
                                                       const int32_t *__restrict__ h_ienc,
                                                       const int32_t *__restrict__ h_gid,
                                                       const uint32_t *__restrict__ h_count,
                                                       const int32_t *__restrict__ g_label,
                                                       const float4 *__restrict__ spos,
-                                                      const uint32_t *__restrict__ tpos,
-                                                      hf_halo *__restrict__ halos, int64_t cap) {
+                                                      const uint32_t *__restrict__ tpos) {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= NC) return;
     int nuc = h_nuc[s];
-    if (nuc < 0 || h_count[s] < (uint32_t)g.n_l1_min) return;
+    if (nuc < 0) return;
+    const int box = box_of(bx, (uint32_t)nuc);
+    const Geo &g = bx.geo[box];
+    if (h_count[s] < (uint32_t)g.n_l1_min || !g.halos) return;
+    const uint32_t b0 = tpos[bx.base[box]];
+    if ((int64_t)(tpos[bx.base[box + 1]] - b0) > g.halo_cap) return;
     float4 p = spos[nuc];
     uint32_t o = orig_of(p);
-    uint32_t row = tpos[o];
-    if ((int64_t)row >= cap) return;
+    const int32_t lo = (int32_t)(o - g.orig_base);
     hf_halo h;
-    h.id = (int32_t)o + 1;
-    h.nucleus = (int32_t)o;
-    h.l0_id = g_label[h_gid[s]];
+    h.id = lo + 1;
+    h.nucleus = lo;
+    h.l0_id = g_label[h_gid[s]] - (int32_t)g.orig_base;
     h.n = (int32_t)h_count[s];
     h.n_enclosed = h_ienc[s];
     h.x = p.x;
@@ -596,10 +616,10 @@ __global__ __launch_bounds__(kBlock) void k_out_table(int64_t NC, Geo g, const i
     h.z = p.z;
     h.r = (float)cbrt((double)h_ienc[s] / g.K);
     h.mass = (float)h_count[s] * g.particle_mass;
-    halos[row] = h;
+    g.halos[tpos[o] - b0] = h;
 }
 
-__global__ __launch_bounds__(kBlock) void k_out_particles(int64_t n, Geo g, const int32_t *__restrict__ owner,
+__global__ __launch_bounds__(kBlock) void k_out_particles(int64_t n, Boxes bx, const int32_t *__restrict__ owner,
                                                           const int32_t *__restrict__ h_nuc,
                                                           const uint32_t *__restrict__ h_count,
                                                           const int32_t *__restrict__ gkey,
@@ -608,12 +628,37 @@ __global__ __launch_bounds__(kBlock) void k_out_particles(int64_t n, Geo g, cons
                                                           int32_t *__restrict__ l0_out) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const Geo &g = bx.geo[box_of(bx, (uint32_t)i)];
     const uint32_t o = orig_of(spos[i]);
     int own = owner[i];
     int32_t hid = 0;
-    if (own >= 0 && h_count[own] >= (uint32_t)g.n_l1_min) hid = (int32_t)orig_of(spos[h_nuc[own]]) + 1;
+    if (own >= 0 && h_count[own] >= (uint32_t)g.n_l1_min)
+        hid = (int32_t)(orig_of(spos[h_nuc[own]]) - g.orig_base) + 1;
     halo_id[o] = hid;
-    if (l0_out) l0_out[o] = gkey[i] + 1;
+    if (l0_out) l0_out[o] = gkey[i] < 0 ? 0 : gkey[i] + 1 - (int32_t)g.orig_base;
+}
+
+// Groups with candidates in descending size, for the acceptance kernels: keys
+// (~size, group) of the groups listed, padding keys sort last.
+__global__ __launch_bounds__(kBlock) void k_glist_keys(int64_t len, const uint32_t *__restrict__ ngc_p,
+                                                       const int32_t *__restrict__ glist,
+                                                       const int32_t *__restrict__ g_size,
+                                                       uint64_t *__restrict__ keys) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= len) return;
+    uint64_t k = ~0ull;
+    if (t < (int64_t)*ngc_p) {
+        const int gi = glist[t];
+        k = ((uint64_t)(0xffffffffu - (uint32_t)g_size[gi]) << 32) | (uint32_t)gi;
+    }
+    keys[t] = k;
+}
+
+__global__ __launch_bounds__(kBlock) void k_glist_from_keys(int64_t len, const uint32_t *__restrict__ ngc_p,
+                                                            const uint64_t *__restrict__ keys,
+                                                            int32_t *__restrict__ glist) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < len && t < (int64_t)*ngc_p) glist[t] = (int32_t)(keys[t] & 0xffffffffu);
 }
 
 }  // namespace
@@ -634,17 +679,23 @@ void launch_segment_groups(int64_t n, int64_t G, Work &w, hipStream_t s) {
     fill_u32(w.gcfill, 0u, G + 1, s);
 }
 
-void launch_extent(int64_t G, int64_t M, const Geo &g, Work &w, hipStream_t s) {
+void launch_extent(int64_t G, int64_t M, const Boxes &bx, Work &w, hipStream_t s) {
     if (M <= 0) return;
     // flags per group in g_nh and the flagged groups in glist (both free until
     // the candidate stage fills them), their count in counters[12]
     fill_i32(w.g_nh, 0, G + 1, s);
-    hipLaunchKernelGGL(k_extent_far, grid(M), dim3(kBlock), 0, s, M, g, w.mem, w.gid_of, w.g_start, w.spos,
+    hipLaunchKernelGGL(k_extent_far, grid(M), dim3(kBlock), 0, s, M, bx, w.mem, w.gid_of, w.g_start, w.spos,
                        w.g_nh, w.glist, reinterpret_cast<uint32_t *>(w.counters + 12));
     const int64_t blocks = G < 1024 ? G : 1024;
     hipLaunchKernelGGL(k_extent_span, dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                       reinterpret_cast<const uint32_t *>(w.counters + 12), g, w.glist, w.g_start, w.g_size,
+                       reinterpret_cast<const uint32_t *>(w.counters + 12), bx, w.glist, w.g_start, w.g_size,
                        w.mem, w.spos, w.err);
+}
+
+static int bits_for(int64_t x) {
+    int b = 1;
+    while (b < 32 && (x >> b) != 0) b++;
+    return b;
 }
 
 void launch_candidates_sort(int64_t n, int64_t G, int64_t NC, Work &w, hipStream_t s) {
@@ -657,12 +708,23 @@ void launch_candidates_sort(int64_t n, int64_t G, int64_t NC, Work &w, hipStream
     scan_nz_u32(w.gccnt, w.gcidx, G, w.scan_tmp, s);  // ordinal of every group with candidates
     if (G > 0)
         hipLaunchKernelGGL(k_glist, grid(G), dim3(kBlock), 0, s, (int)G, w.gccnt, w.gcidx, w.glist);
+    // the groups with candidates (of every box) in descending size, so that the
+    // acceptance kernels start the longest walks first: a stable sort of
+    // (~size, group) on the size bits (sizes are below n); the radix key
+    // arrays are free at this point
+    const int64_t len = G < NC ? G : NC;
+    if (len > 1) {
+        hipLaunchKernelGGL(k_glist_keys, grid(len), dim3(kBlock), 0, s, len, w.gcidx + G, w.glist, w.g_size,
+                           w.rkey[0]);
+        const uint64_t *sorted = radix_sort_keys(w.rkey[0], w.rkey[1], len, 32, bits_for(n), w, s);
+        hipLaunchKernelGGL(k_glist_from_keys, grid(len), dim3(kBlock), 0, s, len, w.gcidx + G, sorted, w.glist);
+    }
     fill_i32(w.h_nuc, -1, NC + 1, s);
     fill_u32(w.h_count, 0u, NC + 1, s);
     fill_i32(w.g_nh, 0, G + 1, s);
 }
 
-void launch_accept(int64_t n, int64_t G, int64_t NC, int64_t M, const Geo &g, Work &w, hipStream_t s) {
+void launch_accept(int64_t n, int64_t G, int64_t NC, int64_t M, const Boxes &bx, Work &w, hipStream_t s) {
     // groups with candidates (at most min(G, NC)), one wavefront each; the
     // others are listed (in the free chunk-flag array, counts in counters[9]
     // and [11], zero since the call began) for one workgroup each: medium
@@ -676,41 +738,43 @@ void launch_accept(int64_t n, int64_t G, int64_t NC, int64_t M, const Geo &g, Wo
     uint32_t *mid_count = reinterpret_cast<uint32_t *>(w.counters + 9);
     uint32_t *big_count = reinterpret_cast<uint32_t *>(w.counters + 11);
     hipLaunchKernelGGL(k_accept_small, dim3((unsigned)((bound + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), 0,
-                       s, w.gcidx + G, g, w.glist, w.g_start, w.g_size, w.gcoff, w.cand_sorted, w.mem, w.spos,
+                       s, w.gcidx + G, bx, w.glist, w.g_start, w.g_size, w.gcoff, w.cand_sorted, w.mem, w.spos,
                        w.h_nuc, w.h_ienc, w.h_gid, w.g_nh, mid_list, mid_count, big_list, big_count);
     int64_t nmid = M / kWaveHist + NC / (kWaveNuc + 1) + 1;
     if (nmid > bound) nmid = bound;
-    hipLaunchKernelGGL((k_accept<kBlock, kHistMid>), dim3((unsigned)nmid), dim3(kBlock), 0, s, mid_count, g,
+    hipLaunchKernelGGL((k_accept<kBlock, kHistMid>), dim3((unsigned)nmid), dim3(kBlock), 0, s, mid_count, bx,
                        mid_list, w.g_start, w.g_size, w.gcoff, w.cand_sorted, w.mem, w.spos, w.hist, w.h_nuc,
                        w.h_ienc, w.h_gid, w.g_nh);
     int64_t nbig = M / kHistMid + 1;
     if (nbig > bound) nbig = bound;
     // the large groups are few and each is a serial walk: 1024 threads and a
     // 144 KB LDS histogram each (one workgroup per CU)
-    hipLaunchKernelGGL((k_accept<1024, kHistBig>), dim3((unsigned)nbig), dim3(1024), 0, s, big_count, g,
+    hipLaunchKernelGGL((k_accept<1024, kHistBig>), dim3((unsigned)nbig), dim3(1024), 0, s, big_count, bx,
                        big_list, w.g_start, w.g_size, w.gcoff, w.cand_sorted, w.mem, w.spos, w.hist, w.h_nuc,
                        w.h_ienc, w.h_gid, w.g_nh);
 }
 
-void launch_assign(int64_t n, const Geo &g, Work &w, hipStream_t s) {
-    hipLaunchKernelGGL(k_assign, grid(n), dim3(kBlock), 0, s, n, g, w.gid_of, w.gcoff, w.g_nh, w.h_nuc,
+void launch_assign(int64_t n, const Boxes &bx, Work &w, hipStream_t s) {
+    hipLaunchKernelGGL(k_assign, grid(n), dim3(kBlock), 0, s, n, bx, w.gid_of, w.gcoff, w.g_nh, w.h_nuc,
                        w.h_ienc, w.spos, w.owner, w.h_count);
 }
 
-void launch_output_flags(int64_t n, int64_t NC, const Geo &g, Work &w, hipStream_t s) {
+void launch_output_flags(int64_t n, int64_t NC, const Boxes &bx, Work &w, hipStream_t s) {
     fill_u32(w.tflag, 0u, n + 1, s);
     if (NC > 0)
-        hipLaunchKernelGGL(k_out_flags, grid(NC), dim3(kBlock), 0, s, NC, g, w.h_nuc, w.h_count, w.spos,
+        hipLaunchKernelGGL(k_out_flags, grid(NC), dim3(kBlock), 0, s, NC, bx, w.h_nuc, w.h_count, w.spos,
                            w.tflag, w.counters);
     scan_u32(w.tflag, w.tpos, n, w.scan_tmp, s);
 }
 
-void launch_output(int64_t n, int64_t NC, const Geo &g, Work &w, int32_t *halo_id, int32_t *l0_out,
-                   hf_halo *halos, int64_t cap, hipStream_t s) {
-    if (halos && NC > 0)
-        hipLaunchKernelGGL(k_out_table, grid(NC), dim3(kBlock), 0, s, NC, g, w.h_nuc, w.h_ienc, w.h_gid,
-                           w.h_count, w.g_label, w.spos, w.tpos, halos, cap);
-    hipLaunchKernelGGL(k_out_particles, grid(n), dim3(kBlock), 0, s, n, g, w.owner, w.h_nuc, w.h_count,
+void launch_output(int64_t n, int64_t NC, const Boxes &bx, Work &w, int32_t *halo_id, int32_t *l0_out,
+                   int64_t *box_rows, hipStream_t s) {
+    if (NC > 0)
+        hipLaunchKernelGGL(k_out_table, grid(NC), dim3(kBlock), 0, s, NC, bx, w.h_nuc, w.h_ienc, w.h_gid,
+                           w.h_count, w.g_label, w.spos, w.tpos);
+    if (box_rows)
+        hipLaunchKernelGGL(k_box_rows, grid(bx.nbox), dim3(kBlock), 0, s, bx, w.tpos, box_rows);
+    hipLaunchKernelGGL(k_out_particles, grid(n), dim3(kBlock), 0, s, n, bx, w.owner, w.h_nuc, w.h_count,
                        w.gkey, w.spos, halo_id, l0_out);
 }
 

@@ -116,9 +116,8 @@ __device__ __forceinline__ void density_chunk(const Geo &g, uint32_t h, uint32_t
             const_cast<float *>(pq + 4 * (size_t)j0), 0, 256, 0x00020000);
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, loff * 4, 0, 0));
     };
-    const int nc = g.nc;
-    const int cx = (int)(c % (uint32_t)nc), cy = (int)((c / (uint32_t)nc) % (uint32_t)nc),
-              cz = (int)(c / ((uint32_t)nc * (uint32_t)nc));
+    int cx, cy, cz;
+    cell_xyz(g, c, cx, cy, cz);
     // the chunk's rows: A = (2 x_i, 1), accumulator input 1 - |x_i|^2; rows
     // past the chunk get A = (0, 0, 0, 1) and -1, so all their weights clamp
     // to exactly 0
@@ -150,9 +149,7 @@ __device__ __forceinline__ void density_chunk(const Geo &g, uint32_t h, uint32_t
     bool sp = false;
     if (lane < 27) {
         const int ox = lane % 3 - 1, oy = (lane / 3) % 3 - 1, oz = lane / 9 - 1;
-        const uint32_t nb = ((uint32_t)wrapc(cz + oz, nc) * (uint32_t)nc + (uint32_t)wrapc(cy + oy, nc)) *
-                                (uint32_t)nc +
-                            (uint32_t)wrapc(cx + ox, nc);
+        const uint32_t nb = cell_id(g, cx + ox, cy + oy, cz + oz);
         ra = off[nb];
         rb = off[nb + 1];
         // a sparse cell's particles have consecutive sparse ordinals
@@ -366,7 +363,7 @@ __device__ __forceinline__ void density_chunk(const Geo &g, uint32_t h, uint32_t
 
 // One wavefront per workgroup: chunk costs differ widely, and a finished
 // wavefront frees its slot at once.
-__global__ __launch_bounds__(64, 6) void k_density_dense(int64_t nchunks, Geo g, bool narrow,
+__global__ __launch_bounds__(64, 6) void k_density_dense(int64_t nchunks, Boxes bx, bool narrow,
                                                       const int32_t *__restrict__ chunks,
                                                       const float4 *__restrict__ sloc,
                                                       const float4 *__restrict__ pq,
@@ -379,6 +376,7 @@ __global__ __launch_bounds__(64, 6) void k_density_dense(int64_t nchunks, Geo g,
     const int64_t q = (int64_t)xcd_block();
     if (q >= nchunks) return;
     const uint32_t h = (uint32_t)__builtin_amdgcn_readfirstlane(chunks[q]);
+    const Geo &g = bx.geo[__builtin_amdgcn_readfirstlane(box_of(bx, h))];
     const uint32_t c = __builtin_amdgcn_readfirstlane(__float_as_uint(sloc[h].w));
     const uint32_t cend = __builtin_amdgcn_readfirstlane(off[c + 1]);
     const uint32_t end = min(h + 64u, cend);
@@ -399,7 +397,7 @@ __global__ __launch_bounds__(64, 6) void k_density_dense(int64_t nchunks, Geo g,
 
 // Sparse cells: one particle per lane, sparse neighbour cells only; the pairs
 // with dense neighbour cells were summed by the dense kernel into dfx.
-__global__ __launch_bounds__(kBlock) void k_density_sparse(int64_t nsparse, Geo g,
+__global__ __launch_bounds__(kBlock) void k_density_sparse(int64_t nsparse, Boxes bx,
                                                            const int32_t *__restrict__ sparse,
                                                            const float4 *__restrict__ sloc,
                                                            const float4 *__restrict__ spos,
@@ -410,12 +408,13 @@ __global__ __launch_bounds__(kBlock) void k_density_sparse(int64_t nsparse, Geo 
     const int64_t t = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
     if (t >= nsparse) return;
     const int64_t i = sparse[t];
+    const Geo &g = bx.geo[box_of(bx, (uint32_t)i)];
     const float4 li = sloc[i];
     const float4 pi = spos[i];
     const uint32_t c = __float_as_uint(li.w);
     const int nc = g.nc;
-    const int cx = (int)(c % (uint32_t)nc), cy = (int)((c / (uint32_t)nc) % (uint32_t)nc),
-              cz = (int)(c / ((uint32_t)nc * (uint32_t)nc));
+    int cx, cy, cz;
+    cell_xyz(g, c, cx, cy, cz);
     const uint32_t x0 = (uint32_t)wrapc(cx - 1, nc), x1 = (uint32_t)cx, x2 = (uint32_t)wrapc(cx + 1, nc);
     // away from the periodic x edges the three cells of a stencil row are
     // consecutive: their four bounding offsets are one 16-byte load
@@ -428,7 +427,8 @@ __global__ __launch_bounds__(kBlock) void k_density_sparse(int64_t nsparse, Geo 
         uint32_t ra[9], rb[9];
 #pragma unroll
         for (int oy = -1; oy <= 1; oy++) {
-            const uint32_t row = ((uint32_t)z * (uint32_t)nc + (uint32_t)wrapc(cy + oy, nc)) * (uint32_t)nc;
+            const uint32_t row =
+                g.cell_base + ((uint32_t)z * (uint32_t)nc + (uint32_t)wrapc(cy + oy, nc)) * (uint32_t)nc;
             const int r = (oy + 1) * 3;
             if (inner) {
                 const uint32_t *p = off + row + x0;
@@ -469,24 +469,22 @@ __global__ __launch_bounds__(kBlock) void k_density_sparse(int64_t nsparse, Geo 
 
 // Number of ordered pairs (i, j != i) closer than b, for the roofline's
 // algorithmic pair count (evaluated in the same FP32 local coordinates).
-__global__ __launch_bounds__(kBlock) void k_count_pairs(int64_t n, Geo g,
+__global__ __launch_bounds__(kBlock) void k_count_pairs(int64_t n, Boxes bx,
                                                         const float4 *__restrict__ sloc,
                                                         const uint32_t *__restrict__ off,
                                                         unsigned long long *__restrict__ total) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t cnt = 0;
     if (i < n) {
+        const Geo &g = bx.geo[box_of(bx, (uint32_t)i)];
         const float4 li = sloc[i];
         const uint32_t c = __float_as_uint(li.w);
-        const int nc = g.nc;
-        const int cx = (int)(c % (uint32_t)nc), cy = (int)((c / (uint32_t)nc) % (uint32_t)nc),
-                  cz = (int)(c / ((uint32_t)nc * (uint32_t)nc));
+        int cx, cy, cz;
+        cell_xyz(g, c, cx, cy, cz);
         for (int oz = -1; oz <= 1; oz++)
             for (int oy = -1; oy <= 1; oy++)
                 for (int ox = -1; ox <= 1; ox++) {
-                    const uint32_t nb = ((uint32_t)wrapc(cz + oz, nc) * (uint32_t)nc +
-                                         (uint32_t)wrapc(cy + oy, nc)) * (uint32_t)nc +
-                                        (uint32_t)wrapc(cx + ox, nc);
+                    const uint32_t nb = cell_id(g, cx + ox, cy + oy, cz + oz);
                     const float xs = li.x - (float)ox * g.cellb, ys = li.y - (float)oy * g.cellb,
                                 zs = li.z - (float)oz * g.cellb;
                     for (uint32_t j = off[nb]; j < off[nb + 1]; j++) {
@@ -511,7 +509,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_density(int64_t n, const floa
 
 }  // namespace
 
-void launch_density(int64_t n, const Geo &g, Work &w, float *dens_out, hipStream_t s) {
+void launch_density(int64_t n, const Boxes &bx, Work &w, float *dens_out, hipStream_t s) {
     // dfx: dense-neighbour sums of the sparse particles (fixed point), in the
     // radix key array that binning no longer needs
     uint64_t *dfx = w.rkey[0];
@@ -523,17 +521,17 @@ void launch_density(int64_t n, const Geo &g, Work &w, float *dens_out, hipStream
         bool narrow = (n + 32) * 16 <= (int64_t)0xffffff00;
         const char *force = getenv("HF_DENSITY_WIDE");
         if (force && force[0] == '1') narrow = false;
-        hipLaunchKernelGGL(k_density_dense, dim3((unsigned)w.nchunks), dim3(64), 0, s, w.nchunks, g, narrow,
+        hipLaunchKernelGGL(k_density_dense, dim3((unsigned)w.nchunks), dim3(64), 0, s, w.nchunks, bx, narrow,
                            w.chunks, w.sloc, w.pq, w.spos, w.off, w.s_sparse, dfx, w.dens_s, dens_out);
     }
     if (w.nsparse > 0)
         hipLaunchKernelGGL(k_density_sparse, dim3((unsigned)((w.nsparse + kBlock - 1) / kBlock)),
-                           dim3(kBlock), 0, s, w.nsparse, g, w.sparse, w.sloc, w.spos, w.off, dfx, w.dens_s,
+                           dim3(kBlock), 0, s, w.nsparse, bx, w.sparse, w.sloc, w.spos, w.off, dfx, w.dens_s,
                            dens_out);
 }
 
-void launch_count_pairs(int64_t n, const Geo &g, Work &w, unsigned long long *total, hipStream_t s) {
-    hipLaunchKernelGGL(k_count_pairs, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, g, w.sloc,
+void launch_count_pairs(int64_t n, const Boxes &bx, Work &w, unsigned long long *total, hipStream_t s) {
+    hipLaunchKernelGGL(k_count_pairs, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, bx, w.sloc,
                        w.off, total);
 }
 

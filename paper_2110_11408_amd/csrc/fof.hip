@@ -225,7 +225,7 @@ __device__ __forceinline__ void stream_sparse_cells(int32_t *parent, const float
 // sparse cells are roots, and members of dense cells point at the first member
 // of their sub-cell (a valid forest: every parent is a member with a smaller
 // or equal sorted index).
-__global__ __launch_bounds__(kBlock) void k_fof_phase_a(int64_t n, Geo g, const float4 *__restrict__ sloc,
+__global__ __launch_bounds__(kBlock) void k_fof_phase_a(int64_t n, Boxes bx, const float4 *__restrict__ sloc,
                                                         const uint32_t *__restrict__ f_sparse,
                                                         const uint16_t *__restrict__ ssub,
                                                         const uint32_t *__restrict__ cellmap,
@@ -234,6 +234,7 @@ __global__ __launch_bounds__(kBlock) void k_fof_phase_a(int64_t n, Geo g, const 
                                                         int32_t *__restrict__ parent) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const Geo &g = bx.geo[box_of(bx, (uint32_t)i)];
     if (!is_member(dens_s, i, g.dl0)) {
         parent[i] = -1;
         return;
@@ -243,8 +244,7 @@ __global__ __launch_bounds__(kBlock) void k_fof_phase_a(int64_t n, Geo g, const 
         return;
     }
     const uint32_t c = __float_as_uint(sloc[i].w);
-    const int nsub = g.ksub * g.ksub * g.ksub;
-    uint32_t f = subtab[(int64_t)cellmap[c] * (nsub + 1) + ssub[i]];
+    uint32_t f = subtab[(int64_t)cellmap[c] * (bx.nsub_max + 1) + ssub[i]];
     while (f < (uint32_t)i && !is_member(dens_s, f, g.dl0)) f++;
     parent[i] = (int32_t)f;
 }
@@ -259,7 +259,7 @@ __global__ __launch_bounds__(kBlock) void k_fof_phase_a(int64_t n, Geo g, const 
 // that member's parent; a sub-cell already in the set every lane belongs to is
 // skipped (all its members are one set), and the others are streamed as
 // wave-uniform scalar loads and joined to the lanes they link.
-__global__ __launch_bounds__(kBlock) void k_fof_dense(int64_t nchunks, Geo g,
+__global__ __launch_bounds__(kBlock) void k_fof_dense(int64_t nchunks, Boxes bx,
                                                       const int32_t *__restrict__ chunks,
                                                       const float4 *__restrict__ sloc,
                                                       const float4 *__restrict__ spos,
@@ -275,6 +275,7 @@ __global__ __launch_bounds__(kBlock) void k_fof_dense(int64_t nchunks, Geo g,
     if (q >= nchunks) return;
     const int lane = threadIdx.x & 63;
     const uint32_t h = (uint32_t)__builtin_amdgcn_readfirstlane(chunks[q]);
+    const Geo &g = bx.geo[__builtin_amdgcn_readfirstlane(box_of(bx, h))];
     const uint32_t c = __builtin_amdgcn_readfirstlane(__float_as_uint(sloc[h].w));
     const uint32_t cend = (uint32_t)__builtin_amdgcn_readfirstlane(off[c + 1]);
     const uint32_t end = min(h + 64u, cend);
@@ -285,10 +286,10 @@ __global__ __launch_bounds__(kBlock) void k_fof_dense(int64_t nchunks, Geo g,
     const float4 li = sloc[ic];
     const float4 pi = spos[ic];
     int wr = active ? uf_find_hint(parent, (int)ic) : -1;
-    const int nc = g.nc, k = g.ksub, nsub = k * k * k;
+    const int k = g.ksub, nsub = g.nsub, tstride = bx.nsub_max + 1;
     const float subb = g.cellb / (float)k;
-    const int cx = (int)(c % (uint32_t)nc), cy = (int)((c / (uint32_t)nc) % (uint32_t)nc),
-              cz = (int)(c / ((uint32_t)nc * (uint32_t)nc));
+    int cx, cy, cz;
+    cell_xyz(g, c, cx, cy, cz);
     // chunk bounding box (active lanes), for the reach tests of stencil cells
     // and sub-cells
     float bx0 = active ? li.x : 1e30f, by0 = active ? li.y : 1e30f, bz0 = active ? li.z : 1e30f;
@@ -305,8 +306,7 @@ __global__ __launch_bounds__(kBlock) void k_fof_dense(int64_t nchunks, Geo g,
     // its range, if it comes within l of the chunk's box
     const int tl = lane < 27 ? lane : 13;
     const int lx = tl % 3 - 1, ly = (tl / 3) % 3 - 1, lz = tl / 9 - 1;
-    const uint32_t nbl = ((uint32_t)wrapc(cz + lz, nc) * (uint32_t)nc + (uint32_t)wrapc(cy + ly, nc)) *
-                             (uint32_t)nc + (uint32_t)wrapc(cx + lx, nc);
+    const uint32_t nbl = cell_id(g, cx + lx, cy + ly, cz + lz);
     const float gx = lx < 0 ? bx0 : (lx > 0 ? g.cellb - bx1 : 0.0f);
     const float gy = ly < 0 ? by0 : (ly > 0 ? g.cellb - by1 : 0.0f);
     const float gz = lz < 0 ? bz0 : (lz > 0 ? g.cellb - bz1 : 0.0f);
@@ -322,7 +322,7 @@ __global__ __launch_bounds__(kBlock) void k_fof_dense(int64_t nchunks, Geo g,
     if (lvisit) {
         const uint64_t vm = __ballot(lvisit);
         const int slot = __popcll(vm & ((1ull << lane) - 1ull));
-        dbase[wave][slot] = (int64_t)cellmap[nbl] * (nsub + 1);
+        dbase[wave][slot] = (int64_t)cellmap[nbl] * tstride;
         doff[wave][slot] = (int8_t)lane;
     }
     const uint64_t visit = __ballot(lvisit);
@@ -387,12 +387,14 @@ __global__ __launch_bounds__(kBlock) void k_fof_dense(int64_t nchunks, Geo g,
 
 // Members among the sparse-cell particles (about one in ten), compacted so
 // that the linking kernel runs without idle lanes.
-__global__ __launch_bounds__(kBlock) void k_fof_sparse_flags(int64_t nsparse, Geo g,
+__global__ __launch_bounds__(kBlock) void k_fof_sparse_flags(int64_t nsparse, Boxes bx,
                                                              const int32_t *__restrict__ sparse,
                                                              const float *__restrict__ dens_s,
                                                              uint32_t *__restrict__ flag) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < nsparse) flag[t] = is_member(dens_s, sparse[t], g.dl0) ? 1u : 0u;
+    if (t >= nsparse) return;
+    const int i = sparse[t];
+    flag[t] = is_member(dens_s, i, bx.geo[box_of(bx, (uint32_t)i)].dl0) ? 1u : 0u;
 }
 
 __global__ __launch_bounds__(kBlock) void k_fof_sparse_list(int64_t nsparse, const int32_t *__restrict__ sparse,
@@ -410,7 +412,7 @@ __global__ __launch_bounds__(kBlock) void k_fof_sparse_list(int64_t nsparse, con
 // block order spreads over all XCDs.  The kernel waits on memory: it is held
 // to 64 VGPRs (eight wavefronts per SIMD; the compiler fits it without
 // spilling).
-__global__ __launch_bounds__(kBlock, 8) void k_fof_sparse(const uint32_t *__restrict__ count_p, Geo g,
+__global__ __launch_bounds__(kBlock, 8) void k_fof_sparse(const uint32_t *__restrict__ count_p, Boxes bx,
                                                        const int32_t *__restrict__ sparse,
                                                        const float4 *__restrict__ sloc,
                                                        const float4 *__restrict__ spos,
@@ -420,12 +422,13 @@ __global__ __launch_bounds__(kBlock, 8) void k_fof_sparse(const uint32_t *__rest
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)*count_p) return;
     const int i = sparse[t];
+    const Geo &g = bx.geo[box_of(bx, (uint32_t)i)];
     const float4 li = sloc[i];
     const float4 pi = spos[i];
     const uint32_t c = __float_as_uint(li.w);
     const int nc = g.nc;
-    const int cx = (int)(c % (uint32_t)nc), cy = (int)((c / (uint32_t)nc) % (uint32_t)nc),
-              cz = (int)(c / ((uint32_t)nc * (uint32_t)nc));
+    int cx, cy, cz;
+    cell_xyz(g, c, cx, cy, cz);
     const uint32_t x0 = (uint32_t)wrapc(cx - 1, nc), x1 = (uint32_t)cx, x2 = (uint32_t)wrapc(cx + 1, nc);
     int ri = uf_find_hint(parent, i);
     for (int oz = -1; oz <= 1; oz++) {
@@ -436,7 +439,8 @@ __global__ __launch_bounds__(kBlock, 8) void k_fof_sparse(const uint32_t *__rest
         uint32_t ra[9], rb[9];
 #pragma unroll
         for (int oy = -1; oy <= 1; oy++) {
-            const uint32_t row = ((uint32_t)z * (uint32_t)nc + (uint32_t)wrapc(cy + oy, nc)) * (uint32_t)nc;
+            const uint32_t row =
+                g.cell_base + ((uint32_t)z * (uint32_t)nc + (uint32_t)wrapc(cy + oy, nc)) * (uint32_t)nc;
             const int r = (oy + 1) * 3;
             ra[r + 0] = off[row + x0];
             rb[r + 0] = off[row + x0 + 1];
@@ -496,10 +500,11 @@ __global__ __launch_bounds__(kBlock) void k_fof_roots(int64_t n, const int32_t *
     if (r >= 0 && run.rank == 0) atomicMin(&minorig[r], m);
 }
 
-// Group key (smallest original index of the group) per sorted particle, and the
-// L0 label in original order.  A key outside [0, n) would be an internal error;
-// it is flagged instead of being used as an index.
-__global__ __launch_bounds__(kBlock) void k_fof_keys(int64_t n, const int32_t *__restrict__ root,
+// Group key (smallest original index of the group, in the call's numbering)
+// per sorted particle, and the L0 label (box-local) in original order.  A key
+// outside [0, n) would be an internal error; it is flagged instead of being
+// used as an index.
+__global__ __launch_bounds__(kBlock) void k_fof_keys(int64_t n, Boxes bx, const int32_t *__restrict__ root,
                                                      const int32_t *__restrict__ minorig,
                                                      const float4 *__restrict__ spos,
                                                      int32_t *__restrict__ gkey,
@@ -507,14 +512,15 @@ __global__ __launch_bounds__(kBlock) void k_fof_keys(int64_t n, const int32_t *_
                                                      int32_t *__restrict__ err) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const int box = box_of(bx, (uint32_t)i);
     const int r = root[i];
     int k = r < 0 ? -1 : minorig[r];
     if (k >= n) {
-        atomicOr(err, 4);
+        flag_error(err, 4, box);
         k = -1;
     }
     gkey[i] = k;
-    if (l0_out) l0_out[orig_of(spos[i])] = k + 1;
+    if (l0_out) l0_out[orig_of(spos[i])] = k < 0 ? 0 : k + 1 - (int)bx.geo[box].orig_base;
 }
 
 // Group keys from caller-provided labels (1..n, 0 = none), in sorted order,
@@ -531,7 +537,8 @@ __global__ __launch_bounds__(kBlock) void k_pack_labels(int64_t n, const int32_t
     packed[o] = make_uint2((uint32_t)l0_in[o], __float_as_uint(dens_in[o]));
 }
 
-__global__ __launch_bounds__(kBlock) void k_keys_from_labels(int64_t n, const int32_t *__restrict__ l0_in,
+__global__ __launch_bounds__(kBlock) void k_keys_from_labels(int64_t n, Boxes bx,
+                                                             const int32_t *__restrict__ l0_in,
                                                              const uint2 *__restrict__ packed,
                                                              const float4 *__restrict__ spos,
                                                              int32_t *__restrict__ gkey,
@@ -539,6 +546,8 @@ __global__ __launch_bounds__(kBlock) void k_keys_from_labels(int64_t n, const in
                                                              int32_t *__restrict__ err) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const int box = box_of(bx, (uint32_t)i);
+    const Geo &g = bx.geo[box];
     const uint32_t o = orig_of(spos[i]);
     int32_t lab;
     if (packed) {
@@ -549,39 +558,40 @@ __global__ __launch_bounds__(kBlock) void k_keys_from_labels(int64_t n, const in
         // (the same value), NaN and negative values are rejected
         uint32_t db = v.y == 0x80000000u ? 0u : v.y;
         if ((db >> 31) != 0u || (db & 0x7fffffffu) > 0x7f800000u) {
-            atomicOr(err, 16);
+            flag_error(err, 16, box);
             db = 0u;
         }
         dens_s[i] = __uint_as_float(db);
     } else {
         lab = l0_in[o];
     }
-    if (lab < 0 || (int64_t)lab > n) {
-        atomicOr(err, 2);
+    // labels are box-local (1 .. box size, 0 = outside every group)
+    if (lab < 0 || (int64_t)lab > g.n) {
+        flag_error(err, 2, box);
         lab = 0;
     }
-    gkey[i] = lab - 1;
+    gkey[i] = lab > 0 ? lab - 1 + (int32_t)g.orig_base : -1;
 }
 
 }  // namespace
 
-void launch_fof(int64_t n, const Geo &g, Work &w, hipStream_t s) {
-    hipLaunchKernelGGL(k_fof_phase_a, grid(n), dim3(kBlock), 0, s, n, g, w.sloc, w.f_sparse, w.ssub, w.cnt,
+void launch_fof(int64_t n, const Boxes &bx, Work &w, hipStream_t s) {
+    hipLaunchKernelGGL(k_fof_phase_a, grid(n), dim3(kBlock), 0, s, n, bx, w.sloc, w.f_sparse, w.ssub, w.cnt,
                        w.subtab, w.dens_s, w.parent);
     if (w.nchunks > 0)
         // one wavefront per workgroup: chunk costs differ widely, and a
         // finished wavefront's slot is free at once
-        hipLaunchKernelGGL(k_fof_dense, dim3((unsigned)w.nchunks), dim3(64), 0, s, w.nchunks, g,
+        hipLaunchKernelGGL(k_fof_dense, dim3((unsigned)w.nchunks), dim3(64), 0, s, w.nchunks, bx,
                            w.chunks, w.sloc, w.spos, w.off, w.cnt, w.subtab, w.dens_s, w.parent);
     if (w.nsparse > 0) {
         // sparse members: flags, positions and list in arrays that are free
         // during this stage (chunk flags of the binning, the hard-case list)
-        hipLaunchKernelGGL(k_fof_sparse_flags, grid(w.nsparse), dim3(kBlock), 0, s, w.nsparse, g, w.sparse,
+        hipLaunchKernelGGL(k_fof_sparse_flags, grid(w.nsparse), dim3(kBlock), 0, s, w.nsparse, bx, w.sparse,
                            w.dens_s, w.f_chunk);
         scan_u32(w.f_chunk, w.s_chunk, w.nsparse, w.scan_tmp, s);
         hipLaunchKernelGGL(k_fof_sparse_list, grid(w.nsparse), dim3(kBlock), 0, s, w.nsparse, w.sparse,
                            w.f_chunk, w.s_chunk, w.hardlist);
-        hipLaunchKernelGGL(k_fof_sparse, grid(w.nsparse), dim3(kBlock), 0, s, w.s_chunk + w.nsparse, g,
+        hipLaunchKernelGGL(k_fof_sparse, grid(w.nsparse), dim3(kBlock), 0, s, w.s_chunk + w.nsparse, bx,
                            w.hardlist, w.sloc, w.spos, w.off, w.dens_s, w.parent);
     }
     // roots go to the owner array (free until the assignment stage)
@@ -589,19 +599,20 @@ void launch_fof(int64_t n, const Geo &g, Work &w, hipStream_t s) {
     hipLaunchKernelGGL(k_fof_roots, grid(n), dim3(kBlock), 0, s, n, w.parent, w.spos, w.owner, w.minorig);
 }
 
-void launch_fof_labels(int64_t n, const Geo &, Work &w, int32_t *l0_out, hipStream_t s) {
-    hipLaunchKernelGGL(k_fof_keys, grid(n), dim3(kBlock), 0, s, n, w.owner, w.minorig, w.spos, w.gkey,
+void launch_fof_labels(int64_t n, const Boxes &bx, Work &w, int32_t *l0_out, hipStream_t s) {
+    hipLaunchKernelGGL(k_fof_keys, grid(n), dim3(kBlock), 0, s, n, bx, w.owner, w.minorig, w.spos, w.gkey,
                        l0_out, w.err);
 }
 
-void launch_keys_from_labels(const int32_t *l0_in, const float *dens_in, int64_t n, Work &w, hipStream_t s) {
+void launch_keys_from_labels(const int32_t *l0_in, const float *dens_in, int64_t n, const Boxes &bx, Work &w,
+                             hipStream_t s) {
     // the packed copy lives in the second radix key array (free after binning)
     uint2 *packed = nullptr;
     if (dens_in) {
         packed = reinterpret_cast<uint2 *>(w.rkey[1]);
         hipLaunchKernelGGL(k_pack_labels, grid(n), dim3(kBlock), 0, s, n, l0_in, dens_in, packed);
     }
-    hipLaunchKernelGGL(k_keys_from_labels, grid(n), dim3(kBlock), 0, s, n, l0_in, packed, w.spos, w.gkey,
+    hipLaunchKernelGGL(k_keys_from_labels, grid(n), dim3(kBlock), 0, s, n, bx, l0_in, packed, w.spos, w.gkey,
                        w.dens_s, w.err);
 }
 

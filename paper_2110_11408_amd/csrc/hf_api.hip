@@ -1,5 +1,8 @@
 // C ABI of libhf: argument checks, derived constants, the scratch arena of a
-// context, and the order of the stages for each entry point.
+// context, and the order of the stages for each entry point.  Every pass runs
+// over a set of boxes at once (a single-box call is a set of one): the boxes'
+// constants go to the device as a table, particles and cells are numbered box
+// after box, and each stage is one launch over all of them.
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
@@ -123,6 +126,7 @@ hf_status make_geo(Lane *c, const hf_params *p, int64_t n, Geo *g) {
     if (kd > 6.0)
         return fail(c, HF_ERR_INVALID, "l_fof must be at least 0.29 of the cell side (about 0.29 b)");
     g->ksub = (int)kd;
+    g->nsub = g->ksub * g->ksub * g->ksub;
     g->inv_sub = g->ksub / g->cell;
     g->sub2 = (g->cell / g->ksub) * (g->cell / g->ksub);
     g->rsub = (int)ceil(d[D_L] * g->ksub / g->cell);
@@ -148,6 +152,11 @@ hf_status make_geo(Lane *c, const hf_params *p, int64_t n, Geo *g) {
     g->C3 = d[D_C3];
     g->n_l1_min = p->n_l1_min;
     g->particle_mass = (float)p->particle_mass;
+    g->cell_base = 0;
+    g->orig_base = 0;
+    g->n = n;
+    g->halos = nullptr;
+    g->halo_cap = 0;
     return HF_OK;
 }
 
@@ -163,7 +172,8 @@ struct Carver {
     }
 };
 
-size_t carve(char *base, int64_t n, int64_t ncell, int nsub, int64_t rhl, bool extra, Work *w) {
+
+size_t carve(char *base, int64_t n, int64_t ncell, int nsub, int64_t rhl, int nbox, bool extra, Work *w) {
     Carver c{base};
     int64_t n1 = n + 1;
     w->cnt = c.take<uint32_t>(ncell + 1);
@@ -224,16 +234,113 @@ size_t carve(char *base, int64_t n, int64_t ncell, int nsub, int64_t rhl, bool e
     w->scan_tmp = c.take<uint32_t>(hf::scan_tmp_words(scan_len + 1));
     w->counters = c.take<int32_t>(16);
     w->err = c.take<int32_t>(4);
+    w->geo = c.take<Geo>(nbox);
+    w->geo2 = extra ? c.take<Geo>(nbox) : nullptr;
+    w->base = c.take<uint32_t>(nbox + 1);
+    w->box_rows = c.take<int64_t>(nbox);
     w->gcom = extra ? c.take<double>(6 * n1) : nullptr;
     w->ordk = extra ? c.take<int32_t>(n1) : nullptr;
     return c.off + 256;
 }
 
-hf_status prepare(Lane *c, int64_t n, const Geo &g, Work *w, bool extra, const hf::FixedArena *fx) {
-    int64_t ncell = (int64_t)g.nc * g.nc * g.nc;
-    const int nsub = g.ksub * g.ksub * g.ksub;
-    const int64_t rhl = hf::radix_hist_len(n, g);
-    size_t need = carve(nullptr, n, ncell, nsub, rhl, extra, w);
+// The boxes of one call: their constants, particle ranges and cell ranges.
+struct Plan {
+    int nbox = 0;
+    int first = 0;       // the caller's number of box 0
+    bool named = false;  // error texts name the box
+    int64_t n = 0;       // particles of all boxes
+    int64_t ncell = 0;   // cells of all boxes
+    int nsub_max = 1;
+    std::vector<Geo> geo;
+    std::vector<uint32_t> base;
+};
+
+std::string box_prefix(const Plan *pl, int b) {
+    return pl && (pl->named || pl->nbox > 1) ? "box " + std::to_string(pl->first + b) + ": " : std::string();
+}
+
+// Checks the boxes' arguments and derives their constants.  An empty box
+// only has its parameters checked (with a mean density of 1 when none is
+// given) and takes no cells.
+hf_status plan_boxes(Lane *c, const hf::BoxSet &bs, Plan *pl) {
+    if (bs.nbox < 0) return fail(c, HF_ERR_INVALID, "n_boxes is negative");
+    if (bs.nbox > 0 && (!bs.offsets || !bs.params)) return fail(c, HF_ERR_INVALID, "box offsets / params is NULL");
+    pl->nbox = bs.nbox;
+    pl->first = bs.first;
+    pl->named = bs.named;
+    pl->geo.assign(bs.nbox, Geo{});
+    pl->base.assign(bs.nbox + 1, 0u);
+    if (bs.nbox == 0) return HF_OK;
+    if (bs.offsets[0] != 0) return fail(c, HF_ERR_INVALID, "box offsets must start at 0");
+    if (bs.halo_offsets && bs.halo_offsets[0] != 0) return fail(c, HF_ERR_INVALID, "halo offsets must start at 0");
+    for (int b = 0; b < bs.nbox; b++) {
+        const int64_t nb = bs.offsets[b + 1] - bs.offsets[b];
+        if (nb < 0) return fail(c, HF_ERR_INVALID, box_prefix(pl, b) + "n is negative (offsets decrease)");
+        if (bs.halo_offsets && bs.halo_offsets[b + 1] < bs.halo_offsets[b])
+            return fail(c, HF_ERR_INVALID, "halo offsets must not decrease");
+    }
+    if (bs.offsets[bs.nbox] >= (int64_t)0x7fffffff) return fail(c, HF_ERR_INVALID, "n must be below 2^31 - 1");
+    for (int b = 0; b < bs.nbox; b++) {
+        const int64_t o = bs.offsets[b], nb = bs.offsets[b + 1] - o;
+        Geo &g = pl->geo[b];
+        if (nb == 0) {
+            double d[D_COUNT];
+            hf_params q = bs.params[b];
+            if (!(q.mean_density > 0.0)) q.mean_density = 1.0;
+            if (derive(&q, 1, d) != HF_OK) return fail(c, HF_ERR_INVALID, box_prefix(pl, b) + "invalid parameters");
+            g.nsub = 1;
+        } else {
+            const hf_status st = make_geo(c, &bs.params[b], nb, &g);
+            if (st != HF_OK) {
+                c->err = box_prefix(pl, b) + c->err;
+                return st;
+            }
+            g.cell_base = (uint32_t)pl->ncell;
+            pl->ncell += (int64_t)g.nc * g.nc * g.nc;
+            if (pl->ncell >= (int64_t)0xffffffff)
+                return fail(c, HF_ERR_INVALID, "the boxes of one call hold more than 2^32 - 1 cells");
+            if (g.nsub > pl->nsub_max) pl->nsub_max = g.nsub;
+        }
+        g.orig_base = (uint32_t)o;
+        g.n = nb;
+        if (bs.halos && bs.halo_offsets) {
+            g.halos = bs.halos + bs.halo_offsets[b];
+            g.halo_cap = bs.halo_offsets[b + 1] - bs.halo_offsets[b];
+        }
+        pl->base[b] = (uint32_t)o;
+    }
+    pl->n = bs.offsets[bs.nbox];
+    pl->base[bs.nbox] = (uint32_t)pl->n;
+    // cells with nothing to bin still end the offset grid: at least one
+    if (pl->ncell == 0) pl->ncell = 1;
+    return HF_OK;
+}
+
+size_t plan_arena_bytes(const Plan &pl, bool extra) {
+    Work w;
+    return carve(nullptr, pl.n, pl.ncell, pl.nsub_max, hf::radix_hist_len(pl.n), pl.nbox, extra, &w);
+}
+
+// Pinned staging of at least `bytes` (grown unless nothing may be allocated).
+hf_status ensure_stage(Lane *c, size_t bytes, bool may_grow) {
+    if (bytes <= c->stage_bytes) return HF_OK;
+    if (!may_grow) return fail(c, HF_ERR_INVALID, "too many boxes for the staging of an allocation-free call");
+    if (c->stage) (void)hipHostFree(c->stage);
+    c->stage = nullptr;
+    c->stage_bytes = 0;
+    const size_t want = bytes + bytes / 2;
+    if (hipHostMalloc(&c->stage, want, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        c->stage = nullptr;
+        return fail(c, HF_ERR_NOMEM, "hipHostMalloc of the box tables failed");
+    }
+    c->stage_bytes = want;
+    return HF_OK;
+}
+
+hf_status prepare(Lane *c, const Plan &pl, Work *w, bool extra, const hf::FixedArena *fx) {
+    const int64_t rhl = hf::radix_hist_len(pl.n);
+    size_t need = carve(nullptr, pl.n, pl.ncell, pl.nsub_max, rhl, pl.nbox, extra, w);
     HIP_OK(c, hipSetDevice(c->device));
     if (fx) {
         // a caller-given region: nothing is allocated
@@ -241,42 +348,41 @@ hf_status prepare(Lane *c, int64_t n, const Geo &g, Work *w, bool extra, const h
             return fail(c, HF_ERR_INVALID,
                         "this box needs " + std::to_string(need) + " bytes of scratch, more than the " +
                             std::to_string(fx->bytes) + " of the static scratch");
-        carve((char *)fx->base, n, ncell, nsub, rhl, extra, w);
-        w->host = c->host;
-        c->stats = hf_stats{};
-        c->stats.n_cells = ncell;
-        return HF_OK;
+        carve((char *)fx->base, pl.n, pl.ncell, pl.nsub_max, rhl, pl.nbox, extra, w);
+    } else {
+        if (need > c->arena_bytes) {
+            if (c->arena) {
+                // every call ends synchronized with its stream, so the old arena is idle
+                HIP_OK(c, hipFree(c->arena));
+                if (c->budget) c->budget->give(c->arena_bytes);
+                c->arena = nullptr;
+                c->arena_bytes = 0;
+            }
+            size_t want = need + need / 8;
+            if (c->budget && !c->budget->take(want)) {
+                want = need;  // no headroom for the next, larger call
+                if (!c->budget->take(want))
+                    return fail(c, HF_ERR_NOMEM,
+                                "the scratch arena of " + std::to_string(need) +
+                                    " bytes exceeds the context's HBM budget (" +
+                                    std::to_string(c->budget->held.load()) + " of " +
+                                    std::to_string(c->budget->limit) + " bytes held)");
+            }
+            if (hipMalloc(&c->arena, want) != hipSuccess) {
+                (void)hipGetLastError();
+                c->arena = nullptr;
+                if (c->budget) c->budget->give(want);
+                return fail(c, HF_ERR_NOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+            }
+            c->arena_bytes = want;
+        }
+        carve((char *)c->arena, pl.n, pl.ncell, pl.nsub_max, rhl, pl.nbox, extra, w);
     }
-    if (need > c->arena_bytes) {
-        if (c->arena) {
-            // every call ends synchronized with its stream, so the old arena is idle
-            HIP_OK(c, hipFree(c->arena));
-            if (c->budget) c->budget->give(c->arena_bytes);
-            c->arena = nullptr;
-            c->arena_bytes = 0;
-        }
-        size_t want = need + need / 8;
-        if (c->budget && !c->budget->take(want)) {
-            want = need;  // no headroom for the next, larger call
-            if (!c->budget->take(want))
-                return fail(c, HF_ERR_NOMEM,
-                            "the scratch arena of " + std::to_string(need) + " bytes exceeds the context's HBM budget (" +
-                                std::to_string(c->budget->held.load()) + " of " + std::to_string(c->budget->limit) +
-                                " bytes held)");
-        }
-        if (hipMalloc(&c->arena, want) != hipSuccess) {
-            (void)hipGetLastError();
-            c->arena = nullptr;
-            if (c->budget) c->budget->give(want);
-            return fail(c, HF_ERR_NOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed");
-        }
-        c->arena_bytes = want;
-    }
-    carve((char *)c->arena, n, ncell, nsub, rhl, extra, w);
     w->host = c->host;
     c->stats = hf_stats{};
-    c->stats.n_cells = ncell;
-    return HF_OK;
+    c->stats.n_cells = pl.ncell;
+    // the box tables go up and the per-box rows come back through it
+    return ensure_stage(c, pl.nbox * (2 * sizeof(Geo) + sizeof(uint32_t) + sizeof(int64_t)) + 4096, fx == nullptr);
 }
 
 // Device words read back in one dispatch and one wait (the lane's pinned host
@@ -289,22 +395,25 @@ hf_status read_dev(Lane *c, hipStream_t s, std::initializer_list<const void *> s
     return HF_OK;
 }
 
-hf_status err_status(Lane *c, uint32_t err) {
-    if (err & 1) return fail(c, HF_ERR_INVALID, "positions must lie in [0, box)");
-    if (err & 2) return fail(c, HF_ERR_INVALID, "l0_id values must lie in [0, n]");
-    if (err & 16) return fail(c, HF_ERR_INVALID, "densities must be non-negative numbers");
+// The error bits raised by the kernels (box: the smallest box that raised
+// one, named when the call has several boxes).
+hf_status err_status(Lane *c, uint32_t err, uint32_t box, const Plan *pl) {
+    const std::string pre = box_prefix(pl, (int)box);
+    if (err & 1) return fail(c, HF_ERR_INVALID, pre + "positions must lie in [0, box)");
+    if (err & 2) return fail(c, HF_ERR_INVALID, pre + "l0_id values must lie in [0, n]");
+    if (err & 16) return fail(c, HF_ERR_INVALID, pre + "densities must be non-negative numbers");
     if (err & 8)
         return fail(c, HF_ERR_INVALID,
-                    "an L0 group spans half the periodic box or more along an axis (minimum-image "
-                    "distances would be ambiguous)");
-    if (err & 4) return fail(c, HF_ERR_DEVICE, "internal error: L0 group key out of range");
+                    pre + "an L0 group spans half the periodic box or more along an axis (minimum-image "
+                          "distances would be ambiguous)");
+    if (err & 4) return fail(c, HF_ERR_DEVICE, pre + "internal error: L0 group key out of range");
     return HF_OK;
 }
 
-hf_status check_pos_flags(Lane *c, const Work &w, hipStream_t s) {
-    uint32_t err = 0;
-    hf_status st = read_dev(c, s, {w.err}, &err);
-    return st != HF_OK ? st : err_status(c, err);
+hf_status check_pos_flags(Lane *c, const Work &w, const Plan *pl, hipStream_t s) {
+    uint32_t e[2] = {0, 0};
+    hf_status st = read_dev(c, s, {w.err, w.err + 1}, e);
+    return st != HF_OK ? st : err_status(c, e[0], e[1], pl);
 }
 
 float elapsed(hipEvent_t a, hipEvent_t b) {
@@ -317,25 +426,26 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 }
 
 // CompaSO on the binned particles with group keys in w.gkey.  Fills halo_id,
-// the table and the counts; records events ev[3..8].
-hf_status run_compaso(Lane *c, int64_t n, const Geo &g, Work &w, int32_t *halo_id,
-                      int32_t *l0_out, hf_halo *halos, int64_t cap, int64_t *n_halos,
-                      hipStream_t s) {
+// l0_out (may be null), every box's table and its row count (n_halos, host,
+// nbox entries); records events ev[3..8].  CAPACITY when a table did not fit.
+hf_status run_compaso(Lane *c, const Plan &pl, const hf::Boxes &bx, Work &w, int32_t *halo_id,
+                      int32_t *l0_out, int64_t *n_halos, hipStream_t s) {
+    const int64_t n = pl.n;
     HIP_OK(c, hipEventRecord(c->ev[3], s));
     hf::launch_segment(n, w, s);
     // group and member counts, and the error flags of the steps so far (the
     // kernels before this point clamp what they index, whatever the flags)
-    uint32_t r[3];
-    hf_status st = read_dev(c, s, {w.gidx + n, w.goff + n, w.err}, r);
-    if (st == HF_OK) st = err_status(c, r[2]);
+    uint32_t r[4];
+    hf_status st = read_dev(c, s, {w.gidx + n, w.goff + n, w.err, w.err + 1}, r);
+    if (st == HF_OK) st = err_status(c, r[2], r[3], &pl);
     if (st != HF_OK) return st;
     int64_t G = r[0];
     c->stats.n_groups = G;
     c->stats.n_members = r[1];
     hf::launch_segment_groups(n, G, w, s);
-    hf::launch_extent(G, c->stats.n_members, g, w, s);
+    hf::launch_extent(G, c->stats.n_members, bx, w, s);
     HIP_OK(c, hipEventRecord(c->ev[4], s));
-    hf::launch_candidates(n, g, w, s);
+    hf::launch_candidates(n, bx, w, s);
     hf::scan_u32(w.gccnt, w.gcoff, G, w.scan_tmp, s);
     uint32_t NC32 = 0;
     st = read_dev(c, s, {w.gcoff + G}, &NC32);
@@ -343,21 +453,20 @@ hf_status run_compaso(Lane *c, int64_t n, const Geo &g, Work &w, int32_t *halo_i
     int64_t NC = NC32;
     hf::launch_candidates_sort(n, G, NC, w, s);
     HIP_OK(c, hipEventRecord(c->ev[5], s));
-    hf::launch_accept(n, G, NC, c->stats.n_members, g, w, s);
+    hf::launch_accept(n, G, NC, c->stats.n_members, bx, w, s);
     HIP_OK(c, hipEventRecord(c->ev[6], s));
-    hf::launch_assign(n, g, w, s);
+    hf::launch_assign(n, bx, w, s);
     HIP_OK(c, hipEventRecord(c->ev[7], s));
-    hf::launch_output_flags(n, NC, g, w, s);
-    uint32_t r2[3];  // table rows; nuclei accepted (counter 2); error flags
-    st = read_dev(c, s, {w.tpos + n, w.counters + 2, w.err}, r2);
-    if (st == HF_OK) st = err_status(c, r2[2]);
-    if (st != HF_OK) return st;
-    int64_t NH = r2[0];
-    if (n_halos) *n_halos = NH;
-    bool fits = NH <= cap;
-    hf::launch_output(n, NC, g, w, halo_id, l0_out, fits ? halos : nullptr, cap, s);
+    hf::launch_output_flags(n, NC, bx, w, s);
+    hf::launch_output(n, NC, bx, w, halo_id, l0_out, w.box_rows, s);
     HIP_OK(c, hipEventRecord(c->ev[8], s));
-    HIP_OK(c, hipStreamSynchronize(s));
+    // every box's rows, the nuclei accepted (counter 2) and the error flags
+    int64_t *rows = reinterpret_cast<int64_t *>(c->stage);
+    HIP_OK(c, hipMemcpyAsync(rows, w.box_rows, sizeof(int64_t) * pl.nbox, hipMemcpyDeviceToHost, s));
+    uint32_t r2[3];
+    st = read_dev(c, s, {w.counters + 2, w.err, w.err + 1}, r2);
+    if (st == HF_OK) st = err_status(c, r2[1], r2[2], &pl);
+    if (st != HF_OK) return st;
     c->stats.ms_segment = elapsed(c->ev[3], c->ev[4]);
     c->stats.ms_candidates = elapsed(c->ev[4], c->ev[5]);
     c->stats.ms_accept = elapsed(c->ev[5], c->ev[6]);
@@ -368,38 +477,45 @@ hf_status run_compaso(Lane *c, int64_t n, const Geo &g, Work &w, int32_t *halo_i
     c->stats.n_dense_chunks = w.nchunks;
     c->stats.n_sparse = w.nsparse;
     c->stats.n_hard = w.nhard;
-    c->stats.n_found = r2[1];
-    c->stats.n_halos = NH;
-    if (!fits) return fail(c, HF_ERR_CAPACITY, "halos_cap is smaller than the number of halos");
+    c->stats.n_found = r2[0];
+    int over = -1;
+    int64_t total = 0;
+    for (int b = 0; b < pl.nbox; b++) {
+        if (n_halos) n_halos[b] = rows[b];
+        total += rows[b];
+        if (over < 0 && rows[b] > pl.geo[b].halo_cap) over = b;
+    }
+    c->stats.n_halos = total;
+    if (over >= 0)
+        return fail(c, HF_ERR_CAPACITY,
+                    box_prefix(&pl, over) + "halos_cap is smaller than the number of halos");
     return HF_OK;
 }
 
+// Uploads the box tables, bins all particles and reads the work counts.
 // dens: the call computes densities (binning also writes the records the
-// density kernel reads); extra: halo statistics buffers.
-hf_status begin(Lane *c, const float *pos, int64_t n, const hf_params *p, Geo *g, Work *w,
-                hipStream_t s, bool dens, bool extra = false, const hf::FixedArena *fx = nullptr) {
-    if (!c) return HF_ERR_INVALID;
-    c->err.clear();
-    if (!p) return fail(c, HF_ERR_INVALID, "params is NULL");
-    if (n < 0) return fail(c, HF_ERR_INVALID, "n is negative");
-    if (n == 0) {
-        // an empty input is valid; only the parameter values are checked
-        double d[D_COUNT];
-        hf_params q = *p;
-        if (!(q.mean_density > 0.0)) q.mean_density = 1.0;
-        if (derive(&q, 1, d) != HF_OK) return fail(c, HF_ERR_INVALID, "invalid parameters");
-        return HF_OK;
-    }
-    hf_status st = make_geo(c, p, n, g);
-    if (st != HF_OK) return st;
-    if (!pos) return fail(c, HF_ERR_INVALID, "pos is NULL");
-    st = prepare(c, n, *g, w, extra, fx);
+// density kernel reads); extra: halo statistics buffers.  bx receives the
+// device view of the boxes.
+hf_status begin(Lane *c, const Plan &pl, const float *pos, hf::Boxes *bx, Work *w, hipStream_t s, bool dens,
+                bool extra = false, const hf::FixedArena *fx = nullptr) {
+    if (pl.n > 0 && !pos) return fail(c, HF_ERR_INVALID, "pos is NULL");
+    hf_status st = prepare(c, pl, w, extra, fx);
     if (st != HF_OK) return st;
     if (!dens) w->pq = nullptr;
+    // the tables through pinned staging (the lane's previous call has ended)
+    char *stg = reinterpret_cast<char *>(c->stage);
+    memcpy(stg, pl.geo.data(), sizeof(Geo) * pl.nbox);
+    memcpy(stg + sizeof(Geo) * pl.nbox, pl.base.data(), sizeof(uint32_t) * (pl.nbox + 1));
+    HIP_OK(c, hipMemcpyAsync(w->geo, stg, sizeof(Geo) * pl.nbox, hipMemcpyHostToDevice, s));
+    HIP_OK(c, hipMemcpyAsync(w->base, stg + sizeof(Geo) * pl.nbox, sizeof(uint32_t) * (pl.nbox + 1),
+                             hipMemcpyHostToDevice, s));
+    *bx = hf::Boxes{w->geo, w->base, pl.nbox, pl.nsub_max};
     hf::fill_i32(w->counters, 0, 16, s);
-    hf::fill_i32(w->err, 0, 4, s);
+    hf::fill_i32(w->err, 0, 1, s);
+    hf::fill_i32(w->err + 1, 0x7fffffff, 1, s);
+    const int64_t n = pl.n;
     HIP_OK(c, hipEventRecord(c->ev[0], s));
-    hf::launch_bin(pos, n, *g, *w, s);
+    hf::launch_bin(pos, n, pl.ncell, *bx, *w, s);
     // dense chunks, dense cells, sparse particles, and the range flag of the
     // positions (binning clamps cells, so nothing it wrote is out of bounds).
     // The sub-cell tables take their cell count on the device and are
@@ -410,13 +526,14 @@ hf_status begin(Lane *c, const float *pos, int64_t n, const hf_params *p, Geo *g
     src.p[1] = w->s_dcell + n;
     src.p[2] = w->s_sparse + n;
     src.p[3] = reinterpret_cast<const uint32_t *>(w->err);
-    HIP_OK(c, hf::publish_words(src, 4, c->host, s));
+    src.p[4] = reinterpret_cast<const uint32_t *>(w->err + 1);
+    HIP_OK(c, hf::publish_words(src, 5, c->host, s));
     HIP_OK(c, hipEventRecord(c->pub, s));
-    hf::launch_subtab(n, w->s_dcell + n, *g, *w, s);
+    hf::launch_subtab(n, w->s_dcell + n, *bx, *w, s);
     HIP_OK(c, hipEventSynchronize(c->pub));
-    uint32_t counts[4];
-    hf::collect_words(c->host, 4, counts);
-    st = err_status(c, counts[3]);
+    uint32_t counts[5];
+    hf::collect_words(c->host, 5, counts);
+    st = err_status(c, counts[3], counts[4], &pl);
     if (st != HF_OK) {
         // the sub-cell tables may still run on s: a failed call also ends
         // synchronized with its stream, so the arena is idle when it returns
@@ -431,6 +548,45 @@ hf_status begin(Lane *c, const float *pos, int64_t n, const hf_params *p, Geo *g
     return HF_OK;
 }
 
+// A single box as a set of one.
+struct OneBox {
+    int64_t offs[2];
+    int64_t hoffs[2];
+    hf::BoxSet set(const hf_params *p, hf_halo *halos) const {
+        return hf::BoxSet{1, offs, p, halos, hoffs};
+    }
+};
+
+OneBox one_box(int64_t n, int64_t cap) { return OneBox{{0, n}, {0, cap > 0 ? cap : 0}}; }
+
+hf_status find_boxes(Lane *c, const hf::BoxSet &bs, const float *pos, float *density, int32_t *l0_id,
+                     int32_t *halo_id, int64_t *n_halos, hipStream_t s, const hf::FixedArena *fx) {
+    if (!c) return HF_ERR_INVALID;
+    c->err.clear();
+    Plan pl;
+    hf_status st = plan_boxes(c, bs, &pl);
+    if (st != HF_OK) return st;
+    if (n_halos)
+        for (int b = 0; b < pl.nbox; b++) n_halos[b] = 0;
+    if (pl.n == 0) return HF_OK;
+    if (!halo_id) return fail(c, HF_ERR_INVALID, "halo_id is NULL");
+    hf::Boxes bx;
+    Work w;
+    st = begin(c, pl, pos, &bx, &w, s, true, false, fx);
+    if (st != HF_OK) return st;
+    hf::launch_density(pl.n, bx, w, density, s);
+    HIP_OK(c, hipEventRecord(c->ev[2], s));
+    hf::launch_fof(pl.n, bx, w, s);
+    hf::launch_fof_labels(pl.n, bx, w, l0_id, s);
+    HIP_OK(c, hipEventRecord(c->ev[9], s));
+    st = run_compaso(c, pl, bx, w, halo_id, nullptr, n_halos, s);
+    c->stats.ms_bin = elapsed(c->ev[0], c->ev[1]);
+    c->stats.ms_density = elapsed(c->ev[1], c->ev[2]);
+    c->stats.ms_fof = elapsed(c->ev[2], c->ev[9]);
+    c->stats.ms_total = elapsed(c->ev[0], c->ev[8]);
+    return st;
+}
+
 }  // namespace
 
 namespace hf {
@@ -443,6 +599,12 @@ hf_status lane_init(Lane *L, int device, bool own_stream) {
         L->host = nullptr;
         return HF_ERR_DEVICE;
     }
+    // room for the tables of a few hundred boxes; larger calls grow it
+    if (hipHostMalloc(&L->stage, 64 << 10, hipHostMallocDefault) != hipSuccess) {
+        L->stage = nullptr;
+        return HF_ERR_DEVICE;
+    }
+    L->stage_bytes = 64 << 10;
     for (auto &e : L->ev)
         if (hipEventCreate(&e) != hipSuccess) return HF_ERR_DEVICE;
     if (hipEventCreateWithFlags(&L->pub, hipEventDisableTiming) != hipSuccess) return HF_ERR_DEVICE;
@@ -465,6 +627,9 @@ void lane_destroy(Lane *L) {
     lane_release(L);
     if (L->host) (void)hipHostFree(L->host);
     L->host = nullptr;
+    if (L->stage) (void)hipHostFree(L->stage);
+    L->stage = nullptr;
+    L->stage_bytes = 0;
     for (auto &e : L->ev)
         if (e) (void)hipEventDestroy(e);
     if (L->pub) (void)hipEventDestroy(L->pub);
@@ -473,40 +638,38 @@ void lane_destroy(Lane *L) {
     L->stream = nullptr;
 }
 
+size_t boxes_arena_bytes(const BoxSet &bs, int64_t *n_total, int64_t *ncell_total) {
+    Lane tmp;
+    Plan pl;
+    if (plan_boxes(&tmp, bs, &pl) != HF_OK) return 0;
+    if (n_total) *n_total = pl.n;
+    if (ncell_total) *ncell_total = pl.ncell;
+    const size_t need = plan_arena_bytes(pl, false);
+    return need + need / 8;
+}
+
 size_t lane_arena_bytes(const hf_params *p, int64_t n) {
     if (n <= 0) return 0;
-    Geo g;
-    Work w;
-    if (make_geo(nullptr, p, n, &g) != HF_OK) return 0;
-    const int64_t ncell = (int64_t)g.nc * g.nc * g.nc;
-    const size_t need = carve(nullptr, n, ncell, g.ksub * g.ksub * g.ksub, hf::radix_hist_len(n, g), false, &w);
-    return need + need / 8;
+    const OneBox ob = one_box(n, 0);
+    return boxes_arena_bytes(ob.set(p, nullptr), nullptr, nullptr);
 }
 
 hf_status lane_find(Lane *c, const float *pos, int64_t n, const hf_params *p, float *density,
                     int32_t *l0_id, int32_t *halo_id, hf_halo *halos, int64_t halos_cap,
                     int64_t *n_halos, hipStream_t s, const FixedArena *fx) {
-    Geo g;
-    Work w;
-    if (n > 0 && !halo_id) return fail(c, HF_ERR_INVALID, "halo_id is NULL");
+    if (!c) return HF_ERR_INVALID;
     if (halos_cap < 0 || (halos_cap > 0 && !halos)) return fail(c, HF_ERR_INVALID, "bad halos / halos_cap");
-    hf_status st = begin(c, pos, n, p, &g, &w, s, true, false, fx);
-    if (st != HF_OK) return st;
-    if (n == 0) {
-        if (n_halos) *n_halos = 0;
-        return HF_OK;
-    }
-    hf::launch_density(n, g, w, density, s);
-    HIP_OK(c, hipEventRecord(c->ev[2], s));
-    hf::launch_fof(n, g, w, s);
-    hf::launch_fof_labels(n, g, w, l0_id, s);
-    HIP_OK(c, hipEventRecord(c->ev[9], s));
-    st = run_compaso(c, n, g, w, halo_id, nullptr, halos, halos_cap, n_halos, s);
-    c->stats.ms_bin = elapsed(c->ev[0], c->ev[1]);
-    c->stats.ms_density = elapsed(c->ev[1], c->ev[2]);
-    c->stats.ms_fof = elapsed(c->ev[2], c->ev[9]);
-    c->stats.ms_total = elapsed(c->ev[0], c->ev[8]);
+    if (n < 0) return fail(c, HF_ERR_INVALID, "n is negative");
+    const OneBox ob = one_box(n, halos_cap);
+    int64_t nh = 0;
+    const hf_status st = find_boxes(c, ob.set(p, halos), pos, density, l0_id, halo_id, &nh, s, fx);
+    if (n_halos) *n_halos = nh;
     return st;
+}
+
+hf_status lane_find_boxes(Lane *L, const BoxSet &bs, const float *pos, float *density, int32_t *l0_id,
+                          int32_t *halo_id, int64_t *n_halos, hipStream_t s) {
+    return find_boxes(L, bs, pos, density, l0_id, halo_id, n_halos, s, nullptr);
 }
 
 }  // namespace hf
@@ -602,15 +765,22 @@ hf_status hf_get_stats(const hf_ctx *c, hf_stats *out) {
 hf_status hf_density(hf_ctx *ctx, const float *pos, int64_t n, const hf_params *p, float *density,
                      void *stream) {
     Lane *c = ctx ? &ctx->main : nullptr;
+    if (!c) return HF_ERR_INVALID;
+    c->err.clear();
     hipStream_t s = (hipStream_t)stream;
-    Geo g;
-    Work w;
-    hf_status st = begin(c, pos, n, p, &g, &w, s, true);
+    if (n < 0) return fail(c, HF_ERR_INVALID, "n is negative");
+    const OneBox ob = one_box(n, 0);
+    Plan pl;
+    hf_status st = plan_boxes(c, ob.set(p, nullptr), &pl);
     if (st != HF_OK || n == 0) return st;
     if (!density) return fail(c, HF_ERR_INVALID, "density is NULL");
-    hf::launch_density(n, g, w, density, s);
+    hf::Boxes bx;
+    Work w;
+    st = begin(c, pl, pos, &bx, &w, s, true);
+    if (st != HF_OK) return st;
+    hf::launch_density(n, bx, w, density, s);
     HIP_OK(c, hipEventRecord(c->ev[2], s));
-    st = check_pos_flags(c, w, s);
+    st = check_pos_flags(c, w, &pl, s);
     c->stats.ms_bin = elapsed(c->ev[0], c->ev[1]);
     c->stats.ms_density = elapsed(c->ev[1], c->ev[2]);
     c->stats.ms_total = elapsed(c->ev[0], c->ev[2]);
@@ -620,41 +790,55 @@ hf_status hf_density(hf_ctx *ctx, const float *pos, int64_t n, const hf_params *
 hf_status hf_count_pairs(hf_ctx *ctx, const float *pos, int64_t n, const hf_params *p,
                          int64_t *pairs, void *stream) {
     Lane *c = ctx ? &ctx->main : nullptr;
+    if (!c) return HF_ERR_INVALID;
+    c->err.clear();
     hipStream_t s = (hipStream_t)stream;
-    Geo g;
-    Work w;
     if (!pairs) return fail(c, HF_ERR_INVALID, "pairs is NULL");
     *pairs = 0;
-    hf_status st = begin(c, pos, n, p, &g, &w, s, false);
+    if (n < 0) return fail(c, HF_ERR_INVALID, "n is negative");
+    const OneBox ob = one_box(n, 0);
+    Plan pl;
+    hf_status st = plan_boxes(c, ob.set(p, nullptr), &pl);
     if (st != HF_OK || n == 0) return st;
+    hf::Boxes bx;
+    Work w;
+    st = begin(c, pl, pos, &bx, &w, s, false);
+    if (st != HF_OK) return st;
     hf::fill_i32(w.counters + 4, 0, 2, s);
-    hf::launch_count_pairs(n, g, w, (unsigned long long *)(w.counters + 4), s);
+    hf::launch_count_pairs(n, bx, w, (unsigned long long *)(w.counters + 4), s);
     HIP_OK(c, hipMemcpyAsync(pairs, w.counters + 4, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    return check_pos_flags(c, w, s);
+    return check_pos_flags(c, w, &pl, s);
 }
 
 hf_status hf_l0_fof(hf_ctx *ctx, const float *pos, const float *density, int64_t n,
                     const hf_params *p, int32_t *l0_id, int64_t *n_groups, void *stream) {
     Lane *c = ctx ? &ctx->main : nullptr;
+    if (!c) return HF_ERR_INVALID;
+    c->err.clear();
     hipStream_t s = (hipStream_t)stream;
-    Geo g;
-    Work w;
+    if (n < 0) return fail(c, HF_ERR_INVALID, "n is negative");
     if (n > 0 && (!density || !l0_id)) return fail(c, HF_ERR_INVALID, "density / l0_id is NULL");
-    hf_status st = begin(c, pos, n, p, &g, &w, s, false);
+    const OneBox ob = one_box(n, 0);
+    Plan pl;
+    hf_status st = plan_boxes(c, ob.set(p, nullptr), &pl);
     if (st != HF_OK) return st;
     if (n == 0) {
         if (n_groups) *n_groups = 0;
         return HF_OK;
     }
+    hf::Boxes bx;
+    Work w;
+    st = begin(c, pl, pos, &bx, &w, s, false);
+    if (st != HF_OK) return st;
     hf::launch_gather_density(density, n, w, s);
     HIP_OK(c, hipEventRecord(c->ev[2], s));
-    hf::launch_fof(n, g, w, s);
-    hf::launch_fof_labels(n, g, w, l0_id, s);
+    hf::launch_fof(n, bx, w, s);
+    hf::launch_fof_labels(n, bx, w, l0_id, s);
     HIP_OK(c, hipEventRecord(c->ev[3], s));
     hf::launch_segment(n, w, s);
-    uint32_t r[3] = {0, 0, 0};
-    st = read_dev(c, s, {w.gidx + n, w.goff + n, w.err}, r);
-    if (st == HF_OK) st = err_status(c, r[2]);
+    uint32_t r[4] = {0, 0, 0, 0};
+    st = read_dev(c, s, {w.gidx + n, w.goff + n, w.err, w.err + 1}, r);
+    if (st == HF_OK) st = err_status(c, r[2], r[3], &pl);
     const uint32_t G32 = r[0], M32 = r[1];
     c->stats.ms_bin = elapsed(c->ev[0], c->ev[1]);
     c->stats.ms_fof = elapsed(c->ev[2], c->ev[3]);
@@ -669,21 +853,30 @@ hf_status hf_compaso(hf_ctx *ctx, const float *pos, const float *density, const 
                      int64_t n, const hf_params *p, int32_t *halo_id, hf_halo *halos,
                      int64_t halos_cap, int64_t *n_halos, void *stream) {
     Lane *c = ctx ? &ctx->main : nullptr;
+    if (!c) return HF_ERR_INVALID;
+    c->err.clear();
     hipStream_t s = (hipStream_t)stream;
-    Geo g;
-    Work w;
+    if (n < 0) return fail(c, HF_ERR_INVALID, "n is negative");
     if (n > 0 && (!density || !l0_id || !halo_id))
         return fail(c, HF_ERR_INVALID, "density / l0_id / halo_id is NULL");
     if (halos_cap < 0 || (halos_cap > 0 && !halos)) return fail(c, HF_ERR_INVALID, "bad halos / halos_cap");
-    hf_status st = begin(c, pos, n, p, &g, &w, s, false);
+    const OneBox ob = one_box(n, halos_cap);
+    Plan pl;
+    hf_status st = plan_boxes(c, ob.set(p, halos), &pl);
     if (st != HF_OK) return st;
     if (n == 0) {
         if (n_halos) *n_halos = 0;
         return HF_OK;
     }
-    hf::launch_keys_from_labels(l0_id, density, n, w, s);  // also gathers the densities
+    hf::Boxes bx;
+    Work w;
+    st = begin(c, pl, pos, &bx, &w, s, false);
+    if (st != HF_OK) return st;
+    hf::launch_keys_from_labels(l0_id, density, n, bx, w, s);  // also gathers the densities
     HIP_OK(c, hipEventRecord(c->ev[2], s));
-    st = run_compaso(c, n, g, w, halo_id, nullptr, halos, halos_cap, n_halos, s);
+    int64_t nh = 0;
+    st = run_compaso(c, pl, bx, w, halo_id, nullptr, &nh, s);
+    if (n_halos) *n_halos = nh;
     c->stats.ms_bin = elapsed(c->ev[0], c->ev[1]);
     c->stats.ms_total = elapsed(c->ev[0], c->ev[8]);
     return st;
@@ -693,29 +886,44 @@ hf_status hf_halo_stats(hf_ctx *ctx, const float *pos, const float *density, con
                         int64_t n, const hf_params *p, int64_t n_halos, hf_halo_summary *stats,
                         int32_t *group_start, int32_t *group_members, void *stream) {
     Lane *c = ctx ? &ctx->main : nullptr;
+    if (!c) return HF_ERR_INVALID;
+    c->err.clear();
     hipStream_t s = (hipStream_t)stream;
-    Geo g, g2;
-    Work w;
+    if (n < 0) return fail(c, HF_ERR_INVALID, "n is negative");
     if (n > 0 && (!density || !halo_id)) return fail(c, HF_ERR_INVALID, "density / halo_id is NULL");
     if (n_halos < 0 || (n_halos > 0 && !stats)) return fail(c, HF_ERR_INVALID, "bad stats / n_halos");
-    hf_status st = begin(c, pos, n, p, &g, &w, s, false, true);
+    const OneBox ob = one_box(n, 0);
+    Plan pl;
+    hf_status st = plan_boxes(c, ob.set(p, nullptr), &pl);
     if (st != HF_OK) return st;
     if (n == 0) {
         if (n_halos != 0) return fail(c, HF_ERR_INVALID, "n_halos must be 0 for an empty input");
         return HF_OK;
     }
-    // level 2: the same steps with delta_l2 in place of delta_l1
+    // level 2: the same steps with delta_l2 in place of delta_l1 (the cells
+    // depend on b and l only, so the geometry is the same)
     hf_params p2 = *p;
     p2.delta_l1 = p->delta_l2;
+    Geo g2;
     st = make_geo(c, &p2, n, &g2);
     if (st != HF_OK) return st;
-    hf::launch_keys_from_labels(halo_id, density, n, w, s);  // also gathers the densities
+    hf::Boxes bx;
+    Work w;
+    st = begin(c, pl, pos, &bx, &w, s, false, true);
+    if (st != HF_OK) return st;
+    g2.cell_base = pl.geo[0].cell_base;
+    g2.orig_base = 0;
+    char *stg = reinterpret_cast<char *>(c->stage) + sizeof(Geo) * 2 + 256;
+    memcpy(stg, &g2, sizeof(Geo));
+    HIP_OK(c, hipMemcpyAsync(w.geo2, stg, sizeof(Geo), hipMemcpyHostToDevice, s));
+    const hf::Boxes bx2{w.geo2, w.base, 1, pl.nsub_max};
+    hf::launch_keys_from_labels(halo_id, density, n, bx, w, s);  // also gathers the densities
     HIP_OK(c, hipEventRecord(c->ev[2], s));
     HIP_OK(c, hipEventRecord(c->ev[3], s));
     hf::launch_segment(n, w, s);
-    uint32_t r[3];
-    st = read_dev(c, s, {w.gidx + n, w.goff + n, w.err}, r);
-    if (st == HF_OK) st = err_status(c, r[2]);
+    uint32_t r[4];
+    st = read_dev(c, s, {w.gidx + n, w.goff + n, w.err, w.err + 1}, r);
+    if (st == HF_OK) st = err_status(c, r[2], r[3], &pl);
     if (st != HF_OK) return st;
     const int64_t G = r[0], M = r[1];
     if (G != n_halos) return fail(c, HF_ERR_INVALID, "n_halos differs from the number of halo_id labels");
@@ -723,16 +931,16 @@ hf_status hf_halo_stats(hf_ctx *ctx, const float *pos, const float *density, con
     c->stats.n_members = M;
     hf::launch_segment_groups(n, G, w, s);
     HIP_OK(c, hipEventRecord(c->ev[4], s));
-    hf::launch_candidates(n, g2, w, s);
+    hf::launch_candidates(n, bx2, w, s);
     hf::scan_u32(w.gccnt, w.gcoff, G, w.scan_tmp, s);
     uint32_t NC32 = 0;
     st = read_dev(c, s, {w.gcoff + G}, &NC32);
     if (st != HF_OK) return st;
     hf::launch_candidates_sort(n, G, NC32, w, s);
     HIP_OK(c, hipEventRecord(c->ev[5], s));
-    hf::launch_accept(n, G, NC32, M, g2, w, s);
+    hf::launch_accept(n, G, NC32, M, bx2, w, s);
     HIP_OK(c, hipEventRecord(c->ev[6], s));
-    hf::launch_assign(n, g2, w, s);
+    hf::launch_assign(n, bx2, w, s);
     HIP_OK(c, hipEventRecord(c->ev[7], s));
     hf::launch_halo_stats(n, G, M, g2, p->particle_mass, pos, halo_id, w, stats, group_start, group_members, s);
     HIP_OK(c, hipEventRecord(c->ev[8], s));

@@ -12,8 +12,7 @@ namespace hf {
 constexpr int kBlock = 256;
 constexpr int kDenseMin = 8;   // a cell with at least this many particles is "dense"
 
-// Constants of one call, computed on the host (see hf_derived) and passed by
-// value to the kernels.
+// Constants of one periodic box, computed on the host (see hf_derived).
 struct Geo {
     double L, half;        // periodic side and L/2 (minimum-image test)
     double cell, inv_cell; // binning cell side (>= max(b, l)) and its inverse
@@ -22,6 +21,7 @@ struct Geo {
     float cellb;           // cell / b in FP32 (image offset of a neighbour cell)
     int nc;                // cells per side (>= 3)
     int ksub;              // sub-cells per cell side (sub-cell diagonal < l)
+    int nsub;              // ksub^3
     int rsub;              // FoF reach in sub-cells: ceil(l / sub-cell side)
     double inv_sub;        // ksub / cell
     double sub2;           // squared sub-cell side
@@ -35,7 +35,38 @@ struct Geo {
     double K, K2, A6, C3;  // R^3 = i/K; alpha^6; c_Roche^3
     int n_l1_min;
     float particle_mass;
+    // the box's place among the boxes of one call
+    uint32_t cell_base;    // its first cell in the call's cell numbering
+    uint32_t orig_base;    // its first particle (input and sorted order alike)
+    int64_t n;             // its particles
+    hf_halo *halos;        // its halo table (device), or null
+    int64_t halo_cap;      // rows of that table
 };
+
+// The boxes of one call.  Particles and cells of all boxes are numbered
+// together, box after box, so box b holds particles [base[b], base[b + 1])
+// both in input order and after the sort (the sort key leads with the cell,
+// and box b's cells follow box b - 1's), and cells
+// [geo[b].cell_base, geo[b + 1].cell_base).  Labels are 1 + an index inside
+// the box.
+struct Boxes {
+    const Geo *geo;        // device [nbox]
+    const uint32_t *base;  // device [nbox + 1]: first particle of each box, then the total
+    int nbox;
+    int nsub_max;          // largest ksub^3: the sort-key stride of a cell and the row
+                           // length - 1 of the dense-cell sub-tables
+};
+
+// Box of particle i (input or sorted order): binary search of base (no load
+// when there is one box).
+__device__ __forceinline__ int box_of(const Boxes &bx, uint32_t i) {
+    int lo = 0, hi = bx.nbox - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (bx.base[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
 
 // ---------------------------------------------------------------- predicates
 // Canonical minimum-image squared distance in FP64: the same sequence of IEEE
@@ -109,6 +140,29 @@ __device__ __forceinline__ int wrapc(int c, int nc) {
     return c < 0 ? c + nc : (c >= nc ? c - nc : c);
 }
 
+// Coordinates inside its box of cell c (the call's numbering) of box g.
+__device__ __forceinline__ void cell_xyz(const Geo &g, uint32_t c, int &cx, int &cy, int &cz) {
+    const uint32_t lc = c - g.cell_base, nc = (uint32_t)g.nc;
+    cx = (int)(lc % nc);
+    cy = (int)((lc / nc) % nc);
+    cz = (int)(lc / (nc * nc));
+}
+
+// The cell at coordinates (x, y, z) of box g, each wrapped once (one cell
+// beyond a face at most), in the call's numbering.
+__device__ __forceinline__ uint32_t cell_id(const Geo &g, int x, int y, int z) {
+    const int nc = g.nc;
+    return g.cell_base + ((uint32_t)wrapc(z, nc) * (uint32_t)nc + (uint32_t)wrapc(y, nc)) * (uint32_t)nc +
+           (uint32_t)wrapc(x, nc);
+}
+
+// Record error bit `bit` for box `box` (err[0] collects the bits, err[1] the
+// smallest box that raised one).
+__device__ __forceinline__ void flag_error(int32_t *err, int32_t bit, int box) {
+    atomicOr(err, bit);
+    atomicMin(err + 1, box);
+}
+
 __device__ __forceinline__ bool is_member(const float *dens_s, int64_t j, double dl0) {
     return (double)dens_s[j] > dl0;
 }
@@ -179,7 +233,10 @@ struct Work {
     double *gcom;                    // halo statistics only: centres per group (6 doubles)
     int32_t *ordk;                   // halo statistics only: group ordinal per key
     int32_t *counters;                                 // small device counters
-    int32_t *err;
+    int32_t *err;                    // [0] error bits, [1] smallest box with an error
+    Geo *geo, *geo2;                 // the boxes' constants (geo2: level 2, halo statistics only)
+    uint32_t *base;                  // first particle of every box, then the total
+    int64_t *box_rows;               // halo-table rows of every box
     uint32_t *host;                                    // the lane's pinned host words (read_words)
 };
 
@@ -206,37 +263,46 @@ void scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipSt
 void scan_nz_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipStream_t s);
 int64_t scan_tmp_words(int64_t n);
 
-void launch_bin(const float *pos, int64_t n, const Geo &g, Work &w, hipStream_t s);
-// Level 2 summaries and position statistics after an L2 pass (stats.hip).
+// Every launcher works on all boxes of the call at once: n is the particle
+// total, bx the boxes (device tables), ncell the cell total.
+void launch_bin(const float *pos, int64_t n, int64_t ncell, const Boxes &bx, Work &w, hipStream_t s);
+// Level 2 summaries and position statistics after an L2 pass (stats.hip; one
+// box, g its constants).
 void launch_halo_stats(int64_t n, int64_t G, int64_t M, const Geo &g, double particle_mass, const float *pos,
                        const int32_t *halo_id, Work &w, hf_halo_summary *out, int32_t *group_start,
                        int32_t *group_members, hipStream_t s);
-// Length of the radix count arrays for n particles on grid g.
-int64_t radix_hist_len(int64_t n, const Geo &g);
+// Length of the radix count arrays for n particles.
+int64_t radix_hist_len(int64_t n);
 // Stable LSD radix sort of n 64-bit keys a[] by their bits [lo, lo + bits),
 // using b[] as the second buffer and w's count arrays; returns the buffer
 // (a or b) that holds the result.
 uint64_t *radix_sort_keys(uint64_t *a, uint64_t *b, int64_t n, int lo, int bits, Work &w, hipStream_t s);
-void launch_subtab(int64_t n, const uint32_t *ndc_p, const Geo &g, Work &w, hipStream_t s);
-void launch_density(int64_t n, const Geo &g, Work &w, float *dens_out, hipStream_t s);
-void launch_count_pairs(int64_t n, const Geo &g, Work &w, unsigned long long *total, hipStream_t s);
+void launch_subtab(int64_t n, const uint32_t *ndc_p, const Boxes &bx, Work &w, hipStream_t s);
+void launch_density(int64_t n, const Boxes &bx, Work &w, float *dens_out, hipStream_t s);
+void launch_count_pairs(int64_t n, const Boxes &bx, Work &w, unsigned long long *total, hipStream_t s);
 void launch_gather_density(const float *dens_in, int64_t n, Work &w, hipStream_t s);
-void launch_fof(int64_t n, const Geo &g, Work &w, hipStream_t s);
-void launch_fof_labels(int64_t n, const Geo &g, Work &w, int32_t *l0_out, hipStream_t s);
-void launch_keys_from_labels(const int32_t *l0_in, const float *dens_in, int64_t n, Work &w, hipStream_t s);
+void launch_fof(int64_t n, const Boxes &bx, Work &w, hipStream_t s);
+void launch_fof_labels(int64_t n, const Boxes &bx, Work &w, int32_t *l0_out, hipStream_t s);
+void launch_keys_from_labels(const int32_t *l0_in, const float *dens_in, int64_t n, const Boxes &bx, Work &w,
+                             hipStream_t s);
 void launch_segment(int64_t n, Work &w, hipStream_t s);
 void launch_segment_groups(int64_t n, int64_t G, Work &w, hipStream_t s);
-// Extent check of the L0 groups (sets err bit 8 when a group spans half the
+// Extent check of the L0 groups (sets err bit 8 when a group spans half its
 // box or more along an axis); M members in G groups.
-void launch_extent(int64_t G, int64_t M, const Geo &g, Work &w, hipStream_t s);
-void launch_candidates(int64_t n, const Geo &g, Work &w, hipStream_t s);   // candidates.hip
+void launch_extent(int64_t G, int64_t M, const Boxes &bx, Work &w, hipStream_t s);
+void launch_candidates(int64_t n, const Boxes &bx, Work &w, hipStream_t s);   // candidates.hip
+// Candidates in descending density per group; the groups with candidates in
+// descending size (the largest first, over all boxes).
 void launch_candidates_sort(int64_t n, int64_t G, int64_t NC, Work &w, hipStream_t s);
 // Groups with candidates (their count is read on the device; grid bound
 // min(G, NC)); M = members of all groups, n = particles.
-void launch_accept(int64_t n, int64_t G, int64_t NC, int64_t M, const Geo &g, Work &w, hipStream_t s);
-void launch_assign(int64_t n, const Geo &g, Work &w, hipStream_t s);
-void launch_output_flags(int64_t n, int64_t NC, const Geo &g, Work &w, hipStream_t s);
-void launch_output(int64_t n, int64_t NC, const Geo &g, Work &w, int32_t *halo_id,
-                   int32_t *l0_out, hf_halo *halos, int64_t cap, hipStream_t s);
+void launch_accept(int64_t n, int64_t G, int64_t NC, int64_t M, const Boxes &bx, Work &w, hipStream_t s);
+void launch_assign(int64_t n, const Boxes &bx, Work &w, hipStream_t s);
+void launch_output_flags(int64_t n, int64_t NC, const Boxes &bx, Work &w, hipStream_t s);
+// halo_id / l0_out: device [n], box-local labels.  Each box's table goes to
+// its Geo::halos when its rows fit in Geo::halo_cap; box_rows (device [nbox])
+// receives every box's row count.
+void launch_output(int64_t n, int64_t NC, const Boxes &bx, Work &w, int32_t *halo_id, int32_t *l0_out,
+                   int64_t *box_rows, hipStream_t s);
 
 }  // namespace hf

@@ -41,6 +41,20 @@ struct Lane {
     hipStream_t stream = nullptr;  // owned; null for a context's main lane
     uint32_t *host = nullptr;      // pinned, coherent host words for count read-backs
     hipEvent_t pub = nullptr;      // marks a copy into host whose words are read while later work runs
+    void *stage = nullptr;         // pinned staging of the box tables sent to the device, and of
+    size_t stage_bytes = 0;        // the per-box results read back (grown for large calls)
+};
+
+// One call over several boxes: the boxes' particle ranges in the concatenated
+// arrays, their parameters and their halo tables.
+struct BoxSet {
+    int32_t nbox;
+    const int64_t *offsets;       // host [nbox + 1], offsets[0] = 0, non-decreasing
+    const hf_params *params;      // host [nbox]
+    hf_halo *halos;               // device, or null
+    const int64_t *halo_offsets;  // host [nbox + 1] (rows of each box's table), or null
+    int32_t first = 0;            // number of box 0 in the caller's numbering (error texts)
+    bool named = false;           // name the box in error texts even when there is one
 };
 
 // Size of the static scratch region of hf_find_noalloc (per device).
@@ -66,6 +80,16 @@ size_t lane_arena_bytes(const hf_params *p, int64_t n);
 hf_status lane_find(Lane *L, const float *pos, int64_t n, const hf_params *p, float *density,
                     int32_t *l0_id, int32_t *halo_id, hf_halo *halos, int64_t halos_cap,
                     int64_t *n_halos, hipStream_t s, const FixedArena *fx = nullptr);
+// The whole pass for all boxes of bs at once on stream s (every stage one
+// launch over all boxes): concatenated pos / density / l0_id / halo_id,
+// n_halos[nbox] (host) per box.  Returns the first error (text naming the
+// box), or HF_ERR_CAPACITY when only halo tables were too small (n_halos then
+// holds the needed rows; tables that fit are written).
+hf_status lane_find_boxes(Lane *L, const BoxSet &bs, const float *pos, float *density, int32_t *l0_id,
+                          int32_t *halo_id, int64_t *n_halos, hipStream_t s);
+// Particle and cell totals of a set of boxes and its arena size, or 0 when a
+// box's parameters are invalid (for the planning of batches).
+size_t boxes_arena_bytes(const BoxSet &bs, int64_t *n_total, int64_t *ncell_total);
 
 }  // namespace hf
 

@@ -1,11 +1,13 @@
 // Many boxes per call (hf_find_batch) and a request loop (hf_server).
 //
-// Both run the single-box pipeline on several lanes at once, each lane with its
-// own stream, arena and host thread.  The pipeline reads a few counts back to
-// the host between stages; while one lane waits for its counts the other lanes'
-// kernels keep the GPU busy, and small boxes that cannot fill 256 CUs on their
-// own share the device.  Results do not depend on which lane runs a box or on
-// what runs beside it: every lane computes the same deterministic pass.
+// hf_find_batch finds its boxes in fused passes: every stage is one launch over
+// all boxes of a group, whose particles and cells are numbered together, so
+// that small boxes that could not fill 256 CUs on their own run as one large
+// problem.  A batch may be cut into a few groups that run at once on lanes
+// (stream, arena and host thread each), so that one group's waits for its
+// counts overlap with another's kernels.  The request loop runs one request
+// per lane.  Results do not depend on the grouping or on what runs beside a
+// box: the pass is deterministic and no box reads another box's data.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -19,7 +21,7 @@
 
 namespace {
 
-constexpr int kDefaultLanes = 8;
+constexpr int kDefaultBatchGroups = 1;  // fused groups of hf_find_batch when none is asked for
 constexpr int kMaxLanes = 16;
 
 void add_stats(hf_stats &a, const hf_stats &b) {
@@ -73,8 +75,39 @@ hf_status hf_find_batch(hf_ctx *ctx, int32_t n_boxes, const int64_t *box_offsets
     if (total > 0 && (!pos || !halo_id)) return batch_fail(ctx, HF_ERR_INVALID, "pos / halo_id is NULL");
     if (halo_offsets[n_boxes] > 0 && !halos) return batch_fail(ctx, HF_ERR_INVALID, "halos is NULL");
 
-    const int k = std::min(std::min(n_lanes > 0 ? n_lanes : kDefaultLanes, kMaxLanes), (int)n_boxes);
-    while ((int)ctx->pool.size() < k) {
+    // Groups of consecutive boxes, each found in one fused pass (every stage
+    // one launch over all its boxes): k groups of about equal particle counts,
+    // which run at once on k lanes so that one group's waits for its counts
+    // overlap with another's kernels.  A group is also closed before its cell
+    // count would pass 2^31 (cell numbers of a pass stay 32-bit).
+    const int k = std::max(1, std::min(std::min(n_lanes > 0 ? n_lanes : kDefaultBatchGroups, kMaxLanes),
+                                       (int)n_boxes));
+    std::vector<int32_t> cut{0};
+    {
+        int64_t cells = 0;
+        const double target = (double)total / k;
+        for (int32_t b = 0; b < n_boxes; b++) {
+            const int64_t nb = box_offsets[b + 1] - box_offsets[b];
+            int64_t cb = 0;  // the box's cells (0 if its parameters are invalid: its pass reports it)
+            if (nb > 0) {
+                const int64_t o2[2] = {0, nb};
+                int64_t nt = 0;
+                hf::boxes_arena_bytes(hf::BoxSet{1, o2, params + b, nullptr, nullptr}, &nt, &cb);
+            }
+            const bool full_cells = b > cut.back() && cells + cb >= ((int64_t)1 << 31);
+            const bool full_share = (int)cut.size() < k && b > cut.back() &&
+                                    (double)box_offsets[b] >= target * (double)cut.size();
+            if (full_cells || full_share) {
+                cut.push_back(b);
+                cells = 0;
+            }
+            cells += cb;
+        }
+        cut.push_back(n_boxes);
+    }
+    const int ngroups = (int)cut.size() - 1;
+    const int lanes = std::min(k, ngroups);
+    while ((int)ctx->pool.size() < lanes) {
         auto L = std::make_unique<hf::Lane>();
         L->budget = &ctx->budget;
         if (hf::lane_init(L.get(), ctx->main.device, true) != HF_OK) {
@@ -87,50 +120,48 @@ hf_status hf_find_batch(hf_ctx *ctx, int32_t n_boxes, const int64_t *box_offsets
     if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
         return batch_fail(ctx, HF_ERR_DEVICE, "hipStreamSynchronize of the caller's stream failed");
 
-    // largest boxes first, so that the tail of the batch is made of small ones
-    std::vector<int32_t> order(n_boxes);
-    for (int32_t b = 0; b < n_boxes; b++) order[b] = b;
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-        return box_offsets[a + 1] - box_offsets[a] > box_offsets[b + 1] - box_offsets[b];
-    });
-    std::vector<hf_status> st(n_boxes, HF_OK);
-    std::vector<std::string> msg(n_boxes);
-    std::vector<hf_stats> lane_stats(k, hf_stats{});
+    std::vector<hf_status> st(ngroups, HF_OK);
+    std::vector<std::string> msg(ngroups);
+    std::vector<hf_stats> lane_stats(lanes, hf_stats{});
     std::atomic<int32_t> next{0};
     const auto t0 = std::chrono::steady_clock::now();
     auto work = [&](int t) {
         hf::Lane *L = ctx->pool[t].get();
         (void)hipSetDevice(L->device);
+        std::vector<int64_t> offs, hoffs;
         for (;;) {
             const int32_t q = next.fetch_add(1);
-            if (q >= n_boxes) break;
-            const int32_t b = order[q];
-            const int64_t o = box_offsets[b], nb = box_offsets[b + 1] - o;
-            const int64_t ho = halo_offsets[b], cap = halo_offsets[b + 1] - ho;
-            n_halos[b] = 0;
-            st[b] = hf::lane_find(L, nb ? pos + 3 * o : nullptr, nb, &params[b], density ? density + o : nullptr,
-                                  l0_id ? l0_id + o : nullptr, halo_id + o, cap ? halos + ho : nullptr, cap,
-                                  &n_halos[b], L->stream);
-            if (st[b] != HF_OK) msg[b] = L->err;
+            if (q >= ngroups) break;
+            const int32_t b0 = cut[q], b1 = cut[q + 1], nb = b1 - b0;
+            offs.resize(nb + 1);
+            hoffs.resize(nb + 1);
+            for (int32_t j = 0; j <= nb; j++) {
+                offs[j] = box_offsets[b0 + j] - box_offsets[b0];
+                hoffs[j] = halo_offsets[b0 + j] - halo_offsets[b0];
+            }
+            const int64_t o = box_offsets[b0];
+            hf::BoxSet bs{nb, offs.data(), params + b0, halos ? halos + halo_offsets[b0] : nullptr, hoffs.data()};
+            bs.first = b0;
+            bs.named = true;
+            st[q] = hf::lane_find_boxes(L, bs, offs[nb] ? pos + 3 * o : nullptr, density ? density + o : nullptr,
+                                        l0_id ? l0_id + o : nullptr, halo_id + o, n_halos + b0, L->stream);
+            if (st[q] != HF_OK) msg[q] = L->err;
             add_stats(lane_stats[t], L->stats);
         }
     };
     std::vector<std::thread> threads;
-    for (int t = 1; t < k; t++) threads.emplace_back(work, t);
+    for (int t = 1; t < lanes; t++) threads.emplace_back(work, t);
     work(0);
     for (auto &th : threads) th.join();
     const auto t1 = std::chrono::steady_clock::now();
 
-    for (int t = 0; t < k; t++) add_stats(ctx->main.stats, lane_stats[t]);
+    for (int t = 0; t < lanes; t++) add_stats(ctx->main.stats, lane_stats[t]);
     ctx->main.stats.ms_total = (float)std::chrono::duration<double, std::milli>(t1 - t0).count();
-    for (int32_t b = 0; b < n_boxes; b++)
-        if (st[b] != HF_OK && st[b] != HF_ERR_CAPACITY)
-            return batch_fail(ctx, st[b], "box " + std::to_string(b) + ": " + msg[b]);
-    for (int32_t b = 0; b < n_boxes; b++)
-        if (st[b] == HF_ERR_CAPACITY)
-            return batch_fail(ctx, HF_ERR_CAPACITY,
-                              "box " + std::to_string(b) + ": halo capacity too small (n_halos holds the "
-                              "required counts)");
+    for (int q = 0; q < ngroups; q++)
+        if (st[q] != HF_OK && st[q] != HF_ERR_CAPACITY) return batch_fail(ctx, st[q], msg[q]);
+    for (int q = 0; q < ngroups; q++)
+        if (st[q] == HF_ERR_CAPACITY)
+            return batch_fail(ctx, HF_ERR_CAPACITY, msg[q] + " (n_halos holds the required counts)");
     return HF_OK;
 }
 
