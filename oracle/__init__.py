@@ -72,6 +72,9 @@ def _load():
         lib.orc_params_at_redshift.argtypes = [P, ctypes.c_double, ctypes.c_double, P]
         lib.orc_l2_stats.argtypes = [I64, P, P, P, P, ctypes.c_int, I64, P, P, P, I64, P, P, P, P, P]
         lib.orc_events.argtypes = [I64, P, P, P, P, ctypes.c_int, ctypes.c_double, P]
+        lib.orc_radius_search.argtypes = [P, I64, ctypes.c_double, ctypes.c_int, ctypes.c_double, P]
+        lib.orc_radius_search.restype = I64
+        lib.orc_group_sweep.argtypes = [I64, P, I64, P, P, P, P]
         lib.orc_num_threads.restype = ctypes.c_int
         lib.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -151,8 +154,13 @@ def fof(pos, dens, mode: str = "cells", **kw):
     return l0, int(ng[0])
 
 
-def compaso(pos, dens, l0, mode: str = "cells", cap: int | None = None, **kw) -> dict:
-    """CompaSO L1 (literal sequential loop of Sec. 2.2.2) plus the output cut."""
+def compaso(pos, dens, l0, mode: str = "cells", cap: int | None = None, radius: str = "sort",
+            **kw) -> dict:
+    """CompaSO L1 (literal sequential loop of Sec. 2.2.2) plus the output cut.
+    radius: "sort" takes R_L1 from the sorted distances, "bins" by the radial
+    bins of Sec. 2.3.4 (width max(b, l)/sqrt(3)); both give the same count."""
+    if radius not in ("sort", "bins"):
+        raise ValueError(radius)
     pos = _pos(pos)
     n = len(pos)
     dens = np.ascontiguousarray(dens, dtype=np.float64)
@@ -166,7 +174,8 @@ def compaso(pos, dens, l0, mode: str = "cells", cap: int | None = None, **kw) ->
     nh = np.zeros(1, np.int64)
     nf = np.zeros(1, np.int64)
     rc = _load().orc_compaso(n, _ptr(pos), _ptr(p), _ptr(dens), _ptr(l0),
-                             0 if mode == "brute" else 1, _ptr(halo_id), _ptr(owner_all), cap,
+                             (0 if mode == "brute" else 1) | (2 if radius == "bins" else 0),
+                             _ptr(halo_id), _ptr(owner_all), cap,
                              _ptr(t["id"]), _ptr(t["nucleus"]), _ptr(t["l0"]), _ptr(t["n"]),
                              _ptr(t["ienc"]), _ptr(nh), _ptr(nf), n, _ptr(f["nucleus"]),
                              _ptr(f["ienc"]), _ptr(f["count"]), _ptr(f["l0"]))
@@ -179,14 +188,76 @@ def compaso(pos, dens, l0, mode: str = "cells", cap: int | None = None, **kw) ->
             "n_halos": int(nh[0]), "n_found": int(nf[0])}
 
 
-def find(pos, mode: str = "cells", density_override=None, **kw) -> dict:
+def find(pos, mode: str = "cells", density_override=None, radius: str = "sort", **kw) -> dict:
     """The whole pass: density (or the given field), L0 FoF, CompaSO L1, cut."""
     dens = density(pos, mode=mode, **kw) if density_override is None \
         else np.asarray(density_override, dtype=np.float64)
     l0, ng = fof(pos, dens, mode=mode, **kw)
-    res = compaso(pos, dens, l0, mode=mode, **kw)
+    res = compaso(pos, dens, l0, mode=mode, radius=radius, **kw)
     res.update({"density": dens, "l0": l0, "n_groups": ng})
     return res
+
+
+def radius_search(e, K2: float, mode: str = "sort", w: float = 0.0):
+    """Enclosed count i of the threshold radius from the squared distances e
+    of a group's members to a nucleus (the nucleus included, at 0): "sort" is
+    the definition (sorted distances, first k >= 1 with K^2 d_k^6 > k^2, else
+    len(e)); "bins" the radial-bin search of Sec. 2.3.4 with bin width w.
+    Returns (i, number of bins searched)."""
+    e = np.ascontiguousarray(e, dtype=np.float64)
+    searched = np.zeros(1, np.int64)
+    k = _load().orc_radius_search(_ptr(e), len(e), float(K2), 1 if mode == "bins" else 0, float(w),
+                                  _ptr(searched))
+    return int(k), int(searched[0])
+
+
+def group_order(halo_id, table_id):
+    """Members in group order, as defined: the particles of each halo of the
+    table (rows in table order) in ascending original index, then the
+    particles of no halo (halo_id 0) in ascending index.  Returns (members,
+    start) with row r's members in members[start[r]:start[r+1]] and the
+    unassigned ones from start[len(table_id)]."""
+    halo_id = np.asarray(halo_id, dtype=np.int64)
+    table_id = np.asarray(table_id, dtype=np.int64)
+    nrows = len(table_id)
+    key = _row_keys(halo_id, table_id)
+    members = np.argsort(key, kind="stable").astype(np.int64)
+    start = np.searchsorted(key[members], np.arange(nrows + 1), side="left").astype(np.int64)
+    return members, start
+
+
+def _row_keys(halo_id, table_id):
+    # table row of every particle's halo, len(table_id) for halo_id 0
+    nrows = len(table_id)
+    if nrows == 0:
+        if np.any(halo_id != 0):
+            raise ValueError("a halo_id label is not in the table")
+        return np.zeros(len(halo_id), np.int64)
+    order = np.argsort(table_id)
+    pos = np.minimum(np.searchsorted(table_id[order], halo_id), nrows - 1)
+    key = np.where(halo_id == 0, nrows, order[pos]).astype(np.int64)
+    bad = (halo_id != 0) & (table_id[order][pos] != halo_id)
+    if bad.any():
+        raise ValueError("a halo_id label is not in the table")
+    return key
+
+
+def group_sweep(halo_id, table_id, table_n):
+    """The partition sweep of Sec. 2.3.5 (largest halo first, then the
+    unassigned particles, then the other halos): (members, start) in the
+    layout of group_order, with the order inside a run left by the in-place
+    partitions."""
+    halo_id = np.ascontiguousarray(halo_id, dtype=np.int32)
+    table_id = np.ascontiguousarray(table_id, dtype=np.int32)
+    table_n = np.ascontiguousarray(table_n, dtype=np.int32)
+    n, nrows = len(halo_id), len(table_id)
+    members = np.zeros(max(n, 1), np.int64)
+    start = np.zeros(nrows + 1, np.int64)
+    rc = _load().orc_group_sweep(n, _ptr(halo_id), nrows, _ptr(table_id), _ptr(table_n), _ptr(members),
+                                 _ptr(start))
+    if rc:
+        raise ValueError("a halo_id label is not in the table")
+    return members[:n], start
 
 
 # bits of events(): see orc_events

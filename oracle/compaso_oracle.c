@@ -15,6 +15,10 @@
  *     competitive reassignment, density floor), with the flat-rotation-curve
  *     enclosed density of Sec. 2.3.2 and squared distances as in Sec. 2.3.3.
  *   - output cut at the minimum L1 halo size (end of Sec. 2.2.2, Table 1).
+ *   - the threshold radius either from the sorted distances or by the radial
+ *     bins of Sec. 2.3.4 (orc_radius_search; both give the same count), and
+ *     the members collected into group order by the partition sweep of
+ *     Sec. 2.3.5 (orc_group_sweep).
  *   - the near-threshold events through which a slightly different density
  *     field can change the labels (orc_events; used to attribute label
  *     differences against a float32 field to the density comparisons of
@@ -397,6 +401,7 @@ typedef struct {
     const double *d;
     const grid_t *g;       /* cell list with cells >= b, or NULL (brute force) */
     int64_t n;
+    double rbin;           /* > 0: threshold radius by radial bins of this width (Sec. 2.3.4) */
 } ctx_t;
 
 /* "Denser" in the total order used for nuclei: higher density first, ties
@@ -435,6 +440,93 @@ static int cmp_double(const void *a, const void *b)
 {
     double x = *(const double *)a, y = *(const double *)b;
     return (x > y) - (x < y);
+}
+
+/* ------------------------------------------------- threshold radius (R_L1) */
+
+/* Enclosed count of the threshold radius from the squared distances e[0..m)
+ * of the m members of a group to a nucleus (the nucleus itself included, at
+ * e = 0), as defined by sorting (Sec. 2.2.2 step 1 and Sec. 2.3.3): with the
+ * distances in ascending order d_0 <= d_1 <= ..., the enclosed count at sorted
+ * position k is k, and the radius is the innermost d_k (k >= 1) at which the
+ * enclosed density k / (K d_k^3) drops below 1 (in units of Delta_L1), i.e.
+ * K^2 d_k^6 > k^2.  No such position: m (the radius is bounded by the L0
+ * group).  es receives the sorted copy (scratch of m doubles). */
+static int64_t radius_sorted(const double *e, int64_t m, double K2, double *es)
+{
+    memcpy(es, e, (size_t)m * sizeof(double));
+    qsort(es, (size_t)m, sizeof(double), cmp_double);
+    for (int64_t k = 1; k < m; k++)
+        if (K2 * e3(es[k]) > ii(k)) return k;
+    return m;
+}
+
+/* Squared outer edge of radial bin j of width w: ((j + 1) w)^2. */
+static double bin_edge2(int64_t j, double w)
+{
+    double r = (double)(j + 1) * w;
+    return r * r;
+}
+
+/* The same count by the search of Sec. 2.3.4: the members are partitioned
+ * into radial bins of width w (bin j holds edge2(j-1) <= e < edge2(j)).  Let
+ * C_j be the number of members inside bin j's inner edge.  If those C_j
+ * members placed at the bin's outer edge still reach the density threshold
+ * (K^2 edge2(j)^3 <= C_j^2), every member of the bin, being inside that edge
+ * and at a sorted position >= C_j, has enclosed density above the threshold:
+ * the bin is passed over.  Otherwise its members are sorted and searched in
+ * order; a bin without the crossing sends the search on outwards.  The
+ * innermost bin is always searched (C_0 = 0).  *searched (may be NULL)
+ * receives the number of bins searched. */
+static int64_t radius_bins(const double *e, int64_t m, double K2, double w, int64_t *searched)
+{
+    double emax = 0.0;
+    for (int64_t t = 0; t < m; t++) if (e[t] > emax) emax = e[t];
+    int64_t nb = (int64_t)(sqrt(emax) / w) + 1;
+    while (!(emax < bin_edge2(nb - 1, w))) nb++;
+    int64_t *cnt = (int64_t *)calloc((size_t)nb, sizeof(int64_t));
+    double *v = (double *)malloc((size_t)(m > 0 ? m : 1) * sizeof(double));
+    int64_t found = m, nsearch = 0;
+    /* bin of each member: the first j with e < edge2(j) */
+    for (int64_t t = 0; t < m; t++) {
+        int64_t j = (int64_t)(sqrt(e[t]) / w);
+        if (j >= nb) j = nb - 1;
+        while (j > 0 && e[t] < bin_edge2(j - 1, w)) j--;
+        while (!(e[t] < bin_edge2(j, w))) j++;
+        cnt[j]++;
+    }
+    int64_t C = 0;   /* members inside the current bin's inner edge */
+    for (int64_t j = 0; j < nb && found == m; C += cnt[j], j++) {
+        if (cnt[j] == 0) continue;
+        if (K2 * e3(bin_edge2(j, w)) <= ii(C)) continue;   /* threshold not crossed in this bin */
+        nsearch++;
+        double lo = j > 0 ? bin_edge2(j - 1, w) : -1.0, hi = bin_edge2(j, w);
+        int64_t c = 0;
+        for (int64_t t = 0; t < m; t++)
+            if (e[t] >= lo && e[t] < hi) v[c++] = e[t];
+        qsort(v, (size_t)c, sizeof(double), cmp_double);
+        for (int64_t u = 0; u < c; u++) {
+            int64_t k = C + u;
+            if (k >= 1 && k < m && K2 * e3(v[u]) > ii(k)) { found = k; break; }
+        }
+    }
+    free(cnt);
+    free(v);
+    if (searched) *searched = nsearch;
+    return found;
+}
+
+/* Exported for the tests: mode 0 the sorted definition, mode 1 the radial-bin
+ * search with bin width w (searched: bins searched). */
+int64_t orc_radius_search(const double *e, int64_t m, double K2, int mode, double w, int64_t *searched)
+{
+    if (m <= 0) return 0;
+    if (mode == 1) return radius_bins(e, m, K2, w, searched);
+    double *es = (double *)malloc((size_t)m * sizeof(double));
+    int64_t k = radius_sorted(e, m, K2, es);
+    free(es);
+    if (searched) *searched = 0;
+    return k;
 }
 
 typedef struct { double dens; int64_t idx; int64_t t; } rank_t;
@@ -494,15 +586,10 @@ static int64_t compaso_group(const ctx_t *c, const int64_t *mem, int64_t m,
             if (peak[t]) { cand = q; break; }
         }
         if (cand < 0) break;
-        /* R from all particles of the group, by sorting squared distances. */
-        for (int64_t t = 0; t < m; t++) {
-            e[t] = d2_periodic(c->pos, cand, mem[t], c->L);
-            es[t] = e[t];
-        }
-        qsort(es, (size_t)m, sizeof(double), cmp_double);
-        int64_t ienc = m;   /* no crossing inside the group: R bounded by the L0 edge */
-        for (int64_t k = 1; k < m; k++)
-            if (K2 * e3(es[k]) > ii(k)) { ienc = k; break; }
+        /* R from all particles of the group: sorted squared distances, or
+         * the radial-bin search of Sec. 2.3.4 (the same count) */
+        for (int64_t t = 0; t < m; t++) e[t] = d2_periodic(c->pos, cand, mem[t], c->L);
+        int64_t ienc = c->rbin > 0.0 ? radius_bins(e, m, K2, c->rbin, NULL) : radius_sorted(e, m, K2, es);
         if (nh == cap) { cap *= 2; halos = (halo_t *)realloc(halos, (size_t)cap * sizeof(halo_t)); }
         int64_t h = nh++;
         halos[h].nucleus = cand;
@@ -574,12 +661,14 @@ int orc_compaso(int64_t n, const float *pos, const double *p, const double *dens
 
     grid_t g;
     int use_grid = 0;
-    if (mode == 1) {
+    if (mode & 1) {
         int rc = grid_build(&g, n, pos, p[P_BOX], d[D_B]);
         if (rc == 2) { free(mem); free(gstart); free(glab); return 2; }
         use_grid = rc == 0;
     }
-    ctx_t c = { pos, dens, l0, p[P_BOX], d, use_grid ? &g : NULL, n };
+    /* mode bit 2: R_L1 by radial bins of width max(b, l)/sqrt(3) (Sec. 2.3.4) */
+    double rbin = (mode & 2) ? fmax(d[D_B], d[D_L]) / sqrt(3.0) : 0.0;
+    ctx_t c = { pos, dens, l0, p[P_BOX], d, use_grid ? &g : NULL, n, rbin };
 
     halo_t **gh = (halo_t **)calloc((size_t)(ngroups > 0 ? ngroups : 1), sizeof(halo_t *));
     int64_t *gnh = (int64_t *)calloc((size_t)(ngroups > 0 ? ngroups : 1), sizeof(int64_t));
@@ -771,6 +860,61 @@ int orc_events(int64_t n, const float *pos, const double *p, const double *dens,
     return 0;
 }
 
+/* ------------------------------------------------------- group order */
+
+/* Members collected into group order by the sweep of Sec. 2.3.5: the index
+ * array is partitioned in place, first for the largest halo (the most likely
+ * to be the biggest set), then for the unassigned particles (halo_id 0, the
+ * other big set, so that later passes do not go through them again), then for
+ * each remaining halo in table order.  row_id / row_n: the halo table's ids
+ * and sizes (nrows rows).  Output in table layout: row r's members in
+ * members[start[r] .. start[r+1]), the unassigned ones from start[nrows] to n;
+ * the order inside a run is whatever the in-place partitions leave.  Returns
+ * 1 when a particle's label is neither 0 nor a table id. */
+static int64_t partition_by(int64_t *idx, int64_t lo, int64_t hi, const int32_t *halo_id, int32_t id)
+{
+    /* in-place two-pointer partition of idx[lo, hi): label == id first */
+    int64_t a = lo, b = hi - 1;
+    for (;;) {
+        while (a <= b && halo_id[idx[a]] == id) a++;
+        while (a <= b && halo_id[idx[b]] != id) b--;
+        if (a >= b) break;
+        int64_t t = idx[a]; idx[a] = idx[b]; idx[b] = t;
+        a++; b--;
+    }
+    return a;
+}
+
+int orc_group_sweep(int64_t n, const int32_t *halo_id, int64_t nrows, const int32_t *row_id,
+                    const int32_t *row_n, int64_t *members, int64_t *start)
+{
+    int64_t *idx = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    int64_t *seg = (int64_t *)malloc((size_t)(nrows + 1) * 2 * sizeof(int64_t));
+    if (!idx || !seg) { free(idx); free(seg); return 2; }
+    for (int64_t i = 0; i < n; i++) idx[i] = i;
+    int64_t big = -1;
+    for (int64_t r = 0; r < nrows; r++)
+        if (big < 0 || row_n[r] > row_n[big]) big = r;
+    int64_t lo = 0;
+    /* seg[2r], seg[2r+1]: row r's range in idx; row nrows: the unassigned */
+    if (big >= 0) { int64_t e = partition_by(idx, lo, n, halo_id, row_id[big]); seg[2 * big] = lo; seg[2 * big + 1] = e; lo = e; }
+    { int64_t e = partition_by(idx, lo, n, halo_id, 0); seg[2 * nrows] = lo; seg[2 * nrows + 1] = e; lo = e; }
+    for (int64_t r = 0; r < nrows; r++) {
+        if (r == big) continue;
+        int64_t e = partition_by(idx, lo, n, halo_id, row_id[r]);
+        seg[2 * r] = lo; seg[2 * r + 1] = e; lo = e;
+    }
+    int rc = lo == n ? 0 : 1;   /* every particle went to some run */
+    int64_t w = 0;
+    for (int64_t r = 0; r <= nrows; r++) {
+        start[r] = w;
+        for (int64_t t = seg[2 * r]; t < seg[2 * r + 1]; t++) members[w++] = idx[t];
+    }
+    free(idx);
+    free(seg);
+    return rc;
+}
+
 /* ------------------------------------------------------ redshift scaling */
 
 /* Thresholds at redshift z (Sec. 2.3.1) for a flat universe of matter and a
@@ -903,7 +1047,7 @@ int orc_l2_stats(int64_t n, const float *pos, const double *p, const double *den
         if (rc == 2) { free(mem); free(gstart); free(glab); return 2; }
         use_grid = rc == 0;
     }
-    ctx_t c = { pos, dens, halo_id, L, d, use_grid ? &g : NULL, n };
+    ctx_t c = { pos, dens, halo_id, L, d, use_grid ? &g : NULL, n, 0.0 };
     halo_t **gh = (halo_t **)calloc((size_t)(ng > 0 ? ng : 1), sizeof(halo_t *));
     int64_t *gnh = (int64_t *)calloc((size_t)(ng > 0 ? ng : 1), sizeof(int64_t));
     int64_t *own = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
