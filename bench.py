@@ -2,13 +2,15 @@
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batched96]
                 [--no-cpu-baseline] [--cpu-seconds S] [--no-plain256] [--no-serving]
-                [--large] [--only-steps] [--lanes L]
+                [--large] [--only-steps] [--lanes L] [--tune-groups G] [--tune-table F]
 
 Headline workload (``batched96``): 96 independent periodic sub-boxes of side
 log-uniform in 24..160 (about 60M particles), found in one ``hf_find_batch``
-call per step, positions already resident in HBM.  Whole-job particles/s over
-the K timed steps is ``value``; ``plain_value`` is the same boxes found one
-``hf_find`` call at a time.  The line also carries:
+call per step, positions already resident in HBM.  Before the warmup (untimed),
+``hf_tune_batch`` picks the fused group count for the batch, which the timed
+calls take.  Whole-job particles/s over the K timed steps is ``value``;
+``plain_value`` is the same boxes found one ``hf_find`` call at a time.  The
+line also carries:
   roofline      the dominant stage over the batch's boxes, timed with HIP events
                 on the stream each box runs on (boxes one at a time, so that no
                 other box shares the device during a stage);
@@ -228,6 +230,13 @@ def batched(ctx, boxes, args, np, torch, _lib):
     params = [_lib.default_params(box=b[1]) for b in boxes]
     caps = np.maximum(sizes // 64, 64)
     lanes = args.lanes
+    tuned = None
+    if lanes <= 0 and args.tune_groups > 0:
+        # untimed: hf_tune_batch picks the fused group count for this batch shape,
+        # which the timed calls (n_lanes = 0) then take from the context
+        g, ms, _ = ctx.tune_batch(pos, offs, params, max_groups=args.tune_groups, reps=1,
+                                  table_path=args.tune_table or None)
+        tuned = {"groups": g, "ms": ms, "max_groups": args.tune_groups}
     for _ in range(args.warmup):
         ctx.find_batch(pos, offs, params, halos_caps=caps, n_lanes=lanes, want_l0=False)
     torch.cuda.synchronize()
@@ -238,7 +247,8 @@ def batched(ctx, boxes, args, np, torch, _lib):
     wall = time.perf_counter() - t0
     total = int(offs[-1])
     res = {"value": total * args.steps / wall, "ms_per_step": wall * 1e3 / args.steps,
-           "n_halos": int(np.sum(out["n_halos"]))}
+           "n_halos": int(np.sum(out["n_halos"])),
+           "groups": ctx.batch_groups(len(boxes), total, n_lanes=lanes), "tuning": tuned}
     if args.only_steps:
         return res
     # one hf_find per box, in the same order, as the plain comparison
@@ -314,9 +324,38 @@ def single_box(ctx, name, steps, warmup, np, torch, _lib, synth, halo_stats=Fals
         ms = float(np.median(t)) * 1e3
         res["halo_stats"] = {"ms": ms, "value": n / (ms / 1e3), "unit": "particles/s", "n_halos": nh,
                              "n_l2": int(np.sum(r["n_l2"]))}
+        res["variants"] = variants(ctx, pos_d, p, cap, out, np, torch)
     del pos_d
     torch.cuda.empty_cache()
     return res
+
+
+def variants(ctx, pos_d, p, cap, ref, np, torch):
+    """The same box with the threshold radius searched by radial bins
+    (Sec. 2.3.4) and with the members collected into group order (Sec. 2.3.5,
+    hf_find_grouped): per-call ms (median of 3) and the acceptance stage ms,
+    with a check that the labels equal the reference call's."""
+    def timed(call):
+        call()
+        torch.cuda.synchronize()
+        t, acc = [], []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            o = call()
+            torch.cuda.synchronize()
+            t.append(time.perf_counter() - t0)
+            acc.append(ctx.stats()["ms_accept"])
+        return o, float(np.median(t)) * 1e3, float(np.median(acc))
+    base, ms0, acc0 = timed(lambda: ctx.find(pos_d, p, halos_cap=cap))
+    ctx.set_radius_search("bins")
+    try:
+        rb, ms1, acc1 = timed(lambda: ctx.find(pos_d, p, halos_cap=cap))
+    finally:
+        ctx.set_radius_search("histogram")
+    gr, ms2, _ = timed(lambda: ctx.find_grouped(pos_d, p, halos_cap=cap))
+    same = bool(torch.equal(rb["halo_id"], ref["halo_id"]) and torch.equal(gr["halo_id"], ref["halo_id"]))
+    return {"find_ms": ms0, "accept_ms": acc0, "radius_bins_ms": ms1, "radius_bins_accept_ms": acc1,
+            "grouped_ms": ms2, "grouped_extra_ms": ms2 - ms0, "labels_identical": same}
 
 
 def _pct(x, q):
@@ -423,6 +462,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="batched96", choices=sorted(WORKLOADS))
     ap.add_argument("--lanes", type=int, default=0, help="pipelines of hf_find_batch (0: the library's)")
+    ap.add_argument("--tune-groups", type=int, default=4,
+                    help="hf_tune_batch over 1..G fused groups before timing (0: no tuning)")
+    ap.add_argument("--tune-table", default="", help="tuning table file hf_tune_batch rewrites")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-plain256", action="store_true")

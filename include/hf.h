@@ -153,6 +153,26 @@ void hf_destroy(hf_ctx *ctx);
 const char *hf_last_error(const hf_ctx *ctx);
 hf_status hf_get_stats(const hf_ctx *ctx, hf_stats *out);
 
+/* Options of a context (hf_set_option / hf_get_option; they apply to the
+ * calls made after the change, batches included). */
+enum {
+    HF_OPT_RADIUS_SEARCH = 1  /* how the enclosed count i of a nucleus (R_L1) is searched */
+};
+/* Values of HF_OPT_RADIUS_SEARCH.  Both give the count of the sorted
+ * definition (Sec. 2.2.2 step 1, Sec. 2.3.3), so every output is the same. */
+enum {
+    HF_RADIUS_HISTOGRAM = 0,  /* default: one pass over the group into a histogram
+                                 of the integer crossing buckets, then a prefix scan */
+    HF_RADIUS_BINS = 1        /* the radial bins of Sec. 2.3.4 (width: cell side /
+                                 sqrt(3)): a pass counts the members per bin, bins
+                                 whose inner count placed at their outer edge still
+                                 meets the threshold are passed over, and the others
+                                 are searched outwards, each by one more pass */
+};
+/* HF_ERR_INVALID for an unknown option or value. */
+hf_status hf_set_option(hf_ctx *ctx, int32_t option, int64_t value);
+hf_status hf_get_option(const hf_ctx *ctx, int32_t option, int64_t *value);
+
 /* Step 1 (Sec. 2.2.1): density[i] = norm * sum_{j != i, r_ij < b} (1 - r_ij^2/b^2)
  * over periodic minimum images; norm makes a uniform field average 1 (App. B.2).
  * density: float32 [n], original particle order. */
@@ -223,6 +243,18 @@ hf_status hf_find_noalloc(hf_ctx *ctx, const float *pos, int64_t n, const hf_par
                           float *density, int32_t *l0_id, int32_t *halo_id, hf_halo *halos,
                           int64_t halos_cap, int64_t *n_halos, void *stream);
 
+/* hf_find plus its members collected into group order (Sec. 2.3.5): members
+ * (device int32 [n]) holds the particles of each halo of the table, rows in
+ * table order and ascending original index inside a row, then the particles
+ * of no halo (halo_id 0) in ascending index; halo_start (device int64
+ * [halos_cap + 1]) receives in entries 0..*n_halos the first position of each
+ * row's run and, last, of the rest.  On HF_ERR_CAPACITY members and
+ * halo_start are not written.  The call ends synchronized with its stream. */
+hf_status hf_find_grouped(hf_ctx *ctx, const float *pos, int64_t n, const hf_params *p,
+                          float *density, int32_t *l0_id, int32_t *halo_id, hf_halo *halos,
+                          int64_t halos_cap, int64_t *n_halos, int32_t *members,
+                          int64_t *halo_start, void *stream);
+
 /* ---- Many boxes per call ------------------------------------------------
  * hf_find on n_boxes independent periodic boxes (Sec. 2.2 applied to each box
  * on its own).  Box b holds particles [box_offsets[b], box_offsets[b+1]) of the
@@ -235,8 +267,14 @@ hf_status hf_find_noalloc(hf_ctx *ctx, const float *pos, int64_t n, const hf_par
  * receives its count.  box_offsets and halo_offsets are host arrays of
  * n_boxes + 1 non-decreasing values starting at 0.
  *
- * The boxes run on n_lanes pipelines at once (<= 0: 8; at most 16), each with
- * its own stream and scratch arena held by the context, largest boxes first.
+ * The boxes are found in fused passes: every stage is one launch over all
+ * boxes of a group of consecutive boxes, whose particles and cells are numbered
+ * together (the L0 groups of all its boxes form one work list for the
+ * acceptance step, largest first).  The batch is cut into n_lanes groups of
+ * about equal particle counts (at most 16 and n_boxes; a group also closes
+ * before its cells reach 2^31), which run at once, each on its own stream and
+ * scratch arena held by the context.  n_lanes <= 0 takes the count that
+ * hf_tune_batch or hf_load_tuning recorded for this batch shape, else 1.
  * Every box's outputs are identical to hf_find's on that box alone.  The call
  * first waits for the caller's stream and returns when all boxes are done.
  * Returns the first failing box's error (text names the box); if only halo
@@ -247,6 +285,36 @@ hf_status hf_find_batch(hf_ctx *ctx, int32_t n_boxes, const int64_t *box_offsets
                         int32_t *l0_id, int32_t *halo_id, hf_halo *halos,
                         const int64_t *halo_offsets, int64_t *n_halos, int32_t n_lanes,
                         void *stream);
+
+/* Autotuning of hf_find_batch (a measurement helper, no step of the method):
+ * runs the batch (same arguments as hf_find_batch) with 1 .. max_groups fused
+ * groups, each once untimed and then reps times, and keeps the count of the
+ * fastest run (a larger count must win by more than 2 %).  The context
+ * remembers it for batches with the same n_boxes and a particle total within
+ * 25 %, which hf_find_batch then uses when called with n_lanes <= 0.
+ * *best_groups and *best_ms (host, may be NULL) receive the choice and its
+ * time in milliseconds.  table_path (may be NULL): a text file rewritten with
+ * this shape's line replaced or appended, one line per shape:
+ *   hf-tune v1 <arch> n_boxes=<b> total=<n> groups=<g> ms=<t>
+ * The outputs hold the last run's results (identical for every count). */
+hf_status hf_tune_batch(hf_ctx *ctx, int32_t n_boxes, const int64_t *box_offsets,
+                        const float *pos, const hf_params *params, float *density,
+                        int32_t *l0_id, int32_t *halo_id, hf_halo *halos,
+                        const int64_t *halo_offsets, int64_t *n_halos, int32_t max_groups,
+                        int32_t reps, const char *table_path, int32_t *best_groups,
+                        float *best_ms, void *stream);
+
+/* Load a table written by hf_tune_batch into the context: lines of the
+ * context's device architecture are kept (a later line of the same shape
+ * replaces an earlier one), others and lines starting with '#' are skipped.
+ * *n_entries (may be NULL) receives the number of lines taken.
+ * HF_ERR_INVALID when the file cannot be read. */
+hf_status hf_load_tuning(hf_ctx *ctx, const char *table_path, int32_t *n_entries);
+
+/* The group count hf_find_batch uses for a batch of n_boxes boxes and `total`
+ * particles when called with n_lanes (host only, *groups receives it). */
+hf_status hf_batch_groups(const hf_ctx *ctx, int32_t n_boxes, int64_t total, int32_t n_lanes,
+                          int32_t *groups);
 
 /* ---- Request loop ----------------------------------------------------------
  * A server runs halo-finding requests for boxes of different sizes as they

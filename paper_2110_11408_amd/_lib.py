@@ -14,13 +14,16 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhf.so")
 
 HF_OK, HF_ERR_INVALID, HF_ERR_NOMEM, HF_ERR_CAPACITY, HF_ERR_DEVICE, HF_ERR_UNSUPPORTED = range(6)
+HF_OPT_RADIUS_SEARCH = 1
+HF_RADIUS_HISTOGRAM, HF_RADIUS_BINS = 0, 1
 STATUS = {0: "HF_OK", 1: "HF_ERR_INVALID", 2: "HF_ERR_NOMEM", 3: "HF_ERR_CAPACITY",
           4: "HF_ERR_DEVICE", 5: "HF_ERR_UNSUPPORTED"}
 
 EXPORTS = ["hf_default_params", "hf_params_at_redshift", "hf_derived", "hf_create", "hf_destroy", "hf_last_error",
-           "hf_get_stats", "hf_density", "hf_l0_fof", "hf_compaso", "hf_find", "hf_find_noalloc", "hf_count_pairs",
-           "hf_halo_stats",
-           "hf_find_batch", "hf_server_create", "hf_server_submit", "hf_server_wait",
+           "hf_get_stats", "hf_set_option", "hf_get_option", "hf_density", "hf_l0_fof", "hf_compaso", "hf_find", "hf_find_noalloc", "hf_find_grouped",
+           "hf_count_pairs", "hf_halo_stats",
+           "hf_find_batch", "hf_tune_batch", "hf_load_tuning", "hf_batch_groups",
+           "hf_server_create", "hf_server_submit", "hf_server_wait",
            "hf_server_now", "hf_server_held_bytes", "hf_server_last_error", "hf_server_destroy"]
 
 
@@ -106,14 +109,22 @@ def load(path: str = LIB_PATH):
         lib.hf_last_error.argtypes = [P]
         lib.hf_last_error.restype = ctypes.c_char_p
         lib.hf_get_stats.argtypes = [P, ctypes.POINTER(HfStats)]
+        lib.hf_set_option.argtypes = [P, ctypes.c_int32, I64]
+        lib.hf_get_option.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
         lib.hf_density.argtypes = [P, P, I64, PP, P, P]
         lib.hf_l0_fof.argtypes = [P, P, P, I64, PP, P, P, P]
         lib.hf_compaso.argtypes = [P, P, P, P, I64, PP, P, P, I64, P, P]
         lib.hf_find.argtypes = [P, P, I64, PP, P, P, P, P, I64, P, P]
         lib.hf_find_noalloc.argtypes = [P, P, I64, PP, P, P, P, P, I64, P, P]
+        lib.hf_find_grouped.argtypes = [P, P, I64, PP, P, P, P, P, I64, P, P, P, P]
         lib.hf_count_pairs.argtypes = [P, P, I64, PP, P, P]
         lib.hf_halo_stats.argtypes = [P, P, P, P, I64, PP, I64, P, P, P, P]
         lib.hf_find_batch.argtypes = [P, ctypes.c_int32, P, P, P, P, P, P, P, P, P, ctypes.c_int32, P]
+        lib.hf_tune_batch.argtypes = [P, ctypes.c_int32, P, P, P, P, P, P, P, P, P, ctypes.c_int32,
+                                      ctypes.c_int32, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_float), P]
+        lib.hf_load_tuning.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)]
+        lib.hf_batch_groups.argtypes = [P, ctypes.c_int32, I64, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
         lib.hf_server_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), I32, ctypes.c_int32,
                                          ctypes.c_uint64]
         lib.hf_server_submit.argtypes = [P, ctypes.POINTER(HfRequest), ctypes.POINTER(ctypes.c_int64)]
@@ -126,8 +137,10 @@ def load(path: str = LIB_PATH):
         lib.hf_server_last_error.restype = ctypes.c_char_p
         lib.hf_server_destroy.argtypes = [P]
         lib.hf_server_destroy.restype = None
-        for name in ("hf_derived", "hf_params_at_redshift", "hf_create", "hf_get_stats", "hf_density", "hf_l0_fof",
-                     "hf_compaso", "hf_find", "hf_find_noalloc", "hf_count_pairs", "hf_halo_stats", "hf_find_batch",
+        for name in ("hf_derived", "hf_params_at_redshift", "hf_create", "hf_get_stats", "hf_set_option",
+                     "hf_get_option", "hf_density", "hf_l0_fof",
+                     "hf_compaso", "hf_find", "hf_find_noalloc", "hf_find_grouped", "hf_count_pairs", "hf_halo_stats", "hf_find_batch",
+                     "hf_tune_batch", "hf_load_tuning", "hf_batch_groups",
                      "hf_server_create", "hf_server_submit", "hf_server_wait"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib

@@ -115,6 +115,31 @@ class Context:
                 _ptr(buf), cap, ctypes.byref(nh), _stream(pos.device)),
             halos_cap, n, pos.device, {"density": dens, "l0_id": l0, "halo_id": halo_id})
 
+    def find_grouped(self, pos, p: HfParams, halos_cap: int | None = None, want_density=True,
+                     want_l0=True):
+        """hf_find_grouped: hf_find plus the members in group order (Sec. 2.3.5):
+        "members" (int32 [n]) holds each halo's particles (table order,
+        ascending index), then the particles of no halo; "halo_start" (int64
+        [n_halos + 1]) the first position of each halo's run and of the rest."""
+        pos = _check_pos(pos)
+        n = pos.shape[0]
+        dens = torch.empty(n, dtype=torch.float32, device=pos.device) if want_density else None
+        l0 = torch.empty(n, dtype=torch.int32, device=pos.device) if want_l0 else None
+        halo_id = torch.empty(n, dtype=torch.int32, device=pos.device)
+        members = torch.empty(max(n, 1), dtype=torch.int32, device=pos.device)
+        box = {}
+
+        def call(cap, buf, nh):
+            box["start"] = torch.empty(cap + 1, dtype=torch.int64, device=pos.device)
+            return self.lib.hf_find_grouped(self.h, _ptr(pos), n, ctypes.byref(p), _ptr(dens), _ptr(l0),
+                                            _ptr(halo_id), _ptr(buf), cap, ctypes.byref(nh), _ptr(members),
+                                            _ptr(box["start"]), _stream(pos.device))
+        out = self._with_table(call, halos_cap, n, pos.device,
+                               {"density": dens, "l0_id": l0, "halo_id": halo_id})
+        out["members"] = members[:n]
+        out["halo_start"] = box["start"][: out["n_halos"] + 1]
+        return out
+
     def find_noalloc(self, pos, p: HfParams, halo_id, halos, density=None, l0_id=None) -> int:
         """hf_find_noalloc into caller-allocated device tensors (halo_id int32 [n],
         halos int32 [cap, HALO_WORDS], density / l0_id optional): the library's
@@ -194,6 +219,60 @@ class Context:
             return {"density": dens, "l0_id": l0, "halo_id": halo_id, "n_halos": nh[:nb].copy(),
                     "halos": tables}
         raise HfError(_lib.HF_ERR_CAPACITY, "halo table capacity retry failed")
+
+    def set_radius_search(self, mode: str):
+        """hf_set_option(HF_OPT_RADIUS_SEARCH): "histogram" (default) or "bins"
+        (the radial bins of Sec. 2.3.4); the results are the same."""
+        value = {"histogram": _lib.HF_RADIUS_HISTOGRAM, "bins": _lib.HF_RADIUS_BINS}[mode]
+        self._raise(self.lib.hf_set_option(self.h, _lib.HF_OPT_RADIUS_SEARCH, value))
+
+    def radius_search(self) -> str:
+        v = ctypes.c_int64(-1)
+        self._raise(self.lib.hf_get_option(self.h, _lib.HF_OPT_RADIUS_SEARCH, ctypes.byref(v)))
+        return "bins" if v.value == _lib.HF_RADIUS_BINS else "histogram"
+
+    def tune_batch(self, pos, offsets, params, max_groups=4, reps=2, table_path=None):
+        """hf_tune_batch: times hf_find_batch on these boxes with 1..max_groups
+        fused groups and records the fastest count for this batch shape (in the
+        context, and in table_path when given).  Returns (best_groups, best_ms,
+        results as find_batch returns them)."""
+        import numpy as np
+        first = self.find_batch(pos, offsets, params, n_lanes=1)
+        pos = _check_pos(pos)
+        offs = np.ascontiguousarray(offsets, dtype=np.int64)
+        nb = len(offs) - 1
+        total = int(offs[-1])
+        pa = (HfParams * max(nb, 1))(*params)
+        caps = np.maximum(first["n_halos"], 1)
+        hoffs = np.ascontiguousarray(np.concatenate([[0], np.cumsum(caps)]), dtype=np.int64)
+        buf = torch.empty((int(hoffs[-1]), HALO_WORDS), dtype=torch.int32, device=pos.device)
+        dens = torch.empty(total, dtype=torch.float32, device=pos.device)
+        l0 = torch.empty(total, dtype=torch.int32, device=pos.device)
+        halo_id = torch.empty(total, dtype=torch.int32, device=pos.device)
+        nh = np.zeros(max(nb, 1), dtype=np.int64)
+        best = ctypes.c_int32(0)
+        ms = ctypes.c_float(0.0)
+        path = table_path.encode() if table_path else None
+        self._raise(self.lib.hf_tune_batch(self.h, nb, offs.ctypes.data, _ptr(pos), ctypes.byref(pa), _ptr(dens),
+                                           _ptr(l0), _ptr(halo_id), _ptr(buf), hoffs.ctypes.data,
+                                           nh.ctypes.data, int(max_groups), int(reps), path,
+                                           ctypes.byref(best), ctypes.byref(ms), _stream(pos.device)))
+        tables = [buf[hoffs[b]: hoffs[b] + nh[b]] for b in range(nb)]
+        return best.value, ms.value, {"density": dens, "l0_id": l0, "halo_id": halo_id,
+                                      "n_halos": nh[:nb].copy(), "halos": tables}
+
+    def load_tuning(self, table_path):
+        """hf_load_tuning: take a tuning table's lines for this device; returns
+        the number of lines taken."""
+        k = ctypes.c_int32(0)
+        self._raise(self.lib.hf_load_tuning(self.h, table_path.encode(), ctypes.byref(k)))
+        return k.value
+
+    def batch_groups(self, n_boxes, total, n_lanes=0):
+        """hf_batch_groups: the fused group count hf_find_batch would use."""
+        g = ctypes.c_int32(0)
+        self._raise(self.lib.hf_batch_groups(self.h, int(n_boxes), int(total), int(n_lanes), ctypes.byref(g)))
+        return g.value
 
     def _with_table(self, call, cap, n, device, outs):
         cap = max(1, n // 32) if cap is None else int(cap)

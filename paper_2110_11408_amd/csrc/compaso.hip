@@ -289,14 +289,27 @@ __device__ __forceinline__ int block_min(int v, int *s_min) {
 constexpr int kWaveHist = 1024;   // groups below this size run one per wavefront
 constexpr int kWaveNuc = 64;      // ... when they have at most this many candidates
 
-// Groups with candidates, one wavefront each (four per workgroup), for the
-// groups of fewer than kWaveHist particles with at most kWaveNuc candidates:
-// the same walk as k_accept with the histogram, the accepted nuclei and their
-// positions in the wavefront's LDS and wave-level scans instead of workgroup
-// barriers, so that many small groups run on a CU at once.  The other groups
-// are appended to mid_list (fewer than kHistMid particles) or big_list, with
-// their counts in *mid_count and *big_count, for k_accept.
-__global__ __launch_bounds__(kBlock) void k_accept_small(const uint32_t *__restrict__ ngc_p, Boxes bx,
+// Next item of a device work queue: *head counts the items taken so far
+// (zero when the call began); every caller of one wavefront gets the same
+// item.
+__device__ __forceinline__ uint32_t wave_pop(uint32_t *head) {
+    uint32_t q = 0;
+    if ((threadIdx.x & 63) == 0) q = atomicAdd(head, 1u);
+    return (uint32_t)__builtin_amdgcn_readfirstlane(__shfl(q, 0, 64));
+}
+
+// Groups with candidates (all boxes, largest first), one wavefront at a time
+// each: a persistent grid whose wavefronts take the next group from the list
+// until it is exhausted.  Groups of fewer than kWaveHist particles with at
+// most kWaveNuc candidates run here: the same walk as k_accept with the
+// histogram, the accepted nuclei and their positions in the wavefront's LDS
+// and wave-level scans instead of workgroup barriers, so that many small
+// groups run on a CU at once.  The other groups are appended to mid_list
+// (fewer than kHistMid particles) or big_list, with their counts in
+// *mid_count and *big_count, for k_accept (route_all: every group, when R is
+// searched by radial bins).
+__global__ __launch_bounds__(kBlock) void k_accept_small(const uint32_t *__restrict__ ngc_p,
+                                                         uint32_t *__restrict__ head, bool route_all, Boxes bx,
                                                          const int32_t *__restrict__ glist,
                                                          const int32_t *__restrict__ g_start,
                                                          const int32_t *__restrict__ g_size,
@@ -318,106 +331,215 @@ __global__ __launch_bounds__(kBlock) void k_accept_small(const uint32_t *__restr
     __shared__ int32_t s_hi[kBlock / 64][kWaveNuc];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const uint32_t q = blockIdx.x * (kBlock / 64) + (uint32_t)wave;
-    if (q >= *ngc_p) return;
-    const int gi = glist[q];
-    const int64_t start = g_start[gi];
-    const int64_t m = g_size[gi];
-    const Geo &g = bx.geo[__builtin_amdgcn_readfirstlane(box_of(bx, (uint32_t)mem[start]))];
-    const uint32_t cs = gcoff[gi], ce = gcoff[gi + 1];
-    if (m + 1 > kWaveHist || ce - cs > (uint32_t)kWaveNuc) {
-        if (lane == 0) {
-            if (m + 1 <= kHistMid) mid_list[atomicAdd(mid_count, 1u)] = gi;
-            else big_list[atomicAdd(big_count, 1u)] = gi;
-        }
-        return;
-    }
+    const uint32_t ngc = *ngc_p;
     uint32_t *hist = s_hist[wave];
-    int nh = 0;
-    for (uint32_t r = cs; r < ce; r++) {
-        const int c = cand_sorted[r];
-        const float4 pc = spos[c];
-        // eligibility: not inside alpha R of any accepted nucleus (nh <= 64)
-        bool inel = false;
-        if (lane < nh) {
-            const double e = d2_exact(pc, s_hp[wave][lane], g.L, g.half);
-            inel = g.K2 * e3(e) < g.A6 * ii(s_hi[wave][lane]);
+    for (uint32_t q = wave_pop(head); q < ngc; q = wave_pop(head)) {
+        const int gi = glist[q];
+        const int64_t start = g_start[gi];
+        const int64_t m = g_size[gi];
+        const Geo &g = bx.geo[__builtin_amdgcn_readfirstlane(box_of(bx, (uint32_t)mem[start]))];
+        const uint32_t cs = gcoff[gi], ce = gcoff[gi + 1];
+        if (route_all || m + 1 > kWaveHist || ce - cs > (uint32_t)kWaveNuc) {
+            if (lane == 0) {
+                if (m + 1 <= kHistMid) mid_list[atomicAdd(mid_count, 1u)] = gi;
+                else big_list[atomicAdd(big_count, 1u)] = gi;
+            }
+            continue;
         }
-        if (__ballot(inel)) continue;
-        // bucket histogram over all m particles of the group
-        for (int64_t k = lane; k <= m; k += 64) hist[k] = 0u;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        for (int64_t t = lane; t < m; t += 64) {
-            const double e = d2_exact(pc, spos[mem[start + t]], g.L, g.half);
-            atomicAdd(&hist[bucket_of(g.K2 * e3(e), m)], 1u);
+        int nh = 0;
+        for (uint32_t r = cs; r < ce; r++) {
+            const int c = cand_sorted[r];
+            const float4 pc = spos[c];
+            // eligibility: not inside alpha R of any accepted nucleus (nh <= 64)
+            bool inel = false;
+            if (lane < nh) {
+                const double e = d2_exact(pc, s_hp[wave][lane], g.L, g.half);
+                inel = g.K2 * e3(e) < g.A6 * ii(s_hi[wave][lane]);
+            }
+            if (__ballot(inel)) continue;
+            // bucket histogram over all m particles of the group
+            for (int64_t k = lane; k <= m; k += 64) hist[k] = 0u;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            for (int64_t t = lane; t < m; t += 64) {
+                const double e = d2_exact(pc, spos[mem[start + t]], g.L, g.half);
+                atomicAdd(&hist[bucket_of(g.K2 * e3(e), m)], 1u);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            // first k in [1, m-1] with C(k) <= k, C(k) = sum of buckets 0..k;
+            // lane L covers buckets 16L .. 16L + 15 (m < 1024)
+            uint32_t v[16];
+            uint32_t sum = 0;
+    #pragma unroll
+            for (int u = 0; u < 16; u++) {
+                const int64_t k = (int64_t)lane * 16 + u;
+                v[u] = k < m ? hist[k] : 0u;
+                sum += v[u];
+            }
+            uint32_t incl = sum;
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t y = __shfl_up(incl, d, 64);
+                if (lane >= d) incl += y;
+            }
+            uint32_t C = incl - sum;
+            int hit = -1;
+    #pragma unroll
+            for (int u = 0; u < 16; u++) {
+                const int64_t k = (int64_t)lane * 16 + u;
+                C += v[u];
+                if (hit < 0 && k >= 1 && k < m && (int64_t)C <= k) hit = (int)k;
+            }
+            const uint64_t hm = __ballot(hit >= 0);
+            const int64_t found = hm ? (int64_t)lane_get(hit, __ffsll((unsigned long long)hm) - 1) : m;
+            if (lane == 0) {
+                h_nuc[cs + nh] = c;
+                h_ienc[cs + nh] = (int32_t)found;
+                h_gid[cs + nh] = gi;
+                s_hp[wave][nh] = pc;
+                s_hi[wave][nh] = (int32_t)found;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            nh++;
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        // first k in [1, m-1] with C(k) <= k, C(k) = sum of buckets 0..k;
-        // lane L covers buckets 16L .. 16L + 15 (m < 1024)
-        uint32_t v[16];
-        uint32_t sum = 0;
-#pragma unroll
-        for (int u = 0; u < 16; u++) {
-            const int64_t k = (int64_t)lane * 16 + u;
-            v[u] = k < m ? hist[k] : 0u;
-            sum += v[u];
-        }
-        uint32_t incl = sum;
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint32_t y = __shfl_up(incl, d, 64);
-            if (lane >= d) incl += y;
-        }
-        uint32_t C = incl - sum;
-        int hit = -1;
-#pragma unroll
-        for (int u = 0; u < 16; u++) {
-            const int64_t k = (int64_t)lane * 16 + u;
-            C += v[u];
-            if (hit < 0 && k >= 1 && k < m && (int64_t)C <= k) hit = (int)k;
-        }
-        const uint64_t hm = __ballot(hit >= 0);
-        const int64_t found = hm ? (int64_t)lane_get(hit, __ffsll((unsigned long long)hm) - 1) : m;
-        if (lane == 0) {
-            h_nuc[cs + nh] = c;
-            h_ienc[cs + nh] = (int32_t)found;
-            h_gid[cs + nh] = gi;
-            s_hp[wave][nh] = pc;
-            s_hi[wave][nh] = (int32_t)found;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        nh++;
+        if (lane == 0) g_nh[gi] = nh;
     }
-    if (lane == 0) g_nh[gi] = nh;
 }
 
-// One workgroup per L0 group in `list` (count on the device): walk the
-// candidates in descending density; a candidate inside alpha R of an accepted
-// nucleus is ineligible; an eligible one is accepted and its enclosed count i
-// found from the bucket histogram of all particles of the group.
+// Squared outer edge of radial bin j of width w: ((j + 1) w)^2; bin j holds
+// the squared distances e with edge(j - 1) <= e < edge(j).
+__device__ __forceinline__ double rbin_edge2(int j, double w) {
+    const double r = (double)(j + 1) * w;
+    return r * r;
+}
+
+// The bin of e (the bin width is such that every minimum-image distance lies
+// inside the last edge).
+__device__ __forceinline__ int rbin_of(double e, double w) {
+    int j = (int)(sqrt(e) / w);
+    if (j > kRadBins - 1) j = kRadBins - 1;
+    while (j > 0 && e < rbin_edge2(j - 1, w)) j--;
+    while (j < kRadBins - 1 && !(e < rbin_edge2(j, w))) j++;
+    return j;
+}
+
+// f(e) for the squared distance e of every member of the group to pc, the
+// members spread over the workgroup (UB per thread and round, their loads
+// issued together).
+template <int NT, class F>
+__device__ __forceinline__ void for_members(int64_t m, int64_t start, const int32_t *__restrict__ mem,
+                                            const float4 *__restrict__ spos, const float4 &pc, const Geo &g,
+                                            F f) {
+    constexpr int UB = NT >= 1024 ? 4 : 8;
+    for (int64_t t0 = threadIdx.x; t0 < m; t0 += UB * NT) {
+        int32_t id[UB];
+#pragma unroll
+        for (int u = 0; u < UB; u++) {
+            const int64_t t = t0 + (int64_t)u * NT;
+            id[u] = t < m ? mem[start + t] : -1;
+        }
+        float4 pm[UB];
+#pragma unroll
+        for (int u = 0; u < UB; u++) pm[u] = id[u] >= 0 ? spos[id[u]] : pc;
+#pragma unroll
+        for (int u = 0; u < UB; u++)
+            if (id[u] >= 0) f(d2_exact(pc, pm[u], g.L, g.half));
+    }
+}
+
+// Zero hist[0..len]: LDS below HL, the group's global region gh beyond.
 template <int NT, int HL>
-__global__ __launch_bounds__(NT) void k_accept(const uint32_t *__restrict__ ngc_p, Boxes bx,
+__device__ __forceinline__ void hist_clear(uint32_t *s_hist, uint32_t *gh, int64_t len) {
+    for (int64_t k = threadIdx.x; k <= len && k < HL; k += NT) s_hist[k] = 0u;
+    if (len + 1 > HL) {
+        for (int64_t k = HL + threadIdx.x; k <= len; k += NT) stu(gh + k, 0u);
+        __threadfence();
+    }
+}
+
+__device__ __forceinline__ void hist_add(uint32_t *s_hist, uint32_t *gh, int64_t k, int hl) {
+    if (k < hl) atomicAdd(&s_hist[k], 1u);
+    else atomicAdd(gh + k, 1u);
+}
+
+// First t in [0, len) with C(t) <= t and 1 <= base + t <= m - 1, where
+// C(t) = hist[0] + ... + hist[t]; -1 when there is none.
+template <int NT, int HL>
+__device__ __forceinline__ int64_t first_crossing(const uint32_t *s_hist, const uint32_t *gh, int64_t len,
+                                                  int64_t base, int64_t m, uint32_t *s_red, int *s_min) {
+    constexpr int SI = NT >= 1024 ? kScanIpt / 2 : kScanIpt;
+    uint32_t run = 0;
+    for (int64_t b0 = 0; b0 < len; b0 += (int64_t)NT * SI) {
+        const int64_t k0 = b0 + (int64_t)threadIdx.x * SI;
+        uint32_t v[SI];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int u = 0; u < SI; u++) {
+            const int64_t k = k0 + u;
+            v[u] = k < len ? (k < HL ? s_hist[k] : ldu(gh + k)) : 0u;
+            sum += v[u];
+        }
+        uint32_t tot;
+        uint32_t C = run + block_excl<NT>(sum, s_red, &tot);
+        int hit = 0x7fffffff;
+#pragma unroll
+        for (int u = 0; u < SI; u++) {
+            const int64_t k = k0 + u;
+            C += v[u];
+            if (hit == 0x7fffffff && k < len && base + k >= 1 && base + k < m && (int64_t)C <= k)
+                hit = (int)(k - b0);
+        }
+        const int best = block_min<NT>(hit, s_min);
+        run += tot;
+        if (best != 0x7fffffff) return b0 + best;
+    }
+    return -1;
+}
+
+// One workgroup per L0 group in `glist` (count on the device; the grid is an
+// upper bound).  No persistent loop here: a group index broadcast through LDS
+// by one thread, with a barrier inside a loop whose exit depends on it, is a
+// form the compiler may restructure so that the other threads pass the barrier
+// again before that thread has written the next index.  Walk the candidates
+// in descending density; a
+// candidate inside alpha R of an accepted nucleus is ineligible; an eligible
+// one is accepted and its enclosed count i found
+//   BINS = false: from the bucket histogram of all particles of the group;
+//   BINS = true:  by the radial bins of Sec. 2.3.4.  Counts of the members per
+//                 radial bin (width g.rbin, in LDS) give C_j, the members
+//                 inside bin j's inner edge.  A bin whose C_j members, placed
+//                 at its outer edge, still meet the threshold
+//                 (K^2 edge^3 <= C_j^2) holds no crossing: every member in it
+//                 is inside that edge at a sorted position >= C_j.  The first
+//                 bin that is not passed over is searched with the bucket
+//                 histogram of its own members (positions C_j .. C_j + c_j - 1
+//                 of the sorted order: the crossing is the first t with
+//                 #{bin members with bucket <= C_j + t} <= t), and the search
+//                 moves outwards while a bin holds no crossing.
+template <int NT, int HL, bool BINS>
+__global__ __launch_bounds__(NT) void k_accept(const uint32_t *__restrict__ ngc_p,
+                                               Boxes bx,
                                                const int32_t *__restrict__ glist,
-                                                   const int32_t *__restrict__ g_start,
-                                                   const int32_t *__restrict__ g_size,
-                                                   const uint32_t *__restrict__ gcoff,
-                                                   const int32_t *__restrict__ cand_sorted,
-                                                   const int32_t *__restrict__ mem,
-                                                   const float4 *__restrict__ spos,
-                                                   uint32_t *__restrict__ hist_all,
-                                                   int32_t *__restrict__ h_nuc,
-                                                   int32_t *__restrict__ h_ienc,
-                                                   int32_t *__restrict__ h_gid,
-                                                   int32_t *__restrict__ g_nh) {
+                                               const int32_t *__restrict__ g_start,
+                                               const int32_t *__restrict__ g_size,
+                                               const uint32_t *__restrict__ gcoff,
+                                               const int32_t *__restrict__ cand_sorted,
+                                               const int32_t *__restrict__ mem,
+                                               const float4 *__restrict__ spos,
+                                               uint32_t *__restrict__ hist_all,
+                                               int32_t *__restrict__ h_nuc,
+                                               int32_t *__restrict__ h_ienc,
+                                               int32_t *__restrict__ h_gid,
+                                               int32_t *__restrict__ g_nh) {
 #pragma clang fp contract(off)
     __shared__ uint32_t s_hist[HL + 1];
+    __shared__ uint32_t s_rb[BINS ? kRadBins : 1];
     __shared__ int s_nh;
     __shared__ uint32_t s_red[NT / 64];
     __shared__ int s_min[NT / 64];
-    // the grid is an upper bound; the number of groups with candidates is read here
     if (blockIdx.x >= *ngc_p) return;
+    const int tid = threadIdx.x;
     const int gi = glist[blockIdx.x];
     const int64_t start = g_start[gi];
     const int64_t m = g_size[gi];
@@ -427,9 +549,7 @@ __global__ __launch_bounds__(NT) void k_accept(const uint32_t *__restrict__ ngc_
     // rest in its own global region (m + 1 words, disjoint per group).  The
     // small buckets are where the particles of a dense core pile up, so the
     // global atomics are only the sparse outer ones.
-    const bool spill = m + 1 > HL;
     uint32_t *ghist = hist_all + start + gi;
-    const int tid = threadIdx.x;
     if (tid == 0) s_nh = 0;
     __syncthreads();
     for (uint32_t r = cs; r < ce; r++) {
@@ -443,65 +563,74 @@ __global__ __launch_bounds__(NT) void k_accept(const uint32_t *__restrict__ ngc_
             if (g.K2 * e3(e) < g.A6 * ii(ldi(h_ienc + cs + h))) inel = 1;
         }
         if (__syncthreads_or(inel)) continue;
-        // histogram of buckets over all particles of the group
-        for (int64_t k = tid; k <= m && k < HL; k += NT) s_hist[k] = 0u;
-        if (spill) {
-            for (int64_t k = HL + tid; k <= m; k += NT) stu(ghist + k, 0u);
-            __threadfence();
-        }
-        __syncthreads();
-        // UB members per thread and round, their loads issued together
-        constexpr int UB = NT >= 1024 ? 4 : 8;
-        for (int64_t t0 = tid; t0 < m; t0 += UB * NT) {
-            int32_t id[UB];
-#pragma unroll
-            for (int u = 0; u < UB; u++) {
-                const int64_t t = t0 + (int64_t)u * NT;
-                id[u] = t < m ? mem[start + t] : -1;
-            }
-            float4 pm[UB];
-#pragma unroll
-            for (int u = 0; u < UB; u++) pm[u] = id[u] >= 0 ? spos[id[u]] : pc;
-#pragma unroll
-            for (int u = 0; u < UB; u++) {
-                if (id[u] < 0) continue;
-                const double e = d2_exact(pc, pm[u], g.L, g.half);
-                const int64_t bk = bucket_of(g.K2 * e3(e), m);
-                if (bk < HL) atomicAdd(&s_hist[bk], 1u);
-                else atomicAdd(ghist + bk, 1u);
-            }
-        }
-        if (spill) __threadfence();
-        __syncthreads();
-        // first k in [1, m-1] with C(k) <= k, C(k) = sum of buckets 0..k
-        constexpr int SI = NT >= 1024 ? kScanIpt / 2 : kScanIpt;
         int64_t found = m;
-        uint32_t run = 0;
-        for (int64_t base = 0; base < m; base += (int64_t)NT * SI) {
-            const int64_t k0 = base + (int64_t)tid * SI;
-            uint32_t v[SI];
+        if constexpr (BINS) {
+            // members per radial bin, then their inclusive prefix in place
+            for (int k = tid; k < kRadBins; k += NT) s_rb[k] = 0u;
+            __syncthreads();
+            for_members<NT>(m, start, mem, spos, pc, g,
+                            [&](double e) { atomicAdd(&s_rb[rbin_of(e, g.rbin)], 1u); });
+            __syncthreads();
+            constexpr int BI = kRadBins / NT;
+            uint32_t v[BI];
             uint32_t sum = 0;
 #pragma unroll
-            for (int u = 0; u < SI; u++) {
-                const int64_t k = k0 + u;
-                v[u] = k < m ? (k < HL ? s_hist[k] : ldu(ghist + k)) : 0u;
+            for (int u = 0; u < BI; u++) {
+                v[u] = s_rb[tid * BI + u];
                 sum += v[u];
             }
             uint32_t tot;
-            uint32_t C = run + block_excl<NT>(sum, s_red, &tot);
-            int hit = 0x7fffffff;
+            uint32_t P = block_excl<NT>(sum, s_red, &tot);
 #pragma unroll
-            for (int u = 0; u < SI; u++) {
-                const int64_t k = k0 + u;
-                C += v[u];
-                if (hit == 0x7fffffff && k >= 1 && k < m && (int64_t)C <= k) hit = (int)(k - base);
+            for (int u = 0; u < BI; u++) {
+                P += v[u];
+                s_rb[tid * BI + u] = P;
             }
-            const int best = block_min<NT>(hit, s_min);
-            run += tot;
-            if (best != 0x7fffffff) {
-                found = base + best;
-                break;
+            __syncthreads();
+            for (int j0 = 0;;) {
+                // the innermost occupied bin from j0 on that is not passed over
+                int jb = 0x7fffffff;
+                for (int j = j0 + tid; j < kRadBins; j += NT) {
+                    const uint32_t Cj = j ? s_rb[j - 1] : 0u;
+                    if (s_rb[j] > Cj && !(g.K2 * e3(rbin_edge2(j, g.rbin)) <= ii(Cj))) {
+                        jb = j;
+                        break;
+                    }
+                }
+                const int js = block_min<NT>(jb, s_min);
+                if (js == 0x7fffffff) break;  // no crossing inside the group
+                const int64_t C = js ? s_rb[js - 1] : 0u;
+                const int64_t cnt = (int64_t)s_rb[js] - C;
+                const double lo = js ? rbin_edge2(js - 1, g.rbin) : -1.0, hi = rbin_edge2(js, g.rbin);
+                hist_clear<NT, HL>(s_hist, ghist, cnt);
+                __syncthreads();
+                for_members<NT>(m, start, mem, spos, pc, g, [&](double e) {
+                    if (e >= lo && e < hi) {
+                        int64_t k = bucket_of(g.K2 * e3(e), m) - C;
+                        k = k < 0 ? 0 : (k > cnt ? cnt : k);
+                        hist_add(s_hist, ghist, k, HL);
+                    }
+                });
+                if (cnt + 1 > HL) __threadfence();
+                __syncthreads();
+                const int64_t t = first_crossing<NT, HL>(s_hist, ghist, cnt, C, m, s_red, s_min);
+                if (t >= 0) {
+                    found = C + t;
+                    break;
+                }
+                j0 = js + 1;
             }
+        } else {
+            // histogram of buckets over all particles of the group
+            hist_clear<NT, HL>(s_hist, ghist, m);
+            __syncthreads();
+            for_members<NT>(m, start, mem, spos, pc, g,
+                            [&](double e) { hist_add(s_hist, ghist, bucket_of(g.K2 * e3(e), m), HL); });
+            if (m + 1 > HL) __threadfence();
+            __syncthreads();
+            // first k in [1, m-1] with C(k) <= k, C(k) = sum of buckets 0..k
+            const int64_t t = first_crossing<NT, HL>(s_hist, ghist, m, 0, m, s_red, s_min);
+            if (t >= 0) found = t;
         }
         if (tid == 0) {
             h_nuc[cs + nh] = c;
@@ -661,6 +790,40 @@ __global__ __launch_bounds__(kBlock) void k_glist_from_keys(int64_t len, const u
     if (t < len && t < (int64_t)*ngc_p) glist[t] = (int32_t)(keys[t] & 0xffffffffu);
 }
 
+// ------------------------------------------------------------ group order
+// Members collected into group order (Sec. 2.3.5): the particles sorted by the
+// table row of their halo (particles of no halo after the last row), ascending
+// original index within a row.  The paper sweeps the particles with in-place
+// partitions, the largest halo and the unassigned ones first; here one stable
+// sort by row gives every run at once.
+
+// key = (row, original index); row = nrows for particles of no halo.  halo_id
+// is in original order with labels 1 + nucleus index; tpos maps a kept
+// nucleus to its table row.
+__global__ __launch_bounds__(kBlock) void k_order_keys(int64_t n, int64_t nrows,
+                                                       const int32_t *__restrict__ halo_id,
+                                                       const uint32_t *__restrict__ tpos,
+                                                       uint64_t *__restrict__ keys) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t h = halo_id[i];
+    const uint64_t row = h > 0 ? (uint64_t)tpos[h - 1] : (uint64_t)nrows;
+    keys[i] = (row << 32) | (uint64_t)i;
+}
+
+// members[t] from the sorted keys; halo_start[r] = first position of row r
+// (the rows between two consecutive keys' rows start at the later key).
+__global__ __launch_bounds__(kBlock) void k_order_out(int64_t n, int64_t nrows, const uint64_t *__restrict__ keys,
+                                                      int32_t *__restrict__ members,
+                                                      int64_t *__restrict__ halo_start) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > n) return;
+    if (t < n) members[t] = (int32_t)(keys[t] & 0xffffffffu);
+    const int64_t rp = t > 0 ? (int64_t)(keys[t - 1] >> 32) : -1;
+    const int64_t rc = t < n ? (int64_t)(keys[t] >> 32) : nrows + 1;
+    for (int64_t r = rp + 1; r <= rc && r <= nrows; r++) halo_start[r] = t;
+}
+
 }  // namespace
 
 void launch_segment(int64_t n, Work &w, hipStream_t s) {
@@ -727,31 +890,48 @@ void launch_candidates_sort(int64_t n, int64_t G, int64_t NC, Work &w, hipStream
 void launch_accept(int64_t n, int64_t G, int64_t NC, int64_t M, const Boxes &bx, Work &w, hipStream_t s) {
     // groups with candidates (at most min(G, NC)), one wavefront each; the
     // others are listed (in the free chunk-flag array, counts in counters[9]
-    // and [11], zero since the call began) for one workgroup each: medium
-    // groups (at most M / kWaveHist of kWaveHist particles or more, and
-    // NC / (kWaveNuc + 1) with more than kWaveNuc candidates) and large ones
-    // (at most M / kHistMid), whose list starts halfway through the array
+    // and [11]) for one workgroup each: medium groups (at most M / kWaveHist
+    // of kWaveHist particles or more, and NC / (kWaveNuc + 1) with more than
+    // kWaveNuc candidates) and large ones (at most M / kHistMid), whose list
+    // starts halfway through the array.  The first kernel is a persistent
+    // grid of a few workgroups per compute unit whose wavefronts take groups
+    // from the list (queue head counters[13]); the others run one workgroup
+    // per listed group.  All these words are zero since the call began.
     const int64_t bound = G < NC ? G : NC;
     if (bound <= 0) return;
     int32_t *mid_list = reinterpret_cast<int32_t *>(w.f_chunk);
     int32_t *big_list = reinterpret_cast<int32_t *>(w.f_chunk) + n / 2;
     uint32_t *mid_count = reinterpret_cast<uint32_t *>(w.counters + 9);
     uint32_t *big_count = reinterpret_cast<uint32_t *>(w.counters + 11);
-    hipLaunchKernelGGL(k_accept_small, dim3((unsigned)((bound + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), 0,
-                       s, w.gcidx + G, bx, w.glist, w.g_start, w.g_size, w.gcoff, w.cand_sorted, w.mem, w.spos,
-                       w.h_nuc, w.h_ienc, w.h_gid, w.g_nh, mid_list, mid_count, big_list, big_count);
-    int64_t nmid = M / kWaveHist + NC / (kWaveNuc + 1) + 1;
-    if (nmid > bound) nmid = bound;
-    hipLaunchKernelGGL((k_accept<kBlock, kHistMid>), dim3((unsigned)nmid), dim3(kBlock), 0, s, mid_count, bx,
-                       mid_list, w.g_start, w.g_size, w.gcoff, w.cand_sorted, w.mem, w.spos, w.hist, w.h_nuc,
-                       w.h_ienc, w.h_gid, w.g_nh);
-    int64_t nbig = M / kHistMid + 1;
-    if (nbig > bound) nbig = bound;
+    uint32_t *heads = reinterpret_cast<uint32_t *>(w.counters + 13);
+    const int64_t ncu = w.ncu > 0 ? w.ncu : 1;
+    auto cap = [](int64_t a, int64_t b) { return (unsigned)(a < b ? a : b); };
+    const bool bins = w.radius_bins;
+    hipLaunchKernelGGL(k_accept_small, dim3(cap((bound + kBlock / 64 - 1) / (kBlock / 64), 8 * ncu)), dim3(kBlock),
+                       0, s, w.gcidx + G, heads, bins, bx, w.glist, w.g_start, w.g_size, w.gcoff, w.cand_sorted,
+                       w.mem, w.spos, w.h_nuc, w.h_ienc, w.h_gid, w.g_nh, mid_list, mid_count, big_list, big_count);
+    // with radial bins every group is listed: at most bound medium groups
+    const int64_t nmid = bins ? bound : M / kWaveHist + NC / (kWaveNuc + 1) + 1;
+    const dim3 gmid(cap(nmid, bound));
     // the large groups are few and each is a serial walk: 1024 threads and a
     // 144 KB LDS histogram each (one workgroup per CU)
-    hipLaunchKernelGGL((k_accept<1024, kHistBig>), dim3((unsigned)nbig), dim3(1024), 0, s, big_count, bx,
-                       big_list, w.g_start, w.g_size, w.gcoff, w.cand_sorted, w.mem, w.spos, w.hist, w.h_nuc,
-                       w.h_ienc, w.h_gid, w.g_nh);
+    const int64_t nbig = M / kHistMid + 1;
+    const dim3 gbig(cap(nbig, bound));
+    if (bins) {
+        hipLaunchKernelGGL((k_accept<kBlock, kHistMid, true>), gmid, dim3(kBlock), 0, s, mid_count, bx,
+                           mid_list, w.g_start, w.g_size, w.gcoff, w.cand_sorted, w.mem, w.spos, w.hist, w.h_nuc,
+                           w.h_ienc, w.h_gid, w.g_nh);
+        hipLaunchKernelGGL((k_accept<1024, kHistBig, true>), gbig, dim3(1024), 0, s, big_count, bx,
+                           big_list, w.g_start, w.g_size, w.gcoff, w.cand_sorted, w.mem, w.spos, w.hist, w.h_nuc,
+                           w.h_ienc, w.h_gid, w.g_nh);
+    } else {
+        hipLaunchKernelGGL((k_accept<kBlock, kHistMid, false>), gmid, dim3(kBlock), 0, s, mid_count, bx,
+                           mid_list, w.g_start, w.g_size, w.gcoff, w.cand_sorted, w.mem, w.spos, w.hist, w.h_nuc,
+                           w.h_ienc, w.h_gid, w.g_nh);
+        hipLaunchKernelGGL((k_accept<1024, kHistBig, false>), gbig, dim3(1024), 0, s, big_count, bx,
+                           big_list, w.g_start, w.g_size, w.gcoff, w.cand_sorted, w.mem, w.spos, w.hist, w.h_nuc,
+                           w.h_ienc, w.h_gid, w.g_nh);
+    }
 }
 
 void launch_assign(int64_t n, const Boxes &bx, Work &w, hipStream_t s) {
@@ -776,6 +956,14 @@ void launch_output(int64_t n, int64_t NC, const Boxes &bx, Work &w, int32_t *hal
         hipLaunchKernelGGL(k_box_rows, grid(bx.nbox), dim3(kBlock), 0, s, bx, w.tpos, box_rows);
     hipLaunchKernelGGL(k_out_particles, grid(n), dim3(kBlock), 0, s, n, bx, w.owner, w.h_nuc, w.h_count,
                        w.gkey, w.spos, halo_id, l0_out);
+}
+
+void launch_group_order(int64_t n, int64_t nrows, const int32_t *halo_id, Work &w, int32_t *members,
+                        int64_t *halo_start, hipStream_t s) {
+    // the radix key arrays are free once the output is written
+    hipLaunchKernelGGL(k_order_keys, grid(n), dim3(kBlock), 0, s, n, nrows, halo_id, w.tpos, w.rkey[0]);
+    const uint64_t *sorted = radix_sort_keys(w.rkey[0], w.rkey[1], n, 32, bits_for(nrows + 1), w, s);
+    hipLaunchKernelGGL(k_order_out, grid(n + 1), dim3(kBlock), 0, s, n, nrows, sorted, members, halo_start);
 }
 
 }  // namespace hf

@@ -150,6 +150,10 @@ hf_status make_geo(Lane *c, const hf_params *p, int64_t n, Geo *g) {
     g->K2 = d[D_K2];
     g->A6 = d[D_A6];
     g->C3 = d[D_C3];
+    // radial bins of the threshold-radius search (Sec. 2.3.4): steps of the
+    // cell side / sqrt(3), wider when kRadBins bins would not reach the
+    // farthest minimum image, sqrt(3) L/2
+    g->rbin = fmax(g->cell / sqrt(3.0), 1.0001 * sqrt(3.0) * g->half / hf::kRadBins);
     g->n_l1_min = p->n_l1_min;
     g->particle_mass = (float)p->particle_mass;
     g->cell_base = 0;
@@ -379,6 +383,8 @@ hf_status prepare(Lane *c, const Plan &pl, Work *w, bool extra, const hf::FixedA
         carve((char *)c->arena, pl.n, pl.ncell, pl.nsub_max, rhl, pl.nbox, extra, w);
     }
     w->host = c->host;
+    w->ncu = c->ncu;
+    w->radius_bins = c->radius_bins;
     c->stats = hf_stats{};
     c->stats.n_cells = pl.ncell;
     // the box tables go up and the per-box rows come back through it
@@ -428,8 +434,14 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 // CompaSO on the binned particles with group keys in w.gkey.  Fills halo_id,
 // l0_out (may be null), every box's table and its row count (n_halos, host,
 // nbox entries); records events ev[3..8].  CAPACITY when a table did not fit.
+// Optional output of a one-box pass: its members in group order (Sec. 2.3.5).
+struct GroupOut {
+    int32_t *members = nullptr;     // device [n]
+    int64_t *halo_start = nullptr;  // device [halo rows + 1]
+};
+
 hf_status run_compaso(Lane *c, const Plan &pl, const hf::Boxes &bx, Work &w, int32_t *halo_id,
-                      int32_t *l0_out, int64_t *n_halos, hipStream_t s) {
+                      int32_t *l0_out, int64_t *n_halos, hipStream_t s, const GroupOut &go = GroupOut{}) {
     const int64_t n = pl.n;
     HIP_OK(c, hipEventRecord(c->ev[3], s));
     hf::launch_segment(n, w, s);
@@ -489,6 +501,14 @@ hf_status run_compaso(Lane *c, const Plan &pl, const hf::Boxes &bx, Work &w, int
     if (over >= 0)
         return fail(c, HF_ERR_CAPACITY,
                     box_prefix(&pl, over) + "halos_cap is smaller than the number of halos");
+    if (go.members) {
+        // the rows are known and fit: members by table row (the call ends
+        // synchronized with its stream, as every call does)
+        hf::launch_group_order(n, total, halo_id, w, go.members, go.halo_start, s);
+        HIP_OK(c, hipEventRecord(c->ev[8], s));
+        HIP_OK(c, hipStreamSynchronize(s));
+        c->stats.ms_output = elapsed(c->ev[7], c->ev[8]);
+    }
     return HF_OK;
 }
 
@@ -560,7 +580,8 @@ struct OneBox {
 OneBox one_box(int64_t n, int64_t cap) { return OneBox{{0, n}, {0, cap > 0 ? cap : 0}}; }
 
 hf_status find_boxes(Lane *c, const hf::BoxSet &bs, const float *pos, float *density, int32_t *l0_id,
-                     int32_t *halo_id, int64_t *n_halos, hipStream_t s, const hf::FixedArena *fx) {
+                     int32_t *halo_id, int64_t *n_halos, hipStream_t s, const hf::FixedArena *fx,
+                     const GroupOut &go = GroupOut{}) {
     if (!c) return HF_ERR_INVALID;
     c->err.clear();
     Plan pl;
@@ -568,7 +589,15 @@ hf_status find_boxes(Lane *c, const hf::BoxSet &bs, const float *pos, float *den
     if (st != HF_OK) return st;
     if (n_halos)
         for (int b = 0; b < pl.nbox; b++) n_halos[b] = 0;
-    if (pl.n == 0) return HF_OK;
+    if (go.members && pl.nbox != 1) return fail(c, HF_ERR_INVALID, "group order is for one box");
+    if (pl.n == 0) {
+        if (go.halo_start) {
+            // no halos and no members: halo_start[0] = 0
+            hf::fill_i32(reinterpret_cast<int32_t *>(go.halo_start), 0, 2, s);
+            HIP_OK(c, hipStreamSynchronize(s));
+        }
+        return HF_OK;
+    }
     if (!halo_id) return fail(c, HF_ERR_INVALID, "halo_id is NULL");
     hf::Boxes bx;
     Work w;
@@ -579,7 +608,7 @@ hf_status find_boxes(Lane *c, const hf::BoxSet &bs, const float *pos, float *den
     hf::launch_fof(pl.n, bx, w, s);
     hf::launch_fof_labels(pl.n, bx, w, l0_id, s);
     HIP_OK(c, hipEventRecord(c->ev[9], s));
-    st = run_compaso(c, pl, bx, w, halo_id, nullptr, n_halos, s);
+    st = run_compaso(c, pl, bx, w, halo_id, nullptr, n_halos, s, go);
     c->stats.ms_bin = elapsed(c->ev[0], c->ev[1]);
     c->stats.ms_density = elapsed(c->ev[1], c->ev[2]);
     c->stats.ms_fof = elapsed(c->ev[2], c->ev[9]);
@@ -594,6 +623,9 @@ namespace hf {
 hf_status lane_init(Lane *L, int device, bool own_stream) {
     L->device = device;
     if (hipSetDevice(device) != hipSuccess) return HF_ERR_DEVICE;
+    if (hipDeviceGetAttribute(&L->ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        L->ncu <= 0)
+        return HF_ERR_DEVICE;
     if (hipHostMalloc(reinterpret_cast<void **>(&L->host), 64 * sizeof(uint32_t), hipHostMallocCoherent) !=
         hipSuccess) {
         L->host = nullptr;
@@ -759,6 +791,23 @@ const char *hf_last_error(const hf_ctx *c) { return c ? c->main.err.c_str() : "n
 hf_status hf_get_stats(const hf_ctx *c, hf_stats *out) {
     if (!c || !out) return HF_ERR_INVALID;
     *out = c->main.stats;
+    return HF_OK;
+}
+
+hf_status hf_set_option(hf_ctx *ctx, int32_t option, int64_t value) {
+    if (!ctx) return HF_ERR_INVALID;
+    if (option != HF_OPT_RADIUS_SEARCH) return fail(&ctx->main, HF_ERR_INVALID, "unknown option");
+    if (value != HF_RADIUS_HISTOGRAM && value != HF_RADIUS_BINS)
+        return fail(&ctx->main, HF_ERR_INVALID, "HF_OPT_RADIUS_SEARCH takes HF_RADIUS_HISTOGRAM or HF_RADIUS_BINS");
+    ctx->radius_bins = value == HF_RADIUS_BINS;
+    ctx->main.radius_bins = ctx->radius_bins;
+    for (auto &L : ctx->pool) L->radius_bins = ctx->radius_bins;
+    return HF_OK;
+}
+
+hf_status hf_get_option(const hf_ctx *ctx, int32_t option, int64_t *value) {
+    if (!ctx || !value || option != HF_OPT_RADIUS_SEARCH) return HF_ERR_INVALID;
+    *value = ctx->radius_bins ? HF_RADIUS_BINS : HF_RADIUS_HISTOGRAM;
     return HF_OK;
 }
 
@@ -962,6 +1011,26 @@ hf_status hf_find(hf_ctx *ctx, const float *pos, int64_t n, const hf_params *p, 
     if (!ctx) return HF_ERR_INVALID;
     return hf::lane_find(&ctx->main, pos, n, p, density, l0_id, halo_id, halos, halos_cap, n_halos,
                          (hipStream_t)stream);
+}
+
+hf_status hf_find_grouped(hf_ctx *ctx, const float *pos, int64_t n, const hf_params *p, float *density,
+                          int32_t *l0_id, int32_t *halo_id, hf_halo *halos, int64_t halos_cap,
+                          int64_t *n_halos, int32_t *members, int64_t *halo_start, void *stream) {
+    if (!ctx) return HF_ERR_INVALID;
+    Lane *c = &ctx->main;
+    c->err.clear();
+    if (!members || !halo_start) return fail(c, HF_ERR_INVALID, "members / halo_start is NULL");
+    if (halos_cap < 0 || (halos_cap > 0 && !halos)) return fail(c, HF_ERR_INVALID, "bad halos / halos_cap");
+    if (n < 0) return fail(c, HF_ERR_INVALID, "n is negative");
+    const OneBox ob = one_box(n, halos_cap);
+    GroupOut go;
+    go.members = members;
+    go.halo_start = halo_start;
+    int64_t nh = 0;
+    const hf_status st = find_boxes(c, ob.set(p, halos), pos, density, l0_id, halo_id, &nh, (hipStream_t)stream,
+                                    nullptr, go);
+    if (n_halos) *n_halos = nh;
+    return st;
 }
 
 hf_status hf_find_noalloc(hf_ctx *ctx, const float *pos, int64_t n, const hf_params *p, float *density,

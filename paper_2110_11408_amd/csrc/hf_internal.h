@@ -11,6 +11,7 @@ namespace hf {
 
 constexpr int kBlock = 256;
 constexpr int kDenseMin = 8;   // a cell with at least this many particles is "dense"
+constexpr int kRadBins = 2048; // radial bins of the threshold-radius search by bins
 
 // Constants of one periodic box, computed on the host (see hf_derived).
 struct Geo {
@@ -33,6 +34,7 @@ struct Geo {
     double dl0;            // L0 density threshold
     double floor_nuc;      // nucleation floor
     double K, K2, A6, C3;  // R^3 = i/K; alpha^6; c_Roche^3
+    double rbin;           // radial bin width of the threshold-radius search by bins
     int n_l1_min;
     float particle_mass;
     // the box's place among the boxes of one call
@@ -216,6 +218,8 @@ struct Work {
     int32_t *subarg;
     int32_t *hardlist;                                 // candidate tests left after stage 1
     int64_t nchunks, ndcells, nsparse, nhard;
+    int ncu;                         // compute units (grids of the persistent kernels)
+    bool radius_bins;                // R_L1 by radial bins instead of the whole-group histogram
     // density / FoF / groups (sorted order unless noted)
     float *dens_s;
     int32_t *parent, *minorig, *gkey, *gid_of, *owner;
@@ -304,5 +308,10 @@ void launch_output_flags(int64_t n, int64_t NC, const Boxes &bx, Work &w, hipStr
 // receives every box's row count.
 void launch_output(int64_t n, int64_t NC, const Boxes &bx, Work &w, int32_t *halo_id, int32_t *l0_out,
                    int64_t *box_rows, hipStream_t s);
+// One box after launch_output: its n particles by table row of their halo
+// (nrows rows, then the particles of no halo), ascending index within a row,
+// into members [n]; halo_start [nrows + 1] receives each row's first position.
+void launch_group_order(int64_t n, int64_t nrows, const int32_t *halo_id, Work &w, int32_t *members,
+                        int64_t *halo_start, hipStream_t s);
 
 }  // namespace hf

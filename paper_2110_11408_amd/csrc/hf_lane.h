@@ -32,6 +32,8 @@ struct Budget {
 
 struct Lane {
     int device = 0;
+    int ncu = 0;                   // compute units of the device (persistent grids)
+    bool radius_bins = false;      // R_L1 by radial bins (the owning context's option)
     Budget *budget = nullptr;      // the owning context's, or null (no accounting)
     void *arena = nullptr;
     size_t arena_bytes = 0;
@@ -93,9 +95,22 @@ size_t boxes_arena_bytes(const BoxSet &bs, int64_t *n_total, int64_t *ncell_tota
 
 }  // namespace hf
 
+namespace hf {
+// A tuned setting of hf_find_batch for batches of n_boxes boxes and about
+// `total` particles: the number of fused groups and its measured time.
+struct TuneEntry {
+    int32_t n_boxes;
+    int64_t total;
+    int32_t groups;
+    float ms;
+};
+}  // namespace hf
+
 struct hf_ctx {
     hf::Budget budget;
     hf::Lane main;
     void *scratch = nullptr;  // device address of the static scratch on main.device
     std::vector<std::unique_ptr<hf::Lane>> pool;  // lanes of hf_find_batch, created on demand
+    std::vector<hf::TuneEntry> tuning;            // hf_tune_batch / hf_load_tuning
+    bool radius_bins = false;                     // HF_OPT_RADIUS_SEARCH = HF_RADIUS_BINS
 };

@@ -11,8 +11,11 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
+#include <fstream>
 #include <condition_variable>
 #include <deque>
+#include <stdio.h>
 #include <string.h>
 #include <thread>
 #include <unordered_map>
@@ -50,6 +53,75 @@ hf_status batch_fail(hf_ctx *c, hf_status st, const std::string &msg) {
     return st;
 }
 
+// The tuned group count for a batch of n_boxes boxes and `total` particles:
+// the entry with the same box count whose particle total is nearest, within
+// 25 % of it; 0 when there is none.
+int tuned_groups(const hf_ctx *c, int32_t n_boxes, int64_t total) {
+    int best = 0;
+    double best_rel = 0.25;
+    for (const auto &e : c->tuning) {
+        if (e.n_boxes != n_boxes || e.total <= 0) continue;
+        const double rel = std::fabs((double)total - (double)e.total) / (double)e.total;
+        if (rel <= best_rel) {
+            best_rel = rel;
+            best = e.groups;
+        }
+    }
+    return best;
+}
+
+// Group count hf_find_batch uses for an explicit n_lanes (> 0) or, for
+// n_lanes <= 0, the tuned one, else the default; at most kMaxLanes and
+// n_boxes.
+int batch_groups(const hf_ctx *c, int32_t n_boxes, int64_t total, int32_t n_lanes) {
+    int k = n_lanes > 0 ? n_lanes : tuned_groups(c, n_boxes, total);
+    if (k <= 0) k = kDefaultBatchGroups;
+    return std::max(1, std::min(std::min(k, kMaxLanes), (int)n_boxes));
+}
+
+// The device's architecture name without its feature suffixes ("gfx950").
+std::string arch_name(int device) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t colon = a.find(':');
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+// One line of a tuning table:
+//   hf-tune v1 <arch> n_boxes=<b> total=<n> groups=<g> ms=<t>
+// Lines of another architecture or format, and lines starting with '#', are
+// skipped.
+bool parse_tune_line(const std::string &line, const std::string &arch, hf::TuneEntry *e) {
+    char a[64] = {0};
+    int nb = 0, g = 0;
+    long long tot = 0;
+    float ms = 0.0f;
+    if (line.empty() || line[0] == '#') return false;
+    if (sscanf(line.c_str(), "hf-tune v1 %63s n_boxes=%d total=%lld groups=%d ms=%f", a, &nb, &tot, &g, &ms) != 5)
+        return false;
+    if (arch != a || nb <= 0 || tot < 0 || g <= 0 || g > kMaxLanes) return false;
+    *e = hf::TuneEntry{nb, (int64_t)tot, g, ms};
+    return true;
+}
+
+std::string tune_line(const std::string &arch, const hf::TuneEntry &e) {
+    char buf[256];
+    snprintf(buf, sizeof buf, "hf-tune v1 %s n_boxes=%d total=%lld groups=%d ms=%.3f", arch.c_str(), e.n_boxes,
+             (long long)e.total, e.groups, e.ms);
+    return buf;
+}
+
+// Keep e in the context's table (replacing an entry of the same shape).
+void remember(hf_ctx *c, const hf::TuneEntry &e) {
+    for (auto &x : c->tuning)
+        if (x.n_boxes == e.n_boxes && x.total == e.total) {
+            x = e;
+            return;
+        }
+    c->tuning.push_back(e);
+}
+
 }  // namespace
 
 extern "C" {
@@ -80,8 +152,7 @@ hf_status hf_find_batch(hf_ctx *ctx, int32_t n_boxes, const int64_t *box_offsets
     // which run at once on k lanes so that one group's waits for its counts
     // overlap with another's kernels.  A group is also closed before its cell
     // count would pass 2^31 (cell numbers of a pass stay 32-bit).
-    const int k = std::max(1, std::min(std::min(n_lanes > 0 ? n_lanes : kDefaultBatchGroups, kMaxLanes),
-                                       (int)n_boxes));
+    const int k = batch_groups(ctx, n_boxes, total, n_lanes);
     std::vector<int32_t> cut{0};
     {
         int64_t cells = 0;
@@ -110,6 +181,7 @@ hf_status hf_find_batch(hf_ctx *ctx, int32_t n_boxes, const int64_t *box_offsets
     while ((int)ctx->pool.size() < lanes) {
         auto L = std::make_unique<hf::Lane>();
         L->budget = &ctx->budget;
+        L->radius_bins = ctx->radius_bins;
         if (hf::lane_init(L.get(), ctx->main.device, true) != HF_OK) {
             hf::lane_destroy(L.get());
             return batch_fail(ctx, HF_ERR_DEVICE, "could not create a batch lane");
@@ -162,6 +234,91 @@ hf_status hf_find_batch(hf_ctx *ctx, int32_t n_boxes, const int64_t *box_offsets
     for (int q = 0; q < ngroups; q++)
         if (st[q] == HF_ERR_CAPACITY)
             return batch_fail(ctx, HF_ERR_CAPACITY, msg[q] + " (n_halos holds the required counts)");
+    return HF_OK;
+}
+
+hf_status hf_batch_groups(const hf_ctx *ctx, int32_t n_boxes, int64_t total, int32_t n_lanes, int32_t *groups) {
+    if (!ctx || !groups || n_boxes <= 0 || total < 0) return HF_ERR_INVALID;
+    *groups = batch_groups(ctx, n_boxes, total, n_lanes);
+    return HF_OK;
+}
+
+hf_status hf_tune_batch(hf_ctx *ctx, int32_t n_boxes, const int64_t *box_offsets, const float *pos,
+                        const hf_params *params, float *density, int32_t *l0_id, int32_t *halo_id,
+                        hf_halo *halos, const int64_t *halo_offsets, int64_t *n_halos, int32_t max_groups,
+                        int32_t reps, const char *table_path, int32_t *best_groups, float *best_ms,
+                        void *stream) {
+    if (!ctx) return HF_ERR_INVALID;
+    if (n_boxes <= 0 || !box_offsets) return batch_fail(ctx, HF_ERR_INVALID, "nothing to tune: n_boxes <= 0");
+    if (max_groups <= 0 || reps <= 0) return batch_fail(ctx, HF_ERR_INVALID, "max_groups and reps must be > 0");
+    const int gmax = std::min(std::min((int)max_groups, kMaxLanes), (int)n_boxes);
+    const int64_t total = box_offsets[n_boxes];
+    hf::TuneEntry best{n_boxes, total, 0, 0.0f};
+    for (int g = 1; g <= gmax; g++) {
+        // one untimed call (it also sizes the lanes' arenas), then the fastest of reps
+        hf_status st = hf_find_batch(ctx, n_boxes, box_offsets, pos, params, density, l0_id, halo_id, halos,
+                                     halo_offsets, n_halos, g, stream);
+        if (st != HF_OK) return st;
+        double ms = 0.0;
+        for (int r = 0; r < reps; r++) {
+            const auto t0 = std::chrono::steady_clock::now();
+            st = hf_find_batch(ctx, n_boxes, box_offsets, pos, params, density, l0_id, halo_id, halos, halo_offsets,
+                               n_halos, g, stream);
+            const auto t1 = std::chrono::steady_clock::now();
+            if (st != HF_OK) return st;
+            const double t = std::chrono::duration<double, std::milli>(t1 - t0).count();
+            if (r == 0 || t < ms) ms = t;
+        }
+        // a larger count must be faster by more than 2 % to be taken
+        if (best.groups == 0 || ms < 0.98 * best.ms) {
+            best.groups = g;
+            best.ms = (float)ms;
+        }
+    }
+    remember(ctx, best);
+    if (best_groups) *best_groups = best.groups;
+    if (best_ms) *best_ms = best.ms;
+    if (table_path && table_path[0]) {
+        // rewrite the table with this shape's line replaced (or appended)
+        const std::string arch = arch_name(ctx->main.device);
+        std::vector<std::string> lines;
+        {
+            std::ifstream in(table_path);
+            std::string line;
+            hf::TuneEntry e;
+            while (std::getline(in, line)) {
+                if (parse_tune_line(line, arch, &e) && e.n_boxes == best.n_boxes && e.total == best.total) continue;
+                lines.push_back(line);
+            }
+        }
+        if (lines.empty()) lines.push_back("# hf_find_batch tuning: fused group count per batch shape");
+        lines.push_back(tune_line(arch, best));
+        const std::string tmp = std::string(table_path) + ".tmp";
+        {
+            std::ofstream out(tmp, std::ios::trunc);
+            for (const auto &l : lines) out << l << "\n";
+            if (!out) return batch_fail(ctx, HF_ERR_INVALID, std::string("cannot write ") + tmp);
+        }
+        if (rename(tmp.c_str(), table_path) != 0)
+            return batch_fail(ctx, HF_ERR_INVALID, std::string("cannot replace ") + table_path);
+    }
+    return HF_OK;
+}
+
+hf_status hf_load_tuning(hf_ctx *ctx, const char *table_path, int32_t *n_entries) {
+    if (!ctx || !table_path) return HF_ERR_INVALID;
+    std::ifstream in(table_path);
+    if (!in) return batch_fail(ctx, HF_ERR_INVALID, std::string("cannot read ") + table_path);
+    const std::string arch = arch_name(ctx->main.device);
+    std::string line;
+    hf::TuneEntry e;
+    int32_t k = 0;
+    while (std::getline(in, line))
+        if (parse_tune_line(line, arch, &e)) {
+            remember(ctx, e);
+            k++;
+        }
+    if (n_entries) *n_entries = k;
     return HF_OK;
 }
 

@@ -129,6 +129,16 @@ def test_batch_and_server_reject_bad_arguments(lib):
     st = lib.hf_find_batch(None, 1, offs, None, ctypes.byref(p), None, None, None, None, offs,
                            None, 0, None)
     assert st == _lib.HF_ERR_INVALID
+    g = ctypes.c_int32(0)
+    assert lib.hf_tune_batch(None, 1, offs, None, ctypes.byref(p), None, None, None, None, offs, None,
+                             2, 1, None, ctypes.byref(g), None, None) == _lib.HF_ERR_INVALID
+    assert lib.hf_load_tuning(None, b"/nonexistent", None) == _lib.HF_ERR_INVALID
+    assert lib.hf_batch_groups(None, 1, 10, 0, ctypes.byref(g)) == _lib.HF_ERR_INVALID
+    v = ctypes.c_int64(0)
+    assert lib.hf_set_option(None, _lib.HF_OPT_RADIUS_SEARCH, _lib.HF_RADIUS_BINS) == _lib.HF_ERR_INVALID
+    assert lib.hf_get_option(None, _lib.HF_OPT_RADIUS_SEARCH, ctypes.byref(v)) == _lib.HF_ERR_INVALID
+    assert lib.hf_find_grouped(None, None, 0, ctypes.byref(p), None, None, None, None, 0, None, None, None,
+                               None) == _lib.HF_ERR_INVALID
     h = ctypes.c_void_p()
     # slot count outside 1..16 and a zero budget are argument errors, checked first
     assert lib.hf_server_create(ctypes.byref(h), 0, 0, 1 << 30) == _lib.HF_ERR_INVALID

@@ -226,3 +226,47 @@ def test_server_error_stays_with_its_request(boxes, singles):
         _server_check(srv.wait(t2), singles[2])
     finally:
         srv.close()
+
+
+def test_tune_batch_table_roundtrip(ctx, boxes, singles, tmp_path):
+    import torch
+    from paper_2110_11408_amd.api import Context
+    sub = boxes[:BIG]
+    pos = np.concatenate([b[0] for b in sub]).astype(np.float32)
+    offs = np.concatenate([[0], np.cumsum([len(b[0]) for b in sub])])
+    params = [_params(L, len(p)) for p, L in sub]
+    total = int(offs[-1])
+    table = tmp_path / "tune.txt"
+    _say(f"[gpu] hf_tune_batch boxes={len(sub)} total={total}")
+    best, ms, out = ctx.tune_batch(torch.from_numpy(pos).cuda(), offs, params, max_groups=3, reps=1,
+                                   table_path=str(table))
+    assert 1 <= best <= 3 and ms > 0.0
+    dens, l0, hid = (out[k].cpu().numpy() for k in ("density", "l0_id", "halo_id"))
+    for b, single in enumerate(singles[:BIG]):
+        a, e = offs[b], offs[b + 1]
+        if single is not None:
+            _assert_box_equal(single, dens[a:e], l0[a:e], hid[a:e], out["halos"][b].cpu().numpy())
+    lines = [ln for ln in table.read_text().splitlines() if ln.startswith("hf-tune v1 ")]
+    assert len(lines) == 1
+    assert f" n_boxes={len(sub)} total={total} groups={best} " in lines[0]
+    # the tuned count serves batches of the same box count and a total within 25 %
+    assert ctx.batch_groups(len(sub), total) == best
+    assert ctx.batch_groups(len(sub), int(total * 1.2)) == best
+    assert ctx.batch_groups(len(sub), total * 2) == 1
+    assert ctx.batch_groups(len(sub) + 1, total) == 1
+    assert ctx.batch_groups(len(sub), total, n_lanes=2) == 2
+    # tuning again rewrites the shape's line instead of adding one; lines of
+    # another architecture and comments are skipped on loading
+    ctx.tune_batch(torch.from_numpy(pos).cuda(), offs, params, max_groups=2, reps=1, table_path=str(table))
+    with open(table, "a") as f:
+        f.write(f"hf-tune v1 gfx000 n_boxes={len(sub)} total={total} groups=4 ms=1.000\n# note\n")
+    assert sum(ln.startswith("hf-tune v1 ") and "gfx000" not in ln
+               for ln in table.read_text().splitlines()) == 1
+    fresh = Context(0)
+    assert fresh.batch_groups(len(sub), total) == 1
+    assert fresh.load_tuning(str(table)) == 1
+    tuned = ctx.batch_groups(len(sub), total)
+    assert fresh.batch_groups(len(sub), total) == tuned
+    offs2, out2 = _run_batch(fresh, sub)
+    np.testing.assert_array_equal(out2["halo_id"].cpu().numpy(), hid)
+    np.testing.assert_array_equal(out2["density"].cpu().numpy(), dens)
