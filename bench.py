@@ -281,13 +281,15 @@ def batched(ctx, boxes, args, np, torch, _lib):
     return res
 
 
-def single_box(ctx, name, steps, warmup, np, torch, _lib, synth, halo_stats=False):
-    """One box found by one hf_find call per step, with its stage rooflines."""
+def single_box(ctx, name, steps, warmup, np, torch, _lib, synth, halo_stats=False, count=True):
+    """One box found by one hf_find call per step, with its stage rooflines
+    (count=False: no pair count and no rooflines, so that a counter run sees
+    only the steps' dispatches)."""
     pos, L, _ = synth.named_box(name)
     n = len(pos)
     pos_d = torch.from_numpy(pos).cuda()
     p = _lib.default_params(box=L)
-    pairs = ctx.count_pairs(pos_d, p)
+    pairs = ctx.count_pairs(pos_d, p) if count else 0
     cap = max(1024, n // 64)
     for _ in range(warmup):
         ctx.find(pos_d, p, halos_cap=cap)
@@ -302,7 +304,7 @@ def single_box(ctx, name, steps, warmup, np, torch, _lib, synth, halo_stats=Fals
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     stages = {k[3:]: acc[k] / steps for k in STAGE_KEYS}
-    roof, lines = rooflines(name, n, st["n_cells"], pairs, stages)
+    roof, lines = rooflines(name, n, st["n_cells"], pairs, stages) if count else (None, None)
     res = {"workload": name, "description": WORKLOADS[name], "n_particles": n,
            "value": n * steps / wall, "unit": "particles/s", "ms_per_step": wall * 1e3 / steps,
            "steps": steps, "roofline": roof, "stage_rooflines": lines, "stages_ms": stages,
@@ -527,7 +529,7 @@ def main():
         res["batched"] = b
     else:
         s = single_box(ctx, args.workload, args.steps, args.warmup, np, torch, _lib, synth,
-                       halo_stats=not args.only_steps)
+                       halo_stats=not args.only_steps, count=not args.only_steps)
         res.update({"value": s.pop("value"), "ms_per_step": s.pop("ms_per_step"), "roofline": s.pop("roofline"),
                     "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
                                "n_particles": s["n_particles"], "path": "hf_find (one box per call)"}})
