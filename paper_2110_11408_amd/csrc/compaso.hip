@@ -289,18 +289,13 @@ __device__ __forceinline__ int block_min(int v, int *s_min) {
 constexpr int kWaveHist = 1024;   // groups below this size run one per wavefront
 constexpr int kWaveNuc = 64;      // ... when they have at most this many candidates
 
-// Next item of a device work queue: *head counts the items taken so far
-// (zero when the call began); every caller of one wavefront gets the same
-// item.
-__device__ __forceinline__ uint32_t wave_pop(uint32_t *head) {
-    uint32_t q = 0;
-    if ((threadIdx.x & 63) == 0) q = atomicAdd(head, 1u);
-    return (uint32_t)__builtin_amdgcn_readfirstlane(__shfl(q, 0, 64));
-}
-
 // Groups with candidates (all boxes, largest first), one wavefront at a time
-// each: a persistent grid whose wavefronts take the next group from the list
-// until it is exhausted.  Groups of fewer than kWaveHist particles with at
+// each: a persistent grid of W wavefronts in which wavefront w takes groups
+// w, w + W, w + 2W, ... of the list (its length read on the device), so that
+// every wavefront gets one group of each size tier.  (A shared counter that
+// every wavefront increments per group serialises on its one address: tens of
+// thousands of groups cost more in atomics than in work.)  Groups of fewer
+// than kWaveHist particles with at
 // most kWaveNuc candidates run here: the same walk as k_accept with the
 // histogram, the accepted nuclei and their positions in the wavefront's LDS
 // and wave-level scans instead of workgroup barriers, so that many small
@@ -308,8 +303,8 @@ __device__ __forceinline__ uint32_t wave_pop(uint32_t *head) {
 // (fewer than kHistMid particles) or big_list, with their counts in
 // *mid_count and *big_count, for k_accept (route_all: every group, when R is
 // searched by radial bins).
-__global__ __launch_bounds__(kBlock) void k_accept_small(const uint32_t *__restrict__ ngc_p,
-                                                         uint32_t *__restrict__ head, bool route_all, Boxes bx,
+__global__ __launch_bounds__(kBlock) void k_accept_small(const uint32_t *__restrict__ ngc_p, bool route_all,
+                                                         Boxes bx,
                                                          const int32_t *__restrict__ glist,
                                                          const int32_t *__restrict__ g_start,
                                                          const int32_t *__restrict__ g_size,
@@ -331,9 +326,10 @@ __global__ __launch_bounds__(kBlock) void k_accept_small(const uint32_t *__restr
     __shared__ int32_t s_hi[kBlock / 64][kWaveNuc];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const uint32_t ngc = *ngc_p;
+    const uint32_t ngc = __builtin_amdgcn_readfirstlane(*ngc_p);
+    const uint32_t nw = gridDim.x * (kBlock / 64);
     uint32_t *hist = s_hist[wave];
-    for (uint32_t q = wave_pop(head); q < ngc; q = wave_pop(head)) {
+    for (uint32_t q = blockIdx.x * (kBlock / 64) + (uint32_t)wave; q < ngc; q += nw) {
         const int gi = glist[q];
         const int64_t start = g_start[gi];
         const int64_t m = g_size[gi];
@@ -894,21 +890,21 @@ void launch_accept(int64_t n, int64_t G, int64_t NC, int64_t M, const Boxes &bx,
     // of kWaveHist particles or more, and NC / (kWaveNuc + 1) with more than
     // kWaveNuc candidates) and large ones (at most M / kHistMid), whose list
     // starts halfway through the array.  The first kernel is a persistent
-    // grid of a few workgroups per compute unit whose wavefronts take groups
-    // from the list (queue head counters[13]); the others run one workgroup
-    // per listed group.  All these words are zero since the call began.
+    // grid (as many wavefronts as fit on the chip at once) striding over the
+    // list; the others run one workgroup per listed group.  The counts are
+    // zero since the call began.
     const int64_t bound = G < NC ? G : NC;
     if (bound <= 0) return;
     int32_t *mid_list = reinterpret_cast<int32_t *>(w.f_chunk);
     int32_t *big_list = reinterpret_cast<int32_t *>(w.f_chunk) + n / 2;
     uint32_t *mid_count = reinterpret_cast<uint32_t *>(w.counters + 9);
     uint32_t *big_count = reinterpret_cast<uint32_t *>(w.counters + 11);
-    uint32_t *heads = reinterpret_cast<uint32_t *>(w.counters + 13);
     const int64_t ncu = w.ncu > 0 ? w.ncu : 1;
     auto cap = [](int64_t a, int64_t b) { return (unsigned)(a < b ? a : b); };
     const bool bins = w.radius_bins;
-    hipLaunchKernelGGL(k_accept_small, dim3(cap((bound + kBlock / 64 - 1) / (kBlock / 64), 8 * ncu)), dim3(kBlock),
-                       0, s, w.gcidx + G, heads, bins, bx, w.glist, w.g_start, w.g_size, w.gcoff, w.cand_sorted,
+    // six wavefronts per SIMD (its register use): 6 workgroups of 4 per CU
+    hipLaunchKernelGGL(k_accept_small, dim3(cap((bound + kBlock / 64 - 1) / (kBlock / 64), 6 * ncu)), dim3(kBlock),
+                       0, s, w.gcidx + G, bins, bx, w.glist, w.g_start, w.g_size, w.gcoff, w.cand_sorted,
                        w.mem, w.spos, w.h_nuc, w.h_ienc, w.h_gid, w.g_nh, mid_list, mid_count, big_list, big_count);
     // with radial bins every group is listed: at most bound medium groups
     const int64_t nmid = bins ? bound : M / kWaveHist + NC / (kWaveNuc + 1) + 1;
