@@ -16,11 +16,12 @@
 //
 // Particles of sparse cells have few neighbours, often near r = b where the
 // weights are small, so the tolerance of their density is only about 1e-6 in
-// the weight sum: every pair that involves one of them is evaluated in FP64
-// from the original float positions (minimum-image difference, 1 - d^2/b^2),
-// by one thread per sparse particle for its sparse neighbour cells, and by the
-// dense chunks for the sparse particles around them (one lane per sparse
-// particle, summing over the chunk's particles, added in fixed point).  The
+// the weight sum: the density of a sparse-cell particle is a sum of FP64
+// weights from the original float positions (1 - d^2/b^2, the periodic image
+// of a neighbour cell taken once per cell), by one thread per sparse particle
+// for its sparse neighbour cells, and by the dense chunks for the sparse
+// particles around them (one lane per sparse particle, summing over the
+// chunk's particles, added in fixed point).  The
 // rank-4 form has terms up to about 6 in magnitude, so its weights are only
 // good to a few 1e-7 each; that suffices for dense-cell particles, whose sums
 // have many terms.
@@ -32,24 +33,34 @@ namespace hf {
 
 namespace {
 
-// Weight 1 - d^2/b^2 (0 beyond b) of particle j about particle i in FP64, from
-// the float positions with the minimum-image fold of each axis.
-__device__ __forceinline__ double weight64(const float4 &pi, const float4 &pj, const Geo &g) {
-    double dx = (double)pj.x - (double)pi.x;
-    double dy = (double)pj.y - (double)pi.y;
-    double dz = (double)pj.z - (double)pi.z;
-    if (dx > g.half) dx -= g.L; else if (dx < -g.half) dx += g.L;
-    if (dy > g.half) dy -= g.L; else if (dy < -g.half) dy += g.L;
-    if (dz > g.half) dz -= g.L; else if (dz < -g.half) dz += g.L;
-    const double t = 1.0 - (dx * dx + dy * dy + dz * dz) * g.inv_b2;
-    return t > 0.0 ? t : 0.0;
+// FP64 position of particle p as seen from a particle whose neighbour cell it
+// is through stencil offset (ox, oy, oz) from cell (cx, cy, cz): the periodic
+// image across a box face is taken by adding or subtracting L once per cell
+// (a stencil cell that wraps), so no pair needs a minimum-image fold.  Where
+// a weight is nonzero (r < b <= the cell side < L/2) this is the minimum
+// image.
+struct Pos64 {
+    double x, y, z;
+};
+__device__ __forceinline__ double image_shift(int c, int o, int nc, double L) {
+    return c + o < 0 ? -L : (c + o >= nc ? L : 0.0);
 }
 
-// Accumulate one neighbour cell [a, b) for particle i (the sparse-cell kernel,
-// one particle per lane; its own cell includes i, whose weight is exactly 1).
+// Weight 1 - d^2/b^2 (0 beyond b) of the pair (a, q) in FP64, with q a float
+// position and a an FP64 position in q's frame.
+__device__ __forceinline__ double weight64(const Pos64 &a, const float4 &q, double inv_b2) {
+    const double dx = (double)q.x - a.x, dy = (double)q.y - a.y, dz = (double)q.z - a.z;
+    const double t = 1.0 - (dx * dx + dy * dy + dz * dz) * inv_b2;
+    return fmax(t, 0.0);
+}
+
+// Accumulate one neighbour cell [a, b) for particle i at FP64 position pi in
+// that cell's frame (the sparse-cell kernel, one particle per lane; its own
+// cell includes i, whose weight is exactly 1).  Loading the positions of a
+// cell four at a time was slower: the kernel is held by occupancy.
 __device__ __forceinline__ void accum_range(const float4 *__restrict__ spos, uint32_t a, uint32_t b,
-                                            const float4 &pi, const Geo &g, double &acc) {
-    for (uint32_t j = a; j < b; j++) acc += weight64(pi, spos[j], g);
+                                            const Pos64 &pi, double inv_b2, double &acc) {
+    for (uint32_t j = a; j < b; j++) acc += weight64(pi, spos[j], inv_b2);
 }
 
 // Dense-neighbour contributions of sparse particles are added in fixed point
@@ -332,6 +343,7 @@ __device__ __forceinline__ void density_chunk(const Geo &g, uint32_t h, uint32_t
     for (uint32_t p0 = 0; p0 < ntot; p0 += 64) {
         const uint32_t q = p0 + (uint32_t)lane;  // this lane's column number
         uint32_t js = h, dst = 0;                 // its particle and sparse ordinal
+        int kc = 13;                              // and its stencil cell
         uint32_t pre = 0;
         for (uint64_t m = spm; m; m &= m - 1) {
             const int k = __builtin_ctzll(m);
@@ -340,12 +352,17 @@ __device__ __forceinline__ void density_chunk(const Geo &g, uint32_t h, uint32_t
             if (q >= pre && q < pre + cnt) {
                 js = a + (q - pre);
                 dst = (uint32_t)__builtin_amdgcn_readlane((int)sb, k) + (q - pre);
+                kc = k;
             }
             pre += cnt;
         }
+        // the sparse particle's image in the chunk's frame
         const float4 pj = spos[js];
+        const Pos64 pjm{(double)pj.x + image_shift(cx, kc % 3 - 1, g.nc, g.L),
+                        (double)pj.y + image_shift(cy, (kc / 3) % 3 - 1, g.nc, g.L),
+                        (double)pj.z + image_shift(cz, kc / 9 - 1, g.nc, g.L)};
         double v = 0.0;
-        for (uint32_t r = h; r < end; r++) v += weight64(spos[r], pj, g);
+        for (uint32_t r = h; r < end; r++) v += weight64(pjm, spos[r], g.inv_b2);
         if (q < ntot && v > 0.0)
             atomicAdd(reinterpret_cast<unsigned long long *>(&dfx[dst]),
                       (unsigned long long)__double2ll_rn(v * kFixScale));
@@ -459,7 +476,11 @@ __global__ __launch_bounds__(kBlock) void k_density_sparse(int64_t nsparse, Boxe
                 // above the rounding of the local coordinates) weighs nothing
                 const float gx = ox < 0 ? li.x : (ox > 0 ? g.cellb - li.x : 0.0f);
                 if (gx * gx + gy * gy + gz * gz >= 1.0f + 1e-5f) continue;
-                accum_range(spos, ra[r], rb[r], pi, g, acc);
+                // i's position in this cell's frame
+                const Pos64 pim{(double)pi.x - image_shift(cx, ox, nc, g.L),
+                                (double)pi.y - image_shift(cy, oy, nc, g.L),
+                                (double)pi.z - image_shift(cz, oz, nc, g.L)};
+                accum_range(spos, ra[r], rb[r], pim, g.inv_b2, acc);
             }
         }
     }

@@ -177,6 +177,15 @@ struct Carver {
 };
 
 
+// Entries of the particle -> box table of a call over nbox boxes: a power of
+// two, at least 4 per box and 4096, at most 2^20 (1 when there is one box).
+int64_t box_table_len(int nbox) {
+    if (nbox <= 1) return 1;
+    int64_t t = 4096;
+    while (t < 4 * (int64_t)nbox && t < ((int64_t)1 << 20)) t <<= 1;
+    return t;
+}
+
 size_t carve(char *base, int64_t n, int64_t ncell, int nsub, int64_t rhl, int nbox, bool extra, Work *w) {
     Carver c{base};
     int64_t n1 = n + 1;
@@ -241,6 +250,7 @@ size_t carve(char *base, int64_t n, int64_t ncell, int nsub, int64_t rhl, int nb
     w->geo = c.take<Geo>(nbox);
     w->geo2 = extra ? c.take<Geo>(nbox) : nullptr;
     w->base = c.take<uint32_t>(nbox + 1);
+    w->btab = c.take<int32_t>(box_table_len(nbox));
     w->box_rows = c.take<int64_t>(nbox);
     w->gcom = extra ? c.take<double>(6 * n1) : nullptr;
     w->ordk = extra ? c.take<int32_t>(n1) : nullptr;
@@ -257,6 +267,8 @@ struct Plan {
     int nsub_max = 1;
     std::vector<Geo> geo;
     std::vector<uint32_t> base;
+    std::vector<int32_t> btab;  // particle -> box table (more than one box)
+    int bshift = 0;
 };
 
 std::string box_prefix(const Plan *pl, int b) {
@@ -315,6 +327,21 @@ hf_status plan_boxes(Lane *c, const hf::BoxSet &bs, Plan *pl) {
     }
     pl->n = bs.offsets[bs.nbox];
     pl->base[bs.nbox] = (uint32_t)pl->n;
+    if (pl->nbox > 1) {
+        // bucket k covers particles [k << shift, (k + 1) << shift); its entry
+        // is the box of its first particle (the last box for buckets past n)
+        const int64_t t = box_table_len(pl->nbox);
+        int sh = 0;
+        while ((t << sh) < pl->n) sh++;
+        pl->bshift = sh;
+        pl->btab.assign(t, 0);
+        int b = 0;
+        for (int64_t k = 0; k < t; k++) {
+            const int64_t first = k << sh;
+            while (b + 1 < pl->nbox && (int64_t)pl->base[b + 1] <= first) b++;
+            pl->btab[k] = b;
+        }
+    }
     // cells with nothing to bin still end the offset grid: at least one
     if (pl->ncell == 0) pl->ncell = 1;
     return HF_OK;
@@ -388,7 +415,9 @@ hf_status prepare(Lane *c, const Plan &pl, Work *w, bool extra, const hf::FixedA
     c->stats = hf_stats{};
     c->stats.n_cells = pl.ncell;
     // the box tables go up and the per-box rows come back through it
-    return ensure_stage(c, pl.nbox * (2 * sizeof(Geo) + sizeof(uint32_t) + sizeof(int64_t)) + 4096, fx == nullptr);
+    return ensure_stage(c, pl.nbox * (2 * sizeof(Geo) + sizeof(uint32_t) + sizeof(int64_t)) +
+                               pl.btab.size() * sizeof(int32_t) + 4096,
+                        fx == nullptr);
 }
 
 // Device words read back in one dispatch and one wait (the lane's pinned host
@@ -529,7 +558,12 @@ hf_status begin(Lane *c, const Plan &pl, const float *pos, hf::Boxes *bx, Work *
     HIP_OK(c, hipMemcpyAsync(w->geo, stg, sizeof(Geo) * pl.nbox, hipMemcpyHostToDevice, s));
     HIP_OK(c, hipMemcpyAsync(w->base, stg + sizeof(Geo) * pl.nbox, sizeof(uint32_t) * (pl.nbox + 1),
                              hipMemcpyHostToDevice, s));
-    *bx = hf::Boxes{w->geo, w->base, pl.nbox, pl.nsub_max};
+    if (!pl.btab.empty()) {
+        char *tb = stg + sizeof(Geo) * pl.nbox + sizeof(uint32_t) * (pl.nbox + 1);
+        memcpy(tb, pl.btab.data(), sizeof(int32_t) * pl.btab.size());
+        HIP_OK(c, hipMemcpyAsync(w->btab, tb, sizeof(int32_t) * pl.btab.size(), hipMemcpyHostToDevice, s));
+    }
+    *bx = hf::Boxes{w->geo, w->base, pl.nbox, pl.nsub_max, w->btab, pl.bshift};
     hf::fill_i32(w->counters, 0, 16, s);
     hf::fill_i32(w->err, 0, 1, s);
     hf::fill_i32(w->err + 1, 0x7fffffff, 1, s);
@@ -965,7 +999,7 @@ hf_status hf_halo_stats(hf_ctx *ctx, const float *pos, const float *density, con
     char *stg = reinterpret_cast<char *>(c->stage) + sizeof(Geo) * 2 + 256;
     memcpy(stg, &g2, sizeof(Geo));
     HIP_OK(c, hipMemcpyAsync(w.geo2, stg, sizeof(Geo), hipMemcpyHostToDevice, s));
-    const hf::Boxes bx2{w.geo2, w.base, 1, pl.nsub_max};
+    const hf::Boxes bx2{w.geo2, w.base, 1, pl.nsub_max, nullptr, 0};
     hf::launch_keys_from_labels(halo_id, density, n, bx, w, s);  // also gathers the densities
     HIP_OK(c, hipEventRecord(c->ev[2], s));
     HIP_OK(c, hipEventRecord(c->ev[3], s));

@@ -57,17 +57,19 @@ struct Boxes {
     int nbox;
     int nsub_max;          // largest ksub^3: the sort-key stride of a cell and the row
                            // length - 1 of the dense-cell sub-tables
+    const int32_t *btab;   // device (nbox > 1): btab[k] = box of particle k << bshift
+    int bshift;
 };
 
-// Box of particle i (input or sorted order): binary search of base (no load
-// when there is one box).
+// Box of particle i (input or sorted order): the box of the table bucket that
+// holds i, then forward over the box starts inside the bucket (a step or two:
+// the table has several buckets per box on average).  No load when there is
+// one box.
 __device__ __forceinline__ int box_of(const Boxes &bx, uint32_t i) {
-    int lo = 0, hi = bx.nbox - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (bx.base[mid] <= i) lo = mid; else hi = mid - 1;
-    }
-    return lo;
+    if (bx.nbox <= 1) return 0;
+    int b = bx.btab[i >> bx.bshift];
+    while (b + 1 < bx.nbox && bx.base[b + 1] <= i) b++;
+    return b;
 }
 
 // ---------------------------------------------------------------- predicates
@@ -240,6 +242,7 @@ struct Work {
     int32_t *err;                    // [0] error bits, [1] smallest box with an error
     Geo *geo, *geo2;                 // the boxes' constants (geo2: level 2, halo statistics only)
     uint32_t *base;                  // first particle of every box, then the total
+    int32_t *btab;                   // box of every 2^bshift-th particle (Boxes::btab)
     int64_t *box_rows;               // halo-table rows of every box
     uint32_t *host;                                    // the lane's pinned host words (read_words)
 };
