@@ -143,13 +143,17 @@ __global__ __launch_bounds__(kBlock) void k_submax_wave(int64_t ndc, Boxes bx,
 // Stage 1, one thread per particle: a member at or above the floor that is not
 // the densest particle of its sub-cell is decided at once when that densest
 // particle belongs to its group and lies within b (the usual case inside an L0
-// group, the sub-cell diagonal being below l).  Every other member at or above
-// the floor is flagged as a hard case.
+// group, the sub-cell diagonal being below l).  A member that is its
+// sub-cell's densest is decided when the densest particle of a face-adjacent
+// sub-cell of the same cell is denser and in its group, where such sub-cells
+// lie within b of each other entirely (s sqrt(6) < b).  Every other member at
+// or above the floor is flagged as a hard case.
 __global__ __launch_bounds__(kBlock) void k_cand_quick(int64_t n, Boxes bx, const float4 *__restrict__ sloc,
                                                        const float4 *__restrict__ spos,
                                                        const uint32_t *__restrict__ f_sparse,
                                                        const uint16_t *__restrict__ ssub,
                                                        const uint32_t *__restrict__ cellmap,
+                                                       const uint64_t *__restrict__ submax,
                                                        const int32_t *__restrict__ subarg,
                                                        const float *__restrict__ dens_s,
                                                        const int32_t *__restrict__ gkey,
@@ -167,17 +171,36 @@ __global__ __launch_bounds__(kBlock) void k_cand_quick(int64_t n, Boxes bx, cons
         const float4 li = sloc[i];
         const uint32_t c = __float_as_uint(li.w);
         if (!f_sparse[i]) {
-            const int32_t top = subarg[(int64_t)cellmap[c] * (bx.nsub_max + 1) + ssub[i]];
-            // top, the maximum of i's sub-cell, is denser than i (the bit
-            // order of the key matches the values for the non-negative
-            // densities the stage works on; checked anyway)
-            if (top != (int32_t)i && gkey[top] == key &&
-                denser(dens_s[top], orig_of(spos[top]), di, orig_of(spos[i]))) {
-                const float4 lt = sloc[top];
-                const float dx = lt.x - li.x, dy = lt.y - li.y, dz = lt.z - li.z;
-                const float d2f = dx * dx + dy * dy + dz * dz;
-                if (d2f < g.b2b_lo || (d2f < g.b2b_hi && d2_exact(spos[i], spos[top], g.L, g.half) < g.b2))
-                    is_hard = false;
+            const int64_t base = (int64_t)cellmap[c] * (bx.nsub_max + 1);
+            const int si = ssub[i];
+            const int32_t top = subarg[base + si];
+            const uint32_t oi = orig_of(spos[i]);
+            if (top != (int32_t)i) {
+                // top, the maximum of i's sub-cell, is denser than i (the bit
+                // order of the key matches the values for the non-negative
+                // densities the stage works on; checked anyway)
+                if (gkey[top] == key && denser(dens_s[top], orig_of(spos[top]), di, oi)) {
+                    const float4 lt = sloc[top];
+                    const float dx = lt.x - li.x, dy = lt.y - li.y, dz = lt.z - li.z;
+                    const float d2f = dx * dx + dy * dy + dz * dz;
+                    if (d2f < g.b2b_lo || (d2f < g.b2b_hi && d2_exact(spos[i], spos[top], g.L, g.half) < g.b2))
+                        is_hard = false;
+                }
+            } else if (g.face_sub_in_b) {
+                const int k = g.ksub;
+                const int sx = si % k, sy = (si / k) % k, sz = si / (k * k);
+                const uint64_t mykey = dkey(di, oi);
+#pragma unroll
+                for (int f = 0; f < 6 && is_hard; f++) {
+                    const int ax = f >> 1, dir = (f & 1) ? 1 : -1;
+                    const int nx = sx + (ax == 0 ? dir : 0), ny = sy + (ax == 1 ? dir : 0),
+                              nz = sz + (ax == 2 ? dir : 0);
+                    if (nx < 0 || nx >= k || ny < 0 || ny >= k || nz < 0 || nz >= k) continue;
+                    const int s2 = (nz * k + ny) * k + nx;
+                    if (!(submax[base + s2] > mykey)) continue;
+                    const int32_t t2 = subarg[base + s2];
+                    if (gkey[t2] == key && denser(dens_s[t2], orig_of(spos[t2]), di, oi)) is_hard = false;
+                }
             }
         }
     }
@@ -469,7 +492,7 @@ void launch_candidates(int64_t n, const Boxes &bx, Work &w, hipStream_t s) {
     // candidate flags live in the owner array until the assignment overwrites
     // it; the hard-case flags and their scan reuse the dense-cell flag arrays
     hipLaunchKernelGGL(k_cand_quick, dim3(blocks), dim3(kBlock), 0, s, n, bx, w.sloc, w.spos, w.f_sparse, w.ssub,
-                       w.cnt, w.subarg, w.dens_s, w.gkey, w.owner, w.f_dcell);
+                       w.cnt, w.submax, w.subarg, w.dens_s, w.gkey, w.owner, w.f_dcell);
     scan_u32(w.f_dcell, w.s_dcell, n, w.scan_tmp, s);
     hipLaunchKernelGGL(k_hard_list, dim3(blocks), dim3(kBlock), 0, s, n, w.f_dcell, w.s_dcell, w.hardlist);
     uint32_t nh = 0;

@@ -129,6 +129,11 @@ hf_status make_geo(Lane *c, const hf_params *p, int64_t n, Geo *g) {
     g->nsub = g->ksub * g->ksub * g->ksub;
     g->inv_sub = g->ksub / g->cell;
     g->sub2 = (g->cell / g->ksub) * (g->cell / g->ksub);
+    // two face-adjacent sub-cells of side s fit in a 2s x s x s box, whose
+    // diagonal is s sqrt(6); the 2 % margin covers a particle binned a
+    // coordinate ulp outside its sub-cell (the cell index comes from float
+    // coordinates)
+    g->face_sub_in_b = (g->cell / g->ksub) * sqrt(6.0) < 0.98 * d[D_B] ? 1 : 0;
     g->rsub = (int)ceil(d[D_L] * g->ksub / g->cell);
     if (g->rsub > g->ksub) g->rsub = g->ksub;
     // FP32 prefilter margin (units of b^2): 256 ulps of the largest local

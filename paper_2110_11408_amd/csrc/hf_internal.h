@@ -26,6 +26,7 @@ struct Geo {
     int rsub;              // FoF reach in sub-cells: ceil(l / sub-cell side)
     double inv_sub;        // ksub / cell
     double sub2;           // squared sub-cell side
+    int face_sub_in_b;     // any two points of face-adjacent sub-cells are closer than b
     double b2, l2;         // FP64 squared radii of the peak test and of FoF links
     float l2b_lo, l2b_hi;  // (l/b)^2 shrunk / grown by the FP32 prefilter margin
     float b2b_lo, b2b_hi;  // 1 shrunk / grown by the same margin (peak test, units of b^2)
