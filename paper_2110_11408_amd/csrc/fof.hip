@@ -6,10 +6,11 @@
 //   phase A  a sub-cell's diagonal is below l, so all members of a sub-cell are
 //            friends: in dense cells every member points at the first member of
 //            its sub-cell;
-//   dense    one wavefront per dense chunk streams the neighbour members within
-//            reach (FP32 prefilter on the cell-local coordinates, canonical FP64
-//            distance for the undecided band) and joins each linked member's set
-//            to the sets of the lanes it links, with a per-lane root cache;
+//   dense    one wavefront per dense chunk gathers the neighbour members within
+//            reach 64 at a time and tests them against its lanes (FP32
+//            prefilter on the cell-local coordinates, canonical FP64 distance
+//            for the undecided band); it joins sets in its own view of the
+//            forest and applies the resulting hooks in bulk;
 //   sparse   members of sparse cells link to the later members of sparse
 //            neighbour cells;
 //   labels   compression, then 1 + the smallest ORIGINAL index of each set.
@@ -78,146 +79,101 @@ __device__ __forceinline__ bool linked(float xs, float ys, float zs, const float
     return d2_exact(pa, spos[b], g.L, g.half) < g.l2;
 }
 
-// Join the lanes linked to a member of the set rj (rj: any node of that set)
-// to that set; every lane keeps the root of its own set in wr.  Returns the
-// root of the joined set.
-__device__ __forceinline__ int join_lanes(int32_t *parent, bool lk, int &wr, int rj) {
+// Hooks a wavefront has decided on but not yet applied to the forest: lane
+// k < n holds hook k, a root c to be attached under p < c.  Deferring them
+// takes the compare-and-swap round trips out of the serial candidate loop:
+// the wavefront joins sets in its own registers and applies all hooks at
+// once, one lane each.
+struct Hooks {
+    int c = -1, p = -1, n = 0;
+};
+
+// Applies every queued hook: a compare-and-swap while c is still a root,
+// otherwise a full union (c was hooked elsewhere meanwhile).
+__device__ __forceinline__ void hooks_apply(int32_t *parent, Hooks &h) {
+    if ((int)(threadIdx.x & 63) < h.n && atomicCAS(parent + h.c, h.c, h.p) != h.c) uf_unite(parent, h.c, h.p);
+    h.n = 0;
+}
+
+__device__ __forceinline__ void hooks_push(int32_t *parent, Hooks &h, int c, int p) {
+    if (h.n == 64) hooks_apply(parent, h);
+    if ((int)(threadIdx.x & 63) == h.n) {
+        h.c = c;
+        h.p = p;
+    }
+    h.n++;
+}
+
+// A value equal in every lane, moved to a scalar register.
+__device__ __forceinline__ float uniform(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+    for (int d = 32; d >= 1; d >>= 1) v = min(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
+// The lanes lk are linked to a particle whose set has the local root r.  In
+// the wavefront's view of the forest (every root it holds is a node of its
+// set), the smallest of r and the lanes' roots becomes the root of all of
+// them; the others are queued as hooks under it, and every reference the
+// wavefront holds to one of them (lane roots wr, candidate roots rc, task
+// roots rt) is moved to it.
+__device__ __forceinline__ void join_local(int32_t *parent, Hooks &h, bool lk, int r, int &wr, int &rc, int &rt) {
+    const int m = min(r, wave_min(lk ? wr : 0x7fffffff));
+    if (r != m) {
+        hooks_push(parent, h, r, m);
+        if (wr == r) wr = m;
+        if (rc == r) rc = m;
+        if (rt == r) rt = m;
+    }
+    uint64_t mask;
+    while ((mask = __ballot(lk && wr != m)) != 0ull) {
+        const int x = lane_get(wr, (int)__builtin_ctzll(mask));
+        hooks_push(parent, h, x, m);
+        if (wr == x) wr = m;
+        if (rc == x) rc = m;
+        if (rt == x) rt = m;
+    }
+}
+
+// Tests the member candidates of a batch (lane p: candidate p) against the
+// chunk's lanes, then joins their sets.  A candidate holds whether it is a
+// member, its coordinates in the chunk's cell frame (units of b), its index
+// and its local root rc.  The tests run with the candidates in the lanes and
+// the chunk's particles broadcast one after the other (both sides are mostly
+// far below 64); each candidate collects the chunk lanes it links as a bit
+// mask.  The joins then take the linked candidates one after the other.  A
+// candidate already in the set of every lane needs no test.
+__device__ __forceinline__ void test_candidates(int32_t *parent, Hooks &h, const float4 *__restrict__ spos,
+                                                const Geo &g, bool active, const float4 &li, uint32_t h0,
+                                                int &wr, bool cmem, float qx, float qy, float qz, uint32_t cj,
+                                                int &rc, int &rt) {
     const int lane = threadIdx.x & 63;
-    bool need = lk && wr != rj;
-    uint64_t m;
-    while ((m = __ballot(need)) != 0ull) {
-        const int L = __ffsll((unsigned long long)m) - 1;
-        const int w = lane_get(wr, L);
-        int r = 0;
-        if (lane == L) {
-            // fast path: both are usually current roots, so hooking the larger
-            // under the smaller is one compare-and-swap; otherwise a full union
-            const int lo = min(w, rj), hi = max(w, rj);
-            if (atomicCAS(parent + hi, hi, lo) == hi) {
-                r = lo;
-            } else {
-                uf_unite(parent, w, rj);
-                r = uf_find(parent, w);
-            }
-        }
-        r = lane_get(r, L);
-        if (wr == w || wr == rj) wr = r;
-        rj = r;
-        need = lk && wr != rj;
+    const uint64_t am = __ballot(active);
+    const int w0 = lane_get(wr, (int)__builtin_ctzll(am));
+    const bool common = !__ballot(active && wr != w0);
+    const bool need = cmem && !(common && rc == w0);
+    if (!__ballot(need)) return;
+    uint32_t lo = 0u, hi = 0u;  // linked chunk lanes 0..31 and 32..63
+    for (uint64_t m = am; m; m &= m - 1) {
+        const int I = (int)__builtin_ctzll(m);
+        const float dx = qx - lane_get(li.x, I), dy = qy - lane_get(li.y, I), dz = qz - lane_get(li.z, I);
+        const float d2f = d2_f32(dx, dy, dz);
+        bool lk = need && d2f < g.l2b_hi;
+        if (lk && !(d2f < g.l2b_lo)) lk = d2_exact(spos[h0 + (uint32_t)I], spos[cj], g.L, g.half) < g.l2;
+        if (I < 32)
+            lo |= lk ? 1u << I : 0u;
+        else
+            hi |= lk ? 1u << (I - 32) : 0u;
     }
-    return rj;
-}
-
-// Friends test from FP32 differences already taken in one frame (dx = x_b - x_a):
-// FP32 prefilter, canonical FP64 distance of the original positions in the
-// undecided band.
-__device__ __forceinline__ bool linked_d(float dx, float dy, float dz, const float4 &pa,
-                                         const float4 *__restrict__ spos, uint32_t b, const Geo &g) {
-    const float d2f = d2_f32(dx, dy, dz);
-    if (d2f >= g.l2b_hi) return false;
-    if (d2f < g.l2b_lo) return true;
-    return d2_exact(pa, spos[b], g.L, g.half) < g.l2;
-}
-
-// Joins the lanes linked to any member of [a, b) to that range's set rset
-// (the range is one sub-cell, so its members are one set).  Every lane tests
-// the members in order (wave-uniform loads, coordinates as scalar operands)
-// and keeps whether it links to any of them, with the canonical FP64
-// distance in the FP32 prefilter's undecided band.  The linked lanes are
-// then joined in one go.  Returns whether any join was made.
-__device__ __forceinline__ bool stream_range(int32_t *parent, const float *__restrict__ dens_s,
-                                             const float4 *__restrict__ sloc,
-                                             const float4 *__restrict__ spos, const Geo &g, bool active,
-                                             const float4 &li, const float4 &pi, int &wr, uint32_t a,
-                                             uint32_t b, int ox, int oy, int oz, int rset) {
-    // the lane's coordinates in the neighbour cell's frame
-    const float xs = li.x - (float)ox * g.cellb, ys = li.y - (float)oy * g.cellb,
-                zs = li.z - (float)oz * g.cellb;
-    const bool want = active && wr != rset;
-    // the smallest FP32 squared distance to a member (one minimum per member,
-    // no branch); only a lane whose minimum falls in the prefilter's
-    // undecided band repeats the range with the canonical FP64 distance
-    float mind = 3.0e38f;
-    for (uint32_t j = a; j < b; j++) {
-        if (!is_member(dens_s, j, g.dl0)) continue;
-        const float4 lj = sloc[j];
-        const float dx = lj.x - xs, dy = lj.y - ys, dz = lj.z - zs;
-        mind = fminf(mind, d2_f32(dx, dy, dz));
-    }
-    bool any = mind < g.l2b_lo;
-    if (want && !any && mind < g.l2b_hi) {
-        for (uint32_t j = a; j < b && !any; j++)
-            if (is_member(dens_s, j, g.dl0) && d2_exact(pi, spos[j], g.L, g.half) < g.l2) any = true;
-    }
-    const bool lk = want && any;
-    if (!__ballot(lk)) return false;
-    join_lanes(parent, lk, wr, rset);
-    return true;
-}
-
-// All sparse neighbour cells of a chunk at once: lane t < 27 holds stencil
-// cell t's range [la, lb) and whether it is to be visited; their particles are
-// numbered through a prefix sum and loaded 64 at a time (each lane finds its
-// particle's cell by one walk over the cells that hold particles), then
-// broadcast in order and joined to the lanes they link.
-__device__ __forceinline__ void stream_sparse_cells(int32_t *parent, const float *__restrict__ dens_s,
-                                                    const float4 *__restrict__ sloc,
-                                                    const float4 *__restrict__ spos, const Geo &g,
-                                                    bool active, const float4 &li, const float4 &pi,
-                                                    int &wr, bool visit, uint32_t la, uint32_t lb) {
-    const int lane = threadIdx.x & 63;
-    const int cntl = visit ? (int)(lb - la) : 0;
-    int incl = cntl;
-    for (int d = 1; d < 64; d <<= 1) {
-        const int y = __shfl_up(incl, d, 64);
-        if (lane >= d) incl += y;
-    }
-    const int P = lane_get(incl, 63);
-    if (P == 0) return;
-    // the visited cells that hold particles (lane t for stencil cell t)
-    const uint64_t cells = __ballot(cntl > 0);
-    for (int p0 = 0; p0 < P; p0 += 64) {
-        const int p = p0 + lane;
-        bool mem = false;
-        uint32_t j = 0;
-        float xj = 0.0f, yj = 0.0f, zj = 0.0f;
-        int rj = -1;
-        // the visited cell whose particles include number p, found by one
-        // walk over the cells with particles (their starts are scalars)
-        int t = 0;
-        uint32_t jt = 0;
-        for (uint64_t m = cells; m; m &= m - 1) {
-            const int u = __builtin_ctzll(m);
-            const int st = lane_get(incl, u) - lane_get(cntl, u);
-            if (p >= st) {
-                t = u;
-                jt = lane_get(la, u) + (uint32_t)(p - st);
-            }
-        }
-        if (p < P) {
-            j = jt;
-            mem = is_member(dens_s, j, g.dl0);
-            if (mem) {
-                const float4 lj = sloc[j];
-                xj = lj.x + (float)(t % 3 - 1) * g.cellb;
-                yj = lj.y + (float)((t / 3) % 3 - 1) * g.cellb;
-                zj = lj.z + (float)(t / 9 - 1) * g.cellb;
-                rj = uf_find_hint(parent, (int)j);
-            }
-        }
-        uint64_t mm = __ballot(mem);
-        while (mm) {
-            const int J = __ffsll((unsigned long long)mm) - 1;
-            mm &= mm - 1;
-            int r = lane_get(rj, J);
-            if (!__ballot(active && wr != r)) continue;
-            const uint32_t jj = lane_get(j, J);
-            const float dx = lane_get(xj, J) - li.x, dy = lane_get(yj, J) - li.y,
-                        dz = lane_get(zj, J) - li.z;
-            const bool lk = active && wr != r && linked_d(dx, dy, dz, pi, spos, jj, g);
-            if (!__ballot(lk)) continue;
-            join_lanes(parent, lk, wr, r);
-        }
+    for (uint64_t mm = __ballot((lo | hi) != 0u); mm; mm &= mm - 1) {
+        const int J = (int)__builtin_ctzll(mm);
+        const int r = lane_get(rc, J);
+        const uint32_t bits = lane < 32 ? lane_get(lo, J) >> lane : lane_get(hi, J) >> (lane - 32);
+        const bool lk = (bits & 1u) != 0u && wr != r;
+        if (__ballot(lk)) join_local(parent, h, lk, r, wr, rc, rt);
     }
 }
 
@@ -253,13 +209,17 @@ __global__ __launch_bounds__(kBlock) void k_fof_phase_a(int64_t n, Boxes bx, con
 // visits the neighbour cells that come within l of some lane: sparse cells in
 // all 26 directions, dense cells only in the forward half (the backward ones
 // visit this cell themselves), and its own cell from the chunk start on.
-// The 27 cell ranges are loaded at once (one stencil cell per lane); sparse
-// cells are then streamed particle by particle.  The sub-cells of all visited
-// dense cells are examined 64 at a time (one per lane): range, first member and
-// that member's parent; a sub-cell already in the set every lane belongs to is
-// skipped (all its members are one set), and the others are streamed as
-// wave-uniform scalar loads and joined to the lanes they link.
-__global__ __launch_bounds__(kBlock) void k_fof_dense(int64_t nchunks, Boxes bx,
+// The 27 cell ranges are loaded at once (one stencil cell per lane).
+// Neighbour particles are gathered 64 at a time (one per lane, shifted into
+// the chunk's cell frame) and tested one after the other against all lanes;
+// sets are joined in the wavefront's registers and the hooks applied to the
+// forest in bulk, before each round of sub-cells and at the end:
+//   sparse cells  all their particles, each member with its root;
+//   dense cells   their sub-cells, 64 at a time (one per lane): range, first
+//                 member and that member's root.  A sub-cell already in the
+//                 set of every lane is passed over (its members are one set);
+//                 the particles of the others are gathered in lane order.
+__global__ __launch_bounds__(kBlock, 8) void k_fof_dense(int64_t nchunks, Boxes bx,
                                                       const int32_t *__restrict__ chunks,
                                                       const float4 *__restrict__ sloc,
                                                       const float4 *__restrict__ spos,
@@ -284,7 +244,6 @@ __global__ __launch_bounds__(kBlock) void k_fof_dense(int64_t nchunks, Boxes bx,
     const bool active = i < end && is_member(dens_s, ic, g.dl0);
     if (!__ballot(active)) return;
     const float4 li = sloc[ic];
-    const float4 pi = spos[ic];
     int wr = active ? uf_find_hint(parent, (int)ic) : -1;
     const int k = g.ksub, nsub = g.nsub, tstride = bx.nsub_max + 1;
     const float subb = g.cellb / (float)k;
@@ -302,6 +261,12 @@ __global__ __launch_bounds__(kBlock) void k_fof_dense(int64_t nchunks, Boxes bx,
         by1 = fmaxf(by1, __shfl_xor(by1, d, 64));
         bz1 = fmaxf(bz1, __shfl_xor(bz1, d, 64));
     }
+    bx0 = uniform(bx0);
+    by0 = uniform(by0);
+    bz0 = uniform(bz0);
+    bx1 = uniform(bx1);
+    by1 = uniform(by1);
+    bz1 = uniform(bz1);
     // one stencil cell per lane (offset (t % 3 - 1, t / 3 % 3 - 1, t / 9 - 1)):
     // its range, if it comes within l of the chunk's box
     const int tl = lane < 27 ? lane : 13;
@@ -325,64 +290,128 @@ __global__ __launch_bounds__(kBlock) void k_fof_dense(int64_t nchunks, Boxes bx,
         dbase[wave][slot] = (int64_t)cellmap[nbl] * tstride;
         doff[wave][slot] = (int8_t)lane;
     }
-    const uint64_t visit = __ballot(lvisit);
-    const int nvisit = __popcll(visit);
-    // sparse neighbour cells, all together
-    stream_sparse_cells(parent, dens_s, sloc, spos, g, active, li, pi, wr, lreach && !ldense && lb > la, la, lb);
-    if (nvisit == 0) return;
-    __builtin_amdgcn_wave_barrier();
-    // (visited dense cell, sub-cell) pairs, 64 at a time
-    const int ntask = nvisit * nsub;
-    for (int t0 = 0; t0 < ntask; t0 += 64) {
-        const int tq = t0 + lane;
-        uint32_t u0 = 0, u1 = 0;
-        int fs = -1, st = 0;
-        if (tq < ntask) {
-            const int r = tq / nsub, sl = tq - r * nsub;
-            st = doff[wave][r];
-            const int64_t base = dbase[wave][r];
-            const int ox = st % 3 - 1, oy = (st / 3) % 3 - 1, oz = st / 9 - 1;
-            u0 = subtab[base + sl];
-            u1 = subtab[base + sl + 1];
-            if (st == 13 && u0 < h) u0 = h;  // own cell: from the chunk start on
-            const int sx = sl % k, sy = (sl / k) % k, sz = sl / (k * k);
-            // sub-cell box (neighbour frame) shifted into the chunk's frame
-            const float ex = fmaxf(fmaxf(sx * subb + (float)ox * g.cellb - bx1,
-                                         bx0 - ((sx + 1) * subb + (float)ox * g.cellb)), 0.0f);
-            const float ey = fmaxf(fmaxf(sy * subb + (float)oy * g.cellb - by1,
-                                         by0 - ((sy + 1) * subb + (float)oy * g.cellb)), 0.0f);
-            const float ez = fmaxf(fmaxf(sz * subb + (float)oz * g.cellb - bz1,
-                                         bz0 - ((sz + 1) * subb + (float)oz * g.cellb)), 0.0f);
-            if (ex * ex + ey * ey + ez * ez < g.l2b_hi + 1e-4f) {
-                for (uint32_t j = u0; j < u1; j++)
-                    if (is_member(dens_s, j, g.dl0)) {
-                        fs = (int)j;
-                        break;
-                    }
-            }
+    const int nvisit = __popcll(__ballot(lvisit));
+    Hooks hk;
+    int no_rt = -1;
+    // sparse neighbour cells: their particles numbered through a prefix sum of
+    // the cell sizes; lane p finds the cell of particle p by one walk over the
+    // cells that hold particles (their starts are scalars)
+    {
+        const int cntl = lreach && !ldense ? (int)(lb - la) : 0;
+        int incl = cntl;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += y;
         }
-        // root hints of all sub-cells at once; a sub-cell whose set is the one
-        // every active lane belongs to needs nothing
-        int rL = fs >= 0 ? uf_find_hint(parent, fs) : -1;
-        const uint64_t am = __ballot(active);
-        for (;;) {
-            const int w0 = lane_get(wr, __ffsll((unsigned long long)am) - 1);
-            const int wcommon = __ballot(active && wr != w0) ? -2 : w0;
-            const uint64_t todo = __ballot(fs >= 0 && rL != wcommon);
-            if (!todo) break;
-            const int S = __ffsll((unsigned long long)todo) - 1;
-            const int f = lane_get(fs, S);
-            const uint32_t e = lane_get(u1, S);
-            const int sts = lane_get(st, S);
-            const int rS = lane_get(rL, S);
-            if (lane == S) fs = -1;  // done with it
-            if (!__ballot(active && wr != rS)) continue;
-            const bool joined = stream_range(parent, dens_s, sloc, spos, g, active, li, pi, wr, (uint32_t)f, e,
-                                             sts % 3 - 1, (sts / 3) % 3 - 1, sts / 9 - 1, rS);
-            // after a join the remaining hints may be stale: refresh them
-            if (joined && fs >= 0) rL = uf_find_hint(parent, fs);
+        const int P = lane_get(incl, 63);
+        const uint64_t cells = __ballot(cntl > 0);
+        for (int p0 = 0; p0 < P; p0 += 64) {
+            const int p = p0 + lane;
+            int t = 0;
+            uint32_t jt = 0;
+            for (uint64_t m = cells; m; m &= m - 1) {
+                const int u = (int)__builtin_ctzll(m);
+                const int stt = lane_get(incl, u) - lane_get(cntl, u);
+                if (p >= stt) {
+                    t = u;
+                    jt = lane_get(la, u) + (uint32_t)(p - stt);
+                }
+            }
+            bool cmem = false;
+            float qx = 0.0f, qy = 0.0f, qz = 0.0f;
+            int rc = -1;
+            if (p < P) {
+                const float4 lj = sloc[jt];
+                cmem = is_member(dens_s, jt, g.dl0);
+                qx = lj.x + (float)(t % 3 - 1) * g.cellb;
+                qy = lj.y + (float)((t / 3) % 3 - 1) * g.cellb;
+                qz = lj.z + (float)(t / 9 - 1) * g.cellb;
+            }
+            if (cmem) rc = uf_find_hint(parent, (int)jt);
+            test_candidates(parent, hk, spos, g, active, li, h, wr, cmem, qx, qy, qz, jt, rc, no_rt);
         }
     }
+    if (nvisit > 0) {
+        __builtin_amdgcn_wave_barrier();
+        const int a0 = (int)__builtin_ctzll(__ballot(active));
+        const int ntask = nvisit * nsub;
+        // (visited dense cell, sub-cell) pairs, 64 at a time
+        for (int t0 = 0; t0 < ntask; t0 += 64) {
+            // the forest learns this chunk's joins so far, the lanes their roots
+            hooks_apply(parent, hk);
+            if (active) wr = uf_find_hint(parent, wr);
+            const int tq = t0 + lane;
+            uint32_t u1 = 0;
+            int fs = -1, st = 0;
+            if (tq < ntask) {
+                const int r = tq / nsub, sl = tq - r * nsub;
+                st = doff[wave][r];
+                const int64_t base = dbase[wave][r];
+                const int ox = st % 3 - 1, oy = (st / 3) % 3 - 1, oz = st / 9 - 1;
+                uint32_t u0 = subtab[base + sl];
+                u1 = subtab[base + sl + 1];
+                if (st == 13 && u0 < h) u0 = h;  // own cell: from the chunk start on
+                const int sx = sl % k, sy = (sl / k) % k, sz = sl / (k * k);
+                // sub-cell box (neighbour frame) shifted into the chunk's frame
+                const float ex = fmaxf(fmaxf(sx * subb + (float)ox * g.cellb - bx1,
+                                             bx0 - ((sx + 1) * subb + (float)ox * g.cellb)), 0.0f);
+                const float ey = fmaxf(fmaxf(sy * subb + (float)oy * g.cellb - by1,
+                                             by0 - ((sy + 1) * subb + (float)oy * g.cellb)), 0.0f);
+                const float ez = fmaxf(fmaxf(sz * subb + (float)oz * g.cellb - bz1,
+                                             bz0 - ((sz + 1) * subb + (float)oz * g.cellb)), 0.0f);
+                if (ex * ex + ey * ey + ez * ez < g.l2b_hi + 1e-4f) {
+                    for (uint32_t j = u0; j < u1; j++)
+                        if (is_member(dens_s, j, g.dl0)) {
+                            fs = (int)j;
+                            break;
+                        }
+                }
+            }
+            int rt = fs >= 0 ? uf_find_hint(parent, fs) : -1;
+            uint32_t pos = fs >= 0 ? (uint32_t)fs : 0u;  // next particle of the sub-cell to gather
+            for (;;) {
+                const int w0 = lane_get(wr, a0);
+                const int wcommon = __ballot(active && wr != w0) ? -2 : w0;
+                const uint32_t len = fs >= 0 && pos < u1 && rt != wcommon ? u1 - pos : 0u;
+                uint32_t incl = len;
+                for (int d = 1; d < 64; d <<= 1) {
+                    const uint32_t y = __shfl_up(incl, d, 64);
+                    if (lane >= d) incl += y;
+                }
+                const uint32_t T = lane_get(incl, 63);
+                if (T == 0) break;
+                // lane p takes particle p of the sub-cells' runs laid end to end
+                int tst = 13, trt = -1;
+                uint32_t jt = 0;
+                for (uint64_t m = __ballot(len > 0); m; m &= m - 1) {
+                    const int u = (int)__builtin_ctzll(m);
+                    const uint32_t stu = lane_get(incl, u) - lane_get(len, u);
+                    if (stu >= 64u) break;
+                    if ((uint32_t)lane >= stu) {
+                        tst = lane_get(st, u);
+                        trt = lane_get(rt, u);
+                        jt = lane_get(pos, u) + ((uint32_t)lane - stu);
+                    }
+                }
+                // every sub-cell moves past what this round takes from it
+                const uint32_t mine = incl - len;
+                if (mine < 64u) pos += min(len, 64u - mine);
+                bool cmem = false;
+                float qx = 0.0f, qy = 0.0f, qz = 0.0f;
+                int rc = -1;
+                if ((uint32_t)lane < T) {
+                    const float4 lj = sloc[jt];
+                    cmem = is_member(dens_s, jt, g.dl0);
+                    qx = lj.x + (float)(tst % 3 - 1) * g.cellb;
+                    qy = lj.y + (float)((tst / 3) % 3 - 1) * g.cellb;
+                    qz = lj.z + (float)(tst / 9 - 1) * g.cellb;
+                    rc = trt;
+                }
+                test_candidates(parent, hk, spos, g, active, li, h, wr, cmem, qx, qy, qz, jt, rc, rt);
+            }
+        }
+    }
+    hooks_apply(parent, hk);
 }
 
 // Members among the sparse-cell particles (about one in ten), compacted so
