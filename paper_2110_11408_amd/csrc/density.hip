@@ -54,15 +54,6 @@ __device__ __forceinline__ double weight64(const Pos64 &a, const float4 &q, doub
     return fmax(t, 0.0);
 }
 
-// Accumulate one neighbour cell [a, b) for particle i at FP64 position pi in
-// that cell's frame (the sparse-cell kernel, one particle per lane; its own
-// cell includes i, whose weight is exactly 1).  Loading the positions of a
-// cell four at a time was slower: the kernel is held by occupancy.
-__device__ __forceinline__ void accum_range(const float4 *__restrict__ spos, uint32_t a, uint32_t b,
-                                            const Pos64 &pi, double inv_b2, double &acc) {
-    for (uint32_t j = a; j < b; j++) acc += weight64(pi, spos[j], inv_b2);
-}
-
 // Dense-neighbour contributions of sparse particles are added in fixed point
 // (2^-32), so their order does not change the result.
 constexpr double kFixScale = 4294967296.0;
@@ -413,8 +404,10 @@ __global__ __launch_bounds__(64, 6) void k_density_dense(int64_t nchunks, Boxes 
 }
 
 // Sparse cells: one particle per lane, sparse neighbour cells only; the pairs
-// with dense neighbour cells were summed by the dense kernel into dfx.
-__global__ __launch_bounds__(kBlock) void k_density_sparse(int64_t nsparse, Boxes bx,
+// with dense neighbour cells were summed by the dense kernel into dfx.  The
+// kernel waits on memory, so it is held to 64 VGPRs (eight wavefronts per
+// SIMD, the most a SIMD runs; the compiler fits it without spilling).
+__global__ __launch_bounds__(kBlock, 8) void k_density_sparse(int64_t nsparse, Boxes bx,
                                                            const int32_t *__restrict__ sparse,
                                                            const float4 *__restrict__ sloc,
                                                            const float4 *__restrict__ spos,
@@ -437,51 +430,74 @@ __global__ __launch_bounds__(kBlock) void k_density_sparse(int64_t nsparse, Boxe
     // consecutive: their four bounding offsets are one 16-byte load
     const bool inner = cx > 0 && cx < nc - 1;
     double acc = 0.0;
+#pragma unroll 1
     for (int oz = -1; oz <= 1; oz++) {
         const int z = wrapc(cz + oz, nc);
         const float gz = oz < 0 ? li.z : (oz > 0 ? g.cellb - li.z : 0.0f);
-        // the offsets of this plane are loaded together so their latencies overlap
-        uint32_t ra[9], rb[9];
+        // the offsets of this plane are loaded together so their latencies
+        // overlap; the cells to visit are kept as their starts and, packed
+        // three bits each, their particle counts (0: dense, empty or out of
+        // reach)
+        uint32_t ra[9], cnts = 0;
 #pragma unroll
         for (int oy = -1; oy <= 1; oy++) {
             const uint32_t row =
                 g.cell_base + ((uint32_t)z * (uint32_t)nc + (uint32_t)wrapc(cy + oy, nc)) * (uint32_t)nc;
             const int r = (oy + 1) * 3;
+            uint32_t o[6];
             if (inner) {
                 const uint32_t *p = off + row + x0;
-                const uint32_t o0 = p[0], o1 = p[1], o2 = p[2], o3 = p[3];
-                ra[r + 0] = o0;
-                rb[r + 0] = o1;
-                ra[r + 1] = o1;
-                rb[r + 1] = o2;
-                ra[r + 2] = o2;
-                rb[r + 2] = o3;
+                o[0] = p[0];
+                o[1] = p[1];
+                o[2] = p[1];
+                o[3] = p[2];
+                o[4] = p[2];
+                o[5] = p[3];
             } else {
-                ra[r + 0] = off[row + x0];
-                rb[r + 0] = off[row + x0 + 1];
-                ra[r + 1] = off[row + x1];
-                rb[r + 1] = off[row + x1 + 1];
-                ra[r + 2] = off[row + x2];
-                rb[r + 2] = off[row + x2 + 1];
+                o[0] = off[row + x0];
+                o[1] = off[row + x0 + 1];
+                o[2] = off[row + x1];
+                o[3] = off[row + x1 + 1];
+                o[4] = off[row + x2];
+                o[5] = off[row + x2 + 1];
             }
-        }
-#pragma unroll
-        for (int oy = -1; oy <= 1; oy++) {
             const float gy = oy < 0 ? li.y : (oy > 0 ? g.cellb - li.y : 0.0f);
 #pragma unroll
             for (int ox = -1; ox <= 1; ox++) {
-                const int r = (oy + 1) * 3 + (ox + 1);
-                if (rb[r] - ra[r] >= (uint32_t)kDenseMin) continue;
+                const uint32_t a = o[2 * (ox + 1)], cnt = o[2 * (ox + 1) + 1] - a;
                 // a cell whose nearest face is b or more away (by a margin far
                 // above the rounding of the local coordinates) weighs nothing
                 const float gx = ox < 0 ? li.x : (ox > 0 ? g.cellb - li.x : 0.0f);
-                if (gx * gx + gy * gy + gz * gz >= 1.0f + 1e-5f) continue;
-                // i's position in this cell's frame
-                const Pos64 pim{(double)pi.x - image_shift(cx, ox, nc, g.L),
-                                (double)pi.y - image_shift(cy, oy, nc, g.L),
-                                (double)pi.z - image_shift(cz, oz, nc, g.L)};
-                accum_range(spos, ra[r], rb[r], pim, g.inv_b2, acc);
+                const bool use = cnt < (uint32_t)kDenseMin && gx * gx + gy * gy + gz * gz < 1.0f + 1e-5f;
+                ra[r + ox + 1] = a;
+                cnts |= (use ? cnt : 0u) << (3 * (r + ox + 1));
             }
+        }
+        // the plane's cells walked as one sequence of particles (cell after
+        // cell in stencil order, so the summation order is that of a loop per
+        // cell): every lane runs through its own particles, and the wavefront
+        // waits on the longest lane's count for the whole plane rather than on
+        // the longest count of each cell
+        uint32_t j = 0, e = 0;
+        Pos64 pim{0.0, 0.0, 0.0};
+        for (;;) {
+            if (j == e) {
+                if (cnts == 0u) break;
+                const int r = __builtin_ctz(cnts) / 3;
+                const uint32_t cnt = (cnts >> (3 * r)) & 7u;
+                cnts &= ~(7u << (3 * r));
+                uint32_t a = ra[0];
+#pragma unroll
+                for (int u = 1; u < 9; u++) a = r == u ? ra[u] : a;
+                j = a;
+                e = a + cnt;
+                // i's position in this cell's frame
+                const int ox = r % 3 - 1, oy = r / 3 - 1;
+                pim = Pos64{(double)pi.x - image_shift(cx, ox, nc, g.L), (double)pi.y - image_shift(cy, oy, nc, g.L),
+                            (double)pi.z - image_shift(cz, oz, nc, g.L)};
+            }
+            acc += weight64(pim, spos[j], g.inv_b2);
+            j++;
         }
     }
     acc += (double)dfx[t] * (1.0 / kFixScale);

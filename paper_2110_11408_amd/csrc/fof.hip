@@ -66,19 +66,6 @@ __device__ void uf_unite(int32_t *parent, int a, int b) {
     }
 }
 
-// Friends test of a (shifted local coordinates xs, ys, zs) and b: FP32 prefilter,
-// canonical FP64 distance only in the undecided band.
-__device__ __forceinline__ bool linked(float xs, float ys, float zs, const float4 &pa,
-                                       const float4 *__restrict__ sloc, const float4 *__restrict__ spos,
-                                       uint32_t b, const Geo &g) {
-    const float4 lb = sloc[b];
-    const float dx = lb.x - xs, dy = lb.y - ys, dz = lb.z - zs;
-    const float d2f = d2_f32(dx, dy, dz);
-    if (d2f >= g.l2b_hi) return false;
-    if (d2f < g.l2b_lo) return true;
-    return d2_exact(pa, spos[b], g.L, g.half) < g.l2;
-}
-
 // Hooks a wavefront has decided on but not yet applied to the forest: lane
 // k < n holds hook k, a root c to be attached under p < c.  Deferring them
 // takes the compare-and-swap round trips out of the serial candidate loop:
@@ -437,7 +424,7 @@ __global__ __launch_bounds__(kBlock) void k_fof_sparse_list(int64_t nsparse, con
 // Members of sparse cells (the compacted list, its length on the device):
 // links to the later members of sparse neighbour cells (pairs with dense cells
 // are found by the dense chunks).  The offsets of a stencil plane are loaded
-// together.  The list fills only the first blocks of the grid, which the plain
+// together, and the plane's particles are walked as one sequence.  The list fills only the first blocks of the grid, which the plain
 // block order spreads over all XCDs.  The kernel waits on memory: it is held
 // to 64 VGPRs (eight wavefronts per SIMD; the compiler fits it without
 // spilling).
@@ -460,46 +447,63 @@ __global__ __launch_bounds__(kBlock, 8) void k_fof_sparse(const uint32_t *__rest
     cell_xyz(g, c, cx, cy, cz);
     const uint32_t x0 = (uint32_t)wrapc(cx - 1, nc), x1 = (uint32_t)cx, x2 = (uint32_t)wrapc(cx + 1, nc);
     int ri = uf_find_hint(parent, i);
+#pragma unroll 1
     for (int oz = -1; oz <= 1; oz++) {
-        const float zs = li.z - (float)oz * g.cellb;
         const float gz = oz < 0 ? li.z : (oz > 0 ? g.cellb - li.z : 0.0f);
         if (gz * gz >= g.l2b_hi) continue;
         const int z = wrapc(cz + oz, nc);
-        uint32_t ra[9], rb[9];
+        // the plane's later particles in sparse cells within reach: per cell
+        // its first one and, packed three bits each, their count
+        uint32_t ra[9], cnts = 0;
 #pragma unroll
         for (int oy = -1; oy <= 1; oy++) {
             const uint32_t row =
                 g.cell_base + ((uint32_t)z * (uint32_t)nc + (uint32_t)wrapc(cy + oy, nc)) * (uint32_t)nc;
-            const int r = (oy + 1) * 3;
-            ra[r + 0] = off[row + x0];
-            rb[r + 0] = off[row + x0 + 1];
-            ra[r + 1] = off[row + x1];
-            rb[r + 1] = off[row + x1 + 1];
-            ra[r + 2] = off[row + x2];
-            rb[r + 2] = off[row + x2 + 1];
-        }
-#pragma unroll
-        for (int oy = -1; oy <= 1; oy++) {
-            const float ys = li.y - (float)oy * g.cellb;
+            const uint32_t o[6] = {off[row + x0], off[row + x0 + 1], off[row + x1],
+                                   off[row + x1 + 1], off[row + x2], off[row + x2 + 1]};
+            const float gy = oy < 0 ? li.y : (oy > 0 ? g.cellb - li.y : 0.0f);
 #pragma unroll
             for (int ox = -1; ox <= 1; ox++) {
                 const int r = (oy + 1) * 3 + (ox + 1);
+                uint32_t a = o[2 * (ox + 1)];
+                const uint32_t b = o[2 * (ox + 1) + 1];
                 const float gx = ox < 0 ? li.x : (ox > 0 ? g.cellb - li.x : 0.0f);
-                const float gy = oy < 0 ? li.y : (oy > 0 ? g.cellb - li.y : 0.0f);
-                if (gx * gx + gy * gy + gz * gz >= g.l2b_hi) continue;
-                uint32_t a = ra[r];
-                const uint32_t b = rb[r];
-                if (b - a >= (uint32_t)kDenseMin) continue;
+                const bool use = b - a < (uint32_t)kDenseMin && gx * gx + gy * gy + gz * gz < g.l2b_hi;
                 if (a <= (uint32_t)i) a = (uint32_t)i + 1;
-                const float xs = li.x - (float)ox * g.cellb;
-                for (uint32_t j = a; j < b; j++) {
-                    if (!is_member(dens_s, j, g.dl0)) continue;
-                    if (!linked(xs, ys, zs, pi, sloc, spos, j, g)) continue;
-                    if (uf_find_hint(parent, (int)j) == ri) continue;
-                    uf_unite(parent, i, (int)j);
-                    ri = uf_find_hint(parent, i);
-                }
+                ra[r] = a;
+                cnts |= (use && b > a ? b - a : 0u) << (3 * r);
             }
+        }
+        // walked as one sequence (cell after cell): the wavefront waits on the
+        // longest lane's count for the plane, not on the longest of each cell
+        uint32_t j = 0, e = 0;
+        float xs = 0.0f, ys = 0.0f, zs = 0.0f;
+        for (;;) {
+            if (j == e) {
+                if (cnts == 0u) break;
+                const int r = __builtin_ctz(cnts) / 3;
+                const uint32_t cnt = (cnts >> (3 * r)) & 7u;
+                cnts &= ~(7u << (3 * r));
+                uint32_t a = ra[0];
+#pragma unroll
+                for (int u = 1; u < 9; u++) a = r == u ? ra[u] : a;
+                j = a;
+                e = a + cnt;
+                // the lane's coordinates in this cell's frame
+                xs = li.x - (float)(r % 3 - 1) * g.cellb;
+                ys = li.y - (float)(r / 3 - 1) * g.cellb;
+                zs = li.z - (float)oz * g.cellb;
+            }
+            const uint32_t jj = j++;
+            const float dj = dens_s[jj];
+            const float4 lj = sloc[jj];
+            if (!((double)dj > g.dl0)) continue;
+            const float d2f = d2_f32(lj.x - xs, lj.y - ys, lj.z - zs);
+            if (d2f >= g.l2b_hi) continue;
+            if (!(d2f < g.l2b_lo) && !(d2_exact(pi, spos[jj], g.L, g.half) < g.l2)) continue;
+            if (uf_find_hint(parent, (int)jj) == ri) continue;
+            uf_unite(parent, i, (int)jj);
+            ri = uf_find_hint(parent, i);
         }
     }
 }
