@@ -26,23 +26,18 @@ __device__ __forceinline__ void stencil_offset(int t, int &ox, int &oy, int &oz)
     oz = u / 9 - 1;
 }
 
-// j is a denser particle of the same group within b (FP32 prefilter on the
-// cell-local coordinates, canonical FP64 distance in the undecided band).
+// j is a denser particle of the same group within b.  Its group key and
+// position are loaded together (one round trip: the searches wait on memory,
+// not on arithmetic), and the distance is the canonical FP64 one.
 __device__ __forceinline__ bool denser_within_b(int64_t j, const float *__restrict__ dens_s,
                                                 const int32_t *__restrict__ gkey,
-                                                const float4 *__restrict__ sloc,
                                                 const float4 *__restrict__ spos, int key, float di,
-                                                uint32_t oi, float xs, float ys, float zs,
-                                                const float4 &pi, const Geo &g) {
+                                                uint32_t oi, const float4 &pi, const Geo &g) {
     const float dj = dens_s[j];
-    if (dj < di || gkey[j] != key) return false;
+    const int kj = gkey[j];
     const float4 pj = spos[j];
+    if (dj < di || kj != key) return false;
     if (!denser(dj, orig_of(pj), di, oi)) return false;
-    const float4 lj = sloc[j];
-    const float dx = lj.x - xs, dy = lj.y - ys, dz = lj.z - zs;
-    const float d2f = dx * dx + dy * dy + dz * dz;
-    if (d2f >= g.b2b_hi) return false;
-    if (d2f < g.b2b_lo) return true;
     return d2_exact(pi, pj, g.L, g.half) < g.b2;
 }
 
@@ -248,24 +243,26 @@ __device__ bool has_denser_within_b(int i, int tt0, int tt1, const Geo &g, int t
         const uint32_t nb = cell_id(g, cx + ox, cy + oy, cz + oz);
         const uint32_t a = off[nb], b = off[nb + 1];
         if (b - a < (uint32_t)kDenseMin) {
-            // sparse cell: the densities first (all loads together), then the
-            // few denser ones in full
-            float dj[kDenseMin];
+            // sparse cell: densities four at a time (their loads together),
+            // then the few denser ones in full
+            for (uint32_t a0 = a; a0 < b; a0 += 4) {
+                float dj[4];
 #pragma unroll
-            for (int u = 0; u < kDenseMin; u++) dj[u] = a + u < b ? dens_s[a + u] : -1.0f;
+                for (int u = 0; u < 4; u++) dj[u] = a0 + u < b ? dens_s[a0 + u] : -1.0f;
 #pragma unroll
-            for (int u = 0; u < kDenseMin; u++) {
-                const uint32_t j = a + u;
-                if (dj[u] < di || (int)j == i) continue;
-                if (denser_within_b(j, dens_s, gkey, sloc, spos, key, di, oi, xs, ys, zs, pi, g)) return true;
+                for (int u = 0; u < 4; u++) {
+                    const uint32_t j = a0 + u;
+                    if (dj[u] < di || (int)j == i) continue;
+                    if (denser_within_b(j, dens_s, gkey, spos, key, di, oi, pi, g)) return true;
+                }
             }
             continue;
         }
         const int64_t base = (int64_t)cellmap[nb] * tstride;
         for (int s0 = 0; s0 < nsub; s0 += 3) {
-            // three sub-cell maxima per round of loads (small batches keep the
-            // thread-per-case kernel at 74 VGPRs: it waits on memory, and
-            // six wavefronts per SIMD hide more than longer batches would)
+            // three sub-cell maxima per round of loads (the thread-per-case
+            // kernel waits on memory: small batches keep it at eight
+            // wavefronts per SIMD, which hide more than longer batches would)
             uint64_t mx[3];
 #pragma unroll
             for (int u = 0; u < 3; u++) mx[u] = s0 + u < nsub ? submax[base + s0 + u] : 0ull;
@@ -279,19 +276,19 @@ __device__ bool has_denser_within_b(int i, int tt0, int tt1, const Geo &g, int t
                 const float ez = fmaxf(fmaxf(sz * subb - 1e-5f - zs, zs - (sz + 1) * subb - 1e-5f), 0.0f);
                 if (ex * ex + ey * ey + ez * ez >= g.b2b_hi) continue;
                 const int32_t top = subarg[base + s2];
-                if (denser_within_b(top, dens_s, gkey, sloc, spos, key, di, oi, xs, ys, zs, pi, g)) return true;
-                // the rest of the sub-cell: densities 8 at a time, then the
+                if (denser_within_b(top, dens_s, gkey, spos, key, di, oi, pi, g)) return true;
+                // the rest of the sub-cell: densities four at a time, then the
                 // denser ones in full
                 const uint32_t u1 = subtab[base + s2 + 1];
-                for (uint32_t j0 = subtab[base + s2]; j0 < u1; j0 += 8) {
-                    float dj[8];
+                for (uint32_t j0 = subtab[base + s2]; j0 < u1; j0 += 4) {
+                    float dj[4];
 #pragma unroll
-                    for (int v = 0; v < 8; v++) dj[v] = j0 + v < u1 ? dens_s[j0 + v] : -1.0f;
+                    for (int v = 0; v < 4; v++) dj[v] = j0 + v < u1 ? dens_s[j0 + v] : -1.0f;
 #pragma unroll
-                    for (int v = 0; v < 8; v++) {
+                    for (int v = 0; v < 4; v++) {
                         const uint32_t j = j0 + v;
                         if (dj[v] < di || (int32_t)j == top || (int)j == i) continue;
-                        if (denser_within_b(j, dens_s, gkey, sloc, spos, key, di, oi, xs, ys, zs, pi, g))
+                        if (denser_within_b(j, dens_s, gkey, spos, key, di, oi, pi, g))
                             return true;
                     }
                 }
@@ -306,8 +303,10 @@ __device__ bool has_denser_within_b(int i, int tt0, int tt1, const Geo &g, int t
 // found), then the face neighbours (stage 2).  With `rest`, the cases left are
 // appended to it (one atomic per wavefront), so that the few exhaustive
 // searches (mostly the actual candidates) do not hold up waves of quick ones;
-// without it, the cases left are candidates.
-__global__ __launch_bounds__(kBlock) void k_cand_hard(const uint32_t *__restrict__ nhard_p, int stage, int tt0,
+// without it, the cases left are candidates.  Held to 64 VGPRs (eight
+// wavefronts per SIMD): a few values spill to scratch, which costs less than
+// the two wavefronts per SIMD it buys.
+__global__ __launch_bounds__(kBlock, 8) void k_cand_hard(const uint32_t *__restrict__ nhard_p, int stage, int tt0,
                                                       int tt1, Boxes bx,
                                                       const int32_t *__restrict__ hard,
                                                       const float4 *__restrict__ sloc,
@@ -420,7 +419,7 @@ __global__ __launch_bounds__(kBlock) void k_cand_wave(const uint32_t *__restrict
         if (in_reach && !dense) {
             for (uint32_t j = a; j < b && !found; j++)
                 if ((int)j != i && dens_s[j] >= di &&
-                    denser_within_b(j, dens_s, gkey, sloc, spos, key, di, oi, xs, ys, zs, pi, g))
+                    denser_within_b(j, dens_s, gkey, spos, key, di, oi, pi, g))
                     found = true;
         }
         if (__ballot(found)) continue;
@@ -457,11 +456,11 @@ __global__ __launch_bounds__(kBlock) void k_cand_wave(const uint32_t *__restrict
                     const float ez = fmaxf(fmaxf(sz * subb - 1e-5f - tzs, tzs - (sz + 1) * subb - 1e-5f), 0.0f);
                     if (ex * ex + ey * ey + ez * ez < g.b2b_hi) {
                         const int32_t top = subarg[base + sl];
-                        found = denser_within_b(top, dens_s, gkey, sloc, spos, key, di, oi, txs, tys, tzs, pi, g);
+                        found = denser_within_b(top, dens_s, gkey, spos, key, di, oi, pi, g);
                         const uint32_t u1 = subtab[base + sl + 1];
                         for (uint32_t j = subtab[base + sl]; j < u1 && !found; j++)
                             if ((int32_t)j != top && (int)j != i && dens_s[j] >= di &&
-                                denser_within_b(j, dens_s, gkey, sloc, spos, key, di, oi, txs, tys, tzs, pi, g))
+                                denser_within_b(j, dens_s, gkey, spos, key, di, oi, pi, g))
                                 found = true;
                     }
                 }
