@@ -163,39 +163,62 @@ __global__ __launch_bounds__(kBlock) void k_cand_quick(int64_t n, Boxes bx, cons
     const float di = dens_s[i];
     if (key >= 0 && (double)di >= g.floor_nuc) {
         is_hard = true;
-        const float4 li = sloc[i];
-        const uint32_t c = __float_as_uint(li.w);
-        if (!f_sparse[i]) {
+        // everything indexed by i in one round of loads
+        const uint32_t c = __float_as_uint(sloc[i].w);
+        const uint32_t sparse_i = f_sparse[i];
+        const int si = ssub[i];
+        const float4 pi = spos[i];
+        if (!sparse_i) {
             const int64_t base = (int64_t)cellmap[c] * (bx.nsub_max + 1);
-            const int si = ssub[i];
             const int32_t top = subarg[base + si];
-            const uint32_t oi = orig_of(spos[i]);
+            const uint32_t oi = orig_of(pi);
             if (top != (int32_t)i) {
                 // top, the maximum of i's sub-cell, is denser than i (the bit
                 // order of the key matches the values for the non-negative
-                // densities the stage works on; checked anyway)
-                if (gkey[top] == key && denser(dens_s[top], orig_of(spos[top]), di, oi)) {
-                    const float4 lt = sloc[top];
-                    const float dx = lt.x - li.x, dy = lt.y - li.y, dz = lt.z - li.z;
-                    const float d2f = dx * dx + dy * dy + dz * dz;
-                    if (d2f < g.b2b_lo || (d2f < g.b2b_hi && d2_exact(spos[i], spos[top], g.L, g.half) < g.b2))
-                        is_hard = false;
-                }
+                // densities the stage works on; checked anyway); its key,
+                // density and position are loaded together
+                const int kt = gkey[top];
+                const float dt = dens_s[top];
+                const float4 pt = spos[top];
+                if (kt == key && denser(dt, orig_of(pt), di, oi) && d2_exact(pi, pt, g.L, g.half) < g.b2)
+                    is_hard = false;
             } else if (g.face_sub_in_b) {
+                // the six face-adjacent sub-cells at once: their maxima, then
+                // the particles that hold them, then those particles' keys
                 const int k = g.ksub;
                 const int sx = si % k, sy = (si / k) % k, sz = si / (k * k);
                 const uint64_t mykey = dkey(di, oi);
+                int s2[6];
+                uint64_t mx[6];
 #pragma unroll
-                for (int f = 0; f < 6 && is_hard; f++) {
+                for (int f = 0; f < 6; f++) {
                     const int ax = f >> 1, dir = (f & 1) ? 1 : -1;
                     const int nx = sx + (ax == 0 ? dir : 0), ny = sy + (ax == 1 ? dir : 0),
                               nz = sz + (ax == 2 ? dir : 0);
-                    if (nx < 0 || nx >= k || ny < 0 || ny >= k || nz < 0 || nz >= k) continue;
-                    const int s2 = (nz * k + ny) * k + nx;
-                    if (!(submax[base + s2] > mykey)) continue;
-                    const int32_t t2 = subarg[base + s2];
-                    if (gkey[t2] == key && denser(dens_s[t2], orig_of(spos[t2]), di, oi)) is_hard = false;
+                    const bool in = nx >= 0 && nx < k && ny >= 0 && ny < k && nz >= 0 && nz < k;
+                    s2[f] = in ? (nz * k + ny) * k + nx : -1;
+                    mx[f] = in ? submax[base + s2[f]] : 0ull;
                 }
+                int32_t t2[6];
+#pragma unroll
+                for (int f = 0; f < 6; f++) t2[f] = mx[f] > mykey ? subarg[base + s2[f]] : -1;
+                int kt[6];
+                float dt[6];
+                uint32_t ot[6];
+#pragma unroll
+                for (int f = 0; f < 6; f++) {
+                    kt[f] = -1;
+                    dt[f] = 0.0f;
+                    ot[f] = 0u;
+                    if (t2[f] >= 0) {
+                        kt[f] = gkey[t2[f]];
+                        dt[f] = dens_s[t2[f]];
+                        ot[f] = orig_of(spos[t2[f]]);
+                    }
+                }
+#pragma unroll
+                for (int f = 0; f < 6; f++)
+                    if (t2[f] >= 0 && kt[f] == key && denser(dt[f], ot[f], di, oi)) is_hard = false;
             }
         }
     }

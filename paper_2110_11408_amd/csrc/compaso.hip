@@ -661,22 +661,37 @@ __global__ __launch_bounds__(kBlock) void k_assign(int64_t n, Boxes bx, const in
         const int nh = g_nh[gi];
         const float4 pi = spos[i];
         double eown = 0.0, iown = 0.0;
-        for (int h = 0; h < nh; h++) {
-            const double e = d2_exact(pi, spos[h_nuc[cs + h]], g.L, g.half);
-            const double ih = ii(h_ienc[cs + h]);
-            if (!(g.K2 * e3(e) < ih)) continue;
-            bool take;
-            if (own < 0) {
-                take = true;
-            } else {
-                const double lhs = ih * e3(eown);
-                const double rhs = (g.C3 * iown) * e3(e);
-                take = lhs >= rhs;
+        // the halos in creation order, four per round of loads (their
+        // nuclei, then the nuclei's positions)
+        for (int h0 = 0; h0 < nh; h0 += 4) {
+            int nuc[4], ienc[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                nuc[u] = h0 + u < nh ? h_nuc[cs + h0 + u] : 0;
+                ienc[u] = h0 + u < nh ? h_ienc[cs + h0 + u] : 0;
             }
-            if (take) {
-                own = (int)cs + h;
-                eown = e;
-                iown = ih;
+            float4 pn[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) pn[u] = h0 + u < nh ? spos[nuc[u]] : pi;
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                if (h0 + u >= nh) break;
+                const double e = d2_exact(pi, pn[u], g.L, g.half);
+                const double ih = ii(ienc[u]);
+                if (!(g.K2 * e3(e) < ih)) continue;
+                bool take;
+                if (own < 0) {
+                    take = true;
+                } else {
+                    const double lhs = ih * e3(eown);
+                    const double rhs = (g.C3 * iown) * e3(e);
+                    take = lhs >= rhs;
+                }
+                if (take) {
+                    own = (int)cs + h0 + u;
+                    eown = e;
+                    iown = ih;
+                }
             }
         }
     }
@@ -691,13 +706,25 @@ __global__ __launch_bounds__(kBlock) void k_out_flags(int64_t NC, Boxes bx, cons
                                                       const uint32_t *__restrict__ h_count,
                                                       const float4 *__restrict__ spos,
                                                       uint32_t *__restrict__ tflag,
+                                                      int32_t *__restrict__ h_label,
                                                       int32_t *__restrict__ counters) {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int nuc = s < NC ? h_nuc[s] : -1;
     const uint64_t b = __ballot(nuc >= 0);
     if ((threadIdx.x & 63) == 0 && b) atomicAdd(&counters[2], __popcll(b));
-    if (nuc < 0) return;
-    if (h_count[s] >= (uint32_t)bx.geo[box_of(bx, (uint32_t)nuc)].n_l1_min) tflag[orig_of(spos[nuc])] = 1u;
+    if (s >= NC) return;
+    // the label every member of this halo gets: 1 + its nucleus's index in
+    // the box when the halo is kept, else 0
+    int32_t lab = 0;
+    if (nuc >= 0) {
+        const Geo &g = bx.geo[box_of(bx, (uint32_t)nuc)];
+        if (h_count[s] >= (uint32_t)g.n_l1_min) {
+            const uint32_t o = orig_of(spos[nuc]);
+            tflag[o] = 1u;
+            lab = (int32_t)(o - g.orig_base) + 1;
+        }
+    }
+    h_label[s] = lab;
 }
 
 // Rows of the halo table of every box: the kept halos are flagged at their
@@ -745,22 +772,20 @@ __global__ __launch_bounds__(kBlock) void k_out_table(int64_t NC, Boxes bx, cons
 }
 
 __global__ __launch_bounds__(kBlock) void k_out_particles(int64_t n, Boxes bx, const int32_t *__restrict__ owner,
-                                                          const int32_t *__restrict__ h_nuc,
-                                                          const uint32_t *__restrict__ h_count,
+                                                          const int32_t *__restrict__ h_label,
                                                           const int32_t *__restrict__ gkey,
                                                           const float4 *__restrict__ spos,
                                                           int32_t *__restrict__ halo_id,
                                                           int32_t *__restrict__ l0_out) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const Geo &g = bx.geo[box_of(bx, (uint32_t)i)];
     const uint32_t o = orig_of(spos[i]);
-    int own = owner[i];
-    int32_t hid = 0;
-    if (own >= 0 && h_count[own] >= (uint32_t)g.n_l1_min)
-        hid = (int32_t)(orig_of(spos[h_nuc[own]]) - g.orig_base) + 1;
-    halo_id[o] = hid;
-    if (l0_out) l0_out[o] = gkey[i] < 0 ? 0 : gkey[i] + 1 - (int32_t)g.orig_base;
+    const int own = owner[i];
+    halo_id[o] = own >= 0 ? h_label[own] : 0;
+    if (l0_out) {
+        const Geo &g = bx.geo[box_of(bx, (uint32_t)i)];
+        l0_out[o] = gkey[i] < 0 ? 0 : gkey[i] + 1 - (int32_t)g.orig_base;
+    }
 }
 
 // Groups with candidates in descending size, for the acceptance kernels: keys
@@ -938,8 +963,10 @@ void launch_assign(int64_t n, const Boxes &bx, Work &w, hipStream_t s) {
 void launch_output_flags(int64_t n, int64_t NC, const Boxes &bx, Work &w, hipStream_t s) {
     fill_u32(w.tflag, 0u, n + 1, s);
     if (NC > 0)
+        // the candidates' member labels go to the hard-case list (free after
+        // the candidate stage)
         hipLaunchKernelGGL(k_out_flags, grid(NC), dim3(kBlock), 0, s, NC, bx, w.h_nuc, w.h_count, w.spos,
-                           w.tflag, w.counters);
+                           w.tflag, w.hardlist, w.counters);
     scan_u32(w.tflag, w.tpos, n, w.scan_tmp, s);
 }
 
@@ -950,8 +977,8 @@ void launch_output(int64_t n, int64_t NC, const Boxes &bx, Work &w, int32_t *hal
                            w.h_count, w.g_label, w.spos, w.tpos);
     if (box_rows)
         hipLaunchKernelGGL(k_box_rows, grid(bx.nbox), dim3(kBlock), 0, s, bx, w.tpos, box_rows);
-    hipLaunchKernelGGL(k_out_particles, grid(n), dim3(kBlock), 0, s, n, bx, w.owner, w.h_nuc, w.h_count,
-                       w.gkey, w.spos, halo_id, l0_out);
+    hipLaunchKernelGGL(k_out_particles, grid(n), dim3(kBlock), 0, s, n, bx, w.owner, w.hardlist, w.gkey, w.spos,
+                       halo_id, l0_out);
 }
 
 void launch_group_order(int64_t n, int64_t nrows, const int32_t *halo_id, Work &w, int32_t *members,

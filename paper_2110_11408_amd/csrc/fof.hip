@@ -182,12 +182,15 @@ __global__ __launch_bounds__(kBlock) void k_fof_phase_a(int64_t n, Boxes bx, con
         parent[i] = -1;
         return;
     }
-    if (f_sparse[i]) {
+    // a member's sparse flag, cell and sub-cell in one round of loads
+    const uint32_t sp = f_sparse[i];
+    const uint32_t c = __float_as_uint(sloc[i].w);
+    const int si = ssub[i];
+    if (sp) {
         parent[i] = (int32_t)i;
         return;
     }
-    const uint32_t c = __float_as_uint(sloc[i].w);
-    uint32_t f = subtab[(int64_t)cellmap[c] * (bx.nsub_max + 1) + ssub[i]];
+    uint32_t f = subtab[(int64_t)cellmap[c] * (bx.nsub_max + 1) + si];
     while (f < (uint32_t)i && !is_member(dens_s, f, g.dl0)) f++;
     parent[i] = (int32_t)f;
 }
