@@ -91,6 +91,15 @@ __device__ __forceinline__ void hooks_push(int32_t *parent, Hooks &h, int c, int
     h.n++;
 }
 
+// A root hint read from the forest, moved through the queued hooks in the
+// order they were queued: a hook's parent was a root of the wavefront's view
+// when queued, so only a later hook can move it again.
+__device__ __forceinline__ int hooks_map(const Hooks &h, int x) {
+    for (int k = 0; k < h.n; k++)
+        if (x == lane_get(h.c, k)) x = lane_get(h.p, k);
+    return x;
+}
+
 // A value equal in every lane, moved to a scalar register.
 __device__ __forceinline__ float uniform(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
@@ -167,32 +176,41 @@ __device__ __forceinline__ void test_candidates(int32_t *parent, Hooks &h, const
 // Phase A, which also initializes the forest: non-members get -1, members of
 // sparse cells are roots, and members of dense cells point at the first member
 // of their sub-cell (a valid forest: every parent is a member with a smaller
-// or equal sorted index).
+// or equal sorted index).  The first particle of every dense sub-cell also
+// records the sub-cell's first member (-1 if none) in submem, laid out like
+// the sub-cell table.
 __global__ __launch_bounds__(kBlock) void k_fof_phase_a(int64_t n, Boxes bx, const float4 *__restrict__ sloc,
                                                         const uint32_t *__restrict__ f_sparse,
                                                         const uint16_t *__restrict__ ssub,
                                                         const uint32_t *__restrict__ cellmap,
                                                         const uint32_t *__restrict__ subtab,
                                                         const float *__restrict__ dens_s,
-                                                        int32_t *__restrict__ parent) {
+                                                        int32_t *__restrict__ parent,
+                                                        int32_t *__restrict__ submem) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const Geo &g = bx.geo[box_of(bx, (uint32_t)i)];
-    if (!is_member(dens_s, i, g.dl0)) {
-        parent[i] = -1;
+    const bool mem = is_member(dens_s, i, g.dl0);
+    if (f_sparse[i]) {
+        parent[i] = mem ? (int32_t)i : -1;
         return;
     }
-    // a member's sparse flag, cell and sub-cell in one round of loads
-    const uint32_t sp = f_sparse[i];
     const uint32_t c = __float_as_uint(sloc[i].w);
-    const int si = ssub[i];
-    if (sp) {
-        parent[i] = (int32_t)i;
-        return;
+    const int64_t row = (int64_t)cellmap[c] * (bx.nsub_max + 1) + ssub[i];
+    const uint32_t u0 = subtab[row];
+    if (mem) {
+        uint32_t f = u0;
+        while (f < (uint32_t)i && !is_member(dens_s, f, g.dl0)) f++;
+        parent[i] = (int32_t)f;
+    } else {
+        parent[i] = -1;
     }
-    uint32_t f = subtab[(int64_t)cellmap[c] * (bx.nsub_max + 1) + si];
-    while (f < (uint32_t)i && !is_member(dens_s, f, g.dl0)) f++;
-    parent[i] = (int32_t)f;
+    if ((uint32_t)i == u0) {
+        const uint32_t u1 = subtab[row + 1];
+        uint32_t f = u0;
+        while (f < u1 && !is_member(dens_s, f, g.dl0)) f++;
+        submem[row] = f < u1 ? (int32_t)f : -1;
+    }
 }
 
 // Dense chunks, one wavefront each (lanes = the chunk's particles).  The wave
@@ -203,12 +221,15 @@ __global__ __launch_bounds__(kBlock) void k_fof_phase_a(int64_t n, Boxes bx, con
 // Neighbour particles are gathered 64 at a time (one per lane, shifted into
 // the chunk's cell frame) and tested one after the other against all lanes;
 // sets are joined in the wavefront's registers and the hooks applied to the
-// forest in bulk, before each round of sub-cells and at the end:
+// forest in bulk after every gather round with joins, before each round of
+// sub-cells and at the end (root hints read meanwhile are moved through the
+// queued hooks):
 //   sparse cells  all their particles, each member with its root;
 //   dense cells   their sub-cells, 64 at a time (one per lane): range, first
-//                 member and that member's root.  A sub-cell already in the
-//                 set of every lane is passed over (its members are one set);
-//                 the particles of the others are gathered in lane order.
+//                 member (recorded by phase A) and that member's root.  A
+//                 sub-cell already in the set of every lane is passed over
+//                 (its members are one set); the particles of the others are
+//                 gathered in lane order.
 __global__ __launch_bounds__(kBlock, 8) void k_fof_dense(int64_t nchunks, Boxes bx,
                                                       const int32_t *__restrict__ chunks,
                                                       const float4 *__restrict__ sloc,
@@ -216,6 +237,7 @@ __global__ __launch_bounds__(kBlock, 8) void k_fof_dense(int64_t nchunks, Boxes 
                                                       const uint32_t *__restrict__ off,
                                                       const uint32_t *__restrict__ cellmap,
                                                       const uint32_t *__restrict__ subtab,
+                                                      const int32_t *__restrict__ submem,
                                                       const float *__restrict__ dens_s,
                                                       int32_t *parent) {
     __shared__ int64_t dbase[kBlock / 64][27];  // visited dense cells: sub-table base
@@ -317,7 +339,7 @@ __global__ __launch_bounds__(kBlock, 8) void k_fof_dense(int64_t nchunks, Boxes 
                 qy = lj.y + (float)((t / 3) % 3 - 1) * g.cellb;
                 qz = lj.z + (float)(t / 9 - 1) * g.cellb;
             }
-            if (cmem) rc = uf_find_hint(parent, (int)jt);
+            if (cmem) rc = hooks_map(hk, uf_find_hint(parent, (int)jt));
             test_candidates(parent, hk, spos, g, active, li, h, wr, cmem, qx, qy, qz, jt, rc, no_rt);
         }
     }
@@ -327,7 +349,9 @@ __global__ __launch_bounds__(kBlock, 8) void k_fof_dense(int64_t nchunks, Boxes 
         const int ntask = nvisit * nsub;
         // (visited dense cell, sub-cell) pairs, 64 at a time
         for (int t0 = 0; t0 < ntask; t0 += 64) {
-            // the forest learns this chunk's joins so far, the lanes their roots
+            // the forest learns this chunk's joins so far, the lanes their
+            // current roots (a sub-cell joined meanwhile, by any chunk, is
+            // then passed over)
             hooks_apply(parent, hk);
             if (active) wr = uf_find_hint(parent, wr);
             const int tq = t0 + lane;
@@ -340,7 +364,9 @@ __global__ __launch_bounds__(kBlock, 8) void k_fof_dense(int64_t nchunks, Boxes 
                 const int ox = st % 3 - 1, oy = (st / 3) % 3 - 1, oz = st / 9 - 1;
                 uint32_t u0 = subtab[base + sl];
                 u1 = subtab[base + sl + 1];
-                if (st == 13 && u0 < h) u0 = h;  // own cell: from the chunk start on
+                const int32_t fm = submem[base + sl];
+                const bool cut = st == 13 && u0 < h;
+                if (cut) u0 = h;  // own cell: from the chunk start on
                 const int sx = sl % k, sy = (sl / k) % k, sz = sl / (k * k);
                 // sub-cell box (neighbour frame) shifted into the chunk's frame
                 const float ex = fmaxf(fmaxf(sx * subb + (float)ox * g.cellb - bx1,
@@ -349,17 +375,32 @@ __global__ __launch_bounds__(kBlock, 8) void k_fof_dense(int64_t nchunks, Boxes 
                                              by0 - ((sy + 1) * subb + (float)oy * g.cellb)), 0.0f);
                 const float ez = fmaxf(fmaxf(sz * subb + (float)oz * g.cellb - bz1,
                                              bz0 - ((sz + 1) * subb + (float)oz * g.cellb)), 0.0f);
-                if (ex * ex + ey * ey + ez * ez < g.l2b_hi + 1e-4f) {
-                    for (uint32_t j = u0; j < u1; j++)
-                        if (is_member(dens_s, j, g.dl0)) {
-                            fs = (int)j;
-                            break;
-                        }
+                if (ex * ex + ey * ey + ez * ez < g.l2b_hi + 1e-4f && u1 > u0) {
+                    // first member: recorded by phase A, searched where the
+                    // own cell's sub-cell is cut at the chunk start
+                    if (!cut) {
+                        fs = fm;
+                    } else {
+                        for (uint32_t j = u0; j < u1; j++)
+                            if (is_member(dens_s, j, g.dl0)) {
+                                fs = (int)j;
+                                break;
+                            }
+                    }
                 }
             }
-            int rt = fs >= 0 ? uf_find_hint(parent, fs) : -1;
+            int rt = fs >= 0 ? hooks_map(hk, uf_find_hint(parent, fs)) : -1;
             uint32_t pos = fs >= 0 ? (uint32_t)fs : 0u;  // next particle of the sub-cell to gather
-            for (;;) {
+            for (int gr = 0;; gr++) {
+                // after the joins of a gather round the forest learns them
+                // and the lanes and sub-cells read their current roots, so
+                // that sub-cells joined meanwhile (by this chunk or another)
+                // are passed over
+                if (gr > 0 && hk.n > 0) {
+                    hooks_apply(parent, hk);
+                    if (active) wr = uf_find_hint(parent, wr);
+                    if (rt >= 0) rt = uf_find_hint(parent, rt);
+                }
                 const int w0 = lane_get(wr, a0);
                 const int wcommon = __ballot(active && wr != w0) ? -2 : w0;
                 const uint32_t len = fs >= 0 && pos < u1 && rt != wcommon ? u1 - pos : 0u;
@@ -612,13 +653,15 @@ __global__ __launch_bounds__(kBlock) void k_keys_from_labels(int64_t n, Boxes bx
 }  // namespace
 
 void launch_fof(int64_t n, const Boxes &bx, Work &w, hipStream_t s) {
+    // the first members of the dense sub-cells go to the sub-cell maxima's
+    // argument table (free until the candidate stage)
     hipLaunchKernelGGL(k_fof_phase_a, grid(n), dim3(kBlock), 0, s, n, bx, w.sloc, w.f_sparse, w.ssub, w.cnt,
-                       w.subtab, w.dens_s, w.parent);
+                       w.subtab, w.dens_s, w.parent, w.subarg);
     if (w.nchunks > 0)
         // one wavefront per workgroup: chunk costs differ widely, and a
         // finished wavefront's slot is free at once
         hipLaunchKernelGGL(k_fof_dense, dim3((unsigned)w.nchunks), dim3(64), 0, s, w.nchunks, bx,
-                           w.chunks, w.sloc, w.spos, w.off, w.cnt, w.subtab, w.dens_s, w.parent);
+                           w.chunks, w.sloc, w.spos, w.off, w.cnt, w.subtab, w.subarg, w.dens_s, w.parent);
     if (w.nsparse > 0) {
         // sparse members: flags, positions and list in arrays that are free
         // during this stage (chunk flags of the binning, the hard-case list)
