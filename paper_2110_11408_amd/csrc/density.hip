@@ -9,7 +9,8 @@
 // particles of the cell.  The weights of 16 i-particles against 16 neighbours
 // come from one FP32 matrix-core product (the squared distance expanded into
 // a rank-4 inner product), so the vector ALU only clamps and sums; blocks of
-// 16 lanes that hold no particle are skipped.  The self pair is masked out and
+// 16 lanes that hold no particle are skipped, and the few particles of the
+// sparse neighbour cells are packed 16 to a block.  The self pair is masked out and
 // added back as exactly 1 when it counts.  Partial sums run in FP32 over
 // bounded stretches and are accumulated in FP64 in a fixed order, so the
 // result does not depend on the launch shape.
@@ -90,10 +91,11 @@ __device__ __forceinline__ float clamp0(float x) { return __int_as_float(max(__f
 // A[l % 16][l / 16] and B[l / 16][l % 16]; result register v of lane l is
 // D[4 (l / 16) + v][l % 16].  Lane l therefore sums, for the rows
 // 16 r + 4 (l / 16) + v, the neighbours in column l % 16; the 16 lanes of a
-// row group are reduced at the end.  Neighbours stream in blocks of 16
-// consecutive sorted particles per cell; a column past the cell's end gets
-// B = (., ., ., -1e30) and weighs 0 (pq is padded so that the load stays in
-// bounds).
+// row group are reduced at the end.  The neighbours of dense cells stream in
+// blocks of 16 consecutive sorted particles per cell; a column past the cell's
+// end gets B = (., ., ., -1e30) and weighs 0 (pq is padded so that the load
+// stays in bounds).  The particles of the sparse neighbour cells (fewer than
+// 8 each) share blocks instead, with the shift on their side.
 template <int R, bool kNarrow>
 __device__ __forceinline__ void density_chunk(const Geo &g, uint32_t h, uint32_t c, uint32_t end,
                                               const float *__restrict__ pq,
@@ -101,7 +103,8 @@ __device__ __forceinline__ void density_chunk(const Geo &g, uint32_t h, uint32_t
                                               const uint32_t *__restrict__ off,
                                               const uint32_t *__restrict__ s_sparse,
                                               uint64_t *__restrict__ dfx, float *__restrict__ dens_s,
-                                              float *__restrict__ dens_out, float *__restrict__ cl) {
+                                              float *__restrict__ dens_out, float *__restrict__ cl,
+                                              float4 *__restrict__ s_pk) {
     const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
     const int loff = 4 * col + grp;  // this lane's word of a block of 16 pq records
     // this lane's word of the block of 16 records from j0, as a buffer load
@@ -166,7 +169,9 @@ __device__ __forceinline__ void density_chunk(const Geo &g, uint32_t h, uint32_t
         rb = cend > tail ? cend : tail;
     }
     const uint64_t spm = __ballot(sp);
-    uint64_t todo = __ballot(lane < 28 && rb > ra);
+    // the dense ranges stream block by block; the sparse cells' few particles
+    // are packed 16 to a block below
+    uint64_t todo = __ballot(lane < 28 && rb > ra && !sp);
 
     // FP32 partials over at most 32 blocks.  A flush sums them over the 16
     // lanes of each row group (halving exchanges in a fixed order; afterwards
@@ -347,6 +352,33 @@ __device__ __forceinline__ void density_chunk(const Geo &g, uint32_t h, uint32_t
             }
             pre += cnt;
         }
+        // The chunk's rows against the sparse particles packed 16 to a block:
+        // the image shift goes to the neighbour side, B = (x_j + s, -|x_j +
+        // s|^2) in the chunk's cell-centred frame (staged in LDS, one particle
+        // per lane), A and the accumulator input are the rows' unshifted ones.
+        // For the pairs that count the terms stay below about 4 in magnitude,
+        // as in the blocks above.
+        {
+            const float4 qj = reinterpret_cast<const float4 *>(pq)[js];
+            const float x = qj.x + (float)(kc % 3 - 1) * g.cellb, y = qj.y + (float)((kc / 3) % 3 - 1) * g.cellb,
+                        z = qj.z + (float)(kc / 9 - 1) * g.cellb;
+            s_pk[lane] = make_float4(x, y, z, q < ntot ? -(x * x + y * y + z * z) : -1e30f);
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            const uint32_t nb = min(ntot - p0, 64u);
+            for (uint32_t b0 = 0; b0 < nb; b0 += 16) {
+                const float4 e = s_pk[b0 + (uint32_t)col];
+                const float bv = grp == 0 ? e.x : (grp == 1 ? e.y : (grp == 2 ? e.z : e.w));
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x4f32(A[r], bv, Cget(r), 0, 0, 0);
+#pragma unroll
+                    for (int u = 0; u < 4; u++) pf[4 * r + u] += clamp0(d[u]);
+                }
+                flush();
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
         // the sparse particle's image in the chunk's frame
         const float4 pj = spos[js];
         const Pos64 pjm{(double)pj.x + image_shift(cx, kc % 3 - 1, g.nc, g.L),
@@ -389,11 +421,12 @@ __global__ __launch_bounds__(64, 6) void k_density_dense(int64_t nchunks, Boxes 
     const uint32_t cend = __builtin_amdgcn_readfirstlane(off[c + 1]);
     const uint32_t end = min(h + 64u, cend);
     const float *p = reinterpret_cast<const float *>(pq);
-    // the rows' accumulator inputs
+    // the rows' accumulator inputs, and the packed sparse neighbours
     __shared__ float cl[16 * 64];
+    __shared__ float4 s_pk[64];
 #define HF_DENSITY_CHUNK(RR)                                                                        \
-    (narrow ? density_chunk<RR, true>(g, h, c, end, p, spos, off, s_sparse, dfx, dens_s, dens_out, cl) \
-            : density_chunk<RR, false>(g, h, c, end, p, spos, off, s_sparse, dfx, dens_s, dens_out, cl))
+    (narrow ? density_chunk<RR, true>(g, h, c, end, p, spos, off, s_sparse, dfx, dens_s, dens_out, cl, s_pk) \
+            : density_chunk<RR, false>(g, h, c, end, p, spos, off, s_sparse, dfx, dens_s, dens_out, cl, s_pk))
     switch ((end - h + 15u) >> 4) {
     case 1: HF_DENSITY_CHUNK(1); break;
     case 2: HF_DENSITY_CHUNK(2); break;
