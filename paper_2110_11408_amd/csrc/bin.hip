@@ -12,7 +12,9 @@
 //      gives every (digit, tile) its output offset; the tile is then walked
 //      again in order, each element's rank among equal digits coming from the
 //      ballots of its digit bits (lower lanes first), so the pass is stable,
-//      and written out through LDS in digit order (coalesced runs);
+//      and written out through LDS in digit order (coalesced runs).
+//      Consecutive tiles run on one XCD, so the runs that consecutive tiles
+//      write for a digit (adjacent in the output) meet in one L2;
 //   3. the sorted order writes two float4 streams per particle:
 //        spos = (x, y, z, original index bits)    -- the paper's float quad with
 //               the index stored bitwise (Sec. 2.3.3), used by FP64 predicates;
@@ -106,7 +108,7 @@ __global__ __launch_bounds__(256) void k_radix_count(const uint64_t *__restrict_
                                                      int D, int64_t ntiles, uint32_t *__restrict__ hist) {
     __shared__ uint32_t h[1 << kRadixMaxBits];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t t = blockIdx.x;
+    const int64_t t = xcd_block();
     const int nd = 1 << D;
     for (int d = threadIdx.x; d < nd; d += 256) h[d] = 0u;
     const int64_t base = t * kTile + (int64_t)w * (64 * kRadixIters) + lane;
@@ -160,7 +162,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t *__restric
     __shared__ uint64_t sk[kTile];
     __shared__ uint32_t sv[kPacked ? 1 : kTile];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, tid = threadIdx.x;
-    const int64_t t = blockIdx.x;
+    const int64_t t = xcd_block();
     const int nd = 1 << D;
     const uint32_t dmask = (uint32_t)(nd - 1);
     for (int d = lane; d < nd; d += 64) o[w][d] = 0u;
