@@ -135,13 +135,15 @@ __device__ __forceinline__ void join_local(int32_t *parent, Hooks &h, bool lk, i
 }
 
 // Tests the member candidates of a batch (lane p: candidate p) against the
-// chunk's lanes, then joins their sets.  A candidate holds whether it is a
+// chunk's lanes and joins their sets.  A candidate holds whether it is a
 // member, its coordinates in the chunk's cell frame (units of b), its index
-// and its local root rc.  The tests run with the candidates in the lanes and
-// the chunk's particles broadcast one after the other (both sides are mostly
-// far below 64); each candidate collects the chunk lanes it links as a bit
-// mask.  The joins then take the linked candidates one after the other.  A
-// candidate already in the set of every lane needs no test.
+// and its local root rc; a candidate already in the set of every lane needs no
+// test.  The loop runs over the smaller side: with fewer candidates than chunk
+// particles, each candidate is broadcast to the chunk's lanes and joined to
+// the lanes it links at once; otherwise the candidates stay in the lanes, the
+// chunk's particles are broadcast one after the other (each candidate
+// collecting a bit mask of the lanes it links), and the linked candidates are
+// joined one after the other.
 __device__ __forceinline__ void test_candidates(int32_t *parent, Hooks &h, const float4 *__restrict__ spos,
                                                 const Geo &g, bool active, const float4 &li, uint32_t h0,
                                                 int &wr, bool cmem, float qx, float qy, float qz, uint32_t cj,
@@ -151,7 +153,21 @@ __device__ __forceinline__ void test_candidates(int32_t *parent, Hooks &h, const
     const int w0 = lane_get(wr, (int)__builtin_ctzll(am));
     const bool common = !__ballot(active && wr != w0);
     const bool need = cmem && !(common && rc == w0);
-    if (!__ballot(need)) return;
+    const uint64_t nm = __ballot(need);
+    if (!nm) return;
+    if (__popcll(nm) < __popcll(am)) {
+        for (uint64_t mm = nm; mm; mm &= mm - 1) {
+            const int J = (int)__builtin_ctzll(mm);
+            const int r = lane_get(rc, J);
+            if (!__ballot(active && wr != r)) continue;
+            const float dx = lane_get(qx, J) - li.x, dy = lane_get(qy, J) - li.y, dz = lane_get(qz, J) - li.z;
+            const float d2f = d2_f32(dx, dy, dz);
+            bool lk = active && wr != r && d2f < g.l2b_hi;
+            if (lk && !(d2f < g.l2b_lo)) lk = d2_exact(spos[h0 + (uint32_t)lane], spos[lane_get(cj, J)], g.L, g.half) < g.l2;
+            if (__ballot(lk)) join_local(parent, h, lk, r, wr, rc, rt);
+        }
+        return;
+    }
     uint32_t lo = 0u, hi = 0u;  // linked chunk lanes 0..31 and 32..63
     for (uint64_t m = am; m; m &= m - 1) {
         const int I = (int)__builtin_ctzll(m);
