@@ -186,7 +186,8 @@ __global__ __launch_bounds__(kBlock) void k_cand_quick(int64_t n, Boxes bx, cons
                 // the six face-adjacent sub-cells at once: their maxima, then
                 // the particles that hold them, then those particles' keys
                 const int k = g.ksub;
-                const int sx = si % k, sy = (si / k) % k, sz = si / (k * k);
+                const int sz = div_small(si, 1.0f / (float)(k * k)), syx = si - sz * k * k,
+                          sy = div_small(syx, 1.0f / (float)k), sx = syx - sy * k;
                 const uint64_t mykey = dkey(di, oi);
                 int s2[6];
                 uint64_t mx[6];
@@ -250,7 +251,7 @@ __device__ bool has_denser_within_b(int i, int tt0, int tt1, const Geo &g, int t
     const uint64_t mykey = dkey(di, oi);
     const uint32_t c = __float_as_uint(li.w);
     const int k = g.ksub, nsub = g.nsub;
-    const float subb = g.cellb / (float)k;
+    const float subb = g.cellb / (float)k, inv_k = 1.0f / (float)k, inv_k2 = 1.0f / (float)(k * k);
     int cx, cy, cz;
     cell_xyz(g, c, cx, cy, cz);
     for (int tt = tt0; tt < tt1; tt++) {
@@ -293,7 +294,8 @@ __device__ bool has_denser_within_b(int i, int tt0, int tt1, const Geo &g, int t
             for (int u = 0; u < 3; u++) {
                 const int s2 = s0 + u;
                 if (!(mx[u] > mykey)) continue;
-                const int sx = s2 % k, sy = (s2 / k) % k, sz = s2 / (k * k);
+                const int sz = div_small(s2, inv_k2), syx = s2 - sz * k * k, sy = div_small(syx, inv_k),
+                          sx = syx - sy * k;
                 const float ex = fmaxf(fmaxf(sx * subb - 1e-5f - xs, xs - (sx + 1) * subb - 1e-5f), 0.0f);
                 const float ey = fmaxf(fmaxf(sy * subb - 1e-5f - ys, ys - (sy + 1) * subb - 1e-5f), 0.0f);
                 const float ez = fmaxf(fmaxf(sz * subb - 1e-5f - zs, zs - (sz + 1) * subb - 1e-5f), 0.0f);
@@ -466,14 +468,15 @@ __global__ __launch_bounds__(kBlock) void k_cand_wave(const uint32_t *__restrict
         for (int t0 = 0; t0 < ntask; t0 += 64) {
             const int tq = t0 + lane;
             if (tq < ntask) {
-                const int r = tq / nsub, sl = tq - r * nsub;
+                const int r = div_small(tq, 1.0f / (float)nsub), sl = tq - r * nsub;
                 const int64_t base = s_base[wave][r];
                 if (submax[base + sl] > mykey) {
                     int ox, oy, oz;
                     stencil_offset(s_tt[wave][r], ox, oy, oz);
                     const float txs = li.x - (float)ox * g.cellb, tys = li.y - (float)oy * g.cellb,
                                 tzs = li.z - (float)oz * g.cellb;
-                    const int sx = sl % k, sy = (sl / k) % k, sz = sl / (k * k);
+                    const int sz = div_small(sl, 1.0f / (float)(k * k)), syx = sl - sz * k * k,
+                              sy = div_small(syx, 1.0f / (float)k), sx = syx - sy * k;
                     const float ex = fmaxf(fmaxf(sx * subb - 1e-5f - txs, txs - (sx + 1) * subb - 1e-5f), 0.0f);
                     const float ey = fmaxf(fmaxf(sy * subb - 1e-5f - tys, tys - (sy + 1) * subb - 1e-5f), 0.0f);
                     const float ez = fmaxf(fmaxf(sz * subb - 1e-5f - tzs, tzs - (sz + 1) * subb - 1e-5f), 0.0f);

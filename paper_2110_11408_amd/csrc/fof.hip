@@ -105,11 +105,6 @@ __device__ __forceinline__ float uniform(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
-__device__ __forceinline__ int wave_min(int v) {
-    for (int d = 32; d >= 1; d >>= 1) v = min(v, __shfl_xor(v, d, 64));
-    return v;
-}
-
 // The lanes lk are linked to a particle whose set has the local root r.  In
 // the wavefront's view of the forest (every root it holds is a node of its
 // set), the smallest of r and the lanes' roots becomes the root of all of
@@ -117,7 +112,14 @@ __device__ __forceinline__ int wave_min(int v) {
 // wavefront holds to one of them (lane roots wr, candidate roots rc, task
 // roots rt) is moved to it.
 __device__ __forceinline__ void join_local(int32_t *parent, Hooks &h, bool lk, int r, int &wr, int &rc, int &rt) {
-    const int m = min(r, wave_min(lk ? wr : 0x7fffffff));
+    // the smallest root: one step per distinct root among the linked lanes
+    // (rarely more than one or two), with no cross-lane shuffle
+    int m = r;
+    for (uint64_t mask = __ballot(lk); mask;) {
+        const int x = lane_get(wr, (int)__builtin_ctzll(mask));
+        m = min(m, x);
+        mask &= ~__ballot(wr == x);
+    }
     if (r != m) {
         hooks_push(parent, h, r, m);
         if (wr == r) wr = m;
@@ -363,6 +365,7 @@ __global__ __launch_bounds__(kBlock, 8) void k_fof_dense(int64_t nchunks, Boxes 
         __builtin_amdgcn_wave_barrier();
         const int a0 = (int)__builtin_ctzll(__ballot(active));
         const int ntask = nvisit * nsub;
+        const float inv_nsub = 1.0f / (float)nsub, inv_k = 1.0f / (float)k, inv_k2 = 1.0f / (float)(k * k);
         // (visited dense cell, sub-cell) pairs, 64 at a time
         for (int t0 = 0; t0 < ntask; t0 += 64) {
             // the forest learns this chunk's joins so far, the lanes their
@@ -374,7 +377,7 @@ __global__ __launch_bounds__(kBlock, 8) void k_fof_dense(int64_t nchunks, Boxes 
             uint32_t u1 = 0;
             int fs = -1, st = 0;
             if (tq < ntask) {
-                const int r = tq / nsub, sl = tq - r * nsub;
+                const int r = div_small(tq, inv_nsub), sl = tq - r * nsub;
                 st = doff[wave][r];
                 const int64_t base = dbase[wave][r];
                 const int ox = st % 3 - 1, oy = (st / 3) % 3 - 1, oz = st / 9 - 1;
@@ -383,7 +386,8 @@ __global__ __launch_bounds__(kBlock, 8) void k_fof_dense(int64_t nchunks, Boxes 
                 const int32_t fm = submem[base + sl];
                 const bool cut = st == 13 && u0 < h;
                 if (cut) u0 = h;  // own cell: from the chunk start on
-                const int sx = sl % k, sy = (sl / k) % k, sz = sl / (k * k);
+                const int sz = div_small(sl, inv_k2), syx = sl - sz * k * k, sy = div_small(syx, inv_k),
+                          sx = syx - sy * k;
                 // sub-cell box (neighbour frame) shifted into the chunk's frame
                 const float ex = fmaxf(fmaxf(sx * subb + (float)ox * g.cellb - bx1,
                                              bx0 - ((sx + 1) * subb + (float)ox * g.cellb)), 0.0f);

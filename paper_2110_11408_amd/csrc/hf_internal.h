@@ -141,6 +141,13 @@ __device__ __forceinline__ float lane_get(float v, int L) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), L));
 }
 
+// a / d for 0 <= a < 2^16 and 1 <= d <= 256 from FP32, given inv_d = 1/d:
+// (a + 1/2) / d is at least 1/(2d) away from every integer and its FP32
+// product with inv_d is within a few ulps of it, far less, so the truncation
+// is the integer quotient (a few instructions instead of an integer division
+// by a variable; checked exhaustively over that range).
+__device__ __forceinline__ int div_small(int a, float inv_d) { return (int)(((float)a + 0.5f) * inv_d); }
+
 __device__ __forceinline__ int wrapc(int c, int nc) {
     return c < 0 ? c + nc : (c >= nc ? c - nc : c);
 }
