@@ -118,6 +118,7 @@ hf_status make_geo(Lane *c, const hf_params *p, int64_t n, Geo *g) {
     g->half = 0.5 * L;
     g->cell = L / g->nc;
     g->inv_cell = (double)g->nc / L;
+    g->inv_nc = 1.0 / (double)g->nc;
     g->inv_b = 1.0 / d[D_B];
     g->inv_b2 = 1.0 / d[D_B2];
     g->cellb = (float)(g->cell / d[D_B]);

@@ -21,6 +21,7 @@ struct Geo {
     double inv_b2;         // 1/b^2: FP64 kernel weights 1 - r^2/b^2
     float cellb;           // cell / b in FP32 (image offset of a neighbour cell)
     int nc;                // cells per side (>= 3)
+    double inv_nc;         // 1 / nc (cell coordinates from a cell id)
     int ksub;              // sub-cells per cell side (sub-cell diagonal < l)
     int nsub;              // ksub^3
     int rsub;              // FoF reach in sub-cells: ceil(l / sub-cell side)
@@ -152,12 +153,25 @@ __device__ __forceinline__ int wrapc(int c, int nc) {
     return c < 0 ? c + nc : (c >= nc ? c - nc : c);
 }
 
+// x / nc for a cell id x < 2^32: the FP64 product with 1/nc is within far
+// less than one of x / nc (x is exact in FP64), so its truncation is the
+// quotient or one below it; one comparison corrects that (and, for safety, one
+// above).
+__device__ __forceinline__ uint32_t div_nc(uint32_t x, const Geo &g) {
+    uint32_t q = (uint32_t)((double)x * g.inv_nc);
+    const uint64_t nc = (uint64_t)g.nc;
+    if ((uint64_t)(q + 1) * nc <= (uint64_t)x) q++;
+    else if ((uint64_t)q * nc > (uint64_t)x) q--;
+    return q;
+}
+
 // Coordinates inside its box of cell c (the call's numbering) of box g.
 __device__ __forceinline__ void cell_xyz(const Geo &g, uint32_t c, int &cx, int &cy, int &cz) {
     const uint32_t lc = c - g.cell_base, nc = (uint32_t)g.nc;
-    cx = (int)(lc % nc);
-    cy = (int)((lc / nc) % nc);
-    cz = (int)(lc / (nc * nc));
+    const uint32_t q = div_nc(lc, g), q2 = div_nc(q, g);
+    cx = (int)(lc - q * nc);
+    cy = (int)(q - q2 * nc);
+    cz = (int)q2;
 }
 
 // The cell at coordinates (x, y, z) of box g, each wrapped once (one cell
