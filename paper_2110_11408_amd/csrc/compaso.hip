@@ -779,12 +779,18 @@ __global__ __launch_bounds__(kBlock) void k_out_particles(int64_t n, Boxes bx, c
                                                           int32_t *__restrict__ l0_out) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const uint32_t o = orig_of(spos[i]);
     const int own = owner[i];
-    halo_id[o] = own >= 0 ? h_label[own] : 0;
+    const int32_t lab = own >= 0 ? h_label[own] : 0;
+    // halo_id was filled with 0: only the members of kept halos are written
+    // (scattered stores into the input order, so the fewer the better), and
+    // their original index is read only for them
     if (l0_out) {
+        const uint32_t o = orig_of(spos[i]);
+        if (lab) halo_id[o] = lab;
         const Geo &g = bx.geo[box_of(bx, (uint32_t)i)];
         l0_out[o] = gkey[i] < 0 ? 0 : gkey[i] + 1 - (int32_t)g.orig_base;
+    } else if (lab) {
+        halo_id[orig_of(spos[i])] = lab;
     }
 }
 
@@ -977,6 +983,7 @@ void launch_output(int64_t n, int64_t NC, const Boxes &bx, Work &w, int32_t *hal
                            w.h_count, w.g_label, w.spos, w.tpos);
     if (box_rows)
         hipLaunchKernelGGL(k_box_rows, grid(bx.nbox), dim3(kBlock), 0, s, bx, w.tpos, box_rows);
+    fill_i32(halo_id, 0, n, s);
     hipLaunchKernelGGL(k_out_particles, grid(n), dim3(kBlock), 0, s, n, bx, w.owner, w.hardlist, w.gkey, w.spos,
                        halo_id, l0_out);
 }
