@@ -401,11 +401,11 @@ __global__ __launch_bounds__(kBlock) void k_bin_lists(int64_t n, const uint32_t 
 }
 
 // Sub-cell table of one dense cell d, by one wavefront: entry s is the first
-// particle of the cell whose sub-cell is s or later, that is the cell start
-// plus the number of its particles in sub-cells below s (an empty sub-cell
-// gets the start of the next non-empty one; entry nsub is the cell end).  The
-// cell's particles are sorted by sub-cell; each 64-particle step counts, for
-// 64 values of s at a time, the particles below s by ballot.
+// particle of the cell whose sub-cell is s or later (an empty sub-cell gets
+// the start of the next non-empty one; entry nsub is the cell end).  The
+// cell's particles are sorted by sub-cell, so particle j writes the entries
+// after its predecessor's sub-cell up to its own, and the entries after the
+// last particle's sub-cell get the cell end; every entry is written once.
 __device__ __forceinline__ void sub_table_cell(int64_t d, const Boxes &bx, const uint32_t *__restrict__ dcells,
                                                const uint32_t *__restrict__ off,
                                                const uint16_t *__restrict__ ssub,
@@ -416,18 +416,15 @@ __device__ __forceinline__ void sub_table_cell(int64_t d, const Boxes &bx, const
     const uint32_t b = (uint32_t)__builtin_amdgcn_readfirstlane(off[c + 1]);
     const int nsub = __builtin_amdgcn_readfirstlane(bx.geo[box_of(bx, a)].nsub);
     uint32_t *t = subtab + d * (bx.nsub_max + 1);
-    for (int s0 = 0; s0 <= nsub; s0 += 64) {
-        const int ns = min(64, nsub + 1 - s0);
-        uint32_t below = 0;  // for s = s0 + lane
-        for (uint32_t j0 = a; j0 < b; j0 += 64) {
-            const uint32_t j = j0 + (uint32_t)lane;
-            const int v = j < b ? (int)ssub[j] : 0x7fffffff;
-            for (int u = 0; u < ns; u++) {
-                const uint32_t cnt = (uint32_t)__popcll(__ballot(v < s0 + u));
-                if (lane == u) below += cnt;
-            }
+    for (uint32_t j0 = a; j0 < b; j0 += 64) {
+        const uint32_t j = j0 + (uint32_t)lane;
+        if (j < b) {
+            const int cur = ssub[j];
+            const int prev = j > a ? (int)ssub[j - 1] : -1;
+            for (int s2 = prev + 1; s2 <= cur; s2++) t[s2] = j;
+            if (j + 1 == b)
+                for (int s2 = cur + 1; s2 <= nsub; s2++) t[s2] = b;
         }
-        if (lane < ns) t[s0 + lane] = a + below;
     }
 }
 
