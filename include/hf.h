@@ -323,8 +323,12 @@ hf_status hf_batch_groups(const hf_ctx *ctx, int32_t n_boxes, int64_t total, int
  * A free slot takes the oldest waiting request when the device memory of all
  * slots, with this request's need, stays within hbm_budget_bytes (idle slots
  * give their memory back when that makes it fit); requests therefore overlap
- * on the GPU while the budget allows.  Each request's result is identical to
- * hf_find on the same box alone. */
+ * on the GPU while the budget allows.  When several requests of at most 4 Mi
+ * particles wait, the slot takes them together (up to 16 Mi particles, 32
+ * requests, and the sum of their needs within the budget) and finds them in
+ * one fused pass, as hf_find_batch does; a single waiting request runs alone.
+ * Each request's result is identical to hf_find on the same box alone; the
+ * requests of one pass share its t_start, t_done and ms_gpu. */
 typedef struct hf_server hf_server;
 
 typedef struct {

@@ -335,6 +335,15 @@ struct Pending {
     size_t need;
 };
 
+// Requests of at most kFuseBox particles that wait together are found in one
+// fused pass (the pass of hf_find_batch), up to kFuseTotal particles and
+// kFuseCount requests: small boxes alone cannot fill the GPU.  A slot that
+// frees up with a single request waiting runs it alone, so at low load no
+// request waits for others.
+constexpr int64_t kFuseBox = (int64_t)4 << 20;
+constexpr int64_t kFuseTotal = (int64_t)16 << 20;
+constexpr size_t kFuseCount = 32;
+
 struct Slot {
     hf::Lane lane;
     void *io = nullptr;  // device copies of the request's input and outputs
@@ -406,6 +415,7 @@ struct hf_server {
         return false;
     }
     void run(int t, const Pending &q, hf_result &res);
+    void run_fused(int t, const std::vector<Pending> &qs, std::vector<hf_result> &res);
     void worker(int t);
 };
 
@@ -461,27 +471,146 @@ void hf_server::run(int t, const Pending &q, hf_result &res) {
     res.status = HF_OK;
 }
 
+// Requests qs (two or more) as one fused pass on slot t: their positions laid
+// end to end in the slot's buffers, one box each, then every request's outputs
+// copied back.  A box's outputs are those of hf_find on it alone; a request
+// whose halo table is too small gets HF_ERR_CAPACITY (its halo_id is still
+// written).  Any other failure of the pass runs the requests one by one, so
+// that each gets its own status.
+void hf_server::run_fused(int t, const std::vector<Pending> &qs, std::vector<hf_result> &res) {
+    Slot &sl = *slots[t];
+    hf::Lane *L = &sl.lane;
+    const hipStream_t s = L->stream;
+    const size_t nb = qs.size();
+    std::vector<int64_t> offs(nb + 1, 0), hoffs(nb + 1, 0), nh(nb, 0);
+    std::vector<hf_params> params(nb);
+    for (size_t b = 0; b < nb; b++) {
+        offs[b + 1] = offs[b] + qs[b].r.n;
+        hoffs[b + 1] = hoffs[b] + (qs[b].r.halos_cap > 0 ? qs[b].r.halos_cap : 0);
+        params[b] = qs[b].r.params;
+    }
+    const size_t n = (size_t)offs[nb];
+    const size_t iob = round256(12 * n) + round256(4 * n) * 3 +
+                       round256(sizeof(hf_halo) * (size_t)(hoffs[nb] > 0 ? hoffs[nb] : 1));
+    auto alone = [&] {
+        for (size_t b = 0; b < nb; b++) run(t, qs[b], res[b]);
+    };
+    if (iob > sl.io_bytes) {
+        if (sl.io) (void)hipFree(sl.io);
+        sl.io = nullptr;
+        sl.io_bytes = 0;
+        if (hipMalloc(&sl.io, iob) != hipSuccess) {
+            (void)hipGetLastError();
+            sl.io = nullptr;
+            return alone();
+        }
+        sl.io_bytes = iob;
+    }
+    char *base = (char *)sl.io;
+    float *pos_d = (float *)base;
+    float *dens_d = (float *)(base + round256(12 * n));
+    int32_t *l0_d = (int32_t *)(base + round256(12 * n) + round256(4 * n));
+    int32_t *halo_d = (int32_t *)(base + round256(12 * n) + 2 * round256(4 * n));
+    hf_halo *halos_d = (hf_halo *)(base + round256(12 * n) + 3 * round256(4 * n));
+    bool ok = true;
+    for (size_t b = 0; b < nb; b++)
+        if (qs[b].r.n > 0)
+            ok &= hipMemcpyAsync(pos_d + 3 * offs[b], qs[b].r.pos, 12 * (size_t)qs[b].r.n, hipMemcpyHostToDevice,
+                                 s) == hipSuccess;
+    if (!ok) return alone();
+    bool want_d = false, want_l0 = false;
+    for (const Pending &q : qs) {
+        want_d |= q.r.density != nullptr;
+        want_l0 |= q.r.l0_id != nullptr;
+    }
+    hf::BoxSet bs{(int32_t)nb, offs.data(), params.data(), hoffs[nb] > 0 ? halos_d : nullptr, hoffs.data()};
+    bs.named = true;
+    const hf_status st = hf::lane_find_boxes(L, bs, n ? pos_d : nullptr, want_d ? dens_d : nullptr,
+                                             want_l0 ? l0_d : nullptr, halo_d, nh.data(), s);
+    if (st != HF_OK && st != HF_ERR_CAPACITY) return alone();
+    for (size_t b = 0; b < nb; b++) {
+        const hf_request &r = qs[b].r;
+        const size_t o = (size_t)offs[b], m = (size_t)r.n;
+        res[b].n_halos = nh[b];
+        res[b].ms_gpu = L->stats.ms_total;
+        if (m > 0) {
+            ok &= hipMemcpyAsync(r.halo_id, halo_d + o, 4 * m, hipMemcpyDeviceToHost, s) == hipSuccess;
+            if (r.density)
+                ok &= hipMemcpyAsync(r.density, dens_d + o, 4 * m, hipMemcpyDeviceToHost, s) == hipSuccess;
+            if (r.l0_id) ok &= hipMemcpyAsync(r.l0_id, l0_d + o, 4 * m, hipMemcpyDeviceToHost, s) == hipSuccess;
+        }
+        const bool fits = nh[b] <= (r.halos_cap > 0 ? r.halos_cap : 0);
+        if (fits && nh[b] > 0)
+            ok &= hipMemcpyAsync(r.halos, halos_d + hoffs[b], sizeof(hf_halo) * (size_t)nh[b],
+                                 hipMemcpyDeviceToHost, s) == hipSuccess;
+        res[b].status = fits ? HF_OK : HF_ERR_CAPACITY;
+        if (!fits)
+            strncpy(res[b].error, "halos_cap too small: n_halos holds the required capacity",
+                    sizeof(res[b].error) - 1);
+    }
+    ok &= hipStreamSynchronize(s) == hipSuccess;
+    if (!ok)
+        for (size_t b = 0; b < nb; b++) {
+            res[b].status = HF_ERR_DEVICE;
+            strncpy(res[b].error, "copy of the results to the host failed", sizeof(res[b].error) - 1);
+        }
+}
+
 void hf_server::worker(int t) {
     (void)hipSetDevice(device);
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {
         while (!(stop && queue.empty()) && (queue.empty() || slots[t]->busy || !admit(t))) cv_work.wait(lk);
         if (queue.empty()) break;  // stopping and nothing left
-        Pending q = queue.front();
+        std::vector<Pending> qs{queue.front()};
         queue.pop_front();
-        slots[t]->reserved = std::max(slots[t]->held(), q.need);
-        slots[t]->busy = true;
+        // more small requests that wait, while their sum stays within the
+        // fusion limits and, with their needs added up, within the budget
+        size_t need = qs[0].need;
+        int64_t total = qs[0].r.n, cells = 0;
+        Slot &me = *slots[t];
+        auto box_cells = [](const hf_request &r) -> int64_t {
+            if (r.n <= 0) return 0;
+            const int64_t o2[2] = {0, r.n};
+            int64_t nt = 0, cb = 0;
+            hf::boxes_arena_bytes(hf::BoxSet{1, o2, &r.params, nullptr, nullptr}, &nt, &cb);
+            return cb;
+        };
+        if (qs[0].r.n <= kFuseBox && !queue.empty()) cells = box_cells(qs[0].r);
+        while (qs[0].r.n <= kFuseBox && !queue.empty() && qs.size() < kFuseCount) {
+            const Pending &nx = queue.front();
+            if (nx.r.n > kFuseBox || total + nx.r.n > kFuseTotal) break;
+            const int64_t cb = box_cells(nx.r);
+            if (cells + cb >= ((int64_t)1 << 31)) break;
+            if (held_total() - me.charged() + std::max(me.held(), need + nx.need) > budget) break;
+            qs.push_back(nx);
+            queue.pop_front();
+            need += nx.need;
+            total += nx.r.n;
+            cells += cb;
+        }
+        me.reserved = std::max(me.held(), need);
+        me.busy = true;
         lk.unlock();
-        hf_result res;
-        memset(&res, 0, sizeof(res));
-        res.slot = t;
-        res.t_submit = q.t_submit;
-        res.t_start = now();
-        run(t, q, res);
-        res.t_done = now();
+        std::vector<hf_result> res(qs.size());
+        const double t_start = now();
+        for (size_t b = 0; b < qs.size(); b++) {
+            memset(&res[b], 0, sizeof(hf_result));
+            res[b].slot = t;
+            res[b].t_submit = qs[b].t_submit;
+            res[b].t_start = t_start;
+        }
+        if (qs.size() == 1)
+            run(t, qs[0], res[0]);
+        else
+            run_fused(t, qs, res);
+        const double t_done = now();
         lk.lock();
-        slots[t]->busy = false;
-        done[q.ticket] = res;
+        me.busy = false;
+        for (size_t b = 0; b < qs.size(); b++) {
+            res[b].t_done = t_done;
+            done[qs[b].ticket] = res[b];
+        }
         cv_done.notify_all();
         cv_work.notify_all();
     }
