@@ -241,7 +241,11 @@ __global__ __launch_bounds__(kBlock) void k_extent_span(const uint32_t *__restri
 __device__ __forceinline__ int64_t bucket_of(double T, int64_t m) {
     if (!(T > 0.0)) return 0;
     if (m <= 1 || T > ii(m - 1)) return m;
-    int64_t k = (int64_t)ceil(sqrt(T));
+    // the loops below reach the exact k from any start in [0, m - 1]: the
+    // start only sets their length, so it comes from the FP32 square root
+    // (T < 2^62 here; within a few units of k below 2^23, one or two steps),
+    // not from the much longer FP64 one
+    int64_t k = (int64_t)ceilf(__builtin_amdgcn_sqrtf((float)T));
     if (k > m - 1) k = m - 1;
     if (k < 0) k = 0;
     while (k > 0 && T <= ii(k - 1)) k--;
@@ -771,27 +775,49 @@ __global__ __launch_bounds__(kBlock) void k_out_table(int64_t NC, Boxes bx, cons
     g.halos[tpos[o] - b0] = h;
 }
 
-__global__ __launch_bounds__(kBlock) void k_out_particles(int64_t n, Boxes bx, const int32_t *__restrict__ owner,
+// Only the halo labels to return: halo_id was filled with 0, and only the
+// members of kept halos are written (scattered stores into the input order,
+// so the fewer the better; their original index is read only for them).
+__global__ __launch_bounds__(kBlock) void k_out_particles(int64_t n, const int32_t *__restrict__ owner,
                                                           const int32_t *__restrict__ h_label,
-                                                          const int32_t *__restrict__ gkey,
                                                           const float4 *__restrict__ spos,
-                                                          int32_t *__restrict__ halo_id,
-                                                          int32_t *__restrict__ l0_out) {
+                                                          int32_t *__restrict__ halo_id) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int own = owner[i];
     const int32_t lab = own >= 0 ? h_label[own] : 0;
-    // halo_id was filled with 0: only the members of kept halos are written
-    // (scattered stores into the input order, so the fewer the better), and
-    // their original index is read only for them
-    if (l0_out) {
-        const uint32_t o = orig_of(spos[i]);
-        if (lab) halo_id[o] = lab;
-        const Geo &g = bx.geo[box_of(bx, (uint32_t)i)];
-        l0_out[o] = gkey[i] < 0 ? 0 : gkey[i] + 1 - (int32_t)g.orig_base;
-    } else if (lab) {
-        halo_id[orig_of(spos[i])] = lab;
-    }
+    if (lab) halo_id[orig_of(spos[i])] = lab;
+}
+
+// With more than the halo labels to return: the record (density, L0 label,
+// halo label) of every sorted particle stored at its original index, one
+// scattered 16-byte store (one cache line) per particle instead of one per
+// output array; k_out_split then writes the arrays in input order.
+__global__ __launch_bounds__(kBlock) void k_out_records(int64_t n, Boxes bx, const int32_t *__restrict__ owner,
+                                                        const int32_t *__restrict__ h_label,
+                                                        const int32_t *__restrict__ gkey,
+                                                        const float4 *__restrict__ spos,
+                                                        const float *__restrict__ dens_s,
+                                                        uint4 *__restrict__ rec) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int own = owner[i];
+    const int32_t lab = own >= 0 ? h_label[own] : 0;
+    const int32_t key = gkey[i];
+    const Geo &g = bx.geo[box_of(bx, (uint32_t)i)];
+    const int32_t l0 = key < 0 ? 0 : key + 1 - (int32_t)g.orig_base;
+    rec[orig_of(spos[i])] = make_uint4(__float_as_uint(dens_s[i]), (uint32_t)l0, (uint32_t)lab, 0u);
+}
+
+__global__ __launch_bounds__(kBlock) void k_out_split(int64_t n, const uint4 *__restrict__ rec,
+                                                      float *__restrict__ dens_out, int32_t *__restrict__ l0_out,
+                                                      int32_t *__restrict__ halo_id) {
+    int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= n) return;
+    const uint4 r = rec[o];
+    if (dens_out) dens_out[o] = __uint_as_float(r.x);
+    if (l0_out) l0_out[o] = (int32_t)r.y;
+    halo_id[o] = (int32_t)r.z;
 }
 
 // Groups with candidates in descending size, for the acceptance kernels: keys
@@ -977,15 +1003,23 @@ void launch_output_flags(int64_t n, int64_t NC, const Boxes &bx, Work &w, hipStr
 }
 
 void launch_output(int64_t n, int64_t NC, const Boxes &bx, Work &w, int32_t *halo_id, int32_t *l0_out,
-                   int64_t *box_rows, hipStream_t s) {
+                   float *dens_out, int64_t *box_rows, hipStream_t s) {
     if (NC > 0)
         hipLaunchKernelGGL(k_out_table, grid(NC), dim3(kBlock), 0, s, NC, bx, w.h_nuc, w.h_ienc, w.h_gid,
                            w.h_count, w.g_label, w.spos, w.tpos);
     if (box_rows)
         hipLaunchKernelGGL(k_box_rows, grid(bx.nbox), dim3(kBlock), 0, s, bx, w.tpos, box_rows);
-    fill_i32(halo_id, 0, n, s);
-    hipLaunchKernelGGL(k_out_particles, grid(n), dim3(kBlock), 0, s, n, bx, w.owner, w.hardlist, w.gkey, w.spos,
-                       halo_id, l0_out);
+    if (!l0_out && !dens_out) {
+        fill_i32(halo_id, 0, n, s);
+        hipLaunchKernelGGL(k_out_particles, grid(n), dim3(kBlock), 0, s, n, w.owner, w.hardlist, w.spos,
+                           halo_id);
+        return;
+    }
+    // records in the radix key block (2n words, free at this point)
+    uint4 *rec = reinterpret_cast<uint4 *>(w.rkey[0]);
+    hipLaunchKernelGGL(k_out_records, grid(n), dim3(kBlock), 0, s, n, bx, w.owner, w.hardlist, w.gkey, w.spos,
+                       w.dens_s, rec);
+    hipLaunchKernelGGL(k_out_split, grid(n), dim3(kBlock), 0, s, n, rec, dens_out, l0_out, halo_id);
 }
 
 void launch_group_order(int64_t n, int64_t nrows, const int32_t *halo_id, Work &w, int32_t *members,

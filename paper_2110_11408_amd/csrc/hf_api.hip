@@ -197,8 +197,9 @@ size_t carve(char *base, int64_t n, int64_t ncell, int nsub, int64_t rhl, int nb
     int64_t n1 = n + 1;
     w->cnt = c.take<uint32_t>(ncell + 1);
     w->off = c.take<uint32_t>(ncell + 1);
-    w->rkey[0] = c.take<uint64_t>(n);
-    w->rkey[1] = c.take<uint64_t>(n);
+    // one block: the output stage stores a 16-byte record per particle there
+    w->rkey[0] = c.take<uint64_t>(2 * n);
+    w->rkey[1] = w->rkey[0] ? w->rkey[0] + n : nullptr;
     w->rval[0] = c.take<uint32_t>(n);
     w->rval[1] = c.take<uint32_t>(n);
     w->rhist = c.take<uint32_t>(rhl);
@@ -467,7 +468,8 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 }
 
 // CompaSO on the binned particles with group keys in w.gkey.  Fills halo_id,
-// l0_out (may be null), every box's table and its row count (n_halos, host,
+// l0_out and dens_out (either may be null; the densities from w.dens_s), every
+// box's table and its row count (n_halos, host,
 // nbox entries); records events ev[3..8].  CAPACITY when a table did not fit.
 // Optional output of a one-box pass: its members in group order (Sec. 2.3.5).
 struct GroupOut {
@@ -476,7 +478,8 @@ struct GroupOut {
 };
 
 hf_status run_compaso(Lane *c, const Plan &pl, const hf::Boxes &bx, Work &w, int32_t *halo_id,
-                      int32_t *l0_out, int64_t *n_halos, hipStream_t s, const GroupOut &go = GroupOut{}) {
+                      int32_t *l0_out, float *dens_out, int64_t *n_halos, hipStream_t s,
+                      const GroupOut &go = GroupOut{}) {
     const int64_t n = pl.n;
     HIP_OK(c, hipEventRecord(c->ev[3], s));
     hf::launch_segment(n, w, s);
@@ -505,7 +508,7 @@ hf_status run_compaso(Lane *c, const Plan &pl, const hf::Boxes &bx, Work &w, int
     hf::launch_assign(n, bx, w, s);
     HIP_OK(c, hipEventRecord(c->ev[7], s));
     hf::launch_output_flags(n, NC, bx, w, s);
-    hf::launch_output(n, NC, bx, w, halo_id, l0_out, w.box_rows, s);
+    hf::launch_output(n, NC, bx, w, halo_id, l0_out, dens_out, w.box_rows, s);
     HIP_OK(c, hipEventRecord(c->ev[8], s));
     // every box's rows, the nuclei accepted (counter 2) and the error flags
     int64_t *rows = reinterpret_cast<int64_t *>(c->stage);
@@ -643,12 +646,17 @@ hf_status find_boxes(Lane *c, const hf::BoxSet &bs, const float *pos, float *den
     Work w;
     st = begin(c, pl, pos, &bx, &w, s, true, false, fx);
     if (st != HF_OK) return st;
-    hf::launch_density(pl.n, bx, w, density, s);
+    // with the L0 labels asked for, the three outputs leave together in the
+    // output stage (one scattered record per particle costs less than three
+    // scattered words); else the density kernels store the densities and the
+    // output stage only the halo labels (two words cost less than a record)
+    float *dens_late = l0_id ? density : nullptr;
+    hf::launch_density(pl.n, bx, w, l0_id ? nullptr : density, s);
     HIP_OK(c, hipEventRecord(c->ev[2], s));
     hf::launch_fof(pl.n, bx, w, s);
-    hf::launch_fof_labels(pl.n, bx, w, l0_id, s);
+    hf::launch_fof_labels(pl.n, bx, w, nullptr, s);
     HIP_OK(c, hipEventRecord(c->ev[9], s));
-    st = run_compaso(c, pl, bx, w, halo_id, nullptr, n_halos, s, go);
+    st = run_compaso(c, pl, bx, w, halo_id, l0_id, dens_late, n_halos, s, go);
     c->stats.ms_bin = elapsed(c->ev[0], c->ev[1]);
     c->stats.ms_density = elapsed(c->ev[1], c->ev[2]);
     c->stats.ms_fof = elapsed(c->ev[2], c->ev[9]);
@@ -964,7 +972,7 @@ hf_status hf_compaso(hf_ctx *ctx, const float *pos, const float *density, const 
     hf::launch_keys_from_labels(l0_id, density, n, bx, w, s);  // also gathers the densities
     HIP_OK(c, hipEventRecord(c->ev[2], s));
     int64_t nh = 0;
-    st = run_compaso(c, pl, bx, w, halo_id, nullptr, &nh, s);
+    st = run_compaso(c, pl, bx, w, halo_id, nullptr, nullptr, &nh, s);
     if (n_halos) *n_halos = nh;
     c->stats.ms_bin = elapsed(c->ev[0], c->ev[1]);
     c->stats.ms_total = elapsed(c->ev[0], c->ev[8]);

@@ -228,7 +228,7 @@ __device__ __forceinline__ int32_t wave_run_min(int32_t v, const WaveRun &r) {
 struct Work {
     // binning
     uint32_t *cnt, *off;             // cnt: cell -> dense-cell ordinal (dense cells only)
-    uint64_t *rkey[2];               // radix sort keys (ping-pong); rkey[0] is reused after binning
+    uint64_t *rkey[2];               // radix sort keys (ping-pong, rkey[1] = rkey[0] + n); reused after binning
     uint32_t *rval[2];               // radix sort payload: original index
     uint32_t *rhist, *rscan;         // per-pass [digit][tile] counts and their scan
     uint16_t *ssub;
@@ -328,11 +328,12 @@ void launch_candidates_sort(int64_t n, int64_t G, int64_t NC, Work &w, hipStream
 void launch_accept(int64_t n, int64_t G, int64_t NC, int64_t M, const Boxes &bx, Work &w, hipStream_t s);
 void launch_assign(int64_t n, const Boxes &bx, Work &w, hipStream_t s);
 void launch_output_flags(int64_t n, int64_t NC, const Boxes &bx, Work &w, hipStream_t s);
-// halo_id / l0_out: device [n], box-local labels.  Each box's table goes to
-// its Geo::halos when its rows fit in Geo::halo_cap; box_rows (device [nbox])
+// halo_id / l0_out: device [n], box-local labels; dens_out: device [n], the
+// densities (l0_out and dens_out may be null).  Each box's table goes to its
+// Geo::halos when its rows fit in Geo::halo_cap; box_rows (device [nbox])
 // receives every box's row count.
 void launch_output(int64_t n, int64_t NC, const Boxes &bx, Work &w, int32_t *halo_id, int32_t *l0_out,
-                   int64_t *box_rows, hipStream_t s);
+                   float *dens_out, int64_t *box_rows, hipStream_t s);
 // One box after launch_output: its n particles by table row of their halo
 // (nrows rows, then the particles of no halo), ascending index within a row,
 // into members [n]; halo_start [nrows + 1] receives each row's first position.

@@ -144,6 +144,30 @@ def test_run_to_run_determinism(ctx, runs):
         np.testing.assert_array_equal(g2[k], g[k])
 
 
+@pytest.mark.parametrize("want_density,want_l0", [(True, False), (False, True), (False, False)])
+def test_optional_outputs(ctx, runs, want_density, want_l0):
+    """The outputs a call asks for are those of the full call, whichever of
+    the density and L0 arrays it leaves out (the output stage takes a
+    different path when only the halo labels are wanted)."""
+    import torch
+    from paper_2110_11408_amd import _lib
+    pos, L, g = runs["s40123"]
+    _say(f"[gpu] optional outputs s40123 density={want_density} l0={want_l0}")
+    out = ctx.find(torch.from_numpy(pos).cuda(), _lib.default_params(box=L), want_density=want_density,
+                   want_l0=want_l0)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out["halo_id"].cpu().numpy(), g["halo_id"])
+    assert out["n_halos"] == g["n_halos"]
+    if want_density:
+        np.testing.assert_array_equal(out["density"].cpu().numpy(), g["density"])
+    else:
+        assert out["density"] is None
+    if want_l0:
+        np.testing.assert_array_equal(out["l0_id"].cpu().numpy(), g["l0"])
+    else:
+        assert out["l0_id"] is None
+
+
 def test_params_variants(ctx):
     """Non-default parameters (z = 0.5 thresholds of Table 1 scaled as the paper
     does, other alpha / c_Roche / kernel radius, a linking length above the
