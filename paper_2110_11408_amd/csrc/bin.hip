@@ -295,8 +295,10 @@ __global__ __launch_bounds__(kBlock) void k_cell_offsets(int64_t n, int64_t ncel
     }
     const uint32_t pre = incl - g;
     const uint32_t G = lane_get(incl, 63);
-    // first cell owned by the wavefront: one past the cell of the slot before it
-    const int64_t first = s0 == 0 ? 0 : (int64_t)__float_as_uint(sloc[s0 - 1].w) + 1;
+    // first cell owned by the wavefront: one past the cell of the slot before
+    // it, which lane 0 holds as lo (a cell id below 2^32 when s0 > 0)
+    const int64_t first =
+        s0 == 0 ? 0 : (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)lo) + 1;
     const int64_t end = first + (int64_t)G;
     // the slots that own cells, in order: rank -> slot
     const uint64_t owners = __ballot(g > 0);
@@ -331,7 +333,10 @@ __global__ __launch_bounds__(kBlock) void k_cell_offsets(int64_t n, int64_t ncel
             const int64_t cell = w0 + p + u;
             const bool valid = cell >= first && cell < end;
             all = all && valid;
-            v[u] = valid ? (uint32_t)(s0 + s_slot[w][cnt > 0u ? cnt - 1u : 0u]) : 0u;
+            // read for every cell (the rank is at most 64), so that the four
+            // reads are issued together
+            const uint32_t sl = s_slot[w][(cnt > 0u ? cnt - 1u : 0u) & 63u];
+            v[u] = valid ? (uint32_t)s0 + sl : 0u;
         }
         if (all) {
             *reinterpret_cast<uint4 *>(off + w0 + p) = make_uint4(v[0], v[1], v[2], v[3]);
@@ -360,10 +365,14 @@ __global__ __launch_bounds__(kBlock) void k_bin_flags(int64_t n, const float4 *_
     const int lane = threadIdx.x & 63;
     const int64_t s0 = i - lane;
     const bool act = i < n;
+    // the cells beyond the wavefront's two ends are loaded with the lanes'
+    // own (lane 0: slot s0 - 1, lane 63: slot s0 + 64)
+    const int64_t e = lane == 0 ? s0 - 1 : (lane == 63 ? s0 + 64 : -1);
     const uint32_t c = act ? __float_as_uint(sloc[i].w) : 0xffffffffu;
+    const uint32_t ce = e >= 0 && e < n ? __float_as_uint(sloc[e].w) : 0u;
     uint32_t cprev = __shfl_up(c, 1, 64), cnext = __shfl_down(c, 1, 64);
-    if (lane == 0) cprev = s0 > 0 ? __float_as_uint(sloc[s0 - 1].w) : 0xfffffffeu;
-    if (lane == 63) cnext = s0 + 64 < n ? __float_as_uint(sloc[s0 + 64].w) : 0xfffffffdu;
+    if (lane == 0) cprev = s0 > 0 ? ce : 0xfffffffeu;
+    if (lane == 63) cnext = s0 + 64 < n ? ce : 0xfffffffdu;
     const uint64_t heads = __ballot(act && c != cprev);
     const uint64_t tails = __ballot(act && c != cnext);
     if (!act) return;
