@@ -553,16 +553,31 @@ __global__ __launch_bounds__(NT) void k_accept(const uint32_t *__restrict__ ngc_
     if (tid == 0) s_nh = 0;
     __syncthreads();
     for (uint32_t r = cs; r < ce; r++) {
+        const int nh = s_nh;
+        // the next candidate from r on that is eligible (not inside alpha R of
+        // any nucleus accepted so far), NT candidates tested at once, one per
+        // thread: the ones passed over are ineligible in the serial order too,
+        // since the nuclei change only when a candidate is accepted
+        int next = 0x7fffffff;
+        for (uint32_t r0 = r; r0 < ce; r0 += NT) {
+            const uint32_t q = r0 + (uint32_t)tid;
+            int hit = 0x7fffffff;
+            if (q < ce) {
+                const float4 pq = spos[cand_sorted[q]];
+                bool el = true;
+                for (int h = 0; h < nh && el; h++) {
+                    const double e = d2_exact(pq, spos[ldi(h_nuc + cs + h)], g.L, g.half);
+                    el = !(g.K2 * e3(e) < g.A6 * ii(ldi(h_ienc + cs + h)));
+                }
+                if (el) hit = (int)(q - r);
+            }
+            next = block_min<NT>(hit, s_min);
+            if (next != 0x7fffffff) break;
+        }
+        if (next == 0x7fffffff) break;
+        r += (uint32_t)next;
         const int c = cand_sorted[r];
         const float4 pc = spos[c];
-        const int nh = s_nh;
-        // eligibility: not inside alpha R of any accepted nucleus
-        int inel = 0;
-        for (int h = tid; h < nh; h += NT) {
-            const double e = d2_exact(pc, spos[ldi(h_nuc + cs + h)], g.L, g.half);
-            if (g.K2 * e3(e) < g.A6 * ii(ldi(h_ienc + cs + h))) inel = 1;
-        }
-        if (__syncthreads_or(inel)) continue;
         int64_t found = m;
         if constexpr (BINS) {
             // members per radial bin, then their inclusive prefix in place
