@@ -437,21 +437,14 @@ __global__ __launch_bounds__(64, 6) void k_density_dense(int64_t nchunks, Boxes 
 }
 
 // Sparse cells: one particle per lane, sparse neighbour cells only; the pairs
-// with dense neighbour cells were summed by the dense kernel into dfx.  The
-// kernel waits on memory, so it is held to 64 VGPRs (eight wavefronts per
-// SIMD, the most a SIMD runs; the compiler fits it without spilling).
-__global__ __launch_bounds__(kBlock, 8) void k_density_sparse(int64_t nsparse, Boxes bx,
-                                                           const int32_t *__restrict__ sparse,
-                                                           const float4 *__restrict__ sloc,
-                                                           const float4 *__restrict__ spos,
-                                                           const uint32_t *__restrict__ off,
-                                                           const uint64_t *__restrict__ dfx,
-                                                           float *__restrict__ dens_s,
-                                                           float *__restrict__ dens_out) {
-    const int64_t t = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
-    if (t >= nsparse) return;
-    const int64_t i = sparse[t];
-    const Geo &g = bx.geo[box_of(bx, (uint32_t)i)];
+// with dense neighbour cells were summed by the dense kernel into dfx.  This
+// is particle i (entry t of the sparse list) of box g.
+__device__ __forceinline__ void density_sparse_one(const Geo &g, int64_t t, int64_t i,
+                                                   const float4 *__restrict__ sloc,
+                                                   const float4 *__restrict__ spos,
+                                                   const uint32_t *__restrict__ off,
+                                                   const uint64_t *__restrict__ dfx,
+                                                   float *__restrict__ dens_s, float *__restrict__ dens_out) {
     const float4 li = sloc[i];
     const float4 pi = spos[i];
     const uint32_t c = __float_as_uint(li.w);
@@ -537,6 +530,55 @@ __global__ __launch_bounds__(kBlock, 8) void k_density_sparse(int64_t nsparse, B
     write_density(i, acc, g, spos, dens_s, dens_out);
 }
 
+// The sparse-cell particles whose wavefront lies in one box (nearly all): the
+// box's constants are read with a box index uniform over the wavefront, so
+// they come with scalar loads into scalar registers.  A wavefront that spans
+// a box boundary (one per boundary at most) is listed in mixed[] and left to
+// k_density_sparse_mixed.  The kernel waits on memory, so it is held to 64
+// VGPRs (eight wavefronts per SIMD, the most a SIMD runs).
+__global__ __launch_bounds__(kBlock, 8) void k_density_sparse(int64_t nsparse, Boxes bx,
+                                                           const int32_t *__restrict__ sparse,
+                                                           const float4 *__restrict__ sloc,
+                                                           const float4 *__restrict__ spos,
+                                                           const uint32_t *__restrict__ off,
+                                                           const uint64_t *__restrict__ dfx,
+                                                           float *__restrict__ dens_s,
+                                                           float *__restrict__ dens_out,
+                                                           int32_t *__restrict__ mixed,
+                                                           uint32_t *__restrict__ nmixed) {
+    const int64_t t = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
+    if (t >= nsparse) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t i = sparse[t];
+    const int b = box_of(bx, (uint32_t)i);
+    const int b0 = __builtin_amdgcn_readfirstlane(b);
+    if (__ballot(b != b0) != 0ull) {
+        const uint64_t act = __ballot(true);
+        if (lane == __ffsll((unsigned long long)act) - 1) mixed[atomicAdd(nmixed, 1u)] = (int32_t)(t - lane);
+        return;
+    }
+    density_sparse_one(bx.geo[b0], t, i, sloc, spos, off, dfx, dens_s, dens_out);
+}
+
+// The wavefronts of the sparse list that span a box boundary: each lane reads
+// its own box's constants.
+__global__ __launch_bounds__(64) void k_density_sparse_mixed(int64_t nsparse, Boxes bx,
+                                                             const uint32_t *__restrict__ nmixed,
+                                                             const int32_t *__restrict__ mixed,
+                                                             const int32_t *__restrict__ sparse,
+                                                             const float4 *__restrict__ sloc,
+                                                             const float4 *__restrict__ spos,
+                                                             const uint32_t *__restrict__ off,
+                                                             const uint64_t *__restrict__ dfx,
+                                                             float *__restrict__ dens_s,
+                                                             float *__restrict__ dens_out) {
+    if (blockIdx.x >= *nmixed) return;
+    const int64_t t = (int64_t)mixed[blockIdx.x] + threadIdx.x;
+    if (t >= nsparse) return;
+    const int64_t i = sparse[t];
+    density_sparse_one(bx.geo[box_of(bx, (uint32_t)i)], t, i, sloc, spos, off, dfx, dens_s, dens_out);
+}
+
 // Number of ordered pairs (i, j != i) closer than b, for the roofline's
 // algorithmic pair count (evaluated in the same FP32 local coordinates).
 __global__ __launch_bounds__(kBlock) void k_count_pairs(int64_t n, Boxes bx,
@@ -594,10 +636,19 @@ void launch_density(int64_t n, const Boxes &bx, Work &w, float *dens_out, hipStr
         hipLaunchKernelGGL(k_density_dense, dim3((unsigned)w.nchunks), dim3(64), 0, s, w.nchunks, bx, narrow,
                            w.chunks, w.sloc, w.pq, w.spos, w.off, w.s_sparse, dfx, w.dens_s, dens_out);
     }
-    if (w.nsparse > 0)
+    if (w.nsparse > 0) {
+        // the wavefronts that span a box boundary: at most nbox - 1, listed
+        // in the table-flag array (free until the output stage), their count
+        // in counters[14] (zero since the call began)
+        int32_t *mixed = reinterpret_cast<int32_t *>(w.tflag);
+        uint32_t *nmixed = reinterpret_cast<uint32_t *>(w.counters + 14);
         hipLaunchKernelGGL(k_density_sparse, dim3((unsigned)((w.nsparse + kBlock - 1) / kBlock)),
                            dim3(kBlock), 0, s, w.nsparse, bx, w.sparse, w.sloc, w.spos, w.off, dfx, w.dens_s,
-                           dens_out);
+                           dens_out, mixed, nmixed);
+        if (bx.nbox > 1)
+            hipLaunchKernelGGL(k_density_sparse_mixed, dim3((unsigned)bx.nbox), dim3(64), 0, s, w.nsparse, bx,
+                               nmixed, mixed, w.sparse, w.sloc, w.spos, w.off, dfx, w.dens_s, dens_out);
+    }
 }
 
 void launch_count_pairs(int64_t n, const Boxes &bx, Work &w, unsigned long long *total, hipStream_t s) {
