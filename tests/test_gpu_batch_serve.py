@@ -108,6 +108,29 @@ def test_batch_equals_single_calls(ctx, boxes, singles, lanes):
         _assert_box_equal(single, dens[a:e], l0[a:e], hid[a:e], out["halos"][b].cpu().numpy())
 
 
+def test_batch_of_many_small_boxes(ctx):
+    """Twenty-four boxes of 64 to 400 particles in one fused pass: wavefronts
+    of the per-particle kernels span several box boundaries (the sparse-cell
+    density lists such wavefronts for a kernel that reads each lane's own box
+    constants).  Every box equals its single call."""
+    import torch
+    sizes = [150, 90, 400, 64, 200, 120, 80, 260] * 3
+    small = []
+    for k, n in enumerate(sizes):
+        pos, L, _ = synth.small_box(n, seed=400 + k, nmax=80, halo_frac=0.5)
+        small.append((pos, L))
+    singles = []
+    for pos, L in small:
+        r = ctx.find(torch.from_numpy(pos).cuda(), _params(L, len(pos)))
+        singles.append({k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in r.items()})
+    offs, out = _run_batch(ctx, small, n_lanes=1)
+    dens, l0, hid = (out[k].cpu().numpy() for k in ("density", "l0_id", "halo_id"))
+    for b, single in enumerate(singles):
+        a, e = offs[b], offs[b + 1]
+        assert out["n_halos"][b] == single["n_halos"]
+        _assert_box_equal(single, dens[a:e], l0[a:e], hid[a:e], out["halos"][b].cpu().numpy())
+
+
 def test_batch_matches_oracle(ctx, boxes):
     from paper_2110_11408_amd.api import halo_table
     offs, out = _run_batch(ctx, boxes)
