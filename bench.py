@@ -20,6 +20,7 @@ line also carries:
                 the same arrival times: p50/p99 latency and particles/s of both;
   plain256      the 256^3 box (16.8M particles) as a single ``hf_find`` call,
                 with its stage rooflines and ``hf_halo_stats``;
+  plain64       the 64^3 box (262k particles) as a single ``hf_find`` call;
   large512      (``--large``) the 512^3 box (134M particles);
   cpu_baseline  the FP64 oracle on a bounded sample of the headline workload's
                 boxes, per stage, on all host threads and on one.
@@ -541,6 +542,8 @@ def main():
     if args.workload == "batched96" and not args.no_plain256:
         _say("[bench] plain256")
         res["plain256"] = single_box(ctx, "plain256", 5, 2, np, torch, _lib, synth, halo_stats=True)
+        _say("[bench] plain64")
+        res["plain64"] = single_box(ctx, "plain64", 20, 3, np, torch, _lib, synth)
     if args.large:
         _say("[bench] large512")
         res["large512"] = single_box(ctx, "large512", 3, 1, np, torch, _lib, synth)
