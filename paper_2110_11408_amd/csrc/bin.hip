@@ -59,23 +59,40 @@ __device__ __forceinline__ int sub_coord(float x, int c, const Geo &g) {
 // call's numbering (box after box).  Packed mode stores (key << ib) | i in one
 // word (ib bits hold the index); otherwise the index travels in a separate
 // payload array.
+// A thread keys kKeyIlp particles (i0, i0 + kBlock, ...), their positions
+// loaded together (one load in flight per thread leaves most of the
+// bandwidth unused).
+constexpr int kKeyIlp = 4;
 __global__ __launch_bounds__(kBlock) void k_bin_key(const float *__restrict__ pos, int64_t n, Boxes bx, int ib,
                                                     uint64_t *__restrict__ key,
                                                     int32_t *__restrict__ err) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int box = box_of(bx, (uint32_t)i);
-    const Geo &g = bx.geo[box];
-    float x = pos[3 * i + 0], y = pos[3 * i + 1], z = pos[3 * i + 2];
-    float Lf = (float)g.L;
-    bool ok = x >= 0.0f && x < Lf && y >= 0.0f && y < Lf && z >= 0.0f && z < Lf;
-    if (!ok) flag_error(err, 1, box);
-    int cx = cell_coord(x, g), cy = cell_coord(y, g), cz = cell_coord(z, g);
-    uint32_t c = g.cell_base + ((uint32_t)cz * (uint32_t)g.nc + (uint32_t)cy) * (uint32_t)g.nc + (uint32_t)cx;
-    int k = g.ksub;
-    uint32_t sub = (uint32_t)((sub_coord(z, cz, g) * k + sub_coord(y, cy, g)) * k + sub_coord(x, cx, g));
-    const uint64_t kk = (uint64_t)c * (uint64_t)bx.nsub_max + sub;
-    key[i] = ib > 0 ? (kk << ib) | (uint64_t)i : kk;
+    const int64_t i0 = (int64_t)blockIdx.x * (kBlock * kKeyIlp) + threadIdx.x;
+    float px[kKeyIlp], py[kKeyIlp], pz[kKeyIlp];
+#pragma unroll
+    for (int u = 0; u < kKeyIlp; u++) {
+        const int64_t i = i0 + (int64_t)u * kBlock;
+        px[u] = i < n ? pos[3 * i + 0] : 0.0f;
+        py[u] = i < n ? pos[3 * i + 1] : 0.0f;
+        pz[u] = i < n ? pos[3 * i + 2] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < kKeyIlp; u++) {
+        const int64_t i = i0 + (int64_t)u * kBlock;
+        if (i >= n) break;
+        const int box = box_of(bx, (uint32_t)i);
+        const Geo &g = bx.geo[box];
+        const float x = px[u], y = py[u], z = pz[u];
+        const float Lf = (float)g.L;
+        const bool ok = x >= 0.0f && x < Lf && y >= 0.0f && y < Lf && z >= 0.0f && z < Lf;
+        if (!ok) flag_error(err, 1, box);
+        const int cx = cell_coord(x, g), cy = cell_coord(y, g), cz = cell_coord(z, g);
+        const uint32_t c =
+            g.cell_base + ((uint32_t)cz * (uint32_t)g.nc + (uint32_t)cy) * (uint32_t)g.nc + (uint32_t)cx;
+        const int k = g.ksub;
+        const uint32_t sub = (uint32_t)((sub_coord(z, cz, g) * k + sub_coord(y, cy, g)) * k + sub_coord(x, cx, g));
+        const uint64_t kk = (uint64_t)c * (uint64_t)bx.nsub_max + sub;
+        key[i] = ib > 0 ? (kk << ib) | (uint64_t)i : kk;
+    }
 }
 
 constexpr int kRadixMaxBits = 8;
@@ -386,6 +403,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_flags(int64_t n, const float4 *_
     f_sparse[i] = !dense;
 }
 
+constexpr int kListIlp = 4;
 __global__ __launch_bounds__(kBlock) void k_bin_lists(int64_t n, const uint32_t *__restrict__ f_chunk,
                                                       const uint32_t *__restrict__ s_chunk,
                                                       const uint32_t *__restrict__ f_dcell,
@@ -397,15 +415,32 @@ __global__ __launch_bounds__(kBlock) void k_bin_lists(int64_t n, const uint32_t 
                                                       uint32_t *__restrict__ dcells,
                                                       int32_t *__restrict__ sparse,
                                                       uint32_t *__restrict__ cellmap) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    if (f_chunk[i]) chunks[s_chunk[i]] = (int32_t)i;
-    if (f_sparse[i]) sparse[s_sparse[i]] = (int32_t)i;
-    if (f_dcell[i]) {
-        const uint32_t c = __float_as_uint(sloc[i].w);
-        const uint32_t d = s_dcell[i];
-        dcells[d] = c;
-        cellmap[c] = d;  // the cell-count array is reused as cell -> dense-cell map
+    // kListIlp particles per thread (i0, i0 + kBlock, ...): their flags and
+    // list positions loaded together, the positions whatever the flags (one
+    // round of loads instead of two)
+    const int64_t i0 = (int64_t)blockIdx.x * (kBlock * kListIlp) + threadIdx.x;
+    uint32_t fc[kListIlp], sc[kListIlp], fs[kListIlp], ss[kListIlp], fd[kListIlp];
+#pragma unroll
+    for (int u = 0; u < kListIlp; u++) {
+        const int64_t i = i0 + (int64_t)u * kBlock;
+        const bool in = i < n;
+        fc[u] = in ? f_chunk[i] : 0u;
+        sc[u] = in ? s_chunk[i] : 0u;
+        fs[u] = in ? f_sparse[i] : 0u;
+        ss[u] = in ? s_sparse[i] : 0u;
+        fd[u] = in ? f_dcell[i] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < kListIlp; u++) {
+        const int64_t i = i0 + (int64_t)u * kBlock;
+        if (fc[u]) chunks[sc[u]] = (int32_t)i;
+        if (fs[u]) sparse[ss[u]] = (int32_t)i;
+        if (fd[u]) {
+            const uint32_t c = __float_as_uint(sloc[i].w);
+            const uint32_t d = s_dcell[i];
+            dcells[d] = c;
+            cellmap[c] = d;  // the cell-count array is reused as cell -> dense-cell map
+        }
     }
 }
 
@@ -510,7 +545,8 @@ uint64_t *radix_sort_keys(uint64_t *a, uint64_t *b, int64_t n, int lo, int bits,
 void launch_bin(const float *pos, int64_t n, int64_t ncell, const Boxes &bx, Work &w, hipStream_t s) {
     const RadixPlan r = radix_plan(n, ncell, bx.nsub_max);
     const bool packed = r.ib > 0;
-    hipLaunchKernelGGL(k_bin_key, dim3(blocks(n)), dim3(kBlock), 0, s, pos, n, bx, r.ib, w.rkey[0], w.err);
+    hipLaunchKernelGGL(k_bin_key, dim3(blocks((n + kKeyIlp - 1) / kKeyIlp)), dim3(kBlock), 0, s, pos, n, bx, r.ib,
+                       w.rkey[0], w.err);
     const int64_t ntiles = (n + kTile - 1) / kTile;
     const int64_t hl = ((int64_t)1 << r.D) * ntiles;
     int cur = 0;
@@ -542,7 +578,8 @@ void launch_bin(const float *pos, int64_t n, int64_t ncell, const Boxes &bx, Wor
     scan_u32(w.f_chunk, w.s_chunk, n, w.scan_tmp, s);
     scan_u32(w.f_dcell, w.s_dcell, n, w.scan_tmp, s);
     scan_u32(w.f_sparse, w.s_sparse, n, w.scan_tmp, s);
-    hipLaunchKernelGGL(k_bin_lists, dim3(blocks(n)), dim3(kBlock), 0, s, n, w.f_chunk, w.s_chunk,
+    hipLaunchKernelGGL(k_bin_lists, dim3(blocks((n + kListIlp - 1) / kListIlp)), dim3(kBlock), 0, s, n, w.f_chunk,
+                       w.s_chunk,
                        w.f_dcell, w.s_dcell, w.f_sparse, w.s_sparse, w.sloc, w.chunks, w.dcells,
                        w.sparse, w.cnt);
 }
