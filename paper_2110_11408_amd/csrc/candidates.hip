@@ -226,11 +226,25 @@ __global__ __launch_bounds__(kBlock) void k_cand_quick(int64_t n, Boxes bx, cons
     f_hard[i] = is_hard ? 1u : 0u;
 }
 
+// Four particles per thread (i0, i0 + kBlock, ...), their flags loaded
+// together: the kernel streams the flags, and one load in flight per thread
+// leaves most of the bandwidth unused.
+constexpr int kHardIlp = 4;
 __global__ __launch_bounds__(kBlock) void k_hard_list(int64_t n, const uint32_t *__restrict__ f_hard,
                                                       const uint32_t *__restrict__ s_hard,
                                                       int32_t *__restrict__ hard) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n && f_hard[i]) hard[s_hard[i]] = (int32_t)i;
+    const int64_t i0 = (int64_t)blockIdx.x * (kBlock * kHardIlp) + threadIdx.x;
+    uint32_t f[kHardIlp];
+#pragma unroll
+    for (int u = 0; u < kHardIlp; u++) {
+        const int64_t i = i0 + (int64_t)u * kBlock;
+        f[u] = i < n ? f_hard[i] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < kHardIlp; u++) {
+        const int64_t i = i0 + (int64_t)u * kBlock;
+        if (f[u]) hard[s_hard[i]] = (int32_t)i;
+    }
 }
 
 // Whether particle i has a denser particle of its group within b in the
@@ -519,7 +533,8 @@ void launch_candidates(int64_t n, const Boxes &bx, Work &w, hipStream_t s) {
     hipLaunchKernelGGL(k_cand_quick, dim3(blocks), dim3(kBlock), 0, s, n, bx, w.sloc, w.spos, w.f_sparse, w.ssub,
                        w.cnt, w.submax, w.subarg, w.dens_s, w.gkey, w.owner, w.f_dcell);
     scan_u32(w.f_dcell, w.s_dcell, n, w.scan_tmp, s);
-    hipLaunchKernelGGL(k_hard_list, dim3(blocks), dim3(kBlock), 0, s, n, w.f_dcell, w.s_dcell, w.hardlist);
+    hipLaunchKernelGGL(k_hard_list, dim3((unsigned)((n + kBlock * kHardIlp - 1) / (kBlock * kHardIlp))), dim3(kBlock),
+                       0, s, n, w.f_dcell, w.s_dcell, w.hardlist);
     uint32_t nh = 0;
     WordSrc src{};
     src.p[0] = w.s_dcell + n;

@@ -485,12 +485,25 @@ __global__ __launch_bounds__(kBlock) void k_fof_sparse_flags(int64_t nsparse, Bo
     flag[t] = is_member(dens_s, i, bx.geo[box_of(bx, (uint32_t)i)].dl0) ? 1u : 0u;
 }
 
+// Four entries per thread (t0, t0 + kBlock, ...), their flags loaded
+// together (the kernel streams the flags).
+constexpr int kSparseListIlp = 4;
 __global__ __launch_bounds__(kBlock) void k_fof_sparse_list(int64_t nsparse, const int32_t *__restrict__ sparse,
                                                             const uint32_t *__restrict__ flag,
                                                             const uint32_t *__restrict__ at,
                                                             int32_t *__restrict__ list) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < nsparse && flag[t]) list[at[t]] = sparse[t];
+    const int64_t t0 = (int64_t)blockIdx.x * (kBlock * kSparseListIlp) + threadIdx.x;
+    uint32_t f[kSparseListIlp];
+#pragma unroll
+    for (int u = 0; u < kSparseListIlp; u++) {
+        const int64_t t = t0 + (int64_t)u * kBlock;
+        f[u] = t < nsparse ? flag[t] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < kSparseListIlp; u++) {
+        const int64_t t = t0 + (int64_t)u * kBlock;
+        if (f[u]) list[at[t]] = sparse[t];
+    }
 }
 
 // Members of sparse cells (the compacted list, its length on the device):
@@ -696,7 +709,8 @@ void launch_fof(int64_t n, const Boxes &bx, Work &w, hipStream_t s) {
         hipLaunchKernelGGL(k_fof_sparse_flags, grid(w.nsparse), dim3(kBlock), 0, s, w.nsparse, bx, w.sparse,
                            w.dens_s, w.f_chunk);
         scan_u32(w.f_chunk, w.s_chunk, w.nsparse, w.scan_tmp, s);
-        hipLaunchKernelGGL(k_fof_sparse_list, grid(w.nsparse), dim3(kBlock), 0, s, w.nsparse, w.sparse,
+        hipLaunchKernelGGL(k_fof_sparse_list, grid((w.nsparse + kSparseListIlp - 1) / kSparseListIlp), dim3(kBlock),
+                           0, s, w.nsparse, w.sparse,
                            w.f_chunk, w.s_chunk, w.hardlist);
         hipLaunchKernelGGL(k_fof_sparse, grid(w.nsparse), dim3(kBlock), 0, s, w.s_chunk + w.nsparse, bx,
                            w.hardlist, w.sloc, w.spos, w.off, w.dens_s, w.parent);
